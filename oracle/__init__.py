@@ -1,0 +1,23 @@
+"""FP64 CPU oracle for the SBI wave solver -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously-correct numpy implementation of what the GPU path
+computes, written from the paper (Wang, "An Enhanced Spectral Boundary Integral
+Method for Modeling Highly Nonlinear Water Waves in Variable Depth"):
+
+* Sec. 2.2, Eq. (prognostic) and its integrating-factor form: the time step;
+* Sec. 2.4 (successive approximations) with Appendix C, Eqs. (v2)-(v7): the
+  surface vertical velocity V;
+* Sec. 3.1, Eq. (energy): the total energy diagnostic;
+* Sec. 3.3, Eq. (filter): the optional low-pass filter.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never does; it
+shares no code, tables or constants with this package.
+"""
+from .sbi_oracle import (  # noqa: F401
+    Grid,
+    Solver,
+    SolveInfo,
+    w_sa_appc,
+)
+from . import dft  # noqa: F401

@@ -1,0 +1,500 @@
+"""Plain FP64 oracle of the SBI wave solver (numpy).  TEST INFRASTRUCTURE ONLY.
+
+Notation follows the paper: eta (surface elevation), phi_s (surface potential,
+"phi tilde"), phi_b (bottom potential, "varphi tilde"), V (surface vertical
+velocity), h (reference depth), delta (seabed variation; seabed at z=-h+delta),
+T = tanh(kh), S = sech(kh).  Fourier transform: forward exp(-i k.x)
+unnormalised, inverse 1/N (Sec. 2.2); numpy's pocketfft serves as the FFT
+primitive and is pinned against a brute-force DFT in the tests.
+
+Readings of the paper that this oracle fixes (each also listed in the design
+notes of the repository):
+
+* dealiasing ("2/(l+1) rule", Sec. 2.4): keep |m_x| <= floor(alpha nx/2) and
+  |m_y| <= floor(alpha ny/2) with alpha = 1/2; applied to the spectrum of every
+  product and to the state;
+* the explicit orders of Appendix C, Eqs. (v2)-(v7), are authoritative where
+  the general recursion of Sec. 2.4 differs from them;
+* the iteration mode solves the fixed point of the recursion summed over
+  orders (same expansion, J = L-1 convolution orders in both equations);
+* time stepping is Lawson integrating-factor RK4 on the integrating-factor
+  form of Eq. (prognostic) with omega = sqrt(k tanh(kh)).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# status codes (same meaning as the C interface)
+OK = 0
+WARN_NOT_CONVERGED = 1
+WARN_DEPTH_CRITERION = 2
+ERR_NONFINITE = -5
+ERR_DIVERGED = -6
+
+
+class Grid:
+    """Periodic grid, rfft2 half-spectrum layout (ny, nx//2+1)."""
+
+    def __init__(self, nx: int, ny: int, lx: float, ly: float = 1.0, dealias: float = 0.5):
+        self.nx, self.ny, self.lx, self.ly = int(nx), int(ny), float(lx), float(ly)
+        mx = np.arange(self.nx // 2 + 1)
+        my = np.fft.fftfreq(self.ny, 1.0 / self.ny) if self.ny > 1 else np.zeros(1)
+        self.kx = (2 * np.pi * mx / self.lx)[None, :]
+        self.ky = (2 * np.pi * my / self.ly)[:, None] if self.ny > 1 else np.zeros((1, 1))
+        self.k = np.sqrt(self.kx ** 2 + self.ky ** 2)
+        self.Mx = int(math.floor(dealias * self.nx / 2 + 1e-9))
+        self.My = 0 if self.ny == 1 else int(math.floor(dealias * self.ny / 2 + 1e-9))
+        keep = (mx[None, :] <= self.Mx) & (np.abs(my)[:, None] <= self.My)
+        self.mask = keep.astype(np.float64)
+        self.dA = (self.lx / self.nx) * ((self.ly / self.ny) if self.ny > 1 else 1.0)
+        self.kband = math.hypot(2 * np.pi * self.Mx / self.lx,
+                                (2 * np.pi * self.My / self.ly) if self.ny > 1 else 0.0)
+
+    # transforms -----------------------------------------------------------
+    def fft(self, f):
+        return np.fft.rfft2(np.asarray(f, dtype=np.float64))
+
+    def ifft(self, F):
+        return np.fft.irfft2(F, s=(self.ny, self.nx))
+
+    def MF(self, f):
+        """Masked forward transform of a (product) field."""
+        return self.mask * self.fft(f)
+
+    def grad(self, F):
+        """Physical gradient of the field whose spectrum is F."""
+        gx = self.ifft(1j * self.kx * F)
+        gy = self.ifft(1j * self.ky * F) if self.ny > 1 else None
+        return gx, gy
+
+    def ikdot(self, Fx, Fy):
+        """ik . (Fx, Fy) in spectral space."""
+        out = 1j * self.kx * Fx
+        if Fy is not None:
+            out = out + 1j * self.ky * Fy
+        return out
+
+
+def _sech(x):
+    e = np.exp(-np.abs(x))
+    return 2.0 * e / (1.0 + e * e)
+
+
+@dataclass
+class SolveInfo:
+    sweeps: int = 0
+    residual: float = 0.0
+    status: int = OK
+    omega: float = 1.0
+    history: list = field(default_factory=list)
+
+
+class Solver:
+    """W solve (successive approximation / iteration) and IF-RK4 time step."""
+
+    def __init__(self, grid: Grid, depth, h_ref: float | None = None, order: int = 7,
+                 mode: str = "iter", max_sweeps: int = 64, relax: bool = True,
+                 filter_beta=None, relaxation_zone=None):
+        self.g = grid
+        depth = np.asarray(depth, dtype=np.float64).reshape(grid.ny, grid.nx)
+        if np.any(~np.isfinite(depth)) or np.any(depth <= 0):
+            raise ValueError("depth must be finite and positive")
+        self.h = float(depth.max()) if (h_ref is None or h_ref <= 0) else float(h_ref)
+        # seabed at z = -h + delta  (Sec. 2.1)
+        self.delta = self.h - depth
+        self.flat = not np.any(self.delta != 0.0)
+        self.L = int(order)
+        if not 1 <= self.L <= 7:
+            raise ValueError("order must be in 1..7")
+        self.mode = mode
+        self.max_sweeps = int(max_sweeps)
+        self.relax = relax
+        k = grid.k
+        kh = k * self.h
+        self.T = np.tanh(kh)
+        self.S = _sech(kh)
+        self.om2 = k * self.T              # omega^2 = k tanh(kh)
+        self.om = np.sqrt(self.om2)
+        self.filter_beta = filter_beta
+        self.rz = relaxation_zone
+        # depth-validity criterion of Sec. 5: k |delta| < 2.4 at the largest wavenumber
+        self.depth_warning = grid.kband * float(np.abs(self.delta).max()) > 2.4
+
+    # helpers ---------------------------------------------------------------
+    def Tn(self, n):
+        """tanh^<n/2>(kh): T for odd n, 1 for even n (Sec. 2.4)."""
+        return self.T if (n % 2) else 1.0
+
+    def kpow(self, p):
+        """k^p with the k = 0 mode set to 0 for p < 0 (every such term carries ik)."""
+        k = self.g.k
+        if p >= 0:
+            return k ** p
+        with np.errstate(divide="ignore"):
+            out = np.where(k > 0, k ** float(p), 0.0)
+        return out
+
+    # ------------------------------------------------------------------------
+    # Successive approximation, paper-exact (Sec. 2.4, Appendix C)
+    # ------------------------------------------------------------------------
+    def w_sa_hat(self, eta, ph):
+        """Spectrum of V = sum_{l=1}^{L} V_l for masked potential spectrum ph.
+
+        Order recursion in the form of Appendix C: for 2 <= l <= L,
+          F{V_l}   = sum_j [ -T_j k^j/j! MF{eta^j V_{l-j}}
+                              + <j> S k^(j-1)/j! ik.MF{delta^j grad phi_b,l-j} ]
+                     - T_l k^(l-2)/(l-1)! ik.MF{eta^(l-1) grad phi_s}
+          F{phi_b,l} = sum_j [ -<j> S k^(j-1)/j! MF{eta^j V_{l-j}}
+                              + (-1)^j T_j k^(j-2)/j! ik.MF{delta^j grad phi_b,l-j} ]
+                     - <l> S k^(l-3)/(l-1)! ik.MF{eta^(l-1) grad phi_s}
+        with V_1 = k T phi_hat and phi_b,1 = S phi_hat; phi_b only to order L-1.
+        """
+        g, k, S, L = self.g, self.g.k, self.S, self.L
+        gpx, gpy = g.grad(ph)
+        Vh = {1: k * self.T * ph}
+        Bh = {1: S * ph}
+        Vp = {1: g.ifft(Vh[1])}
+        gB = {1: g.grad(Bh[1])}
+        for l in range(2, L + 1):
+            acc = np.zeros_like(ph)
+            accB = np.zeros_like(ph)
+            for j in range(1, l):
+                fj = math.factorial(j)
+                P = g.MF(eta ** j * Vp[l - j])
+                acc = acc - self.Tn(j) * k ** j / fj * P
+                accB = accB - (j % 2) * S * self.kpow(j - 1) / fj * P
+                if not self.flat:
+                    bx, by = gB[l - j]
+                    D = g.ikdot(g.MF(self.delta ** j * bx),
+                                g.MF(self.delta ** j * by) if by is not None else None)
+                    acc = acc + (j % 2) * S * self.kpow(j - 1) / fj * D
+                    accB = accB + (-1) ** j * self.Tn(j) * self.kpow(j - 2) / fj * D
+            fl = math.factorial(l - 1)
+            Fl = g.ikdot(g.MF(eta ** (l - 1) * gpx),
+                         g.MF(eta ** (l - 1) * gpy) if gpy is not None else None)
+            acc = acc - self.Tn(l) * self.kpow(l - 2) / fl * Fl
+            accB = accB - (l % 2) * S * self.kpow(l - 3) / fl * Fl
+            Vh[l] = acc
+            Vp[l] = g.ifft(acc)
+            if l <= L - 1:
+                Bh[l] = accB
+                gB[l] = g.grad(accB)
+        return sum(Vh[l] for l in range(1, L + 1))
+
+    # ------------------------------------------------------------------------
+    # Iteration on the summed operator (fixed point of the same expansion)
+    # ------------------------------------------------------------------------
+    def forcing(self, eta, ph):
+        """Constant parts (b_V, b_phi) of the summed operator."""
+        g, k, S, L = self.g, self.g.k, self.S, self.L
+        gpx, gpy = g.grad(ph)
+        bV = k * self.T * ph
+        bB = S * ph
+        for l in range(2, L + 1):
+            fl = math.factorial(l - 1)
+            Fl = g.ikdot(g.MF(eta ** (l - 1) * gpx),
+                         g.MF(eta ** (l - 1) * gpy) if gpy is not None else None)
+            bV = bV - self.Tn(l) * self.kpow(l - 2) / fl * Fl
+            bB = bB - (l % 2) * S * self.kpow(l - 3) / fl * Fl
+        return bV, bB
+
+    def apply_T(self, eta, bV, bB, Vh, Bh):
+        """One sweep (V', phi_b') = T(V, phi_b) of the summed operator, J = L-1."""
+        g, k, S = self.g, self.g.k, self.S
+        J = self.L - 1
+        V = g.ifft(Vh)
+        bx, by = g.grad(Bh)
+        Vn = bV.copy()
+        Bn = bB.copy()
+        for j in range(1, J + 1):
+            fj = math.factorial(j)
+            P = g.MF(eta ** j * V)
+            Vn = Vn - self.Tn(j) * k ** j / fj * P
+            Bn = Bn - (j % 2) * S * self.kpow(j - 1) / fj * P
+            if not self.flat:
+                D = g.ikdot(g.MF(self.delta ** j * bx),
+                            g.MF(self.delta ** j * by) if by is not None else None)
+                Vn = Vn + (j % 2) * S * self.kpow(j - 1) / fj * D
+                Bn = Bn + (-1) ** j * self.Tn(j) * self.kpow(j - 2) / fj * D
+        return Vn, Bn
+
+    def relax_factor(self, eta):
+        """Relaxation weight from the local symbol of the sweep (truncated exp).
+
+        lambda(x) = sum_{j<=J} x^j/j!, x = k_band * eta at the highest crest and
+        the deepest trough; omega_r = min(1, 2 / (lambda_min + lambda_max)).
+        """
+        if not self.relax or self.L < 2:
+            return 1.0
+        J = self.L - 1
+        kb = self.g.kband
+
+        def lam(x):
+            return sum(x ** j / math.factorial(j) for j in range(J + 1))
+
+        lmax = lam(kb * float(np.max(eta)))
+        lmin = lam(kb * float(np.min(eta)))
+        s = lmin + lmax
+        if not np.isfinite(s) or s <= 0:
+            return 1.0
+        return min(1.0, 2.0 / s)
+
+    def w_iter_hat(self, eta, ph, tol, seed_hat=None):
+        g = self.g
+        info = SolveInfo()
+        bV, bB = self.forcing(eta, ph)
+        Vh = g.k * self.T * ph if seed_hat is None else g.mask * seed_hat
+        Bh = self.S * ph
+        w = self.relax_factor(eta)
+        info.omega = w
+        rmin = np.inf
+        Vn = Vh
+        for n in range(self.max_sweeps):
+            Vn, Bn = self.apply_T(eta, bV, bB, Vh, Bh)
+            Vnew = g.ifft(Vn)
+            dif = g.ifft(Vn - Vh)
+            num = float(np.max(np.abs(dif)))
+            den = float(np.max(np.abs(Vnew)))
+            if not (np.isfinite(num) and np.isfinite(den)):
+                info.status = ERR_NONFINITE
+                info.sweeps = n + 1
+                info.residual = float("nan")
+                return Vn, info
+            r = 0.0 if num == 0.0 else (num / den if den > 0 else np.inf)
+            info.history.append(r)
+            info.sweeps = n + 1
+            info.residual = r
+            if r <= tol:
+                return Vn, info
+            rmin = min(rmin, r)
+            if r > 1e6 or (n >= 3 and r > 10.0 * rmin):
+                info.status = ERR_DIVERGED
+                return Vn, info
+            Vh = Vh + w * (Vn - Vh)
+            Bh = Bh + w * (Bn - Bh)
+        info.status = WARN_NOT_CONVERGED
+        return Vn, info
+
+    # ------------------------------------------------------------------------
+    def solve_hat(self, eta, ph, tol=1e-10, seed_hat=None):
+        if self.mode == "sa":
+            return self.w_sa_hat(eta, ph), SolveInfo(sweeps=0)
+        return self.w_iter_hat(eta, ph, tol, seed_hat)
+
+    def vertical_velocity(self, eta, phi_s, tol=1e-10, seed=None):
+        """W = V at z = eta for physical (eta, phi_s); phi_s is band-limited by the mask."""
+        g = self.g
+        eta = np.asarray(eta, dtype=np.float64).reshape(g.ny, g.nx)
+        ph = g.MF(phi_s)
+        seed_hat = None if seed is None else g.fft(seed)
+        Vh, info = self.solve_hat(eta, ph, tol, seed_hat)
+        return g.ifft(Vh), info
+
+    # ------------------------------------------------------------------------
+    # Prognostic step: Eq. (prognostic) in integrating-factor form
+    # ------------------------------------------------------------------------
+    def rhs(self, eh, ph, tol):
+        """N = (V_hat - omega^2 phi_hat, MF{ (V + grad eta.grad phi)^2/(2(1+|grad eta|^2))
+        - |grad phi|^2/2 })  for masked state spectra (eh, ph)."""
+        g = self.g
+        eta = g.ifft(eh)
+        Vh, info = self.solve_hat(eta, ph, tol)
+        if info.status < 0:
+            raise FloatingPointError(f"W solve failed with status {info.status}")
+        V = g.ifft(Vh)
+        ex, ey = g.grad(eh)
+        px, py = g.grad(ph)
+        if ey is None:
+            gg = ex * ex
+            q = V + ex * px
+            pp = px * px
+        else:
+            gg = ex * ex + ey * ey
+            q = V + ex * px + ey * py
+            pp = px * px + py * py
+        nphi = 0.5 * (q * q / (1.0 + gg) - pp)
+        return Vh - self.om2 * ph, g.MF(nphi), Vh, info
+
+    def propagate(self, a, b, tau):
+        """E(tau) applied to the pair (a, b): exact linear propagator."""
+        om = self.om
+        c = np.cos(om * tau)
+        s = np.sin(om * tau)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            sw = np.where(om > 0, s / np.where(om > 0, om, 1.0), tau)
+        return c * a + om * s * b, -sw * a + c * b
+
+    def step_hat(self, eh, ph, dt, tol, stats=None):
+        """One Lawson IF-RK4 step on masked spectra."""
+        h = dt
+        a = self.rhs(eh, ph, tol)
+        if stats is not None:
+            stats.append(a[3])
+        u2 = self.propagate(eh + h / 2 * a[0], ph + h / 2 * a[1], h / 2)
+        b = self.rhs(*u2, tol)
+        eh_h, ph_h = self.propagate(eh, ph, h / 2)
+        u3 = (eh_h + h / 2 * b[0], ph_h + h / 2 * b[1])
+        c = self.rhs(*u3, tol)
+        ec, pc = self.propagate(c[0], c[1], h / 2)
+        eh_f, ph_f = self.propagate(eh, ph, h)
+        u4 = (eh_f + h * ec, ph_f + h * pc)
+        d = self.rhs(*u4, tol)
+        if stats is not None:
+            stats.extend([b[3], c[3], d[3]])
+        ea, pa = self.propagate(a[0], a[1], h)
+        ebc, pbc = self.propagate(b[0] + c[0], b[1] + c[1], h / 2)
+        en = eh_f + h / 6 * (ea + 2 * ebc + d[0])
+        pn = ph_f + h / 6 * (pa + 2 * pbc + d[1])
+        en = self.g.mask * en
+        pn = self.g.mask * pn
+        if self.filter_beta is not None:
+            b1, b2 = self.filter_beta
+            lam = np.exp(-np.abs(self.g.k / b1) ** b2)  # Eq. (filter)
+            en = lam * en
+            pn = lam * pn
+        return en, pn
+
+    def relaxation_target(self, t):
+        rz = self.rz
+        T = 2 * np.pi / rz["omega"]
+        tr = rz["ramp_periods"] * T
+        r = 0.5 * (1 - np.cos(np.pi * t / tr)) if t < tr else 1.0
+        x = np.arange(self.g.nx) * (self.g.lx / self.g.nx)
+        th = rz["k"] * x - rz["omega"] * t
+        eta_t = rz["a"] * r * np.cos(th)
+        phi_t = rz["a"] * r / rz["omega"] * np.sin(th)
+        return eta_t[None, :], phi_t[None, :]
+
+    def relaxation_weights(self):
+        rz = self.rz
+        x = np.arange(self.g.nx) * (self.g.lx / self.g.nx)
+        L = self.g.lx
+        wg = np.zeros_like(x)
+        m = x < rz["gen_len"]
+        s = x[m] / rz["gen_len"]
+        wg[m] = 1.0 - (3 * s * s - 2 * s ** 3)
+        wa = np.zeros_like(x)
+        m = x > L - rz["abs_len"]
+        s = (L - x[m]) / rz["abs_len"]
+        wa[m] = 1.0 - (3 * s * s - 2 * s ** 3)
+        return wg[None, :], wa[None, :]
+
+    def apply_relaxation(self, eh, ph, t):
+        g = self.g
+        eta = g.ifft(eh)
+        phi = g.ifft(ph)
+        wg, wa = self.relaxation_weights()
+        et, pt = self.relaxation_target(t)
+        eta = (1 - wg) * eta + wg * et
+        phi = (1 - wg) * phi + wg * pt
+        eta = (1 - wa) * eta
+        phi = (1 - wa) * phi
+        return g.MF(eta), g.MF(phi)
+
+    def step(self, eta, phi_s, dt, n, tol=1e-10, t0=0.0):
+        """Advance physical (eta, phi_s) by n steps of dt; returns (eta, phi_s, solve_infos)."""
+        g = self.g
+        eh = g.MF(np.asarray(eta, dtype=np.float64).reshape(g.ny, g.nx))
+        ph = g.MF(np.asarray(phi_s, dtype=np.float64).reshape(g.ny, g.nx))
+        stats = []
+        t = t0
+        for _ in range(n):
+            eh, ph = self.step_hat(eh, ph, dt, tol, stats)
+            t += dt
+            if self.rz is not None:
+                eh, ph = self.apply_relaxation(eh, ph, t)
+        return g.ifft(eh), g.ifft(ph), stats
+
+    # ------------------------------------------------------------------------
+    # Diagnostics, Eq. (energy)
+    # ------------------------------------------------------------------------
+    def diagnostics(self, eta, phi_s, tol=1e-10):
+        """(mass, energy) = (dA sum eta, dA/2 sum (V phi_s + eta^2)) at the masked state."""
+        g = self.g
+        eh = g.MF(eta)
+        ph = g.MF(phi_s)
+        e = g.ifft(eh)
+        p = g.ifft(ph)
+        Vh, _ = self.solve_hat(e, ph, tol)
+        V = g.ifft(Vh)
+        mass = g.dA * float(np.sum(e))
+        energy = 0.5 * g.dA * float(np.sum(V * p + e * e))
+        return mass, energy
+
+
+# ---------------------------------------------------------------------------
+# Second, independent coding: the explicit orders of Appendix C written out
+# term by term (Eqs. v2-v7).  Used only to cross-check Solver.w_sa_hat.
+# ---------------------------------------------------------------------------
+def w_sa_appc(solver: Solver, eta, phi_s, L: int = 7):
+    g = solver.g
+    k, T, S = g.k, solver.T, solver.S
+    d = solver.delta
+    ph = g.MF(phi_s)
+    with np.errstate(divide="ignore"):
+        kinv = np.where(k > 0, 1.0 / np.where(k > 0, k, 1.0), 0.0)
+
+    def F(f):
+        return g.MF(f)
+
+    def ik(fx, fy):
+        return g.ikdot(fx, fy)
+
+    gx, gy = g.grad(ph)
+
+    def eg(p):  # F{eta^p grad phi_s} as a pair
+        return F(eta ** p * gx), (F(eta ** p * gy) if gy is not None else None)
+
+    def dgB(p, B):  # F{delta^p grad phi_b} as a pair
+        bx, by = g.grad(B)
+        return F(d ** p * bx), (F(d ** p * by) if by is not None else None)
+
+    def eV(p, V):  # F{eta^p V}
+        return F(eta ** p * g.ifft(V))
+
+    def lin(a, pa, b, pb):  # a*pa + b*pb for pairs
+        x = a * pa[0] + b * pb[0]
+        y = None if pa[1] is None else a * pa[1] + b * pb[1]
+        return x, y
+
+    V1 = k * T * ph
+    B1 = S * ph
+    # Eq. (v2)
+    V2 = -k * T * eV(1, V1) - ik(*lin(1.0, eg(1), -S, dgB(1, B1)))
+    B2 = -S * eV(1, V1) - kinv * T * ik(*dgB(1, B1))
+    # third order
+    V3 = -k * T * eV(1, V2) - 0.5 * k ** 2 * eV(2, V1) \
+        - ik(*lin(0.5 * k * T, eg(2), -S, dgB(1, B2)))
+    t1 = lin(-0.5 * S, eg(2), -kinv * T, dgB(1, B2))
+    t2 = dgB(2, B1)
+    B3 = -S * eV(1, V2) + ik(*lin(1.0, t1, 0.5, t2))
+    # fourth order
+    V4 = -T * (k * eV(1, V3) + k ** 3 / 6 * eV(3, V1)) - 0.5 * k ** 2 * eV(2, V2) \
+        - ik(*lin(k ** 2 / 6, eg(3), -S, lin(1.0, dgB(1, B3), k ** 2 / 6, dgB(3, B1))))
+    B4 = -S * (eV(1, V3) + k ** 2 / 6 * eV(3, V1)) \
+        + ik(*lin(0.5, dgB(2, B2), -T, lin(kinv, dgB(1, B3), k / 6, dgB(3, B1))))
+    # fifth order
+    V5 = -T * (k * eV(1, V4) + k ** 3 / 6 * eV(3, V2)) - 0.5 * k ** 2 * eV(2, V3) \
+        - k ** 4 / 24 * eV(4, V1) \
+        + ik(*lin(-k ** 3 / 24 * T, eg(4), S, lin(1.0, dgB(1, B4), k ** 2 / 6, dgB(3, B2))))
+    B5 = -S * (eV(1, V4) + k ** 2 / 6 * eV(3, V2)) \
+        + ik(*lin(1.0, lin(-k ** 2 / 24 * S, eg(4), -T, lin(kinv, dgB(1, B4), k / 6, dgB(3, B2))),
+                  1.0, lin(0.5, dgB(2, B3), k ** 2 / 24, dgB(4, B1))))
+    # sixth order
+    V6 = -T * (k * eV(1, V5) + k ** 3 / 6 * eV(3, V3) + k ** 5 / 120 * eV(5, V1)) \
+        - 0.5 * k ** 2 * eV(2, V4) - k ** 4 / 24 * eV(4, V2) \
+        + ik(*lin(-k ** 4 / 120, eg(5), S,
+                  lin(1.0, lin(1.0, dgB(1, B5), k ** 2 / 6, dgB(3, B3)), k ** 4 / 120, dgB(5, B1))))
+    B6 = -S * (eV(1, V5) + k ** 2 / 6 * eV(3, V3) + k ** 4 / 120 * eV(5, V1)) \
+        + ik(*lin(-T, lin(1.0, lin(kinv, dgB(1, B5), k / 6, dgB(3, B3)), k ** 3 / 120, dgB(5, B1)),
+                  1.0, lin(0.5, dgB(2, B4), k ** 2 / 24, dgB(4, B2))))
+    # Eq. (v7)
+    V7 = -T * (k * eV(1, V6) + k ** 3 / 6 * eV(3, V4) + k ** 5 / 120 * eV(5, V2)) \
+        - 0.5 * k ** 2 * eV(2, V5) - k ** 4 / 24 * eV(4, V3) - k ** 6 / 720 * eV(6, V1) \
+        + ik(*lin(-k ** 5 / 720 * T, eg(6), S,
+                  lin(1.0, lin(1.0, dgB(1, B6), k ** 2 / 6, dgB(3, B4)), k ** 4 / 120, dgB(5, B2))))
+    Vs = [V1, V2, V3, V4, V5, V6, V7][:L]
+    return g.ifft(sum(Vs))
