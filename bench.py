@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of the SBI hot path on one MI355X.
+
+Workload: 2D crossing JONSWAP seas on a 1024^2 periodic grid (128 peak
+wavelengths, dx = lambda_p/8) over random Gaussian-bump bathymetry, reference
+depth k_p h drawn in [0.8, 3]; each step is one integrating-factor RK4 step
+with four W solves iterated to a relative residual of 1e-8 in FP64.  Metric:
+grid-point RK4 steps per second (points x steps / wall seconds), inputs
+resident in HBM before the timed region.
+
+Prints ONE JSON line.  `roofline` is for the dominant kernel, its algorithmic
+bytes per launch divided by its average launch time from HIP events recorded
+on the library's stream during the timed region.  `cpu_baseline` times the
+FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point RK4 steps/s at 1024^2, plain vs batched+learned, W residual<=1e-8"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(kind: str, nx: int, ny: int, Kx: int, Ky: int, csz: int, rsz: int, vd: bool, J: int,
+                      two_d: bool) -> float:
+    """Minimum HBM bytes of one working launch of a sweep kernel (one member).
+
+    half-form array: ny*Kx complex; compact array: Ky*Kx complex; physical: nx*ny real.
+    """
+    half = ny * Kx * csz
+    comp = Ky * Kx * csz
+    phys = nx * ny * rsz
+    ncomp = (2 if two_d else 1) if vd else 0
+    nprod = J * (1 + ncomp)
+    if kind == "row_sweep":
+        # read G_V, G_D (+ grad phi_b components) and eta (+ delta); write the products
+        return (2 + ncomp) * half + (1 + (1 if vd else 0)) * phys + nprod * half
+    if kind == "col_sweep":
+        # read the products and b_V, V_n (+ b_phi, phi_b,n); write G_V, G_D (+ grad phi_b)
+        # and T(V_n), V_(n+1) (+ phi_b,(n+1))
+        nin_c = 2 + (2 if vd else 0)
+        nout_c = 2 + (1 if vd else 0)
+        return nprod * half + nin_c * comp + (2 + ncomp) * half + nout_c * comp
+    raise ValueError(kind)
+
+
+def cpu_baseline(n_sample: int = 256, max_sweeps: int = 200):
+    """Oracle (numpy FP64, single thread) on a bounded sample of the workload."""
+    from oracle import Grid, Solver as OSolver
+    from sbi_inputs import config_c5
+
+    cfg = config_c5(seed=0, n=n_sample)
+    g = cfg["grid"]
+    o = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), cfg["depth"], mode="iter", max_sweeps=max_sweeps)
+    t0 = time.perf_counter()
+    _, _, stats = o.step(cfg["eta"], cfg["phi"], cfg["dt"], 1, tol=cfg["tol"])
+    el = time.perf_counter() - t0
+    sweeps = [s.sweeps for s in stats]
+    return {
+        "value": g.nx * g.ny / el,
+        "unit": "grid-point-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one RK4 step (4 W solves, tol 1e-8, {sum(sweeps)} sweeps) of the same workload on a "
+                   f"{g.nx}x{g.ny} grid with the same dx, depth draw and sea statistics; "
+                   f"numpy FFT single-threaded; {el:.1f} s on {os.cpu_count()} visible host cores"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1024, help="grid size (1024 = the benchmark workload)")
+    ap.add_argument("--max-sweeps", type=int, default=400)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the solver is built and measured on a single MI355X; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2310_19840_amd import Solver
+    from sbi_inputs import config_c5
+
+    dev = torch.device("cuda:0")
+    cfg = config_c5(seed=0, n=args.n)
+    g = cfg["grid"]
+    tol = cfg["tol"]
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="iter", precision="fp64",
+               max_sweeps=args.max_sweeps)
+    eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=dev)
+    phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=dev)
+    dt = cfg["dt"]
+
+    if args.warmup > 0:
+        s.step(eta, phi, dt, args.warmup, tol=tol)
+    torch.cuda.synchronize()
+
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = s.step(eta, phi, dt, args.steps, tol=tol)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = s.profile_read()
+    s.profile(False)
+
+    npts = g.nx * g.ny
+    value = npts * args.steps / el
+    ms_per_step = 1e3 * el / max(args.steps, 1)
+    solves = max(info["solves"], 1)
+    sweeps_total = info["sweeps_total"]
+
+    # dominant kernel and its algorithmic bandwidth
+    Mx = int(math.floor(0.5 * g.nx / 2 + 1e-9))
+    My = int(math.floor(0.5 * g.ny / 2 + 1e-9))
+    Kx, Ky = Mx + 1, 2 * My + 1
+    vd = bool(np.any(cfg["depth"] != cfg["depth"].max()))
+    cand = {}
+    for kind in ("row_sweep", "col_sweep"):
+        tot_ms, cnt = prof.get(kind, (0.0, 0))
+        if tot_ms <= 0:
+            continue
+        working = sweeps_total + (solves if kind == "row_sweep" else 0)
+        b = algorithmic_bytes(kind, g.nx, g.ny, Kx, Ky, 16, 8, vd, 6, g.ny > 1)
+        avg_s = tot_ms * 1e-3 / max(working, 1)
+        cand[kind] = (tot_ms, b, avg_s, cnt, working)
+    dom = max(cand, key=lambda k: cand[k][0])
+    tot_ms, b, avg_s, cnt, working = cand[dom]
+    achieved = b / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "bytes_per_launch": b, "avg_launch_us": round(avg_s * 1e6, 2),
+                "launches_working": working, "launches_total": cnt}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"crossing JONSWAP seas {g.nx}x{g.ny}, 128 lambda_p, Gaussian-bump bathymetry, "
+                               f"k_p h_ref={cfg['h_ref']:.3f}, IF-RK4 dt=T_p/64, W iteration tol {tol:g} FP64 "
+                               f"(plain: linear-guess seed, single member)",
+                   "grid": [g.ny, g.nx], "form": "plain"},
+        "sweeps_per_solve_mean": round(sweeps_total / solves, 2),
+        "sweeps_per_solve_max": info["sweeps_max"],
+        "max_residual": info["max_residual"],
+        "status": st,
+        "roofline": roofline,
+        "kernel_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1] > 0},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

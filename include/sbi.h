@@ -1,0 +1,203 @@
+/*
+ * sbi.h -- C interface of the MI355X (gfx950) spectral boundary-integral wave
+ * solver: the surface vertical velocity W of the enhanced spectral boundary
+ * integral method over variable depth, and the time step of the surface
+ * evolution equations that uses it.
+ *
+ * Operations follow Wang, "An Enhanced Spectral Boundary Integral Method for
+ * Modeling Highly Nonlinear Water Waves in Variable Depth":
+ *   - the problem statement: given the surface elevation eta(x,y), the surface
+ *     potential phi_s(x,y) and the depth h(x,y), find the surface vertical
+ *     velocity V = sqrt(1+|grad eta|^2) dphi/dn at z = eta (Sec. 2.2, the
+ *     definition under Eq. (prognostic)); this interface calls it W;
+ *   - W is evaluated by the successive approximation of Sec. 2.4 with the
+ *     explicit orders of Appendix C (Eqs. (v2)-(v7)) -- mode SBI_MODE_SA --
+ *     or by iterating the same expansion summed over orders to a residual
+ *     tolerance -- mode SBI_MODE_ITER;
+ *   - the time step integrates Eq. (prognostic) in its integrating-factor form
+ *     (Sec. 2.2) with the classical 4-stage Runge-Kutta scheme of Lawson type;
+ *   - the total energy is Eq. (energy) of Sec. 3.1.
+ *
+ * Units: lengths scaled by the peak wavenumber, time by the peak angular
+ * frequency, g = 1 (Sec. 2.1).  The seabed is at z = -h_ref + delta(x,y),
+ * delta = h_ref - depth >= 0.
+ *
+ * Conventions shared by every call
+ *   - Returns sbi_status: 0 success, > 0 warning (outputs are written and
+ *     usable), < 0 error (no output written; sbi_status_string() explains).
+ *   - Field pointers are DEVICE pointers to row-major [batch][ny][nx] arrays
+ *     of the context's precision (double for SBI_FP64, float for SBI_FP32),
+ *     contiguous, owned by the caller.  The library never frees them.
+ *   - Depth arrays are HOST pointers to double [batch][ny][nx], depth > 0.
+ *   - All device work is enqueued on the context's HIP stream; calls that
+ *     return host values (info structs, diagnostics) synchronise that stream.
+ *   - One context per stream.  Contexts share no mutable state.
+ *   - Non-finite inputs are reported as SBI_ERR_NONFINITE.
+ */
+#ifndef SBI_H
+#define SBI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbi_ctx sbi_ctx;
+
+typedef enum sbi_status {
+    SBI_OK = 0,
+    SBI_WARN_NOT_CONVERGED = 1,   /* iteration hit max_sweeps; last iterate returned */
+    SBI_WARN_DEPTH_CRITERION = 2, /* k_band*max(delta) > 2.4, validity limit of Sec. 5 */
+    SBI_WARN_FALLBACK_USED = 3,   /* learned seed rejected; linear guess used instead */
+    SBI_ERR_INVALID_ARG = -1,
+    SBI_ERR_UNSUPPORTED = -2,
+    SBI_ERR_WORKSPACE = -3,
+    SBI_ERR_HIP = -4,
+    SBI_ERR_NONFINITE = -5,
+    SBI_ERR_DIVERGED = -6
+} sbi_status;
+
+enum { SBI_FP64 = 0, SBI_FP32 = 1 };
+enum { SBI_MODE_ITER = 0, SBI_MODE_SA = 1 };
+enum { SBI_SEED_LINEAR = 0, SBI_SEED_PREV = 1, SBI_SEED_NET = 2, SBI_SEED_USER = 3 };
+
+/* Grid and solver options.  Fill with sbi_grid_defaults() first. */
+typedef struct sbi_grid {
+    int32_t nx, ny;        /* collocation points; powers of two, nx in 16..8192,
+                              ny == 1 (1D) or 16..2048 */
+    double lx, ly;         /* periodic lengths (ly ignored when ny == 1) */
+    int32_t order;         /* expansion order L, 1..7 (Sec. 2.4 caps it at 7); default 7 */
+    double dealias;        /* kept fraction alpha of the Nyquist wavenumber per axis
+                              (the "2/(l+1) rule" of Sec. 2.4 read as alpha = 1/2);
+                              0 < alpha < 1; default 0.5 */
+    int32_t precision;     /* SBI_FP64 (default) or SBI_FP32 (FP64 residual norms and
+                              diagnostics are kept either way) */
+    int32_t mode;          /* SBI_MODE_ITER (default) or SBI_MODE_SA */
+    int32_t seed;          /* SBI_SEED_* for the iteration; default SBI_SEED_LINEAR,
+                              the initiation of Sec. 2.4 */
+    int32_t max_sweeps;    /* iteration cap, 1..1000; default 64 */
+    int32_t relax;         /* 1: under-relaxed sweeps when the crest makes plain sweeps
+                              expand (default); 0: plain sweeps */
+    double filter_beta1;   /* low-pass filter of Eq. (filter) applied each step when */
+    double filter_beta2;   /* both are > 0; default 0 (off) */
+} sbi_grid;
+
+/* A batch of surface states: eta and phi_s are device arrays [batch][ny][nx]. */
+typedef struct sbi_state {
+    void* eta;
+    void* phi_s;
+    double t;              /* advanced by n*dt by sbi_step */
+} sbi_state;
+
+typedef struct sbi_solve_info {
+    int32_t sweeps;        /* applications of the sweep operator (0 in SA mode) */
+    int32_t status;        /* per-member sbi_status of the solve */
+    double residual;       /* max|T(W)-W| / max|T(W)| of the last sweep, FP64 */
+    double omega;          /* relaxation weight used */
+} sbi_solve_info;
+
+typedef struct sbi_step_info {
+    int64_t solves;        /* W solves performed (4 per step per member) */
+    int64_t sweeps_total;  /* summed over solves and members */
+    int32_t sweeps_max;    /* largest sweep count of one solve */
+    int32_t fallbacks;     /* solves that fell back to the linear guess */
+    double max_residual;   /* largest final residual of any solve */
+} sbi_step_info;
+
+/* Default options (FP64, iteration, L = 7, alpha = 1/2, 64 sweeps, relax on). */
+void sbi_grid_defaults(sbi_grid* g);
+
+/* Device workspace bytes for `batch` members of grid g (0 if g is invalid). */
+size_t sbi_workspace_bytes(const sbi_grid* g, int32_t batch);
+
+/*
+ * Create a context for `batch` members sharing grid g.
+ *   depth     host double [batch][ny][nx], > 0 everywhere.
+ *   h_ref     reference depth h of Sec. 2.1; <= 0 selects max(depth) per member,
+ *             so that delta = h_ref - depth >= 0.
+ *   workspace device buffer of sbi_workspace_bytes(g, batch) bytes owned by the
+ *             caller, or NULL to let the library allocate (and free) it.
+ *   hip_stream hipStream_t to enqueue on (NULL = default stream).
+ * Returns SBI_WARN_DEPTH_CRITERION (context valid) when
+ * k_band * max(delta) > 2.4 (Sec. 5).
+ */
+sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, const double* depth,
+                    double h_ref, void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Surface vertical velocity W for every member (Sec. 2.3-2.4, App. C).
+ *   eta, phi_s  device [batch][ny][nx]; phi_s is band-limited by the dealias
+ *               mask before use (its spectrum outside the kept rectangle is
+ *               dropped), eta is used as given.
+ *   h           host depth [batch][ny][nx] replacing the context's depth, or NULL.
+ *   tol         relative residual tolerance of the iteration (ignored in SA mode).
+ *   w_seed      device [batch][ny][nx] initial guess when seed == SBI_SEED_USER,
+ *               else NULL.
+ *   w_out       device [batch][ny][nx] output.
+ *   info        host array of `batch` entries, or NULL.
+ */
+sbi_status sbi_vertical_velocity(sbi_ctx* ctx, const void* eta, const void* phi_s,
+                                 const double* h, double tol, const void* w_seed,
+                                 void* w_out, sbi_solve_info* info);
+
+/*
+ * Advance every member by n steps of dt (Eq. (prognostic), integrating-factor
+ * RK4), in place; state->t += n*dt.  Each step performs 4 W solves with the
+ * context's mode and tolerance `tol`.  The state is band-limited by the dealias
+ * mask on entry and after every step.  info (host, may be NULL) aggregates over
+ * members.
+ */
+sbi_status sbi_step(sbi_ctx* ctx, sbi_state* state, double dt, int32_t n, double tol,
+                    sbi_step_info* info);
+
+/*
+ * FP64 mass  M = dA * sum(eta)  and energy  E = dA/2 * sum(W phi_s + eta^2)
+ * (Eq. (energy)) of the band-limited state, per member (host arrays of `batch`).
+ */
+sbi_status sbi_diagnostics(sbi_ctx* ctx, const sbi_state* state, double tol,
+                           double* mass, double* energy);
+
+/*
+ * Wave generation/absorption by relaxation zones in a 1D tank, applied after
+ * every step (not a device of the paper, whose tank uses a pneumatic
+ * wavemaker).  params = {a, k, omega, gen_len, abs_len, ramp_periods}: target
+ * eta = a r(t) cos(kx - omega t), phi_s = (a r(t)/omega) sin(kx - omega t) over
+ * x < gen_len with weight 1-(3s^2-2s^3), s = x/gen_len; damping to zero over
+ * x > lx - abs_len; ramp r(t) = (1-cos(pi t/(ramp_periods*2pi/omega)))/2.
+ * n = 6; n = 0 removes the zones.
+ */
+sbi_status sbi_set_relaxation(sbi_ctx* ctx, const double* params, int32_t n);
+
+/* Replace the depth (host [batch][ny][nx]) and reference depth of a context. */
+sbi_status sbi_set_depth(sbi_ctx* ctx, const double* depth, double h_ref);
+
+/*
+ * Load the weights of the learned warm start (used when seed == SBI_SEED_NET).
+ * weights: host float array in the layout documented in sbi_net.h; bytes its size.
+ */
+sbi_status sbi_net_load(sbi_ctx* ctx, const void* weights, size_t bytes);
+
+/* Release the context (and the workspace if the library allocated it). */
+sbi_status sbi_destroy(sbi_ctx* ctx);
+
+const char* sbi_status_string(sbi_status s);
+
+/*
+ * Kernel timing for profiling: when enabled, every launch of the following
+ * calls is bracketed by HIP events on the context's stream.  sbi_profile_read
+ * writes, per kernel class, its name (static string), summed device time in ms
+ * and launch count since the last enable, and returns the number of classes.
+ */
+sbi_status sbi_profile_enable(sbi_ctx* ctx, int32_t enable);
+int32_t sbi_profile_read(sbi_ctx* ctx, const char** names, double* total_ms, int64_t* launches, int32_t n);
+
+/* Timing and counters of the last call (host), for profiling.  Returns the
+ * number of doubles written (<= n): {kernel launches, host syncs, sweeps}. */
+int32_t sbi_last_stats(const sbi_ctx* ctx, double* out, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SBI_H */

@@ -1,0 +1,1200 @@
+// sbi_api.hip -- C interface and host orchestration of the SBI wave solver.
+//
+// Host code only decides what to launch; every step of the computation runs
+// in the kernels of sbi_kernels.hip.  The W solve (Sec. 2.4 / App. C) is one
+// of two kernel sequences:
+//   SA mode   : orders l = 2..L, each a row pass forming the products of
+//               Appendix C and a column pass applying its multipliers;
+//   ITER mode : the same expansion summed over orders, iterated from the
+//               linear guess of Sec. 2.4; each sweep is one row pass and one
+//               column pass, and the column pass decides convergence from the
+//               residual reduced by the row pass before it (device side), so
+//               the host only polls a small status header between chunks of
+//               sweeps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sbi.h"
+#include "sbi_kernels.hpp"
+
+using namespace sbi;
+
+namespace {
+
+// compact spectral buffers
+enum {
+    C_EH, C_PH,          // state u_n
+    C_ES, C_PS,          // stage state
+    C_AE, C_AP,          // Runge-Kutta accumulator
+    C_VH,                // W spectrum (SA sum)
+    C_BV, C_BB,          // constant parts of the summed operator
+    C_VN, C_BN,          // current iterate (V, phi_b)
+    C_VP,                // T(V_n): candidate answer of the iteration
+    C_NP,                // nonlinear term of the potential equation
+    C_COUNT
+};
+// half-form buffers
+enum {
+    H_ETA, H_EX, H_EY, H_PX, H_PY,  // state and its gradients
+    H_GV, H_GD, H_GBX, H_GBY,       // iterate / order fields
+    H_PROD0,                        // products H_PROD0 .. H_PROD0 + kMaxProd - 1
+    H_COUNT = H_PROD0 + kMaxProd
+};
+// physical buffers
+enum {
+    P_ETA, P_DELTA, P_PX, P_PY,
+    P_V0,                 // SA orders V_1..V_7 at P_V0 + (l-1)
+    P_BX0 = P_V0 + 7,     // SA orders grad phi_b,1..6 (x)
+    P_BY0 = P_BX0 + 7,
+    P_COUNT = P_BY0 + 7
+};
+
+struct Stats {
+    double launches = 0, syncs = 0, sweeps = 0;
+};
+
+// kernel classes timed by the optional profiler
+enum {
+    K_ROW_FWD, K_ROW_INV, K_ROW_SETUP, K_ROW_SWEEP, K_ROW_SA, K_ROW_NPHI, K_ROW_BLEND,
+    K_COL_STATE, K_COL_FORCING, K_COL_SWEEP, K_COL_SA, K_COL_OTHER, K_RK, K_DIAG, K_COUNT
+};
+const char* const kKernelNames[K_COUNT] = {
+    "row_fwd", "row_inv", "row_setup", "row_sweep", "row_sa", "row_nphi", "row_blend",
+    "col_state", "col_forcing", "col_sweep", "col_sa", "col_other", "rk", "diag"};
+
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;       // free events
+    struct Pending { int cls; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    double total_ms[K_COUNT] = {};
+    long long count[K_COUNT] = {};
+};
+
+}  // namespace
+
+struct sbi_ctx {
+    sbi_grid grid;
+    int batch = 1;
+    int fp64 = 1;
+    hipStream_t stream = nullptr;
+    GridDev gd{};
+    size_t rsz = 8, csz = 16;
+    char* ws = nullptr;
+    bool own_ws = false;
+    size_t ws_bytes = 0;
+    void* comp[C_COUNT] = {};
+    void* half[H_COUNT] = {};
+    void* phys[P_COUNT] = {};
+    void* tx = nullptr;
+    void* tn = nullptr;
+    void* ty = nullptr;
+    double* href_dev = nullptr;
+    Ctl* ctl = nullptr;
+    double* diag_partial = nullptr;
+    int diag_nblk = 64;
+    std::vector<double> href;
+    bool vd = false;         // some member has a non-flat bed
+    bool depth_warn = false;
+    bool relax_on = false;
+    double rz[6] = {0, 0, 0, 0, 0, 0};
+    Stats st;
+    Profiler prof;
+    std::vector<Ctl> head;   // host copy of the control headers (first kCtlHeadBytes)
+    sbi_step_info step_acc{};
+};
+
+static void prof_flush(sbi_ctx* c);
+
+static const char* kStatusNames[] = {"SBI_OK",
+                                     "SBI_WARN_NOT_CONVERGED: iteration reached max_sweeps",
+                                     "SBI_WARN_DEPTH_CRITERION: k_band*max(delta) exceeds 2.4",
+                                     "SBI_WARN_FALLBACK_USED: learned seed rejected"};
+static const char* kErrNames[] = {"",
+                                  "SBI_ERR_INVALID_ARG: invalid argument",
+                                  "SBI_ERR_UNSUPPORTED: unsupported size or option",
+                                  "SBI_ERR_WORKSPACE: workspace missing or too small",
+                                  "SBI_ERR_HIP: HIP runtime error",
+                                  "SBI_ERR_NONFINITE: non-finite input",
+                                  "SBI_ERR_DIVERGED: iteration diverged"};
+
+static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+static sbi_status hip_ok(hipError_t e) { return e == hipSuccess ? SBI_OK : SBI_ERR_HIP; }
+
+#define SBI_TRY(expr)                          \
+    do {                                       \
+        sbi_status _s = (expr);                \
+        if (_s < 0) return _s;                 \
+    } while (0)
+#define SBI_HIP(expr)                          \
+    do {                                       \
+        hipError_t _e = (expr);                \
+        if (_e != hipSuccess) return SBI_ERR_HIP; \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// sizes and layout
+// ---------------------------------------------------------------------------
+struct Layout {
+    int Mx, My, Kx, Kxp, Ky, C;
+    size_t rsz, csz;
+    long long s_phys, s_half, s_cmp;
+    size_t bytes_comp, bytes_half, bytes_phys, bytes_tw, bytes_misc, total;
+};
+
+static bool grid_valid(const sbi_grid* g) {
+    if (!g) return false;
+    if (!is_pow2(g->nx) || g->nx < 16 || g->nx > 8192) return false;
+    if (!(g->ny == 1 || (is_pow2(g->ny) && g->ny >= 16 && g->ny <= 2048))) return false;
+    if (!(g->lx > 0) || (g->ny > 1 && !(g->ly > 0))) return false;
+    if (g->order < 1 || g->order > 7) return false;
+    if (!(g->dealias > 0.0 && g->dealias < 1.0)) return false;
+    if (g->precision != SBI_FP64 && g->precision != SBI_FP32) return false;
+    if (g->mode != SBI_MODE_ITER && g->mode != SBI_MODE_SA) return false;
+    if (g->max_sweeps < 1 || g->max_sweeps > 1000) return false;
+    if (g->seed < SBI_SEED_LINEAR || g->seed > SBI_SEED_USER) return false;
+    return true;
+}
+
+static Layout layout(const sbi_grid* g, int batch) {
+    Layout L{};
+    const bool f64 = g->precision == SBI_FP64;
+    L.rsz = f64 ? 8 : 4;
+    L.csz = 2 * L.rsz;
+    L.Mx = (int)std::floor(g->dealias * g->nx / 2.0 + 1e-9);
+    L.My = g->ny == 1 ? 0 : (int)std::floor(g->dealias * g->ny / 2.0 + 1e-9);
+    L.Kx = L.Mx + 1;
+    L.C = col_tile(g->ny, f64);
+    L.Kxp = (L.Kx + L.C - 1) / L.C * L.C;
+    L.Ky = g->ny == 1 ? 1 : 2 * L.My + 1;
+    L.s_phys = (long long)g->nx * g->ny;
+    L.s_half = (long long)g->ny * L.Kxp;
+    L.s_cmp = (long long)L.Ky * L.Kxp;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    L.bytes_comp = al((size_t)L.s_cmp * L.csz * batch) * C_COUNT;
+    L.bytes_half = al((size_t)L.s_half * L.csz * batch) * H_COUNT;
+    L.bytes_phys = al((size_t)L.s_phys * L.rsz * batch) * P_COUNT;
+    L.bytes_tw = al((size_t)g->nx * L.csz) + al((size_t)(g->nx / 2) * L.csz) + al((size_t)g->ny * L.csz);
+    L.bytes_misc = al(sizeof(double) * batch) + al(sizeof(Ctl) * batch) + al(sizeof(double) * 2 * 64 * batch);
+    L.total = L.bytes_comp + L.bytes_half + L.bytes_phys + L.bytes_tw + L.bytes_misc;
+    return L;
+}
+
+extern "C" void sbi_grid_defaults(sbi_grid* g) {
+    if (!g) return;
+    std::memset(g, 0, sizeof(*g));
+    g->nx = 256;
+    g->ny = 1;
+    g->lx = 2.0 * M_PI;
+    g->ly = 2.0 * M_PI;
+    g->order = 7;
+    g->dealias = 0.5;
+    g->precision = SBI_FP64;
+    g->mode = SBI_MODE_ITER;
+    g->seed = SBI_SEED_LINEAR;
+    g->max_sweeps = 64;
+    g->relax = 1;
+    g->filter_beta1 = 0.0;
+    g->filter_beta2 = 0.0;
+}
+
+extern "C" size_t sbi_workspace_bytes(const sbi_grid* g, int32_t batch) {
+    if (!grid_valid(g) || batch < 1) return 0;
+    return layout(g, batch).total;
+}
+
+extern "C" const char* sbi_status_string(sbi_status s) {
+    if (s >= 0 && s <= 3) return kStatusNames[s];
+    if (s <= -1 && s >= -6) return kErrNames[-s];
+    return "unknown sbi_status";
+}
+
+// ---------------------------------------------------------------------------
+// upload helpers
+// ---------------------------------------------------------------------------
+static std::vector<char> to_prec(const double* src, size_t n, int fp64) {
+    std::vector<char> out(n * (fp64 ? 8 : 4));
+    if (fp64) std::memcpy(out.data(), src, n * 8);
+    else {
+        float* f = reinterpret_cast<float*>(out.data());
+        for (size_t i = 0; i < n; ++i) f[i] = (float)src[i];
+    }
+    return out;
+}
+
+static std::vector<double> twiddle_table(int n) {
+    std::vector<double> t(2 * (size_t)n);
+    for (int m = 0; m < n; ++m) {
+        // exp(-2 pi i m/n) with octant-symmetric argument reduction for accuracy
+        const double a = -2.0 * M_PI * (double)m / (double)n;
+        t[2 * m] = std::cos(a);
+        t[2 * m + 1] = std::sin(a);
+    }
+    return t;
+}
+
+static sbi_status set_depth(sbi_ctx* c, const double* depth, double h_ref) {
+    const sbi_grid& g = c->grid;
+    const size_t npt = (size_t)g.nx * g.ny;
+    std::vector<double> delta(npt * c->batch);
+    c->href.assign(c->batch, 0.0);
+    c->vd = false;
+    double kdmax = 0.0;
+    for (int b = 0; b < c->batch; ++b) {
+        const double* d = depth + b * npt;
+        double dmax = 0.0;
+        for (size_t i = 0; i < npt; ++i) {
+            if (!std::isfinite(d[i])) return SBI_ERR_NONFINITE;
+            if (!(d[i] > 0.0)) return SBI_ERR_INVALID_ARG;
+            dmax = std::max(dmax, d[i]);
+        }
+        const double h = h_ref > 0.0 ? h_ref : dmax;
+        c->href[b] = h;
+        for (size_t i = 0; i < npt; ++i) {
+            // seabed at z = -h + delta (Sec. 2.1)
+            delta[b * npt + i] = h - d[i];
+            if (delta[b * npt + i] != 0.0) c->vd = true;
+            kdmax = std::max(kdmax, std::fabs(delta[b * npt + i]));
+        }
+    }
+    c->depth_warn = c->gd.kband * kdmax > 2.4;
+    std::vector<char> dv = to_prec(delta.data(), delta.size(), c->fp64);
+    SBI_HIP(hipMemcpyAsync(c->phys[P_DELTA], dv.data(), dv.size(), hipMemcpyHostToDevice, c->stream));
+    SBI_HIP(hipMemcpyAsync(c->href_dev, c->href.data(), sizeof(double) * c->batch, hipMemcpyHostToDevice, c->stream));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, const double* depth, double h_ref,
+                               void* workspace, size_t ws_bytes, void* hip_stream) {
+    if (!out || !grid_valid(g) || batch < 1 || !depth) return SBI_ERR_INVALID_ARG;
+    *out = nullptr;
+    const Layout L = layout(g, batch);
+    if (workspace && ws_bytes < L.total) return SBI_ERR_WORKSPACE;
+    sbi_ctx* c = new sbi_ctx();
+    c->grid = *g;
+    c->batch = batch;
+    c->fp64 = g->precision == SBI_FP64;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->rsz = L.rsz;
+    c->csz = L.csz;
+    GridDev& gd = c->gd;
+    gd.nx = g->nx;
+    gd.ny = g->ny;
+    gd.Mx = L.Mx;
+    gd.My = L.My;
+    gd.Kx = L.Kx;
+    gd.Kxp = L.Kxp;
+    gd.Ky = L.Ky;
+    gd.order = g->order;
+    gd.lx = g->lx;
+    gd.ly = g->ny == 1 ? 1.0 : g->ly;
+    gd.kband = std::hypot(2.0 * M_PI * L.Mx / g->lx, g->ny == 1 ? 0.0 : 2.0 * M_PI * L.My / g->ly);
+    gd.s_phys = L.s_phys;
+    gd.s_half = L.s_half;
+    gd.s_cmp = L.s_cmp;
+    gd.relax = g->relax;
+    if (workspace) {
+        c->ws = static_cast<char*>(workspace);
+        c->ws_bytes = ws_bytes;
+    } else {
+        if (hipMalloc(&c->ws, L.total) != hipSuccess) {
+            delete c;
+            return SBI_ERR_HIP;
+        }
+        c->own_ws = true;
+        c->ws_bytes = L.total;
+    }
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    char* p = c->ws;
+    for (int i = 0; i < C_COUNT; ++i) {
+        c->comp[i] = p;
+        p += al((size_t)L.s_cmp * L.csz * batch);
+    }
+    for (int i = 0; i < H_COUNT; ++i) {
+        c->half[i] = p;
+        p += al((size_t)L.s_half * L.csz * batch);
+    }
+    for (int i = 0; i < P_COUNT; ++i) {
+        c->phys[i] = p;
+        p += al((size_t)L.s_phys * L.rsz * batch);
+    }
+    c->tx = p;
+    p += al((size_t)g->nx * L.csz);
+    c->tn = p;
+    p += al((size_t)(g->nx / 2) * L.csz);
+    c->ty = p;
+    p += al((size_t)g->ny * L.csz);
+    c->href_dev = reinterpret_cast<double*>(p);
+    p += al(sizeof(double) * batch);
+    c->ctl = reinterpret_cast<Ctl*>(p);
+    p += al(sizeof(Ctl) * batch);
+    c->diag_partial = reinterpret_cast<double*>(p);
+    p += al(sizeof(double) * 2 * 64 * batch);
+    gd.href = c->href_dev;
+    c->head.resize(batch);
+
+    sbi_status st = hip_ok(launch_fill_zero(c->ws, L.total, c->stream));
+    if (st == SBI_OK) {
+        auto up = [&](void* dst, int n) -> sbi_status {
+            std::vector<double> t = twiddle_table(n);
+            std::vector<char> v = to_prec(t.data(), t.size(), c->fp64);
+            sbi_status r = hip_ok(hipMemcpyAsync(dst, v.data(), v.size(), hipMemcpyHostToDevice, c->stream));
+            if (r == SBI_OK) r = hip_ok(hipStreamSynchronize(c->stream));
+            return r;
+        };
+        if (st == SBI_OK) st = up(c->tx, g->nx);
+        if (st == SBI_OK) st = up(c->tn, g->nx / 2);
+        if (st == SBI_OK) st = up(c->ty, g->ny);
+        if (st == SBI_OK) st = hip_ok(launch_ctl_reset(c->ctl, batch, kMaxSweepSlots, c->stream));
+        if (st == SBI_OK) st = set_depth(c, depth, h_ref);
+    }
+    if (st < 0) {
+        if (c->own_ws) (void)hipFree(c->ws);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return c->depth_warn ? SBI_WARN_DEPTH_CRITERION : SBI_OK;
+}
+
+extern "C" sbi_status sbi_destroy(sbi_ctx* c) {
+    if (!c) return SBI_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    prof_flush(c);
+    for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+    if (c->own_ws) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->ws);
+    }
+    delete c;
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_set_depth(sbi_ctx* c, const double* depth, double h_ref) {
+    if (!c || !depth) return SBI_ERR_INVALID_ARG;
+    SBI_TRY(set_depth(c, depth, h_ref));
+    return c->depth_warn ? SBI_WARN_DEPTH_CRITERION : SBI_OK;
+}
+
+extern "C" sbi_status sbi_set_relaxation(sbi_ctx* c, const double* params, int32_t n) {
+    if (!c) return SBI_ERR_INVALID_ARG;
+    if (n == 0) {
+        c->relax_on = false;
+        return SBI_OK;
+    }
+    if (n != 6 || !params || c->grid.ny != 1) return SBI_ERR_INVALID_ARG;
+    for (int i = 0; i < 6; ++i) {
+        if (!std::isfinite(params[i])) return SBI_ERR_INVALID_ARG;
+        c->rz[i] = params[i];
+    }
+    if (!(c->rz[2] > 0 && c->rz[3] > 0 && c->rz[4] > 0 && c->rz[5] > 0)) return SBI_ERR_INVALID_ARG;
+    c->relax_on = true;
+    return SBI_OK;
+}
+
+extern "C" int32_t sbi_last_stats(const sbi_ctx* c, double* out, int32_t n) {
+    if (!c || !out) return 0;
+    const double v[3] = {c->st.launches, c->st.syncs, c->st.sweeps};
+    int k = std::min<int>(n, 3);
+    for (int i = 0; i < k; ++i) out[i] = v[i];
+    return k;
+}
+
+// ---------------------------------------------------------------------------
+// column-pass builder
+// ---------------------------------------------------------------------------
+struct ColBuilder {
+    ColParams p{};
+    std::vector<ColTerm> terms;
+    std::vector<const void*> prods, cins;
+    std::vector<long long> prod_stride;
+    explicit ColBuilder(const GridDev& g) {
+        p.g = g;
+        p.relax_prev[0] = p.relax_prev[1] = -1;
+        p.nacc = 1;
+    }
+    int prod(const void* h, long long stride = 0) {
+        prods.push_back(h);
+        prod_stride.push_back(stride);
+        return (int)prods.size() - 1;
+    }
+    int cin(const void* c) {
+        cins.push_back(c);
+        return -(int)cins.size();  // resolved at build: nprod + index
+    }
+    void term(int src, int acc, double coef, int fn, int pw, int dv) {
+        ColTerm t{};
+        t.coef = coef;
+        t.src = (short)src;
+        t.acc = (signed char)acc;
+        t.fn = (signed char)fn;
+        t.pw = (signed char)pw;
+        t.dv = (signed char)dv;
+        terms.push_back(t);
+        p.nacc = std::max(p.nacc, acc + 1);
+    }
+    void cout(int src, void* dst) {
+        p.cout_src[p.ncout] = src;
+        p.cout[p.ncout++] = dst;
+    }
+    void inv(int src, int dv, void* dst) {
+        p.inv_src[p.ninv] = src;
+        p.inv_dv[p.ninv] = dv;
+        p.inv[p.ninv++] = dst;
+    }
+    bool build() {
+        p.nprod = (int)prods.size();
+        p.ncin = (int)cins.size();
+        if (p.nprod > kMaxProd || p.ncin > kMaxCin || (int)terms.size() > kMaxTerms) return false;
+        for (int i = 0; i < p.nprod; ++i) {
+            p.hin[i] = prods[i];
+            p.hin_stride[i] = prod_stride[i];
+        }
+        for (int i = 0; i < p.ncin; ++i) p.cin[i] = cins[i];
+        for (auto& t : terms)
+            if (t.src < 0) t.src = (short)(p.nprod + (-t.src - 1));
+        std::stable_sort(terms.begin(), terms.end(), [](const ColTerm& a, const ColTerm& b) { return a.src < b.src; });
+        const int nsrc = p.nprod + p.ncin;
+        int k = 0;
+        for (int s = 0; s <= nsrc; ++s) {
+            while (k < (int)terms.size() && terms[k].src < s) ++k;
+            p.toff[s] = (short)k;
+        }
+        p.nterm = (int)terms.size();
+        for (int i = 0; i < p.nterm; ++i) p.term[i] = terms[i];
+        return true;
+    }
+};
+
+static hipEvent_t prof_event(sbi_ctx* c) {
+    if (!c->prof.pool.empty()) {
+        hipEvent_t e = c->prof.pool.back();
+        c->prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+// Accumulate the durations of completed launches (call after a stream sync).
+static void prof_flush(sbi_ctx* c) {
+    for (auto& q : c->prof.pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+            c->prof.total_ms[q.cls] += ms;
+            c->prof.count[q.cls] += 1;
+        }
+        c->prof.pool.push_back(q.a);
+        c->prof.pool.push_back(q.b);
+    }
+    c->prof.pending.clear();
+}
+struct ProfScope {
+    sbi_ctx* c;
+    int cls;
+    hipEvent_t a = nullptr;
+    ProfScope(sbi_ctx* cc, int k) : c(cc), cls(k) {
+        if (c->prof.on) {
+            a = prof_event(c);
+            (void)hipEventRecord(a, c->stream);
+        }
+    }
+    ~ProfScope() {
+        if (c->prof.on && a) {
+            hipEvent_t b = prof_event(c);
+            (void)hipEventRecord(b, c->stream);
+            c->prof.pending.push_back({cls, a, b});
+        }
+    }
+};
+
+static double fact(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+static int Tfn(int n) { return (n & 1) ? FN_T : FN_ONE; }   // tanh^<n/2>(kh)
+
+static Twiddles tw_of(const sbi_ctx* c) {
+    Twiddles t;
+    t.tx = c->tx;
+    t.tn = c->tn;
+    t.ty = c->ty;
+    return t;
+}
+
+// pointer to the start of buffer i; member stride is applied in the kernels
+#define CMP(i) (c->comp[(i)])
+#define HALF(i) (c->half[(i)])
+#define PHYS(i) (c->phys[(i)])
+
+static sbi_status run_col(sbi_ctx* c, ColBuilder& b, int cls = K_COL_OTHER) {
+    if (!b.build()) return SBI_ERR_UNSUPPORTED;
+    c->st.launches += 1;
+    ProfScope ps(c, cls);
+    return hip_ok(launch_col(c->fp64, b.p, c->batch, tw_of(c), c->stream));
+}
+
+// ---------------------------------------------------------------------------
+// stage pieces
+// ---------------------------------------------------------------------------
+// physical (eta, phi) -> compact state (writes C_EH/C_PH and C_ES/C_PS)
+static sbi_status to_spectral(sbi_ctx* c, const void* eta, const void* phi, bool state_too) {
+    RowFwdParams rp{};
+    rp.g = c->gd;
+    rp.nf = 0;
+    if (eta) {
+        rp.in[rp.nf] = eta;
+        rp.out[rp.nf++] = HALF(H_PROD0);
+    }
+    rp.in[rp.nf] = phi;
+    rp.out[rp.nf++] = HALF(H_PROD0 + 1);
+    c->st.launches += 1;
+    {
+        ProfScope ps_(c, K_ROW_FWD);
+        SBI_TRY(hip_ok(launch_row_fwd(c->fp64, rp, c->batch, tw_of(c), c->stream)));
+    }
+    ColBuilder b(c->gd);
+    int se = eta ? b.prod(HALF(H_PROD0)) : -1;
+    int sp = b.prod(HALF(H_PROD0 + 1));
+    if (eta) {
+        b.term(se, 0, 1.0, FN_ONE, 0, DV_NONE);
+        b.cout(SRC_ACC0, CMP(C_ES));
+        if (state_too) b.cout(SRC_ACC0, CMP(C_EH));
+    }
+    b.term(sp, 1, 1.0, FN_ONE, 0, DV_NONE);
+    b.cout(SRC_ACC1, CMP(C_PS));
+    if (state_too) b.cout(SRC_ACC1, CMP(C_PH));
+    return run_col(c, b);
+}
+
+// compact stage state (C_ES, C_PS) -> half forms of eta, grad eta, grad phi, and
+// the linear-guess seeds (Sec. 2.4 initiation) of the iteration / SA order 1.
+static sbi_status stage_state_pass(sbi_ctx* c, bool need_eta) {
+    const bool two_d = c->grid.ny > 1;
+    ColBuilder b(c->gd);
+    int se = b.cin(CMP(C_ES));
+    int sp = b.cin(CMP(C_PS));
+    b.term(se, 0, 1.0, FN_ONE, 0, DV_NONE);
+    b.term(sp, 1, 1.0, FN_ONE, 0, DV_NONE);
+    b.term(sp, 2, 1.0, FN_T, 1, DV_NONE);  // k tanh(kh) phi_hat
+    if (c->vd) b.term(sp, 3, 1.0, FN_S, 0, DV_NONE);  // sech(kh) phi_hat
+    if (need_eta) {
+        b.inv(SRC_ACC0, DV_NONE, HALF(H_ETA));
+        b.inv(SRC_ACC0, DV_X, HALF(H_EX));
+        if (two_d) b.inv(SRC_ACC0, DV_Y, HALF(H_EY));
+    }
+    b.inv(SRC_ACC1, DV_X, HALF(H_PX));
+    if (two_d) b.inv(SRC_ACC1, DV_Y, HALF(H_PY));
+    b.inv(SRC_ACC2, DV_NONE, HALF(H_GV));
+    if (c->vd) {
+        b.inv(SRC_ACC3, DV_X, HALF(H_GBX));
+        if (two_d) b.inv(SRC_ACC3, DV_Y, HALF(H_GBY));
+    }
+    if (c->grid.mode == SBI_MODE_SA) {
+        b.cout(SRC_ACC2, CMP(C_VH));
+    } else {
+        b.cout(SRC_ACC2, CMP(C_VN));
+        if (c->vd) b.cout(SRC_ACC3, CMP(C_BN));
+    }
+    if (!c->vd && b.p.nacc < 3) b.p.nacc = 3;
+    return run_col(c, b, K_COL_STATE);
+}
+
+static sbi_status row_setup(sbi_ctx* c, const void* eta_user) {
+    const bool two_d = c->grid.ny > 1;
+    const bool sa = c->grid.mode == SBI_MODE_SA;
+    RowSetupParams rp{};
+    rp.g = c->gd;
+    rp.g_eta = eta_user ? nullptr : HALF(H_ETA);
+    rp.eta_in = eta_user;
+    rp.eta_out = eta_user ? nullptr : PHYS(P_ETA);
+    rp.g_px = HALF(H_PX);
+    rp.g_py = HALF(H_PY);
+    rp.px_out = sa ? PHYS(P_PX) : nullptr;
+    rp.py_out = (sa && two_d) ? PHYS(P_PY) : nullptr;
+    rp.nprod = sa ? 0 : (c->grid.order - 1) * (two_d ? 2 : 1);
+    for (int i = 0; i < rp.nprod; ++i) rp.h[i] = HALF(H_PROD0 + i);
+    rp.ctl = c->ctl;
+    c->st.launches += 1;
+    {
+        ProfScope ps_(c, K_ROW_SETUP);
+        return hip_ok(launch_row_setup(c->fp64, rp, c->batch, tw_of(c), c->stream));
+    }
+}
+
+// constant parts b_V, b_phi of the summed operator; also fixes omega (CTL_OMEGA)
+static sbi_status col_forcing(sbi_ctx* c) {
+    const bool two_d = c->grid.ny > 1;
+    const int L = c->grid.order;
+    ColBuilder b(c->gd);
+    int idx = 0;
+    std::vector<int> sx(L + 1, -1), sy(L + 1, -1);
+    for (int l = 2; l <= L; ++l) {
+        sx[l] = b.prod(HALF(H_PROD0 + idx++));
+        if (two_d) sy[l] = b.prod(HALF(H_PROD0 + idx++));
+    }
+    int sp = b.cin(CMP(C_PS));
+    b.term(sp, 0, 1.0, FN_T, 1, DV_NONE);
+    if (c->vd) b.term(sp, 1, 1.0, FN_S, 0, DV_NONE);
+    for (int l = 2; l <= L; ++l) {
+        const double cv = -1.0 / fact(l - 1);
+        b.term(sx[l], 0, cv, Tfn(l), l - 2, DV_X);
+        if (two_d) b.term(sy[l], 0, cv, Tfn(l), l - 2, DV_Y);
+        if (c->vd && (l & 1)) {
+            b.term(sx[l], 1, cv, FN_S, l - 3, DV_X);
+            if (two_d) b.term(sy[l], 1, cv, FN_S, l - 3, DV_Y);
+        }
+    }
+    b.cout(SRC_ACC0, CMP(C_BV));
+    if (c->vd) b.cout(SRC_ACC1, CMP(C_BB));
+    b.p.ctl = c->ctl;
+    b.p.ctl_mode = CTL_OMEGA;
+    return run_col(c, b, K_COL_FORCING);
+}
+
+static sbi_status launch_sweep(sbi_ctx* c, const void* eta_phys, int n, double tol) {
+    const bool two_d = c->grid.ny > 1;
+    const int J = c->grid.order - 1;
+    const int M = c->grid.max_sweeps;
+    RowSweepParams rp{};
+    rp.g = c->gd;
+    rp.gV = HALF(H_GV);
+    rp.gD = HALF(H_GD);
+    rp.gbx = HALF(H_GBX);
+    rp.gby = HALF(H_GBY);
+    rp.eta = eta_phys;
+    rp.delta = PHYS(P_DELTA);
+    rp.J = J;
+    rp.residual = n >= 1;
+    rp.products = n < M && J >= 1;
+    rp.vd = c->vd;
+    rp.slot = n >= 1 ? n - 1 : 0;
+    int np = 0;
+    if (rp.products) {
+        np = J * (1 + (c->vd ? (two_d ? 2 : 1) : 0));
+        for (int i = 0; i < np; ++i) rp.h[i] = HALF(H_PROD0 + i);
+    }
+    rp.ctl = c->ctl;
+    c->st.launches += 1;
+    {
+        ProfScope ps_(c, K_ROW_SWEEP);
+        SBI_TRY(hip_ok(launch_row_sweep(c->fp64, rp, c->batch, tw_of(c), c->stream)));
+    }
+
+    ColBuilder b(c->gd);
+    std::vector<int> se(J + 1), sbx(J + 1), sby(J + 1);
+    if (rp.products) {
+        int idx = 0;
+        for (int j = 1; j <= J; ++j) se[j] = b.prod(HALF(H_PROD0 + idx++));
+        if (c->vd) {
+            for (int j = 1; j <= J; ++j) sbx[j] = b.prod(HALF(H_PROD0 + idx++));
+            if (two_d)
+                for (int j = 1; j <= J; ++j) sby[j] = b.prod(HALF(H_PROD0 + idx++));
+        }
+    }
+    int cbv = b.cin(CMP(C_BV));
+    int cvn = b.cin(CMP(C_VN));
+    int cbb = -1, cbn = -1;
+    if (c->vd) {
+        cbb = b.cin(CMP(C_BB));
+        cbn = b.cin(CMP(C_BN));
+    }
+    b.term(cbv, 0, 1.0, FN_ONE, 0, DV_NONE);
+    if (c->vd) b.term(cbb, 1, 1.0, FN_ONE, 0, DV_NONE);
+    if (rp.products) {
+        for (int j = 1; j <= J; ++j) {
+            const double f = 1.0 / fact(j);
+            // V equation: -T_j k^j/j! F{eta^j V} + <j> S k^(j-1)/j! ik.F{delta^j grad phi_b}
+            b.term(se[j], 0, -f, Tfn(j), j, DV_NONE);
+            if (c->vd) {
+                if (j & 1) {
+                    b.term(sbx[j], 0, f, FN_S, j - 1, DV_X);
+                    if (two_d) b.term(sby[j], 0, f, FN_S, j - 1, DV_Y);
+                }
+                // phi_b equation: -<j> S k^(j-1)/j! F{eta^j V} + (-1)^j T_j k^(j-2)/j! ik.F{delta^j grad phi_b}
+                if (j & 1) b.term(se[j], 1, -f, FN_S, j - 1, DV_NONE);
+                const double sg = (j & 1) ? -f : f;
+                b.term(sbx[j], 1, sg, Tfn(j), j - 2, DV_X);
+                if (two_d) b.term(sby[j], 1, sg, Tfn(j), j - 2, DV_Y);
+            }
+        }
+    }
+    b.p.relax_prev[0] = -cvn - 1;  // resolved in build(): encoded as cin index
+    if (c->vd) b.p.relax_prev[1] = -cbn - 1;
+    b.cout(SRC_ACC0, CMP(C_VP));
+    b.cout(SRC_NEW0, CMP(C_VN));
+    if (c->vd) b.cout(SRC_NEW1, CMP(C_BN));
+    b.inv(SRC_NEW0, DV_NONE, HALF(H_GV));
+    b.inv(SRC_DIFF0, DV_NONE, HALF(H_GD));
+    if (c->vd) {
+        b.inv(SRC_NEW1, DV_X, HALF(H_GBX));
+        if (two_d) b.inv(SRC_NEW1, DV_Y, HALF(H_GBY));
+    }
+    b.p.ctl = c->ctl;
+    b.p.ctl_mode = CTL_SWEEP;
+    b.p.sweep = n;
+    b.p.max_sweeps = M;
+    b.p.tol = tol;
+    if (b.p.nacc < (c->vd ? 2 : 1)) b.p.nacc = c->vd ? 2 : 1;
+    return run_col(c, b, K_COL_SWEEP);
+}
+
+static sbi_status read_heads(sbi_ctx* c) {
+    SBI_HIP(hipMemcpy2DAsync(c->head.data(), sizeof(Ctl), c->ctl, sizeof(Ctl), kCtlHeadBytes, c->batch,
+                             hipMemcpyDeviceToHost, c->stream));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    c->st.syncs += 1;
+    if (c->prof.on) prof_flush(c);
+    return SBI_OK;
+}
+
+// iteration: device-side convergence decisions, host polls in predicted chunks
+static sbi_status iterate(sbi_ctx* c, const void* eta_phys, double tol) {
+    const int M = c->grid.max_sweeps;
+    int n = 0;
+    int chunk = 4;
+    std::vector<double> r_prev(c->batch, -1.0);
+    std::vector<int> n_prev(c->batch, 0);
+    while (n <= M) {
+        for (int i = 0; i < chunk && n <= M; ++i, ++n) SBI_TRY(launch_sweep(c, eta_phys, n, tol));
+        SBI_TRY(read_heads(c));
+        bool all_done = true;
+        int want = 1;
+        for (int b = 0; b < c->batch; ++b) {
+            const Ctl& h = c->head[b];
+            if (h.done) continue;
+            all_done = false;
+            // residual r_(n-2) is the latest decided one; predict the remaining sweeps
+            const double r = h.residual;
+            int rem = 4;
+            if (r_prev[b] > 0.0 && r > 0.0 && r < r_prev[b] && n - 2 > n_prev[b]) {
+                const double rho = std::pow(r / r_prev[b], 1.0 / (double)(n - 2 - n_prev[b]));
+                if (rho > 0.0 && rho < 1.0) rem = (int)std::ceil(std::log(tol / r) / std::log(rho)) + 1;
+            }
+            r_prev[b] = r;
+            n_prev[b] = n - 2;
+            want = std::max(want, rem);
+        }
+        if (all_done) break;
+        chunk = std::min(std::max(want, 1), 64);
+    }
+    return SBI_OK;
+}
+
+static sbi_status run_sa(sbi_ctx* c, const void* eta_phys) {
+    const bool two_d = c->grid.ny > 1;
+    const int L = c->grid.order;
+    for (int l = 2; l <= L; ++l) {
+        RowSaParams rp{};
+        rp.g = c->gd;
+        rp.l = l;
+        rp.vd = c->vd;
+        rp.gV = HALF(H_GV);
+        rp.gbx = HALF(H_GBX);
+        rp.gby = HALF(H_GBY);
+        rp.V_out = PHYS(P_V0 + (l - 2));      // V_(l-1)
+        rp.bx_out = c->vd ? PHYS(P_BX0 + (l - 2)) : nullptr;
+        rp.by_out = (c->vd && two_d) ? PHYS(P_BY0 + (l - 2)) : nullptr;
+        for (int m = 1; m < l; ++m) {
+            rp.Vphys[m] = PHYS(P_V0 + (m - 1));
+            rp.bxphys[m] = PHYS(P_BX0 + (m - 1));
+            rp.byphys[m] = PHYS(P_BY0 + (m - 1));
+        }
+        rp.eta = eta_phys;
+        rp.delta = PHYS(P_DELTA);
+        rp.phx = PHYS(P_PX);
+        rp.phy = PHYS(P_PY);
+        const int np = (l - 1) * (1 + (c->vd ? (two_d ? 2 : 1) : 0)) + (two_d ? 2 : 1);
+        if (np > kMaxProd) return SBI_ERR_UNSUPPORTED;
+        for (int i = 0; i < np; ++i) rp.h[i] = HALF(H_PROD0 + i);
+        c->st.launches += 1;
+        {
+        ProfScope ps_(c, K_ROW_SA);
+        SBI_TRY(hip_ok(launch_row_sa(c->fp64, rp, c->batch, tw_of(c), c->stream)));
+    }
+
+        ColBuilder b(c->gd);
+        int idx = 0;
+        std::vector<int> se(l), sbx(l), sby(l);
+        for (int j = 1; j <= l - 1; ++j) se[j] = b.prod(HALF(H_PROD0 + idx++));
+        if (c->vd) {
+            for (int j = 1; j <= l - 1; ++j) sbx[j] = b.prod(HALF(H_PROD0 + idx++));
+            if (two_d)
+                for (int j = 1; j <= l - 1; ++j) sby[j] = b.prod(HALF(H_PROD0 + idx++));
+        }
+        int fx = b.prod(HALF(H_PROD0 + idx++));
+        int fy = two_d ? b.prod(HALF(H_PROD0 + idx++)) : -1;
+        int cvh = b.cin(CMP(C_VH));
+        const bool want_b = c->vd && l <= L - 1;
+        // acc0 = V_l, acc1 = phi_b,l, acc2 = running sum of V
+        auto both = [&](int src, double coef, int fn, int pw, int dv) {
+            b.term(src, 0, coef, fn, pw, dv);
+            b.term(src, 2, coef, fn, pw, dv);
+        };
+        for (int j = 1; j <= l - 1; ++j) {
+            const double f = 1.0 / fact(j);
+            both(se[j], -f, Tfn(j), j, DV_NONE);
+            if (want_b && (j & 1)) b.term(se[j], 1, -f, FN_S, j - 1, DV_NONE);
+            if (c->vd) {
+                if (j & 1) {
+                    both(sbx[j], f, FN_S, j - 1, DV_X);
+                    if (two_d) both(sby[j], f, FN_S, j - 1, DV_Y);
+                }
+                if (want_b) {
+                    const double sg = (j & 1) ? -f : f;
+                    b.term(sbx[j], 1, sg, Tfn(j), j - 2, DV_X);
+                    if (two_d) b.term(sby[j], 1, sg, Tfn(j), j - 2, DV_Y);
+                }
+            }
+        }
+        const double fl = -1.0 / fact(l - 1);
+        both(fx, fl, Tfn(l), l - 2, DV_X);
+        if (two_d) both(fy, fl, Tfn(l), l - 2, DV_Y);
+        if (want_b && (l & 1)) {
+            b.term(fx, 1, fl, FN_S, l - 3, DV_X);
+            if (two_d) b.term(fy, 1, fl, FN_S, l - 3, DV_Y);
+        }
+        b.term(cvh, 2, 1.0, FN_ONE, 0, DV_NONE);
+        b.p.nacc = 3;
+        b.cout(SRC_ACC2, CMP(C_VH));
+        if (l < L) {
+            b.inv(SRC_ACC0, DV_NONE, HALF(H_GV));
+            if (want_b) {
+                b.inv(SRC_ACC1, DV_X, HALF(H_GBX));
+                if (two_d) b.inv(SRC_ACC1, DV_Y, HALF(H_GBY));
+            }
+        } else {
+            b.inv(SRC_ACC2, DV_NONE, HALF(H_GV));
+        }
+        SBI_TRY(run_col(c, b, K_COL_SA));
+    }
+    return SBI_OK;
+}
+
+// W solve at the stage state held in (C_ES, C_PS) [or physical eta_user with
+// C_PS]; leaves the W spectrum in *vh_buf and its half form in H_GV (+ H_GD).
+// seed of the iteration from a physical field: V_0 = mask F{w_seed}
+static sbi_status seed_from_physical(sbi_ctx* c, const void* w_seed) {
+    RowFwdParams rp{};
+    rp.g = c->gd;
+    rp.nf = 1;
+    rp.in[0] = w_seed;
+    rp.out[0] = HALF(H_PROD0);
+    c->st.launches += 1;
+    {
+        ProfScope ps_(c, K_ROW_FWD);
+        SBI_TRY(hip_ok(launch_row_fwd(c->fp64, rp, c->batch, tw_of(c), c->stream)));
+    }
+    ColBuilder b(c->gd);
+    int s = b.prod(HALF(H_PROD0));
+    b.term(s, 0, 1.0, FN_ONE, 0, DV_NONE);
+    b.cout(SRC_ACC0, CMP(C_VN));
+    b.inv(SRC_ACC0, DV_NONE, HALF(H_GV));
+    return run_col(c, b);
+}
+
+static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool need_eta_grad, int* vh_buf,
+                              const void* w_seed = nullptr) {
+    SBI_TRY(hip_ok(launch_ctl_reset(c->ctl, c->batch, c->grid.max_sweeps + 2, c->stream)));
+    c->st.launches += 1;
+    SBI_TRY(stage_state_pass(c, need_eta_grad || !eta_user));
+    SBI_TRY(row_setup(c, eta_user));
+    const void* eta_phys = eta_user ? eta_user : PHYS(P_ETA);
+    if (c->grid.mode == SBI_MODE_SA) {
+        SBI_TRY(run_sa(c, eta_phys));
+        *vh_buf = C_VH;
+    } else {
+        SBI_TRY(col_forcing(c));
+        if (w_seed) SBI_TRY(seed_from_physical(c, w_seed));
+        SBI_TRY(iterate(c, eta_phys, tol));
+        *vh_buf = C_VP;
+    }
+    return SBI_OK;
+}
+
+static sbi_status solve_status(sbi_ctx* c, sbi_solve_info* info, bool fresh) {
+    if (!fresh) SBI_TRY(read_heads(c));
+    sbi_status worst = SBI_OK;
+    for (int b = 0; b < c->batch; ++b) {
+        const Ctl& h = c->head[b];
+        int s = c->grid.mode == SBI_MODE_SA ? 0 : h.status;
+        if (h.nonfinite) s = SBI_ERR_NONFINITE;
+        if (info) {
+            info[b].sweeps = c->grid.mode == SBI_MODE_SA ? 0 : h.sweeps;
+            info[b].status = s;
+            info[b].residual = h.residual;
+            info[b].omega = h.omega;
+        }
+        c->st.sweeps += c->grid.mode == SBI_MODE_SA ? 0 : h.sweeps;
+        if (s < 0) worst = (worst < 0) ? worst : (sbi_status)s;
+        else if (worst >= 0 && s > worst) worst = (sbi_status)s;
+    }
+    return worst;
+}
+
+extern "C" sbi_status sbi_vertical_velocity(sbi_ctx* c, const void* eta, const void* phi_s, const double* h,
+                                            double tol, const void* w_seed, void* w_out, sbi_solve_info* info) {
+    if (!c || !eta || !phi_s || !w_out) return SBI_ERR_INVALID_ARG;
+    if (c->grid.mode == SBI_MODE_ITER && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
+    if (c->grid.seed == SBI_SEED_USER && !w_seed) return SBI_ERR_INVALID_ARG;
+    c->st = Stats();
+    sbi_status warn = SBI_OK;
+    if (h) {
+        SBI_TRY(set_depth(c, h, -1.0));
+        if (c->depth_warn) warn = SBI_WARN_DEPTH_CRITERION;
+    }
+    SBI_TRY(to_spectral(c, nullptr, phi_s, false));
+    int vh = 0;
+    SBI_TRY(solve_stage(c, eta, tol, false, &vh,
+                        (c->grid.seed == SBI_SEED_USER && c->grid.mode == SBI_MODE_ITER) ? w_seed : nullptr));
+    sbi_status st = solve_status(c, info, false);
+    if (st < 0) return st;
+    RowInvParams ip{};
+    ip.g = c->gd;
+    ip.nf = 1;
+    ip.in[0] = HALF(H_GV);
+    ip.in2[0] = c->grid.mode == SBI_MODE_ITER ? HALF(H_GD) : nullptr;
+    ip.out[0] = w_out;
+    ip.ctl = c->ctl;
+    c->st.launches += 1;
+    {
+        ProfScope ps_(c, K_ROW_INV);
+        SBI_TRY(hip_ok(launch_row_inv(c->fp64, ip, c->batch, tw_of(c), c->stream)));
+    }
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    return st != SBI_OK ? st : warn;
+}
+
+// nonlinear term and RK stage update after a solve
+static sbi_status stage_update(sbi_ctx* c, int stage, double dt, int vh_buf) {
+    const bool iter = c->grid.mode == SBI_MODE_ITER;
+    RowNphiParams np{};
+    np.g = c->gd;
+    np.gV = HALF(H_GV);
+    np.gD = iter ? HALF(H_GD) : nullptr;
+    np.gex = HALF(H_EX);
+    np.gey = HALF(H_EY);
+    np.gpx = HALF(H_PX);
+    np.gpy = HALF(H_PY);
+    np.h = HALF(H_PROD0);
+    np.ctl = c->ctl;
+    c->st.launches += 1;
+    {
+        ProfScope ps_(c, K_ROW_NPHI);
+        SBI_TRY(hip_ok(launch_row_nphi(c->fp64, np, c->batch, tw_of(c), c->stream)));
+    }
+    ColBuilder b(c->gd);
+    int s = b.prod(HALF(H_PROD0));
+    b.term(s, 0, 1.0, FN_ONE, 0, DV_NONE);
+    b.cout(SRC_ACC0, CMP(C_NP));
+    SBI_TRY(run_col(c, b));
+    RkParams rp{};
+    rp.g = c->gd;
+    rp.stage = stage;
+    rp.h = dt;
+    rp.eh = CMP(C_EH);
+    rp.ph = CMP(C_PH);
+    rp.es = CMP(C_ES);
+    rp.ps = CMP(C_PS);
+    rp.Vh = CMP(vh_buf);
+    rp.Nph = CMP(C_NP);
+    rp.ae = CMP(C_AE);
+    rp.ap = CMP(C_AP);
+    rp.fb1 = c->grid.filter_beta1;
+    rp.fb2 = c->grid.filter_beta2;
+    c->st.launches += 1;
+    {
+        ProfScope ps_(c, K_RK);
+        return hip_ok(launch_rk(c->fp64, rp, c->batch, c->stream));
+    }
+}
+
+static sbi_status relax_zone(sbi_ctx* c, double t) {
+    ColBuilder b(c->gd);
+    int se = b.cin(CMP(C_EH));
+    int sp = b.cin(CMP(C_PH));
+    b.term(se, 0, 1.0, FN_ONE, 0, DV_NONE);
+    b.term(sp, 1, 1.0, FN_ONE, 0, DV_NONE);
+    b.inv(SRC_ACC0, DV_NONE, HALF(H_PROD0));
+    b.inv(SRC_ACC1, DV_NONE, HALF(H_PROD0 + 1));
+    SBI_TRY(run_col(c, b));
+    RowBlendParams rp{};
+    rp.g = c->gd;
+    rp.ge = HALF(H_PROD0);
+    rp.gp = HALF(H_PROD0 + 1);
+    rp.he = HALF(H_PROD0 + 2);
+    rp.hp = HALF(H_PROD0 + 3);
+    rp.a = c->rz[0];
+    rp.k = c->rz[1];
+    rp.om = c->rz[2];
+    rp.gen = c->rz[3];
+    rp.absl = c->rz[4];
+    rp.ramp_time = c->rz[5] * 2.0 * M_PI / c->rz[2];
+    rp.t = t;
+    c->st.launches += 1;
+    {
+        ProfScope ps_(c, K_ROW_BLEND);
+        SBI_TRY(hip_ok(launch_row_blend(c->fp64, rp, c->batch, tw_of(c), c->stream)));
+    }
+    ColBuilder b2(c->gd);
+    int he = b2.prod(HALF(H_PROD0 + 2));
+    int hp = b2.prod(HALF(H_PROD0 + 3));
+    b2.term(he, 0, 1.0, FN_ONE, 0, DV_NONE);
+    b2.term(hp, 1, 1.0, FN_ONE, 0, DV_NONE);
+    b2.cout(SRC_ACC0, CMP(C_EH));
+    b2.cout(SRC_ACC0, CMP(C_ES));
+    b2.cout(SRC_ACC1, CMP(C_PH));
+    b2.cout(SRC_ACC1, CMP(C_PS));
+    return run_col(c, b2);
+}
+
+static sbi_status to_physical(sbi_ctx* c, void* eta, void* phi) {
+    ColBuilder b(c->gd);
+    int se = b.cin(CMP(C_EH));
+    int sp = b.cin(CMP(C_PH));
+    b.term(se, 0, 1.0, FN_ONE, 0, DV_NONE);
+    b.term(sp, 1, 1.0, FN_ONE, 0, DV_NONE);
+    b.inv(SRC_ACC0, DV_NONE, HALF(H_PROD0));
+    b.inv(SRC_ACC1, DV_NONE, HALF(H_PROD0 + 1));
+    SBI_TRY(run_col(c, b));
+    RowInvParams ip{};
+    ip.g = c->gd;
+    ip.nf = 2;
+    ip.in[0] = HALF(H_PROD0);
+    ip.in[1] = HALF(H_PROD0 + 1);
+    ip.out[0] = eta;
+    ip.out[1] = phi;
+    ip.ctl = c->ctl;
+    c->st.launches += 1;
+    {
+        ProfScope ps_(c, K_ROW_INV);
+        return hip_ok(launch_row_inv(c->fp64, ip, c->batch, tw_of(c), c->stream));
+    }
+}
+
+static void acc_info(sbi_ctx* c, sbi_step_info* si) {
+    for (int b = 0; b < c->batch; ++b) {
+        const Ctl& h = c->head[b];
+        si->solves += 1;
+        const int sw = c->grid.mode == SBI_MODE_SA ? 0 : h.sweeps;
+        si->sweeps_total += sw;
+        si->sweeps_max = std::max(si->sweeps_max, sw);
+        si->max_residual = std::max(si->max_residual, c->grid.mode == SBI_MODE_SA ? 0.0 : h.residual);
+    }
+}
+
+extern "C" sbi_status sbi_step(sbi_ctx* c, sbi_state* state, double dt, int32_t n, double tol, sbi_step_info* info) {
+    if (!c || !state || !state->eta || !state->phi_s || n < 0 || !std::isfinite(dt)) return SBI_ERR_INVALID_ARG;
+    if (c->grid.mode == SBI_MODE_ITER && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
+    c->st = Stats();
+    sbi_step_info si{};
+    SBI_TRY(to_spectral(c, state->eta, state->phi_s, true));
+    sbi_status worst = SBI_OK;
+    double t = state->t;
+    for (int s = 0; s < n; ++s) {
+        for (int stage = 0; stage < 4; ++stage) {
+            int vh = 0;
+            SBI_TRY(solve_stage(c, nullptr, tol, true, &vh));
+            if (c->grid.mode == SBI_MODE_ITER) {
+                // the iteration already read the control headers at its last poll
+                sbi_status st = solve_status(c, nullptr, true);
+                if (st < 0) return st;
+                if (st > worst) worst = st;
+                acc_info(c, &si);
+            } else {
+                si.solves += c->batch;
+            }
+            SBI_TRY(stage_update(c, stage, dt, vh));
+        }
+        t += dt;
+        if (c->relax_on) SBI_TRY(relax_zone(c, t));
+    }
+    if (c->grid.mode == SBI_MODE_SA) {
+        // SA mode has no residual; non-finite values surface through the last setup
+        SBI_TRY(read_heads(c));
+        for (int b = 0; b < c->batch; ++b)
+            if (c->head[b].nonfinite) return SBI_ERR_NONFINITE;
+    }
+    SBI_TRY(to_physical(c, state->eta, state->phi_s));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    state->t = t;
+    if (info) *info = si;
+    return worst;
+}
+
+extern "C" sbi_status sbi_diagnostics(sbi_ctx* c, const sbi_state* state, double tol, double* mass, double* energy) {
+    if (!c || !state || !state->eta || !state->phi_s || !mass || !energy) return SBI_ERR_INVALID_ARG;
+    c->st = Stats();
+    SBI_TRY(to_spectral(c, state->eta, state->phi_s, false));
+    int vh = 0;
+    SBI_TRY(solve_stage(c, nullptr, tol, false, &vh));
+    sbi_status st = solve_status(c, nullptr, c->grid.mode == SBI_MODE_ITER);
+    if (st < 0) return st;
+    DiagParams dp{};
+    dp.g = c->gd;
+    dp.eh = CMP(C_ES);
+    dp.ph = CMP(C_PS);
+    dp.Vh = CMP(vh);
+    dp.partial = c->diag_partial;
+    dp.nblk = c->diag_nblk;
+    {
+        ProfScope ps_(c, K_DIAG);
+        SBI_TRY(hip_ok(launch_diag(c->fp64, dp, c->batch, c->stream)));
+    }
+    std::vector<double> part((size_t)c->batch * dp.nblk * 2);
+    SBI_HIP(hipMemcpyAsync(part.data(), c->diag_partial, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    const sbi_grid& g = c->grid;
+    const double dA = (g.lx / g.nx) * (g.ny > 1 ? g.ly / g.ny : 1.0);
+    const double ntot = (double)g.nx * g.ny;
+    for (int b = 0; b < c->batch; ++b) {
+        double se = 0.0, sm = 0.0;
+        for (int k = 0; k < dp.nblk; ++k) {
+            se += part[((size_t)b * dp.nblk + k) * 2];
+            sm += part[((size_t)b * dp.nblk + k) * 2 + 1];
+        }
+        // Parseval on the kept half spectrum: sum_i f_i g_i = (1/N) sum_m w_m Re(F_m conj G_m)
+        energy[b] = 0.5 * dA * se / ntot;
+        mass[b] = dA * sm;
+    }
+    return st;
+}
+
+extern "C" sbi_status sbi_profile_enable(sbi_ctx* c, int32_t enable) {
+    if (!c) return SBI_ERR_INVALID_ARG;
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    prof_flush(c);
+    c->prof.on = enable != 0;
+    for (int k = 0; k < K_COUNT; ++k) {
+        c->prof.total_ms[k] = 0.0;
+        c->prof.count[k] = 0;
+    }
+    return SBI_OK;
+}
+
+extern "C" int32_t sbi_profile_read(sbi_ctx* c, const char** names, double* total_ms, int64_t* launches, int32_t n) {
+    if (!c) return 0;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return 0;
+    prof_flush(c);
+    const int k = std::min<int>(n, K_COUNT);
+    for (int i = 0; i < k; ++i) {
+        if (names) names[i] = kKernelNames[i];
+        if (total_ms) total_ms[i] = c->prof.total_ms[i];
+        if (launches) launches[i] = c->prof.count[i];
+    }
+    return k;
+}
+
+extern "C" sbi_status sbi_net_load(sbi_ctx* c, const void* weights, size_t bytes) {
+    if (!c || !weights || bytes == 0) return SBI_ERR_INVALID_ARG;
+    return SBI_ERR_UNSUPPORTED;
+}

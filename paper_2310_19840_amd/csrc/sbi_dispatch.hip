@@ -1,0 +1,73 @@
+// sbi_dispatch.hip -- precision dispatch of the kernel launchers and the
+// precision-independent control kernels.
+#include "sbi_kernels.hpp"
+
+namespace sbi {
+
+int col_tile(int ny, int fp64) {
+    if (ny == 1) return 64;
+    int c = 65536 / (ny * (fp64 ? 16 : 8));
+    if (c > 16) c = 16;
+    if (c < 1) c = 1;
+    return c;
+}
+
+__global__ void k_ctl_reset(Ctl* ctl, int slots) {
+    Ctl* c = ctl + blockIdx.x;
+    for (int i = threadIdx.x; i < slots; i += blockDim.x) {
+        c->num[i] = 0ull;
+        c->den[i] = 0ull;
+    }
+    if (threadIdx.x == 0) {
+        c->eta_max = 0ull;
+        c->eta_min = ~0ull;
+        c->nonfinite = 0;
+        c->done = 0;
+        c->status = 0;
+        c->sweeps = 0;
+        c->omega = 1.0;
+        c->residual = 0.0;
+        c->rmin = INFINITY;
+    }
+}
+
+__global__ void k_fill_zero(uint4* p, size_t n16) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+hipError_t launch_ctl_reset(Ctl* ctl, int batch, int slots, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_reset, dim3(batch), dim3(256), 0, s, ctl, slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s) {
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    unsigned nb = (unsigned)((n16 + 255) / 256);
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_fill_zero, dim3(nb), dim3(256), 0, s, (uint4*)ptr, n16);
+    return hipGetLastError();
+}
+
+#define SBI_DISPATCH(NAME, PTYPE)                                                                   \
+    hipError_t NAME(int fp64, const PTYPE& p, int b, const Twiddles& tw, hipStream_t s) {           \
+        return fp64 ? NAME##_t<double>(p, b, tw, s) : NAME##_t<float>(p, b, tw, s);                 \
+    }
+SBI_DISPATCH(launch_row_fwd, RowFwdParams)
+SBI_DISPATCH(launch_row_inv, RowInvParams)
+SBI_DISPATCH(launch_row_setup, RowSetupParams)
+SBI_DISPATCH(launch_row_sweep, RowSweepParams)
+SBI_DISPATCH(launch_row_sa, RowSaParams)
+SBI_DISPATCH(launch_row_nphi, RowNphiParams)
+SBI_DISPATCH(launch_row_blend, RowBlendParams)
+SBI_DISPATCH(launch_col, ColParams)
+
+hipError_t launch_rk(int fp64, const RkParams& p, int batch, hipStream_t s) {
+    return fp64 ? launch_rk_t<double>(p, batch, s) : launch_rk_t<float>(p, batch, s);
+}
+hipError_t launch_diag(int fp64, const DiagParams& p, int batch, hipStream_t s) {
+    return fp64 ? launch_diag_t<double>(p, batch, s) : launch_diag_t<float>(p, batch, s);
+}
+
+}  // namespace sbi

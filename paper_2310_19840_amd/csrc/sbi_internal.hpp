@@ -1,0 +1,94 @@
+// sbi_internal.hpp -- structures shared by the host orchestration and the
+// gfx950 kernels of the SBI solver.
+//
+// Spectral layouts (per batch member), complex values of the run precision:
+//   half form  [ny][Kxp]  : x transformed (kept m_x = 0..Mx), y physical.
+//                           Row-pass output / column-pass input ("H" and "G").
+//   compact    [Ky][Kxp]  : both axes transformed, only the kept rectangle
+//                           |m_x| <= Mx, |m_y| <= My.  Row r holds m_y = r for
+//                           r <= My and m_y = r - Ky for r > My.
+// Kx = Mx + 1 and Kxp rounds Kx up to the column-tile width; Ky = 2 My + 1
+// (1 when ny == 1).  Every spectrum of the method lives inside the kept
+// rectangle, so the compact form is exact, not an approximation.
+#pragma once
+#include <stdint.h>
+
+namespace sbi {
+
+constexpr int kMaxSweepSlots = 1024;   // max_sweeps <= 1000
+constexpr int kMaxProd = 24;           // forward inputs of one column pass
+constexpr int kMaxCin = 8;             // compact inputs of one column pass
+constexpr int kMaxTerms = 48;
+constexpr int kMaxCout = 6;
+constexpr int kMaxInv = 8;
+
+// Per-member control block in device memory.  The small header comes first so
+// the host can read it for every member with one strided copy.
+struct Ctl {
+    int done;                                // iteration finished (any reason)
+    int status;                              // sbi_status of the solve
+    int sweeps;                              // sweep-operator applications
+    int nonfinite;                           // a non-finite input value was seen
+    double omega;                            // relaxation weight
+    double residual;                         // last residual
+    double rmin;                             // smallest residual seen so far
+    unsigned long long eta_max;              // order-preserving bits of max(eta)
+    unsigned long long eta_min;              // order-preserving bits of min(eta)
+    unsigned long long pad;
+    unsigned long long num[kMaxSweepSlots];  // bits of max|W'-W| (non-negative doubles)
+    unsigned long long den[kMaxSweepSlots];  // bits of max|W'|
+};
+constexpr int kCtlHeadBytes = 64;
+
+struct GridDev {
+    int nx, ny, Mx, My, Kx, Kxp, Ky, order;
+    double lx, ly, kband;
+    long long s_phys;   // reals per member of a physical field
+    long long s_half;   // complex per member of a half-form field
+    long long s_cmp;    // complex per member of a compact field
+    const double* href; // [batch] reference depth
+    int relax;
+};
+
+// Multiplier of one contribution to a column-pass accumulator:
+//   coef * fn(k) * k^pw * dv,  fn in {1, tanh(kh), sech(kh)}, dv in {1, i kx, i ky}
+// (k^-1 and i k terms vanish at k = 0).
+struct ColTerm {
+    double coef;
+    short src;      // product index (< nprod) or nprod + compact-input index
+    signed char acc, fn, pw, dv;
+    signed char pad[2];
+};
+
+enum { FN_ONE = 0, FN_T = 1, FN_S = 2 };
+enum { DV_NONE = 0, DV_X = 1, DV_Y = 2 };
+// sources of column-pass outputs
+enum { SRC_ACC0 = 0, SRC_ACC1 = 1, SRC_ACC2 = 2, SRC_ACC3 = 3, SRC_NEW0 = 4, SRC_NEW1 = 5,
+       SRC_DIFF0 = 6, SRC_DIFF1 = 7 };
+// control modes of a column pass
+enum { CTL_NONE = 0, CTL_OMEGA = 1, CTL_SWEEP = 2 };
+
+struct ColParams {
+    GridDev g;
+    int nprod, ncin, nterm, nacc;
+    const void* hin[kMaxProd];
+    long long hin_stride[kMaxProd];   // per-member stride override (0 = g.s_half)
+    const void* cin[kMaxCin];
+    short toff[kMaxProd + kMaxCin + 1]; // terms sorted by source: [toff[s], toff[s+1])
+    ColTerm term[kMaxTerms];
+    int relax_prev[2];                 // compact-input index of the previous iterate of acc0/acc1, -1 none
+    int ncout;
+    int cout_src[kMaxCout];
+    void* cout[kMaxCout];
+    int ninv;
+    int inv_src[kMaxInv];
+    int inv_dv[kMaxInv];
+    void* inv[kMaxInv];
+    Ctl* ctl;
+    int ctl_mode;
+    int sweep;        // sweep index n of this pass (CTL_SWEEP)
+    int max_sweeps;
+    double tol;
+};
+
+}  // namespace sbi

@@ -1,0 +1,980 @@
+// sbi_kernels.hip -- gfx950 kernels of the SBI wave solver.
+//
+// Every 2D transform is split into a row pass (real <-> half form, one row per
+// group of P threads, half-length complex FFT plus the standard real/complex
+// twist) and a column pass (C adjacent columns per workgroup, length-ny complex
+// FFT).  The products of the method (eta^j V, delta^j grad phi_b, ...) are
+// formed in registers inside the row pass; the Fourier multipliers of the
+// method (k^j/j! tanh(kh), sech(kh), i k, ...) are applied and summed inside
+// the column pass, which then runs the inverse column transforms of the new
+// iterate directly from registers.  Only kept modes are ever written, so the
+// spectra in memory are 1/4 (2D) of the full size.
+#include <math.h>
+#include "sbi_fft.hpp"
+#include "sbi_kernels.hpp"
+
+#ifndef SBI_REAL
+#error "compile with -DSBI_REAL=double or -DSBI_REAL=float"
+#endif
+
+namespace sbi {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long ord_bits(double x) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double unord_bits(unsigned long long o) {
+    unsigned long long b = (o >> 63) ? (o & 0x7fffffffffffffffull) : ~o;
+    return __longlong_as_double((long long)b);
+}
+__device__ __forceinline__ unsigned long long abs_bits(double x) {
+    return (unsigned long long)__double_as_longlong(fabs(x));
+}
+__device__ __forceinline__ double bits_to_double(unsigned long long b) {
+    return __longlong_as_double((long long)b);
+}
+// Block-wide max/min of 64-bit keys through LDS; valid for any block size
+// (row blocks can be narrower than a wavefront).  Every thread must call it.
+template <bool MAX>
+__device__ __forceinline__ unsigned long long block_reduce_u64(unsigned long long v) {
+    __shared__ unsigned long long red[1024];
+    const int t = threadIdx.x;
+    const int n = blockDim.x;
+    __syncthreads();
+    red[t] = v;
+    __syncthreads();
+    for (int s = 1; s < n; s <<= 1) {
+        if ((t & (2 * s - 1)) == 0 && t + s < n) {
+            const unsigned long long w = red[t + s];
+            const unsigned long long u = red[t];
+            red[t] = MAX ? (w > u ? w : u) : (w < u ? w : u);
+        }
+        __syncthreads();
+    }
+    const unsigned long long r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double sech_d(double x) {
+    double e = exp(-fabs(x));
+    return 2.0 * e / (1.0 + e * e);
+}
+
+template <typename V> __device__ __forceinline__ V rmul(V a, V b) {  // componentwise real product
+    return cx<V>(a.x * b.x, a.y * b.y);
+}
+
+// ---------------------------------------------------------------------------
+// Row pass helpers: real row of length NX <-> kept half spectrum F[0..Mx]
+// via the length-NX/2 complex transform of z[n] = f[2n] + i f[2n+1].
+// ---------------------------------------------------------------------------
+template <typename R, int NX> struct Row {
+    using V = typename cplx_of<R>::type;
+    static constexpr int N = NX / 2;
+    static constexpr int E = FftShape<N>::E;
+    static constexpr int P = FftShape<N>::P;
+
+    // v <- z = inverse row transform of (G + c2 G2), scaled.
+    static __device__ __forceinline__ void inverse(V (&v)[E], const V* __restrict__ G, const V* __restrict__ G2,
+                                                   R c2, int Mx, V* lds, int j, bool valid,
+                                                   const V* __restrict__ twN, const V* __restrict__ twX, R scale) {
+        for (int m = j; m < N; m += P) {
+            V f = cx<V>(R(0), R(0));
+            if (valid && m <= Mx) {
+                f = G[m];
+                if (G2) {
+                    V f2 = G2[m];
+                    f = cx<V>(f.x + c2 * f2.x, f.y + c2 * f2.y);
+                }
+            }
+            lds[m] = f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int m = j + q * P;
+            V fm = lds[m];
+            V fc = (m == 0) ? cx<V>(R(0), R(0)) : cconj(lds[N - m]);
+            V ev = cx<V>(R(0.5) * (fm.x + fc.x), R(0.5) * (fm.y + fc.y));
+            V od = cx<V>(R(0.5) * (fm.x - fc.x), R(0.5) * (fm.y - fc.y));
+            od = cmul(od, cconj(twX[m]));           // exp(+2 pi i m / NX)
+            v[q] = cadd(ev, mul_i(od));
+        }
+        __syncthreads();
+        fft<V, N, true, 1>(v, lds, 0, j, twN);
+#pragma unroll
+        for (int q = 0; q < E; ++q) v[q] = cscale(v[q], scale);
+    }
+
+    // H[0..Mx] <- forward row transform of the real pairs in v (v is destroyed).
+    static __device__ __forceinline__ void forward(V (&v)[E], V* __restrict__ H, int Mx, V* lds, int j, bool valid,
+                                                   const V* __restrict__ twN, const V* __restrict__ twX) {
+        fft<V, N, false, 1>(v, lds, 0, j, twN);
+#pragma unroll
+        for (int q = 0; q < E; ++q) lds[j + q * P] = v[q];
+        __syncthreads();
+        for (int m = j; m <= Mx; m += P) {
+            V zm = lds[m];
+            V zc = cconj(lds[(N - m) & (N - 1)]);
+            V ev = cx<V>(R(0.5) * (zm.x + zc.x), R(0.5) * (zm.y + zc.y));
+            V od = mul_mi<false>(cx<V>(R(0.5) * (zm.x - zc.x), R(0.5) * (zm.y - zc.y)));
+            V f = cadd(ev, cmul(twX[m], od));
+            if (valid) H[m] = f;
+        }
+        __syncthreads();
+    }
+
+    static __device__ __forceinline__ void load(V (&v)[E], const R* __restrict__ row, int j, bool valid) {
+        const V* r2 = reinterpret_cast<const V*>(row);
+#pragma unroll
+        for (int q = 0; q < E; ++q) v[q] = valid ? r2[j + q * P] : cx<V>(R(0), R(0));
+    }
+    static __device__ __forceinline__ void store(const V (&v)[E], R* __restrict__ row, int j, bool valid) {
+        if (!valid) return;
+        V* r2 = reinterpret_cast<V*>(row);
+#pragma unroll
+        for (int q = 0; q < E; ++q) r2[j + q * P] = v[q];
+    }
+};
+
+// threads per row-pass workgroup: rows of P threads packed up to 256 threads
+template <int NX> __host__ __device__ constexpr int row_threads() {
+    return FftShape<NX / 2>::P > 256 ? FftShape<NX / 2>::P : 256;
+}
+
+struct RowIdx {
+    int t, j, rl, y, mem;
+    bool valid;
+};
+
+template <int P> __device__ __forceinline__ RowIdx row_index(int ny) {
+    RowIdx r;
+    r.t = threadIdx.x;
+    r.j = r.t % P;
+    r.rl = r.t / P;
+    const int rpw = blockDim.x / P;
+    r.y = blockIdx.x * rpw + r.rl;
+    r.mem = blockIdx.y;
+    r.valid = r.y < ny;
+    return r;
+}
+
+#define ROW_PROLOGUE(R, NX)                                              \
+    using RW = Row<R, NX>;                                               \
+    using V = typename RW::V;                                            \
+    constexpr int E = RW::E;                                             \
+    extern __shared__ unsigned char smem_raw[];                          \
+    const RowIdx ri = row_index<RW::P>(p.g.ny);                          \
+    V* lds = reinterpret_cast<V*>(smem_raw) + ri.rl * RW::N;             \
+    const long long ho = ri.mem * p.g.s_half + (long long)(ri.valid ? ri.y : 0) * p.g.Kxp; \
+    const long long po = ri.mem * p.g.s_phys + (long long)(ri.valid ? ri.y : 0) * p.g.nx;  \
+    const R iscale = R(1.0 / ((double)RW::N * (double)p.g.ny));          \
+    (void)po; (void)iscale;
+
+// ---------------------------------------------------------------------------
+// Row kernels
+// ---------------------------------------------------------------------------
+template <typename R, int NX>
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_fwd(const RowFwdParams p, const typename cplx_of<R>::type* twN,
+                          const typename cplx_of<R>::type* twX) {
+    ROW_PROLOGUE(R, NX)
+    for (int f = 0; f < p.nf; ++f) {
+        V v[E];
+        RW::load(v, static_cast<const R*>(p.in[f]) + po, ri.j, ri.valid);
+        RW::forward(v, static_cast<V*>(p.out[f]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+    }
+}
+
+template <typename R, int NX>
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_inv(const RowInvParams p, const typename cplx_of<R>::type* twN,
+                          const typename cplx_of<R>::type* twX) {
+    ROW_PROLOGUE(R, NX)
+    for (int f = 0; f < p.nf; ++f) {
+        V v[E];
+        const V* g2 = p.in2[f] ? static_cast<const V*>(p.in2[f]) + ho : nullptr;
+        R c2 = R(0);
+        if (g2) c2 = R(1.0 - p.ctl[ri.mem].omega);
+        RW::inverse(v, static_cast<const V*>(p.in[f]) + ho, g2, c2, p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+        RW::store(v, static_cast<R*>(p.out[f]) + po, ri.j, ri.valid);
+    }
+}
+
+template <typename R, int NX>
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupParams p, const typename cplx_of<R>::type* twN,
+                            const typename cplx_of<R>::type* twX) {
+    ROW_PROLOGUE(R, NX)
+    V e[E];
+    if (p.g_eta) {
+        RW::inverse(e, static_cast<const V*>(p.g_eta) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+    } else {
+        RW::load(e, static_cast<const R*>(p.eta_in) + po, ri.j, ri.valid);
+    }
+    if (p.eta_out) RW::store(e, static_cast<R*>(p.eta_out) + po, ri.j, ri.valid);
+    // extrema of eta (relaxation weight)
+    {
+        unsigned long long mx = 0ull, mn = ~0ull;
+        if (ri.valid) {
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                unsigned long long a = ord_bits((double)e[q].x), b = ord_bits((double)e[q].y);
+                mx = a > mx ? a : mx;
+                mx = b > mx ? b : mx;
+                mn = a < mn ? a : mn;
+                mn = b < mn ? b : mn;
+            }
+        }
+        mx = block_reduce_u64<true>(mx);
+        mn = block_reduce_u64<false>(mn);
+        if (threadIdx.x == 0 && p.ctl) {
+            atomicMax(&p.ctl[ri.mem].eta_max, mx);
+            atomicMin(&p.ctl[ri.mem].eta_min, mn);
+        }
+    }
+    int bad = 0;
+    if (ri.valid) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) bad |= !isfinite((double)e[q].x) || !isfinite((double)e[q].y);
+    }
+    V px[E], py[E];
+    RW::inverse(px, static_cast<const V*>(p.g_px) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+    if (p.px_out) RW::store(px, static_cast<R*>(p.px_out) + po, ri.j, ri.valid);
+    const bool two_d = p.g.ny > 1;
+    if (two_d) {
+        RW::inverse(py, static_cast<const V*>(p.g_py) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+        if (p.py_out) RW::store(py, static_cast<R*>(p.py_out) + po, ri.j, ri.valid);
+    }
+    if (ri.valid) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            bad |= !isfinite((double)px[q].x) || !isfinite((double)px[q].y);
+            if (two_d) bad |= !isfinite((double)py[q].x) || !isfinite((double)py[q].y);
+        }
+    }
+    if (bad && p.ctl) atomicOr(&p.ctl[ri.mem].nonfinite, 1);
+    if (p.nprod > 0) {
+        V ep[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) ep[q] = e[q];
+        int idx = 0;
+        for (int l = 2; l <= p.g.order; ++l) {
+            if (l > 2) {
+#pragma unroll
+                for (int q = 0; q < E; ++q) ep[q] = rmul(ep[q], e[q]);
+            }
+            V w[E];
+#pragma unroll
+            for (int q = 0; q < E; ++q) w[q] = rmul(ep[q], px[q]);
+            RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+            if (two_d) {
+#pragma unroll
+                for (int q = 0; q < E; ++q) w[q] = rmul(ep[q], py[q]);
+                RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+            }
+        }
+    }
+}
+
+template <typename R, int NX>
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_sweep(const RowSweepParams p, const typename cplx_of<R>::type* twN,
+                            const typename cplx_of<R>::type* twX) {
+    ROW_PROLOGUE(R, NX)
+    Ctl* ctl = p.ctl + ri.mem;
+    if (ctl->done) return;  // block-uniform
+    V vv[E];
+    RW::inverse(vv, static_cast<const V*>(p.gV) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+    if (p.residual) {
+        V dd[E];
+        RW::inverse(dd, static_cast<const V*>(p.gD) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+        const double c = 1.0 - ctl->omega;
+        unsigned long long nu = 0ull, de = 0ull;
+        if (ri.valid) {
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const double d0 = (double)dd[q].x, d1 = (double)dd[q].y;
+                const double w0 = (double)vv[q].x + c * d0, w1 = (double)vv[q].y + c * d1;
+                unsigned long long a = abs_bits(d0), b = abs_bits(d1);
+                nu = a > nu ? a : nu;
+                nu = b > nu ? b : nu;
+                a = abs_bits(w0);
+                b = abs_bits(w1);
+                de = a > de ? a : de;
+                de = b > de ? b : de;
+            }
+        }
+        nu = block_reduce_u64<true>(nu);
+        de = block_reduce_u64<true>(de);
+        if (threadIdx.x == 0) {
+            atomicMax(&ctl->num[p.slot], nu);
+            atomicMax(&ctl->den[p.slot], de);
+        }
+    }
+    if (!p.products) return;
+    V ev[E];
+    RW::load(ev, static_cast<const R*>(p.eta) + po, ri.j, ri.valid);
+    int idx = 0;
+    {
+        V pw[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) pw[q] = vv[q];
+        for (int jj = 1; jj <= p.J; ++jj) {
+            V w[E];
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                pw[q] = rmul(pw[q], ev[q]);
+                w[q] = pw[q];
+            }
+            RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+        }
+    }
+    if (p.vd) {
+        V dv[E];
+        RW::load(dv, static_cast<const R*>(p.delta) + po, ri.j, ri.valid);
+        const int ncomp = p.g.ny > 1 ? 2 : 1;
+        for (int comp = 0; comp < ncomp; ++comp) {
+            V pw[E];
+            RW::inverse(pw, static_cast<const V*>(comp == 0 ? p.gbx : p.gby) + ho, nullptr, R(0), p.g.Mx, lds,
+                        ri.j, ri.valid, twN, twX, iscale);
+            for (int jj = 1; jj <= p.J; ++jj) {
+                V w[E];
+#pragma unroll
+                for (int q = 0; q < E; ++q) {
+                    pw[q] = rmul(pw[q], dv[q]);
+                    w[q] = pw[q];
+                }
+                RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+            }
+        }
+    }
+}
+
+template <typename R, int NX>
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_sa(const RowSaParams p, const typename cplx_of<R>::type* twN,
+                         const typename cplx_of<R>::type* twX) {
+    ROW_PROLOGUE(R, NX)
+    const int l = p.l;
+    int idx = 0;
+    V a[E], base[E], pw[E];
+    // eta^j V_(l-j)
+    RW::inverse(a, static_cast<const V*>(p.gV) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+    if (p.V_out) RW::store(a, static_cast<R*>(p.V_out) + po, ri.j, ri.valid);
+    RW::load(base, static_cast<const R*>(p.eta) + po, ri.j, ri.valid);
+#pragma unroll
+    for (int q = 0; q < E; ++q) pw[q] = base[q];
+    for (int jj = 1; jj <= l - 1; ++jj) {
+        V src[E], w[E];
+        if (jj == 1) {
+#pragma unroll
+            for (int q = 0; q < E; ++q) src[q] = a[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < E; ++q) pw[q] = rmul(pw[q], base[q]);
+            RW::load(src, static_cast<const R*>(p.Vphys[l - jj]) + po, ri.j, ri.valid);
+        }
+#pragma unroll
+        for (int q = 0; q < E; ++q) w[q] = rmul(pw[q], src[q]);
+        RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+    }
+    // delta^j grad phi_b,(l-j)
+    if (p.vd) {
+        const int ncomp = p.g.ny > 1 ? 2 : 1;
+        for (int comp = 0; comp < ncomp; ++comp) {
+            const void* gsrc = comp == 0 ? p.gbx : p.gby;
+            void* outp = comp == 0 ? p.bx_out : p.by_out;
+            const void* const* phys = comp == 0 ? p.bxphys : p.byphys;
+            RW::inverse(a, static_cast<const V*>(gsrc) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+            if (outp) RW::store(a, static_cast<R*>(outp) + po, ri.j, ri.valid);
+            RW::load(base, static_cast<const R*>(p.delta) + po, ri.j, ri.valid);
+#pragma unroll
+            for (int q = 0; q < E; ++q) pw[q] = base[q];
+            for (int jj = 1; jj <= l - 1; ++jj) {
+                V src[E], w[E];
+                if (jj == 1) {
+#pragma unroll
+                    for (int q = 0; q < E; ++q) src[q] = a[q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < E; ++q) pw[q] = rmul(pw[q], base[q]);
+                    RW::load(src, static_cast<const R*>(phys[l - jj]) + po, ri.j, ri.valid);
+                }
+#pragma unroll
+                for (int q = 0; q < E; ++q) w[q] = rmul(pw[q], src[q]);
+                RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+            }
+        }
+    }
+    // forcing eta^(l-1) grad phi_s
+    RW::load(base, static_cast<const R*>(p.eta) + po, ri.j, ri.valid);
+#pragma unroll
+    for (int q = 0; q < E; ++q) pw[q] = base[q];
+    for (int jj = 2; jj <= l - 1; ++jj) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) pw[q] = rmul(pw[q], base[q]);
+    }
+    const int ncomp = p.g.ny > 1 ? 2 : 1;
+    for (int comp = 0; comp < ncomp; ++comp) {
+        V w[E];
+        RW::load(a, static_cast<const R*>(comp == 0 ? p.phx : p.phy) + po, ri.j, ri.valid);
+#pragma unroll
+        for (int q = 0; q < E; ++q) w[q] = rmul(pw[q], a[q]);
+        RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+    }
+}
+
+template <typename R, int NX>
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi(const RowNphiParams p, const typename cplx_of<R>::type* twN,
+                           const typename cplx_of<R>::type* twX) {
+    ROW_PROLOGUE(R, NX)
+    V q[E], gg[E], pp[E], a[E], b[E];
+    const V* gD = p.gD ? static_cast<const V*>(p.gD) + ho : nullptr;
+    const R c2 = gD ? R(1.0 - p.ctl[ri.mem].omega) : R(0);
+    RW::inverse(q, static_cast<const V*>(p.gV) + ho, gD, c2, p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+    RW::inverse(a, static_cast<const V*>(p.gex) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+    RW::inverse(b, static_cast<const V*>(p.gpx) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        q[k] = cx<V>(q[k].x + a[k].x * b[k].x, q[k].y + a[k].y * b[k].y);
+        gg[k] = rmul(a[k], a[k]);
+        pp[k] = rmul(b[k], b[k]);
+    }
+    if (p.g.ny > 1) {
+        RW::inverse(a, static_cast<const V*>(p.gey) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+        RW::inverse(b, static_cast<const V*>(p.gpy) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            q[k] = cx<V>(q[k].x + a[k].x * b[k].x, q[k].y + a[k].y * b[k].y);
+            gg[k] = cx<V>(gg[k].x + a[k].x * a[k].x, gg[k].y + a[k].y * a[k].y);
+            pp[k] = cx<V>(pp[k].x + b[k].x * b[k].x, pp[k].y + b[k].y * b[k].y);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        q[k] = cx<V>(R(0.5) * (q[k].x * q[k].x / (R(1) + gg[k].x) - pp[k].x),
+                     R(0.5) * (q[k].y * q[k].y / (R(1) + gg[k].y) - pp[k].y));
+    }
+    RW::forward(q, static_cast<V*>(p.h) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+}
+
+template <typename R, int NX>
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_blend(const RowBlendParams p, const typename cplx_of<R>::type* twN,
+                            const typename cplx_of<R>::type* twX) {
+    ROW_PROLOGUE(R, NX)
+    V e[E], f[E];
+    RW::inverse(e, static_cast<const V*>(p.ge) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+    RW::inverse(f, static_cast<const V*>(p.gp) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+    const double dx = p.g.lx / p.g.nx;
+    const double r = p.t < p.ramp_time ? 0.5 * (1.0 - cos(M_PI * p.t / p.ramp_time)) : 1.0;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int n = ri.j + q * RW::P;
+        double ev[2] = {(double)e[q].x, (double)e[q].y};
+        double fv[2] = {(double)f[q].x, (double)f[q].y};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double x = (2 * n + h) * dx;
+            double wg = 0.0, wa = 0.0;
+            if (x < p.gen) {
+                const double s = x / p.gen;
+                wg = 1.0 - (3 * s * s - 2 * s * s * s);
+            }
+            if (x > p.g.lx - p.absl) {
+                const double s = (p.g.lx - x) / p.absl;
+                wa = 1.0 - (3 * s * s - 2 * s * s * s);
+            }
+            const double th = p.k * x - p.om * p.t;
+            const double et = p.a * r * cos(th), pt = p.a * r / p.om * sin(th);
+            ev[h] = (1.0 - wg) * ev[h] + wg * et;
+            fv[h] = (1.0 - wg) * fv[h] + wg * pt;
+            ev[h] *= (1.0 - wa);
+            fv[h] *= (1.0 - wa);
+        }
+        e[q] = cx<V>(R(ev[0]), R(ev[1]));
+        f[q] = cx<V>(R(fv[0]), R(fv[1]));
+    }
+    RW::forward(e, static_cast<V*>(p.he) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+    RW::forward(f, static_cast<V*>(p.hp) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+}
+
+// ---------------------------------------------------------------------------
+// Column pass: forward column transforms of the products, multiplier sums,
+// relaxation, compact outputs, inverse column transforms of the results.
+// ---------------------------------------------------------------------------
+template <typename R, int NY> __host__ __device__ constexpr int col_width() {
+    if (NY == 1) return 64;
+    int c = 65536 / (NY * (int)(2 * sizeof(R)));
+    if (c > 16) c = 16;
+    if (c < 1) c = 1;
+    return c;
+}
+
+// decision of a sweep pass from the completed residual of the previous sweep.
+// returns 0 to continue, else the terminating sbi_status + 100 (so 0 is free).
+__device__ __forceinline__ int sweep_decision(Ctl* ctl, int n, int M, double tol, double* r_out, double* rmin_out) {
+    *r_out = 0.0;
+    *rmin_out = ctl->rmin;
+    if (n == 0) return 0;
+    const double num = bits_to_double(ctl->num[n - 1]);
+    const double den = bits_to_double(ctl->den[n - 1]);
+    if (!isfinite(num) || !isfinite(den)) {
+        *r_out = __longlong_as_double(0x7ff8000000000000ll);
+        return 100 - 5;  // SBI_ERR_NONFINITE
+    }
+    const double r = (num == 0.0) ? 0.0 : (den > 0.0 ? num / den : INFINITY);
+    *r_out = r;
+    if (r <= tol) return 100;  // converged: SBI_OK
+    double rmin = fmin(ctl->rmin, r);
+    *rmin_out = rmin;
+    if (r > 1e6 || ((n - 1) >= 3 && r > 10.0 * rmin)) return 100 - 6;  // SBI_ERR_DIVERGED
+    if (n >= M) return 100 + 1;                                        // SBI_WARN_NOT_CONVERGED
+    return 0;
+}
+
+template <typename R, int NY, int NACC>
+__global__ void __launch_bounds__((col_width<R, NY>() * FftShape<NY>::P))
+k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
+    using V = typename cplx_of<R>::type;
+    constexpr int N = NY;
+    constexpr int E = FftShape<N>::E;
+    constexpr int P = FftShape<N>::P;
+    constexpr int C = col_width<R, NY>();
+    extern __shared__ unsigned char smem_raw[];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+    const int t = threadIdx.x;
+    const int c = t % C;
+    const int j = t / C;
+    const int mem = blockIdx.y;
+    const int x0 = blockIdx.x * C;
+    const int mx = x0 + c;
+    const GridDev& g = p.g;
+    Ctl* ctl = p.ctl ? p.ctl + mem : nullptr;
+
+    double omega = 1.0;
+    if (p.ctl_mode == CTL_SWEEP) {
+        if (ctl->done) return;
+        double r, rmin;
+        const int dec = sweep_decision(ctl, p.sweep, p.max_sweeps, p.tol, &r, &rmin);
+        if (dec) {
+            if (blockIdx.x == 0 && t == 0) {
+                ctl->status = dec - 100;
+                ctl->sweeps = p.sweep;
+                ctl->residual = r;
+                ctl->done = 1;
+            }
+            return;
+        }
+        if (blockIdx.x == 0 && t == 0) {
+            ctl->rmin = rmin;
+            ctl->residual = r;
+        }
+        omega = ctl->omega;
+    } else if (p.ctl_mode == CTL_OMEGA) {
+        // relaxation weight from the local symbol sum_{j<=J} (k eta)^j / j!
+        const double emax = unord_bits(ctl->eta_max), emin = unord_bits(ctl->eta_min);
+        const int J = g.order - 1;
+        double w = 1.0;
+        if (g.relax && J >= 1) {
+            double lmax = 0.0, lmin = 0.0, tmax = 1.0, tmin = 1.0;
+            const double xmax = g.kband * emax, xmin = g.kband * emin;
+            for (int jj = 0; jj <= J; ++jj) {
+                if (jj > 0) {
+                    tmax *= xmax / jj;
+                    tmin *= xmin / jj;
+                }
+                lmax += tmax;
+                lmin += tmin;
+            }
+            const double s = lmin + lmax;
+            if (isfinite(s) && s > 0.0) w = fmin(1.0, 2.0 / s);
+        }
+        omega = w;
+        if (blockIdx.x == 0 && t == 0) ctl->omega = w;
+    }
+
+    // mode geometry of the E values this thread owns: m_y index n = j + q P
+    const double href = g.href[mem];
+    const double kx = 2.0 * M_PI * (double)mx / g.lx;
+    R kk[E], TT[E], SS[E], kyv[E];
+    int crow[E];  // compact row, -1 if not kept
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int n = j + q * P;
+        const int my = (n <= N / 2) ? n : n - N;
+        const bool keep = (mx < g.Kx) && (my <= g.My) && (my >= -g.My);
+        crow[q] = keep ? (my >= 0 ? my : my + g.Ky) : -1;
+        const double ky = (N == 1) ? 0.0 : 2.0 * M_PI * (double)my / g.ly;
+        const double k = sqrt(kx * kx + ky * ky);
+        kk[q] = R(k);
+        kyv[q] = R(ky);
+        TT[q] = R(tanh(k * href));
+        SS[q] = R(sech_d(k * href));
+    }
+    const R kxr = R(kx);
+
+    V acc[NACC][E];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a)
+#pragma unroll
+        for (int q = 0; q < E; ++q) acc[a][q] = cx<V>(R(0), R(0));
+
+    auto apply_terms = [&](int src, const V (&v)[E]) {
+        for (int ti = p.toff[src]; ti < p.toff[src + 1]; ++ti) {
+            const ColTerm tm = p.term[ti];
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                if (crow[q] < 0) continue;
+                R m = R(tm.coef);
+                if (tm.fn == FN_T) m *= TT[q];
+                else if (tm.fn == FN_S) m *= SS[q];
+                if (tm.pw >= 0) {
+                    for (int e = 0; e < tm.pw; ++e) m *= kk[q];
+                } else {
+                    m = kk[q] > R(0) ? m / kk[q] : R(0);
+                }
+                V val = cscale(v[q], m);
+                if (tm.dv == DV_X) val = mul_i(cscale(val, kxr));
+                else if (tm.dv == DV_Y) val = mul_i(cscale(val, kyv[q]));
+#pragma unroll
+                for (int a = 0; a < NACC; ++a)
+                    if (a == tm.acc) acc[a][q] = cadd(acc[a][q], val);
+            }
+        }
+    };
+
+    // forward column transforms of the products
+    for (int s = 0; s < p.nprod; ++s) {
+        const long long st = p.hin_stride[s] ? p.hin_stride[s] : g.s_half;
+        const V* H = static_cast<const V*>(p.hin[s]) + mem * st;
+        V v[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) v[q] = H[(long long)(j + q * P) * g.Kxp + mx];
+        fft<V, N, false, C>(v, lds, c, j, twY);
+        apply_terms(s, v);
+    }
+    // compact inputs
+    for (int ci = 0; ci < p.ncin; ++ci) {
+        if (p.toff[p.nprod + ci] == p.toff[p.nprod + ci + 1]) continue;  // no term reads it
+        const V* Ci = static_cast<const V*>(p.cin[ci]) + mem * g.s_cmp;
+        V v[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) v[q] = crow[q] >= 0 ? Ci[(long long)crow[q] * g.Kxp + mx] : cx<V>(R(0), R(0));
+        apply_terms(p.nprod + ci, v);
+    }
+
+    // relaxation of the iterate: NEW = prev + omega (acc - prev), DIFF = acc - prev
+    auto prev_of = [&](int a, int q) -> V {
+        const int pi = p.relax_prev[a];
+        if (pi < 0 || crow[q] < 0) return cx<V>(R(0), R(0));
+        return static_cast<const V*>(p.cin[pi])[mem * g.s_cmp + (long long)crow[q] * g.Kxp + mx];
+    };
+    auto acc_of = [&](int a, int q) -> V {
+        V r = cx<V>(R(0), R(0));
+#pragma unroll
+        for (int k = 0; k < NACC; ++k)
+            if (k == a) r = acc[k][q];
+        return r;
+    };
+    auto source = [&](int src, int q) -> V {
+        if (src <= SRC_ACC3) return acc_of(src, q);
+        const int a = (src == SRC_NEW0 || src == SRC_DIFF0) ? 0 : 1;
+        const V pv = prev_of(a, q);
+        const V d = csub(acc_of(a, q), pv);
+        if (src == SRC_DIFF0 || src == SRC_DIFF1) return d;
+        return cadd(pv, cscale(d, R(omega)));
+    };
+    // inverse column transforms (before any compact output is written: the
+    // NEW/DIFF sources re-read the previous iterate from its compact array)
+    for (int o = 0; o < p.ninv; ++o) {
+        V v[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            V s = crow[q] >= 0 ? source(p.inv_src[o], q) : cx<V>(R(0), R(0));
+            if (p.inv_dv[o] == DV_X) s = mul_i(cscale(s, kxr));
+            else if (p.inv_dv[o] == DV_Y) s = mul_i(cscale(s, kyv[q]));
+            v[q] = s;
+        }
+        fft<V, N, true, C>(v, lds, c, j, twY);
+        V* G = static_cast<V*>(p.inv[o]) + mem * g.s_half;
+#pragma unroll
+        for (int q = 0; q < E; ++q) G[(long long)(j + q * P) * g.Kxp + mx] = v[q];
+    }
+    // compact outputs: every output of a mode is formed before any is written,
+    // so an output may overwrite an input of the same pass in place
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        if (crow[q] < 0) continue;
+        V vals[kMaxCout];
+        for (int o = 0; o < p.ncout; ++o) vals[o] = source(p.cout_src[o], q);
+        for (int o = 0; o < p.ncout; ++o)
+            static_cast<V*>(p.cout[o])[mem * g.s_cmp + (long long)crow[q] * g.Kxp + mx] = vals[o];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise spectral kernels
+// ---------------------------------------------------------------------------
+struct ModeGeo {
+    int r, mx;
+    bool valid;
+    double kx, ky, k;
+};
+__device__ __forceinline__ ModeGeo mode_geo(const GridDev& g, long long idx) {
+    ModeGeo m;
+    m.r = (int)(idx / g.Kxp);
+    m.mx = (int)(idx % g.Kxp);
+    m.valid = m.r < g.Ky && m.mx < g.Kx;
+    const int my = m.r <= g.My ? m.r : m.r - g.Ky;
+    m.kx = 2.0 * M_PI * m.mx / g.lx;
+    m.ky = g.ny == 1 ? 0.0 : 2.0 * M_PI * my / g.ly;
+    m.k = sqrt(m.kx * m.kx + m.ky * m.ky);
+    return m;
+}
+
+template <typename R>
+__global__ void k_rk(const RkParams p) {
+    using V = typename cplx_of<R>::type;
+    const int mem = blockIdx.y;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= p.g.s_cmp) return;
+    const ModeGeo m = mode_geo(p.g, idx);
+    if (!m.valid) return;
+    const long long o = mem * p.g.s_cmp + idx;
+    const double href = p.g.href[mem];
+    const double om2 = m.k * tanh(m.k * href);
+    const double om = sqrt(om2);
+    const double h = p.h;
+    V* eh = static_cast<V*>(p.eh);
+    V* ph = static_cast<V*>(p.ph);
+    V* es = static_cast<V*>(p.es);
+    V* ps = static_cast<V*>(p.ps);
+    V* ae = static_cast<V*>(p.ae);
+    V* ap = static_cast<V*>(p.ap);
+    const V vh = static_cast<const V*>(p.Vh)[o];
+    const V nph = static_cast<const V*>(p.Nph)[o];
+    const V psv = ps[o];
+    // derivative of the stage: (W_hat - omega^2 phi_hat, N_phi)
+    const double de_r = (double)vh.x - om2 * (double)psv.x, de_i = (double)vh.y - om2 * (double)psv.y;
+    const double dp_r = (double)nph.x, dp_i = (double)nph.y;
+    const double u_er = (double)eh[o].x, u_ei = (double)eh[o].y;
+    const double u_pr = (double)ph[o].x, u_pi = (double)ph[o].y;
+    auto prop = [&](double tau, double er, double ei, double pr, double pi_, double* oer, double* oei, double* opr,
+                    double* opi) {
+        const double c = cos(om * tau), s = sin(om * tau);
+        const double sw = om > 0.0 ? s / om : tau;
+        *oer = c * er + om * s * pr;
+        *oei = c * ei + om * s * pi_;
+        *opr = -sw * er + c * pr;
+        *opi = -sw * ei + c * pi_;
+    };
+    double a_er, a_ei, a_pr, a_pi;   // accumulator
+    double n_er, n_ei, n_pr, n_pi;   // next stage state
+    if (p.stage == 0) {
+        prop(h, de_r, de_i, dp_r, dp_i, &a_er, &a_ei, &a_pr, &a_pi);
+        prop(0.5 * h, u_er + 0.5 * h * de_r, u_ei + 0.5 * h * de_i, u_pr + 0.5 * h * dp_r, u_pi + 0.5 * h * dp_i,
+             &n_er, &n_ei, &n_pr, &n_pi);
+    } else if (p.stage == 1 || p.stage == 2) {
+        double b_er, b_ei, b_pr, b_pi;
+        prop(0.5 * h, de_r, de_i, dp_r, dp_i, &b_er, &b_ei, &b_pr, &b_pi);
+        a_er = (double)ae[o].x + 2.0 * b_er;
+        a_ei = (double)ae[o].y + 2.0 * b_ei;
+        a_pr = (double)ap[o].x + 2.0 * b_pr;
+        a_pi = (double)ap[o].y + 2.0 * b_pi;
+        if (p.stage == 1) {
+            prop(0.5 * h, u_er, u_ei, u_pr, u_pi, &n_er, &n_ei, &n_pr, &n_pi);
+            n_er += 0.5 * h * de_r;
+            n_ei += 0.5 * h * de_i;
+            n_pr += 0.5 * h * dp_r;
+            n_pi += 0.5 * h * dp_i;
+        } else {
+            prop(h, u_er, u_ei, u_pr, u_pi, &n_er, &n_ei, &n_pr, &n_pi);
+            n_er += h * b_er;
+            n_ei += h * b_ei;
+            n_pr += h * b_pr;
+            n_pi += h * b_pi;
+        }
+    } else {
+        prop(h, u_er, u_ei, u_pr, u_pi, &n_er, &n_ei, &n_pr, &n_pi);
+        n_er += h / 6.0 * ((double)ae[o].x + de_r);
+        n_ei += h / 6.0 * ((double)ae[o].y + de_i);
+        n_pr += h / 6.0 * ((double)ap[o].x + dp_r);
+        n_pi += h / 6.0 * ((double)ap[o].y + dp_i);
+        if (p.fb1 > 0.0 && p.fb2 > 0.0) {
+            const double lam = exp(-pow(fabs(m.k / p.fb1), p.fb2));
+            n_er *= lam;
+            n_ei *= lam;
+            n_pr *= lam;
+            n_pi *= lam;
+        }
+        eh[o] = cx<V>(R(n_er), R(n_ei));
+        ph[o] = cx<V>(R(n_pr), R(n_pi));
+        es[o] = cx<V>(R(n_er), R(n_ei));
+        ps[o] = cx<V>(R(n_pr), R(n_pi));
+        return;
+    }
+    ae[o] = cx<V>(R(a_er), R(a_ei));
+    ap[o] = cx<V>(R(a_pr), R(a_pi));
+    es[o] = cx<V>(R(n_er), R(n_ei));
+    ps[o] = cx<V>(R(n_pr), R(n_pi));
+}
+
+template <typename R>
+__global__ void k_diag(const DiagParams p) {
+    using V = typename cplx_of<R>::type;
+    __shared__ double red[2][256];
+    const int mem = blockIdx.y;
+    double se = 0.0, sm = 0.0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < p.g.s_cmp;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const ModeGeo m = mode_geo(p.g, idx);
+        if (!m.valid) continue;
+        const long long o = mem * p.g.s_cmp + idx;
+        const V e = static_cast<const V*>(p.eh)[o];
+        const V f = static_cast<const V*>(p.ph)[o];
+        const V w = static_cast<const V*>(p.Vh)[o];
+        const double wt = m.mx == 0 ? 1.0 : 2.0;
+        se += wt * ((double)w.x * (double)f.x + (double)w.y * (double)f.y + (double)e.x * (double)e.x +
+                    (double)e.y * (double)e.y);
+        if (idx == 0) sm += (double)e.x;
+    }
+    red[0][threadIdx.x] = se;
+    red[1][threadIdx.x] = sm;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        p.partial[((long long)mem * p.nblk + blockIdx.x) * 2 + 0] = red[0][0];
+        p.partial[((long long)mem * p.nblk + blockIdx.x) * 2 + 1] = red[1][0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers (size dispatch)
+// ---------------------------------------------------------------------------
+template <typename R, int NX> struct RowLaunch {
+    using V = typename cplx_of<R>::type;
+    static void shape(int ny, dim3* grid, dim3* block, size_t* lds, int batch) {
+        constexpr int P = Row<R, NX>::P;
+        int rpw = 256 / P;
+        if (rpw < 1) rpw = 1;
+        if (rpw > ny) rpw = ny;
+        *block = dim3(P * rpw);
+        *grid = dim3((ny + rpw - 1) / rpw, batch);
+        *lds = (size_t)rpw * Row<R, NX>::N * sizeof(V);
+    }
+};
+
+#define SBI_ROW_LAUNCH(KNAME, PTYPE)                                                                       \
+    template <typename R, int NX>                                                                          \
+    static hipError_t KNAME##_go(const PTYPE& p, int batch, const Twiddles& tw, hipStream_t s) {           \
+        using V = typename cplx_of<R>::type;                                                               \
+        dim3 grid, block;                                                                                  \
+        size_t lds;                                                                                        \
+        RowLaunch<R, NX>::shape(p.g.ny, &grid, &block, &lds, batch);                                       \
+        hipLaunchKernelGGL((KNAME<R, NX>), grid, block, lds, s, p, (const V*)tw.tn, (const V*)tw.tx);      \
+        return hipGetLastError();                                                                          \
+    }                                                                                                      \
+    template <typename R>                                                                                  \
+    static hipError_t KNAME##_nx(const PTYPE& p, int batch, const Twiddles& tw, hipStream_t s) {           \
+        switch (p.g.nx) {                                                                                  \
+            case 16: return KNAME##_go<R, 16>(p, batch, tw, s);                                            \
+            case 32: return KNAME##_go<R, 32>(p, batch, tw, s);                                            \
+            case 64: return KNAME##_go<R, 64>(p, batch, tw, s);                                            \
+            case 128: return KNAME##_go<R, 128>(p, batch, tw, s);                                          \
+            case 256: return KNAME##_go<R, 256>(p, batch, tw, s);                                          \
+            case 512: return KNAME##_go<R, 512>(p, batch, tw, s);                                          \
+            case 1024: return KNAME##_go<R, 1024>(p, batch, tw, s);                                        \
+            case 2048: return KNAME##_go<R, 2048>(p, batch, tw, s);                                        \
+            case 4096: return KNAME##_go<R, 4096>(p, batch, tw, s);                                        \
+            case 8192: return KNAME##_go<R, 8192>(p, batch, tw, s);                                        \
+            default: return hipErrorInvalidValue;                                                          \
+        }                                                                                                  \
+    }
+
+SBI_ROW_LAUNCH(k_row_fwd, RowFwdParams)
+SBI_ROW_LAUNCH(k_row_inv, RowInvParams)
+SBI_ROW_LAUNCH(k_row_setup, RowSetupParams)
+SBI_ROW_LAUNCH(k_row_sweep, RowSweepParams)
+SBI_ROW_LAUNCH(k_row_sa, RowSaParams)
+SBI_ROW_LAUNCH(k_row_nphi, RowNphiParams)
+SBI_ROW_LAUNCH(k_row_blend, RowBlendParams)
+
+template <typename R, int NY, int NACC>
+static hipError_t col_go(const ColParams& p, int batch, const Twiddles& tw, hipStream_t s) {
+    using V = typename cplx_of<R>::type;
+    constexpr int C = col_width<R, NY>();
+    constexpr int P = FftShape<NY>::P;
+    dim3 block(C * P);
+    dim3 grid(p.g.Kxp / C, batch);
+    size_t lds = NY > 1 ? (size_t)NY * C * sizeof(V) : 0;
+    hipLaunchKernelGGL((k_col<R, NY, NACC>), grid, block, lds, s, p, (const V*)tw.ty);
+    return hipGetLastError();
+}
+template <typename R, int NY>
+static hipError_t col_acc(const ColParams& p, int batch, const Twiddles& tw, hipStream_t s) {
+    if (p.nacc <= 1) return col_go<R, NY, 1>(p, batch, tw, s);
+    if (p.nacc <= 2) return col_go<R, NY, 2>(p, batch, tw, s);
+    return col_go<R, NY, 4>(p, batch, tw, s);
+}
+template <typename R>
+static hipError_t col_ny(const ColParams& p, int batch, const Twiddles& tw, hipStream_t s) {
+    switch (p.g.ny) {
+        case 1: return col_acc<R, 1>(p, batch, tw, s);
+        case 16: return col_acc<R, 16>(p, batch, tw, s);
+        case 32: return col_acc<R, 32>(p, batch, tw, s);
+        case 64: return col_acc<R, 64>(p, batch, tw, s);
+        case 128: return col_acc<R, 128>(p, batch, tw, s);
+        case 256: return col_acc<R, 256>(p, batch, tw, s);
+        case 512: return col_acc<R, 512>(p, batch, tw, s);
+        case 1024: return col_acc<R, 1024>(p, batch, tw, s);
+        case 2048: return col_acc<R, 2048>(p, batch, tw, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+// ---------------------------------------------------------------------------
+// per-precision entry points (this file is compiled once per precision with
+// SBI_REAL defined; sbi_dispatch.hip selects between them)
+// ---------------------------------------------------------------------------
+using Real = SBI_REAL;
+template <> hipError_t launch_row_fwd_t<Real>(const RowFwdParams& p, int b, const Twiddles& tw, hipStream_t s) {
+    return k_row_fwd_nx<Real>(p, b, tw, s);
+}
+template <> hipError_t launch_row_inv_t<Real>(const RowInvParams& p, int b, const Twiddles& tw, hipStream_t s) {
+    return k_row_inv_nx<Real>(p, b, tw, s);
+}
+template <> hipError_t launch_row_setup_t<Real>(const RowSetupParams& p, int b, const Twiddles& tw, hipStream_t s) {
+    return k_row_setup_nx<Real>(p, b, tw, s);
+}
+template <> hipError_t launch_row_sweep_t<Real>(const RowSweepParams& p, int b, const Twiddles& tw, hipStream_t s) {
+    return k_row_sweep_nx<Real>(p, b, tw, s);
+}
+template <> hipError_t launch_row_sa_t<Real>(const RowSaParams& p, int b, const Twiddles& tw, hipStream_t s) {
+    return k_row_sa_nx<Real>(p, b, tw, s);
+}
+template <> hipError_t launch_row_nphi_t<Real>(const RowNphiParams& p, int b, const Twiddles& tw, hipStream_t s) {
+    return k_row_nphi_nx<Real>(p, b, tw, s);
+}
+template <> hipError_t launch_row_blend_t<Real>(const RowBlendParams& p, int b, const Twiddles& tw, hipStream_t s) {
+    return k_row_blend_nx<Real>(p, b, tw, s);
+}
+template <> hipError_t launch_col_t<Real>(const ColParams& p, int b, const Twiddles& tw, hipStream_t s) {
+    return col_ny<Real>(p, b, tw, s);
+}
+template <> hipError_t launch_rk_t<Real>(const RkParams& p, int batch, hipStream_t s) {
+    dim3 block(256), grid((unsigned)((p.g.s_cmp + 255) / 256), batch);
+    hipLaunchKernelGGL(k_rk<Real>, grid, block, 0, s, p);
+    return hipGetLastError();
+}
+template <> hipError_t launch_diag_t<Real>(const DiagParams& p, int batch, hipStream_t s) {
+    dim3 block(256), grid(p.nblk, batch);
+    hipLaunchKernelGGL(k_diag<Real>, grid, block, 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace sbi

@@ -1,0 +1,154 @@
+// sbi_kernels.hpp -- parameter blocks of the row passes and pointwise kernels,
+// and the size-dispatching launch functions implemented in sbi_kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "sbi_internal.hpp"
+
+namespace sbi {
+
+struct RowFwdParams {
+    GridDev g;
+    int nf;
+    const void* in[4];   // physical [ny][nx]
+    void* out[4];        // half form
+};
+
+struct RowInvParams {
+    GridDev g;
+    int nf;
+    const void* in[8];   // half form
+    const void* in2[8];  // optional second half form added with (1 - omega)
+    void* out[8];        // physical
+    Ctl* ctl;
+};
+
+struct RowSetupParams {
+    GridDev g;
+    const void* g_eta;        // half form of eta (or null when eta_in is given)
+    const void* eta_in;       // physical eta given by the caller (or null)
+    void* eta_out;            // physical eta written (may be null when eta_in)
+    const void* g_px;         // half forms of the potential gradient
+    const void* g_py;
+    void* px_out;             // physical gradient (SA mode), may be null
+    void* py_out;
+    int nprod;                // forcing products eta^(l-1) grad phi, l = 2..L
+    void* h[kMaxProd];
+    Ctl* ctl;
+};
+
+struct RowSweepParams {
+    GridDev g;
+    const void* gV;     // half form of the current iterate V_n
+    const void* gD;     // half form of D_(n-1) = T(V_(n-1)) - V_(n-1)
+    const void* gbx;    // half forms of grad phi_b,n (variable depth)
+    const void* gby;
+    const void* eta;    // physical
+    const void* delta;  // physical
+    int J;              // convolution orders of the sweep
+    int residual;       // compute the residual of the previous sweep into slot
+    int products;       // form the products of this sweep
+    int vd;             // variable depth
+    int slot;
+    void* h[kMaxProd];
+    Ctl* ctl;
+};
+
+struct RowSaParams {
+    GridDev g;
+    int l;              // order being formed
+    int vd;
+    const void* gV;     // half form of V_(l-1)
+    const void* gbx;    // half forms of grad phi_b,(l-1) (vd and l-1 <= L-1)
+    const void* gby;
+    void* V_out;        // physical V_(l-1) (kept for higher orders), may be null
+    void* bx_out;
+    void* by_out;
+    const void* Vphys[8];   // physical V_m, m < l-1
+    const void* bxphys[8];
+    const void* byphys[8];
+    const void* eta;
+    const void* delta;
+    const void* phx;    // physical grad phi_s
+    const void* phy;
+    void* h[kMaxProd];
+};
+
+struct RowNphiParams {
+    GridDev g;
+    const void* gV;
+    const void* gD;     // optional: V' = V + (1-omega) D
+    const void* gex;
+    const void* gey;
+    const void* gpx;
+    const void* gpy;
+    void* h;
+    Ctl* ctl;
+};
+
+struct RowBlendParams {
+    GridDev g;
+    const void* ge;
+    const void* gp;
+    void* he;
+    void* hp;
+    double a, k, om, gen, absl, ramp_time, t;
+};
+
+struct RkParams {
+    GridDev g;
+    int stage;
+    double h;
+    void* eh;        // u_n (updated at stage 3)
+    void* ph;
+    void* es;        // stage state in / next stage state out
+    void* ps;
+    const void* Vh;  // W spectrum at the stage state
+    const void* Nph; // nonlinear term of the potential equation
+    void* ae;        // accumulator
+    void* ap;
+    double fb1, fb2; // filter
+};
+
+struct DiagParams {
+    GridDev g;
+    const void* eh;
+    const void* ph;
+    const void* Vh;
+    double* partial;  // [batch][nblk][2]
+    int nblk;
+};
+
+struct Twiddles {
+    const void* tx;   // length nx
+    const void* tn;   // length nx/2
+    const void* ty;   // length ny
+};
+
+int col_tile(int ny, int fp64);   // column-tile width C for a grid
+
+// per-precision launchers (defined in sbi_kernels.hip, one object per precision)
+template <typename R> hipError_t launch_row_fwd_t(const RowFwdParams&, int, const Twiddles&, hipStream_t);
+template <typename R> hipError_t launch_row_inv_t(const RowInvParams&, int, const Twiddles&, hipStream_t);
+template <typename R> hipError_t launch_row_setup_t(const RowSetupParams&, int, const Twiddles&, hipStream_t);
+template <typename R> hipError_t launch_row_sweep_t(const RowSweepParams&, int, const Twiddles&, hipStream_t);
+template <typename R> hipError_t launch_row_sa_t(const RowSaParams&, int, const Twiddles&, hipStream_t);
+template <typename R> hipError_t launch_row_nphi_t(const RowNphiParams&, int, const Twiddles&, hipStream_t);
+template <typename R> hipError_t launch_row_blend_t(const RowBlendParams&, int, const Twiddles&, hipStream_t);
+template <typename R> hipError_t launch_col_t(const ColParams&, int, const Twiddles&, hipStream_t);
+template <typename R> hipError_t launch_rk_t(const RkParams&, int, hipStream_t);
+template <typename R> hipError_t launch_diag_t(const DiagParams&, int, hipStream_t);
+
+hipError_t launch_row_fwd(int fp64, const RowFwdParams& p, int batch, const Twiddles& tw, hipStream_t s);
+hipError_t launch_row_inv(int fp64, const RowInvParams& p, int batch, const Twiddles& tw, hipStream_t s);
+hipError_t launch_row_setup(int fp64, const RowSetupParams& p, int batch, const Twiddles& tw, hipStream_t s);
+hipError_t launch_row_sweep(int fp64, const RowSweepParams& p, int batch, const Twiddles& tw, hipStream_t s);
+hipError_t launch_row_sa(int fp64, const RowSaParams& p, int batch, const Twiddles& tw, hipStream_t s);
+hipError_t launch_row_nphi(int fp64, const RowNphiParams& p, int batch, const Twiddles& tw, hipStream_t s);
+hipError_t launch_row_blend(int fp64, const RowBlendParams& p, int batch, const Twiddles& tw, hipStream_t s);
+hipError_t launch_col(int fp64, const ColParams& p, int batch, const Twiddles& tw, hipStream_t s);
+hipError_t launch_rk(int fp64, const RkParams& p, int batch, hipStream_t s);
+hipError_t launch_diag(int fp64, const DiagParams& p, int batch, hipStream_t s);
+hipError_t launch_ctl_reset(Ctl* ctl, int batch, int slots, hipStream_t s);
+hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
+
+}  // namespace sbi

@@ -1,0 +1,93 @@
+"""The C interface: every symbol declared in include/sbi.h is exported by
+libsbi.so, and the host-only entry points validate their arguments.  Runs
+without a GPU (no compute call is made)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sbi.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sbi_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2310_19840_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libsbi.so not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_header_declares_the_interface():
+    names = _declared_functions()
+    for n in ("sbi_init", "sbi_vertical_velocity", "sbi_step", "sbi_diagnostics", "sbi_destroy",
+              "sbi_workspace_bytes", "sbi_status_string"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2310_19840_amd import _lib
+    for n in _declared_functions():
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, f"binding lacks {n}"
+
+
+def test_grid_defaults_and_workspace(lib):
+    from paper_2310_19840_amd import _lib, make_grid
+    g = _lib.sbi_grid()
+    lib.sbi_grid_defaults(C.byref(g))
+    assert g.order == 7 and abs(g.dealias - 0.5) < 1e-15 and g.max_sweeps == 64 and g.relax == 1
+    g = make_grid(1024, 1024, 100.0, 100.0)
+    b1 = lib.sbi_workspace_bytes(C.byref(g), 1)
+    b2 = lib.sbi_workspace_bytes(C.byref(g), 2)
+    assert b1 > 0 and b2 > b1
+    g32 = make_grid(1024, 1024, 100.0, 100.0, precision="fp32")
+    assert lib.sbi_workspace_bytes(C.byref(g32), 1) < b1
+
+
+@pytest.mark.parametrize("bad", [dict(nx=100), dict(nx=8), dict(ny=8), dict(ny=3000), dict(order=8),
+                                 dict(order=0), dict(dealias=1.0), dict(max_sweeps=0), dict(lx=-1.0)])
+def test_invalid_grids_rejected(lib, bad):
+    from paper_2310_19840_amd import make_grid
+    kw = dict(nx=64, ny=16, lx=10.0, ly=10.0)
+    kw.update(bad)
+    g = make_grid(**kw)
+    assert lib.sbi_workspace_bytes(C.byref(g), 1) == 0
+    assert lib.sbi_workspace_bytes(C.byref(make_grid(64, 16, 10.0, 10.0)), 0) == 0
+
+
+def test_status_strings(lib):
+    from paper_2310_19840_amd import _lib
+    for code in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6):
+        s = _lib.status_string(code)
+        assert s.startswith("SBI_")
+    assert "unknown" in _lib.status_string(42)
+
+
+def test_null_arguments_rejected(lib):
+    from paper_2310_19840_amd import _lib, make_grid
+    g = make_grid(64, 1, 10.0)
+    ctx = C.c_void_p()
+    # null depth / null out
+    assert lib.sbi_init(C.byref(ctx), C.byref(g), 1, None, -1.0, None, 0, None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_init(None, C.byref(g), 1, None, -1.0, None, 0, None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_destroy(None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_vertical_velocity(None, None, None, None, 1e-8, None, None, None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_step(None, None, 0.1, 1, 1e-8, None) == _lib.SBI_ERR_INVALID_ARG
+
+
+def test_product_path_has_no_cpu_fallback():
+    # the package must not import the oracle nor offer a CPU path
+    pkg = os.path.join(ROOT, "paper_2310_19840_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(".py"):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in src.replace("the oracle", ""), f
