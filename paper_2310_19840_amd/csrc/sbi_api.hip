@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -97,6 +98,10 @@ struct sbi_ctx {
     double* href_dev = nullptr;
     Ctl* ctl = nullptr;
     double* diag_partial = nullptr;
+    void* part = nullptr;    // partial sums of grouped column passes
+    int* cnt = nullptr;      // tile tickets of grouped column passes
+    int col_C = 1;
+    int group_target = 0;    // workgroups a column pass should reach by splitting products (0: never split)
     int diag_nblk = 64;
     std::vector<double> href;
     bool vd = false;         // some member has a non-flat bed
@@ -105,7 +110,7 @@ struct sbi_ctx {
     double rz[6] = {0, 0, 0, 0, 0, 0};
     Stats st;
     Profiler prof;
-    std::vector<Ctl> head;   // host copy of the control headers (first kCtlHeadBytes)
+    Ctl* head = nullptr;     // pinned host copy of the control headers
     sbi_step_info step_acc{};
 };
 
@@ -142,7 +147,7 @@ static sbi_status hip_ok(hipError_t e) { return e == hipSuccess ? SBI_OK : SBI_E
 // sizes and layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    int Mx, My, Kx, Kxp, Ky, C;
+    int Mx, My, Kx, Kxp, Ky, C, ldh;
     size_t rsz, csz;
     long long s_phys, s_half, s_cmp;
     size_t bytes_comp, bytes_half, bytes_phys, bytes_tw, bytes_misc, total;
@@ -162,6 +167,15 @@ static bool grid_valid(const sbi_grid* g) {
     return true;
 }
 
+// pad (bytes) appended to every half-form column; SBI_HALF_PAD_BYTES overrides
+static int half_pad_bytes() {
+    static int v = [] {
+        const char* e = std::getenv("SBI_HALF_PAD_BYTES");
+        return e ? std::max(0, std::atoi(e)) : 256;
+    }();
+    return v;
+}
+
 static Layout layout(const sbi_grid* g, int batch) {
     Layout L{};
     const bool f64 = g->precision == SBI_FP64;
@@ -174,14 +188,17 @@ static Layout layout(const sbi_grid* g, int batch) {
     L.Kxp = (L.Kx + L.C - 1) / L.C * L.C;
     L.Ky = g->ny == 1 ? 1 : 2 * L.My + 1;
     L.s_phys = (long long)g->nx * g->ny;
-    L.s_half = (long long)g->ny * L.Kxp;
+    L.ldh = g->ny == 1 ? 1 : g->ny + (int)(half_pad_bytes() / L.csz);
+    L.s_half = (long long)L.ldh * L.Kxp;
     L.s_cmp = (long long)L.Ky * L.Kxp;
     auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     L.bytes_comp = al((size_t)L.s_cmp * L.csz * batch) * C_COUNT;
     L.bytes_half = al((size_t)L.s_half * L.csz * batch) * H_COUNT;
     L.bytes_phys = al((size_t)L.s_phys * L.rsz * batch) * P_COUNT;
     L.bytes_tw = al((size_t)g->nx * L.csz) + al((size_t)(g->nx / 2) * L.csz) + al((size_t)g->ny * L.csz);
-    L.bytes_misc = al(sizeof(double) * batch) + al(sizeof(Ctl) * batch) + al(sizeof(double) * 2 * 64 * batch);
+    L.bytes_misc = al(sizeof(double) * batch) + al(sizeof(Ctl) * batch) + al(sizeof(CtlSlots) * batch) +
+                   al(sizeof(double) * 2 * 64 * batch) +
+                   al((size_t)L.s_cmp * L.csz * batch * kMaxGroups * 4) + al(sizeof(int) * (size_t)kMaxTiles * batch);
     L.total = L.bytes_comp + L.bytes_half + L.bytes_phys + L.bytes_tw + L.bytes_misc;
     return L;
 }
@@ -298,6 +315,7 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
     gd.kband = std::hypot(2.0 * M_PI * L.Mx / g->lx, g->ny == 1 ? 0.0 : 2.0 * M_PI * L.My / g->ly);
     gd.s_phys = L.s_phys;
     gd.s_half = L.s_half;
+    gd.ldh = L.ldh;
     gd.s_cmp = L.s_cmp;
     gd.relax = g->relax;
     if (workspace) {
@@ -335,10 +353,24 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
     p += al(sizeof(double) * batch);
     c->ctl = reinterpret_cast<Ctl*>(p);
     p += al(sizeof(Ctl) * batch);
+    CtlSlots* slots = reinterpret_cast<CtlSlots*>(p);
+    p += al(sizeof(CtlSlots) * batch);
     c->diag_partial = reinterpret_cast<double*>(p);
     p += al(sizeof(double) * 2 * 64 * batch);
+    c->part = p;
+    p += al((size_t)L.s_cmp * L.csz * batch * kMaxGroups * 4);
+    c->cnt = reinterpret_cast<int*>(p);
+    p += al(sizeof(int) * (size_t)kMaxTiles * batch);
+    c->col_C = L.C;
     gd.href = c->href_dev;
-    c->head.resize(batch);
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->head), sizeof(Ctl) * batch, hipHostMallocDefault) != hipSuccess) {
+        if (c->own_ws) (void)hipFree(c->ws);
+        delete c;
+        return SBI_ERR_HIP;
+    }
+    // SBI_COL_GROUP_TARGET: workgroups a column pass aims for by splitting its
+    // products over workgroups (tuning knob; 0 = one workgroup per tile)
+    if (const char* e = std::getenv("SBI_COL_GROUP_TARGET")) c->group_target = std::atoi(e);
 
     sbi_status st = hip_ok(launch_fill_zero(c->ws, L.total, c->stream));
     if (st == SBI_OK) {
@@ -352,11 +384,20 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
         if (st == SBI_OK) st = up(c->tx, g->nx);
         if (st == SBI_OK) st = up(c->tn, g->nx / 2);
         if (st == SBI_OK) st = up(c->ty, g->ny);
+        if (st == SBI_OK) {
+            for (int b = 0; b < batch; ++b) {
+                std::memset(&c->head[b], 0, sizeof(Ctl));
+                c->head[b].slots = slots + b;
+            }
+            st = hip_ok(hipMemcpyAsync(c->ctl, c->head, sizeof(Ctl) * batch, hipMemcpyHostToDevice, c->stream));
+            if (st == SBI_OK) st = hip_ok(hipStreamSynchronize(c->stream));
+        }
         if (st == SBI_OK) st = hip_ok(launch_ctl_reset(c->ctl, batch, kMaxSweepSlots, c->stream));
         if (st == SBI_OK) st = set_depth(c, depth, h_ref);
     }
     if (st < 0) {
         if (c->own_ws) (void)hipFree(c->ws);
+        (void)hipHostFree(c->head);
         delete c;
         return st;
     }
@@ -369,6 +410,7 @@ extern "C" sbi_status sbi_destroy(sbi_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     prof_flush(c);
     for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+    (void)hipHostFree(c->head);
     if (c->own_ws) {
         (void)hipStreamSynchronize(c->stream);
         (void)hipFree(c->ws);
@@ -535,8 +577,24 @@ static Twiddles tw_of(const sbi_ctx* c) {
 #define HALF(i) (c->half[(i)])
 #define PHYS(i) (c->phys[(i)])
 
+// Split the products of a column pass over workgroups along y when the tiles
+// alone cannot fill the GPU (~512 workgroups wanted).
+static void set_groups(sbi_ctx* c, ColParams& p) {
+    p.ngroup = 1;
+    p.part = c->part;
+    p.cnt = c->cnt;
+    const int np = p.nprod;
+    if (np <= 1 || c->grid.ny == 1 || c->group_target <= 0) return;
+    const int tiles = c->gd.Kxp / c->col_C;
+    int want = (c->group_target + tiles * c->batch - 1) / (tiles * c->batch);
+    want = std::max(1, std::min(want, std::min(np, kMaxGroups)));
+    p.ngroup = want;
+    for (int g = 0; g <= want; ++g) p.gstart[g] = (g * np) / want;
+}
+
 static sbi_status run_col(sbi_ctx* c, ColBuilder& b, int cls = K_COL_OTHER) {
     if (!b.build()) return SBI_ERR_UNSUPPORTED;
+    set_groups(c, b.p);
     c->st.launches += 1;
     ProfScope ps(c, cls);
     return hip_ok(launch_col(c->fp64, b.p, c->batch, tw_of(c), c->stream));
@@ -677,6 +735,7 @@ static sbi_status launch_sweep(sbi_ctx* c, const void* eta_phys, int n, double t
     rp.products = n < M && J >= 1;
     rp.vd = c->vd;
     rp.slot = n >= 1 ? n - 1 : 0;
+    rp.nfam = rp.products ? 1 + (c->vd ? (two_d ? 2 : 1) : 0) : 1;
     int np = 0;
     if (rp.products) {
         np = J * (1 + (c->vd ? (two_d ? 2 : 1) : 0));
@@ -748,8 +807,7 @@ static sbi_status launch_sweep(sbi_ctx* c, const void* eta_phys, int n, double t
 }
 
 static sbi_status read_heads(sbi_ctx* c) {
-    SBI_HIP(hipMemcpy2DAsync(c->head.data(), sizeof(Ctl), c->ctl, sizeof(Ctl), kCtlHeadBytes, c->batch,
-                             hipMemcpyDeviceToHost, c->stream));
+    SBI_HIP(hipMemcpyAsync(c->head, c->ctl, sizeof(Ctl) * c->batch, hipMemcpyDeviceToHost, c->stream));
     SBI_HIP(hipStreamSynchronize(c->stream));
     c->st.syncs += 1;
     if (c->prof.on) prof_flush(c);

@@ -4,19 +4,21 @@
 
 namespace sbi {
 
+// columns per column-pass workgroup (must equal col_width<R, NY>() of the kernels)
 int col_tile(int ny, int fp64) {
     if (ny == 1) return 64;
-    int c = 65536 / (ny * (fp64 ? 16 : 8));
-    if (c > 16) c = 16;
-    if (c < 1) c = 1;
-    return c;
+    int e = fp64 ? 4 : 8;
+    if (e > ny) e = ny;
+    const int P = ny / e;
+    return P >= 256 ? 1 : 256 / P;
 }
 
 __global__ void k_ctl_reset(Ctl* ctl, int slots) {
     Ctl* c = ctl + blockIdx.x;
+    CtlSlots* sl = c->slots;
     for (int i = threadIdx.x; i < slots; i += blockDim.x) {
-        c->num[i] = 0ull;
-        c->den[i] = 0ull;
+        sl->num[i] = 0ull;
+        sl->den[i] = 0ull;
     }
     if (threadIdx.x == 0) {
         c->eta_max = 0ull;

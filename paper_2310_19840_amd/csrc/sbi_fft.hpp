@@ -20,7 +20,6 @@ template <> struct cplx_of<double> { using type = double2; };
 template <> struct cplx_of<float> { using type = float2; };
 
 template <typename V> __device__ __forceinline__ V cx(decltype(V::x) a, decltype(V::x) b) { V r; r.x = a; r.y = b; return r; }
-template <typename V> __device__ __forceinline__ V operator_add(V a, V b) { return cx<V>(a.x + b.x, a.y + b.y); }
 
 template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return cx<V>(a.x + b.x, a.y + b.y); }
 template <typename V> __device__ __forceinline__ V csub(V a, V b) { return cx<V>(a.x - b.x, a.y - b.y); }
@@ -34,6 +33,14 @@ template <bool INV, typename V> __device__ __forceinline__ V mul_mi(V a) {
     return INV ? cx<V>(-a.y, a.x) : cx<V>(a.y, -a.x);
 }
 template <typename V> __device__ __forceinline__ V mul_i(V a) { return cx<V>(-a.y, a.x); }
+
+// Workgroup barrier that orders LDS only: outstanding global loads (prefetch)
+// stay in flight across it.
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 template <int R, bool INV, typename V> struct Dft;
 
@@ -91,16 +98,73 @@ template <bool INV, typename V> struct Dft<8, INV, V> {
 
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
-// Elements per thread for a length-N transform.
-template <int N> struct FftShape {
-    static constexpr int E = N >= 8 ? 8 : N;
+// Elements per thread for a length-N transform (at most EMAX, a power of two
+// in {2, 4, 8}).
+template <int N, int EMAX = 8> struct FftShape {
+    static constexpr int E = N >= EMAX ? EMAX : N;
     static constexpr int P = N / E;
 };
 
+// Pass sequence of a length-N transform with E elements per thread: radix
+// R_i = min(E, N / Ns_i), Ns_0 = 1, Ns_(i+1) = Ns_i R_i.  Passes with Ns > 1
+// need one base twiddle per butterfly (E / R per thread); TwCount/TwOffset
+// size and index the per-thread twiddle cache.
+template <int N, int E, int Ns> struct PassInfo {
+    static constexpr int REM = N / Ns;
+    static constexpr int R = REM >= E ? E : REM;
+    static constexpr bool LAST = (Ns * R == N);
+    static constexpr int B = E / R;
+    static constexpr int NEED = (Ns > 1) ? B : 0;
+    static constexpr int NEXT = Ns * R;
+};
+template <int N, int E, int Ns, bool DONE = (Ns >= N)> struct TwCountFrom {
+    static constexpr int value = PassInfo<N, E, Ns>::NEED + TwCountFrom<N, E, PassInfo<N, E, Ns>::NEXT>::value;
+};
+template <int N, int E, int Ns> struct TwCountFrom<N, E, Ns, true> {
+    static constexpr int value = 0;
+};
+// offset of pass Ns in the cache = twiddles of all earlier passes
+template <int N, int E, int Ns, int Cur = 1, bool AT = (Cur == Ns)> struct TwOffset {
+    static constexpr int value = PassInfo<N, E, Cur>::NEED + TwOffset<N, E, Ns, PassInfo<N, E, Cur>::NEXT>::value;
+};
+template <int N, int E, int Ns, int Cur> struct TwOffset<N, E, Ns, Cur, true> {
+    static constexpr int value = 0;
+};
+
+// Per-thread twiddle cache: the base twiddles of every pass for thread j,
+// loaded once and reused by every transform of the same length.
+template <typename V, int N, int E> struct Twid {
+    static constexpr int NT = TwCountFrom<N, E, 1>::value;
+    V w[NT > 0 ? NT : 1];
+    template <int Ns> __device__ __forceinline__ void load_from(const V* __restrict__ tw, int j) {
+        if constexpr (Ns < N) {
+            using PI = PassInfo<N, E, Ns>;
+            if constexpr (Ns > 1) {
+                constexpr int off = TwOffset<N, E, Ns>::value;
+                constexpr int P = N / E;
+#pragma unroll
+                for (int s = 0; s < PI::B; ++s) {
+                    const int b = j + s * P;
+                    const int k = b & (Ns - 1);
+                    w[off + s] = tw[k * (N / (Ns * PI::R))];
+                }
+            }
+            load_from<PI::NEXT>(tw, j);
+        }
+    }
+    __device__ __forceinline__ void load(const V* __restrict__ tw, int j) { load_from<1>(tw, j); }
+};
+
+// LDS slot of transform element idx: the first Stockham pass writes with a
+// stride of E elements (E x 16 B in FP64), which folds a wavefront onto a few
+// LDS banks; one pad slot per E elements spreads every pass over all banks.
+template <int E> __device__ __forceinline__ int lds_slot(int idx) { return E >= 2 ? idx + idx / E : idx; }
+// LDS elements one transform of length N with E elements per thread needs
+template <int N, int E> __host__ __device__ constexpr int fft_lds_elems() { return E >= 2 ? N + N / E : N; }
+
 // One Stockham pass of radix R with current span Ns (product of earlier radices).
-// tw: table of length N with tw[m] = exp(-2 pi i m / N) (host FP64 values).
 template <typename V, int N, int E, int R, int Ns, bool INV, bool LAST, int LS>
-__device__ __forceinline__ void stockham_pass(V (&v)[E], V* lds, int lo, int j, const V* __restrict__ tw) {
+__device__ __forceinline__ void stockham_pass(V (&v)[E], V* lds, int lo, int j, const Twid<V, N, E>& tw) {
     constexpr int P = N / E;
     constexpr int B = E / R;
 #pragma unroll
@@ -110,12 +174,16 @@ __device__ __forceinline__ void stockham_pass(V (&v)[E], V* lds, int lo, int j, 
         V u[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) u[r] = v[s + r * B];
-        if (Ns > 1) {
+        if constexpr (Ns > 1) {
+            // base twiddle from the cache; higher powers by recurrence
+            V w1 = tw.w[TwOffset<N, E, Ns>::value + s];
+            if (INV) w1.y = -w1.y;
+            V wr = w1;
+            u[1] = cmul(u[1], w1);
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                V w = tw[(r * k) * (N / (Ns * R))];
-                if (INV) w.y = -w.y;
-                u[r] = cmul(u[r], w);
+            for (int r = 2; r < R; ++r) {
+                wr = cmul(wr, w1);
+                u[r] = cmul(u[r], wr);
             }
         }
         Dft<R, INV, V>::run(u);
@@ -125,32 +193,31 @@ __device__ __forceinline__ void stockham_pass(V (&v)[E], V* lds, int lo, int j, 
         } else {
             const int base = (b - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[(base + r * Ns) * LS + lo] = u[r];
+            for (int r = 0; r < R; ++r) lds[lds_slot<E>(base + r * Ns) * LS + lo] = u[r];
         }
     }
     if (!LAST) {
-        __syncthreads();
+        lds_sync();
 #pragma unroll
-        for (int q = 0; q < E; ++q) v[q] = lds[(j + q * P) * LS + lo];
-        __syncthreads();
+        for (int q = 0; q < E; ++q) v[q] = lds[lds_slot<E>(j + q * P) * LS + lo];
+        lds_sync();
     }
 }
 
 template <typename V, int N, int E, int Ns, bool INV, int LS>
 struct StockhamRun {
-    static constexpr int REM = N / Ns;
-    static constexpr int R = REM >= E ? E : REM;
-    static constexpr bool LAST = (Ns * R == N);
-    static __device__ __forceinline__ void run(V (&v)[E], V* lds, int lo, int j, const V* __restrict__ tw) {
-        stockham_pass<V, N, E, R, Ns, INV, LAST, LS>(v, lds, lo, j, tw);
-        if constexpr (!LAST) StockhamRun<V, N, E, Ns * R, INV, LS>::run(v, lds, lo, j, tw);
+    using PI = PassInfo<N, E, Ns>;
+    static __device__ __forceinline__ void run(V (&v)[E], V* lds, int lo, int j, const Twid<V, N, E>& tw) {
+        stockham_pass<V, N, E, PI::R, Ns, INV, PI::LAST, LS>(v, lds, lo, j, tw);
+        if constexpr (!PI::LAST) StockhamRun<V, N, E, PI::NEXT, INV, LS>::run(v, lds, lo, j, tw);
     }
 };
 
 // Full transform.  All threads of the workgroup must call it (it synchronises).
-template <typename V, int N, bool INV, int LS>
-__device__ __forceinline__ void fft(V (&v)[FftShape<N>::E], V* lds, int lo, int j, const V* __restrict__ tw) {
-    if constexpr (N > 1) StockhamRun<V, N, FftShape<N>::E, 1, INV, LS>::run(v, lds, lo, j, tw);
+template <typename V, int N, bool INV, int LS, int EMAX = 8>
+__device__ __forceinline__ void fft(V (&v)[(FftShape<N, EMAX>::E)], V* lds, int lo, int j,
+                                    const Twid<V, N, FftShape<N, EMAX>::E>& tw) {
+    if constexpr (N > 1) StockhamRun<V, N, FftShape<N, EMAX>::E, 1, INV, LS>::run(v, lds, lo, j, tw);
 }
 
 }  // namespace sbi

@@ -1,11 +1,16 @@
 // sbi_internal.hpp -- structures shared by the host orchestration and the
 // gfx950 kernels of the SBI solver.
 //
-// Spectral layouts (per batch member), complex values of the run precision:
-//   half form  [ny][Kxp]  : x transformed (kept m_x = 0..Mx), y physical.
-//                           Row-pass output / column-pass input ("H" and "G").
-//   compact    [Ky][Kxp]  : both axes transformed, only the kept rectangle
-//                           |m_x| <= Mx, |m_y| <= My.  Row r holds m_y = r for
+// Spectral layouts (per batch member), complex values of the run precision,
+// both column-major so a column pass reads and writes contiguous runs:
+//   half form  [Kxp][ldh] : x transformed (kept m_x = 0..Mx), y physical;
+//                           ldh = ny + pad, so columns do not all start on the
+//                           same memory channel.
+//                           Row-pass output / column-pass input ("H" and "G");
+//                           row passes stage rows through LDS to access it in
+//                           segments of several consecutive y.
+//   compact    [Kxp][Ky]  : both axes transformed, only the kept rectangle
+//                           |m_x| <= Mx, |m_y| <= My.  Entry r holds m_y = r for
 //                           r <= My and m_y = r - Ky for r > My.
 // Kx = Mx + 1 and Kxp rounds Kx up to the column-tile width; Ky = 2 My + 1
 // (1 when ny == 1).  Every spectrum of the method lives inside the kept
@@ -21,9 +26,16 @@ constexpr int kMaxCin = 8;             // compact inputs of one column pass
 constexpr int kMaxTerms = 48;
 constexpr int kMaxCout = 6;
 constexpr int kMaxInv = 8;
+constexpr int kMaxGroups = 8;          // product groups of one column pass
+constexpr int kMaxTiles = 4096;        // column tiles per member (ticket counters)
 
-// Per-member control block in device memory.  The small header comes first so
-// the host can read it for every member with one strided copy.
+// Per-member control block in device memory: a small header the host reads
+// for all members with one contiguous copy, plus a pointer to the member's
+// residual slots.
+struct CtlSlots {
+    unsigned long long num[kMaxSweepSlots];  // bits of max|W'-W| (non-negative doubles)
+    unsigned long long den[kMaxSweepSlots];  // bits of max|W'|
+};
 struct Ctl {
     int done;                                // iteration finished (any reason)
     int status;                              // sbi_status of the solve
@@ -34,14 +46,12 @@ struct Ctl {
     double rmin;                             // smallest residual seen so far
     unsigned long long eta_max;              // order-preserving bits of max(eta)
     unsigned long long eta_min;              // order-preserving bits of min(eta)
-    unsigned long long pad;
-    unsigned long long num[kMaxSweepSlots];  // bits of max|W'-W| (non-negative doubles)
-    unsigned long long den[kMaxSweepSlots];  // bits of max|W'|
+    CtlSlots* slots;                         // this member's residual slots
 };
-constexpr int kCtlHeadBytes = 64;
 
 struct GridDev {
     int nx, ny, Mx, My, Kx, Kxp, Ky, order;
+    int ldh;            // column pitch of a half form (ny + pad: spreads columns over memory channels)
     double lx, ly, kband;
     long long s_phys;   // reals per member of a physical field
     long long s_half;   // complex per member of a half-form field
@@ -89,6 +99,13 @@ struct ColParams {
     int sweep;        // sweep index n of this pass (CTL_SWEEP)
     int max_sweeps;
     double tol;
+    // products split over workgroups along y: group g transforms products
+    // [gstart[g], gstart[g+1]); partial sums go to `part` and the last
+    // workgroup of a tile (ticket in `cnt`) adds them in group order.
+    int ngroup;
+    int gstart[kMaxGroups + 1];
+    void* part;       // [batch][kMaxGroups][4][Ky][Kxp] complex
+    int* cnt;         // [batch][kMaxTiles]
 };
 
 }  // namespace sbi

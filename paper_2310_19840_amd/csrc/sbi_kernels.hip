@@ -72,31 +72,46 @@ template <typename V> __device__ __forceinline__ V rmul(V a, V b) {  // componen
 // Row pass helpers: real row of length NX <-> kept half spectrum F[0..Mx]
 // via the length-NX/2 complex transform of z[n] = f[2n] + i f[2n+1].
 // ---------------------------------------------------------------------------
+// Per-thread view of a row-pass workgroup: rpw rows of P threads each.
+struct RowCtx {
+    int t, nthr, j, rl, y0, rpw, ny, ldh, Mx, mem;
+    bool valid;
+};
+
 template <typename R, int NX> struct Row {
     using V = typename cplx_of<R>::type;
     static constexpr int N = NX / 2;
     static constexpr int E = FftShape<N>::E;
     static constexpr int P = FftShape<N>::P;
+    // LDS row pitch: room for the padded transform, odd against bank conflicts
+    static constexpr int LS = fft_lds_elems<N, E>() + 1;
+    static constexpr int NF = (N / 2 + 1 + P - 1) / P + 1;  // kept outputs per thread (bound)
 
-    // v <- z = inverse row transform of (G + c2 G2), scaled.
+    // v <- z = inverse row transform of (G + c2 G2) for the thread's row.
+    // G, G2: member base of a half form [m_x][ny]; all rows of the workgroup
+    // stage their kept spectra through LDS with coalesced column segments.
+    using TW = Twid<V, N, E>;
     static __device__ __forceinline__ void inverse(V (&v)[E], const V* __restrict__ G, const V* __restrict__ G2,
-                                                   R c2, int Mx, V* lds, int j, bool valid,
-                                                   const V* __restrict__ twN, const V* __restrict__ twX, R scale) {
-        for (int m = j; m < N; m += P) {
+                                                   R c2, const RowCtx& rc, V* lds_all,
+                                                   const TW& twN, const V* __restrict__ twX, R scale) {
+        for (int idx = rc.t; idx < rc.rpw * N; idx += rc.nthr) {
+            const int r2 = idx % rc.rpw, m = idx / rc.rpw;
             V f = cx<V>(R(0), R(0));
-            if (valid && m <= Mx) {
-                f = G[m];
+            if (m <= rc.Mx && rc.y0 + r2 < rc.ny) {
+                const long long o = (long long)m * rc.ldh + rc.y0 + r2;
+                f = G[o];
                 if (G2) {
-                    V f2 = G2[m];
+                    const V f2 = G2[o];
                     f = cx<V>(f.x + c2 * f2.x, f.y + c2 * f2.y);
                 }
             }
-            lds[m] = f;
+            lds_all[r2 * LS + m] = f;
         }
-        __syncthreads();
+        lds_sync();
+        V* lds = lds_all + rc.rl * LS;
 #pragma unroll
         for (int q = 0; q < E; ++q) {
-            const int m = j + q * P;
+            const int m = rc.j + q * P;
             V fm = lds[m];
             V fc = (m == 0) ? cx<V>(R(0), R(0)) : cconj(lds[N - m]);
             V ev = cx<V>(R(0.5) * (fm.x + fc.x), R(0.5) * (fm.y + fc.y));
@@ -104,28 +119,45 @@ template <typename R, int NX> struct Row {
             od = cmul(od, cconj(twX[m]));           // exp(+2 pi i m / NX)
             v[q] = cadd(ev, mul_i(od));
         }
-        __syncthreads();
-        fft<V, N, true, 1>(v, lds, 0, j, twN);
+        lds_sync();
+        fft<V, N, true, 1>(v, lds, 0, rc.j, twN);
 #pragma unroll
         for (int q = 0; q < E; ++q) v[q] = cscale(v[q], scale);
     }
 
-    // H[0..Mx] <- forward row transform of the real pairs in v (v is destroyed).
-    static __device__ __forceinline__ void forward(V (&v)[E], V* __restrict__ H, int Mx, V* lds, int j, bool valid,
-                                                   const V* __restrict__ twN, const V* __restrict__ twX) {
-        fft<V, N, false, 1>(v, lds, 0, j, twN);
+    // H[kept m][row] <- forward row transform of the real pairs in v (v is destroyed).
+    static __device__ __forceinline__ void forward(V (&v)[E], V* __restrict__ H, const RowCtx& rc, V* lds_all,
+                                                   const TW& twN, const V* __restrict__ twX) {
+        V* lds = lds_all + rc.rl * LS;
+        fft<V, N, false, 1>(v, lds, 0, rc.j, twN);
 #pragma unroll
-        for (int q = 0; q < E; ++q) lds[j + q * P] = v[q];
-        __syncthreads();
-        for (int m = j; m <= Mx; m += P) {
-            V zm = lds[m];
-            V zc = cconj(lds[(N - m) & (N - 1)]);
-            V ev = cx<V>(R(0.5) * (zm.x + zc.x), R(0.5) * (zm.y + zc.y));
-            V od = mul_mi<false>(cx<V>(R(0.5) * (zm.x - zc.x), R(0.5) * (zm.y - zc.y)));
-            V f = cadd(ev, cmul(twX[m], od));
-            if (valid) H[m] = f;
+        for (int q = 0; q < E; ++q) lds[rc.j + q * P] = v[q];
+        lds_sync();
+        V fo[NF];
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const int m = rc.j + i * P;
+            fo[i] = cx<V>(R(0), R(0));
+            if (m <= rc.Mx) {
+                V zm = lds[m];
+                V zc = cconj(lds[(N - m) & (N - 1)]);
+                V ev = cx<V>(R(0.5) * (zm.x + zc.x), R(0.5) * (zm.y + zc.y));
+                V od = mul_mi<false>(cx<V>(R(0.5) * (zm.x - zc.x), R(0.5) * (zm.y - zc.y)));
+                fo[i] = cadd(ev, cmul(twX[m], od));
+            }
         }
-        __syncthreads();
+        lds_sync();
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const int m = rc.j + i * P;
+            if (m <= rc.Mx) lds[m] = fo[i];
+        }
+        lds_sync();
+        for (int idx = rc.t; idx < rc.rpw * (rc.Mx + 1); idx += rc.nthr) {
+            const int r2 = idx % rc.rpw, m = idx / rc.rpw;
+            if (rc.y0 + r2 < rc.ny) H[(long long)m * rc.ldh + rc.y0 + r2] = lds_all[r2 * LS + m];
+        }
+        lds_sync();
     }
 
     static __device__ __forceinline__ void load(V (&v)[E], const R* __restrict__ row, int j, bool valid) {
@@ -146,20 +178,19 @@ template <int NX> __host__ __device__ constexpr int row_threads() {
     return FftShape<NX / 2>::P > 256 ? FftShape<NX / 2>::P : 256;
 }
 
-struct RowIdx {
-    int t, j, rl, y, mem;
-    bool valid;
-};
-
-template <int P> __device__ __forceinline__ RowIdx row_index(int ny) {
-    RowIdx r;
+template <int P> __device__ __forceinline__ RowCtx row_ctx(const GridDev& g) {
+    RowCtx r;
     r.t = threadIdx.x;
+    r.nthr = blockDim.x;
     r.j = r.t % P;
     r.rl = r.t / P;
-    const int rpw = blockDim.x / P;
-    r.y = blockIdx.x * rpw + r.rl;
-    r.mem = blockIdx.y;
-    r.valid = r.y < ny;
+    r.rpw = blockDim.x / P;
+    r.y0 = blockIdx.x * r.rpw;
+    r.ny = g.ny;
+    r.ldh = g.ldh;
+    r.Mx = g.Mx;
+    r.mem = blockIdx.z;
+    r.valid = r.y0 + r.rl < g.ny;
     return r;
 }
 
@@ -167,49 +198,55 @@ template <int P> __device__ __forceinline__ RowIdx row_index(int ny) {
     using RW = Row<R, NX>;                                               \
     using V = typename RW::V;                                            \
     constexpr int E = RW::E;                                             \
-    extern __shared__ unsigned char smem_raw[];                          \
-    const RowIdx ri = row_index<RW::P>(p.g.ny);                          \
-    V* lds = reinterpret_cast<V*>(smem_raw) + ri.rl * RW::N;             \
-    const long long ho = ri.mem * p.g.s_half + (long long)(ri.valid ? ri.y : 0) * p.g.Kxp; \
-    const long long po = ri.mem * p.g.s_phys + (long long)(ri.valid ? ri.y : 0) * p.g.nx;  \
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];                          \
+    const RowCtx rc = row_ctx<RW::P>(p.g);                               \
+    const struct {                                                       \
+        int j, mem;                                                      \
+        bool valid;                                                      \
+    } ri = {rc.j, rc.mem, rc.valid};                                     \
+    V* lds_all = reinterpret_cast<V*>(smem_raw);                         \
+    const long long hb = (long long)rc.mem * p.g.s_half;                 \
+    const long long po = rc.mem * p.g.s_phys + (long long)(rc.valid ? rc.y0 + rc.rl : 0) * p.g.nx; \
     const R iscale = R(1.0 / ((double)RW::N * (double)p.g.ny));          \
-    (void)po; (void)iscale;
+    typename RW::TW twN;                                                 \
+    twN.load(twN_tab, rc.j);                                             \
+    (void)po; (void)iscale; (void)hb;
 
 // ---------------------------------------------------------------------------
 // Row kernels
 // ---------------------------------------------------------------------------
 template <typename R, int NX>
-__global__ void __launch_bounds__(row_threads<NX>()) k_row_fwd(const RowFwdParams p, const typename cplx_of<R>::type* twN,
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_fwd(const RowFwdParams p, const typename cplx_of<R>::type* twN_tab,
                           const typename cplx_of<R>::type* twX) {
     ROW_PROLOGUE(R, NX)
     for (int f = 0; f < p.nf; ++f) {
         V v[E];
         RW::load(v, static_cast<const R*>(p.in[f]) + po, ri.j, ri.valid);
-        RW::forward(v, static_cast<V*>(p.out[f]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+        RW::forward(v, static_cast<V*>(p.out[f]) + hb, rc, lds_all, twN, twX);
     }
 }
 
 template <typename R, int NX>
-__global__ void __launch_bounds__(row_threads<NX>()) k_row_inv(const RowInvParams p, const typename cplx_of<R>::type* twN,
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_inv(const RowInvParams p, const typename cplx_of<R>::type* twN_tab,
                           const typename cplx_of<R>::type* twX) {
     ROW_PROLOGUE(R, NX)
     for (int f = 0; f < p.nf; ++f) {
         V v[E];
-        const V* g2 = p.in2[f] ? static_cast<const V*>(p.in2[f]) + ho : nullptr;
+        const V* g2 = p.in2[f] ? static_cast<const V*>(p.in2[f]) + hb : nullptr;
         R c2 = R(0);
         if (g2) c2 = R(1.0 - p.ctl[ri.mem].omega);
-        RW::inverse(v, static_cast<const V*>(p.in[f]) + ho, g2, c2, p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+        RW::inverse(v, static_cast<const V*>(p.in[f]) + hb, g2, c2, rc, lds_all, twN, twX, iscale);
         RW::store(v, static_cast<R*>(p.out[f]) + po, ri.j, ri.valid);
     }
 }
 
 template <typename R, int NX>
-__global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupParams p, const typename cplx_of<R>::type* twN,
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupParams p, const typename cplx_of<R>::type* twN_tab,
                             const typename cplx_of<R>::type* twX) {
     ROW_PROLOGUE(R, NX)
     V e[E];
     if (p.g_eta) {
-        RW::inverse(e, static_cast<const V*>(p.g_eta) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+        RW::inverse(e, static_cast<const V*>(p.g_eta) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
     } else {
         RW::load(e, static_cast<const R*>(p.eta_in) + po, ri.j, ri.valid);
     }
@@ -240,11 +277,11 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupP
         for (int q = 0; q < E; ++q) bad |= !isfinite((double)e[q].x) || !isfinite((double)e[q].y);
     }
     V px[E], py[E];
-    RW::inverse(px, static_cast<const V*>(p.g_px) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+    RW::inverse(px, static_cast<const V*>(p.g_px) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
     if (p.px_out) RW::store(px, static_cast<R*>(p.px_out) + po, ri.j, ri.valid);
     const bool two_d = p.g.ny > 1;
     if (two_d) {
-        RW::inverse(py, static_cast<const V*>(p.g_py) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+        RW::inverse(py, static_cast<const V*>(p.g_py) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
         if (p.py_out) RW::store(py, static_cast<R*>(p.py_out) + po, ri.j, ri.valid);
     }
     if (ri.valid) {
@@ -268,55 +305,55 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupP
             V w[E];
 #pragma unroll
             for (int q = 0; q < E; ++q) w[q] = rmul(ep[q], px[q]);
-            RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+            RW::forward(w, static_cast<V*>(p.h[idx++]) + hb, rc, lds_all, twN, twX);
             if (two_d) {
 #pragma unroll
                 for (int q = 0; q < E; ++q) w[q] = rmul(ep[q], py[q]);
-                RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+                RW::forward(w, static_cast<V*>(p.h[idx++]) + hb, rc, lds_all, twN, twX);
             }
         }
     }
 }
 
 template <typename R, int NX>
-__global__ void __launch_bounds__(row_threads<NX>()) k_row_sweep(const RowSweepParams p, const typename cplx_of<R>::type* twN,
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_sweep(const RowSweepParams p, const typename cplx_of<R>::type* twN_tab,
                             const typename cplx_of<R>::type* twX) {
     ROW_PROLOGUE(R, NX)
     Ctl* ctl = p.ctl + ri.mem;
     if (ctl->done) return;  // block-uniform
-    V vv[E];
-    RW::inverse(vv, static_cast<const V*>(p.gV) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
-    if (p.residual) {
-        V dd[E];
-        RW::inverse(dd, static_cast<const V*>(p.gD) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
-        const double c = 1.0 - ctl->omega;
-        unsigned long long nu = 0ull, de = 0ull;
-        if (ri.valid) {
+    const int fam = blockIdx.y;  // product family of this workgroup
+    if (fam == 0) {
+        V vv[E];
+        RW::inverse(vv, static_cast<const V*>(p.gV) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+        if (p.residual) {
+            V dd[E];
+            RW::inverse(dd, static_cast<const V*>(p.gD) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+            const double c = 1.0 - ctl->omega;
+            unsigned long long nu = 0ull, de = 0ull;
+            if (ri.valid) {
 #pragma unroll
-            for (int q = 0; q < E; ++q) {
-                const double d0 = (double)dd[q].x, d1 = (double)dd[q].y;
-                const double w0 = (double)vv[q].x + c * d0, w1 = (double)vv[q].y + c * d1;
-                unsigned long long a = abs_bits(d0), b = abs_bits(d1);
-                nu = a > nu ? a : nu;
-                nu = b > nu ? b : nu;
-                a = abs_bits(w0);
-                b = abs_bits(w1);
-                de = a > de ? a : de;
-                de = b > de ? b : de;
+                for (int q = 0; q < E; ++q) {
+                    const double d0 = (double)dd[q].x, d1 = (double)dd[q].y;
+                    const double w0 = (double)vv[q].x + c * d0, w1 = (double)vv[q].y + c * d1;
+                    unsigned long long a = abs_bits(d0), b = abs_bits(d1);
+                    nu = a > nu ? a : nu;
+                    nu = b > nu ? b : nu;
+                    a = abs_bits(w0);
+                    b = abs_bits(w1);
+                    de = a > de ? a : de;
+                    de = b > de ? b : de;
+                }
+            }
+            nu = block_reduce_u64<true>(nu);
+            de = block_reduce_u64<true>(de);
+            if (threadIdx.x == 0) {
+                atomicMax(&ctl->slots->num[p.slot], nu);
+                atomicMax(&ctl->slots->den[p.slot], de);
             }
         }
-        nu = block_reduce_u64<true>(nu);
-        de = block_reduce_u64<true>(de);
-        if (threadIdx.x == 0) {
-            atomicMax(&ctl->num[p.slot], nu);
-            atomicMax(&ctl->den[p.slot], de);
-        }
-    }
-    if (!p.products) return;
-    V ev[E];
-    RW::load(ev, static_cast<const R*>(p.eta) + po, ri.j, ri.valid);
-    int idx = 0;
-    {
+        if (!p.products) return;
+        V ev[E];
+        RW::load(ev, static_cast<const R*>(p.eta) + po, ri.j, ri.valid);
         V pw[E];
 #pragma unroll
         for (int q = 0; q < E; ++q) pw[q] = vv[q];
@@ -327,39 +364,36 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_sweep(const RowSweepP
                 pw[q] = rmul(pw[q], ev[q]);
                 w[q] = pw[q];
             }
-            RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+            RW::forward(w, static_cast<V*>(p.h[jj - 1]) + hb, rc, lds_all, twN, twX);
         }
+        return;
     }
-    if (p.vd) {
-        V dv[E];
-        RW::load(dv, static_cast<const R*>(p.delta) + po, ri.j, ri.valid);
-        const int ncomp = p.g.ny > 1 ? 2 : 1;
-        for (int comp = 0; comp < ncomp; ++comp) {
-            V pw[E];
-            RW::inverse(pw, static_cast<const V*>(comp == 0 ? p.gbx : p.gby) + ho, nullptr, R(0), p.g.Mx, lds,
-                        ri.j, ri.valid, twN, twX, iscale);
-            for (int jj = 1; jj <= p.J; ++jj) {
-                V w[E];
+    // families 1, 2: delta^j d_x phi_b, delta^j d_y phi_b
+    if (!p.products || !p.vd) return;
+    const int comp = fam - 1;
+    V dv[E], pw[E];
+    RW::inverse(pw, static_cast<const V*>(comp == 0 ? p.gbx : p.gby) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+    RW::load(dv, static_cast<const R*>(p.delta) + po, ri.j, ri.valid);
+    for (int jj = 1; jj <= p.J; ++jj) {
+        V w[E];
 #pragma unroll
-                for (int q = 0; q < E; ++q) {
-                    pw[q] = rmul(pw[q], dv[q]);
-                    w[q] = pw[q];
-                }
-                RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
-            }
+        for (int q = 0; q < E; ++q) {
+            pw[q] = rmul(pw[q], dv[q]);
+            w[q] = pw[q];
         }
+        RW::forward(w, static_cast<V*>(p.h[fam * p.J + jj - 1]) + hb, rc, lds_all, twN, twX);
     }
 }
 
 template <typename R, int NX>
-__global__ void __launch_bounds__(row_threads<NX>()) k_row_sa(const RowSaParams p, const typename cplx_of<R>::type* twN,
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_sa(const RowSaParams p, const typename cplx_of<R>::type* twN_tab,
                          const typename cplx_of<R>::type* twX) {
     ROW_PROLOGUE(R, NX)
     const int l = p.l;
     int idx = 0;
     V a[E], base[E], pw[E];
     // eta^j V_(l-j)
-    RW::inverse(a, static_cast<const V*>(p.gV) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+    RW::inverse(a, static_cast<const V*>(p.gV) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
     if (p.V_out) RW::store(a, static_cast<R*>(p.V_out) + po, ri.j, ri.valid);
     RW::load(base, static_cast<const R*>(p.eta) + po, ri.j, ri.valid);
 #pragma unroll
@@ -376,7 +410,7 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_sa(const RowSaParams 
         }
 #pragma unroll
         for (int q = 0; q < E; ++q) w[q] = rmul(pw[q], src[q]);
-        RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+        RW::forward(w, static_cast<V*>(p.h[idx++]) + hb, rc, lds_all, twN, twX);
     }
     // delta^j grad phi_b,(l-j)
     if (p.vd) {
@@ -385,7 +419,7 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_sa(const RowSaParams 
             const void* gsrc = comp == 0 ? p.gbx : p.gby;
             void* outp = comp == 0 ? p.bx_out : p.by_out;
             const void* const* phys = comp == 0 ? p.bxphys : p.byphys;
-            RW::inverse(a, static_cast<const V*>(gsrc) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+            RW::inverse(a, static_cast<const V*>(gsrc) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
             if (outp) RW::store(a, static_cast<R*>(outp) + po, ri.j, ri.valid);
             RW::load(base, static_cast<const R*>(p.delta) + po, ri.j, ri.valid);
 #pragma unroll
@@ -402,7 +436,7 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_sa(const RowSaParams 
                 }
 #pragma unroll
                 for (int q = 0; q < E; ++q) w[q] = rmul(pw[q], src[q]);
-                RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+                RW::forward(w, static_cast<V*>(p.h[idx++]) + hb, rc, lds_all, twN, twX);
             }
         }
     }
@@ -420,20 +454,20 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_sa(const RowSaParams 
         RW::load(a, static_cast<const R*>(comp == 0 ? p.phx : p.phy) + po, ri.j, ri.valid);
 #pragma unroll
         for (int q = 0; q < E; ++q) w[q] = rmul(pw[q], a[q]);
-        RW::forward(w, static_cast<V*>(p.h[idx++]) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+        RW::forward(w, static_cast<V*>(p.h[idx++]) + hb, rc, lds_all, twN, twX);
     }
 }
 
 template <typename R, int NX>
-__global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi(const RowNphiParams p, const typename cplx_of<R>::type* twN,
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi(const RowNphiParams p, const typename cplx_of<R>::type* twN_tab,
                            const typename cplx_of<R>::type* twX) {
     ROW_PROLOGUE(R, NX)
     V q[E], gg[E], pp[E], a[E], b[E];
-    const V* gD = p.gD ? static_cast<const V*>(p.gD) + ho : nullptr;
+    const V* gD = p.gD ? static_cast<const V*>(p.gD) + hb : nullptr;
     const R c2 = gD ? R(1.0 - p.ctl[ri.mem].omega) : R(0);
-    RW::inverse(q, static_cast<const V*>(p.gV) + ho, gD, c2, p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
-    RW::inverse(a, static_cast<const V*>(p.gex) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
-    RW::inverse(b, static_cast<const V*>(p.gpx) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+    RW::inverse(q, static_cast<const V*>(p.gV) + hb, gD, c2, rc, lds_all, twN, twX, iscale);
+    RW::inverse(a, static_cast<const V*>(p.gex) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+    RW::inverse(b, static_cast<const V*>(p.gpx) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         q[k] = cx<V>(q[k].x + a[k].x * b[k].x, q[k].y + a[k].y * b[k].y);
@@ -441,8 +475,8 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi(const RowNphiPar
         pp[k] = rmul(b[k], b[k]);
     }
     if (p.g.ny > 1) {
-        RW::inverse(a, static_cast<const V*>(p.gey) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
-        RW::inverse(b, static_cast<const V*>(p.gpy) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+        RW::inverse(a, static_cast<const V*>(p.gey) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+        RW::inverse(b, static_cast<const V*>(p.gpy) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             q[k] = cx<V>(q[k].x + a[k].x * b[k].x, q[k].y + a[k].y * b[k].y);
@@ -455,16 +489,16 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi(const RowNphiPar
         q[k] = cx<V>(R(0.5) * (q[k].x * q[k].x / (R(1) + gg[k].x) - pp[k].x),
                      R(0.5) * (q[k].y * q[k].y / (R(1) + gg[k].y) - pp[k].y));
     }
-    RW::forward(q, static_cast<V*>(p.h) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+    RW::forward(q, static_cast<V*>(p.h) + hb, rc, lds_all, twN, twX);
 }
 
 template <typename R, int NX>
-__global__ void __launch_bounds__(row_threads<NX>()) k_row_blend(const RowBlendParams p, const typename cplx_of<R>::type* twN,
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_blend(const RowBlendParams p, const typename cplx_of<R>::type* twN_tab,
                             const typename cplx_of<R>::type* twX) {
     ROW_PROLOGUE(R, NX)
     V e[E], f[E];
-    RW::inverse(e, static_cast<const V*>(p.ge) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
-    RW::inverse(f, static_cast<const V*>(p.gp) + ho, nullptr, R(0), p.g.Mx, lds, ri.j, ri.valid, twN, twX, iscale);
+    RW::inverse(e, static_cast<const V*>(p.ge) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+    RW::inverse(f, static_cast<const V*>(p.gp) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
     const double dx = p.g.lx / p.g.nx;
     const double r = p.t < p.ramp_time ? 0.5 * (1.0 - cos(M_PI * p.t / p.ramp_time)) : 1.0;
 #pragma unroll
@@ -494,20 +528,25 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_blend(const RowBlendP
         e[q] = cx<V>(R(ev[0]), R(ev[1]));
         f[q] = cx<V>(R(fv[0]), R(fv[1]));
     }
-    RW::forward(e, static_cast<V*>(p.he) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
-    RW::forward(f, static_cast<V*>(p.hp) + ho, p.g.Mx, lds, ri.j, ri.valid, twN, twX);
+    RW::forward(e, static_cast<V*>(p.he) + hb, rc, lds_all, twN, twX);
+    RW::forward(f, static_cast<V*>(p.hp) + hb, rc, lds_all, twN, twX);
 }
 
 // ---------------------------------------------------------------------------
 // Column pass: forward column transforms of the products, multiplier sums,
 // relaxation, compact outputs, inverse column transforms of the results.
 // ---------------------------------------------------------------------------
+// elements per thread of the column transforms: 4 in FP64 and 8 in FP32 keep
+// the accumulators, mode geometry and transform data of a thread in registers
+template <typename R> __host__ __device__ constexpr int col_e() { return sizeof(R) == 8 ? 4 : 8; }
+
+// columns per workgroup: a column of NY values is carried by NY/E threads;
+// workgroups hold 256 threads (half forms are column-major, so each column is
+// one contiguous run whatever the tile width)
 template <typename R, int NY> __host__ __device__ constexpr int col_width() {
     if (NY == 1) return 64;
-    int c = 65536 / (NY * (int)(2 * sizeof(R)));
-    if (c > 16) c = 16;
-    if (c < 1) c = 1;
-    return c;
+    constexpr int P = FftShape<NY, col_e<R>()>::P;
+    return P >= 256 ? 1 : 256 / P;
 }
 
 // decision of a sweep pass from the completed residual of the previous sweep.
@@ -516,8 +555,8 @@ __device__ __forceinline__ int sweep_decision(Ctl* ctl, int n, int M, double tol
     *r_out = 0.0;
     *rmin_out = ctl->rmin;
     if (n == 0) return 0;
-    const double num = bits_to_double(ctl->num[n - 1]);
-    const double den = bits_to_double(ctl->den[n - 1]);
+    const double num = bits_to_double(ctl->slots->num[n - 1]);
+    const double den = bits_to_double(ctl->slots->den[n - 1]);
     if (!isfinite(num) || !isfinite(den)) {
         *r_out = __longlong_as_double(0x7ff8000000000000ll);
         return 100 - 5;  // SBI_ERR_NONFINITE
@@ -532,20 +571,88 @@ __device__ __forceinline__ int sweep_decision(Ctl* ctl, int n, int M, double tol
     return 0;
 }
 
+// multiplier sum of one source into the accumulators (kept and masked modes
+// alike; masked modes are never written out)
+template <typename R, typename V, int E, int NACC>
+__device__ __forceinline__ void col_apply_terms(const ColParams& p, int src, const V (&v)[E], V (&acc)[NACC][E],
+                                                const R (&kk)[E], const R (&TT)[E], const R (&SS)[E],
+                                                const R (&kyv)[E], R kxr) {
+    for (int ti = p.toff[src]; ti < p.toff[src + 1]; ++ti) {
+        const ColTerm tm = p.term[ti];
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            R m = R(tm.coef);
+            if (tm.fn == FN_T) m *= TT[q];
+            else if (tm.fn == FN_S) m *= SS[q];
+            if (tm.pw >= 0) {
+                for (int e = 0; e < tm.pw; ++e) m *= kk[q];
+            } else {
+                m = kk[q] > R(0) ? m / kk[q] : R(0);
+            }
+            V val = cscale(v[q], m);
+            if (tm.dv == DV_X) val = mul_i(cscale(val, kxr));
+            else if (tm.dv == DV_Y) val = mul_i(cscale(val, kyv[q]));
+#pragma unroll
+            for (int a = 0; a < NACC; ++a)
+                if (a == tm.acc) acc[a][q] = cadd(acc[a][q], val);
+        }
+    }
+}
+
+// value of output source `src` at the thread's mode q (crow >= 0)
+template <typename R, typename V, int E, int NACC>
+__device__ __forceinline__ V col_source(const ColParams& p, int src, int q, const V (&acc)[NACC][E], int crow,
+                                        int mem, int mx, double omega) {
+    if (src <= SRC_ACC3) {
+        V r = cx<V>(R(0), R(0));
+#pragma unroll
+        for (int a = 0; a < NACC; ++a)
+            if (a == src) r = acc[a][q];
+        return r;
+    }
+    const int a = (src == SRC_NEW0 || src == SRC_DIFF0) ? 0 : 1;
+    V cur = cx<V>(R(0), R(0));
+#pragma unroll
+    for (int k = 0; k < NACC; ++k)
+        if (k == a) cur = acc[k][q];
+    V pv = cx<V>(R(0), R(0));
+    const int pi = p.relax_prev[a];
+    if (pi >= 0)
+        pv = static_cast<const V*>(p.cin[pi])[mem * p.g.s_cmp + (long long)mx * p.g.Ky + crow];
+    const V d = csub(cur, pv);
+    if (src == SRC_DIFF0 || src == SRC_DIFF1) return d;
+    return cadd(pv, cscale(d, R(omega)));
+}
+
+// product lanes of a column-pass workgroup: independent thread groups that
+// transform alternate products of the same columns (more waves per CU to hide
+// memory latency); their partial sums are combined through LDS
+template <typename R, int NY> __host__ __device__ constexpr int col_lanes() { return NY == 1 ? 1 : 2; }
+
+template <typename R, int NY> __host__ __device__ constexpr int col_threads() {
+    return col_lanes<R, NY>() * col_width<R, NY>() * FftShape<NY, col_e<R>()>::P;
+}
+
 template <typename R, int NY, int NACC>
-__global__ void __launch_bounds__((col_width<R, NY>() * FftShape<NY>::P))
+__global__ void __launch_bounds__((col_threads<R, NY>()))
 k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     using V = typename cplx_of<R>::type;
     constexpr int N = NY;
-    constexpr int E = FftShape<N>::E;
-    constexpr int P = FftShape<N>::P;
+    constexpr int CE = col_e<R>();
+    constexpr int E = FftShape<N, CE>::E;
+    constexpr int P = FftShape<N, CE>::P;
     constexpr int C = col_width<R, NY>();
-    extern __shared__ unsigned char smem_raw[];
-    V* lds = reinterpret_cast<V*>(smem_raw);
+    constexpr int PL = col_lanes<R, NY>();
+    constexpr int REG = fft_lds_elems<N, E>();  // LDS elements of one column transform
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int t = threadIdx.x;
-    const int c = t % C;
-    const int j = t / C;
-    const int mem = blockIdx.y;
+    const int lane = t / (C * P);
+    const int tl = t % (C * P);
+    const int c = tl / P;  // column of the tile
+    const int j = tl % P;  // thread within the column
+    V* lds = reinterpret_cast<V*>(smem_raw) + (lane * C + c) * REG;
+    const int mem = blockIdx.z;
+    const int grp = blockIdx.y;
     const int x0 = blockIdx.x * C;
     const int mx = x0 + c;
     const GridDev& g = p.g;
@@ -557,7 +664,7 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         double r, rmin;
         const int dec = sweep_decision(ctl, p.sweep, p.max_sweeps, p.tol, &r, &rmin);
         if (dec) {
-            if (blockIdx.x == 0 && t == 0) {
+            if (blockIdx.x == 0 && grp == 0 && t == 0) {
                 ctl->status = dec - 100;
                 ctl->sweeps = p.sweep;
                 ctl->residual = r;
@@ -565,7 +672,7 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
             }
             return;
         }
-        if (blockIdx.x == 0 && t == 0) {
+        if (blockIdx.x == 0 && grp == 0 && t == 0) {
             ctl->rmin = rmin;
             ctl->residual = r;
         }
@@ -590,8 +697,11 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
             if (isfinite(s) && s > 0.0) w = fmin(1.0, 2.0 / s);
         }
         omega = w;
-        if (blockIdx.x == 0 && t == 0) ctl->omega = w;
+        if (blockIdx.x == 0 && grp == 0 && t == 0) ctl->omega = w;
     }
+
+    Twid<V, N, E> twc;
+    twc.load(twY, j);
 
     // mode geometry of the E values this thread owns: m_y index n = j + q P
     const double href = g.href[mem];
@@ -619,96 +729,170 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
 #pragma unroll
         for (int q = 0; q < E; ++q) acc[a][q] = cx<V>(R(0), R(0));
 
-    auto apply_terms = [&](int src, const V (&v)[E]) {
-        for (int ti = p.toff[src]; ti < p.toff[src + 1]; ++ti) {
-            const ColTerm tm = p.term[ti];
+    // forward column transforms of this workgroup's products: lane L takes
+    // products s0 + L, s0 + L + PL, ...; every lane runs the same number of
+    // rounds (empty slots transform zeros) so the barriers line up.  The next
+    // round's column is loaded before the current transform runs.
+    const int s0 = p.ngroup > 1 ? p.gstart[grp] : 0;
+    const int s1 = p.ngroup > 1 ? p.gstart[grp + 1] : p.nprod;
+    const int rounds = (s1 - s0 + PL - 1) / PL;
+    auto load_col = [&](int s, V (&dst)[E]) __attribute__((always_inline)) {
+        if (s < s1) {
+            const long long st = p.hin_stride[s] ? p.hin_stride[s] : g.s_half;
+            const V* H = static_cast<const V*>(p.hin[s]) + mem * st + (long long)mx * g.ldh;
 #pragma unroll
-            for (int q = 0; q < E; ++q) {
-                if (crow[q] < 0) continue;
-                R m = R(tm.coef);
-                if (tm.fn == FN_T) m *= TT[q];
-                else if (tm.fn == FN_S) m *= SS[q];
-                if (tm.pw >= 0) {
-                    for (int e = 0; e < tm.pw; ++e) m *= kk[q];
-                } else {
-                    m = kk[q] > R(0) ? m / kk[q] : R(0);
+            for (int q = 0; q < E; ++q) dst[q] = H[j + q * P];
+        } else {
+#pragma unroll
+            for (int q = 0; q < E; ++q) dst[q] = cx<V>(R(0), R(0));
+        }
+    };
+    V v[E];
+    if (rounds > 0) load_col(s0 + lane, v);
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int s = s0 + rd * PL + lane;
+        V vn[E];
+        if (rd + 1 < rounds) load_col(s + PL, vn);
+        fft<V, N, false, 1, CE>(v, lds, 0, j, twc);
+        if (s < s1) col_apply_terms<R, V, E, NACC>(p, s, v, acc, kk, TT, SS, kyv, kxr);
+#pragma unroll
+        for (int q = 0; q < E; ++q) v[q] = vn[q];
+    }
+    // combine the lanes' partial sums into lane 0
+    if (PL > 1 && rounds > 0) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) {
+            lds_sync();
+            if (lane > 0) {
+#pragma unroll
+                for (int q = 0; q < E; ++q) lds[j + q * P] = acc[a][q];
+            }
+            lds_sync();
+            if (lane == 0) {
+#pragma unroll
+                for (int l2 = 1; l2 < PL; ++l2) {
+                    const V* o = reinterpret_cast<const V*>(smem_raw) + (l2 * C + c) * REG;
+#pragma unroll
+                    for (int q = 0; q < E; ++q) acc[a][q] = cadd(acc[a][q], o[j + q * P]);
                 }
-                V val = cscale(v[q], m);
-                if (tm.dv == DV_X) val = mul_i(cscale(val, kxr));
-                else if (tm.dv == DV_Y) val = mul_i(cscale(val, kyv[q]));
-#pragma unroll
-                for (int a = 0; a < NACC; ++a)
-                    if (a == tm.acc) acc[a][q] = cadd(acc[a][q], val);
             }
         }
-    };
-
-    // forward column transforms of the products
-    for (int s = 0; s < p.nprod; ++s) {
-        const long long st = p.hin_stride[s] ? p.hin_stride[s] : g.s_half;
-        const V* H = static_cast<const V*>(p.hin[s]) + mem * st;
-        V v[E];
-#pragma unroll
-        for (int q = 0; q < E; ++q) v[q] = H[(long long)(j + q * P) * g.Kxp + mx];
-        fft<V, N, false, C>(v, lds, c, j, twY);
-        apply_terms(s, v);
     }
-    // compact inputs
-    for (int ci = 0; ci < p.ncin; ++ci) {
-        if (p.toff[p.nprod + ci] == p.toff[p.nprod + ci + 1]) continue;  // no term reads it
-        const V* Ci = static_cast<const V*>(p.cin[ci]) + mem * g.s_cmp;
-        V v[E];
+    if (p.ngroup > 1) {
+        // publish this group's partial sums; the last workgroup of the tile
+        // continues with their sum in group order (deterministic)
+        V* part = static_cast<V*>(p.part);
+        const long long gs = (long long)g.Ky * g.Kxp;
+        if (lane == 0) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) v[q] = crow[q] >= 0 ? Ci[(long long)crow[q] * g.Kxp + mx] : cx<V>(R(0), R(0));
-        apply_terms(p.nprod + ci, v);
+            for (int a = 0; a < NACC; ++a)
+#pragma unroll
+                for (int q = 0; q < E; ++q)
+                    if (crow[q] >= 0)
+                        part[(((long long)mem * kMaxGroups + grp) * 4 + a) * gs + (long long)mx * g.Ky + crow[q]] =
+                            acc[a][q];
+        }
+        __shared__ int last_flag;
+        __threadfence();
+        __syncthreads();
+        if (t == 0) {
+            const int old = atomicAdd(&p.cnt[(long long)mem * kMaxTiles + blockIdx.x], 1);
+            last_flag = (old == p.ngroup - 1);
+        }
+        __syncthreads();
+        if (!last_flag) return;
+        __threadfence();
+        if (t == 0) p.cnt[(long long)mem * kMaxTiles + blockIdx.x] = 0;
+        if (lane == 0) {
+#pragma unroll
+            for (int a = 0; a < NACC; ++a)
+#pragma unroll
+                for (int q = 0; q < E; ++q) {
+                    V sum = cx<V>(R(0), R(0));
+                    if (crow[q] >= 0) {
+                        for (int gg = 0; gg < p.ngroup; ++gg) {
+                            const R* ps = reinterpret_cast<const R*>(
+                                part + (((long long)mem * kMaxGroups + gg) * 4 + a) * gs + (long long)mx * g.Ky +
+                                crow[q]);
+                            sum = cadd(sum,
+                                       cx<V>(__builtin_nontemporal_load(ps), __builtin_nontemporal_load(ps + 1)));
+                        }
+                    }
+                    acc[a][q] = sum;
+                }
+        }
     }
-
-    // relaxation of the iterate: NEW = prev + omega (acc - prev), DIFF = acc - prev
-    auto prev_of = [&](int a, int q) -> V {
-        const int pi = p.relax_prev[a];
-        if (pi < 0 || crow[q] < 0) return cx<V>(R(0), R(0));
-        return static_cast<const V*>(p.cin[pi])[mem * g.s_cmp + (long long)crow[q] * g.Kxp + mx];
-    };
-    auto acc_of = [&](int a, int q) -> V {
-        V r = cx<V>(R(0), R(0));
+    // compact inputs (lane 0 holds the sums)
+    if (lane == 0) {
+        for (int ci = 0; ci < p.ncin; ++ci) {
+            if (p.toff[p.nprod + ci] == p.toff[p.nprod + ci + 1]) continue;  // no term reads it
+            const V* Ci = static_cast<const V*>(p.cin[ci]) + mem * g.s_cmp;
+            V vc[E];
 #pragma unroll
-        for (int k = 0; k < NACC; ++k)
-            if (k == a) r = acc[k][q];
-        return r;
-    };
-    auto source = [&](int src, int q) -> V {
-        if (src <= SRC_ACC3) return acc_of(src, q);
-        const int a = (src == SRC_NEW0 || src == SRC_DIFF0) ? 0 : 1;
-        const V pv = prev_of(a, q);
-        const V d = csub(acc_of(a, q), pv);
-        if (src == SRC_DIFF0 || src == SRC_DIFF1) return d;
-        return cadd(pv, cscale(d, R(omega)));
-    };
-    // inverse column transforms (before any compact output is written: the
-    // NEW/DIFF sources re-read the previous iterate from its compact array)
-    for (int o = 0; o < p.ninv; ++o) {
-        V v[E];
+            for (int q = 0; q < E; ++q)
+                vc[q] = crow[q] >= 0 ? Ci[(long long)mx * g.Ky + crow[q]] : cx<V>(R(0), R(0));
+            col_apply_terms<R, V, E, NACC>(p, p.nprod + ci, vc, acc, kk, TT, SS, kyv, kxr);
+        }
+    }
+    // broadcast the final sums to every lane
+    if (PL > 1 && p.ninv > 1) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) {
+            lds_sync();
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < E; ++q) lds[j + q * P] = acc[a][q];
+            }
+            lds_sync();
+            if (lane > 0) {
+                const V* o = reinterpret_cast<const V*>(smem_raw) + c * REG;
+#pragma unroll
+                for (int q = 0; q < E; ++q) acc[a][q] = o[j + q * P];
+            }
+        }
+    }
+    // inverse column transforms, spread over the lanes (before any compact
+    // output is written: NEW/DIFF sources re-read the previous iterate)
+    const int lanes_used = (PL > 1 && p.ninv > 1) ? PL : 1;
+    const int irounds = (p.ninv + lanes_used - 1) / lanes_used;
+    for (int rd = 0; rd < irounds; ++rd) {
+        const int o = rd * lanes_used + (lanes_used > 1 ? lane : 0);
+        const bool mine = (lanes_used > 1 || lane == 0) && o < p.ninv;
+        V vi[E];
+        const int src = mine ? p.inv_src[o] : 0;
+        const int dv = mine ? p.inv_dv[o] : 0;
 #pragma unroll
         for (int q = 0; q < E; ++q) {
-            V s = crow[q] >= 0 ? source(p.inv_src[o], q) : cx<V>(R(0), R(0));
-            if (p.inv_dv[o] == DV_X) s = mul_i(cscale(s, kxr));
-            else if (p.inv_dv[o] == DV_Y) s = mul_i(cscale(s, kyv[q]));
-            v[q] = s;
+            V sv = cx<V>(R(0), R(0));
+            if (mine && crow[q] >= 0) sv = col_source<R, V, E, NACC>(p, src, q, acc, crow[q], mem, mx, omega);
+            if (dv == DV_X) sv = mul_i(cscale(sv, kxr));
+            else if (dv == DV_Y) sv = mul_i(cscale(sv, kyv[q]));
+            vi[q] = sv;
         }
-        fft<V, N, true, C>(v, lds, c, j, twY);
-        V* G = static_cast<V*>(p.inv[o]) + mem * g.s_half;
+        fft<V, N, true, 1, CE>(vi, lds, 0, j, twc);
+        if (mine) {
+            V* G = static_cast<V*>(p.inv[o]) + mem * g.s_half + (long long)mx * g.ldh;
 #pragma unroll
-        for (int q = 0; q < E; ++q) G[(long long)(j + q * P) * g.Kxp + mx] = v[q];
+            for (int q = 0; q < E; ++q) G[j + q * P] = vi[q];
+        }
     }
+    if (PL > 1) __syncthreads();  // inverse outputs (read prev) before compact outputs (write)
     // compact outputs: every output of a mode is formed before any is written,
     // so an output may overwrite an input of the same pass in place
+    if (lane == 0) {
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-        if (crow[q] < 0) continue;
-        V vals[kMaxCout];
-        for (int o = 0; o < p.ncout; ++o) vals[o] = source(p.cout_src[o], q);
-        for (int o = 0; o < p.ncout; ++o)
-            static_cast<V*>(p.cout[o])[mem * g.s_cmp + (long long)crow[q] * g.Kxp + mx] = vals[o];
+        for (int q = 0; q < E; ++q) {
+            if (crow[q] >= 0) {
+                V vals[kMaxCout];
+#pragma unroll
+                for (int o = 0; o < kMaxCout; ++o)
+                    if (o < p.ncout) vals[o] = col_source<R, V, E, NACC>(p, p.cout_src[o], q, acc, crow[q], mem, mx, omega);
+#pragma unroll
+                for (int o = 0; o < kMaxCout; ++o)
+                    if (o < p.ncout)
+                        static_cast<V*>(p.cout[o])[mem * g.s_cmp + (long long)mx * g.Ky + crow[q]] = vals[o];
+            }
+        }
     }
 }
 
@@ -722,8 +906,8 @@ struct ModeGeo {
 };
 __device__ __forceinline__ ModeGeo mode_geo(const GridDev& g, long long idx) {
     ModeGeo m;
-    m.r = (int)(idx / g.Kxp);
-    m.mx = (int)(idx % g.Kxp);
+    m.mx = (int)(idx / g.Ky);
+    m.r = (int)(idx % g.Ky);
     m.valid = m.r < g.Ky && m.mx < g.Kx;
     const int my = m.r <= g.My ? m.r : m.r - g.Ky;
     m.kx = 2.0 * M_PI * m.mx / g.lx;
@@ -857,16 +1041,20 @@ __global__ void k_diag(const DiagParams p) {
 // ---------------------------------------------------------------------------
 // launchers (size dispatch)
 // ---------------------------------------------------------------------------
+// workgroups along y of a row pass: the sweep splits its product families
+template <typename PT> static int row_families(const PT&) { return 1; }
+static int row_families(const RowSweepParams& p) { return p.nfam > 0 ? p.nfam : 1; }
+
 template <typename R, int NX> struct RowLaunch {
     using V = typename cplx_of<R>::type;
-    static void shape(int ny, dim3* grid, dim3* block, size_t* lds, int batch) {
+    static void shape(int ny, dim3* grid, dim3* block, size_t* lds, int batch, int nfam) {
         constexpr int P = Row<R, NX>::P;
         int rpw = 256 / P;
         if (rpw < 1) rpw = 1;
         if (rpw > ny) rpw = ny;
         *block = dim3(P * rpw);
-        *grid = dim3((ny + rpw - 1) / rpw, batch);
-        *lds = (size_t)rpw * Row<R, NX>::N * sizeof(V);
+        *grid = dim3((ny + rpw - 1) / rpw, nfam, batch);
+        *lds = (size_t)rpw * Row<R, NX>::LS * sizeof(V);
     }
 };
 
@@ -876,7 +1064,7 @@ template <typename R, int NX> struct RowLaunch {
         using V = typename cplx_of<R>::type;                                                               \
         dim3 grid, block;                                                                                  \
         size_t lds;                                                                                        \
-        RowLaunch<R, NX>::shape(p.g.ny, &grid, &block, &lds, batch);                                       \
+        RowLaunch<R, NX>::shape(p.g.ny, &grid, &block, &lds, batch, row_families(p));                      \
         hipLaunchKernelGGL((KNAME<R, NX>), grid, block, lds, s, p, (const V*)tw.tn, (const V*)tw.tx);      \
         return hipGetLastError();                                                                          \
     }                                                                                                      \
@@ -909,10 +1097,10 @@ template <typename R, int NY, int NACC>
 static hipError_t col_go(const ColParams& p, int batch, const Twiddles& tw, hipStream_t s) {
     using V = typename cplx_of<R>::type;
     constexpr int C = col_width<R, NY>();
-    constexpr int P = FftShape<NY>::P;
-    dim3 block(C * P);
-    dim3 grid(p.g.Kxp / C, batch);
-    size_t lds = NY > 1 ? (size_t)NY * C * sizeof(V) : 0;
+    constexpr int E = FftShape<NY, col_e<R>()>::E;
+    dim3 block(col_threads<R, NY>());
+    dim3 grid(p.g.Kxp / C, p.ngroup > 0 ? p.ngroup : 1, batch);
+    size_t lds = NY > 1 ? (size_t)col_lanes<R, NY>() * C * fft_lds_elems<NY, E>() * sizeof(V) : 0;
     hipLaunchKernelGGL((k_col<R, NY, NACC>), grid, block, lds, s, p, (const V*)tw.ty);
     return hipGetLastError();
 }

@@ -49,6 +49,7 @@ struct RowSweepParams {
     int products;       // form the products of this sweep
     int vd;             // variable depth
     int slot;
+    int nfam;           // workgroups along y: 0 eta^j V (+ residual), 1/2 delta^j d_x/d_y phi_b
     void* h[kMaxProd];
     Ctl* ctl;
 };
