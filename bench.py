@@ -153,8 +153,8 @@ def main():
     sweeps_total = info["sweeps_total"]
 
     # dominant kernel and its algorithmic bandwidth
-    Mx = int(math.floor(0.5 * g.nx / 2 + 1e-9))
-    My = int(math.floor(0.5 * g.ny / 2 + 1e-9))
+    Mx = int(math.ceil(0.5 * g.nx / 2 - 1e-9)) - 1
+    My = int(math.ceil(0.5 * g.ny / 2 - 1e-9)) - 1
     Kx, Ky = Mx + 1, 2 * My + 1
     vd = bool(np.any(cfg["depth"] != cfg["depth"].max()))
     cand = {}

@@ -69,9 +69,9 @@ typedef struct sbi_grid {
                               ny == 1 (1D) or 16..2048 */
     double lx, ly;         /* periodic lengths (ly ignored when ny == 1) */
     int32_t order;         /* expansion order L, 1..7 (Sec. 2.4 caps it at 7); default 7 */
-    double dealias;        /* kept fraction alpha of the Nyquist wavenumber per axis
-                              (the "2/(l+1) rule" of Sec. 2.4 read as alpha = 1/2);
-                              0 < alpha < 1; default 0.5 */
+    double dealias;        /* kept fraction alpha of the Nyquist wavenumber per axis:
+                              modes |m| < alpha n/2 are kept (the "2/(l+1) rule" of
+                              Sec. 2.4 read as alpha = 1/2); 0 < alpha < 1; default 0.5 */
     int32_t precision;     /* SBI_FP64 (default) or SBI_FP32 (FP64 residual norms and
                               diagnostics are kept either way) */
     int32_t mode;          /* SBI_MODE_ITER (default) or SBI_MODE_SA */

@@ -10,9 +10,10 @@ primitive and is pinned against a brute-force DFT in the tests.
 Readings of the paper that this oracle fixes (each also listed in the design
 notes of the repository):
 
-* dealiasing ("2/(l+1) rule", Sec. 2.4): keep |m_x| <= floor(alpha nx/2) and
-  |m_y| <= floor(alpha ny/2) with alpha = 1/2; applied to the spectrum of every
-  product and to the state;
+* dealiasing ("2/(l+1) rule", Sec. 2.4): keep |m_x| < alpha nx/2 and
+  |m_y| < alpha ny/2 with alpha = 1/2 (the submerged-bar case of Sec. 3.2 calls
+  waves longer than L/(N/4) alias-free; Sec. 4 keeps "the first 16 modes" of 64
+  points); applied to the spectrum of every product and to the state;
 * the explicit orders of Appendix C, Eqs. (v2)-(v7), are authoritative where
   the general recursion of Sec. 2.4 differs from them;
 * the iteration mode solves the fixed point of the recursion summed over
@@ -45,8 +46,10 @@ class Grid:
         self.kx = (2 * np.pi * mx / self.lx)[None, :]
         self.ky = (2 * np.pi * my / self.ly)[:, None] if self.ny > 1 else np.zeros((1, 1))
         self.k = np.sqrt(self.kx ** 2 + self.ky ** 2)
-        self.Mx = int(math.floor(dealias * self.nx / 2 + 1e-9))
-        self.My = 0 if self.ny == 1 else int(math.floor(dealias * self.ny / 2 + 1e-9))
+        # kept modes: |m| strictly below alpha*n/2 (alpha = 1/2: waves longer than
+        # 4 grid spacings, Sec. 3.2; "the first 16 modes" of 64 points, Sec. 4)
+        self.Mx = int(math.ceil(dealias * self.nx / 2 - 1e-9)) - 1
+        self.My = 0 if self.ny == 1 else int(math.ceil(dealias * self.ny / 2 - 1e-9)) - 1
         keep = (mx[None, :] <= self.Mx) & (np.abs(my)[:, None] <= self.My)
         self.mask = keep.astype(np.float64)
         self.dA = (self.lx / self.nx) * ((self.ly / self.ny) if self.ny > 1 else 1.0)

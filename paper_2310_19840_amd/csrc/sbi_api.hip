@@ -181,8 +181,9 @@ static Layout layout(const sbi_grid* g, int batch) {
     const bool f64 = g->precision == SBI_FP64;
     L.rsz = f64 ? 8 : 4;
     L.csz = 2 * L.rsz;
-    L.Mx = (int)std::floor(g->dealias * g->nx / 2.0 + 1e-9);
-    L.My = g->ny == 1 ? 0 : (int)std::floor(g->dealias * g->ny / 2.0 + 1e-9);
+    // kept modes |m| < alpha n / 2 (strict)
+    L.Mx = (int)std::ceil(g->dealias * g->nx / 2.0 - 1e-9) - 1;
+    L.My = g->ny == 1 ? 0 : (int)std::ceil(g->dealias * g->ny / 2.0 - 1e-9) - 1;
     L.Kx = L.Mx + 1;
     L.C = col_tile(g->ny, f64);
     L.Kxp = (L.Kx + L.C - 1) / L.C * L.C;

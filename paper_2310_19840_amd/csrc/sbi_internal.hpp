@@ -28,6 +28,7 @@ constexpr int kMaxCout = 6;
 constexpr int kMaxInv = 8;
 constexpr int kMaxGroups = 8;          // product groups of one column pass
 constexpr int kMaxTiles = 4096;        // column tiles per member (ticket counters)
+constexpr size_t kMaxLdsBytes = 160 * 1024;  // LDS of one gfx950 workgroup
 
 // Per-member control block in device memory: a small header the host reads
 // for all members with one contiguous copy, plus a pointer to the member's

@@ -571,27 +571,30 @@ __device__ __forceinline__ int sweep_decision(Ctl* ctl, int n, int M, double tol
     return 0;
 }
 
-// multiplier sum of one source into the accumulators (kept and masked modes
-// alike; masked modes are never written out)
+// Per-mode geometry of a column tile, held in LDS: for kept mode (c, r),
+// geo[(c * Ky + r) * 4 + {0, 1, 2, 3}] = {k, tanh(k h), sech(k h), k_y}.
+// multiplier sum of one source into the accumulators (kept modes only)
 template <typename R, typename V, int E, int NACC>
 __device__ __forceinline__ void col_apply_terms(const ColParams& p, int src, const V (&v)[E], V (&acc)[NACC][E],
-                                                const R (&kk)[E], const R (&TT)[E], const R (&SS)[E],
-                                                const R (&kyv)[E], R kxr) {
+                                                const int (&crow)[E], const R* __restrict__ geo, R kxr) {
     for (int ti = p.toff[src]; ti < p.toff[src + 1]; ++ti) {
         const ColTerm tm = p.term[ti];
 #pragma unroll
         for (int q = 0; q < E; ++q) {
+            if (crow[q] < 0) continue;
+            const R* gq = geo + crow[q] * 4;
+            const R kq = gq[0];
             R m = R(tm.coef);
-            if (tm.fn == FN_T) m *= TT[q];
-            else if (tm.fn == FN_S) m *= SS[q];
+            if (tm.fn == FN_T) m *= gq[1];
+            else if (tm.fn == FN_S) m *= gq[2];
             if (tm.pw >= 0) {
-                for (int e = 0; e < tm.pw; ++e) m *= kk[q];
+                for (int e = 0; e < tm.pw; ++e) m *= kq;
             } else {
-                m = kk[q] > R(0) ? m / kk[q] : R(0);
+                m = kq > R(0) ? m / kq : R(0);
             }
             V val = cscale(v[q], m);
             if (tm.dv == DV_X) val = mul_i(cscale(val, kxr));
-            else if (tm.dv == DV_Y) val = mul_i(cscale(val, kyv[q]));
+            else if (tm.dv == DV_Y) val = mul_i(cscale(val, gq[3]));
 #pragma unroll
             for (int a = 0; a < NACC; ++a)
                 if (a == tm.acc) acc[a][q] = cadd(acc[a][q], val);
@@ -628,6 +631,18 @@ __device__ __forceinline__ V col_source(const ColParams& p, int src, int q, cons
 // transform alternate products of the same columns (more waves per CU to hide
 // memory latency); their partial sums are combined through LDS
 template <typename R, int NY> __host__ __device__ constexpr int col_lanes() { return NY == 1 ? 1 : 2; }
+
+// LDS of a column workgroup: the transform exchange area of every lane and
+// column (none for 1D grids, whose "columns" are single values), followed by
+// the mode-geometry table of C * Ky entries of 4 reals.  Host and kernel both
+// take the offsets from here.
+template <typename R, int NY> __host__ __device__ constexpr int col_xform_elems() {
+    return NY > 1 ? col_lanes<R, NY>() * col_width<R, NY>() * fft_lds_elems<NY, FftShape<NY, col_e<R>()>::E>() : 0;
+}
+template <typename R, int NY> __host__ __device__ constexpr size_t col_lds_bytes(int Ky) {
+    return (size_t)col_xform_elems<R, NY>() * sizeof(typename cplx_of<R>::type) +
+           (size_t)col_width<R, NY>() * Ky * 4 * sizeof(R);
+}
 
 template <typename R, int NY> __host__ __device__ constexpr int col_threads() {
     return col_lanes<R, NY>() * col_width<R, NY>() * FftShape<NY, col_e<R>()>::P;
@@ -703,10 +718,10 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     Twid<V, N, E> twc;
     twc.load(twY, j);
 
-    // mode geometry of the E values this thread owns: m_y index n = j + q P
+    // mode geometry: the compact row of each value this thread owns (m_y index
+    // n = j + q P) and an LDS table of k, tanh(kh), sech(kh), k_y per kept mode
     const double href = g.href[mem];
     const double kx = 2.0 * M_PI * (double)mx / g.lx;
-    R kk[E], TT[E], SS[E], kyv[E];
     int crow[E];  // compact row, -1 if not kept
 #pragma unroll
     for (int q = 0; q < E; ++q) {
@@ -714,13 +729,22 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         const int my = (n <= N / 2) ? n : n - N;
         const bool keep = (mx < g.Kx) && (my <= g.My) && (my >= -g.My);
         crow[q] = keep ? (my >= 0 ? my : my + g.Ky) : -1;
-        const double ky = (N == 1) ? 0.0 : 2.0 * M_PI * (double)my / g.ly;
-        const double k = sqrt(kx * kx + ky * ky);
-        kk[q] = R(k);
-        kyv[q] = R(ky);
-        TT[q] = R(tanh(k * href));
-        SS[q] = R(sech_d(k * href));
     }
+    R* geo_all = reinterpret_cast<R*>(reinterpret_cast<V*>(smem_raw) + col_xform_elems<R, NY>());
+    for (int idx = t; idx < C * g.Ky; idx += blockDim.x) {
+        const int c2 = idx / g.Ky, r2 = idx % g.Ky;
+        const int my = r2 <= g.My ? r2 : r2 - g.Ky;
+        const double kx2 = 2.0 * M_PI * (double)(x0 + c2) / g.lx;
+        const double ky = (N == 1) ? 0.0 : 2.0 * M_PI * (double)my / g.ly;
+        const double k = sqrt(kx2 * kx2 + ky * ky);
+        R* gq = geo_all + idx * 4;
+        gq[0] = R(k);
+        gq[1] = R(tanh(k * href));
+        gq[2] = R(sech_d(k * href));
+        gq[3] = R(ky);
+    }
+    __syncthreads();
+    const R* geo = geo_all + c * g.Ky * 4;
     const R kxr = R(kx);
 
     V acc[NACC][E];
@@ -754,7 +778,7 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         V vn[E];
         if (rd + 1 < rounds) load_col(s + PL, vn);
         fft<V, N, false, 1, CE>(v, lds, 0, j, twc);
-        if (s < s1) col_apply_terms<R, V, E, NACC>(p, s, v, acc, kk, TT, SS, kyv, kxr);
+        if (s < s1) col_apply_terms<R, V, E, NACC>(p, s, v, acc, crow, geo, kxr);
 #pragma unroll
         for (int q = 0; q < E; ++q) v[q] = vn[q];
     }
@@ -831,7 +855,7 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
 #pragma unroll
             for (int q = 0; q < E; ++q)
                 vc[q] = crow[q] >= 0 ? Ci[(long long)mx * g.Ky + crow[q]] : cx<V>(R(0), R(0));
-            col_apply_terms<R, V, E, NACC>(p, p.nprod + ci, vc, acc, kk, TT, SS, kyv, kxr);
+            col_apply_terms<R, V, E, NACC>(p, p.nprod + ci, vc, acc, crow, geo, kxr);
         }
     }
     // broadcast the final sums to every lane
@@ -865,8 +889,10 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         for (int q = 0; q < E; ++q) {
             V sv = cx<V>(R(0), R(0));
             if (mine && crow[q] >= 0) sv = col_source<R, V, E, NACC>(p, src, q, acc, crow[q], mem, mx, omega);
-            if (dv == DV_X) sv = mul_i(cscale(sv, kxr));
-            else if (dv == DV_Y) sv = mul_i(cscale(sv, kyv[q]));
+            if (crow[q] >= 0) {
+                if (dv == DV_X) sv = mul_i(cscale(sv, kxr));
+                else if (dv == DV_Y) sv = mul_i(cscale(sv, geo[crow[q] * 4 + 3]));
+            }
             vi[q] = sv;
         }
         fft<V, N, true, 1, CE>(vi, lds, 0, j, twc);
@@ -1097,10 +1123,10 @@ template <typename R, int NY, int NACC>
 static hipError_t col_go(const ColParams& p, int batch, const Twiddles& tw, hipStream_t s) {
     using V = typename cplx_of<R>::type;
     constexpr int C = col_width<R, NY>();
-    constexpr int E = FftShape<NY, col_e<R>()>::E;
     dim3 block(col_threads<R, NY>());
     dim3 grid(p.g.Kxp / C, p.ngroup > 0 ? p.ngroup : 1, batch);
-    size_t lds = NY > 1 ? (size_t)col_lanes<R, NY>() * C * fft_lds_elems<NY, E>() * sizeof(V) : 0;
+    const size_t lds = col_lds_bytes<R, NY>(p.g.Ky);
+    if (lds > kMaxLdsBytes) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_col<R, NY, NACC>), grid, block, lds, s, p, (const V*)tw.ty);
     return hipGetLastError();
 }

@@ -28,11 +28,12 @@ class GridSpec:
 
     @property
     def mx_max(self) -> int:
-        return int(math.floor(self.dealias * self.nx / 2 + 1e-9))
+        """Largest kept |m_x|: strictly below dealias * nx / 2."""
+        return int(math.ceil(self.dealias * self.nx / 2 - 1e-9)) - 1
 
     @property
     def my_max(self) -> int:
-        return 0 if self.ny == 1 else int(math.floor(self.dealias * self.ny / 2 + 1e-9))
+        return 0 if self.ny == 1 else int(math.ceil(self.dealias * self.ny / 2 - 1e-9)) - 1
 
     def x(self) -> np.ndarray:
         return np.arange(self.nx) * (self.lx / self.nx)

@@ -53,10 +53,13 @@ def test_fft_sign_convention():
 
 
 def test_mask_half_nyquist():
+    # Sec. 4: 64 points per wavelength keep "the first 16 Fourier modes" (0..15);
+    # Sec. 3.2: 1024 points over 64 m keep waves longer than 0.25 m, i.e. |m| < 256
     g = Grid(64, 32, 1.0, 1.0)
-    assert g.Mx == 16 and g.My == 8
-    assert g.mask[0, 16] == 1 and g.mask[0, 17] == 0
-    assert g.mask[8, 0] == 1 and g.mask[9, 0] == 0 and g.mask[-8, 0] == 1 and g.mask[-9, 0] == 0
+    assert g.Mx == 15 and g.My == 7
+    assert g.mask[0, 15] == 1 and g.mask[0, 16] == 0
+    assert g.mask[7, 0] == 1 and g.mask[8, 0] == 0 and g.mask[-7, 0] == 1 and g.mask[-8, 0] == 0
+    assert Grid(1024, 1, 64.0).Mx == 255
 
 
 # ---------------------------------------------------------------------------
@@ -93,7 +96,7 @@ def test_deep_water_recursion():
     W, _ = s.vertical_velocity(eta, phi)
     # independent coding of the deep-water reduction
     k = np.abs(np.fft.rfftfreq(64, 1 / 64))[None, :]
-    M = (np.arange(33) <= 16)[None, :].astype(float)
+    M = (np.arange(33) < 16)[None, :].astype(float)   # modes 0..15 of 64 points (Sec. 4)
     F = lambda f: M * np.fft.rfft(f, axis=1)
     Fi = lambda X: np.fft.irfft(X, 64, axis=1)
     ph = F(phi)
