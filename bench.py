@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1024, help="grid size (1024 = the benchmark workload)")
     ap.add_argument("--max-sweeps", type=int, default=400)
+    ap.add_argument("--seed", default="linear", choices=["linear", "prev"],
+                    help="seed of each W iteration: linear guess (plain) or previous solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -128,7 +130,7 @@ def main():
     g = cfg["grid"]
     tol = cfg["tol"]
     s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="iter", precision="fp64",
-               max_sweeps=args.max_sweeps)
+               max_sweeps=args.max_sweeps, seed=args.seed)
     eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=dev)
     phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=dev)
     dt = cfg["dt"]

@@ -76,7 +76,12 @@ typedef struct sbi_grid {
                               diagnostics are kept either way) */
     int32_t mode;          /* SBI_MODE_ITER (default) or SBI_MODE_SA */
     int32_t seed;          /* SBI_SEED_* for the iteration; default SBI_SEED_LINEAR,
-                              the initiation of Sec. 2.4 */
+                              the initiation of Sec. 2.4.  SBI_SEED_PREV: the linear
+                              guess plus the nonlinear part (V* - k tanh(kh) phi_hat,
+                              phi_b - sech(kh) phi_hat) that the context's previous
+                              solve left (the first solve, and any solve after a
+                              failed one, uses the linear guess).  SBI_SEED_USER: the
+                              w_seed field of sbi_vertical_velocity */
     int32_t max_sweeps;    /* iteration cap, 1..1000; default 64 */
     int32_t relax;         /* 1: under-relaxed sweeps when the crest makes plain sweeps
                               expand (default); 0: plain sweeps */

@@ -100,7 +100,7 @@ class Solver:
 
     def __init__(self, grid: Grid, depth, h_ref: float | None = None, order: int = 7,
                  mode: str = "iter", max_sweeps: int = 64, relax: bool = True,
-                 filter_beta=None, relaxation_zone=None):
+                 filter_beta=None, relaxation_zone=None, seed: str = "linear"):
         self.g = grid
         depth = np.asarray(depth, dtype=np.float64).reshape(grid.ny, grid.nx)
         if np.any(~np.isfinite(depth)) or np.any(depth <= 0):
@@ -123,6 +123,13 @@ class Solver:
         self.om = np.sqrt(self.om2)
         self.filter_beta = filter_beta
         self.rz = relaxation_zone
+        # seed of the iteration: "linear" (initiation of Sec. 2.4) or "prev": the
+        # linear guess plus the nonlinear part left by this solver's previous
+        # solve, (V* - kT phi_hat, phi_b - S phi_hat) of that solve
+        if seed not in ("linear", "prev"):
+            raise ValueError("seed must be 'linear' or 'prev'")
+        self.seed = seed
+        self._prev = None
         # depth-validity criterion of Sec. 5: k |delta| < 2.4 at the largest wavenumber
         self.depth_warning = grid.kband * float(np.abs(self.delta).max()) > 2.4
 
@@ -249,12 +256,24 @@ class Solver:
         g = self.g
         info = SolveInfo()
         bV, bB = self.forcing(eta, ph)
-        Vh = g.k * self.T * ph if seed_hat is None else g.mask * seed_hat
-        Bh = self.S * ph
+        Vlin = g.k * self.T * ph
+        Blin = self.S * ph
+        Vh = Vlin if seed_hat is None else g.mask * seed_hat
+        Bh = Blin
+        if seed_hat is None and self.seed == "prev" and self._prev is not None:
+            Vh = Vlin + self._prev[0]
+            Bh = Blin + self._prev[1]
         w = self.relax_factor(eta)
         info.omega = w
         rmin = np.inf
         Vn = Vh
+
+        def keep(V, B):
+            # nonlinear part of this solve, the seed of the next one; the phi_b
+            # iterate kept is the one after the relaxed update of the last sweep
+            self._prev = (V - Vlin, B - Blin) if info.status >= 0 else None
+            return V, info
+
         for n in range(self.max_sweeps):
             Vn, Bn = self.apply_T(eta, bV, bB, Vh, Bh)
             Vnew = g.ifft(Vn)
@@ -265,21 +284,21 @@ class Solver:
                 info.status = ERR_NONFINITE
                 info.sweeps = n + 1
                 info.residual = float("nan")
-                return Vn, info
+                return keep(Vn, Bn)
             r = 0.0 if num == 0.0 else (num / den if den > 0 else np.inf)
             info.history.append(r)
             info.sweeps = n + 1
             info.residual = r
             if r <= tol:
-                return Vn, info
+                return keep(Vn, Bh + w * (Bn - Bh))
             rmin = min(rmin, r)
             if r > 1e6 or (n >= 3 and r > 10.0 * rmin):
                 info.status = ERR_DIVERGED
-                return Vn, info
+                return keep(Vn, Bn)
             Vh = Vh + w * (Vn - Vh)
             Bh = Bh + w * (Bn - Bh)
         info.status = WARN_NOT_CONVERGED
-        return Vn, info
+        return keep(Vn, Bh)
 
     # ------------------------------------------------------------------------
     def solve_hat(self, eta, ph, tol=1e-10, seed_hat=None):

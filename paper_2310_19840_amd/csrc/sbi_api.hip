@@ -37,6 +37,7 @@ enum {
     C_VN, C_BN,          // current iterate (V, phi_b)
     C_VP,                // T(V_n): candidate answer of the iteration
     C_NP,                // nonlinear term of the potential equation
+    C_DV, C_DB,          // nonlinear part (V* - kT phi, phi_b - S phi) of the last solve
     C_COUNT
 };
 // half-form buffers
@@ -107,6 +108,7 @@ struct sbi_ctx {
     bool vd = false;         // some member has a non-flat bed
     bool depth_warn = false;
     bool relax_on = false;
+    bool have_prev = false;  // C_DV/C_DB hold the last solve's nonlinear part (SBI_SEED_PREV)
     double rz[6] = {0, 0, 0, 0, 0, 0};
     Stats st;
     Profiler prof;
@@ -660,6 +662,11 @@ static sbi_status stage_state_pass(sbi_ctx* c, bool need_eta) {
     if (c->grid.mode == SBI_MODE_SA) {
         b.cout(SRC_ACC2, CMP(C_VH));
     } else {
+        if (c->grid.seed == SBI_SEED_PREV && c->have_prev) {
+            // previous-solve seed: linear guess + the last solve's nonlinear part
+            b.term(b.cin(CMP(C_DV)), 2, 1.0, FN_ONE, 0, DV_NONE);
+            if (c->vd) b.term(b.cin(CMP(C_DB)), 3, 1.0, FN_ONE, 0, DV_NONE);
+        }
         b.cout(SRC_ACC2, CMP(C_VN));
         if (c->vd) b.cout(SRC_ACC3, CMP(C_BN));
     }
@@ -960,6 +967,27 @@ static sbi_status seed_from_physical(sbi_ctx* c, const void* w_seed) {
     return run_col(c, b);
 }
 
+// keeps (V* - kT phi_hat, phi_b - S phi_hat) of the finished solve: the seed of
+// the next one adds them to its own linear guess.  phi_b is the iterate after
+// the relaxed update of the last sweep.
+static sbi_status save_nonlinear_part(sbi_ctx* c) {
+    ColBuilder b(c->gd);
+    int sv = b.cin(CMP(C_VP));
+    int sp = b.cin(CMP(C_PS));
+    b.term(sv, 0, 1.0, FN_ONE, 0, DV_NONE);
+    b.term(sp, 0, -1.0, FN_T, 1, DV_NONE);
+    b.cout(SRC_ACC0, CMP(C_DV));
+    if (c->vd) {
+        int sb = b.cin(CMP(C_BN));
+        b.term(sb, 1, 1.0, FN_ONE, 0, DV_NONE);
+        b.term(sp, 1, -1.0, FN_S, 0, DV_NONE);
+        b.cout(SRC_ACC1, CMP(C_DB));
+    }
+    SBI_TRY(run_col(c, b));
+    c->have_prev = true;
+    return SBI_OK;
+}
+
 static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool need_eta_grad, int* vh_buf,
                               const void* w_seed = nullptr) {
     SBI_TRY(hip_ok(launch_ctl_reset(c->ctl, c->batch, c->grid.max_sweeps + 2, c->stream)));
@@ -975,6 +1003,7 @@ static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool
         if (w_seed) SBI_TRY(seed_from_physical(c, w_seed));
         SBI_TRY(iterate(c, eta_phys, tol));
         *vh_buf = C_VP;
+        if (c->grid.seed == SBI_SEED_PREV) SBI_TRY(save_nonlinear_part(c));
     }
     return SBI_OK;
 }
@@ -996,6 +1025,7 @@ static sbi_status solve_status(sbi_ctx* c, sbi_solve_info* info, bool fresh) {
         if (s < 0) worst = (worst < 0) ? worst : (sbi_status)s;
         else if (worst >= 0 && s > worst) worst = (sbi_status)s;
     }
+    if (worst < 0) c->have_prev = false;  // a failed solve seeds nothing
     return worst;
 }
 

@@ -162,6 +162,39 @@ def test_step_2d_variable_depth(gpu, mode):
     assert _rel(p.cpu().numpy().reshape(po.shape), po) < 1e-10
 
 
+@pytest.mark.parametrize("nx,ny", [(64, 1), (64, 32)])
+def test_prev_seed_matches_oracle(gpu, nx, ny):
+    """Previous-solve seed: same states as the oracle, same sweep count per solve."""
+    import torch
+    Grid, Solver = _oracle()
+    lx, ly = 8 * math.pi, 4 * math.pi
+    gs = si.GridSpec(nx, ny, lx, ly)
+    X, Y = np.meshgrid(gs.x(), gs.y())
+    if ny > 1:
+        eta, phi = si.jonswap_crossing_sea(gs, 1.0, seed=9, hs_half=0.03)
+        depth = 1.0 - 0.15 * np.exp(-((X - lx / 2) ** 2 + (Y - ly / 2) ** 2) / 20.0)
+    else:
+        eta, phi, _ = si.stokes2_finite_depth(gs, 0.03, 1.0, k0=1.0)
+        depth = 1.0 - 0.2 * np.exp(-((X - lx / 2) ** 2) / 8.0)
+    dt = 2 * math.pi / math.sqrt(math.tanh(1.0)) / 64
+    _say("prev seed", nx, ny)
+    s = _solver(gpu, nx, ny, lx, ly, depth, mode="iter", seed="prev", max_sweeps=200)
+    e = _t(eta, torch.float64, gpu)
+    p = _t(phi, torch.float64, gpu)
+    _, info = s.step(e, p, dt, 3, tol=1e-11)
+    o = Solver(Grid(nx, ny, lx, ly), depth, mode="iter", seed="prev", max_sweeps=200)
+    eo, po, so_ = o.step(eta, phi, dt, 3, tol=1e-11)
+    assert info["sweeps_total"] == sum(x.sweeps for x in so_)
+    assert info["sweeps_max"] == max(x.sweeps for x in so_)
+    assert _rel(e.cpu().numpy().reshape(eo.shape), eo) < 1e-10
+    assert _rel(p.cpu().numpy().reshape(po.shape), po) < 1e-10
+    # a repeated solve at one state is seeded with its own answer: one sweep
+    W1, _, i1 = s.vertical_velocity(e, p, tol=1e-11)
+    W2, _, i2 = s.vertical_velocity(e, p, tol=1e-11)
+    assert i2[0][0] == 1 and i2[0][1] == 0
+    assert _rel(W2.cpu().numpy(), W1.cpu().numpy()) < 1e-10
+
+
 def test_diagnostics_match_oracle(gpu):
     import torch
     Grid, Solver = _oracle()

@@ -293,3 +293,48 @@ def test_status_codes():
     # relaxation factor: 1 for eta = 0, < 1 for a steep crest
     assert s.relax_factor(np.zeros((1, 32))) == 1.0
     assert s.relax_factor(eta * 5) < 1.0
+
+
+# ---------------------------------------------------------------------------
+# Previous-solve seed: the same fixed point, reached in fewer sweeps
+# ---------------------------------------------------------------------------
+def _vd_case(seed=21):
+    g = Grid(32, 16, 4 * np.pi, 2 * np.pi)
+    X, Y = np.meshgrid(np.arange(32), np.arange(16))
+    depth = 1.0 - 0.25 * np.exp(-((X - 12) ** 2 / 30.0 + (Y - 7) ** 2 / 12.0))
+    return g, _rand_band(g, seed, amp=0.06), _rand_band(g, seed + 1, amp=0.3), depth
+
+
+def test_prev_seed_repeat_solve_is_one_sweep():
+    g, eta, phi, depth = _vd_case()
+    s = Solver(g, depth, h_ref=1.0, mode="iter", seed="prev")
+    W1, i1 = s.vertical_velocity(eta, phi, tol=1e-11)
+    assert i1.status == 0 and i1.sweeps > 5
+    # seeded with the converged (V, phi_b) of the same state, one sweep meets tol
+    W2, i2 = s.vertical_velocity(eta, phi, tol=1e-11)
+    assert i2.status == 0 and i2.sweeps == 1
+    assert np.abs(W2 - W1).max() < 1e-10 * np.abs(W1).max()
+    # the linear-seed solver is unaffected by history
+    s0 = Solver(g, depth, h_ref=1.0, mode="iter")
+    s0.vertical_velocity(eta, phi, tol=1e-11)
+    _, i3 = s0.vertical_velocity(eta, phi, tol=1e-11)
+    assert i3.sweeps == i1.sweeps
+
+
+def test_prev_seed_steps_match_linear_seed_with_fewer_sweeps():
+    g, eta, phi, depth = _vd_case(23)
+    sl = Solver(g, depth, h_ref=1.0, mode="iter")
+    sp = Solver(g, depth, h_ref=1.0, mode="iter", seed="prev")
+    el, pl, stl = sl.step(eta, phi, 0.1, 3, tol=1e-12)
+    ep, pp, stp = sp.step(eta, phi, 0.1, 3, tol=1e-12)
+    assert all(s.status == 0 for s in stl + stp)
+    assert np.abs(ep - el).max() < 1e-10 * np.abs(el).max()
+    assert np.abs(pp - pl).max() < 1e-10 * np.abs(pl).max()
+    nl = sum(s.sweeps for s in stl)
+    npv = sum(s.sweeps for s in stp)
+    assert stp[0].sweeps == stl[0].sweeps      # first solve has no history
+    assert npv < 0.9 * nl
+    # the third stage sits at the same time level as the second: its seed is
+    # closest there, and every step saves sweeps on it
+    for k in range(3):
+        assert stp[4 * k + 2].sweeps < stl[4 * k + 2].sweeps - 3
