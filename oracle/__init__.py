@@ -8,7 +8,9 @@ Method for Modeling Highly Nonlinear Water Waves in Variable Depth"):
 * Sec. 2.4 (successive approximations) with Appendix C, Eqs. (v2)-(v7): the
   surface vertical velocity V;
 * Sec. 3.1, Eq. (energy): the total energy diagnostic;
-* Sec. 3.3, Eq. (filter): the optional low-pass filter.
+* Sec. 3.3, Eq. (filter): the optional low-pass filter;
+* ``warmstart``: the learned warm start of the W iteration (features, network
+  forward and backward, Adam), defined in that module's header.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product library never does; it
@@ -21,3 +23,4 @@ from .sbi_oracle import (  # noqa: F401
     w_sa_appc,
 )
 from . import dft  # noqa: F401
+from . import warmstart  # noqa: F401
