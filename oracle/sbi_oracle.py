@@ -252,14 +252,17 @@ class Solver:
             return 1.0
         return min(1.0, 2.0 / s)
 
-    def w_iter_hat(self, eta, ph, tol, seed_hat=None):
+    def w_iter_hat(self, eta, ph, tol, seed_hat=None, seed_b_hat=None):
+        """Iteration on the summed operator from the linear guess, or from the
+        seed spectrum seed_hat of V (and the bottom-potential correction
+        seed_b_hat added to its linear guess)."""
         g = self.g
         info = SolveInfo()
         bV, bB = self.forcing(eta, ph)
         Vlin = g.k * self.T * ph
         Blin = self.S * ph
         Vh = Vlin if seed_hat is None else g.mask * seed_hat
-        Bh = Blin
+        Bh = Blin if seed_b_hat is None else Blin + g.mask * seed_b_hat
         if seed_hat is None and self.seed == "prev" and self._prev is not None:
             Vh = Vlin + self._prev[0]
             Bh = Blin + self._prev[1]
@@ -301,18 +304,20 @@ class Solver:
         return keep(Vn, Bh)
 
     # ------------------------------------------------------------------------
-    def solve_hat(self, eta, ph, tol=1e-10, seed_hat=None):
+    def solve_hat(self, eta, ph, tol=1e-10, seed_hat=None, seed_b_hat=None):
         if self.mode == "sa":
             return self.w_sa_hat(eta, ph), SolveInfo(sweeps=0)
-        return self.w_iter_hat(eta, ph, tol, seed_hat)
+        return self.w_iter_hat(eta, ph, tol, seed_hat, seed_b_hat)
 
-    def vertical_velocity(self, eta, phi_s, tol=1e-10, seed=None):
-        """W = V at z = eta for physical (eta, phi_s); phi_s is band-limited by the mask."""
+    def vertical_velocity(self, eta, phi_s, tol=1e-10, seed=None, seed_b=None):
+        """W = V at z = eta for physical (eta, phi_s); phi_s is band-limited by the mask.
+        seed / seed_b: optional physical seed of V and correction of phi_b."""
         g = self.g
         eta = np.asarray(eta, dtype=np.float64).reshape(g.ny, g.nx)
         ph = g.MF(phi_s)
         seed_hat = None if seed is None else g.fft(seed)
-        Vh, info = self.solve_hat(eta, ph, tol, seed_hat)
+        seed_b_hat = None if seed_b is None else g.fft(seed_b)
+        Vh, info = self.solve_hat(eta, ph, tol, seed_hat, seed_b_hat)
         return g.ifft(Vh), info
 
     # ------------------------------------------------------------------------

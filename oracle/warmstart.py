@@ -13,21 +13,25 @@ Network (channel-last fields x[b, y, x, c], periodic in y and x):
     layer 1   z1 = b1 + conv3x3(x; W1)   8 -> 32,  a1 = silu(z1)
     layer 2   z2 = b2 + conv3x3(a1; W2) 32 -> 32,  a2 = silu(z2)
     layer 3   z3 = b3 + conv1x1(a2; W3) 32 -> 32,  a3 = silu(z3)
-    layer 4   y  = b4 + conv1x1(a3; W4) 32 -> 1
-    seed      V0 = W_lin + out_scale * y
+    layer 4   y  = b4 + conv1x1(a3; W4) 32 -> 2
+    seed      V0 = W_lin + out_scale[0] * y[0]                      (surface)
+              phi_b0 = F^-1{sech(kh) phi_hat} + out_scale[1] * y[1]   (bottom)
 
 conv3x3 is a periodic cross-correlation:
     z[o](p) = b[o] + sum_{t=0..8} sum_c W[o, t, c] * a[c](p + off(t)),
     off(t) = (t // 3 - 1, t % 3 - 1)  as (dy, dx);
 silu(z) = z / (1 + exp(-z)).
 
-Training minimises the mean over points of (y - t)^2 with the target
-t = (W* - W_lin) / out_scale, W* the converged W of the iteration.  The
+The iteration is seeded in both of its unknowns: with a variable bed the bottom
+potential's error slows convergence as much as the surface one.  Training
+minimises the mean over points and both outputs of (y - t)^2 with the targets
+t = ((W* - W_lin) / out_scale[0], (phi_b* - phi_b,lin) / out_scale[1]), the
+nonlinear parts left by a converged iteration from the linear guess.  The
 optimiser is Adam (Kingma & Ba 2015) with bias correction; the forward pass
 uses the BF16 rounding of the FP32 master weights.
 
 Parameter vector (FP32 masters, this order): W1[32,9,8], b1[32], W2[32,9,32],
-b2[32], W3[32,32], b3[32], W4[32], b4[1].
+b2[32], W3[32,32], b3[32], W4[2,32], b4[2].
 """
 from __future__ import annotations
 
@@ -40,7 +44,7 @@ WIDTH = 32
 SHAPES = [("W1", (WIDTH, 9, CIN)), ("b1", (WIDTH,)),
           ("W2", (WIDTH, 9, WIDTH)), ("b2", (WIDTH,)),
           ("W3", (WIDTH, WIDTH)), ("b3", (WIDTH,)),
-          ("W4", (WIDTH,)), ("b4", (1,))]
+          ("W4", (2, WIDTH)), ("b4", (2,))]
 PARAM_COUNT = sum(int(np.prod(s)) for _, s in SHAPES)
 
 
@@ -120,7 +124,7 @@ def conv3x3_grad_weight(g, a):
 # network
 # ---------------------------------------------------------------------------
 def forward(theta, x, bf16_weights=True, bf16_acts=False, keep=False):
-    """Network output y[b, y, x] for features x[b, y, x, 8] (already scaled).
+    """Network output y[b, y, x, 2] for features x[b, y, x, 8] (already scaled).
 
     bf16_weights: use the BF16 rounding of the weights and the FP32 rounding
     of the biases, as the device does.
@@ -139,7 +143,7 @@ def forward(theta, x, bf16_weights=True, bf16_acts=False, keep=False):
     a2 = ra(silu(z2))
     z3 = a2 @ rw(p["W3"]).T + b3
     a3 = silu(z3)
-    y = a3 @ rw(p["W4"]) + b4[0]
+    y = a3 @ rw(p["W4"]).T + b4
     if keep:
         return y, dict(x=x0, z1=z1, a1=a1, z2=z2, a2=a2, z3=z3, a3=a3)
     return y
@@ -161,9 +165,9 @@ def loss_and_grad(theta, x, target, bf16_weights=True):
     loss = float(np.sum(r * r) / n)
     gy = 2.0 * r / n                                   # dL/dy
     g = {}
-    g["W4"] = np.einsum("byx,byxc->c", gy, c["a3"])
-    g["b4"] = np.array([gy.sum()])
-    g3 = gy[..., None] * W4[None, None, None, :] * dsilu(c["z3"])   # dL/dz3
+    g["W4"] = np.einsum("byxk,byxc->kc", gy, c["a3"])
+    g["b4"] = gy.reshape(-1, 2).sum(axis=0)
+    g3 = (gy @ W4) * dsilu(c["z3"])                    # dL/dz3
     g["W3"] = g3.reshape(-1, WIDTH).T @ c["a2"].reshape(-1, WIDTH)
     g["b3"] = g3.reshape(-1, WIDTH).sum(axis=0)
     g2 = (g3 @ W3) * dsilu(c["z2"])                    # dL/dz2
@@ -208,11 +212,28 @@ def features(solver, eta, phi_s):
 
 
 def seed(theta, in_scale, out_scale, solver, eta, phi_s, bf16_acts=True):
-    """Physical seed V0 = W_lin + out_scale * y of the iteration (one state)."""
+    """Physical seeds of the iteration for one state: V0 = W_lin + out_scale[0] y[0]
+    and the bottom-potential correction out_scale[1] y[1]."""
     f, wlin = features(solver, eta, phi_s)
     x = (f * np.asarray(in_scale, dtype=np.float32).astype(np.float64))[None]
     y = forward(theta, x, bf16_weights=True, bf16_acts=bf16_acts)[0]
-    return wlin + float(np.float32(out_scale)) * y
+    os_ = np.asarray(out_scale, dtype=np.float32).astype(np.float64)
+    return wlin + os_[0] * y[..., 0], os_[1] * y[..., 1]
+
+
+def labels(solver, eta, phi_s, tol=1e-10):
+    """Targets of one state: the nonlinear parts (W* - W_lin, phi_b - phi_b,lin)
+    left by the iteration from the linear guess, in physical space."""
+    g = solver.g
+    ph = g.MF(phi_s)
+    saved = (solver.seed, solver._prev)
+    solver.seed, solver._prev = "prev", None
+    try:
+        _, info = solver.w_iter_hat(np.asarray(eta, dtype=np.float64).reshape(g.ny, g.nx), ph, tol)
+        dV, dB = solver._prev
+    finally:
+        solver.seed, solver._prev = saved
+    return g.ifft(dV), g.ifft(dB), info
 
 
 def init_params(seed_value=0):
@@ -226,6 +247,6 @@ def init_params(seed_value=0):
     p["b2"] = np.zeros(WIDTH)
     p["W3"] = rng.standard_normal((WIDTH, WIDTH)) * math.sqrt(2.0 / WIDTH)
     p["b3"] = np.zeros(WIDTH)
-    p["W4"] = np.zeros(WIDTH)
-    p["b4"] = np.zeros(1)
+    p["W4"] = np.zeros((2, WIDTH))
+    p["b4"] = np.zeros(2)
     return pack(p).astype(np.float32).astype(np.float64)

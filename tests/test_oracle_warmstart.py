@@ -19,7 +19,7 @@ def _rand_theta(seed, scale=0.3):
 
 
 def test_param_count():
-    assert ws.PARAM_COUNT == 32 * 9 * 8 + 32 + 32 * 9 * 32 + 32 + 32 * 32 + 32 + 32 + 1
+    assert ws.PARAM_COUNT == 32 * 9 * 8 + 32 + 32 * 9 * 32 + 32 + 32 * 32 + 32 + 2 * 32 + 2
 
 
 def test_conv3x3_matches_scipy_wrap_correlation():
@@ -53,7 +53,7 @@ def test_conv3x3_input_gradient_is_adjoint():
 def test_gradient_matches_finite_differences():
     rng = np.random.default_rng(3)
     x = rng.standard_normal((2, 8, 8, 8)) * 0.7
-    t = rng.standard_normal((2, 8, 8)) * 0.2
+    t = rng.standard_normal((2, 8, 8, 2)) * 0.2
     theta = _rand_theta(4)
     _, g = ws.loss_and_grad(theta, x, t, bf16_weights=False)
     # a sample of parameters from every tensor
@@ -109,10 +109,29 @@ def test_untrained_network_gives_linear_seed():
     eta = 0.05 * np.cos(2 * np.pi * (3 * X / 32 + Y / 16) + 0.3)
     phi = 0.2 * np.sin(2 * np.pi * (2 * X / 32 - Y / 16) + 0.1)
     theta = ws.init_params(0)
-    V0 = ws.seed(theta, np.ones(8), 1.0, s, eta, phi)
+    V0, dB = ws.seed(theta, np.ones(8), (1.0, 1.0), s, eta, phi)
     _, wlin = ws.features(s, eta, phi)
-    assert np.abs(V0 - wlin).max() == 0.0
+    assert np.abs(V0 - wlin).max() == 0.0 and np.abs(dB).max() == 0.0
     assert rng is not None
+
+
+def test_labels_seed_the_fixed_point():
+    # seeding both unknowns with the labels of a state reaches the fixed point
+    # in one sweep; either label alone does not
+    g = Grid(32, 16, 8 * np.pi, 4 * np.pi)
+    X, Y = np.meshgrid(np.arange(32), np.arange(16))
+    depth = 1.0 - 0.3 * np.exp(-((X - 10) ** 2 + (Y - 8) ** 2) / 20.0)
+    s = Solver(g, depth, h_ref=1.0, mode="iter", max_sweeps=200)
+    eta = 0.06 * np.cos(2 * np.pi * (3 * X / 32 + Y / 16) + 0.3)
+    phi = 0.3 * np.sin(2 * np.pi * (2 * X / 32 - Y / 16) + 0.1)
+    dV, dB, info = ws.labels(s, eta, phi, tol=1e-13)
+    assert info.status == 0 and info.sweeps > 8
+    _, wlin = ws.features(s, eta, phi)
+    _, both = s.vertical_velocity(eta, phi, tol=1e-10, seed=wlin + dV, seed_b=dB)
+    _, vonly = s.vertical_velocity(eta, phi, tol=1e-10, seed=wlin + dV)
+    _, lin = s.vertical_velocity(eta, phi, tol=1e-10)
+    assert both.sweeps == 1
+    assert vonly.sweeps > 3 and lin.sweeps > 3
 
 
 def test_features_single_mode_closed_form():
@@ -142,7 +161,7 @@ def test_training_reduces_loss_on_a_smooth_target():
     # forward + backward + Adam working together)
     rng = np.random.default_rng(7)
     x = rng.standard_normal((2, 8, 8, 8))
-    t = 0.3 * np.tanh(x[..., 0] * x[..., 1]) + 0.2 * x[..., 2]
+    t = np.stack([0.3 * np.tanh(x[..., 0] * x[..., 1]) + 0.2 * x[..., 2], 0.2 * x[..., 6] * x[..., 3]], axis=-1)
     theta = ws.init_params(1)
     m = np.zeros_like(theta)
     v = np.zeros_like(theta)
