@@ -80,8 +80,10 @@ typedef struct sbi_grid {
                               guess plus the nonlinear part (V* - k tanh(kh) phi_hat,
                               phi_b - sech(kh) phi_hat) that the context's previous
                               solve left (the first solve, and any solve after a
-                              failed one, uses the linear guess).  SBI_SEED_USER: the
-                              w_seed field of sbi_vertical_velocity */
+                              failed one, uses the linear guess).  SBI_SEED_NET: the
+                              learned warm start of sbi_net.h (2D grids, weights from
+                              sbi_net_load).  SBI_SEED_USER: the w_seed field of
+                              sbi_vertical_velocity */
     int32_t max_sweeps;    /* iteration cap, 1..1000; default 64 */
     int32_t relax;         /* 1: under-relaxed sweeps when the crest makes plain sweeps
                               expand (default); 0: plain sweeps */
@@ -180,7 +182,9 @@ sbi_status sbi_set_depth(sbi_ctx* ctx, const double* depth, double h_ref);
 
 /*
  * Load the weights of the learned warm start (used when seed == SBI_SEED_NET).
- * weights: host float array in the layout documented in sbi_net.h; bytes its size.
+ * weights: host blob of sbi_net_blob_bytes() bytes (sbi_net_header followed by
+ * the FP32 parameter vector, see sbi_net.h); copied, caller keeps ownership.
+ * Errors: SBI_ERR_INVALID_ARG for a wrong size, header or non-finite value.
  */
 sbi_status sbi_net_load(sbi_ctx* ctx, const void* weights, size_t bytes);
 

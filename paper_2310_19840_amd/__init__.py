@@ -33,6 +33,29 @@ def make_grid(nx, ny, lx, ly=1.0, order=7, dealias=0.5, precision="fp64", mode="
     return g
 
 
+def net_blob(theta, in_scale, out_scale) -> bytes:
+    """Weight blob of the learned warm start: header + FP32 parameter vector.
+    out_scale: the scales of the V and phi_b corrections (two values)."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).ravel())
+    if th.size != _lib.SBI_NET_PARAMS:
+        raise ValueError(f"expected {_lib.SBI_NET_PARAMS} parameters")
+    h = _lib.sbi_net_header()
+    h.magic = b"SBIW"
+    h.version, h.cin, h.width, h.nparams = 1, 8, 32, _lib.SBI_NET_PARAMS
+    for i, v in enumerate(np.asarray(in_scale, dtype=np.float32).ravel()[:8]):
+        h.in_scale[i] = float(v)
+    osc = np.broadcast_to(np.asarray(out_scale, dtype=np.float64).ravel(), (2,))
+    h.out_scale[0], h.out_scale[1] = float(osc[0]), float(osc[1])
+    return bytes(h) + th.tobytes()
+
+
+def net_blob_parts(blob: bytes):
+    """(theta, in_scale, out_scale) of a weight blob."""
+    h = _lib.sbi_net_header.from_buffer_copy(blob[:C.sizeof(_lib.sbi_net_header)])
+    th = np.frombuffer(blob[C.sizeof(_lib.sbi_net_header):], dtype=np.float32).copy()
+    return th, np.array(h.in_scale[:], dtype=np.float32), np.array(h.out_scale[:], dtype=np.float32)
+
+
 def workspace_bytes(grid: _lib.sbi_grid, batch: int = 1) -> int:
     return int(_lib.load().sbi_workspace_bytes(C.byref(grid), int(batch)))
 
@@ -115,6 +138,44 @@ class Solver:
             raise SBIError(st, "sbi_diagnostics")
         return np.array(m[:]), np.array(e[:])
 
+    # -- learned warm start ----------------------------------------------------
+    def net_load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        st = self.lib.sbi_net_load(self.ctx, C.cast(buf, C.c_void_p), len(blob))
+        if st < 0:
+            raise SBIError(st, "sbi_net_load")
+
+    def net_features(self, eta, phi_s, feat=None, wlin=None):
+        t = self.torch
+        if feat is None:
+            feat = t.empty((self.batch, self.ny, self.nx, 8), dtype=t.float32, device=self.device)
+        if wlin is None:
+            wlin = self.empty()
+        st = self.lib.sbi_net_features(self.ctx, self._dev(eta, "eta"), self._dev(phi_s, "phi_s"),
+                                       C.c_void_p(feat.data_ptr()), self._dev(wlin, "wlin"))
+        if st < 0:
+            raise SBIError(st, "sbi_net_features")
+        return feat, wlin
+
+    def net_infer(self, feat, wlin):
+        """(V seed, phi_b correction) predicted by the loaded network."""
+        out, outb = self.empty(), self.empty()
+        if feat.dtype != self.torch.float32 or not feat.is_contiguous() or feat.numel() != 8 * self.batch * self.ny * self.nx:
+            raise TypeError("feat must be a contiguous float32 [batch, ny, nx, 8] tensor")
+        st = self.lib.sbi_net_infer(self.ctx, C.c_void_p(feat.data_ptr()), self._dev(wlin, "wlin"),
+                                    self._dev(out, "seed_out"), self._dev(outb, "dphib_out"))
+        if st < 0:
+            raise SBIError(st, "sbi_net_infer")
+        return out, outb
+
+    def last_correction(self):
+        """(V* - W_lin, phi_b - phi_b,lin) left by the last solve (seed="prev" contexts)."""
+        dv, db = self.empty(), self.empty()
+        st = self.lib.sbi_last_correction(self.ctx, self._dev(dv, "dv_out"), self._dev(db, "dphib_out"))
+        if st < 0:
+            raise SBIError(st, "sbi_last_correction")
+        return dv, db
+
     def set_relaxation(self, a, k, omega, gen_len, abs_len, ramp_periods):
         arr = (C.c_double * 6)(a, k, omega, gen_len, abs_len, ramp_periods)
         st = self.lib.sbi_set_relaxation(self.ctx, arr, 6)
@@ -143,6 +204,84 @@ class Solver:
         if getattr(self, "ctx", None):
             self.lib.sbi_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class NetTrainer:
+    """The library's warm-start trainer (FP32 masters, Adam) on `batch` periodic ny x nx fields."""
+
+    def __init__(self, batch, ny, nx, theta, device=None, stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = _lib.load()
+        self.batch, self.ny, self.nx = int(batch), int(ny), int(nx)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = int(self.lib.sbi_net_trainer_bytes(self.batch, self.ny, self.nx))
+        if nbytes == 0:
+            raise SBIError(_lib.SBI_ERR_INVALID_ARG, "sbi_net_trainer_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).ravel())
+        if th.size != _lib.SBI_NET_PARAMS:
+            raise ValueError(f"expected {_lib.SBI_NET_PARAMS} parameters")
+        tr = C.c_void_p()
+        st = self.lib.sbi_net_trainer_init(C.byref(tr), self.batch, self.ny, self.nx,
+                                           th.ctypes.data_as(C.POINTER(C.c_float)),
+                                           C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                           C.c_void_p(self.stream.cuda_stream))
+        if st < 0:
+            raise SBIError(st, "sbi_net_trainer_init")
+        self.tr = tr
+
+    def _f32(self, x, shape, name):
+        t = self.torch
+        if not isinstance(x, t.Tensor) or x.dtype != t.float32 or x.device != self.device or not x.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float32 tensor on {self.device}")
+        if x.numel() != int(np.prod(shape)):
+            raise ValueError(f"{name} must hold {int(np.prod(shape))} values")
+        return C.c_void_p(x.data_ptr())
+
+    def forward(self, feat):
+        y = self.torch.empty((self.batch, self.ny, self.nx, 2), dtype=self.torch.float32, device=self.device)
+        st = self.lib.sbi_net_trainer_forward(self.tr, self._f32(feat, (self.batch, self.ny, self.nx, 8), "feat"),
+                                              C.c_void_p(y.data_ptr()))
+        if st < 0:
+            raise SBIError(st, "sbi_net_trainer_forward")
+        return y
+
+    def gradient(self, feat, target, want_grad=False):
+        loss = C.c_double()
+        g = np.zeros(_lib.SBI_NET_PARAMS, dtype=np.float32) if want_grad else None
+        st = self.lib.sbi_net_trainer_gradient(
+            self.tr, self._f32(feat, (self.batch, self.ny, self.nx, 8), "feat"),
+            self._f32(target, (self.batch, self.ny, self.nx, 2), "target"), C.byref(loss),
+            g.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None)
+        if st < 0:
+            raise SBIError(st, "sbi_net_trainer_gradient")
+        return (loss.value, g) if want_grad else loss.value
+
+    def adam(self, lr):
+        st = self.lib.sbi_net_trainer_adam(self.tr, C.c_float(lr))
+        if st < 0:
+            raise SBIError(st, "sbi_net_trainer_adam")
+
+    def params(self):
+        th = np.zeros(_lib.SBI_NET_PARAMS, dtype=np.float32)
+        st = self.lib.sbi_net_trainer_params(self.tr, th.ctypes.data_as(C.POINTER(C.c_float)))
+        if st < 0:
+            raise SBIError(st, "sbi_net_trainer_params")
+        return th
+
+    def close(self):
+        if getattr(self, "tr", None):
+            self.lib.sbi_net_trainer_destroy(self.tr)
+            self.tr = None
 
     def __del__(self):
         try:

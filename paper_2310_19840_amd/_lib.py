@@ -1,4 +1,4 @@
-"""ctypes declarations of the C interface in include/sbi.h (libsbi.so)."""
+"""ctypes declarations of the C interface in include/sbi.h and include/sbi_net.h (libsbi.so)."""
 from __future__ import annotations
 
 import ctypes as C
@@ -69,7 +69,30 @@ SIGNATURES = {
     "sbi_profile_enable": (C.c_int, [C.c_void_p, C.c_int32]),
     "sbi_profile_read": (C.c_int32, [C.c_void_p, C.POINTER(C.c_char_p), C.POINTER(C.c_double),
                                      C.POINTER(C.c_int64), C.c_int32]),
+    # learned warm start (sbi_net.h)
+    "sbi_net_param_count": (C.c_int32, []),
+    "sbi_net_blob_bytes": (C.c_size_t, []),
+    "sbi_net_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sbi_net_infer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sbi_last_correction": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sbi_net_trainer_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
+    "sbi_net_trainer_init": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32,
+                                       C.POINTER(C.c_float), C.c_void_p, C.c_size_t, C.c_void_p]),
+    "sbi_net_trainer_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sbi_net_trainer_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_float)]),
+    "sbi_net_trainer_adam": (C.c_int, [C.c_void_p, C.c_float]),
+    "sbi_net_trainer_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
+    "sbi_net_trainer_destroy": (C.c_int, [C.c_void_p]),
 }
+
+SBI_NET_PARAMS = 12706
+
+
+class sbi_net_header(C.Structure):
+    _fields_ = [("magic", C.c_char * 4), ("version", C.c_uint32), ("cin", C.c_uint32), ("width", C.c_uint32),
+                ("nparams", C.c_uint32), ("in_scale", C.c_float * 8), ("out_scale", C.c_float * 2),
+                ("reserved", C.c_float * 1)]
 
 _lib = None
 

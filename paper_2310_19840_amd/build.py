@@ -29,6 +29,8 @@ UNITS = [
     ("sbi_kernels.hip", "sbi_k32.o", ["-DSBI_REAL=float"]),
     ("sbi_dispatch.hip", "sbi_dispatch.o", []),
     ("sbi_api.hip", "sbi_api.o", []),
+    ("sbi_net.hip", "sbi_net.o", []),
+    ("sbi_net_api.hip", "sbi_net_api.o", []),
 ]
 
 

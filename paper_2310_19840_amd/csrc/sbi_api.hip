@@ -17,11 +17,14 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/sbi.h"
+#include "../../include/sbi_net.h"
 #include "sbi_kernels.hpp"
+#include "sbi_net.hpp"
 
 using namespace sbi;
 
@@ -63,11 +66,11 @@ struct Stats {
 // kernel classes timed by the optional profiler
 enum {
     K_ROW_FWD, K_ROW_INV, K_ROW_SETUP, K_ROW_SWEEP, K_ROW_SA, K_ROW_NPHI, K_ROW_BLEND,
-    K_COL_STATE, K_COL_FORCING, K_COL_SWEEP, K_COL_SA, K_COL_OTHER, K_RK, K_DIAG, K_COUNT
+    K_COL_STATE, K_COL_FORCING, K_COL_SWEEP, K_COL_SA, K_COL_OTHER, K_RK, K_DIAG, K_NET, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {
     "row_fwd", "row_inv", "row_setup", "row_sweep", "row_sa", "row_nphi", "row_blend",
-    "col_state", "col_forcing", "col_sweep", "col_sa", "col_other", "rk", "diag"};
+    "col_state", "col_forcing", "col_sweep", "col_sa", "col_other", "rk", "diag", "net"};
 
 struct Profiler {
     bool on = false;
@@ -109,6 +112,11 @@ struct sbi_ctx {
     bool depth_warn = false;
     bool relax_on = false;
     bool have_prev = false;  // C_DV/C_DB hold the last solve's nonlinear part (SBI_SEED_PREV)
+    NetPacked* net = nullptr;  // learned warm start: packed weights (device)
+    bool net_loaded = false;
+    float net_scale[8] = {1, 1, 1, 1, 1, 1, 1, 1};
+    float* feat = nullptr;     // feature field [batch][ny][nx][8] (SBI_SEED_NET)
+    int fallbacks = 0;         // solves of the current call restarted from the linear guess
     double rz[6] = {0, 0, 0, 0, 0, 0};
     Stats st;
     Profiler prof;
@@ -152,7 +160,7 @@ struct Layout {
     int Mx, My, Kx, Kxp, Ky, C, ldh;
     size_t rsz, csz;
     long long s_phys, s_half, s_cmp;
-    size_t bytes_comp, bytes_half, bytes_phys, bytes_tw, bytes_misc, total;
+    size_t bytes_comp, bytes_half, bytes_phys, bytes_tw, bytes_misc, bytes_net, total;
 };
 
 static bool grid_valid(const sbi_grid* g) {
@@ -202,7 +210,10 @@ static Layout layout(const sbi_grid* g, int batch) {
     L.bytes_misc = al(sizeof(double) * batch) + al(sizeof(Ctl) * batch) + al(sizeof(CtlSlots) * batch) +
                    al(sizeof(double) * 2 * 64 * batch) +
                    al((size_t)L.s_cmp * L.csz * batch * kMaxGroups * 4) + al(sizeof(int) * (size_t)kMaxTiles * batch);
-    L.total = L.bytes_comp + L.bytes_half + L.bytes_phys + L.bytes_tw + L.bytes_misc;
+    // learned warm start: packed weights, and the feature field when it seeds the iteration
+    L.bytes_net = al(sizeof(NetPacked)) +
+                  ((g->seed == SBI_SEED_NET && g->ny > 1) ? al((size_t)L.s_phys * 8 * sizeof(float) * batch) : 0);
+    L.total = L.bytes_comp + L.bytes_half + L.bytes_phys + L.bytes_tw + L.bytes_misc + L.bytes_net;
     return L;
 }
 
@@ -295,6 +306,7 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
                                void* workspace, size_t ws_bytes, void* hip_stream) {
     if (!out || !grid_valid(g) || batch < 1 || !depth) return SBI_ERR_INVALID_ARG;
     *out = nullptr;
+    if (g->seed == SBI_SEED_NET && g->ny == 1) return SBI_ERR_UNSUPPORTED;  // the network is 2D
     const Layout L = layout(g, batch);
     if (workspace && ws_bytes < L.total) return SBI_ERR_WORKSPACE;
     sbi_ctx* c = new sbi_ctx();
@@ -364,6 +376,9 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
     p += al((size_t)L.s_cmp * L.csz * batch * kMaxGroups * 4);
     c->cnt = reinterpret_cast<int*>(p);
     p += al(sizeof(int) * (size_t)kMaxTiles * batch);
+    c->net = reinterpret_cast<NetPacked*>(p);
+    p += al(sizeof(NetPacked));
+    if (g->seed == SBI_SEED_NET && g->ny > 1) c->feat = reinterpret_cast<float*>(p);
     c->col_C = L.C;
     gd.href = c->href_dev;
     if (hipHostMalloc(reinterpret_cast<void**>(&c->head), sizeof(Ctl) * batch, hipHostMallocDefault) != hipSuccess) {
@@ -638,7 +653,7 @@ static sbi_status to_spectral(sbi_ctx* c, const void* eta, const void* phi, bool
 
 // compact stage state (C_ES, C_PS) -> half forms of eta, grad eta, grad phi, and
 // the linear-guess seeds (Sec. 2.4 initiation) of the iteration / SA order 1.
-static sbi_status stage_state_pass(sbi_ctx* c, bool need_eta) {
+static sbi_status stage_state_pass(sbi_ctx* c, bool need_eta, bool allow_prev = true) {
     const bool two_d = c->grid.ny > 1;
     ColBuilder b(c->gd);
     int se = b.cin(CMP(C_ES));
@@ -662,7 +677,7 @@ static sbi_status stage_state_pass(sbi_ctx* c, bool need_eta) {
     if (c->grid.mode == SBI_MODE_SA) {
         b.cout(SRC_ACC2, CMP(C_VH));
     } else {
-        if (c->grid.seed == SBI_SEED_PREV && c->have_prev) {
+        if (allow_prev && c->grid.seed == SBI_SEED_PREV && c->have_prev) {
             // previous-solve seed: linear guess + the last solve's nonlinear part
             b.term(b.cin(CMP(C_DV)), 2, 1.0, FN_ONE, 0, DV_NONE);
             if (c->vd) b.term(b.cin(CMP(C_DB)), 3, 1.0, FN_ONE, 0, DV_NONE);
@@ -967,6 +982,78 @@ static sbi_status seed_from_physical(sbi_ctx* c, const void* w_seed) {
     return run_col(c, b);
 }
 
+// features of the learned warm start at the stage state: reads the half forms
+// left by stage_state_pass (W_lin in H_GV, gradients in H_EX/H_EY/H_PX/H_PY)
+static sbi_status row_features(sbi_ctx* c, const void* eta_phys, float* feat, void* wlin) {
+    RowFeatParams fp{};
+    fp.g = c->gd;
+    fp.gV = HALF(H_GV);
+    fp.gex = HALF(H_EX);
+    fp.gey = HALF(H_EY);
+    fp.gpx = HALF(H_PX);
+    fp.gpy = HALF(H_PY);
+    fp.eta = eta_phys;
+    fp.delta = PHYS(P_DELTA);
+    for (int i = 0; i < 8; ++i) fp.scale[i] = c->net_scale[i];
+    fp.feat = feat;
+    fp.wlin = wlin;
+    c->st.launches += 1;
+    ProfScope ps_(c, K_NET);
+    return hip_ok(launch_row_feat(c->fp64, fp, c->batch, tw_of(c), c->stream));
+}
+
+static sbi_status net_infer(sbi_ctx* c, const float* feat, const void* wlin, void* out, void* out_b) {
+    NetInferParams ip{};
+    ip.feat = feat;
+    ip.wlin = wlin;
+    ip.out = out;
+    ip.out_b = out_b;
+    ip.w = c->net;
+    ip.ny = c->grid.ny;
+    ip.nx = c->grid.nx;
+    ip.s_phys = c->gd.s_phys;
+    c->st.launches += 1;
+    ProfScope ps_(c, K_NET);
+    return hip_ok(launch_net_infer(c->fp64, ip, c->batch, c->stream));
+}
+
+// learned seeds: V0 = W_lin + out_scale[0] y[0] and phi_b0 = S phi_hat +
+// mask F{out_scale[1] y[1]} set as the iterate (runs after stage_state_pass,
+// which left the linear guesses in C_VN / C_BN)
+static sbi_status net_seed(sbi_ctx* c, const void* eta_phys) {
+    if (!c->net_loaded || !c->feat) return SBI_ERR_INVALID_ARG;
+    SBI_TRY(row_features(c, eta_phys, c->feat, PHYS(P_V0)));
+    SBI_TRY(net_infer(c, c->feat, PHYS(P_V0), PHYS(P_V0 + 1), PHYS(P_V0 + 2)));
+    RowFwdParams rp{};
+    rp.g = c->gd;
+    rp.nf = c->vd ? 2 : 1;
+    rp.in[0] = PHYS(P_V0 + 1);
+    rp.out[0] = HALF(H_PROD0);
+    rp.in[1] = PHYS(P_V0 + 2);
+    rp.out[1] = HALF(H_PROD0 + 1);
+    c->st.launches += 1;
+    {
+        ProfScope ps_(c, K_NET);
+        SBI_TRY(hip_ok(launch_row_fwd(c->fp64, rp, c->batch, tw_of(c), c->stream)));
+    }
+    ColBuilder b(c->gd);
+    int sv = b.prod(HALF(H_PROD0));
+    b.term(sv, 0, 1.0, FN_ONE, 0, DV_NONE);
+    b.cout(SRC_ACC0, CMP(C_VN));
+    b.inv(SRC_ACC0, DV_NONE, HALF(H_GV));
+    if (c->vd) {
+        const bool two_d = c->grid.ny > 1;
+        int sb = b.prod(HALF(H_PROD0 + 1));
+        int cb = b.cin(CMP(C_BN));
+        b.term(sb, 1, 1.0, FN_ONE, 0, DV_NONE);
+        b.term(cb, 1, 1.0, FN_ONE, 0, DV_NONE);
+        b.cout(SRC_ACC1, CMP(C_BN));
+        b.inv(SRC_ACC1, DV_X, HALF(H_GBX));
+        if (two_d) b.inv(SRC_ACC1, DV_Y, HALF(H_GBY));
+    }
+    return run_col(c, b, K_NET);
+}
+
 // keeps (V* - kT phi_hat, phi_b - S phi_hat) of the finished solve: the seed of
 // the next one adds them to its own linear guess.  phi_b is the iterate after
 // the relaxed update of the last sweep.
@@ -992,7 +1079,8 @@ static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool
                               const void* w_seed = nullptr) {
     SBI_TRY(hip_ok(launch_ctl_reset(c->ctl, c->batch, c->grid.max_sweeps + 2, c->stream)));
     c->st.launches += 1;
-    SBI_TRY(stage_state_pass(c, need_eta_grad || !eta_user));
+    const bool net = c->grid.seed == SBI_SEED_NET && c->grid.mode == SBI_MODE_ITER;
+    SBI_TRY(stage_state_pass(c, need_eta_grad || !eta_user || net));
     SBI_TRY(row_setup(c, eta_user));
     const void* eta_phys = eta_user ? eta_user : PHYS(P_ETA);
     if (c->grid.mode == SBI_MODE_SA) {
@@ -1000,8 +1088,22 @@ static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool
         *vh_buf = C_VH;
     } else {
         SBI_TRY(col_forcing(c));
+        if (net) SBI_TRY(net_seed(c, eta_phys));
         if (w_seed) SBI_TRY(seed_from_physical(c, w_seed));
         SBI_TRY(iterate(c, eta_phys, tol));
+        if (net) {
+            // the linear guess is the fallback when the learned seed fails
+            bool failed = false;
+            for (int b = 0; b < c->batch; ++b) failed |= c->head[b].status < 0 || c->head[b].nonfinite;
+            if (failed) {
+                c->fallbacks += 1;
+                SBI_TRY(hip_ok(launch_ctl_reset(c->ctl, c->batch, c->grid.max_sweeps + 2, c->stream)));
+                SBI_TRY(stage_state_pass(c, false));
+                SBI_TRY(row_setup(c, eta_user));
+                SBI_TRY(col_forcing(c));
+                SBI_TRY(iterate(c, eta_phys, tol));
+            }
+        }
         *vh_buf = C_VP;
         if (c->grid.seed == SBI_SEED_PREV) SBI_TRY(save_nonlinear_part(c));
     }
@@ -1040,7 +1142,10 @@ extern "C" sbi_status sbi_vertical_velocity(sbi_ctx* c, const void* eta, const v
         SBI_TRY(set_depth(c, h, -1.0));
         if (c->depth_warn) warn = SBI_WARN_DEPTH_CRITERION;
     }
-    SBI_TRY(to_spectral(c, nullptr, phi_s, false));
+    // the learned seed needs the masked spectrum of eta for its gradient features
+    const bool net = c->grid.seed == SBI_SEED_NET && c->grid.mode == SBI_MODE_ITER;
+    c->fallbacks = 0;
+    SBI_TRY(to_spectral(c, net ? eta : nullptr, phi_s, false));
     int vh = 0;
     SBI_TRY(solve_stage(c, eta, tol, false, &vh,
                         (c->grid.seed == SBI_SEED_USER && c->grid.mode == SBI_MODE_ITER) ? w_seed : nullptr));
@@ -1059,6 +1164,7 @@ extern "C" sbi_status sbi_vertical_velocity(sbi_ctx* c, const void* eta, const v
         SBI_TRY(hip_ok(launch_row_inv(c->fp64, ip, c->batch, tw_of(c), c->stream)));
     }
     SBI_HIP(hipStreamSynchronize(c->stream));
+    if (st == SBI_OK && c->fallbacks > 0) st = SBI_WARN_FALLBACK_USED;
     return st != SBI_OK ? st : warn;
 }
 
@@ -1184,6 +1290,7 @@ extern "C" sbi_status sbi_step(sbi_ctx* c, sbi_state* state, double dt, int32_t 
     if (!c || !state || !state->eta || !state->phi_s || n < 0 || !std::isfinite(dt)) return SBI_ERR_INVALID_ARG;
     if (c->grid.mode == SBI_MODE_ITER && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
     c->st = Stats();
+    c->fallbacks = 0;
     sbi_step_info si{};
     SBI_TRY(to_spectral(c, state->eta, state->phi_s, true));
     sbi_status worst = SBI_OK;
@@ -1215,7 +1322,9 @@ extern "C" sbi_status sbi_step(sbi_ctx* c, sbi_state* state, double dt, int32_t 
     SBI_TRY(to_physical(c, state->eta, state->phi_s));
     SBI_HIP(hipStreamSynchronize(c->stream));
     state->t = t;
+    si.fallbacks = c->fallbacks;
     if (info) *info = si;
+    if (worst == SBI_OK && c->fallbacks > 0) worst = SBI_WARN_FALLBACK_USED;
     return worst;
 }
 
@@ -1283,7 +1392,100 @@ extern "C" int32_t sbi_profile_read(sbi_ctx* c, const char** names, double* tota
     return k;
 }
 
+// ---------------------------------------------------------------------------
+// learned warm start
+// ---------------------------------------------------------------------------
+static uint16_t host_bf16(float f) {  // round to nearest even (finite values)
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 extern "C" sbi_status sbi_net_load(sbi_ctx* c, const void* weights, size_t bytes) {
-    if (!c || !weights || bytes == 0) return SBI_ERR_INVALID_ARG;
-    return SBI_ERR_UNSUPPORTED;
+    if (!c || !weights || bytes != sbi_net_blob_bytes()) return SBI_ERR_INVALID_ARG;
+    sbi_net_header h;
+    std::memcpy(&h, weights, sizeof(h));
+    if (std::memcmp(h.magic, "SBIW", 4) != 0 || h.version != 1 || h.cin != kNetCin || h.width != kNetWidth ||
+        h.nparams != kNetParams)
+        return SBI_ERR_INVALID_ARG;
+    for (float v : h.out_scale)
+        if (!std::isfinite(v)) return SBI_ERR_INVALID_ARG;
+    std::vector<float> th(kNetParams);
+    std::memcpy(th.data(), static_cast<const char*>(weights) + sizeof(h), sizeof(float) * kNetParams);
+    for (float v : th)
+        if (!std::isfinite(v)) return SBI_ERR_INVALID_ARG;
+    for (float v : h.in_scale)
+        if (!std::isfinite(v)) return SBI_ERR_INVALID_ARG;
+    auto pk = std::make_unique<NetPacked>();
+    std::memset(pk.get(), 0, sizeof(NetPacked));
+    for (int o = 0; o < 32; ++o) {
+        for (int k = 0; k < 9 * 8; ++k) pk->w1[o * kL1S + k] = host_bf16(th[kOffW1 + o * 72 + k]);
+        for (int k = 0; k < 9 * 32; ++k) pk->w2[o * kL2S + k] = host_bf16(th[kOffW2 + o * 288 + k]);
+        for (int k = 0; k < 32; ++k) pk->w3[o * kL3S + k] = host_bf16(th[kOffW3 + o * 32 + k]);
+        pk->w4[o] = host_bf16(th[kOffW4 + o]);
+        pk->w4[32 + o] = host_bf16(th[kOffW4 + 32 + o]);
+        pk->b1[o] = th[kOffB1 + o];
+        pk->b2[o] = th[kOffB2 + o];
+        pk->b3[o] = th[kOffB3 + o];
+    }
+    for (int k = 0; k < 2; ++k) {
+        pk->b4[k] = th[kOffB4 + k];
+        pk->out_scale[k] = h.out_scale[k];
+    }
+    for (int i = 0; i < 8; ++i) pk->in_scale[i] = h.in_scale[i];
+    SBI_HIP(hipMemcpyAsync(c->net, pk.get(), sizeof(NetPacked), hipMemcpyHostToDevice, c->stream));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 8; ++i) c->net_scale[i] = h.in_scale[i];
+    c->net_loaded = true;
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_net_features(sbi_ctx* c, const void* eta, const void* phi_s, float* feat_out,
+                                       void* wlin_out) {
+    if (!c || !eta || !phi_s || !feat_out) return SBI_ERR_INVALID_ARG;
+    if (c->grid.ny == 1) return SBI_ERR_UNSUPPORTED;
+    c->st = Stats();
+    SBI_TRY(to_spectral(c, eta, phi_s, false));
+    SBI_TRY(stage_state_pass(c, true, false));
+    SBI_TRY(row_features(c, eta, feat_out, wlin_out));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_net_infer(sbi_ctx* c, const float* feat, const void* wlin, void* seed_out,
+                                    void* dphib_out) {
+    if (!c || !feat || !wlin || !seed_out || !dphib_out) return SBI_ERR_INVALID_ARG;
+    if (c->grid.ny == 1) return SBI_ERR_UNSUPPORTED;
+    if (!c->net_loaded) return SBI_ERR_INVALID_ARG;
+    SBI_TRY(net_infer(c, feat, wlin, seed_out, dphib_out));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_last_correction(sbi_ctx* c, void* dv_out, void* dphib_out) {
+    if (!c || !dv_out || !dphib_out) return SBI_ERR_INVALID_ARG;
+    if (c->grid.seed != SBI_SEED_PREV || c->grid.mode != SBI_MODE_ITER || !c->have_prev) return SBI_ERR_INVALID_ARG;
+    c->st = Stats();
+    ColBuilder b(c->gd);
+    b.term(b.cin(CMP(C_DV)), 0, 1.0, FN_ONE, 0, DV_NONE);
+    b.inv(SRC_ACC0, DV_NONE, HALF(H_PROD0));
+    if (c->vd) {
+        b.term(b.cin(CMP(C_DB)), 1, 1.0, FN_ONE, 0, DV_NONE);
+        b.inv(SRC_ACC1, DV_NONE, HALF(H_PROD0 + 1));
+    }
+    SBI_TRY(run_col(c, b));
+    RowInvParams ip{};
+    ip.g = c->gd;
+    ip.nf = c->vd ? 2 : 1;
+    ip.in[0] = HALF(H_PROD0);
+    ip.out[0] = dv_out;
+    ip.in[1] = HALF(H_PROD0 + 1);
+    ip.out[1] = dphib_out;
+    ip.ctl = c->ctl;
+    c->st.launches += 1;
+    SBI_TRY(hip_ok(launch_row_inv(c->fp64, ip, c->batch, tw_of(c), c->stream)));
+    if (!c->vd) SBI_TRY(hip_ok(launch_fill_zero(dphib_out, (size_t)c->gd.s_phys * c->rsz * c->batch, c->stream)));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    return SBI_OK;
 }

@@ -63,6 +63,7 @@ SBI_DISPATCH(launch_row_sweep, RowSweepParams)
 SBI_DISPATCH(launch_row_sa, RowSaParams)
 SBI_DISPATCH(launch_row_nphi, RowNphiParams)
 SBI_DISPATCH(launch_row_blend, RowBlendParams)
+SBI_DISPATCH(launch_row_feat, RowFeatParams)
 SBI_DISPATCH(launch_col, ColParams)
 
 hipError_t launch_rk(int fp64, const RkParams& p, int batch, hipStream_t s) {

@@ -532,6 +532,42 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_blend(const RowBlendP
     RW::forward(f, static_cast<V*>(p.hp) + hb, rc, lds_all, twN, twX);
 }
 
+// Learned-warm-start features of each point, channel-last FP32:
+// (eta, W_lin, d_x eta, d_y eta, d_x phi, d_y phi, delta, eta * W_lin), each
+// multiplied by its channel scale in the working precision before rounding.
+template <typename R, int NX>
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_feat(const RowFeatParams p, const typename cplx_of<R>::type* twN_tab,
+                           const typename cplx_of<R>::type* twX) {
+    ROW_PROLOGUE(R, NX)
+    V wl[E], a[E];
+    RW::inverse(wl, static_cast<const V*>(p.gV) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+    if (p.wlin) RW::store(wl, static_cast<R*>(p.wlin) + po, ri.j, ri.valid);
+    float2 fe[4][E];
+    const void* src[4] = {p.gex, p.gey, p.gpx, p.gpy};
+    const int ch[4] = {2, 3, 4, 5};
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        RW::inverse(a, static_cast<const V*>(src[f]) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+        const R sc = R(p.scale[ch[f]]);
+#pragma unroll
+        for (int q = 0; q < E; ++q) fe[f][q] = make_float2((float)(a[q].x * sc), (float)(a[q].y * sc));
+    }
+    if (!ri.valid) return;  // after the last workgroup barrier
+    V ev[E], dv[E];
+    RW::load(ev, static_cast<const R*>(p.eta) + po, ri.j, true);
+    RW::load(dv, static_cast<const R*>(p.delta) + po, ri.j, true);
+    const R s0 = R(p.scale[0]), s1 = R(p.scale[1]), s6 = R(p.scale[6]), s7 = R(p.scale[7]);
+    float4* out = reinterpret_cast<float4*>(p.feat + po * 8);
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int n = ri.j + q * RW::P;  // points 2n and 2n + 1 of the row
+        out[4 * n + 0] = make_float4((float)(ev[q].x * s0), (float)(wl[q].x * s1), fe[0][q].x, fe[1][q].x);
+        out[4 * n + 1] = make_float4(fe[2][q].x, fe[3][q].x, (float)(dv[q].x * s6), (float)(ev[q].x * wl[q].x * s7));
+        out[4 * n + 2] = make_float4((float)(ev[q].y * s0), (float)(wl[q].y * s1), fe[0][q].y, fe[1][q].y);
+        out[4 * n + 3] = make_float4(fe[2][q].y, fe[3][q].y, (float)(dv[q].y * s6), (float)(ev[q].y * wl[q].y * s7));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Column pass: forward column transforms of the products, multiplier sums,
 // relaxation, compact outputs, inverse column transforms of the results.
@@ -1118,6 +1154,7 @@ SBI_ROW_LAUNCH(k_row_sweep, RowSweepParams)
 SBI_ROW_LAUNCH(k_row_sa, RowSaParams)
 SBI_ROW_LAUNCH(k_row_nphi, RowNphiParams)
 SBI_ROW_LAUNCH(k_row_blend, RowBlendParams)
+SBI_ROW_LAUNCH(k_row_feat, RowFeatParams)
 
 template <typename R, int NY, int NACC>
 static hipError_t col_go(const ColParams& p, int batch, const Twiddles& tw, hipStream_t s) {
@@ -1176,6 +1213,9 @@ template <> hipError_t launch_row_nphi_t<Real>(const RowNphiParams& p, int b, co
 }
 template <> hipError_t launch_row_blend_t<Real>(const RowBlendParams& p, int b, const Twiddles& tw, hipStream_t s) {
     return k_row_blend_nx<Real>(p, b, tw, s);
+}
+template <> hipError_t launch_row_feat_t<Real>(const RowFeatParams& p, int b, const Twiddles& tw, hipStream_t s) {
+    return k_row_feat_nx<Real>(p, b, tw, s);
 }
 template <> hipError_t launch_col_t<Real>(const ColParams& p, int b, const Twiddles& tw, hipStream_t s) {
     return col_ny<Real>(p, b, tw, s);

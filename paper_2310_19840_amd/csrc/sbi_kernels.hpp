@@ -86,6 +86,22 @@ struct RowNphiParams {
     Ctl* ctl;
 };
 
+// features of the learned warm start (channel-last, FP32, scaled per channel):
+// (eta, W_lin, d_x eta, d_y eta, d_x phi, d_y phi, delta, eta * W_lin)
+struct RowFeatParams {
+    GridDev g;
+    const void* gV;     // half form of W_lin = F^-1{k tanh(kh) phi_hat}
+    const void* gex;    // half forms of grad eta
+    const void* gey;
+    const void* gpx;    // half forms of grad phi
+    const void* gpy;
+    const void* eta;    // physical eta as the solve sees it
+    const void* delta;  // physical delta
+    float scale[8];
+    float* feat;        // [batch][ny][nx][8]
+    void* wlin;         // physical W_lin, optional
+};
+
 struct RowBlendParams {
     GridDev g;
     const void* ge;
@@ -135,6 +151,7 @@ template <typename R> hipError_t launch_row_sweep_t(const RowSweepParams&, int, 
 template <typename R> hipError_t launch_row_sa_t(const RowSaParams&, int, const Twiddles&, hipStream_t);
 template <typename R> hipError_t launch_row_nphi_t(const RowNphiParams&, int, const Twiddles&, hipStream_t);
 template <typename R> hipError_t launch_row_blend_t(const RowBlendParams&, int, const Twiddles&, hipStream_t);
+template <typename R> hipError_t launch_row_feat_t(const RowFeatParams&, int, const Twiddles&, hipStream_t);
 template <typename R> hipError_t launch_col_t(const ColParams&, int, const Twiddles&, hipStream_t);
 template <typename R> hipError_t launch_rk_t(const RkParams&, int, hipStream_t);
 template <typename R> hipError_t launch_diag_t(const DiagParams&, int, hipStream_t);
@@ -146,6 +163,7 @@ hipError_t launch_row_sweep(int fp64, const RowSweepParams& p, int batch, const 
 hipError_t launch_row_sa(int fp64, const RowSaParams& p, int batch, const Twiddles& tw, hipStream_t s);
 hipError_t launch_row_nphi(int fp64, const RowNphiParams& p, int batch, const Twiddles& tw, hipStream_t s);
 hipError_t launch_row_blend(int fp64, const RowBlendParams& p, int batch, const Twiddles& tw, hipStream_t s);
+hipError_t launch_row_feat(int fp64, const RowFeatParams& p, int batch, const Twiddles& tw, hipStream_t s);
 hipError_t launch_col(int fp64, const ColParams& p, int batch, const Twiddles& tw, hipStream_t s);
 hipError_t launch_rk(int fp64, const RkParams& p, int batch, hipStream_t s);
 hipError_t launch_diag(int fp64, const DiagParams& p, int batch, hipStream_t s);

@@ -1,0 +1,171 @@
+"""Training of the learned warm start on the GPU, with the library's own kernels.
+
+Samples are states of the crossing-sea workload (two JONSWAP systems crossing
+at +-20 degrees over random Gaussian-bump bathymetry, k_p h_ref in [0.8, 3],
+dx = lambda_p / 8) on periodic n x n grids.  For each state the library gives
+the features (sbi_net_features) and the nonlinear parts (W* - W_lin,
+phi_b - phi_b,lin) of its converged iteration (FP64, tolerance 1e-10, linear
+seed; sbi_last_correction); the network learns both.  Forward, backward and Adam run in the library's trainer kernels;
+this module only moves tensors and schedules the steps.
+
+    python -m paper_2310_19840_amd.warmstart --n 256 --samples 96 --steps 3000 \\
+        --out paper_2310_19840_amd/weights/warmstart_c5.sbiw
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import NetTrainer, Solver, net_blob
+
+WIDTH, CIN = 32, 8
+
+
+def initial_params(seed: int = 0) -> np.ndarray:
+    """He-normal weights, zero biases, and a zero last layer (the untrained
+    network returns the linear seed unchanged)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    he = lambda n, fan_in: rng.standard_normal(n) * math.sqrt(2.0 / fan_in)  # noqa: E731
+    parts = [he(WIDTH * 9 * CIN, 9 * CIN), np.zeros(WIDTH),
+             he(WIDTH * 9 * WIDTH, 9 * WIDTH), np.zeros(WIDTH),
+             he(WIDTH * WIDTH, WIDTH), np.zeros(WIDTH),
+             np.zeros(2 * WIDTH), np.zeros(2)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def make_samples(seeds, n, device, tol=1e-10, members=8, log=None):
+    """Features and labels of the workload's states for the given seeds.
+
+    Returns (feat [S, n, n, 8] float32, dv [S, n, n], dphib [S, n, n] float64,
+    sweeps [S]) as device tensors / numpy array."""
+    import torch
+
+    from sbi_inputs import config_c5
+
+    feats, dvs, dbs, sweeps = [], [], [], []
+    seeds = list(seeds)
+    for i0 in range(0, len(seeds), members):
+        grp = seeds[i0:i0 + members]
+        cfgs = [config_c5(seed=s, n=n) for s in grp]
+        g = cfgs[0]["grid"]
+        depth = np.stack([c["depth"] for c in cfgs])
+        s = Solver(g.nx, g.ny, g.lx, g.ly, depth, h_ref=-1.0, batch=len(grp), device=device, mode="iter",
+                   precision="fp64", seed="prev", max_sweeps=600)
+        eta = torch.tensor(np.stack([c["eta"] for c in cfgs]), dtype=torch.float64, device=device)
+        phi = torch.tensor(np.stack([c["phi"] for c in cfgs]), dtype=torch.float64, device=device)
+        W, st, info = s.vertical_velocity(eta, phi, tol=tol)
+        if st != 0:
+            raise RuntimeError(f"label solve failed with status {st}: {info}")
+        dv, db = s.last_correction()
+        f, _ = s.net_features(eta, phi)
+        feats.append(f)
+        dvs.append(dv)
+        dbs.append(db)
+        sweeps += [i[0] for i in info]
+        if log:
+            log(f"samples {i0 + len(grp)}/{len(seeds)}: mean sweeps {np.mean([i[0] for i in info]):.1f}")
+        s.close()
+    return torch.cat(feats), torch.cat(dvs), torch.cat(dbs), np.array(sweeps)
+
+
+def fit(feat, dv, db, steps, batch=4, lr=2e-3, seed=0, device=None, log=None, log_every=100):
+    """Train on the samples; returns (blob, loss history)."""
+    import torch
+
+    S, n = feat.shape[0], feat.shape[1]
+    # per-channel input scales and the output scales, from the training states
+    std = feat.double().reshape(-1, CIN).std(dim=0).cpu().numpy()
+    in_scale = np.where(std > 0, 1.0 / np.maximum(std, 1e-30), 1.0).astype(np.float32)
+    osv = float(dv.std().item())
+    osb = float(db.std().item())
+    out_scale = np.array([osv if osv > 0 else 1.0, osb if osb > 0 else 1.0])
+    x = (feat * torch.tensor(in_scale, device=feat.device)).contiguous()
+    t = torch.stack([dv / out_scale[0], db / out_scale[1]], dim=-1).float().contiguous()
+    theta = initial_params(seed)
+    tr = NetTrainer(batch, n, n, theta, device=device or feat.device)
+    hist = []
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    order = rng.permutation(S)
+    pos = 0
+    for it in range(steps):
+        if pos + batch > S:
+            order = rng.permutation(S)
+            pos = 0
+        idx = torch.tensor(order[pos:pos + batch], device=feat.device)
+        pos += batch
+        xb = x.index_select(0, idx).contiguous()
+        tb = t.index_select(0, idx).contiguous()
+        loss = tr.gradient(xb, tb)
+        # cosine decay of the step size
+        tr.adam(lr * 0.5 * (1.0 + math.cos(math.pi * it / steps)) + 1e-5)
+        hist.append(loss)
+        if log and (it % log_every == 0 or it == steps - 1):
+            log(f"step {it}: loss {loss:.4e}")
+    th = tr.params()
+    tr.close()
+    return net_blob(th, in_scale, out_scale), np.array(hist)
+
+
+def sweeps_with(blob, seeds, n, device, tol=1e-8, seed_mode="net"):
+    """(sweeps, status) of the iteration at the given states, seeded by the net
+    (seed_mode "net") or the linear guess ("linear")."""
+    import torch
+
+    from sbi_inputs import config_c5
+
+    out = []
+    for s_ in seeds:
+        cfg = config_c5(seed=s_, n=n)
+        g = cfg["grid"]
+        eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=device)
+        phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=device)
+        s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], h_ref=-1.0, device=device, mode="iter", precision="fp64",
+                   seed=seed_mode, max_sweeps=600)
+        if seed_mode == "net":
+            s.net_load(blob)
+        W, st, info = s.vertical_velocity(eta, phi, tol=tol)
+        out.append((info[0][0], st))
+        s.close()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--samples", type=int, default=96)
+    ap.add_argument("--heldout", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "weights", "warmstart_c5.sbiw"))
+    a = ap.parse_args(argv)
+    import torch
+
+    dev = torch.device("cuda:0")
+
+    def log(m):
+        print(m, flush=True)
+
+    t0 = time.time()
+    feat, dv, db, sw = make_samples(range(1000, 1000 + a.samples), a.n, dev, log=log)
+    log(f"data: {a.samples} states at {a.n}^2, {time.time() - t0:.1f} s")
+    blob, hist = fit(feat, dv, db, a.steps, a.batch, a.lr, device=dev, log=log)
+    log(f"trained {a.steps} steps in {time.time() - t0:.1f} s; final loss {np.mean(hist[-50:]):.4e}")
+    held = list(range(5000, 5000 + a.heldout))
+    lin = sweeps_with(blob, held, a.n, dev, seed_mode="linear")
+    net = sweeps_with(blob, held, a.n, dev, seed_mode="net")
+    log(f"held-out sweeps at tol 1e-8: linear {[x[0] for x in lin]}, net {[x[0] for x in net]}")
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    with open(a.out, "wb") as f:
+        f.write(blob)
+    log(f"wrote {a.out}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -8,13 +8,16 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "sbi.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def _declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sbi_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(sbi_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -91,3 +94,23 @@ def test_product_path_has_no_cpu_fallback():
             if f.endswith(".py"):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in src.replace("the oracle", ""), f
+
+
+def test_net_interface_host_checks(lib):
+    from oracle import warmstart as ws
+    from paper_2310_19840_amd import _lib
+    assert lib.sbi_net_param_count() == ws.PARAM_COUNT == _lib.SBI_NET_PARAMS
+    assert lib.sbi_net_blob_bytes() == C.sizeof(_lib.sbi_net_header) + 4 * ws.PARAM_COUNT
+    assert C.sizeof(_lib.sbi_net_header) == 64
+    assert lib.sbi_net_trainer_bytes(0, 64, 64) == 0
+    assert lib.sbi_net_trainer_bytes(1, 64, 48) == 0      # nx must be a multiple of 64
+    assert lib.sbi_net_trainer_bytes(2, 32, 64) > 2 * 32 * 64 * 4 * 9 * 32
+    theta = (C.c_float * ws.PARAM_COUNT)()
+    tr = C.c_void_p()
+    assert lib.sbi_net_trainer_init(None, 1, 64, 64, theta, None, 0, None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_net_trainer_init(C.byref(tr), 1, 64, 64, theta, None, 0, None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_net_trainer_adam(None, C.c_float(1e-3)) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_net_load(None, None, 0) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_net_features(None, None, None, None, None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_net_infer(None, None, None, None, None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_last_correction(None, None, None) == _lib.SBI_ERR_INVALID_ARG
