@@ -82,7 +82,8 @@ typedef struct sbi_grid {
                               solve left (the first solve, and any solve after a
                               failed one, uses the linear guess).  SBI_SEED_NET: the
                               learned warm start of sbi_net.h (2D grids, weights from
-                              sbi_net_load).  SBI_SEED_USER: the w_seed field of
+                              sbi_net_load) for solves with no previous solve to start
+                              from, the SBI_SEED_PREV seed otherwise.  SBI_SEED_USER: the w_seed field of
                               sbi_vertical_velocity */
     int32_t max_sweeps;    /* iteration cap, 1..1000; default 64 */
     int32_t relax;         /* 1: under-relaxed sweeps when the crest makes plain sweeps

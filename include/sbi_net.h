@@ -8,6 +8,10 @@
  * periodic convolution network of local surface quantities:
  *   V0 = W_lin + out_scale[0] y[0],   phi_b0 = phi_b,lin + out_scale[1] y[1]
  * (with a flat bed the iteration has no bottom unknown and y[1] is unused).
+ * A context with seed SBI_SEED_NET uses it for solves that have no previous
+ * solve to start from (the first one, and any after a failed one); later
+ * solves start from the SBI_SEED_PREV seed, which carries the previous
+ * converged nonlinear parts and is the better start in time stepping.
  * The iteration itself, and its residual test, are unchanged: the seed affects
  * the number of sweeps, never the converged answer.  When a solve started from the learned
  * seed fails (divergence, non-finite values) it is redone from the linear
@@ -88,12 +92,12 @@ sbi_status sbi_net_infer(sbi_ctx* ctx, const float* feat, const void* wlin, void
 
 /*
  * Training labels: the nonlinear parts (V* - W_lin, phi_b - phi_b,lin) that the
- * last solve of an SBI_SEED_PREV context left (the parts its next solve starts
+ * last solve of an SBI_SEED_PREV or SBI_SEED_NET context left (the parts its next solve starts
  * from), in physical space.  phi_b is the iterate after the relaxed update of
  * the last sweep; with a flat bed dphib_out is zero.
  *   dv_out, dphib_out  device [batch][ny][nx], context precision
- * Errors: SBI_ERR_INVALID_ARG if the context's seed is not SBI_SEED_PREV or no
- * solve has succeeded yet.
+ * Errors: SBI_ERR_INVALID_ARG for other seeds, or when no solve has succeeded
+ * yet.
  */
 sbi_status sbi_last_correction(sbi_ctx* ctx, void* dv_out, void* dphib_out);
 

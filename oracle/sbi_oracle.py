@@ -93,6 +93,7 @@ class SolveInfo:
     status: int = OK
     omega: float = 1.0
     history: list = field(default_factory=list)
+    fallback: bool = False
 
 
 class Solver:
@@ -100,7 +101,7 @@ class Solver:
 
     def __init__(self, grid: Grid, depth, h_ref: float | None = None, order: int = 7,
                  mode: str = "iter", max_sweeps: int = 64, relax: bool = True,
-                 filter_beta=None, relaxation_zone=None, seed: str = "linear"):
+                 filter_beta=None, relaxation_zone=None, seed: str = "linear", net=None):
         self.g = grid
         depth = np.asarray(depth, dtype=np.float64).reshape(grid.ny, grid.nx)
         if np.any(~np.isfinite(depth)) or np.any(depth <= 0):
@@ -123,12 +124,21 @@ class Solver:
         self.om = np.sqrt(self.om2)
         self.filter_beta = filter_beta
         self.rz = relaxation_zone
-        # seed of the iteration: "linear" (initiation of Sec. 2.4) or "prev": the
-        # linear guess plus the nonlinear part left by this solver's previous
-        # solve, (V* - kT phi_hat, phi_b - S phi_hat) of that solve
-        if seed not in ("linear", "prev"):
-            raise ValueError("seed must be 'linear' or 'prev'")
+        # seed of the iteration:
+        #   "linear": the initiation of Sec. 2.4;
+        #   "prev":   the linear guess plus the nonlinear part left by this
+        #             solver's previous solve, (V* - kT phi_hat, phi_b - S phi_hat);
+        #   "net":    the learned warm start (oracle.warmstart) with net =
+        #             (theta, in_scale, out_scale): the linear guess plus the
+        #             network's corrections (nV, nB) when there is no previous
+        #             solve to start from, else the "prev" seed; a failed solve
+        #             from the network's seed is redone from the linear guess.
+        if seed not in ("linear", "prev", "net"):
+            raise ValueError("seed must be 'linear', 'prev' or 'net'")
+        if seed == "net" and net is None:
+            raise ValueError("seed 'net' needs the network (theta, in_scale, out_scale)")
         self.seed = seed
+        self.net = net
         self._prev = None
         # depth-validity criterion of Sec. 5: k |delta| < 2.4 at the largest wavenumber
         self.depth_warning = grid.kband * float(np.abs(self.delta).max()) > 2.4
@@ -252,31 +262,25 @@ class Solver:
             return 1.0
         return min(1.0, 2.0 / s)
 
-    def w_iter_hat(self, eta, ph, tol, seed_hat=None, seed_b_hat=None):
-        """Iteration on the summed operator from the linear guess, or from the
-        seed spectrum seed_hat of V (and the bottom-potential correction
-        seed_b_hat added to its linear guess)."""
+    def _net_corrections(self, eta, ph):
+        """Physical corrections (nV, nB) of the learned warm start at a state."""
+        from . import warmstart as ws
+        theta, in_scale, out_scale = self.net
+        f, _ = ws.features(self, eta, self.g.ifft(ph))
+        x = (f * np.asarray(in_scale, dtype=np.float32).astype(np.float64))[None]
+        y = ws.forward(theta, x, bf16_weights=True, bf16_acts=True)[0]
+        osc = np.asarray(out_scale, dtype=np.float32).astype(np.float64)
+        return osc[0] * y[..., 0], osc[1] * y[..., 1]
+
+    def _sweeps(self, eta, bV, bB, Vh, Bh, w, tol):
+        """Sweeps from (Vh, Bh) until the stopping rules end them: returns
+        (T_V(V) of the last sweep, the phi_b iterate after the relaxed update
+        of the last sweep, info)."""
         g = self.g
         info = SolveInfo()
-        bV, bB = self.forcing(eta, ph)
-        Vlin = g.k * self.T * ph
-        Blin = self.S * ph
-        Vh = Vlin if seed_hat is None else g.mask * seed_hat
-        Bh = Blin if seed_b_hat is None else Blin + g.mask * seed_b_hat
-        if seed_hat is None and self.seed == "prev" and self._prev is not None:
-            Vh = Vlin + self._prev[0]
-            Bh = Blin + self._prev[1]
-        w = self.relax_factor(eta)
         info.omega = w
         rmin = np.inf
         Vn = Vh
-
-        def keep(V, B):
-            # nonlinear part of this solve, the seed of the next one; the phi_b
-            # iterate kept is the one after the relaxed update of the last sweep
-            self._prev = (V - Vlin, B - Blin) if info.status >= 0 else None
-            return V, info
-
         for n in range(self.max_sweeps):
             Vn, Bn = self.apply_T(eta, bV, bB, Vh, Bh)
             Vnew = g.ifft(Vn)
@@ -287,21 +291,53 @@ class Solver:
                 info.status = ERR_NONFINITE
                 info.sweeps = n + 1
                 info.residual = float("nan")
-                return keep(Vn, Bn)
+                return Vn, Bn, info
             r = 0.0 if num == 0.0 else (num / den if den > 0 else np.inf)
             info.history.append(r)
             info.sweeps = n + 1
             info.residual = r
             if r <= tol:
-                return keep(Vn, Bh + w * (Bn - Bh))
+                return Vn, Bh + w * (Bn - Bh), info
             rmin = min(rmin, r)
             if r > 1e6 or (n >= 3 and r > 10.0 * rmin):
                 info.status = ERR_DIVERGED
-                return keep(Vn, Bn)
+                return Vn, Bn, info
             Vh = Vh + w * (Vn - Vh)
             Bh = Bh + w * (Bn - Bh)
         info.status = WARN_NOT_CONVERGED
-        return keep(Vn, Bh)
+        return Vn, Bh, info
+
+    def w_iter_hat(self, eta, ph, tol, seed_hat=None, seed_b_hat=None):
+        """Iteration on the summed operator from the solver's seed (see the
+        constructor), or from the seed spectrum seed_hat of V (and the
+        bottom-potential correction seed_b_hat added to its linear guess)."""
+        g = self.g
+        bV, bB = self.forcing(eta, ph)
+        Vlin = g.k * self.T * ph
+        Blin = self.S * ph
+        w = self.relax_factor(eta)
+        net = False
+        if seed_hat is not None:
+            Vh = g.mask * seed_hat
+            Bh = Blin if seed_b_hat is None else Blin + g.mask * seed_b_hat
+        elif self.seed == "net" and self._prev is None:
+            net = True
+            nV, nB = self._net_corrections(eta, ph)
+            Vh = Vlin + g.MF(nV)
+            Bh = Blin + g.MF(nB)
+        elif self.seed in ("prev", "net") and self._prev is not None:
+            Vh = Vlin + self._prev[0]
+            Bh = Blin + self._prev[1]
+        else:
+            Vh, Bh = Vlin, Blin
+        Vn, Bl, info = self._sweeps(eta, bV, bB, Vh, Bh, w, tol)
+        if net and info.status < 0:
+            # the linear guess is the fallback of the learned seed
+            Vn, Bl, info = self._sweeps(eta, bV, bB, Vlin, Blin, w, tol)
+            info.fallback = True
+        # nonlinear part of this solve: the seed of the next one
+        self._prev = (Vn - Vlin, Bl - Blin) if info.status >= 0 else None
+        return Vn, info
 
     # ------------------------------------------------------------------------
     def solve_hat(self, eta, ph, tol=1e-10, seed_hat=None, seed_b_hat=None):

@@ -677,7 +677,7 @@ static sbi_status stage_state_pass(sbi_ctx* c, bool need_eta, bool allow_prev = 
     if (c->grid.mode == SBI_MODE_SA) {
         b.cout(SRC_ACC2, CMP(C_VH));
     } else {
-        if (allow_prev && c->grid.seed == SBI_SEED_PREV && c->have_prev) {
+        if (allow_prev && (c->grid.seed == SBI_SEED_PREV || c->grid.seed == SBI_SEED_NET) && c->have_prev) {
             // previous-solve seed: linear guess + the last solve's nonlinear part
             b.term(b.cin(CMP(C_DV)), 2, 1.0, FN_ONE, 0, DV_NONE);
             if (c->vd) b.term(b.cin(CMP(C_DB)), 3, 1.0, FN_ONE, 0, DV_NONE);
@@ -1079,7 +1079,8 @@ static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool
                               const void* w_seed = nullptr) {
     SBI_TRY(hip_ok(launch_ctl_reset(c->ctl, c->batch, c->grid.max_sweeps + 2, c->stream)));
     c->st.launches += 1;
-    const bool net = c->grid.seed == SBI_SEED_NET && c->grid.mode == SBI_MODE_ITER;
+    // the learned seed starts solves that have no previous solve to start from
+    const bool net = c->grid.seed == SBI_SEED_NET && c->grid.mode == SBI_MODE_ITER && !c->have_prev;
     SBI_TRY(stage_state_pass(c, need_eta_grad || !eta_user || net));
     SBI_TRY(row_setup(c, eta_user));
     const void* eta_phys = eta_user ? eta_user : PHYS(P_ETA);
@@ -1105,7 +1106,7 @@ static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool
             }
         }
         *vh_buf = C_VP;
-        if (c->grid.seed == SBI_SEED_PREV) SBI_TRY(save_nonlinear_part(c));
+        if (c->grid.seed == SBI_SEED_PREV || c->grid.seed == SBI_SEED_NET) SBI_TRY(save_nonlinear_part(c));
     }
     return SBI_OK;
 }
@@ -1143,7 +1144,7 @@ extern "C" sbi_status sbi_vertical_velocity(sbi_ctx* c, const void* eta, const v
         if (c->depth_warn) warn = SBI_WARN_DEPTH_CRITERION;
     }
     // the learned seed needs the masked spectrum of eta for its gradient features
-    const bool net = c->grid.seed == SBI_SEED_NET && c->grid.mode == SBI_MODE_ITER;
+    const bool net = c->grid.seed == SBI_SEED_NET && c->grid.mode == SBI_MODE_ITER && !c->have_prev;
     c->fallbacks = 0;
     SBI_TRY(to_spectral(c, net ? eta : nullptr, phi_s, false));
     int vh = 0;
@@ -1465,7 +1466,9 @@ extern "C" sbi_status sbi_net_infer(sbi_ctx* c, const float* feat, const void* w
 
 extern "C" sbi_status sbi_last_correction(sbi_ctx* c, void* dv_out, void* dphib_out) {
     if (!c || !dv_out || !dphib_out) return SBI_ERR_INVALID_ARG;
-    if (c->grid.seed != SBI_SEED_PREV || c->grid.mode != SBI_MODE_ITER || !c->have_prev) return SBI_ERR_INVALID_ARG;
+    if ((c->grid.seed != SBI_SEED_PREV && c->grid.seed != SBI_SEED_NET) || c->grid.mode != SBI_MODE_ITER ||
+        !c->have_prev)
+        return SBI_ERR_INVALID_ARG;
     c->st = Stats();
     ColBuilder b(c->gd);
     b.term(b.cin(CMP(C_DV)), 0, 1.0, FN_ONE, 0, DV_NONE);

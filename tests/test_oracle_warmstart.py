@@ -170,3 +170,25 @@ def test_training_reduces_loss_on_a_smooth_target():
         l, g = ws.loss_and_grad(theta, x, t)
         theta, m, v = ws.adam_step(theta, m, v, g, s, lr=3e-3)
     assert l < 0.1 * l0
+
+
+def test_net_seed_is_used_only_without_history():
+    """seed 'net': the network starts the first solve; later solves start from
+    the previous-solve seed (same sweeps as seed 'prev' from then on)."""
+    g = Grid(32, 16, 8 * np.pi, 4 * np.pi)
+    X, Y = np.meshgrid(np.arange(32), np.arange(16))
+    depth = 1.0 - 0.3 * np.exp(-((X - 10) ** 2 + (Y - 8) ** 2) / 20.0)
+    eta = 0.06 * np.cos(2 * np.pi * (3 * X / 32 + Y / 16) + 0.3)
+    phi = 0.3 * np.sin(2 * np.pi * (2 * X / 32 - Y / 16) + 0.1)
+    theta = ws.init_params(2)
+    p = ws.unpack(theta.copy())
+    p["W4"] = np.random.default_rng(3).standard_normal((2, 32)) * 0.05
+    theta = ws.pack(p)
+    net = (theta, np.ones(8), (0.01, 0.01))
+    en, pn, sn_info = Solver(g, depth, h_ref=1.0, mode="iter", seed="net", net=net, max_sweeps=200).step(
+        eta, phi, 0.1, 2, tol=1e-10)
+    ep, pp, sp_info = Solver(g, depth, h_ref=1.0, mode="iter", seed="prev", max_sweeps=200).step(
+        eta, phi, 0.1, 2, tol=1e-10)
+    assert all(i.status == 0 and not i.fallback for i in sn_info)
+    assert sn_info[0].history[0] != sp_info[0].history[0]   # the first solve: net vs linear seed
+    assert np.abs(en - ep).max() < 1e-8 * np.abs(ep).max()
