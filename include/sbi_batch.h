@@ -1,0 +1,66 @@
+/*
+ * sbi_batch.h -- ensembles of independent sea states of uneven grid sizes,
+ * stepped together.
+ *
+ * Every member is an independent problem of sbi.h (its own grid, depth and
+ * state); nothing couples members.  Members with identical grids are grouped
+ * into one context whose kernels carry the members along their batch
+ * dimension; the groups run concurrently on streams forked from the caller's
+ * stream.  With SBI_BATCH_GRAPH the whole n-step call is captured once into a
+ * HIP graph and replayed: later calls with the same (dt, n, tol, state
+ * pointers) launch the instantiated graph.  With SBI_BATCH_AUTOTUNE the
+ * column-pass layout of each group (how a pass's products are split over
+ * workgroups) is chosen by timing the candidates on the device at init.
+ *
+ * Iterations run without host polling: each solve enqueues max_sweeps + 1
+ * sweep launches and a member's launches after the pass that decides its
+ * solve return at once; sweep statistics are accumulated on the device.  A
+ * learned seed (SBI_SEED_NET) that fails is reported, not redone.
+ *
+ * Conventions are those of sbi.h.
+ */
+#ifndef SBI_BATCH_H
+#define SBI_BATCH_H
+
+#include "sbi.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbi_batch sbi_batch;
+
+enum { SBI_BATCH_GRAPH = 1, SBI_BATCH_AUTOTUNE = 2 };
+
+/* Device workspace bytes for m members with grids[m]; 0 if a grid is invalid. */
+size_t sbi_batch_workspace_bytes(int32_t m, const sbi_grid* grids);
+
+/*
+ * m members: grids[m], depths[m] (host [ny][nx] arrays, depth > 0), one
+ * reference depth rule h_ref for all (<= 0: each member's max depth).
+ * workspace: caller-owned device memory of sbi_batch_workspace_bytes bytes.
+ * flags: SBI_BATCH_GRAPH | SBI_BATCH_AUTOTUNE.
+ * Returns SBI_WARN_DEPTH_CRITERION when any member exceeds the Sec. 5 limit.
+ */
+sbi_status sbi_batch_init(sbi_batch** out, int32_t m, const sbi_grid* grids, const double* const* depths,
+                          double h_ref, void* workspace, size_t ws_bytes, void* hip_stream, int32_t flags);
+
+/*
+ * Advance every member by n steps of dt.  states[m]: each member's device
+ * eta / phi_s arrays [ny][nx] (its grid's precision), updated in place, and
+ * its time t (advanced by n dt).  info: host [m] per-member statistics, or
+ * NULL.  Returns the worst member status (errors < 0 take precedence).
+ */
+sbi_status sbi_batch_step(sbi_batch* b, sbi_state* states, double dt, int32_t n, double tol, sbi_step_info* info);
+
+/* Number of member groups and, per group (g < groups), its member count and
+   the column-pass split the autotuner chose (0: none). */
+int32_t sbi_batch_groups(const sbi_batch* b, int32_t* members_out, int32_t* split_out, int32_t n);
+
+sbi_status sbi_batch_destroy(sbi_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBI_BATCH_H */

@@ -288,3 +288,78 @@ class NetTrainer:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Members of uneven grids stepped together (include/sbi_batch.h).
+
+    members: list of dicts with keys nx, ny, lx, ly, depth and any make_grid
+    option (precision, mode, seed, max_sweeps, ...)."""
+
+    def __init__(self, members, h_ref=-1.0, device=None, stream=None, graph=True, autotune=False):
+        import torch
+
+        self.torch = torch
+        self.lib = _lib.load()
+        self.m = len(members)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        grids = (_lib.sbi_grid * self.m)()
+        self.shapes, self.dtypes = [], []
+        deps = []
+        for i, mb in enumerate(members):
+            opts = {k: v for k, v in mb.items() if k not in ("nx", "ny", "lx", "ly", "depth")}
+            grids[i] = make_grid(mb["nx"], mb["ny"], mb["lx"], mb.get("ly", 1.0), **opts)
+            self.shapes.append((int(mb["ny"]), int(mb["nx"])))
+            self.dtypes.append(torch.float64 if grids[i].precision == _lib.SBI_FP64 else torch.float32)
+            d = np.ascontiguousarray(np.asarray(mb["depth"], dtype=np.float64).reshape(self.shapes[-1]))
+            deps.append(d)
+        self._deps = deps
+        dptr = (C.POINTER(C.c_double) * self.m)(*[d.ctypes.data_as(C.POINTER(C.c_double)) for d in deps])
+        nbytes = int(self.lib.sbi_batch_workspace_bytes(self.m, grids))
+        if nbytes == 0:
+            raise SBIError(_lib.SBI_ERR_INVALID_ARG, "sbi_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        flags = (_lib.SBI_BATCH_GRAPH if graph else 0) | (_lib.SBI_BATCH_AUTOTUNE if autotune else 0)
+        b = C.c_void_p()
+        st = self.lib.sbi_batch_init(C.byref(b), self.m, grids, dptr, float(h_ref),
+                                     C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                     C.c_void_p(self.stream.cuda_stream), flags)
+        if st < 0:
+            raise SBIError(st, "sbi_batch_init")
+        self.init_status = st
+        self.b = b
+
+    def step(self, etas, phis, dt, n, tol=1e-10, t=None):
+        states = (_lib.sbi_state * self.m)()
+        for i in range(self.m):
+            for x, name in ((etas[i], "eta"), (phis[i], "phi_s")):
+                if (x.dtype != self.dtypes[i] or x.device != self.device or not x.is_contiguous()
+                        or x.numel() != self.shapes[i][0] * self.shapes[i][1]):
+                    raise TypeError(f"member {i}: {name} must be a contiguous {self.dtypes[i]} tensor of "
+                                    f"{self.shapes[i]} on {self.device}")
+            states[i] = _lib.sbi_state(C.c_void_p(etas[i].data_ptr()), C.c_void_p(phis[i].data_ptr()),
+                                       0.0 if t is None else float(t[i]))
+        info = (_lib.sbi_step_info * self.m)()
+        st = self.lib.sbi_batch_step(self.b, states, float(dt), int(n), float(tol), info)
+        if st < 0:
+            raise SBIError(st, "sbi_batch_step")
+        return st, [dict(t=states[i].t, solves=info[i].solves, sweeps_total=info[i].sweeps_total,
+                         sweeps_max=info[i].sweeps_max, max_residual=info[i].max_residual) for i in range(self.m)]
+
+    def groups(self):
+        mem = (C.c_int32 * 64)()
+        spl = (C.c_int32 * 64)()
+        k = self.lib.sbi_batch_groups(self.b, mem, spl, 64)
+        return [(mem[i], spl[i]) for i in range(min(k, 64))]
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.lib.sbi_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,4 +1,4 @@
-"""ctypes declarations of the C interface in include/sbi.h and include/sbi_net.h (libsbi.so)."""
+"""ctypes declarations of the C interface in include/sbi.h, sbi_net.h and sbi_batch.h (libsbi.so)."""
 from __future__ import annotations
 
 import ctypes as C
@@ -84,7 +84,18 @@ SIGNATURES = {
     "sbi_net_trainer_adam": (C.c_int, [C.c_void_p, C.c_float]),
     "sbi_net_trainer_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
     "sbi_net_trainer_destroy": (C.c_int, [C.c_void_p]),
+    # ensembles of uneven grids (sbi_batch.h)
+    "sbi_batch_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(sbi_grid)]),
+    "sbi_batch_init": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(sbi_grid),
+                                 C.POINTER(C.POINTER(C.c_double)), C.c_double, C.c_void_p, C.c_size_t, C.c_void_p,
+                                 C.c_int32]),
+    "sbi_batch_step": (C.c_int, [C.c_void_p, C.POINTER(sbi_state), C.c_double, C.c_int32, C.c_double,
+                                 C.POINTER(sbi_step_info)]),
+    "sbi_batch_groups": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]),
+    "sbi_batch_destroy": (C.c_int, [C.c_void_p]),
 }
+
+SBI_BATCH_GRAPH, SBI_BATCH_AUTOTUNE = 1, 2
 
 SBI_NET_PARAMS = 12706
 

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/sbi.h"
+#include "../../include/sbi_batch.h"
 #include "../../include/sbi_net.h"
 #include "sbi_kernels.hpp"
 #include "sbi_net.hpp"
@@ -870,6 +871,14 @@ static sbi_status iterate(sbi_ctx* c, const void* eta_phys, double tol) {
     return SBI_OK;
 }
 
+// iteration without host polling (capturable): all max_sweeps + 1 sweep
+// launches are enqueued; after the column pass that decides a member's solve,
+// that member's later launches return at once
+static sbi_status iterate_fixed(sbi_ctx* c, const void* eta_phys, double tol) {
+    for (int n = 0; n <= c->grid.max_sweeps; ++n) SBI_TRY(launch_sweep(c, eta_phys, n, tol));
+    return SBI_OK;
+}
+
 static sbi_status run_sa(sbi_ctx* c, const void* eta_phys) {
     const bool two_d = c->grid.ny > 1;
     const int L = c->grid.order;
@@ -1075,8 +1084,10 @@ static sbi_status save_nonlinear_part(sbi_ctx* c) {
     return SBI_OK;
 }
 
+// capture_safe: no host synchronisation (fixed sweep launches, no fallback
+// from a failed learned seed)
 static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool need_eta_grad, int* vh_buf,
-                              const void* w_seed = nullptr) {
+                              const void* w_seed = nullptr, bool capture_safe = false) {
     SBI_TRY(hip_ok(launch_ctl_reset(c->ctl, c->batch, c->grid.max_sweeps + 2, c->stream)));
     c->st.launches += 1;
     // the learned seed starts solves that have no previous solve to start from
@@ -1091,8 +1102,12 @@ static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool
         SBI_TRY(col_forcing(c));
         if (net) SBI_TRY(net_seed(c, eta_phys));
         if (w_seed) SBI_TRY(seed_from_physical(c, w_seed));
-        SBI_TRY(iterate(c, eta_phys, tol));
-        if (net) {
+        if (capture_safe) {
+            SBI_TRY(iterate_fixed(c, eta_phys, tol));
+        } else {
+            SBI_TRY(iterate(c, eta_phys, tol));
+        }
+        if (net && !capture_safe) {
             // the linear guess is the fallback when the learned seed fails
             bool failed = false;
             for (int b = 0; b < c->batch; ++b) failed |= c->head[b].status < 0 || c->head[b].nonfinite;
@@ -1490,5 +1505,338 @@ extern "C" sbi_status sbi_last_correction(sbi_ctx* c, void* dv_out, void* dphib_
     SBI_TRY(hip_ok(launch_row_inv(c->fp64, ip, c->batch, tw_of(c), c->stream)));
     if (!c->vd) SBI_TRY(hip_ok(launch_fill_zero(dphib_out, (size_t)c->gd.s_phys * c->rsz * c->batch, c->stream)));
     SBI_HIP(hipStreamSynchronize(c->stream));
+    return SBI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ensembles of uneven grids (sbi_batch.h)
+// ---------------------------------------------------------------------------
+namespace {
+
+bool same_grid(const sbi_grid& a, const sbi_grid& b) {
+    return a.nx == b.nx && a.ny == b.ny && a.lx == b.lx && (a.ny == 1 || a.ly == b.ly) && a.order == b.order &&
+           a.dealias == b.dealias && a.precision == b.precision && a.mode == b.mode && a.seed == b.seed &&
+           a.max_sweeps == b.max_sweeps && a.relax == b.relax && a.filter_beta1 == b.filter_beta1 &&
+           a.filter_beta2 == b.filter_beta2;
+}
+
+// members grouped by identical grids, in order of first appearance
+std::vector<std::vector<int>> group_members(int m, const sbi_grid* grids) {
+    std::vector<std::vector<int>> out;
+    for (int i = 0; i < m; ++i) {
+        bool placed = false;
+        for (auto& g : out)
+            if (same_grid(grids[g[0]], grids[i])) {
+                g.push_back(i);
+                placed = true;
+                break;
+            }
+        if (!placed) out.push_back({i});
+    }
+    return out;
+}
+
+size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t staging_bytes(const sbi_grid& g, int count) {
+    const size_t rsz = g.precision == SBI_FP64 ? 8 : 4;
+    return 2 * al256((size_t)g.nx * g.ny * rsz * count);
+}
+
+}  // namespace
+
+struct sbi_batch {
+    struct Group {
+        sbi_ctx* c = nullptr;
+        std::vector<int> members;
+        hipStream_t s = nullptr;
+        hipEvent_t done = nullptr;
+        char* st_eta = nullptr;  // contiguous [count][ny][nx] staging of the members' states
+        char* st_phi = nullptr;
+        size_t field_bytes = 0;  // one member's field
+    };
+    int m = 0;
+    int flags = 0;
+    hipStream_t stream = nullptr;  // caller's stream
+    hipStream_t cap = nullptr;     // the batch's own stream: work is forked from and joined to it
+    hipEvent_t fork = nullptr;
+    hipEvent_t in = nullptr, out = nullptr;  // caller's stream -> cap -> caller's stream
+    std::vector<Group> g;
+    hipGraphExec_t exec = nullptr;
+    // key of the instantiated graph
+    double key_dt = 0.0, key_tol = 0.0;
+    int key_n = -1;
+    std::vector<const void*> key_ptrs;
+    std::vector<int> key_prev;
+};
+
+static void batch_free(sbi_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    for (auto& gr : b->g) {
+        if (gr.c) sbi_destroy(gr.c);
+        if (gr.done) (void)hipEventDestroy(gr.done);
+        if (gr.s) (void)hipStreamDestroy(gr.s);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->in) (void)hipEventDestroy(b->in);
+    if (b->out) (void)hipEventDestroy(b->out);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+extern "C" size_t sbi_batch_workspace_bytes(int32_t m, const sbi_grid* grids) {
+    if (m < 1 || !grids) return 0;
+    for (int i = 0; i < m; ++i)
+        if (!grid_valid(&grids[i])) return 0;
+    size_t total = 0;
+    for (auto& gm : group_members(m, grids)) {
+        const sbi_grid& g = grids[gm[0]];
+        total += al256(layout(&g, (int)gm.size()).total) + staging_bytes(g, (int)gm.size());
+    }
+    return total;
+}
+
+// times a few sweep launches of the group for each column-pass split and
+// keeps the fastest (buffers hold zeros after init: the work is the same)
+static sbi_status autotune_split(sbi_ctx* c) {
+    const int cand[] = {0, 1024, 2048, 4096};
+    hipEvent_t e0, e1;
+    SBI_HIP(hipEventCreate(&e0));
+    SBI_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int pick = 0;
+    for (int cd : cand) {
+        c->group_target = cd;
+        sbi_status st = hip_ok(launch_ctl_reset(c->ctl, c->batch, c->grid.max_sweeps + 2, c->stream));
+        for (int rep = 0; rep < 2 && st == SBI_OK; ++rep) st = launch_sweep(c, PHYS(P_ETA), 0, 1e-30);  // warm
+        if (st == SBI_OK) st = hip_ok(hipEventRecord(e0, c->stream));
+        for (int rep = 0; rep < 4 && st == SBI_OK; ++rep) st = launch_sweep(c, PHYS(P_ETA), 0, 1e-30);
+        if (st == SBI_OK) st = hip_ok(hipEventRecord(e1, c->stream));
+        if (st == SBI_OK) st = hip_ok(hipEventSynchronize(e1));
+        float ms = 0.f;
+        if (st == SBI_OK) st = hip_ok(hipEventElapsedTime(&ms, e0, e1));
+        if (st != SBI_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return st;
+        }
+        if (ms < best) {
+            best = ms;
+            pick = cd;
+        }
+    }
+    c->group_target = pick;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return hip_ok(launch_ctl_reset(c->ctl, c->batch, c->grid.max_sweeps + 2, c->stream));
+}
+
+extern "C" sbi_status sbi_batch_init(sbi_batch** out, int32_t m, const sbi_grid* grids, const double* const* depths,
+                                     double h_ref, void* workspace, size_t ws_bytes, void* hip_stream,
+                                     int32_t flags) {
+    if (!out || m < 1 || !grids || !depths || !workspace) return SBI_ERR_INVALID_ARG;
+    *out = nullptr;
+    for (int i = 0; i < m; ++i)
+        if (!grid_valid(&grids[i]) || !depths[i]) return SBI_ERR_INVALID_ARG;
+    const size_t need = sbi_batch_workspace_bytes(m, grids);
+    if (ws_bytes < need) return SBI_ERR_WORKSPACE;
+    auto* b = new sbi_batch();
+    b->m = m;
+    b->flags = flags;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->out, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        batch_free(b);
+        return SBI_ERR_HIP;
+    }
+    char* p = static_cast<char*>(workspace);
+    sbi_status warn = SBI_OK;
+    for (auto& gm : group_members(m, grids)) {
+        sbi_batch::Group gr;
+        gr.members = gm;
+        const sbi_grid& g = grids[gm[0]];
+        const int count = (int)gm.size();
+        const size_t npt = (size_t)g.nx * g.ny;
+        gr.field_bytes = npt * (g.precision == SBI_FP64 ? 8 : 4);
+        if (hipStreamCreateWithFlags(&gr.s, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&gr.done, hipEventDisableTiming) != hipSuccess) {
+            b->g.push_back(gr);
+            batch_free(b);
+            return SBI_ERR_HIP;
+        }
+        std::vector<double> dep(npt * count);
+        for (int k = 0; k < count; ++k) std::memcpy(&dep[npt * k], depths[gm[k]], sizeof(double) * npt);
+        const size_t wsb = al256(layout(&g, count).total);
+        sbi_status st = sbi_init(&gr.c, &g, count, dep.data(), h_ref, p, wsb, gr.s);
+        p += wsb;
+        gr.st_eta = p;
+        gr.st_phi = p + al256(gr.field_bytes * count);
+        p += staging_bytes(g, count);
+        b->g.push_back(gr);
+        if (st < 0) {
+            batch_free(b);
+            return st;
+        }
+        if (st == SBI_WARN_DEPTH_CRITERION) warn = st;
+        if ((flags & SBI_BATCH_AUTOTUNE) && g.mode == SBI_MODE_ITER) {
+            st = autotune_split(b->g.back().c);
+            if (st < 0) {
+                batch_free(b);
+                return st;
+            }
+        }
+    }
+    *out = b;
+    return warn;
+}
+
+// enqueue n steps of every group on streams forked from b->cap and joined
+// back to it (capture-safe: no host synchronisation)
+static sbi_status batch_enqueue(sbi_batch* b, sbi_state* states, double dt, int n, double tol) {
+    SBI_HIP(hipEventRecord(b->fork, b->cap));
+    for (auto& gr : b->g) {
+        sbi_ctx* c = gr.c;
+        SBI_HIP(hipStreamWaitEvent(gr.s, b->fork, 0));
+        SBI_TRY(hip_ok(launch_ctl_acc_reset(c->ctl, c->batch, gr.s)));
+        for (size_t k = 0; k < gr.members.size(); ++k) {
+            const sbi_state& s = states[gr.members[k]];
+            SBI_HIP(hipMemcpyAsync(gr.st_eta + k * gr.field_bytes, s.eta, gr.field_bytes, hipMemcpyDeviceToDevice,
+                                   gr.s));
+            SBI_HIP(hipMemcpyAsync(gr.st_phi + k * gr.field_bytes, s.phi_s, gr.field_bytes, hipMemcpyDeviceToDevice,
+                                   gr.s));
+        }
+        SBI_TRY(to_spectral(c, gr.st_eta, gr.st_phi, true));
+        double t = states[gr.members[0]].t;
+        for (int step = 0; step < n; ++step) {
+            for (int stage = 0; stage < 4; ++stage) {
+                int vh = 0;
+                SBI_TRY(solve_stage(c, nullptr, tol, true, &vh, nullptr, true));
+                SBI_TRY(stage_update(c, stage, dt, vh));
+            }
+            t += dt;
+            if (c->relax_on) SBI_TRY(relax_zone(c, t));
+        }
+        SBI_TRY(to_physical(c, gr.st_eta, gr.st_phi));
+        for (size_t k = 0; k < gr.members.size(); ++k) {
+            const sbi_state& s = states[gr.members[k]];
+            SBI_HIP(hipMemcpyAsync(s.eta, gr.st_eta + k * gr.field_bytes, gr.field_bytes, hipMemcpyDeviceToDevice,
+                                   gr.s));
+            SBI_HIP(hipMemcpyAsync(s.phi_s, gr.st_phi + k * gr.field_bytes, gr.field_bytes, hipMemcpyDeviceToDevice,
+                                   gr.s));
+        }
+        SBI_HIP(hipEventRecord(gr.done, gr.s));
+        SBI_HIP(hipStreamWaitEvent(b->cap, gr.done, 0));
+    }
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_batch_step(sbi_batch* b, sbi_state* states, double dt, int32_t n, double tol,
+                                     sbi_step_info* info) {
+    if (!b || !states || n < 0 || !std::isfinite(dt)) return SBI_ERR_INVALID_ARG;
+    for (int i = 0; i < b->m; ++i)
+        if (!states[i].eta || !states[i].phi_s) return SBI_ERR_INVALID_ARG;
+    for (auto& gr : b->g) {
+        if (gr.c->grid.mode == SBI_MODE_ITER && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
+        if (gr.c->grid.seed == SBI_SEED_NET && !gr.c->net_loaded) return SBI_ERR_INVALID_ARG;
+        gr.c->st = Stats();
+        gr.c->fallbacks = 0;
+    }
+    // the caller's work before this call happens first
+    SBI_HIP(hipEventRecord(b->in, b->stream));
+    SBI_HIP(hipStreamWaitEvent(b->cap, b->in, 0));
+    if (b->flags & SBI_BATCH_GRAPH) {
+        std::vector<const void*> ptrs;
+        std::vector<int> prev;
+        for (int i = 0; i < b->m; ++i) {
+            ptrs.push_back(states[i].eta);
+            ptrs.push_back(states[i].phi_s);
+        }
+        for (auto& gr : b->g) prev.push_back(gr.c->have_prev ? 1 : 0);
+        const bool hit = b->exec && b->key_dt == dt && b->key_tol == tol && b->key_n == n && b->key_ptrs == ptrs &&
+                         b->key_prev == prev;
+        if (!hit) {
+            if (b->exec) {
+                (void)hipGraphExecDestroy(b->exec);
+                b->exec = nullptr;
+            }
+            std::vector<int> saved_prof;
+            for (auto& gr : b->g) {
+                saved_prof.push_back(gr.c->prof.on ? 1 : 0);
+                gr.c->prof.on = false;  // no timing events inside a capture
+            }
+            SBI_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+            sbi_status st = batch_enqueue(b, states, dt, n, tol);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(b->cap, &graph);
+            for (size_t k = 0; k < b->g.size(); ++k) b->g[k].c->prof.on = saved_prof[k] != 0;
+            if (st < 0) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return SBI_ERR_HIP;
+            e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                b->exec = nullptr;
+                return SBI_ERR_HIP;
+            }
+            b->key_dt = dt;
+            b->key_tol = tol;
+            b->key_n = n;
+            b->key_ptrs = ptrs;
+            b->key_prev = prev;
+        }
+        SBI_HIP(hipGraphLaunch(b->exec, b->cap));
+    } else {
+        SBI_TRY(batch_enqueue(b, states, dt, n, tol));
+    }
+    SBI_HIP(hipEventRecord(b->out, b->cap));
+    SBI_HIP(hipStreamWaitEvent(b->stream, b->out, 0));
+    SBI_HIP(hipStreamSynchronize(b->cap));
+    sbi_status worst = SBI_OK;
+    for (auto& gr : b->g) {
+        sbi_ctx* c = gr.c;
+        SBI_HIP(hipMemcpy(c->head, c->ctl, sizeof(Ctl) * c->batch, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < gr.members.size(); ++k) {
+            const Ctl& h = c->head[k];
+            const bool iter = c->grid.mode == SBI_MODE_ITER;
+            int st = iter ? h.acc_worst : 0;
+            if (h.nonfinite) st = SBI_ERR_NONFINITE;
+            const int mi = gr.members[k];
+            states[mi].t += n * dt;
+            if (info) {
+                sbi_step_info& si = info[mi];
+                si = sbi_step_info{};
+                si.solves = iter ? h.acc_solves : 4ll * n;
+                si.sweeps_total = iter ? h.acc_sweeps : 0;
+                si.sweeps_max = iter ? h.acc_sweeps_max : 0;
+                si.max_residual = iter ? h.acc_residual_max : 0.0;
+            }
+            if (st < 0) worst = (worst < 0 && worst < st) ? worst : (sbi_status)st;
+            else if (worst >= 0 && st > worst) worst = (sbi_status)st;
+        }
+        if (worst < 0) c->have_prev = false;
+    }
+    return worst;
+}
+
+extern "C" int32_t sbi_batch_groups(const sbi_batch* b, int32_t* members_out, int32_t* split_out, int32_t n) {
+    if (!b) return 0;
+    const int ng = (int)b->g.size();
+    for (int i = 0; i < ng && i < n; ++i) {
+        if (members_out) members_out[i] = (int32_t)b->g[i].members.size();
+        if (split_out) split_out[i] = b->g[i].c->group_target;
+    }
+    return ng;
+}
+
+extern "C" sbi_status sbi_batch_destroy(sbi_batch* b) {
+    if (!b) return SBI_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(b->cap);
+    for (auto& gr : b->g) (void)hipStreamSynchronize(gr.s);
+    batch_free(b);
     return SBI_OK;
 }

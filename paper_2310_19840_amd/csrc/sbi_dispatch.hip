@@ -33,6 +33,22 @@ __global__ void k_ctl_reset(Ctl* ctl, int slots) {
     }
 }
 
+__global__ void k_ctl_acc_reset(Ctl* ctl) {
+    Ctl* c = ctl + blockIdx.x;
+    if (threadIdx.x == 0) {
+        c->acc_solves = 0;
+        c->acc_sweeps = 0;
+        c->acc_sweeps_max = 0;
+        c->acc_worst = 0;
+        c->acc_residual_max = 0.0;
+    }
+}
+
+hipError_t launch_ctl_acc_reset(Ctl* ctl, int batch, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_acc_reset, dim3(batch), dim3(64), 0, s, ctl);
+    return hipGetLastError();
+}
+
 __global__ void k_fill_zero(uint4* p, size_t n16) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
         p[i] = make_uint4(0u, 0u, 0u, 0u);

@@ -48,6 +48,11 @@ struct Ctl {
     unsigned long long eta_max;              // order-preserving bits of max(eta)
     unsigned long long eta_min;              // order-preserving bits of min(eta)
     CtlSlots* slots;                         // this member's residual slots
+    // totals over the solves since the last accumulator reset, written by the
+    // workgroup that decides each solve (host-free statistics of captured runs)
+    long long acc_solves, acc_sweeps;
+    int acc_sweeps_max, acc_worst;
+    double acc_residual_max;
 };
 
 struct GridDev {

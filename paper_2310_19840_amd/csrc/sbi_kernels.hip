@@ -716,10 +716,17 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         const int dec = sweep_decision(ctl, p.sweep, p.max_sweeps, p.tol, &r, &rmin);
         if (dec) {
             if (blockIdx.x == 0 && grp == 0 && t == 0) {
-                ctl->status = dec - 100;
+                const int st = dec - 100;
+                ctl->status = st;
                 ctl->sweeps = p.sweep;
                 ctl->residual = r;
                 ctl->done = 1;
+                ctl->acc_solves += 1;
+                ctl->acc_sweeps += p.sweep;
+                ctl->acc_sweeps_max = max(ctl->acc_sweeps_max, p.sweep);
+                ctl->acc_residual_max = fmax(ctl->acc_residual_max, r);
+                const int w = ctl->acc_worst;
+                if (st < 0 ? (w >= 0 || st < w) : (w >= 0 && st > w)) ctl->acc_worst = st;
             }
             return;
         }

@@ -169,5 +169,6 @@ hipError_t launch_rk(int fp64, const RkParams& p, int batch, hipStream_t s);
 hipError_t launch_diag(int fp64, const DiagParams& p, int batch, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* ctl, int batch, int slots, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
+hipError_t launch_ctl_acc_reset(Ctl* ctl, int batch, hipStream_t s);
 
 }  // namespace sbi

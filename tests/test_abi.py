@@ -114,3 +114,20 @@ def test_net_interface_host_checks(lib):
     assert lib.sbi_net_features(None, None, None, None, None) == _lib.SBI_ERR_INVALID_ARG
     assert lib.sbi_net_infer(None, None, None, None, None) == _lib.SBI_ERR_INVALID_ARG
     assert lib.sbi_last_correction(None, None, None) == _lib.SBI_ERR_INVALID_ARG
+
+
+def test_batch_interface_host_checks(lib):
+    from paper_2310_19840_amd import _lib, make_grid
+    g = (_lib.sbi_grid * 3)(make_grid(64, 64, 10.0, 10.0), make_grid(128, 64, 20.0, 10.0),
+                            make_grid(64, 64, 10.0, 10.0))
+    one = lib.sbi_batch_workspace_bytes(1, g)
+    assert lib.sbi_batch_workspace_bytes(3, g) > one > 0
+    assert lib.sbi_batch_workspace_bytes(0, g) == 0
+    bad = (_lib.sbi_grid * 1)(make_grid(64, 64, 10.0, 10.0))
+    bad[0].nx = 100
+    assert lib.sbi_batch_workspace_bytes(1, bad) == 0
+    b = C.c_void_p()
+    assert lib.sbi_batch_init(C.byref(b), 1, g, None, -1.0, None, 0, None, 0) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_batch_step(None, None, 0.1, 1, 1e-8, None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_batch_destroy(None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_batch_groups(None, None, None, 0) == 0
