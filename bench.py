@@ -8,10 +8,17 @@ with four W solves iterated to a relative residual of 1e-8 in FP64.  Metric:
 grid-point RK4 steps per second (points x steps / wall seconds), inputs
 resident in HBM before the timed region.
 
-Prints ONE JSON line.  `roofline` is for the dominant kernel, its algorithmic
-bytes per launch divided by its average launch time from HIP events recorded
-on the library's stream during the timed region.  `cpu_baseline` times the
-FP64 oracle on a bounded sample of the same workload.
+`value` is the plain form (one realisation, linear-guess seed, eager launches
+with the kernel profiler on).  `forms` adds, at the same tolerance, two
+realisations stepped in one captured HIP graph with the previous-solve seed
+("batched+prev") and with the learned warm start ("batched+learned"), the
+plain step in FP32 (tolerance 1e-6, the FP32 floor), and the ragged C4
+ensemble (96 members, SA mode, FP32) in one graph.
+
+Prints ONE JSON line.  `roofline` is for the dominant kernel of the plain
+form, its algorithmic bytes per launch divided by its average launch time from
+HIP events recorded on the library's stream during the timed region.
+`cpu_baseline` times the FP64 oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -101,6 +108,136 @@ def cpu_baseline(n_sample: int = 256, max_sweeps: int = 200):
     }
 
 
+def c5_members(seeds, n):
+    from sbi_inputs import config_c5
+    return [config_c5(seed=sd, n=n) for sd in seeds]
+
+
+def dominant(prof, sweeps_total, solves, g, vd, csz, rsz):
+    """Dominant sweep kernel and its algorithmic bandwidth from the live profile."""
+    Mx = int(math.ceil(0.5 * g.nx / 2 - 1e-9)) - 1
+    My = int(math.ceil(0.5 * g.ny / 2 - 1e-9)) - 1
+    Kx, Ky = Mx + 1, 2 * My + 1
+    cand = {}
+    for kind in ("row_sweep", "col_sweep"):
+        tot_ms, cnt = prof.get(kind, (0.0, 0))
+        if tot_ms <= 0:
+            continue
+        working = sweeps_total + (solves if kind == "row_sweep" else 0)
+        b = algorithmic_bytes(kind, g.nx, g.ny, Kx, Ky, csz, rsz, vd, 6, g.ny > 1)
+        avg_s = tot_ms * 1e-3 / max(working, 1)
+        cand[kind] = (tot_ms, b, avg_s, cnt, working)
+    dom = max(cand, key=lambda k: cand[k][0])
+    tot_ms, b, avg_s, cnt, working = cand[dom]
+    achieved = b / avg_s / 1e9
+    return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": dom, "bytes_per_launch": b,
+                 "avg_launch_us": round(avg_s * 1e6, 2), "launches_working": working, "launches_total": cnt}
+
+
+def run_plain(args, dev, precision, tol):
+    """One C5 member, linear-guess seed, eager steps with the kernel profiler on."""
+    import numpy as np
+    import torch
+
+    from paper_2310_19840_amd import Solver
+
+    cfg = c5_members([0], args.n)[0]
+    g = cfg["grid"]
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="iter", precision=precision,
+               max_sweeps=args.max_sweeps)
+    eta = torch.tensor(cfg["eta"][None], dtype=dtype, device=dev)
+    phi = torch.tensor(cfg["phi"][None], dtype=dtype, device=dev)
+    dt = cfg["dt"]
+    if args.warmup > 0:
+        s.step(eta, phi, dt, args.warmup, tol=tol)
+    torch.cuda.synchronize()
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = s.step(eta, phi, dt, args.steps, tol=tol)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = s.profile_read()
+    s.profile(False)
+    solves = max(info["solves"], 1)
+    vd = bool(np.any(cfg["depth"] != cfg["depth"].max()))
+    csz, rsz = (16, 8) if precision == "fp64" else (8, 4)
+    dom, roof = dominant(prof, info["sweeps_total"], solves, g, vd, csz, rsz)
+    return dict(value=g.nx * g.ny * args.steps / el, ms_per_step=1e3 * el / max(args.steps, 1), status=st,
+                sweeps_mean=info["sweeps_total"] / solves, sweeps_max=info["sweeps_max"],
+                max_residual=info["max_residual"], roofline=roof, dominant=dom,
+                kernel_ms={k: round(v[0], 3) for k, v in prof.items() if v[1] > 0}, cfg=cfg)
+
+
+def run_batched(args, dev, seed_mode, members):
+    """B C5 realisations in one captured graph, previous-solve or learned seed."""
+    import torch
+
+    from paper_2310_19840_amd import Batch
+
+    cfgs = c5_members(range(members), args.n)
+    blob = None
+    if seed_mode == "net":
+        path = os.path.join(ROOT, "paper_2310_19840_amd", "weights", "warmstart_c5.sbiw")
+        if not os.path.exists(path):
+            return dict(skipped=f"no trained weights at {os.path.relpath(path, ROOT)}")
+        blob = open(path, "rb").read()
+    mem = [dict(nx=c["grid"].nx, ny=c["grid"].ny, lx=c["grid"].lx, ly=c["grid"].ly, depth=c["depth"],
+                precision="fp64", mode="iter", seed=seed_mode, max_sweeps=args.batch_sweeps) for c in cfgs]
+    b = Batch(mem, device=dev, graph=True)
+    if blob is not None:
+        b.net_load(blob)
+    etas = [torch.tensor(c["eta"], dtype=torch.float64, device=dev) for c in cfgs]
+    phis = [torch.tensor(c["phi"], dtype=torch.float64, device=dev) for c in cfgs]
+    dt = cfgs[0]["dt"]
+    tol = cfgs[0]["tol"]
+    first = []
+    # warm-up: the first call starts from no history (captured once); the
+    # second captures the steady graph that the timed call replays
+    _, i1 = b.step(etas, phis, dt, 1, tol=tol)
+    first = [x["sweeps_total"] / max(x["solves"], 1) for x in i1]
+    b.step(etas, phis, dt, args.steps, tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, info = b.step(etas, phis, dt, args.steps, tol=tol)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    npts = sum(c["grid"].nx * c["grid"].ny for c in cfgs)
+    solves = sum(x["solves"] for x in info)
+    return dict(value=npts * args.steps / el, ms_per_step=1e3 * el / max(args.steps, 1), status=st, members=members,
+                sweeps_mean=sum(x["sweeps_total"] for x in info) / max(solves, 1),
+                sweeps_max=max(x["sweeps_max"] for x in info),
+                max_residual=max(x["max_residual"] for x in info),
+                first_step_sweeps_mean=sum(first) / len(first))
+
+
+def run_c4(args, dev):
+    """The ragged ensemble (32 x 128^2 + 48 x 256^2 + 16 x 512^2), SA mode, FP32, one graph."""
+    import torch
+
+    from paper_2310_19840_amd import Batch
+    from sbi_inputs import config_c4_member
+
+    cfgs = [config_c4_member(m) for m in range(96)]
+    mem = [dict(nx=c["grid"].nx, ny=c["grid"].ny, lx=c["grid"].lx, ly=c["grid"].ly, depth=c["depth"],
+                precision="fp32", mode="sa") for c in cfgs]
+    b = Batch(mem, device=dev, graph=True)
+    etas = [torch.tensor(c["eta"], dtype=torch.float32, device=dev) for c in cfgs]
+    phis = [torch.tensor(c["phi"], dtype=torch.float32, device=dev) for c in cfgs]
+    dt = cfgs[0]["dt"]
+    b.step(etas, phis, dt, args.c4_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, _ = b.step(etas, phis, dt, args.c4_steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    npts = sum(c["grid"].nx * c["grid"].ny for c in cfgs)
+    return dict(value=npts * args.c4_steps / el, ms_per_step=1e3 * el / args.c4_steps, status=st, members=96,
+                points=npts, steps=args.c4_steps, groups=b.groups())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,8 +245,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1024, help="grid size (1024 = the benchmark workload)")
     ap.add_argument("--max-sweeps", type=int, default=400)
-    ap.add_argument("--seed", default="linear", choices=["linear", "prev"],
-                    help="seed of each W iteration: linear guess (plain) or previous solve")
+    ap.add_argument("--batch-sweeps", type=int, default=64, help="sweep budget per solve of the captured forms")
+    ap.add_argument("--members", type=int, default=2, help="realisations of the batched forms")
+    ap.add_argument("--c4-steps", type=int, default=4)
+    ap.add_argument("--forms", default="plain,batched+prev,batched+learned,plain-fp32,c4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -119,88 +258,59 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_2310_19840_amd import Solver
-    from sbi_inputs import config_c5
-
     dev = torch.device("cuda:0")
-    cfg = config_c5(seed=0, n=args.n)
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    plain = run_plain(args, dev, "fp64", 1e-8)
+    cfg = plain.pop("cfg")
     g = cfg["grid"]
-    tol = cfg["tol"]
-    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="iter", precision="fp64",
-               max_sweeps=args.max_sweeps, seed=args.seed)
-    eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=dev)
-    phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=dev)
-    dt = cfg["dt"]
-
-    if args.warmup > 0:
-        s.step(eta, phi, dt, args.warmup, tol=tol)
-    torch.cuda.synchronize()
-
-    s.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, info = s.step(eta, phi, dt, args.steps, tol=tol)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    prof = s.profile_read()
-    s.profile(False)
-
-    npts = g.nx * g.ny
-    value = npts * args.steps / el
-    ms_per_step = 1e3 * el / max(args.steps, 1)
-    solves = max(info["solves"], 1)
-    sweeps_total = info["sweeps_total"]
-
-    # dominant kernel and its algorithmic bandwidth
-    Mx = int(math.ceil(0.5 * g.nx / 2 - 1e-9)) - 1
-    My = int(math.ceil(0.5 * g.ny / 2 - 1e-9)) - 1
-    Kx, Ky = Mx + 1, 2 * My + 1
-    vd = bool(np.any(cfg["depth"] != cfg["depth"].max()))
-    cand = {}
-    for kind in ("row_sweep", "col_sweep"):
-        tot_ms, cnt = prof.get(kind, (0.0, 0))
-        if tot_ms <= 0:
-            continue
-        working = sweeps_total + (solves if kind == "row_sweep" else 0)
-        b = algorithmic_bytes(kind, g.nx, g.ny, Kx, Ky, 16, 8, vd, 6, g.ny > 1)
-        avg_s = tot_ms * 1e-3 / max(working, 1)
-        cand[kind] = (tot_ms, b, avg_s, cnt, working)
-    dom = max(cand, key=lambda k: cand[k][0])
-    tot_ms, b, avg_s, cnt, working = cand[dom]
-    achieved = b / avg_s / 1e9
-    traffic = measured_traffic(dom) if (g.nx, g.ny) == (1024, 1024) else None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": round(traffic) if traffic is not None else None, "kernel": dom,
-                "bytes_per_launch": b, "avg_launch_us": round(avg_s * 1e6, 2),
-                "launches_working": working, "launches_total": cnt}
+    traffic = measured_traffic(plain["dominant"]) if (g.nx, g.ny) == (1024, 1024) else None
+    roofline = dict(plain["roofline"])
+    roofline["traffic"] = round(traffic) if traffic is not None else None
+    out_forms = {"plain": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in plain.items()
+                           if k in ("value", "ms_per_step", "sweeps_mean", "sweeps_max", "max_residual", "status")}}
+    if "batched+prev" in forms:
+        out_forms["batched+prev"] = run_batched(args, dev, "prev", args.members)
+    if "batched+learned" in forms:
+        out_forms["batched+learned"] = run_batched(args, dev, "net", args.members)
+    if "plain-fp32" in forms:
+        f32 = run_plain(args, dev, "fp32", 1e-6)
+        f32.pop("cfg")
+        out_forms["plain-fp32"] = {k: v for k, v in f32.items() if k in ("value", "ms_per_step", "sweeps_mean",
+                                                                          "sweeps_max", "max_residual", "status",
+                                                                          "roofline")}
+        out_forms["plain-fp32"]["tol"] = 1e-6
+    if "c4" in forms:
+        out_forms["c4"] = run_c4(args, dev)
+    for f, d in out_forms.items():
+        if isinstance(d.get("value"), float) and f != "plain":
+            d["vs_plain"] = round(d["value"] / plain["value"], 3)
 
     out = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": round(plain["value"], 1),
         "unit": "grid-point-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(plain["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"crossing JONSWAP seas {g.nx}x{g.ny}, 128 lambda_p, Gaussian-bump bathymetry, "
-                               f"k_p h_ref={cfg['h_ref']:.3f}, IF-RK4 dt=T_p/64, W iteration tol {tol:g} FP64 "
-                               f"(plain: linear-guess seed, single member)",
+                               f"k_p h_ref={cfg['h_ref']:.3f}, IF-RK4 dt=T_p/64, W iteration tol 1e-08 FP64 "
+                               f"(plain: linear-guess seed, single member; other forms under 'forms')",
                    "grid": [g.ny, g.nx], "form": "plain"},
-        "sweeps_per_solve_mean": round(sweeps_total / solves, 2),
-        "sweeps_per_solve_max": info["sweeps_max"],
-        "max_residual": info["max_residual"],
-        "status": st,
+        "sweeps_per_solve_mean": round(plain["sweeps_mean"], 2),
+        "sweeps_per_solve_max": plain["sweeps_max"],
+        "max_residual": plain["max_residual"],
+        "status": plain["status"],
         "roofline": roofline,
-        "kernel_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1] > 0},
+        "kernel_ms": plain["kernel_ms"],
+        "forms": out_forms,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

@@ -53,6 +53,10 @@ sbi_status sbi_batch_init(sbi_batch** out, int32_t m, const sbi_grid* grids, con
  */
 sbi_status sbi_batch_step(sbi_batch* b, sbi_state* states, double dt, int32_t n, double tol, sbi_step_info* info);
 
+/* Load the learned warm start (sbi_net.h blob) into every group whose seed is
+   SBI_SEED_NET; SBI_ERR_INVALID_ARG if the blob is rejected. */
+sbi_status sbi_batch_net_load(sbi_batch* b, const void* weights, size_t bytes);
+
 /* Number of member groups and, per group (g < groups), its member count and
    the column-pass split the autotuner chose (0: none). */
 int32_t sbi_batch_groups(const sbi_batch* b, int32_t* members_out, int32_t* split_out, int32_t n);

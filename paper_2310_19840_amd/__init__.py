@@ -347,6 +347,12 @@ class Batch:
         return st, [dict(t=states[i].t, solves=info[i].solves, sweeps_total=info[i].sweeps_total,
                          sweeps_max=info[i].sweeps_max, max_residual=info[i].max_residual) for i in range(self.m)]
 
+    def net_load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        st = self.lib.sbi_batch_net_load(self.b, C.cast(buf, C.c_void_p), len(blob))
+        if st < 0:
+            raise SBIError(st, "sbi_batch_net_load")
+
     def groups(self):
         mem = (C.c_int32 * 64)()
         spl = (C.c_int32 * 64)()

@@ -93,6 +93,7 @@ SIGNATURES = {
                                  C.POINTER(sbi_step_info)]),
     "sbi_batch_groups": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]),
     "sbi_batch_destroy": (C.c_int, [C.c_void_p]),
+    "sbi_batch_net_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
 }
 
 SBI_BATCH_GRAPH, SBI_BATCH_AUTOTUNE = 1, 2

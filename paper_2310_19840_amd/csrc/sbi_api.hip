@@ -1823,6 +1823,13 @@ extern "C" sbi_status sbi_batch_step(sbi_batch* b, sbi_state* states, double dt,
     return worst;
 }
 
+extern "C" sbi_status sbi_batch_net_load(sbi_batch* b, const void* weights, size_t bytes) {
+    if (!b || !weights) return SBI_ERR_INVALID_ARG;
+    for (auto& gr : b->g)
+        if (gr.c->grid.seed == SBI_SEED_NET) SBI_TRY(sbi_net_load(gr.c, weights, bytes));
+    return SBI_OK;
+}
+
 extern "C" int32_t sbi_batch_groups(const sbi_batch* b, int32_t* members_out, int32_t* split_out, int32_t n) {
     if (!b) return 0;
     const int ng = (int)b->g.size();

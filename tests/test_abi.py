@@ -131,3 +131,4 @@ def test_batch_interface_host_checks(lib):
     assert lib.sbi_batch_step(None, None, 0.1, 1, 1e-8, None) == _lib.SBI_ERR_INVALID_ARG
     assert lib.sbi_batch_destroy(None) == _lib.SBI_ERR_INVALID_ARG
     assert lib.sbi_batch_groups(None, None, None, 0) == 0
+    assert lib.sbi_batch_net_load(None, None, 0) == _lib.SBI_ERR_INVALID_ARG
