@@ -10,7 +10,7 @@ int col_tile(int ny, int fp64) {
     int e = fp64 ? 4 : 8;
     if (e > ny) e = ny;
     const int P = ny / e;
-    return P >= 256 ? 1 : 256 / P;
+    return P >= 128 ? 1 : 256 / P;
 }
 
 __global__ void k_ctl_reset(Ctl* ctl, int slots) {

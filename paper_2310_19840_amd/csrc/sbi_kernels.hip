@@ -577,12 +577,14 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_feat(const RowFeatPar
 template <typename R> __host__ __device__ constexpr int col_e() { return sizeof(R) == 8 ? 4 : 8; }
 
 // columns per workgroup: a column of NY values is carried by NY/E threads;
-// workgroups hold 256 threads (half forms are column-major, so each column is
-// one contiguous run whatever the tile width)
+// columns of 128 or more threads get a workgroup of their own (so that a
+// 1024^2 pass has a workgroup per kept column), shorter ones are packed to
+// 256 threads per lane (half forms are column-major, so each column is one
+// contiguous run whatever the tile width)
 template <typename R, int NY> __host__ __device__ constexpr int col_width() {
     if (NY == 1) return 64;
     constexpr int P = FftShape<NY, col_e<R>()>::P;
-    return P >= 256 ? 1 : 256 / P;
+    return P >= 128 ? 1 : 256 / P;
 }
 
 // decision of a sweep pass from the completed residual of the previous sweep.
@@ -666,7 +668,17 @@ __device__ __forceinline__ V col_source(const ColParams& p, int src, int q, cons
 // product lanes of a column-pass workgroup: independent thread groups that
 // transform alternate products of the same columns (more waves per CU to hide
 // memory latency); their partial sums are combined through LDS
-template <typename R, int NY> __host__ __device__ constexpr int col_lanes() { return NY == 1 ? 1 : 2; }
+// product lanes: groups of threads that transform different products of the
+// same columns and add their partial sums; up to four in FP32 (half the
+// registers of FP64) and two in FP64, within 512 threads per workgroup (two
+// waves per SIMD leave each thread 256 registers)
+template <typename R, int NY> __host__ __device__ constexpr int col_lanes() {
+    if (NY == 1) return 1;
+    constexpr int per_lane = col_width<R, NY>() * FftShape<NY, col_e<R>()>::P;
+    constexpr int lmax = sizeof(R) == 4 ? 4 : 2;
+    constexpr int fit = 512 / per_lane;
+    return fit < 1 ? 1 : (fit < lmax ? fit : lmax);
+}
 
 // LDS of a column workgroup: the transform exchange area of every lane and
 // column (none for 1D grids, whose "columns" are single values), followed by
