@@ -78,46 +78,87 @@ struct RowCtx {
     bool valid;
 };
 
+// LDS pitch of a row (elements): room for the padded transform, rounded up so
+// that consecutive rows start 16 banks apart -- the staging loops read and
+// write (row, mode) with the row index fastest, and a quarter wave of 16-byte
+// (half wave of 8-byte) accesses then covers distinct banks
+constexpr int row_pitch(int e0, int vbytes) {
+    const int unit = 256 / vbytes, want = 64 / vbytes;
+    int ls = e0;
+    while (ls % unit != want) ++ls;
+    return ls;
+}
+
 template <typename R, int NX> struct Row {
     using V = typename cplx_of<R>::type;
     static constexpr int N = NX / 2;
     static constexpr int E = FftShape<N>::E;
     static constexpr int P = FftShape<N>::P;
-    // LDS row pitch: room for the padded transform, odd against bank conflicts
-    static constexpr int LS = fft_lds_elems<N, E>() + 1;
-    static constexpr int NF = (N / 2 + 1 + P - 1) / P + 1;  // kept outputs per thread (bound)
+    static constexpr int LS = row_pitch(fft_lds_elems<N, E>(), (int)sizeof(V));
 
     // v <- z = inverse row transform of (G + c2 G2) for the thread's row.
     // G, G2: member base of a half form [m_x][ny]; all rows of the workgroup
     // stage their kept spectra through LDS with coalesced column segments.
+    // z[n] = f[2n] + i f[2n+1] has Z[m] = (F[m] + conj F[N-m]) / 2
+    //   + i (F[m] - conj F[N-m]) / 2 * exp(+2 pi i m / NX).
     using TW = Twid<V, N, E>;
     static __device__ __forceinline__ void inverse(V (&v)[E], const V* __restrict__ G, const V* __restrict__ G2,
                                                    R c2, const RowCtx& rc, V* lds_all,
                                                    const TW& twN, const V* __restrict__ twX, R scale) {
-        for (int idx = rc.t; idx < rc.rpw * N; idx += rc.nthr) {
-            const int r2 = idx % rc.rpw, m = idx / rc.rpw;
-            V f = cx<V>(R(0), R(0));
-            if (m <= rc.Mx && rc.y0 + r2 < rc.ny) {
-                const long long o = (long long)m * rc.ldh + rc.y0 + r2;
-                f = G[o];
-                if (G2) {
-                    const V f2 = G2[o];
-                    f = cx<V>(f.x + c2 * f2.x, f.y + c2 * f2.y);
+        V* lds = lds_all + rc.rl * LS;
+        if (2 * rc.Mx < N) {
+            // kept band below N/2: F[k] alone gives Z[k] and Z[N-k], Z is zero
+            // between them; the staging loop writes Z directly
+            const int K = rc.Mx + 1;
+            for (int idx = rc.t; idx < rc.rpw * K; idx += rc.nthr) {
+                const int r2 = idx % rc.rpw, k = idx / rc.rpw;
+                V f = cx<V>(R(0), R(0));
+                if (rc.y0 + r2 < rc.ny) {
+                    const long long o = (long long)k * rc.ldh + rc.y0 + r2;
+                    f = G[o];
+                    if (G2) {
+                        const V f2 = G2[o];
+                        f = cx<V>(f.x + c2 * f2.x, f.y + c2 * f2.y);
+                    }
+                }
+                const V h = cscale(f, R(0.5));
+                lds_all[r2 * LS + k] = cadd(h, mul_i(cmul(h, cconj(twX[k]))));
+                if (k > 0) {
+                    const V hc = cconj(h);
+                    const V w = mul_i(cmul(hc, cconj(twX[N - k])));
+                    lds_all[r2 * LS + N - k] = cx<V>(hc.x - w.x, hc.y - w.y);
                 }
             }
-            lds_all[r2 * LS + m] = f;
-        }
-        lds_sync();
-        V* lds = lds_all + rc.rl * LS;
+            for (int idx = rc.t; idx < rc.rpw * (N - 2 * K + 1); idx += rc.nthr)
+                lds_all[(idx % rc.rpw) * LS + K + idx / rc.rpw] = cx<V>(R(0), R(0));
+            lds_sync();
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
-            const int m = rc.j + q * P;
-            V fm = lds[m];
-            V fc = (m == 0) ? cx<V>(R(0), R(0)) : cconj(lds[N - m]);
-            V ev = cx<V>(R(0.5) * (fm.x + fc.x), R(0.5) * (fm.y + fc.y));
-            V od = cx<V>(R(0.5) * (fm.x - fc.x), R(0.5) * (fm.y - fc.y));
-            od = cmul(od, cconj(twX[m]));           // exp(+2 pi i m / NX)
-            v[q] = cadd(ev, mul_i(od));
+            for (int q = 0; q < E; ++q) v[q] = lds[rc.j + q * P];
+        } else {
+            for (int idx = rc.t; idx < rc.rpw * N; idx += rc.nthr) {
+                const int r2 = idx % rc.rpw, m = idx / rc.rpw;
+                V f = cx<V>(R(0), R(0));
+                if (m <= rc.Mx && rc.y0 + r2 < rc.ny) {
+                    const long long o = (long long)m * rc.ldh + rc.y0 + r2;
+                    f = G[o];
+                    if (G2) {
+                        const V f2 = G2[o];
+                        f = cx<V>(f.x + c2 * f2.x, f.y + c2 * f2.y);
+                    }
+                }
+                lds_all[r2 * LS + m] = f;
+            }
+            lds_sync();
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const int m = rc.j + q * P;
+                V fm = lds[m];
+                V fc = (m == 0) ? cx<V>(R(0), R(0)) : cconj(lds[N - m]);
+                V ev = cx<V>(R(0.5) * (fm.x + fc.x), R(0.5) * (fm.y + fc.y));
+                V od = cx<V>(R(0.5) * (fm.x - fc.x), R(0.5) * (fm.y - fc.y));
+                od = cmul(od, cconj(twX[m]));           // exp(+2 pi i m / NX)
+                v[q] = cadd(ev, mul_i(od));
+            }
         }
         lds_sync();
         fft<V, N, true, 1>(v, lds, 0, rc.j, twN);
@@ -125,7 +166,9 @@ template <typename R, int NX> struct Row {
         for (int q = 0; q < E; ++q) v[q] = cscale(v[q], scale);
     }
 
-    // H[kept m][row] <- forward row transform of the real pairs in v (v is destroyed).
+    // H[kept m][row] <- forward row transform of the real pairs in v (v is
+    // destroyed): F[m] = (Z[m] + conj Z[N-m]) / 2 - i (Z[m] - conj Z[N-m]) / 2
+    // * exp(-2 pi i m / NX), formed by the cooperative column-segment store.
     static __device__ __forceinline__ void forward(V (&v)[E], V* __restrict__ H, const RowCtx& rc, V* lds_all,
                                                    const TW& twN, const V* __restrict__ twX) {
         V* lds = lds_all + rc.rl * LS;
@@ -133,29 +176,13 @@ template <typename R, int NX> struct Row {
 #pragma unroll
         for (int q = 0; q < E; ++q) lds[rc.j + q * P] = v[q];
         lds_sync();
-        V fo[NF];
-#pragma unroll
-        for (int i = 0; i < NF; ++i) {
-            const int m = rc.j + i * P;
-            fo[i] = cx<V>(R(0), R(0));
-            if (m <= rc.Mx) {
-                V zm = lds[m];
-                V zc = cconj(lds[(N - m) & (N - 1)]);
-                V ev = cx<V>(R(0.5) * (zm.x + zc.x), R(0.5) * (zm.y + zc.y));
-                V od = mul_mi<false>(cx<V>(R(0.5) * (zm.x - zc.x), R(0.5) * (zm.y - zc.y)));
-                fo[i] = cadd(ev, cmul(twX[m], od));
-            }
-        }
-        lds_sync();
-#pragma unroll
-        for (int i = 0; i < NF; ++i) {
-            const int m = rc.j + i * P;
-            if (m <= rc.Mx) lds[m] = fo[i];
-        }
-        lds_sync();
         for (int idx = rc.t; idx < rc.rpw * (rc.Mx + 1); idx += rc.nthr) {
             const int r2 = idx % rc.rpw, m = idx / rc.rpw;
-            if (rc.y0 + r2 < rc.ny) H[(long long)m * rc.ldh + rc.y0 + r2] = lds_all[r2 * LS + m];
+            const V zm = lds_all[r2 * LS + m];
+            const V zc = cconj(lds_all[r2 * LS + ((N - m) & (N - 1))]);
+            const V ev = cx<V>(R(0.5) * (zm.x + zc.x), R(0.5) * (zm.y + zc.y));
+            const V od = mul_mi<false>(cx<V>(R(0.5) * (zm.x - zc.x), R(0.5) * (zm.y - zc.y)));
+            if (rc.y0 + r2 < rc.ny) H[(long long)m * rc.ldh + rc.y0 + r2] = cadd(ev, cmul(twX[m], od));
         }
         lds_sync();
     }
@@ -178,6 +205,15 @@ template <int NX> __host__ __device__ constexpr int row_threads() {
     return FftShape<NX / 2>::P > 256 ? FftShape<NX / 2>::P : 256;
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin by launch order, and each
+// XCD has its own L2.  Neighbouring row groups read neighbouring pieces of the
+// same cache lines of the column-major half forms, so they are mapped to the
+// same XCD: launch index b runs row group (b % 8) * (G / 8) + b / 8.
+__device__ __forceinline__ int xcd_row_group(int b, int G) {
+    constexpr int kXcd = 8;
+    return (G % kXcd) ? b : (b % kXcd) * (G / kXcd) + b / kXcd;
+}
+
 template <int P> __device__ __forceinline__ RowCtx row_ctx(const GridDev& g) {
     RowCtx r;
     r.t = threadIdx.x;
@@ -185,7 +221,7 @@ template <int P> __device__ __forceinline__ RowCtx row_ctx(const GridDev& g) {
     r.j = r.t % P;
     r.rl = r.t / P;
     r.rpw = blockDim.x / P;
-    r.y0 = blockIdx.x * r.rpw;
+    r.y0 = xcd_row_group(blockIdx.x, gridDim.x) * r.rpw;
     r.ny = g.ny;
     r.ldh = g.ldh;
     r.Mx = g.Mx;
