@@ -41,6 +41,20 @@ __device__ __forceinline__ void lds_sync() {
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
+// LDS exchange among the lanes of one wavefront: a wave's LDS operations
+// complete in order, so ordering the wave's own accesses is enough when every
+// thread of a transform sits in the same wavefront
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+template <bool WAVE> __device__ __forceinline__ void xfer_sync() {
+    if constexpr (WAVE)
+        wave_lds_sync();
+    else
+        lds_sync();
+}
 
 template <int R, bool INV, typename V> struct Dft;
 
@@ -163,7 +177,9 @@ template <int E> __device__ __forceinline__ int lds_slot(int idx) { return E >= 
 template <int N, int E> __host__ __device__ constexpr int fft_lds_elems() { return E >= 2 ? N + N / E : N; }
 
 // One Stockham pass of radix R with current span Ns (product of earlier radices).
-template <typename V, int N, int E, int R, int Ns, bool INV, bool LAST, int LS>
+// WAVE: all threads of the transform are in one wavefront (exchanges need no
+// workgroup barrier).
+template <typename V, int N, int E, int R, int Ns, bool INV, bool LAST, int LS, bool WAVE>
 __device__ __forceinline__ void stockham_pass(V (&v)[E], V* lds, int lo, int j, const Twid<V, N, E>& tw) {
     constexpr int P = N / E;
     constexpr int B = E / R;
@@ -197,27 +213,30 @@ __device__ __forceinline__ void stockham_pass(V (&v)[E], V* lds, int lo, int j, 
         }
     }
     if (!LAST) {
-        lds_sync();
+        xfer_sync<WAVE>();
 #pragma unroll
         for (int q = 0; q < E; ++q) v[q] = lds[lds_slot<E>(j + q * P) * LS + lo];
-        lds_sync();
+        xfer_sync<WAVE>();
     }
 }
 
-template <typename V, int N, int E, int Ns, bool INV, int LS>
+template <typename V, int N, int E, int Ns, bool INV, int LS, bool WAVE>
 struct StockhamRun {
     using PI = PassInfo<N, E, Ns>;
     static __device__ __forceinline__ void run(V (&v)[E], V* lds, int lo, int j, const Twid<V, N, E>& tw) {
-        stockham_pass<V, N, E, PI::R, Ns, INV, PI::LAST, LS>(v, lds, lo, j, tw);
-        if constexpr (!PI::LAST) StockhamRun<V, N, E, PI::NEXT, INV, LS>::run(v, lds, lo, j, tw);
+        stockham_pass<V, N, E, PI::R, Ns, INV, PI::LAST, LS, WAVE>(v, lds, lo, j, tw);
+        if constexpr (!PI::LAST) StockhamRun<V, N, E, PI::NEXT, INV, LS, WAVE>::run(v, lds, lo, j, tw);
     }
 };
 
-// Full transform.  All threads of the workgroup must call it (it synchronises).
-template <typename V, int N, bool INV, int LS, int EMAX = 8>
+// Full transform.  All threads of the workgroup must call it (it synchronises;
+// with WAVE only the wavefront holding the transform does).  On return every
+// thread of the transform has passed the last read of its exchange area only
+// when WAVE is false.
+template <typename V, int N, bool INV, int LS, int EMAX = 8, bool WAVE = false>
 __device__ __forceinline__ void fft(V (&v)[(FftShape<N, EMAX>::E)], V* lds, int lo, int j,
                                     const Twid<V, N, FftShape<N, EMAX>::E>& tw) {
-    if constexpr (N > 1) StockhamRun<V, N, FftShape<N, EMAX>::E, 1, INV, LS>::run(v, lds, lo, j, tw);
+    if constexpr (N > 1) StockhamRun<V, N, FftShape<N, EMAX>::E, 1, INV, LS, WAVE>::run(v, lds, lo, j, tw);
 }
 
 }  // namespace sbi

@@ -95,6 +95,9 @@ template <typename R, int NX> struct Row {
     static constexpr int E = FftShape<N>::E;
     static constexpr int P = FftShape<N>::P;
     static constexpr int LS = row_pitch(fft_lds_elems<N, E>(), (int)sizeof(V));
+    // a row of up to 64 threads lies in one wavefront: its transform's LDS
+    // exchanges need only wave-level ordering
+    static constexpr bool WAVE = P <= 64;
 
     // v <- z = inverse row transform of (G + c2 G2) for the thread's row.
     // G, G2: member base of a half form [m_x][ny]; all rows of the workgroup
@@ -106,6 +109,7 @@ template <typename R, int NX> struct Row {
                                                    R c2, const RowCtx& rc, V* lds_all,
                                                    const TW& twN, const V* __restrict__ twX, R scale) {
         V* lds = lds_all + rc.rl * LS;
+        lds_sync();  // other rows' transforms are done with the area the staging loop writes
         if (2 * rc.Mx < N) {
             // kept band below N/2: F[k] alone gives Z[k] and Z[N-k], Z is zero
             // between them; the staging loop writes Z directly
@@ -160,8 +164,8 @@ template <typename R, int NX> struct Row {
                 v[q] = cadd(ev, mul_i(od));
             }
         }
-        lds_sync();
-        fft<V, N, true, 1>(v, lds, 0, rc.j, twN);
+        xfer_sync<WAVE>();  // the row's staged values are in registers before the exchanges reuse them
+        fft<V, N, true, 1, 8, WAVE>(v, lds, 0, rc.j, twN);
 #pragma unroll
         for (int q = 0; q < E; ++q) v[q] = cscale(v[q], scale);
     }
@@ -172,7 +176,10 @@ template <typename R, int NX> struct Row {
     static __device__ __forceinline__ void forward(V (&v)[E], V* __restrict__ H, const RowCtx& rc, V* lds_all,
                                                    const TW& twN, const V* __restrict__ twX) {
         V* lds = lds_all + rc.rl * LS;
-        fft<V, N, false, 1>(v, lds, 0, rc.j, twN);
+        // other rows touch this row's LDS only in the staging and store loops,
+        // each closed by a workgroup barrier
+        fft<V, N, false, 1, 8, WAVE>(v, lds, 0, rc.j, twN);
+        xfer_sync<WAVE>();  // the row's last exchange reads are done before it is overwritten
 #pragma unroll
         for (int q = 0; q < E; ++q) lds[rc.j + q * P] = v[q];
         lds_sync();
@@ -352,7 +359,7 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupP
 }
 
 template <typename R, int NX>
-__global__ void __launch_bounds__(row_threads<NX>()) k_row_sweep(const RowSweepParams p, const typename cplx_of<R>::type* twN_tab,
+__global__ void __launch_bounds__(row_threads<NX>(), 3) k_row_sweep(const RowSweepParams p, const typename cplx_of<R>::type* twN_tab,
                             const typename cplx_of<R>::type* twX) {
     ROW_PROLOGUE(R, NX)
     Ctl* ctl = p.ctl + ri.mem;
@@ -390,15 +397,14 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_sweep(const RowSweepP
         if (!p.products) return;
         V ev[E];
         RW::load(ev, static_cast<const R*>(p.eta) + po, ri.j, ri.valid);
-        V pw[E];
-#pragma unroll
-        for (int q = 0; q < E; ++q) pw[q] = vv[q];
+        // eta^j V: the power is rebuilt from V for each j (the same sequence
+        // of products as a running power, without holding it in registers)
         for (int jj = 1; jj <= p.J; ++jj) {
             V w[E];
 #pragma unroll
             for (int q = 0; q < E; ++q) {
-                pw[q] = rmul(pw[q], ev[q]);
-                w[q] = pw[q];
+                w[q] = vv[q];
+                for (int k = 0; k < jj; ++k) w[q] = rmul(w[q], ev[q]);
             }
             RW::forward(w, static_cast<V*>(p.h[jj - 1]) + hb, rc, lds_all, twN, twX);
         }
@@ -407,15 +413,15 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_sweep(const RowSweepP
     // families 1, 2: delta^j d_x phi_b, delta^j d_y phi_b
     if (!p.products || !p.vd) return;
     const int comp = fam - 1;
-    V dv[E], pw[E];
-    RW::inverse(pw, static_cast<const V*>(comp == 0 ? p.gbx : p.gby) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+    V dv[E], gb[E];
+    RW::inverse(gb, static_cast<const V*>(comp == 0 ? p.gbx : p.gby) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
     RW::load(dv, static_cast<const R*>(p.delta) + po, ri.j, ri.valid);
     for (int jj = 1; jj <= p.J; ++jj) {
         V w[E];
 #pragma unroll
         for (int q = 0; q < E; ++q) {
-            pw[q] = rmul(pw[q], dv[q]);
-            w[q] = pw[q];
+            w[q] = gb[q];
+            for (int k = 0; k < jj; ++k) w[q] = rmul(w[q], dv[q]);
         }
         RW::forward(w, static_cast<V*>(p.h[fam * p.J + jj - 1]) + hb, rc, lds_all, twN, twX);
     }
