@@ -395,12 +395,12 @@ __global__ void __launch_bounds__(row_threads<NX>(), 3) k_row_sweep(const RowSwe
             }
         }
         if (!p.products) return;
-        V ev[E];
-        RW::load(ev, static_cast<const R*>(p.eta) + po, ri.j, ri.valid);
         // eta^j V: the power is rebuilt from V for each j (the same sequence
-        // of products as a running power, without holding it in registers)
+        // of products as a running power); eta is re-read from the cache for
+        // each product rather than held across the transforms
         for (int jj = 1; jj <= p.J; ++jj) {
-            V w[E];
+            V w[E], ev[E];
+            RW::load(ev, static_cast<const R*>(p.eta) + po, ri.j, ri.valid);
 #pragma unroll
             for (int q = 0; q < E; ++q) {
                 w[q] = vv[q];
@@ -413,11 +413,11 @@ __global__ void __launch_bounds__(row_threads<NX>(), 3) k_row_sweep(const RowSwe
     // families 1, 2: delta^j d_x phi_b, delta^j d_y phi_b
     if (!p.products || !p.vd) return;
     const int comp = fam - 1;
-    V dv[E], gb[E];
+    V gb[E];
     RW::inverse(gb, static_cast<const V*>(comp == 0 ? p.gbx : p.gby) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
-    RW::load(dv, static_cast<const R*>(p.delta) + po, ri.j, ri.valid);
     for (int jj = 1; jj <= p.J; ++jj) {
-        V w[E];
+        V w[E], dv[E];
+        RW::load(dv, static_cast<const R*>(p.delta) + po, ri.j, ri.valid);
 #pragma unroll
         for (int q = 0; q < E; ++q) {
             w[q] = gb[q];
