@@ -158,7 +158,7 @@ static sbi_status hip_ok(hipError_t e) { return e == hipSuccess ? SBI_OK : SBI_E
 // sizes and layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    int Mx, My, Kx, Kxp, Ky, C, ldh;
+    int Mx, My, Kx, Kxp, Ky, C, qb, ldh;
     size_t rsz, csz;
     long long s_phys, s_half, s_cmp;
     size_t bytes_comp, bytes_half, bytes_phys, bytes_tw, bytes_misc, bytes_net, total;
@@ -196,7 +196,8 @@ static Layout layout(const sbi_grid* g, int batch) {
     L.Mx = (int)std::ceil(g->dealias * g->nx / 2.0 - 1e-9) - 1;
     L.My = g->ny == 1 ? 0 : (int)std::ceil(g->dealias * g->ny / 2.0 - 1e-9) - 1;
     L.Kx = L.Mx + 1;
-    L.C = col_tile(g->ny, f64);
+    L.qb = col_quarter_band(g->ny, L.My);
+    L.C = col_tile(g->ny, f64, L.qb);
     L.Kxp = (L.Kx + L.C - 1) / L.C * L.C;
     L.Ky = g->ny == 1 ? 1 : 2 * L.My + 1;
     L.s_phys = (long long)g->nx * g->ny;
@@ -381,6 +382,8 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
     p += al(sizeof(NetPacked));
     if (g->seed == SBI_SEED_NET && g->ny > 1) c->feat = reinterpret_cast<float*>(p);
     c->col_C = L.C;
+    gd.col_C = L.C;
+    gd.qb = L.qb;
     gd.href = c->href_dev;
     if (hipHostMalloc(reinterpret_cast<void**>(&c->head), sizeof(Ctl) * batch, hipHostMallocDefault) != hipSuccess) {
         if (c->own_ws) (void)hipFree(c->ws);

@@ -4,14 +4,17 @@
 
 namespace sbi {
 
-// columns per column-pass workgroup (must equal col_width<R, NY>() of the kernels)
-int col_tile(int ny, int fp64) {
+// columns per column-pass workgroup (equals ColCfg<R, NY, QB>::C of the kernels;
+// the launcher checks it)
+int col_tile(int ny, int fp64, int qb) {
     if (ny == 1) return 64;
-    int e = fp64 ? 4 : 8;
+    int e = (fp64 && !qb) ? 4 : 8;
     if (e > ny) e = ny;
     const int P = ny / e;
     return P >= 128 ? 1 : 256 / P;
 }
+
+int col_quarter_band(int ny, int My) { return (ny >= 128 && 4 * My < ny) ? 1 : 0; }
 
 __global__ void k_ctl_reset(Ctl* ctl, int slots) {
     Ctl* c = ctl + blockIdx.x;

@@ -64,6 +64,8 @@ struct GridDev {
     long long s_cmp;    // complex per member of a compact field
     const double* href; // [batch] reference depth
     int relax;
+    int qb;             // kept band below ny/4 and ny >= 128: the quarter-band column pass
+    int col_C;          // columns per column-pass workgroup (Kxp is a multiple)
 };
 
 // Multiplier of one contribution to a column-pass accumulator:

@@ -614,20 +614,33 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_feat(const RowFeatPar
 // Column pass: forward column transforms of the products, multiplier sums,
 // relaxation, compact outputs, inverse column transforms of the results.
 // ---------------------------------------------------------------------------
-// elements per thread of the column transforms: 4 in FP64 and 8 in FP32 keep
-// the accumulators, mode geometry and transform data of a thread in registers
-template <typename R> __host__ __device__ constexpr int col_e() { return sizeof(R) == 8 ? 4 : 8; }
-
-// columns per workgroup: a column of NY values is carried by NY/E threads;
-// columns of 128 or more threads get a workgroup of their own (so that a
-// 1024^2 pass has a workgroup per kept column), shorter ones are packed to
-// 256 threads per lane (half forms are column-major, so each column is one
-// contiguous run whatever the tile width)
-template <typename R, int NY> __host__ __device__ constexpr int col_width() {
-    if (NY == 1) return 64;
-    constexpr int P = FftShape<NY, col_e<R>()>::P;
-    return P >= 128 ? 1 : 256 / P;
-}
+// Shape of a column pass.  QB ("quarter band"): the kept band |m_y| <= My lies
+// below NY/4, so of the E values a thread transforms (modes j + qP) only the
+// first and last E/4 can be kept; the accumulators of the others are never
+// formed.  Elements per thread: 8, or 4 in FP64 without QB (the accumulators of
+// all E modes then share the registers); columns of 128 or more threads get a
+// workgroup of their own, shorter ones are packed to 256 threads per lane (half
+// forms are column-major, so each column is one contiguous run); product
+// lanes (threads transforming different products of the same columns) fill up
+// to 512 threads, at most 2 in FP64 without QB and 4 otherwise.
+template <typename R, int NY, bool QB> struct ColCfg {
+    static constexpr int CE = (sizeof(R) == 8 && !QB) ? 4 : 8;
+    static constexpr int E = FftShape<NY, CE>::E;
+    static constexpr int P = FftShape<NY, CE>::P;
+    static constexpr int C = NY == 1 ? 64 : (P >= 128 ? 1 : 256 / P);
+    static constexpr int LMAX = (sizeof(R) == 8 && !QB) ? 2 : 4;
+    static constexpr int FIT = 512 / (C * P);
+    static constexpr int PL = NY == 1 ? 1 : (FIT < 1 ? 1 : (FIT < LMAX ? FIT : LMAX));
+    static constexpr int THREADS = PL * C * P;
+    // LDS: the transform exchange area of every lane and column (none for 1D
+    // grids, whose "columns" are single values), then the mode-geometry table
+    // of C * Ky entries of 4 reals
+    static constexpr int XFORM = NY > 1 ? PL * C * fft_lds_elems<NY, E>() : 0;
+    static constexpr size_t lds_bytes(int Ky) {
+        return (size_t)XFORM * sizeof(typename cplx_of<R>::type) + (size_t)C * Ky * 4 * sizeof(R);
+    }
+    static constexpr bool keepable(int q) { return !QB || q < E / 4 || q >= E - E / 4; }
+};
 
 // decision of a sweep pass from the completed residual of the previous sweep.
 // returns 0 to continue, else the terminating sbi_status + 100 (so 0 is free).
@@ -654,11 +667,13 @@ __device__ __forceinline__ int sweep_decision(Ctl* ctl, int n, int M, double tol
 // Per-mode geometry of a column tile, held in LDS: for kept mode (c, r),
 // geo[(c * Ky + r) * 4 + {0, 1, 2, 3}] = {k, tanh(k h), sech(k h), k_y}.
 // multiplier sum of one source into the accumulators (kept modes only)
+// toff, term: the pass's term table, staged in LDS
 template <typename R, typename V, int E, int NACC>
-__device__ __forceinline__ void col_apply_terms(const ColParams& p, int src, const V (&v)[E], V (&acc)[NACC][E],
-                                                const int (&crow)[E], const R* __restrict__ geo, R kxr) {
-    for (int ti = p.toff[src]; ti < p.toff[src + 1]; ++ti) {
-        const ColTerm tm = p.term[ti];
+__device__ __forceinline__ void col_apply_terms(const short* toff, const ColTerm* term, int src, const V (&v)[E],
+                                                V (&acc)[NACC][E], const int (&crow)[E], const R* __restrict__ geo,
+                                                R kxr) {
+    for (int ti = toff[src]; ti < toff[src + 1]; ++ti) {
+        const ColTerm tm = term[ti];
 #pragma unroll
         for (int q = 0; q < E; ++q) {
             if (crow[q] < 0) continue;
@@ -710,48 +725,24 @@ __device__ __forceinline__ V col_source(const ColParams& p, int src, int q, cons
 // product lanes of a column-pass workgroup: independent thread groups that
 // transform alternate products of the same columns (more waves per CU to hide
 // memory latency); their partial sums are combined through LDS
-// product lanes: groups of threads that transform different products of the
-// same columns and add their partial sums; up to four in FP32 (half the
-// registers of FP64) and two in FP64, within 512 threads per workgroup (two
-// waves per SIMD leave each thread 256 registers)
-template <typename R, int NY> __host__ __device__ constexpr int col_lanes() {
-    if (NY == 1) return 1;
-    constexpr int per_lane = col_width<R, NY>() * FftShape<NY, col_e<R>()>::P;
-    constexpr int lmax = sizeof(R) == 4 ? 4 : 2;
-    constexpr int fit = 512 / per_lane;
-    return fit < 1 ? 1 : (fit < lmax ? fit : lmax);
-}
-
-// LDS of a column workgroup: the transform exchange area of every lane and
-// column (none for 1D grids, whose "columns" are single values), followed by
-// the mode-geometry table of C * Ky entries of 4 reals.  Host and kernel both
-// take the offsets from here.
-template <typename R, int NY> __host__ __device__ constexpr int col_xform_elems() {
-    return NY > 1 ? col_lanes<R, NY>() * col_width<R, NY>() * fft_lds_elems<NY, FftShape<NY, col_e<R>()>::E>() : 0;
-}
-template <typename R, int NY> __host__ __device__ constexpr size_t col_lds_bytes(int Ky) {
-    return (size_t)col_xform_elems<R, NY>() * sizeof(typename cplx_of<R>::type) +
-           (size_t)col_width<R, NY>() * Ky * 4 * sizeof(R);
-}
-
-template <typename R, int NY> __host__ __device__ constexpr int col_threads() {
-    return col_lanes<R, NY>() * col_width<R, NY>() * FftShape<NY, col_e<R>()>::P;
-}
-
-template <typename R, int NY, int NACC>
-__global__ void __launch_bounds__((col_threads<R, NY>()))
+template <typename R, int NY, int NACC, bool QB>
+__global__ void __launch_bounds__((ColCfg<R, NY, QB>::THREADS))
 k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     using V = typename cplx_of<R>::type;
+    using CF = ColCfg<R, NY, QB>;
     constexpr int N = NY;
-    constexpr int CE = col_e<R>();
-    constexpr int E = FftShape<N, CE>::E;
-    constexpr int P = FftShape<N, CE>::P;
-    constexpr int C = col_width<R, NY>();
-    constexpr int PL = col_lanes<R, NY>();
+    constexpr int CE = CF::CE;
+    constexpr int E = CF::E;
+    constexpr int P = CF::P;
+    constexpr int C = CF::C;
+    constexpr int PL = CF::PL;
     constexpr int REG = fft_lds_elems<N, E>();  // LDS elements of one column transform
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     const int t = threadIdx.x;
-    const int lane = t / (C * P);
+    // a lane is a whole number of wavefronts: make its index wave-uniform, so
+    // that the per-product parameters it selects are scalar loads (a vector
+    // load would also wait for the next product's prefetched column)
+    const int lane = (C * P) % 64 == 0 ? __builtin_amdgcn_readfirstlane(t / (C * P)) : t / (C * P);
     const int tl = t % (C * P);
     const int c = tl / P;  // column of the tile
     const int j = tl % P;  // thread within the column
@@ -824,10 +815,16 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     for (int q = 0; q < E; ++q) {
         const int n = j + q * P;
         const int my = (n <= N / 2) ? n : n - N;
-        const bool keep = (mx < g.Kx) && (my <= g.My) && (my >= -g.My);
+        const bool keep = CF::keepable(q) && (mx < g.Kx) && (my <= g.My) && (my >= -g.My);
         crow[q] = keep ? (my >= 0 ? my : my + g.Ky) : -1;
     }
-    R* geo_all = reinterpret_cast<R*>(reinterpret_cast<V*>(smem_raw) + col_xform_elems<R, NY>());
+    // the pass's term table in LDS: its per-product reads then wait on LDS
+    // only, never on the prefetched column in flight
+    __shared__ ColTerm s_term[kMaxTerms];
+    __shared__ short s_toff[kMaxProd + kMaxCin + 1];
+    for (int i = t; i < p.nterm; i += blockDim.x) s_term[i] = p.term[i];
+    for (int i = t; i <= p.nprod + p.ncin; i += blockDim.x) s_toff[i] = p.toff[i];
+    R* geo_all = reinterpret_cast<R*>(reinterpret_cast<V*>(smem_raw) + CF::XFORM);
     for (int idx = t; idx < C * g.Ky; idx += blockDim.x) {
         const int c2 = idx / g.Ky, r2 = idx % g.Ky;
         const int my = r2 <= g.My ? r2 : r2 - g.Ky;
@@ -844,7 +841,7 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     const R* geo = geo_all + c * g.Ky * 4;
     const R kxr = R(kx);
 
-    V acc[NACC][E];
+    V acc[NACC][E];  // entries of modes that cannot be kept are never used
 #pragma unroll
     for (int a = 0; a < NACC; ++a)
 #pragma unroll
@@ -875,7 +872,7 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         V vn[E];
         if (rd + 1 < rounds) load_col(s + PL, vn);
         fft<V, N, false, 1, CE>(v, lds, 0, j, twc);
-        if (s < s1) col_apply_terms<R, V, E, NACC>(p, s, v, acc, crow, geo, kxr);
+        if (s < s1) col_apply_terms<R, V, E, NACC>(s_toff, s_term, s, v, acc, crow, geo, kxr);
 #pragma unroll
         for (int q = 0; q < E; ++q) v[q] = vn[q];
     }
@@ -886,7 +883,8 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
             lds_sync();
             if (lane > 0) {
 #pragma unroll
-                for (int q = 0; q < E; ++q) lds[j + q * P] = acc[a][q];
+                for (int q = 0; q < E; ++q)
+                    if (CF::keepable(q)) lds[j + q * P] = acc[a][q];
             }
             lds_sync();
             if (lane == 0) {
@@ -894,7 +892,8 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
                 for (int l2 = 1; l2 < PL; ++l2) {
                     const V* o = reinterpret_cast<const V*>(smem_raw) + (l2 * C + c) * REG;
 #pragma unroll
-                    for (int q = 0; q < E; ++q) acc[a][q] = cadd(acc[a][q], o[j + q * P]);
+                    for (int q = 0; q < E; ++q)
+                        if (CF::keepable(q)) acc[a][q] = cadd(acc[a][q], o[j + q * P]);
                 }
             }
         }
@@ -929,6 +928,7 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
             for (int a = 0; a < NACC; ++a)
 #pragma unroll
                 for (int q = 0; q < E; ++q) {
+                    if (!CF::keepable(q)) continue;
                     V sum = cx<V>(R(0), R(0));
                     if (crow[q] >= 0) {
                         for (int gg = 0; gg < p.ngroup; ++gg) {
@@ -946,13 +946,13 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     // compact inputs (lane 0 holds the sums)
     if (lane == 0) {
         for (int ci = 0; ci < p.ncin; ++ci) {
-            if (p.toff[p.nprod + ci] == p.toff[p.nprod + ci + 1]) continue;  // no term reads it
+            if (s_toff[p.nprod + ci] == s_toff[p.nprod + ci + 1]) continue;  // no term reads it
             const V* Ci = static_cast<const V*>(p.cin[ci]) + mem * g.s_cmp;
             V vc[E];
 #pragma unroll
             for (int q = 0; q < E; ++q)
                 vc[q] = crow[q] >= 0 ? Ci[(long long)mx * g.Ky + crow[q]] : cx<V>(R(0), R(0));
-            col_apply_terms<R, V, E, NACC>(p, p.nprod + ci, vc, acc, crow, geo, kxr);
+            col_apply_terms<R, V, E, NACC>(s_toff, s_term, p.nprod + ci, vc, acc, crow, geo, kxr);
         }
     }
     // broadcast the final sums to every lane
@@ -962,13 +962,15 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
             lds_sync();
             if (lane == 0) {
 #pragma unroll
-                for (int q = 0; q < E; ++q) lds[j + q * P] = acc[a][q];
+                for (int q = 0; q < E; ++q)
+                    if (CF::keepable(q)) lds[j + q * P] = acc[a][q];
             }
             lds_sync();
             if (lane > 0) {
                 const V* o = reinterpret_cast<const V*>(smem_raw) + c * REG;
 #pragma unroll
-                for (int q = 0; q < E; ++q) acc[a][q] = o[j + q * P];
+                for (int q = 0; q < E; ++q)
+                    if (CF::keepable(q)) acc[a][q] = o[j + q * P];
             }
         }
     }
@@ -1217,22 +1219,32 @@ SBI_ROW_LAUNCH(k_row_nphi, RowNphiParams)
 SBI_ROW_LAUNCH(k_row_blend, RowBlendParams)
 SBI_ROW_LAUNCH(k_row_feat, RowFeatParams)
 
-template <typename R, int NY, int NACC>
+template <typename R, int NY, int NACC, bool QB>
 static hipError_t col_go(const ColParams& p, int batch, const Twiddles& tw, hipStream_t s) {
     using V = typename cplx_of<R>::type;
-    constexpr int C = col_width<R, NY>();
-    dim3 block(col_threads<R, NY>());
-    dim3 grid(p.g.Kxp / C, p.ngroup > 0 ? p.ngroup : 1, batch);
-    const size_t lds = col_lds_bytes<R, NY>(p.g.Ky);
+    using CF = ColCfg<R, NY, QB>;
+    if (p.g.col_C != CF::C) return hipErrorInvalidValue;  // the layout was made for another tile
+    dim3 block(CF::THREADS);
+    dim3 grid(p.g.Kxp / CF::C, p.ngroup > 0 ? p.ngroup : 1, batch);
+    const size_t lds = CF::lds_bytes(p.g.Ky);
     if (lds > kMaxLdsBytes) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_col<R, NY, NACC>), grid, block, lds, s, p, (const V*)tw.ty);
+    hipLaunchKernelGGL((k_col<R, NY, NACC, QB>), grid, block, lds, s, p, (const V*)tw.ty);
     return hipGetLastError();
 }
+template <typename R, int NY, bool QB>
+static hipError_t col_acc_qb(const ColParams& p, int batch, const Twiddles& tw, hipStream_t s) {
+    if (p.nacc <= 1) return col_go<R, NY, 1, QB>(p, batch, tw, s);
+    if (p.nacc <= 2) return col_go<R, NY, 2, QB>(p, batch, tw, s);
+    return col_go<R, NY, 4, QB>(p, batch, tw, s);
+}
+// the quarter-band variant serves grids of 128 or more rows whose kept band
+// lies below NY/4
 template <typename R, int NY>
 static hipError_t col_acc(const ColParams& p, int batch, const Twiddles& tw, hipStream_t s) {
-    if (p.nacc <= 1) return col_go<R, NY, 1>(p, batch, tw, s);
-    if (p.nacc <= 2) return col_go<R, NY, 2>(p, batch, tw, s);
-    return col_go<R, NY, 4>(p, batch, tw, s);
+    if constexpr (NY >= 128) {
+        if (p.g.qb) return col_acc_qb<R, NY, true>(p, batch, tw, s);
+    }
+    return col_acc_qb<R, NY, false>(p, batch, tw, s);
 }
 template <typename R>
 static hipError_t col_ny(const ColParams& p, int batch, const Twiddles& tw, hipStream_t s) {

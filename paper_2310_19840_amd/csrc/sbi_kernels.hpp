@@ -141,7 +141,8 @@ struct Twiddles {
     const void* ty;   // length ny
 };
 
-int col_tile(int ny, int fp64);   // column-tile width C for a grid
+int col_tile(int ny, int fp64, int qb);   // column-tile width C for a grid
+int col_quarter_band(int ny, int My);     // 1 if the quarter-band column pass applies
 
 // per-precision launchers (defined in sbi_kernels.hip, one object per precision)
 template <typename R> hipError_t launch_row_fwd_t(const RowFwdParams&, int, const Twiddles&, hipStream_t);
