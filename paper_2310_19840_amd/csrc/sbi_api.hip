@@ -517,6 +517,8 @@ struct ColBuilder {
         p.nprod = (int)prods.size();
         p.ncin = (int)cins.size();
         if (p.nprod > kMaxProd || p.ncin > kMaxCin || (int)terms.size() > kMaxTerms) return false;
+        for (auto& t : terms)
+            if (t.pw > 6 || t.pw < -1) return false;  // the column pass forms k^-1 .. k^6
         for (int i = 0; i < p.nprod; ++i) {
             p.hin[i] = prods[i];
             p.hin_stride[i] = prod_stride[i];
