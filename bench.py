@@ -12,8 +12,9 @@ resident in HBM before the timed region.
 with the kernel profiler on).  `forms` adds, at the same tolerance, two
 realisations stepped in one captured HIP graph with the previous-solve seed
 ("batched+prev") and with the learned warm start ("batched+learned"), the
-plain step in FP32 (tolerance 1e-6, the FP32 floor), and the ragged C4
-ensemble (96 members, SA mode, FP32) in one graph.
+plain step in FP32 (tolerance 1e-6, the FP32 floor), the ragged C4
+ensemble (96 members, SA mode, FP32) in one graph, and the 512^2 flat
+crossing sea in FP32 beside FP64 with the FP32 error (max |eta|, energy drift).
 
 Prints ONE JSON line.  `roofline` is for the dominant kernel of the plain
 form, its algorithmic bytes per launch divided by its average launch time from
@@ -238,6 +239,40 @@ def run_c4(args, dev):
                 points=npts, steps=args.c4_steps, groups=b.groups())
 
 
+def run_c3_precision(args, dev):
+    """The 512^2 flat crossing sea (SA mode) in FP32 and FP64 side by side: FP32
+    throughput and its error against the FP64 run (max |eta| and relative energy
+    drift; both diagnostics in FP64)."""
+    import numpy as np
+    import torch
+
+    from paper_2310_19840_amd import Solver
+    from sbi_inputs import config_c3
+
+    cfg = config_c3(seed=3, n=512)
+    g = cfg["grid"]
+    out = {}
+    fields = {}
+    for prec, dt_ in (("fp64", torch.float64), ("fp32", torch.float32)):
+        s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="sa", precision=prec)
+        eta = torch.tensor(cfg["eta"][None], dtype=dt_, device=dev)
+        phi = torch.tensor(cfg["phi"][None], dtype=dt_, device=dev)
+        m0, e0 = s.diagnostics(eta, phi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(eta, phi, cfg["dt"], args.c3_steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        m1, e1 = s.diagnostics(eta, phi)
+        fields[prec] = eta.double().cpu().numpy()[0]
+        out[prec] = dict(value=g.nx * g.ny * args.c3_steps / el, ms_per_step=1e3 * el / args.c3_steps,
+                         energy_drift=float(abs(e1[0] - e0[0]) / abs(e0[0])),
+                         mass_change=float(abs(m1[0] - m0[0])))
+    err = float(np.abs(fields["fp32"] - fields["fp64"]).max() / np.abs(fields["fp64"]).max())
+    return dict(steps=args.c3_steps, grid=[g.ny, g.nx], mode="sa", fp32=out["fp32"], fp64=out["fp64"],
+                fp32_max_eta_rel_error=err)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,7 +283,8 @@ def main():
     ap.add_argument("--batch-sweeps", type=int, default=64, help="sweep budget per solve of the captured forms")
     ap.add_argument("--members", type=int, default=2, help="realisations of the batched forms")
     ap.add_argument("--c4-steps", type=int, default=4)
-    ap.add_argument("--forms", default="plain,batched+prev,batched+learned,plain-fp32,c4")
+    ap.add_argument("--c3-steps", type=int, default=32)
+    ap.add_argument("--forms", default="plain,batched+prev,batched+learned,plain-fp32,c4,c3-precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -283,6 +319,8 @@ def main():
         out_forms["plain-fp32"]["tol"] = 1e-6
     if "c4" in forms:
         out_forms["c4"] = run_c4(args, dev)
+    if "c3-precision" in forms:
+        out_forms["c3-precision"] = run_c3_precision(args, dev)
     for f, d in out_forms.items():
         if isinstance(d.get("value"), float) and f != "plain":
             d["vs_plain"] = round(d["value"] / plain["value"], 3)
