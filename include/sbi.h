@@ -195,11 +195,17 @@ sbi_status sbi_destroy(sbi_ctx* ctx);
 const char* sbi_status_string(sbi_status s);
 
 /*
- * Kernel timing for profiling: when enabled, every launch of the following
- * calls is bracketed by HIP events on the context's stream.  sbi_profile_read
- * writes, per kernel class, its name (static string), summed device time in ms
- * and launch count since the last enable, and returns the number of classes.
+ * Kernel timing for profiling: when enabled, launches of the following calls
+ * are bracketed by HIP events on the context's stream; enable is
+ * SBI_PROFILE_ALL (every kernel class), SBI_PROFILE_SWEEPS (the row and column
+ * sweep passes of the iteration only: each bracket adds a few microseconds of
+ * idle device time, so timing fewer launches disturbs the run less) or
+ * SBI_PROFILE_OFF.  Synchronises the stream and clears the totals.
+ * sbi_profile_read writes, per kernel class, its name (static string), summed
+ * device time in ms and launch count since the last enable, and returns the
+ * number of classes.
  */
+enum { SBI_PROFILE_OFF = 0, SBI_PROFILE_ALL = 1, SBI_PROFILE_SWEEPS = 2 };
 sbi_status sbi_profile_enable(sbi_ctx* ctx, int32_t enable);
 int32_t sbi_profile_read(sbi_ctx* ctx, const char** names, double* total_ms, int64_t* launches, int32_t n);
 

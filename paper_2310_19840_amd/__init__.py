@@ -187,8 +187,10 @@ class Solver:
         n = self.lib.sbi_last_stats(self.ctx, out, 3)
         return dict(zip(("launches", "syncs", "sweeps"), out[:n]))
 
-    def profile(self, enable=True):
-        st = self.lib.sbi_profile_enable(self.ctx, int(bool(enable)))
+    def profile(self, enable=True, sweeps_only=False):
+        """Time kernel launches with HIP events (all classes, or the sweep passes only)."""
+        mode = _lib.SBI_PROFILE_OFF if not enable else (_lib.SBI_PROFILE_SWEEPS if sweeps_only else _lib.SBI_PROFILE_ALL)
+        st = self.lib.sbi_profile_enable(self.ctx, mode)
         if st < 0:
             raise SBIError(st, "sbi_profile_enable")
 

@@ -18,6 +18,8 @@ SBI_ERR_HIP = -4
 SBI_ERR_NONFINITE = -5
 SBI_ERR_DIVERGED = -6
 
+SBI_PROFILE_OFF, SBI_PROFILE_ALL, SBI_PROFILE_SWEEPS = 0, 1, 2
+
 SBI_FP64, SBI_FP32 = 0, 1
 SBI_MODE_ITER, SBI_MODE_SA = 0, 1
 SBI_SEED_LINEAR, SBI_SEED_PREV, SBI_SEED_NET, SBI_SEED_USER = 0, 1, 2, 3

@@ -75,6 +75,7 @@ const char* const kKernelNames[K_COUNT] = {
 
 struct Profiler {
     bool on = false;
+    unsigned mask = 0;                  // kernel classes timed (bit per class)
     std::vector<hipEvent_t> pool;       // free events
     struct Pending { int cls; hipEvent_t a, b; };
     std::vector<Pending> pending;
@@ -122,6 +123,7 @@ struct sbi_ctx {
     Stats st;
     Profiler prof;
     Ctl* head = nullptr;     // pinned host copy of the control headers
+    hipEvent_t poll = nullptr;  // marks a header copy the host waits for while sweeps run on
     sbi_step_info step_acc{};
 };
 
@@ -390,6 +392,12 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
         delete c;
         return SBI_ERR_HIP;
     }
+    if (hipEventCreateWithFlags(&c->poll, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(c->head);
+        if (c->own_ws) (void)hipFree(c->ws);
+        delete c;
+        return SBI_ERR_HIP;
+    }
     // SBI_COL_GROUP_TARGET: workgroups a column pass aims for by splitting its
     // products over workgroups (tuning knob; 0 = one workgroup per tile)
     if (const char* e = std::getenv("SBI_COL_GROUP_TARGET")) c->group_target = std::atoi(e);
@@ -420,6 +428,7 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
     if (st < 0) {
         if (c->own_ws) (void)hipFree(c->ws);
         (void)hipHostFree(c->head);
+        (void)hipEventDestroy(c->poll);
         delete c;
         return st;
     }
@@ -432,6 +441,7 @@ extern "C" sbi_status sbi_destroy(sbi_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     prof_flush(c);
     for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(c->poll);
     (void)hipHostFree(c->head);
     if (c->own_ws) {
         (void)hipStreamSynchronize(c->stream);
@@ -567,7 +577,7 @@ struct ProfScope {
     int cls;
     hipEvent_t a = nullptr;
     ProfScope(sbi_ctx* cc, int k) : c(cc), cls(k) {
-        if (c->prof.on) {
+        if (c->prof.on && ((c->prof.mask >> k) & 1u)) {
             a = prof_event(c);
             (void)hipEventRecord(a, c->stream);
         }
@@ -843,36 +853,52 @@ static sbi_status read_heads(sbi_ctx* c) {
     return SBI_OK;
 }
 
-// iteration: device-side convergence decisions, host polls in predicted chunks
+// iteration: device-side convergence decisions, host polls in predicted
+// chunks.  At each poll the control headers are copied behind the chunk and
+// kAhead more sweeps are enqueued before the host waits for the copy, so the
+// device keeps sweeping while the host decides; sweeps enqueued after a
+// member's solve was decided return at once.
 static sbi_status iterate(sbi_ctx* c, const void* eta_phys, double tol) {
+    constexpr int kAhead = 1;
     const int M = c->grid.max_sweeps;
-    int n = 0;
+    int n = 0;  // next sweep to enqueue
     int chunk = 4;
+    bool final_heads = false;  // c->head reflects every enqueued sweep
     std::vector<double> r_prev(c->batch, -1.0);
     std::vector<int> n_prev(c->batch, 0);
     while (n <= M) {
         for (int i = 0; i < chunk && n <= M; ++i, ++n) SBI_TRY(launch_sweep(c, eta_phys, n, tol));
-        SBI_TRY(read_heads(c));
+        const int np = n;  // sweeps the header copy follows
+        SBI_HIP(hipMemcpyAsync(c->head, c->ctl, sizeof(Ctl) * c->batch, hipMemcpyDeviceToHost, c->stream));
+        SBI_HIP(hipEventRecord(c->poll, c->stream));
+        for (int i = 0; i < kAhead && n <= M; ++i, ++n) SBI_TRY(launch_sweep(c, eta_phys, n, tol));
+        SBI_HIP(hipEventSynchronize(c->poll));
+        c->st.syncs += 1;
         bool all_done = true;
         int want = 1;
         for (int b = 0; b < c->batch; ++b) {
             const Ctl& h = c->head[b];
             if (h.done) continue;
             all_done = false;
-            // residual r_(n-2) is the latest decided one; predict the remaining sweeps
+            // residual r_(np-2) is the latest decided one; predict the remaining sweeps
             const double r = h.residual;
             int rem = 4;
-            if (r_prev[b] > 0.0 && r > 0.0 && r < r_prev[b] && n - 2 > n_prev[b]) {
-                const double rho = std::pow(r / r_prev[b], 1.0 / (double)(n - 2 - n_prev[b]));
+            if (r_prev[b] > 0.0 && r > 0.0 && r < r_prev[b] && np - 2 > n_prev[b]) {
+                const double rho = std::pow(r / r_prev[b], 1.0 / (double)(np - 2 - n_prev[b]));
                 if (rho > 0.0 && rho < 1.0) rem = (int)std::ceil(std::log(tol / r) / std::log(rho)) + 1;
             }
             r_prev[b] = r;
-            n_prev[b] = n - 2;
+            n_prev[b] = np - 2;
             want = std::max(want, rem);
         }
-        if (all_done) break;
-        chunk = std::min(std::max(want, 1), 64);
+        if (all_done) {
+            final_heads = true;  // later sweeps returned at once and changed no header
+            break;
+        }
+        chunk = std::min(std::max(want - (n - np), 1), 64);
     }
+    // the look-ahead sweeps after the last poll may have decided the solves
+    if (!final_heads) SBI_TRY(read_heads(c));
     return SBI_OK;
 }
 
@@ -1389,10 +1415,12 @@ extern "C" sbi_status sbi_diagnostics(sbi_ctx* c, const sbi_state* state, double
 }
 
 extern "C" sbi_status sbi_profile_enable(sbi_ctx* c, int32_t enable) {
-    if (!c) return SBI_ERR_INVALID_ARG;
+    if (!c || (enable != SBI_PROFILE_OFF && enable != SBI_PROFILE_ALL && enable != SBI_PROFILE_SWEEPS))
+        return SBI_ERR_INVALID_ARG;
     SBI_HIP(hipStreamSynchronize(c->stream));
     prof_flush(c);
-    c->prof.on = enable != 0;
+    c->prof.on = enable != SBI_PROFILE_OFF;
+    c->prof.mask = enable == SBI_PROFILE_SWEEPS ? ((1u << K_ROW_SWEEP) | (1u << K_COL_SWEEP)) : ~0u;
     for (int k = 0; k < K_COUNT; ++k) {
         c->prof.total_ms[k] = 0.0;
         c->prof.count[k] = 0;

@@ -4,10 +4,11 @@
 
 namespace sbi {
 
-// columns per column-pass workgroup (equals ColCfg<R, NY, QB>::C of the kernels;
+// columns per column-pass workgroup (equals ColCfg<R, NY, QB, NACC>::C of the kernels;
 // the launcher checks it)
 int col_tile(int ny, int fp64, int qb) {
     if (ny == 1) return 64;
+    if (qb && ny == 1024) return 1;  // one wavefront per column transform
     int e = (fp64 && !qb) ? 4 : 8;
     if (e > ny) e = ny;
     const int P = ny / e;

@@ -110,10 +110,51 @@ template <bool INV, typename V> struct Dft<8, INV, V> {
     }
 };
 
+// a * W16^e, W16 = exp(-i pi/8) forward, exp(+i pi/8) inverse, given
+// c = cos(pi e/8) and s = sin(pi e/8)
+template <bool INV, typename V> __device__ __forceinline__ V rot16(V a, decltype(V::x) c, decltype(V::x) s) {
+    return INV ? cx<V>(a.x * c - a.y * s, a.y * c + a.x * s) : cx<V>(a.x * c + a.y * s, a.y * c - a.x * s);
+}
+
+// 16 points as 4 x 4: DFTs of length 4 over the stride-4 subsequences, the
+// twiddles W16^(n2 k1), then DFTs of length 4 across them; output in natural
+// order.
+template <bool INV, typename V> struct Dft<16, INV, V> {
+    static __device__ __forceinline__ void run(V* a) {
+        using T = decltype(V::x);
+        const T c1 = T(0.92387953251128675612818318939678828682);  // cos(pi/8)
+        const T s1 = T(0.38268343236508977172845998403039886676);  // sin(pi/8)
+        const T r2 = T(0.70710678118654752440084436210484903928);
+        V y[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) y[n2][n1] = a[n2 + 4 * n1];
+            Dft<4, INV, V>::run(y[n2]);
+        }
+        y[1][1] = rot16<INV>(y[1][1], c1, s1);
+        y[1][2] = rot16<INV>(y[1][2], r2, r2);
+        y[1][3] = rot16<INV>(y[1][3], s1, c1);
+        y[2][1] = rot16<INV>(y[2][1], r2, r2);
+        y[2][2] = mul_mi<INV>(y[2][2]);
+        y[2][3] = rot16<INV>(y[2][3], -r2, r2);
+        y[3][1] = rot16<INV>(y[3][1], s1, c1);
+        y[3][2] = rot16<INV>(y[3][2], -r2, r2);
+        y[3][3] = rot16<INV>(y[3][3], -c1, -s1);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            V z[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+            Dft<4, INV, V>::run(z);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = z[k2];
+        }
+    }
+};
+
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
 // Elements per thread for a length-N transform (at most EMAX, a power of two
-// in {2, 4, 8}).
+// in {2, 4, 8, 16}).
 template <int N, int EMAX = 8> struct FftShape {
     static constexpr int E = N >= EMAX ? EMAX : N;
     static constexpr int P = N / E;
@@ -193,6 +234,12 @@ __device__ __forceinline__ void stockham_pass(V (&v)[E], V* lds, int lo, int j, 
         if constexpr (Ns > 1) {
             // base twiddle from the cache; higher powers by recurrence
             V w1 = tw.w[TwOffset<N, E, Ns>::value + s];
+            if constexpr (E >= 16) {
+                // with 16 elements per thread the powers of every pass (15 of
+                // them in a radix-16 pass) would otherwise be hoisted out of
+                // the caller's loops and held in registers
+                asm volatile("" : "+v"(w1.x), "+v"(w1.y));
+            }
             if (INV) w1.y = -w1.y;
             V wr = w1;
             u[1] = cmul(u[1], w1);

@@ -623,15 +623,28 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_feat(const RowFeatPar
 // forms are column-major, so each column is one contiguous run); product
 // lanes (threads transforming different products of the same columns) fill up
 // to 512 threads, at most 2 in FP64 without QB and 4 otherwise.
-template <typename R, int NY, bool QB> struct ColCfg {
-    static constexpr int CE = (sizeof(R) == 8 && !QB) ? 4 : 8;
+// WV ("wave lanes", QB at NY = 1024 with at most 2 accumulators in FP64):
+// 16 elements per thread, so a single wavefront owns a whole column
+// transform; one column per workgroup and up to 8 product lanes of one
+// wavefront each, which never wait on one another until their sums are
+// combined.  (Four FP64 accumulators of 16 elements do not fit in registers.)
+// WAVE: every column transform lies within one wavefront, so its exchanges
+// order only that wavefront.
+template <typename R, int NY, bool QB, int NACC> struct ColCfg {
+    static constexpr bool WV = QB && NY == 1024 && (sizeof(R) == 4 || NACC <= 2);
+    static constexpr int CE = WV ? 16 : ((sizeof(R) == 8 && !QB) ? 4 : 8);
     static constexpr int E = FftShape<NY, CE>::E;
     static constexpr int P = FftShape<NY, CE>::P;
-    static constexpr int C = NY == 1 ? 64 : (P >= 128 ? 1 : 256 / P);
-    static constexpr int LMAX = (sizeof(R) == 8 && !QB) ? 2 : 4;
+    static constexpr int C = NY == 1 ? 64 : ((WV || P >= 128) ? 1 : 256 / P);
+    static constexpr int LMAX = WV ? 8 : ((sizeof(R) == 8 && !QB) ? 2 : 4);
     static constexpr int FIT = 512 / (C * P);
     static constexpr int PL = NY == 1 ? 1 : (FIT < 1 ? 1 : (FIT < LMAX ? FIT : LMAX));
     static constexpr int THREADS = PL * C * P;
+    static constexpr bool WAVE = P <= 64;
+    // the next round's column is loaded during the current transform, except
+    // in FP64 wave lanes, whose registers cannot hold a second column (the
+    // other wavefront of the SIMD covers the load instead)
+    static constexpr bool PREFETCH = !(WV && sizeof(R) == 8);
     // LDS: the transform exchange area of every lane and column (none for 1D
     // grids, whose "columns" are single values), then the mode-geometry table
     // of C * Ky entries of 4 reals
@@ -672,13 +685,16 @@ template <typename R, typename V, int E, int NACC>
 __device__ __forceinline__ void col_apply_terms(const short* toff, const ColTerm* term, int src, const V (&v)[E],
                                                 V (&acc)[NACC][E], const int (&crow)[E], const R* __restrict__ geo,
                                                 R kxr) {
-    for (int ti = toff[src]; ti < toff[src + 1]; ++ti) {
-        const ColTerm tm = term[ti];
+    // modes outer, terms inner: only one mode's geometry is live at a time
+    // (each accumulator still sums its terms in table order)
+    const int t0 = toff[src], t1 = toff[src + 1];
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
-            if (crow[q] < 0) continue;
-            const R* gq = geo + crow[q] * 4;
-            const R kq = gq[0];
+    for (int q = 0; q < E; ++q) {
+        if (crow[q] < 0) continue;
+        const R* gq = geo + crow[q] * 4;
+        const R kq = gq[0];
+        for (int ti = t0; ti < t1; ++ti) {
+            const ColTerm tm = term[ti];
             R m = R(tm.coef);
             if (tm.fn == FN_T) m *= gq[1];
             else if (tm.fn == FN_S) m *= gq[2];
@@ -726,10 +742,10 @@ __device__ __forceinline__ V col_source(const ColParams& p, int src, int q, cons
 // transform alternate products of the same columns (more waves per CU to hide
 // memory latency); their partial sums are combined through LDS
 template <typename R, int NY, int NACC, bool QB>
-__global__ void __launch_bounds__((ColCfg<R, NY, QB>::THREADS))
+__global__ void __launch_bounds__((ColCfg<R, NY, QB, NACC>::THREADS))
 k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     using V = typename cplx_of<R>::type;
-    using CF = ColCfg<R, NY, QB>;
+    using CF = ColCfg<R, NY, QB, NACC>;
     constexpr int N = NY;
     constexpr int CE = CF::CE;
     constexpr int E = CF::E;
@@ -847,15 +863,21 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
 #pragma unroll
         for (int q = 0; q < E; ++q) acc[a][q] = cx<V>(R(0), R(0));
 
-    // forward column transforms of this workgroup's products: lane L takes
-    // products s0 + L, s0 + L + PL, ...; every lane runs the same number of
-    // rounds (empty slots transform zeros) so the barriers line up.  The next
+    // jobs of this workgroup: its products (forward column transforms), then,
+    // in the first product group only, the compact inputs, whose kept values
+    // enter the same multiplier sums without a transform.  Lane L takes jobs
+    // L, L + PL, ...; every lane runs the same number of rounds (slots that
+    // are not products transform zeros so that workgroup barriers line up,
+    // or skip the transform when it synchronises per wavefront).  The next
     // round's column is loaded before the current transform runs.
     const int s0 = p.ngroup > 1 ? p.gstart[grp] : 0;
     const int s1 = p.ngroup > 1 ? p.gstart[grp + 1] : p.nprod;
-    const int rounds = (s1 - s0 + PL - 1) / PL;
-    auto load_col = [&](int s, V (&dst)[E]) __attribute__((always_inline)) {
-        if (s < s1) {
+    const int nps = s1 - s0;
+    const int njob = nps + (grp == 0 ? p.ncin : 0);
+    const int rounds = (njob + PL - 1) / PL;
+    auto load_col = [&](int jb, V (&dst)[E]) __attribute__((always_inline)) {
+        if (jb < nps) {
+            const int s = s0 + jb;
             const long long st = p.hin_stride[s] ? p.hin_stride[s] : g.s_half;
             const V* H = static_cast<const V*>(p.hin[s]) + mem * st + (long long)mx * g.ldh;
 #pragma unroll
@@ -866,15 +888,32 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         }
     };
     V v[E];
-    if (rounds > 0) load_col(s0 + lane, v);
+    if constexpr (CF::PREFETCH) {
+        if (rounds > 0) load_col(lane, v);
+    }
     for (int rd = 0; rd < rounds; ++rd) {
-        const int s = s0 + rd * PL + lane;
+        const int jb = rd * PL + lane;
+        const bool prod = jb < nps;
+        const int src = prod ? s0 + jb : p.nprod + (jb - nps);  // row of the term table
+        const bool live = jb < njob && s_toff[src] < s_toff[src + 1];
         V vn[E];
-        if (rd + 1 < rounds) load_col(s + PL, vn);
-        fft<V, N, false, 1, CE>(v, lds, 0, j, twc);
-        if (s < s1) col_apply_terms<R, V, E, NACC>(s_toff, s_term, s, v, acc, crow, geo, kxr);
+        if constexpr (CF::PREFETCH) {
+            if (rd + 1 < rounds) load_col(jb + PL, vn);
+        } else {
+            if (CF::WAVE && jb >= njob) break;
+            load_col(jb, v);
+        }
+        if (prod || !CF::WAVE) fft<V, N, false, 1, CE, CF::WAVE>(v, lds, 0, j, twc);
+        if (live && !prod) {
+            const V* Ci = static_cast<const V*>(p.cin[jb - nps]) + mem * g.s_cmp + (long long)mx * g.Ky;
 #pragma unroll
-        for (int q = 0; q < E; ++q) v[q] = vn[q];
+            for (int q = 0; q < E; ++q) v[q] = crow[q] >= 0 ? Ci[crow[q]] : cx<V>(R(0), R(0));
+        }
+        if (live) col_apply_terms<R, V, E, NACC>(s_toff, s_term, src, v, acc, crow, geo, kxr);
+        if constexpr (CF::PREFETCH) {
+#pragma unroll
+            for (int q = 0; q < E; ++q) v[q] = vn[q];
+        }
     }
     // combine the lanes' partial sums into lane 0
     if (PL > 1 && rounds > 0) {
@@ -943,18 +982,6 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
                 }
         }
     }
-    // compact inputs (lane 0 holds the sums)
-    if (lane == 0) {
-        for (int ci = 0; ci < p.ncin; ++ci) {
-            if (s_toff[p.nprod + ci] == s_toff[p.nprod + ci + 1]) continue;  // no term reads it
-            const V* Ci = static_cast<const V*>(p.cin[ci]) + mem * g.s_cmp;
-            V vc[E];
-#pragma unroll
-            for (int q = 0; q < E; ++q)
-                vc[q] = crow[q] >= 0 ? Ci[(long long)mx * g.Ky + crow[q]] : cx<V>(R(0), R(0));
-            col_apply_terms<R, V, E, NACC>(s_toff, s_term, p.nprod + ci, vc, acc, crow, geo, kxr);
-        }
-    }
     // broadcast the final sums to every lane
     if (PL > 1 && p.ninv > 1) {
 #pragma unroll
@@ -974,6 +1001,9 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
             }
         }
     }
+    // the exchange areas were last read across lanes (sums combined or
+    // broadcast): every lane is past those reads before it transforms again
+    if (PL > 1) lds_sync();
     // inverse column transforms, spread over the lanes (before any compact
     // output is written: NEW/DIFF sources re-read the previous iterate)
     const int lanes_used = (PL > 1 && p.ninv > 1) ? PL : 1;
@@ -981,6 +1011,7 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     for (int rd = 0; rd < irounds; ++rd) {
         const int o = rd * lanes_used + (lanes_used > 1 ? lane : 0);
         const bool mine = (lanes_used > 1 || lane == 0) && o < p.ninv;
+        if (CF::WAVE && !mine) continue;
         V vi[E];
         const int src = mine ? p.inv_src[o] : 0;
         const int dv = mine ? p.inv_dv[o] : 0;
@@ -994,7 +1025,7 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
             }
             vi[q] = sv;
         }
-        fft<V, N, true, 1, CE>(vi, lds, 0, j, twc);
+        fft<V, N, true, 1, CE, CF::WAVE>(vi, lds, 0, j, twc);
         if (mine) {
             V* G = static_cast<V*>(p.inv[o]) + mem * g.s_half + (long long)mx * g.ldh;
 #pragma unroll
@@ -1002,20 +1033,40 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         }
     }
     if (PL > 1) __syncthreads();  // inverse outputs (read prev) before compact outputs (write)
-    // compact outputs: every output of a mode is formed before any is written,
-    // so an output may overwrite an input of the same pass in place
+    // compact outputs: the previous iterates the relaxed sources need are read
+    // before any output is written, so an output may overwrite an input of
+    // the same pass in place
     if (lane == 0) {
+        V pv[2][E];
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
-            if (crow[q] >= 0) {
-                V vals[kMaxCout];
+        for (int a = 0; a < 2; ++a) {
+            const int pi = p.relax_prev[a];
+            const V* Pp = pi >= 0 ? static_cast<const V*>(p.cin[pi]) + mem * p.g.s_cmp + (long long)mx * p.g.Ky
+                                  : nullptr;
 #pragma unroll
-                for (int o = 0; o < kMaxCout; ++o)
-                    if (o < p.ncout) vals[o] = col_source<R, V, E, NACC>(p, p.cout_src[o], q, acc, crow[q], mem, mx, omega);
+            for (int q = 0; q < E; ++q)
+                pv[a][q] = (Pp && crow[q] >= 0) ? Pp[crow[q]] : cx<V>(R(0), R(0));
+        }
+        for (int o = 0; o < p.ncout; ++o) {
+            const int src = p.cout_src[o];
+            const bool relaxed = src >= SRC_NEW0;
+            const int a = relaxed ? ((src == SRC_NEW0 || src == SRC_DIFF0) ? 0 : 1) : src;
+            const bool diff = src >= SRC_DIFF0;
+            V* out = static_cast<V*>(p.cout[o]) + mem * g.s_cmp + (long long)mx * g.Ky;
 #pragma unroll
-                for (int o = 0; o < kMaxCout; ++o)
-                    if (o < p.ncout)
-                        static_cast<V*>(p.cout[o])[mem * g.s_cmp + (long long)mx * g.Ky + crow[q]] = vals[o];
+            for (int q = 0; q < E; ++q) {
+                if (crow[q] < 0) continue;
+                V cur = cx<V>(R(0), R(0));
+#pragma unroll
+                for (int k = 0; k < NACC; ++k)
+                    if (k == a) cur = acc[k][q];
+                V val = cur;
+                if (relaxed) {
+                    const V pq = a == 0 ? pv[0][q] : pv[1][q];
+                    const V d = csub(cur, pq);
+                    val = diff ? d : cadd(pq, cscale(d, R(omega)));
+                }
+                out[crow[q]] = val;
             }
         }
     }
@@ -1222,7 +1273,7 @@ SBI_ROW_LAUNCH(k_row_feat, RowFeatParams)
 template <typename R, int NY, int NACC, bool QB>
 static hipError_t col_go(const ColParams& p, int batch, const Twiddles& tw, hipStream_t s) {
     using V = typename cplx_of<R>::type;
-    using CF = ColCfg<R, NY, QB>;
+    using CF = ColCfg<R, NY, QB, NACC>;
     if (p.g.col_C != CF::C) return hipErrorInvalidValue;  // the layout was made for another tile
     dim3 block(CF::THREADS);
     dim3 grid(p.g.Kxp / CF::C, p.ngroup > 0 ? p.ngroup : 1, batch);

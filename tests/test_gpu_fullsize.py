@@ -1,0 +1,105 @@
+"""Parity at the full 1024^2 size of the crossing-sea workload, in the launch
+configuration the benchmark times (FP64 and FP32 iteration, one member).
+
+The oracle needs about a second per sweep at this size, so it does not repeat
+whole solves or steps; instead it checks properties that hold at any size:
+
+* the W the GPU converged to is a fixed point of the oracle's own summed
+  operator (App. C): seeded with the GPU's V and phi_b, the oracle's
+  iteration stops at once and moves W by no more than the tolerance;
+* one step conserves the mean elevation (mass), and the energy of Sec. 2
+  changes by far less than the scheme's dealiasing drift.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import sbi_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _c5():
+    return si.config_c5(seed=0, n=1024)
+
+
+@pytest.mark.parametrize("tol", [1e-8, 1e-11])
+def test_fullsize_w_is_an_oracle_fixed_point(gpu, tol):
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    cfg = _c5()
+    g = cfg["grid"]
+    _say("1024^2 fp64 fixed point, tol", tol)
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=gpu, mode="iter", max_sweeps=200, seed="prev")
+    eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=gpu)
+    phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=gpu)
+    W, st, info = s.vertical_velocity(eta, phi, tol=tol)
+    assert st == 0 and info[0][0] > 5, info
+    dv, db = s.last_correction()
+    Wg = W.cpu().numpy().reshape(g.ny, g.nx)
+    dbg = db.cpu().numpy().reshape(g.ny, g.nx)
+    o = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), cfg["depth"], mode="iter", max_sweeps=4)
+    Wo, oi = o.vertical_velocity(cfg["eta"], cfg["phi"], tol=tol, seed=Wg, seed_b=dbg)
+    _say("gpu sweeps", info[0][0], "oracle sweeps from the gpu iterate", oi.sweeps, "residual", oi.residual)
+    assert oi.status == 0 and oi.sweeps <= 2
+    assert _rel(Wg, Wo) <= 3 * tol
+
+
+def test_fullsize_fp32_w_is_near_the_oracle_fixed_point(gpu):
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    cfg = _c5()
+    g = cfg["grid"]
+    _say("1024^2 fp32 fixed point")
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=gpu, mode="iter", max_sweeps=200, seed="prev",
+               precision="fp32")
+    eta = torch.tensor(cfg["eta"][None], dtype=torch.float32, device=gpu)
+    phi = torch.tensor(cfg["phi"][None], dtype=torch.float32, device=gpu)
+    W, st, info = s.vertical_velocity(eta, phi, tol=1e-6)
+    assert st == 0, info
+    _, db = s.last_correction()
+    Wg = W.cpu().numpy().reshape(g.ny, g.nx).astype(np.float64)
+    dbg = db.cpu().numpy().reshape(g.ny, g.nx).astype(np.float64)
+    # the oracle sees the same FP32-rounded inputs and iterates from the GPU's
+    # result to 1e-9
+    e64 = eta.cpu().numpy().reshape(g.ny, g.nx).astype(np.float64)
+    p64 = phi.cpu().numpy().reshape(g.ny, g.nx).astype(np.float64)
+    o = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), cfg["depth"], mode="iter", max_sweeps=40)
+    Wo, oi = o.vertical_velocity(e64, p64, tol=1e-9, seed=Wg, seed_b=dbg)
+    _say("oracle sweeps from the fp32 iterate", oi.sweeps)
+    assert oi.status == 0
+    assert _rel(Wg, Wo) <= 1e-5
+
+
+def test_fullsize_step_conserves_mass_and_energy(gpu):
+    import torch
+    from paper_2310_19840_amd import Solver
+    cfg = _c5()
+    g = cfg["grid"]
+    _say("1024^2 fp64 step invariants")
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=gpu, mode="iter", max_sweeps=200)
+    eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=gpu)
+    phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=gpu)
+    m0, e0 = s.diagnostics(eta, phi, tol=1e-11)
+    st, info = s.step(eta, phi, cfg["dt"], 2, tol=1e-8)
+    assert st == 0 and info["solves"] == 8
+    m1, e1 = s.diagnostics(eta, phi, tol=1e-11)
+    area = g.lx * g.ly
+    amp = float(np.abs(cfg["eta"]).max())
+    assert abs(m1[0] - m0[0]) <= 1e-12 * amp * area
+    # two steps of T/64 move the energy by well under the dealiasing drift
+    # (about 1e-4 per 32 steps on this sea)
+    assert abs(e1[0] - e0[0]) <= 1e-5 * abs(e0[0])
+    assert np.isfinite(eta.cpu().numpy()).all()
