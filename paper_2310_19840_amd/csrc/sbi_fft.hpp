@@ -191,7 +191,8 @@ template <int N, int E, int Ns, int Cur> struct TwOffset<N, E, Ns, Cur, true> {
 template <typename V, int N, int E> struct Twid {
     static constexpr int NT = TwCountFrom<N, E, 1>::value;
     V w[NT > 0 ? NT : 1];
-    template <int Ns> __device__ __forceinline__ void load_from(const V* __restrict__ tw, int j) {
+    // tw: table of exp(-2 pi i m / (N stride)), read at every stride-th entry
+    template <int Ns> __device__ __forceinline__ void load_from(const V* __restrict__ tw, int j, int stride) {
         if constexpr (Ns < N) {
             using PI = PassInfo<N, E, Ns>;
             if constexpr (Ns > 1) {
@@ -201,13 +202,13 @@ template <typename V, int N, int E> struct Twid {
                 for (int s = 0; s < PI::B; ++s) {
                     const int b = j + s * P;
                     const int k = b & (Ns - 1);
-                    w[off + s] = tw[k * (N / (Ns * PI::R))];
+                    w[off + s] = tw[stride * k * (N / (Ns * PI::R))];
                 }
             }
-            load_from<PI::NEXT>(tw, j);
+            load_from<PI::NEXT>(tw, j, stride);
         }
     }
-    __device__ __forceinline__ void load(const V* __restrict__ tw, int j) { load_from<1>(tw, j); }
+    __device__ __forceinline__ void load(const V* __restrict__ tw, int j, int stride = 1) { load_from<1>(tw, j, stride); }
 };
 
 // LDS slot of transform element idx: the first Stockham pass writes with a
@@ -234,10 +235,10 @@ __device__ __forceinline__ void stockham_pass(V (&v)[E], V* lds, int lo, int j, 
         if constexpr (Ns > 1) {
             // base twiddle from the cache; higher powers by recurrence
             V w1 = tw.w[TwOffset<N, E, Ns>::value + s];
-            if constexpr (E >= 16) {
-                // with 16 elements per thread the powers of every pass (15 of
-                // them in a radix-16 pass) would otherwise be hoisted out of
-                // the caller's loops and held in registers
+            if constexpr (E >= 8) {
+                // the powers of every pass (up to 15 in a radix-16 pass) would
+                // otherwise be hoisted out of the caller's loops and held in
+                // registers for the whole kernel
                 asm volatile("" : "+v"(w1.x), "+v"(w1.y));
             }
             if (INV) w1.y = -w1.y;

@@ -677,10 +677,88 @@ __device__ __forceinline__ int sweep_decision(Ctl* ctl, int n, int M, double tol
     return 0;
 }
 
-// Per-mode geometry of a column tile, held in LDS: for kept mode (c, r),
-// geo[(c * Ky + r) * 4 + {0, 1, 2, 3}] = {k, tanh(k h), sech(k h), k_y}.
+// Sweep control of a column pass: decides the solve from the previous
+// sweep's residual (false: this launch has nothing to do) and gives the
+// relaxation weight; the leader thread updates the control header.
+__device__ __forceinline__ bool col_control(const ColParams& p, Ctl* ctl, bool leader, double* omega) {
+    const GridDev& g = p.g;
+    if (p.ctl_mode == CTL_SWEEP) {
+        if (ctl->done) return false;
+        double r, rmin;
+        const int dec = sweep_decision(ctl, p.sweep, p.max_sweeps, p.tol, &r, &rmin);
+        if (dec) {
+            if (leader) {
+                const int st = dec - 100;
+                ctl->status = st;
+                ctl->sweeps = p.sweep;
+                ctl->residual = r;
+                ctl->done = 1;
+                ctl->acc_solves += 1;
+                ctl->acc_sweeps += p.sweep;
+                ctl->acc_sweeps_max = max(ctl->acc_sweeps_max, p.sweep);
+                ctl->acc_residual_max = fmax(ctl->acc_residual_max, r);
+                const int w = ctl->acc_worst;
+                if (st < 0 ? (w >= 0 || st < w) : (w >= 0 && st > w)) ctl->acc_worst = st;
+            }
+            return false;
+        }
+        if (leader) {
+            ctl->rmin = rmin;
+            ctl->residual = r;
+        }
+        *omega = ctl->omega;
+    } else if (p.ctl_mode == CTL_OMEGA) {
+        // relaxation weight from the local symbol sum_{j<=J} (k eta)^j / j!
+        const double emax = unord_bits(ctl->eta_max), emin = unord_bits(ctl->eta_min);
+        const int J = g.order - 1;
+        double w = 1.0;
+        if (g.relax && J >= 1) {
+            double lmax = 0.0, lmin = 0.0, tmax = 1.0, tmin = 1.0;
+            const double xmax = g.kband * emax, xmin = g.kband * emin;
+            for (int jj = 0; jj <= J; ++jj) {
+                if (jj > 0) {
+                    tmax *= xmax / jj;
+                    tmin *= xmin / jj;
+                }
+                lmax += tmax;
+                lmin += tmin;
+            }
+            const double s = lmin + lmax;
+            if (isfinite(s) && s > 0.0) w = fmin(1.0, 2.0 / s);
+        }
+        *omega = w;
+        if (leader) ctl->omega = w;
+    }
+    return true;
+}
+
+// Stage a column pass's term table and the geometry of its C columns' kept
+// modes in LDS: geo[(c * Ky + r) * 4 + {0, 1, 2, 3}] = {k, tanh(k h), sech(k h),
+// k_y} (the caller synchronises).
+template <typename R>
+__device__ __forceinline__ void col_stage_tables(const ColParams& p, int x0, int C, double href, R* geo_all,
+                                                 ColTerm* s_term, short* s_toff) {
+    const GridDev& g = p.g;
+    const int t = threadIdx.x;
+    for (int i = t; i < p.nterm; i += blockDim.x) s_term[i] = p.term[i];
+    for (int i = t; i <= p.nprod + p.ncin; i += blockDim.x) s_toff[i] = p.toff[i];
+    for (int idx = t; idx < C * g.Ky; idx += blockDim.x) {
+        const int c2 = idx / g.Ky, r2 = idx % g.Ky;
+        const int my = r2 <= g.My ? r2 : r2 - g.Ky;
+        const double kx2 = 2.0 * M_PI * (double)(x0 + c2) / g.lx;
+        const double ky = (g.ny == 1) ? 0.0 : 2.0 * M_PI * (double)my / g.ly;
+        const double k = sqrt(kx2 * kx2 + ky * ky);
+        R* gq = geo_all + idx * 4;
+        gq[0] = R(k);
+        gq[1] = R(tanh(k * href));
+        gq[2] = R(sech_d(k * href));
+        gq[3] = R(ky);
+    }
+}
+
 // multiplier sum of one source into the accumulators (kept modes only)
-// toff, term: the pass's term table, staged in LDS
+// toff, term: the pass's term table, staged in LDS; geo: the column's mode
+// geometry (col_stage_tables)
 template <typename R, typename V, int E, int NACC>
 __device__ __forceinline__ void col_apply_terms(const short* toff, const ColTerm* term, int src, const V (&v)[E],
                                                 V (&acc)[NACC][E], const int (&crow)[E], const R* __restrict__ geo,
@@ -771,53 +849,7 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     Ctl* ctl = p.ctl ? p.ctl + mem : nullptr;
 
     double omega = 1.0;
-    if (p.ctl_mode == CTL_SWEEP) {
-        if (ctl->done) return;
-        double r, rmin;
-        const int dec = sweep_decision(ctl, p.sweep, p.max_sweeps, p.tol, &r, &rmin);
-        if (dec) {
-            if (blockIdx.x == 0 && grp == 0 && t == 0) {
-                const int st = dec - 100;
-                ctl->status = st;
-                ctl->sweeps = p.sweep;
-                ctl->residual = r;
-                ctl->done = 1;
-                ctl->acc_solves += 1;
-                ctl->acc_sweeps += p.sweep;
-                ctl->acc_sweeps_max = max(ctl->acc_sweeps_max, p.sweep);
-                ctl->acc_residual_max = fmax(ctl->acc_residual_max, r);
-                const int w = ctl->acc_worst;
-                if (st < 0 ? (w >= 0 || st < w) : (w >= 0 && st > w)) ctl->acc_worst = st;
-            }
-            return;
-        }
-        if (blockIdx.x == 0 && grp == 0 && t == 0) {
-            ctl->rmin = rmin;
-            ctl->residual = r;
-        }
-        omega = ctl->omega;
-    } else if (p.ctl_mode == CTL_OMEGA) {
-        // relaxation weight from the local symbol sum_{j<=J} (k eta)^j / j!
-        const double emax = unord_bits(ctl->eta_max), emin = unord_bits(ctl->eta_min);
-        const int J = g.order - 1;
-        double w = 1.0;
-        if (g.relax && J >= 1) {
-            double lmax = 0.0, lmin = 0.0, tmax = 1.0, tmin = 1.0;
-            const double xmax = g.kband * emax, xmin = g.kband * emin;
-            for (int jj = 0; jj <= J; ++jj) {
-                if (jj > 0) {
-                    tmax *= xmax / jj;
-                    tmin *= xmin / jj;
-                }
-                lmax += tmax;
-                lmin += tmin;
-            }
-            const double s = lmin + lmax;
-            if (isfinite(s) && s > 0.0) w = fmin(1.0, 2.0 / s);
-        }
-        omega = w;
-        if (blockIdx.x == 0 && grp == 0 && t == 0) ctl->omega = w;
-    }
+    if (!col_control(p, ctl, blockIdx.x == 0 && grp == 0 && t == 0, &omega)) return;
 
     Twid<V, N, E> twc;
     twc.load(twY, j);
@@ -838,21 +870,8 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     // only, never on the prefetched column in flight
     __shared__ ColTerm s_term[kMaxTerms];
     __shared__ short s_toff[kMaxProd + kMaxCin + 1];
-    for (int i = t; i < p.nterm; i += blockDim.x) s_term[i] = p.term[i];
-    for (int i = t; i <= p.nprod + p.ncin; i += blockDim.x) s_toff[i] = p.toff[i];
     R* geo_all = reinterpret_cast<R*>(reinterpret_cast<V*>(smem_raw) + CF::XFORM);
-    for (int idx = t; idx < C * g.Ky; idx += blockDim.x) {
-        const int c2 = idx / g.Ky, r2 = idx % g.Ky;
-        const int my = r2 <= g.My ? r2 : r2 - g.Ky;
-        const double kx2 = 2.0 * M_PI * (double)(x0 + c2) / g.lx;
-        const double ky = (N == 1) ? 0.0 : 2.0 * M_PI * (double)my / g.ly;
-        const double k = sqrt(kx2 * kx2 + ky * ky);
-        R* gq = geo_all + idx * 4;
-        gq[0] = R(k);
-        gq[1] = R(tanh(k * href));
-        gq[2] = R(sech_d(k * href));
-        gq[3] = R(ky);
-    }
+    col_stage_tables<R>(p, x0, C, href, geo_all, s_term, s_toff);
     __syncthreads();
     const R* geo = geo_all + c * g.Ky * 4;
     const R kxr = R(kx);
@@ -1043,6 +1062,239 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
             const int pi = p.relax_prev[a];
             const V* Pp = pi >= 0 ? static_cast<const V*>(p.cin[pi]) + mem * p.g.s_cmp + (long long)mx * p.g.Ky
                                   : nullptr;
+#pragma unroll
+            for (int q = 0; q < E; ++q)
+                pv[a][q] = (Pp && crow[q] >= 0) ? Pp[crow[q]] : cx<V>(R(0), R(0));
+        }
+        for (int o = 0; o < p.ncout; ++o) {
+            const int src = p.cout_src[o];
+            const bool relaxed = src >= SRC_NEW0;
+            const int a = relaxed ? ((src == SRC_NEW0 || src == SRC_DIFF0) ? 0 : 1) : src;
+            const bool diff = src >= SRC_DIFF0;
+            V* out = static_cast<V*>(p.cout[o]) + mem * g.s_cmp + (long long)mx * g.Ky;
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                if (crow[q] < 0) continue;
+                V cur = cx<V>(R(0), R(0));
+#pragma unroll
+                for (int k = 0; k < NACC; ++k)
+                    if (k == a) cur = acc[k][q];
+                V val = cur;
+                if (relaxed) {
+                    const V pq = a == 0 ? pv[0][q] : pv[1][q];
+                    const V d = csub(cur, pq);
+                    val = diff ? d : cadd(pq, cscale(d, R(omega)));
+                }
+                out[crow[q]] = val;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass in wave pairs (1024 rows, quarter band, at most two
+// accumulators, one product group).  Decimation in frequency splits a
+// 1024-point column transform into the 512-point transforms of its even and
+// odd outputs: wave 0 of a pair transforms u0[n] = x[n] + x[n + 512] and
+// wave 1 u1[n] = (x[n] - x[n + 512]) W^n, W = exp(-2 pi i / 1024), so that
+// X[2k] = U0[k] and X[2k + 1] = U1[k].  Both waves read the whole column (the
+// second read is served by the cache) and transform with wave-level
+// ordering only; a thread of wave h holds the modes 2 (j + 64 q) + h.  The
+// inverse runs the other way: each wave inverts its half of the modes, the
+// odd half is multiplied by W^-n, and the pair forms x[n] = e[n] + o[n] and
+// x[n + 512] = e[n] - o[n] through LDS.  Seven pairs (14 wavefronts, at most
+// 128 registers each) share the workgroup of one column.
+// ---------------------------------------------------------------------------
+struct ColPairCfg {
+    static constexpr int N = 1024, NH = 512, E = 8, P = 64;
+    static constexpr int PL = 7;
+    static constexpr int THREADS = PL * 2 * P;
+    static constexpr int REG = fft_lds_elems<NH, E>();  // LDS elements of one wave's exchange area
+    static constexpr bool keepable(int q) { return q < E / 4 || q >= E - E / 4; }
+    template <typename R> static constexpr size_t lds_bytes(int Ky) {
+        return (size_t)PL * 2 * REG * sizeof(typename cplx_of<R>::type) + (size_t)Ky * 4 * sizeof(R);
+    }
+};
+
+template <typename R, int NACC>
+__global__ void __launch_bounds__(ColPairCfg::THREADS)
+k_colp(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
+    using V = typename cplx_of<R>::type;
+    using CF = ColPairCfg;
+    constexpr int N = CF::N, NH = CF::NH, E = CF::E, P = CF::P, PL = CF::PL, REG = CF::REG;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    const int t = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(t / P);
+    const int lane = wv >> 1;  // pair
+    const int h = wv & 1;      // 0: even outputs, 1: odd outputs
+    const int j = t % P;
+    V* const xch = reinterpret_cast<V*>(smem_raw);
+    V* lds = xch + wv * REG;
+    const int mem = blockIdx.z;
+    const int mx = blockIdx.x;
+    const GridDev& g = p.g;
+    Ctl* ctl = p.ctl ? p.ctl + mem : nullptr;
+    double omega = 1.0;
+    if (!col_control(p, ctl, blockIdx.x == 0 && t == 0, &omega)) return;
+
+    Twid<V, NH, E> twc;
+    twc.load(twY, j, 2);  // the 512-point twiddles are every other 1024-point one
+    const double href = g.href[mem];
+    const double kx = 2.0 * M_PI * (double)mx / g.lx;
+    int crow[E];  // compact row of mode 2 (j + qP) + h, -1 if not kept
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int n = 2 * (j + q * P) + h;
+        const int my = (n <= N / 2) ? n : n - N;
+        const bool keep = CF::keepable(q) && (mx < g.Kx) && (my <= g.My) && (my >= -g.My);
+        crow[q] = keep ? (my >= 0 ? my : my + g.Ky) : -1;
+    }
+    __shared__ ColTerm s_term[kMaxTerms];
+    __shared__ short s_toff[kMaxProd + kMaxCin + 1];
+    R* geo = reinterpret_cast<R*>(xch + PL * 2 * REG);
+    col_stage_tables<R>(p, mx, 1, href, geo, s_term, s_toff);
+    __syncthreads();
+    const R kxr = R(kx);
+    const V wj = twY[j], wP = twY[P];  // W^(j + qP) = W^j (W^P)^q
+
+    V acc[NACC][E];  // entries of modes that cannot be kept are never used
+#pragma unroll
+    for (int a = 0; a < NACC; ++a)
+#pragma unroll
+        for (int q = 0; q < E; ++q) acc[a][q] = cx<V>(R(0), R(0));
+
+    // jobs: the products (forward transforms), then the compact inputs; pair
+    // L takes jobs L, L + PL, ...; job jb is row jb of the term table
+    const int nps = p.nprod;
+    const int njob = nps + p.ncin;
+    const int rounds = (njob + PL - 1) / PL;
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int jb = rd * PL + lane;
+        if (jb >= njob) break;
+        if (s_toff[jb] == s_toff[jb + 1]) continue;  // no term reads it
+        V v[E];
+        if (jb < nps) {
+            const long long st = p.hin_stride[jb] ? p.hin_stride[jb] : g.s_half;
+            const V* H = static_cast<const V*>(p.hin[jb]) + mem * st + (long long)mx * g.ldh;
+            if (h == 0) {
+#pragma unroll
+                for (int q = 0; q < E; ++q) v[q] = cadd(H[j + q * P], H[j + q * P + NH]);
+            } else {
+                V w = wj;
+                asm volatile("" : "+v"(w.x), "+v"(w.y));  // powers formed here, not held across rounds
+#pragma unroll
+                for (int q = 0; q < E; ++q) {
+                    v[q] = cmul(csub(H[j + q * P], H[j + q * P + NH]), w);
+                    w = cmul(w, wP);
+                }
+            }
+            fft<V, NH, false, 1, E, true>(v, lds, 0, j, twc);
+        } else {
+            const V* Ci = static_cast<const V*>(p.cin[jb - nps]) + mem * g.s_cmp + (long long)mx * g.Ky;
+#pragma unroll
+            for (int q = 0; q < E; ++q) v[q] = crow[q] >= 0 ? Ci[crow[q]] : cx<V>(R(0), R(0));
+        }
+        col_apply_terms<R, V, E, NACC>(s_toff, s_term, jb, v, acc, crow, geo, kxr);
+    }
+    // combine the pairs' partial sums into pair 0 (the same half of every pair
+    // holds the same modes)
+    if (rounds > 0) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) {
+            lds_sync();
+            if (lane > 0) {
+#pragma unroll
+                for (int q = 0; q < E; ++q)
+                    if (CF::keepable(q)) lds[j + q * P] = acc[a][q];
+            }
+            lds_sync();
+            if (lane == 0) {
+#pragma unroll
+                for (int l2 = 1; l2 < PL; ++l2) {
+                    const V* o = xch + (2 * l2 + h) * REG;
+#pragma unroll
+                    for (int q = 0; q < E; ++q)
+                        if (CF::keepable(q)) acc[a][q] = cadd(acc[a][q], o[j + q * P]);
+                }
+            }
+        }
+    }
+    // broadcast the final sums to every pair
+    if (p.ninv > 1) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) {
+            lds_sync();
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < E; ++q)
+                    if (CF::keepable(q)) lds[j + q * P] = acc[a][q];
+            }
+            lds_sync();
+            if (lane > 0) {
+                const V* o = xch + h * REG;
+#pragma unroll
+                for (int q = 0; q < E; ++q)
+                    if (CF::keepable(q)) acc[a][q] = o[j + q * P];
+            }
+        }
+    }
+    lds_sync();  // every pair is past the reads above before the areas are reused
+    // inverse column transforms of the outputs, one per pair and round
+    const int lanes_used = p.ninv > 1 ? PL : 1;
+    const int irounds = (p.ninv + lanes_used - 1) / lanes_used;
+    for (int rd = 0; rd < irounds; ++rd) {
+        const int o = rd * lanes_used + (lanes_used > 1 ? lane : 0);
+        const bool mine = (lanes_used > 1 || lane == 0) && o < p.ninv;
+        if (mine) {
+            const int isrc = p.inv_src[o], dv = p.inv_dv[o];
+            V v[E];
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                V sv = cx<V>(R(0), R(0));
+                if (crow[q] >= 0) {
+                    sv = col_source<R, V, E, NACC>(p, isrc, q, acc, crow[q], mem, mx, omega);
+                    if (dv == DV_X) sv = mul_i(cscale(sv, kxr));
+                    else if (dv == DV_Y) sv = mul_i(cscale(sv, geo[crow[q] * 4 + 3]));
+                }
+                v[q] = sv;
+            }
+            fft<V, NH, true, 1, E, true>(v, lds, 0, j, twc);
+            if (h == 1) {
+                V w = cconj(wj);
+                asm volatile("" : "+v"(w.x), "+v"(w.y));
+                const V wPc = cconj(wP);
+#pragma unroll
+                for (int q = 0; q < E; ++q) {
+                    v[q] = cmul(v[q], w);
+                    w = cmul(w, wPc);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < E; ++q) lds[j + q * P] = v[q];
+        }
+        lds_sync();
+        if (mine) {
+            const V* ev = xch + (2 * lane) * REG;
+            const V* od = xch + (2 * lane + 1) * REG;
+            V* G = static_cast<V*>(p.inv[o]) + mem * g.s_half + (long long)mx * g.ldh + h * NH;
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const int n = j + q * P;
+                G[n] = h == 0 ? cadd(ev[n], od[n]) : csub(ev[n], od[n]);
+            }
+        }
+        lds_sync();
+    }
+    // compact outputs (pair 0): the previous iterates the relaxed sources need
+    // are read before any output is written, so an output may overwrite an
+    // input of the same pass in place; every inverse transform above has read
+    // its sources (the last barrier)
+    if (lane == 0) {
+        V pv[2][E];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int pi = p.relax_prev[a];
+            const V* Pp = pi >= 0 ? static_cast<const V*>(p.cin[pi]) + mem * g.s_cmp + (long long)mx * g.Ky : nullptr;
 #pragma unroll
             for (int q = 0; q < E; ++q)
                 pv[a][q] = (Pp && crow[q] >= 0) ? Pp[crow[q]] : cx<V>(R(0), R(0));
@@ -1279,6 +1531,15 @@ static hipError_t col_go(const ColParams& p, int batch, const Twiddles& tw, hipS
     dim3 grid(p.g.Kxp / CF::C, p.ngroup > 0 ? p.ngroup : 1, batch);
     const size_t lds = CF::lds_bytes(p.g.Ky);
     if (lds > kMaxLdsBytes) return hipErrorInvalidValue;
+    if constexpr (NY == 1024 && QB && NACC <= 2) {
+        if (p.ngroup <= 1) {
+            const size_t lp = ColPairCfg::lds_bytes<R>(p.g.Ky);
+            if (lp > kMaxLdsBytes) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_colp<R, NACC>), dim3(p.g.Kxp, 1, batch), dim3(ColPairCfg::THREADS), lp, s, p,
+                               (const V*)tw.ty);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((k_col<R, NY, NACC, QB>), grid, block, lds, s, p, (const V*)tw.ty);
     return hipGetLastError();
 }
