@@ -36,27 +36,34 @@ __device__ __forceinline__ unsigned long long abs_bits(double x) {
 __device__ __forceinline__ double bits_to_double(unsigned long long b) {
     return __longlong_as_double((long long)b);
 }
-// Block-wide max/min of 64-bit keys through LDS; valid for any block size
-// (row blocks can be narrower than a wavefront).  Every thread must call it.
+// Block-wide max/min of 64-bit keys (order-independent, so every block size
+// and schedule gives the same bits).  Whole wavefronts reduce by lane
+// exchanges and meet in one LDS slot per wavefront; blocks that are not a
+// whole number of wavefronts (narrow grids, at most 256 threads) fold
+// through LDS.  Every thread must call it.
 template <bool MAX>
 __device__ __forceinline__ unsigned long long block_reduce_u64(unsigned long long v) {
-    __shared__ unsigned long long red[1024];
+    __shared__ unsigned long long red[256];
     const int t = threadIdx.x;
     const int n = blockDim.x;
-    __syncthreads();
+    auto pick = [](unsigned long long a, unsigned long long b) { return MAX ? (a > b ? a : b) : (a < b ? a : b); };
+    __syncthreads();  // a previous call's readers are done with red
+    if (n % 64 == 0) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v = pick(v, __shfl_xor(v, off, 64));
+        if ((t & 63) == 0) red[t >> 6] = v;
+        __syncthreads();
+        unsigned long long r = red[0];
+        for (int w = 1; w < n / 64; ++w) r = pick(r, red[w]);
+        return r;
+    }
     red[t] = v;
     __syncthreads();
     for (int s = 1; s < n; s <<= 1) {
-        if ((t & (2 * s - 1)) == 0 && t + s < n) {
-            const unsigned long long w = red[t + s];
-            const unsigned long long u = red[t];
-            red[t] = MAX ? (w > u ? w : u) : (w < u ? w : u);
-        }
+        if ((t & (2 * s - 1)) == 0 && t + s < n) red[t] = pick(red[t], red[t + s]);
         __syncthreads();
     }
-    const unsigned long long r = red[0];
-    __syncthreads();
-    return r;
+    return red[0];
 }
 
 __device__ __forceinline__ double sech_d(double x) {
@@ -114,6 +121,7 @@ template <typename R, int NX> struct Row {
             // kept band below N/2: F[k] alone gives Z[k] and Z[N-k], Z is zero
             // between them; the staging loop writes Z directly
             const int K = rc.Mx + 1;
+#pragma unroll 4
             for (int idx = rc.t; idx < rc.rpw * K; idx += rc.nthr) {
                 const int r2 = idx % rc.rpw, k = idx / rc.rpw;
                 V f = cx<V>(R(0), R(0));
@@ -139,6 +147,7 @@ template <typename R, int NX> struct Row {
 #pragma unroll
             for (int q = 0; q < E; ++q) v[q] = lds[rc.j + q * P];
         } else {
+#pragma unroll 4
             for (int idx = rc.t; idx < rc.rpw * N; idx += rc.nthr) {
                 const int r2 = idx % rc.rpw, m = idx / rc.rpw;
                 V f = cx<V>(R(0), R(0));
@@ -183,6 +192,7 @@ template <typename R, int NX> struct Row {
 #pragma unroll
         for (int q = 0; q < E; ++q) lds[rc.j + q * P] = v[q];
         lds_sync();
+#pragma unroll 4
         for (int idx = rc.t; idx < rc.rpw * (rc.Mx + 1); idx += rc.nthr) {
             const int r2 = idx % rc.rpw, m = idx / rc.rpw;
             const V zm = lds_all[r2 * LS + m];
@@ -253,6 +263,11 @@ template <int P> __device__ __forceinline__ RowCtx row_ctx(const GridDev& g) {
     const R iscale = R(1.0 / ((double)RW::N * (double)p.g.ny));          \
     typename RW::TW twN;                                                 \
     twN.load(twN_tab, rc.j);                                             \
+    /* the twist table exp(-2 pi i m / NX), m < N, staged after the rows'  \
+       areas: the staging and store loops then read it from LDS (a global  \
+       read there would wait behind the loop's own stores) */             \
+    V* const twX = lds_all + rc.rpw * RW::LS;                            \
+    for (int i_ = rc.t; i_ < RW::N; i_ += rc.nthr) twX[i_] = twX_tab[i_]; \
     (void)po; (void)iscale; (void)hb;
 
 // ---------------------------------------------------------------------------
@@ -260,7 +275,7 @@ template <int P> __device__ __forceinline__ RowCtx row_ctx(const GridDev& g) {
 // ---------------------------------------------------------------------------
 template <typename R, int NX>
 __global__ void __launch_bounds__(row_threads<NX>()) k_row_fwd(const RowFwdParams p, const typename cplx_of<R>::type* twN_tab,
-                          const typename cplx_of<R>::type* twX) {
+                          const typename cplx_of<R>::type* twX_tab) {
     ROW_PROLOGUE(R, NX)
     for (int f = 0; f < p.nf; ++f) {
         V v[E];
@@ -271,7 +286,7 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_fwd(const RowFwdParam
 
 template <typename R, int NX>
 __global__ void __launch_bounds__(row_threads<NX>()) k_row_inv(const RowInvParams p, const typename cplx_of<R>::type* twN_tab,
-                          const typename cplx_of<R>::type* twX) {
+                          const typename cplx_of<R>::type* twX_tab) {
     ROW_PROLOGUE(R, NX)
     for (int f = 0; f < p.nf; ++f) {
         V v[E];
@@ -285,7 +300,7 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_inv(const RowInvParam
 
 template <typename R, int NX>
 __global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupParams p, const typename cplx_of<R>::type* twN_tab,
-                            const typename cplx_of<R>::type* twX) {
+                            const typename cplx_of<R>::type* twX_tab) {
     ROW_PROLOGUE(R, NX)
     V e[E];
     if (p.g_eta) {
@@ -360,7 +375,7 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupP
 
 template <typename R, int NX>
 __global__ void __launch_bounds__(row_threads<NX>(), 3) k_row_sweep(const RowSweepParams p, const typename cplx_of<R>::type* twN_tab,
-                            const typename cplx_of<R>::type* twX) {
+                            const typename cplx_of<R>::type* twX_tab) {
     ROW_PROLOGUE(R, NX)
     Ctl* ctl = p.ctl + ri.mem;
     if (ctl->done) return;  // block-uniform
@@ -429,7 +444,7 @@ __global__ void __launch_bounds__(row_threads<NX>(), 3) k_row_sweep(const RowSwe
 
 template <typename R, int NX>
 __global__ void __launch_bounds__(row_threads<NX>()) k_row_sa(const RowSaParams p, const typename cplx_of<R>::type* twN_tab,
-                         const typename cplx_of<R>::type* twX) {
+                         const typename cplx_of<R>::type* twX_tab) {
     ROW_PROLOGUE(R, NX)
     const int l = p.l;
     int idx = 0;
@@ -502,7 +517,7 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_sa(const RowSaParams 
 
 template <typename R, int NX>
 __global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi(const RowNphiParams p, const typename cplx_of<R>::type* twN_tab,
-                           const typename cplx_of<R>::type* twX) {
+                           const typename cplx_of<R>::type* twX_tab) {
     ROW_PROLOGUE(R, NX)
     V q[E], gg[E], pp[E], a[E], b[E];
     const V* gD = p.gD ? static_cast<const V*>(p.gD) + hb : nullptr;
@@ -536,7 +551,7 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi(const RowNphiPar
 
 template <typename R, int NX>
 __global__ void __launch_bounds__(row_threads<NX>()) k_row_blend(const RowBlendParams p, const typename cplx_of<R>::type* twN_tab,
-                            const typename cplx_of<R>::type* twX) {
+                            const typename cplx_of<R>::type* twX_tab) {
     ROW_PROLOGUE(R, NX)
     V e[E], f[E];
     RW::inverse(e, static_cast<const V*>(p.ge) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
@@ -579,7 +594,7 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_blend(const RowBlendP
 // multiplied by its channel scale in the working precision before rounding.
 template <typename R, int NX>
 __global__ void __launch_bounds__(row_threads<NX>()) k_row_feat(const RowFeatParams p, const typename cplx_of<R>::type* twN_tab,
-                           const typename cplx_of<R>::type* twX) {
+                           const typename cplx_of<R>::type* twX_tab) {
     ROW_PROLOGUE(R, NX)
     V wl[E], a[E];
     RW::inverse(wl, static_cast<const V*>(p.gV) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
@@ -1482,7 +1497,7 @@ template <typename R, int NX> struct RowLaunch {
         if (rpw > ny) rpw = ny;
         *block = dim3(P * rpw);
         *grid = dim3((ny + rpw - 1) / rpw, nfam, batch);
-        *lds = (size_t)rpw * Row<R, NX>::LS * sizeof(V);
+        *lds = ((size_t)rpw * Row<R, NX>::LS + Row<R, NX>::N) * sizeof(V);
     }
 };
 
