@@ -81,7 +81,7 @@ template <typename V> __device__ __forceinline__ V rmul(V a, V b) {  // componen
 // ---------------------------------------------------------------------------
 // Per-thread view of a row-pass workgroup: rpw rows of P threads each.
 struct RowCtx {
-    int t, nthr, j, rl, y0, rpw, ny, ldh, Mx, mem;
+    int t, nthr, j, rl, y0, rpw, rsh, ny, ldh, Mx, mem;  // rpw = 1 << rsh rows per workgroup
     bool valid;
 };
 
@@ -117,49 +117,48 @@ template <typename R, int NX> struct Row {
                                                    const TW& twN, const V* __restrict__ twX, R scale) {
         V* lds = lds_all + rc.rl * LS;
         lds_sync();  // other rows' transforms are done with the area the staging loop writes
+        // a thread stages modes k0, k0 + kstep, ... of row r2 of the workgroup
+        // (the block is a whole number of rows, and ny a multiple of rpw)
+        const int r2 = rc.t & (rc.rpw - 1);
+        const int k0 = rc.t >> rc.rsh, kstep = rc.nthr >> rc.rsh;
+        V* const zr = lds_all + r2 * LS;
+        const V* const Gr = G + rc.y0 + r2;
+        const V* const G2r = G2 ? G2 + rc.y0 + r2 : nullptr;
         if (2 * rc.Mx < N) {
             // kept band below N/2: F[k] alone gives Z[k] and Z[N-k], Z is zero
             // between them; the staging loop writes Z directly
             const int K = rc.Mx + 1;
 #pragma unroll 4
-            for (int idx = rc.t; idx < rc.rpw * K; idx += rc.nthr) {
-                const int r2 = idx % rc.rpw, k = idx / rc.rpw;
-                V f = cx<V>(R(0), R(0));
-                if (rc.y0 + r2 < rc.ny) {
-                    const long long o = (long long)k * rc.ldh + rc.y0 + r2;
-                    f = G[o];
-                    if (G2) {
-                        const V f2 = G2[o];
-                        f = cx<V>(f.x + c2 * f2.x, f.y + c2 * f2.y);
-                    }
+            for (int k = k0; k < K; k += kstep) {
+                V f = Gr[k * rc.ldh];
+                if (G2r) {
+                    const V f2 = G2r[k * rc.ldh];
+                    f = cx<V>(f.x + c2 * f2.x, f.y + c2 * f2.y);
                 }
                 const V h = cscale(f, R(0.5));
-                lds_all[r2 * LS + k] = cadd(h, mul_i(cmul(h, cconj(twX[k]))));
+                zr[k] = cadd(h, mul_i(cmul(h, cconj(twX[k]))));
                 if (k > 0) {
                     const V hc = cconj(h);
                     const V w = mul_i(cmul(hc, cconj(twX[N - k])));
-                    lds_all[r2 * LS + N - k] = cx<V>(hc.x - w.x, hc.y - w.y);
+                    zr[N - k] = cx<V>(hc.x - w.x, hc.y - w.y);
                 }
             }
-            for (int idx = rc.t; idx < rc.rpw * (N - 2 * K + 1); idx += rc.nthr)
-                lds_all[(idx % rc.rpw) * LS + K + idx / rc.rpw] = cx<V>(R(0), R(0));
+            for (int k = K + k0; k <= N - K; k += kstep) zr[k] = cx<V>(R(0), R(0));
             lds_sync();
 #pragma unroll
             for (int q = 0; q < E; ++q) v[q] = lds[rc.j + q * P];
         } else {
 #pragma unroll 4
-            for (int idx = rc.t; idx < rc.rpw * N; idx += rc.nthr) {
-                const int r2 = idx % rc.rpw, m = idx / rc.rpw;
+            for (int m = k0; m < N; m += kstep) {
                 V f = cx<V>(R(0), R(0));
-                if (m <= rc.Mx && rc.y0 + r2 < rc.ny) {
-                    const long long o = (long long)m * rc.ldh + rc.y0 + r2;
-                    f = G[o];
-                    if (G2) {
-                        const V f2 = G2[o];
+                if (m <= rc.Mx) {
+                    f = Gr[m * rc.ldh];
+                    if (G2r) {
+                        const V f2 = G2r[m * rc.ldh];
                         f = cx<V>(f.x + c2 * f2.x, f.y + c2 * f2.y);
                     }
                 }
-                lds_all[r2 * LS + m] = f;
+                zr[m] = f;
             }
             lds_sync();
 #pragma unroll
@@ -192,14 +191,18 @@ template <typename R, int NX> struct Row {
 #pragma unroll
         for (int q = 0; q < E; ++q) lds[rc.j + q * P] = v[q];
         lds_sync();
+        // a thread stores modes m0, m0 + mstep, ... of row r2 of the workgroup
+        const int r2 = rc.t & (rc.rpw - 1);
+        const V* const zr = lds_all + r2 * LS;
+        V* const Hr = H + rc.y0 + r2;
+        const int mstep = rc.nthr >> rc.rsh;
 #pragma unroll 4
-        for (int idx = rc.t; idx < rc.rpw * (rc.Mx + 1); idx += rc.nthr) {
-            const int r2 = idx % rc.rpw, m = idx / rc.rpw;
-            const V zm = lds_all[r2 * LS + m];
-            const V zc = cconj(lds_all[r2 * LS + ((N - m) & (N - 1))]);
+        for (int m = rc.t >> rc.rsh; m <= rc.Mx; m += mstep) {
+            const V zm = zr[m];
+            const V zc = cconj(zr[(N - m) & (N - 1)]);
             const V ev = cx<V>(R(0.5) * (zm.x + zc.x), R(0.5) * (zm.y + zc.y));
             const V od = mul_mi<false>(cx<V>(R(0.5) * (zm.x - zc.x), R(0.5) * (zm.y - zc.y)));
-            if (rc.y0 + r2 < rc.ny) H[(long long)m * rc.ldh + rc.y0 + r2] = cadd(ev, cmul(twX[m], od));
+            Hr[m * rc.ldh] = cadd(ev, cmul(twX[m], od));
         }
         lds_sync();
     }
@@ -237,7 +240,8 @@ template <int P> __device__ __forceinline__ RowCtx row_ctx(const GridDev& g) {
     r.nthr = blockDim.x;
     r.j = r.t % P;
     r.rl = r.t / P;
-    r.rpw = blockDim.x / P;
+    r.rpw = blockDim.x / P;  // a power of two (grid sizes are)
+    r.rsh = __builtin_ctz((unsigned)r.rpw);
     r.y0 = xcd_row_group(blockIdx.x, gridDim.x) * r.rpw;
     r.ny = g.ny;
     r.ldh = g.ldh;
@@ -1492,6 +1496,8 @@ template <typename R, int NX> struct RowLaunch {
     using V = typename cplx_of<R>::type;
     static void shape(int ny, dim3* grid, dim3* block, size_t* lds, int batch, int nfam) {
         constexpr int P = Row<R, NX>::P;
+        // rows per workgroup: a power of two dividing ny (sizes are powers of
+        // two), which the row kernels rely on
         int rpw = 256 / P;
         if (rpw < 1) rpw = 1;
         if (rpw > ny) rpw = ny;
