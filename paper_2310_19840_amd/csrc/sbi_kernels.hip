@@ -1153,9 +1153,9 @@ k_colp(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     const int mx = blockIdx.x;
     const GridDev& g = p.g;
     Ctl* ctl = p.ctl ? p.ctl + mem : nullptr;
-    double omega = 1.0;
-    if (!col_control(p, ctl, blockIdx.x == 0 && t == 0, &omega)) return;
 
+    // tables and twiddles are requested before the sweep decision, whose
+    // chain of dependent control reads then overlaps them
     Twid<V, NH, E> twc;
     twc.load(twY, j, 2);  // the 512-point twiddles are every other 1024-point one
     const double href = g.href[mem];
@@ -1172,9 +1172,13 @@ k_colp(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     __shared__ short s_toff[kMaxProd + kMaxCin + 1];
     R* geo = reinterpret_cast<R*>(xch + PL * 2 * REG);
     col_stage_tables<R>(p, mx, 1, href, geo, s_term, s_toff);
+    const V wj = twY[j], wP = twY[P];  // W^(j + qP) = W^j (W^P)^q
+    double omega = 1.0;
+    // the decision is the same in every thread (the leader's header updates
+    // cannot change it), so the workgroup returns as a whole
+    if (!col_control(p, ctl, blockIdx.x == 0 && t == 0, &omega)) return;
     __syncthreads();
     const R kxr = R(kx);
-    const V wj = twY[j], wP = twY[P];  // W^(j + qP) = W^j (W^P)^q
 
     V acc[NACC][E];  // entries of modes that cannot be kept are never used
 #pragma unroll
@@ -1182,14 +1186,16 @@ k_colp(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
 #pragma unroll
         for (int q = 0; q < E; ++q) acc[a][q] = cx<V>(R(0), R(0));
 
-    // jobs: the products (forward transforms), then the compact inputs; pair
-    // L takes jobs L, L + PL, ...; job jb is row jb of the term table
+    // jobs: the products (forward transforms), then the compact inputs; job
+    // jb is row jb of the term table.  Round rd deals jobs rd PL .. rd PL +
+    // PL - 1 to the pairs in alternating direction, so the cheap compact-input
+    // jobs of the last rounds go to pairs with fewer transforms.
     const int nps = p.nprod;
     const int njob = nps + p.ncin;
     const int rounds = (njob + PL - 1) / PL;
     for (int rd = 0; rd < rounds; ++rd) {
-        const int jb = rd * PL + lane;
-        if (jb >= njob) break;
+        const int jb = rd * PL + ((rd & 1) ? PL - 1 - lane : lane);
+        if (jb >= njob) continue;
         if (s_toff[jb] == s_toff[jb + 1]) continue;  // no term reads it
         V v[E];
         if (jb < nps) {
@@ -1258,15 +1264,50 @@ k_colp(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         }
     }
     lds_sync();  // every pair is past the reads above before the areas are reused
-    // inverse column transforms of the outputs, one per pair and round
+    // compact outputs, mode by mode: a mode's previous iterates are read before
+    // any output of that mode is written, so an output may overwrite an input
+    // of the same pass in place
+    auto compact_outputs = [&]() __attribute__((always_inline)) {
+        const long long co = mem * g.s_cmp + (long long)mx * g.Ky;
+        const V* P0 = p.relax_prev[0] >= 0 ? static_cast<const V*>(p.cin[p.relax_prev[0]]) + co : nullptr;
+        const V* P1 = p.relax_prev[1] >= 0 ? static_cast<const V*>(p.cin[p.relax_prev[1]]) + co : nullptr;
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            if (crow[q] < 0) continue;
+            const V pv0 = P0 ? P0[crow[q]] : cx<V>(R(0), R(0));
+            const V pv1 = P1 ? P1[crow[q]] : cx<V>(R(0), R(0));
+            for (int o = 0; o < p.ncout; ++o) {
+                const int src = p.cout_src[o];
+                const bool relaxed = src >= SRC_NEW0;
+                const int a = relaxed ? ((src == SRC_NEW0 || src == SRC_DIFF0) ? 0 : 1) : src;
+                V cur = cx<V>(R(0), R(0));
+#pragma unroll
+                for (int k = 0; k < NACC; ++k)
+                    if (k == a) cur = acc[k][q];
+                V val = cur;
+                if (relaxed) {
+                    const V pq = a == 0 ? pv0 : pv1;
+                    const V d = csub(cur, pq);
+                    val = src >= SRC_DIFF0 ? d : cadd(pq, cscale(d, R(omega)));
+                }
+                static_cast<V*>(p.cout[o])[co + crow[q]] = val;
+            }
+        }
+    };
+    // inverse column transforms of the outputs, one per pair and round.  When
+    // they take a single round and leave a pair idle (which then holds the
+    // broadcast sums too), that pair writes the compact outputs while the
+    // others transform, once every pair has read the previous iterates its
+    // sources need; otherwise pair 0 writes them at the end.
     const int lanes_used = p.ninv > 1 ? PL : 1;
     const int irounds = (p.ninv + lanes_used - 1) / lanes_used;
+    const bool overlap = p.ninv > 1 && irounds == 1 && p.ninv < PL;
     for (int rd = 0; rd < irounds; ++rd) {
         const int o = rd * lanes_used + (lanes_used > 1 ? lane : 0);
         const bool mine = (lanes_used > 1 || lane == 0) && o < p.ninv;
+        V v[E];
         if (mine) {
             const int isrc = p.inv_src[o], dv = p.inv_dv[o];
-            V v[E];
 #pragma unroll
             for (int q = 0; q < E; ++q) {
                 V sv = cx<V>(R(0), R(0));
@@ -1277,6 +1318,12 @@ k_colp(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
                 }
                 v[q] = sv;
             }
+        }
+        if (overlap) {
+            __syncthreads();  // every source above has been formed from the previous iterates
+            if (lane == PL - 1) compact_outputs();
+        }
+        if (mine) {
             fft<V, NH, true, 1, E, true>(v, lds, 0, j, twc);
             if (h == 1) {
                 V w = cconj(wj);
@@ -1304,43 +1351,8 @@ k_colp(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         }
         lds_sync();
     }
-    // compact outputs (pair 0): the previous iterates the relaxed sources need
-    // are read before any output is written, so an output may overwrite an
-    // input of the same pass in place; every inverse transform above has read
-    // its sources (the last barrier)
-    if (lane == 0) {
-        V pv[2][E];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const int pi = p.relax_prev[a];
-            const V* Pp = pi >= 0 ? static_cast<const V*>(p.cin[pi]) + mem * g.s_cmp + (long long)mx * g.Ky : nullptr;
-#pragma unroll
-            for (int q = 0; q < E; ++q)
-                pv[a][q] = (Pp && crow[q] >= 0) ? Pp[crow[q]] : cx<V>(R(0), R(0));
-        }
-        for (int o = 0; o < p.ncout; ++o) {
-            const int src = p.cout_src[o];
-            const bool relaxed = src >= SRC_NEW0;
-            const int a = relaxed ? ((src == SRC_NEW0 || src == SRC_DIFF0) ? 0 : 1) : src;
-            const bool diff = src >= SRC_DIFF0;
-            V* out = static_cast<V*>(p.cout[o]) + mem * g.s_cmp + (long long)mx * g.Ky;
-#pragma unroll
-            for (int q = 0; q < E; ++q) {
-                if (crow[q] < 0) continue;
-                V cur = cx<V>(R(0), R(0));
-#pragma unroll
-                for (int k = 0; k < NACC; ++k)
-                    if (k == a) cur = acc[k][q];
-                V val = cur;
-                if (relaxed) {
-                    const V pq = a == 0 ? pv[0][q] : pv[1][q];
-                    const V d = csub(cur, pq);
-                    val = diff ? d : cadd(pq, cscale(d, R(omega)));
-                }
-                out[crow[q]] = val;
-            }
-        }
-    }
+    // every inverse transform above has read its sources (the last barrier)
+    if (!overlap && lane == 0) compact_outputs();
 }
 
 // ---------------------------------------------------------------------------
