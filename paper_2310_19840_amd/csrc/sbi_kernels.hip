@@ -66,6 +66,37 @@ __device__ __forceinline__ unsigned long long block_reduce_u64(unsigned long lon
     return red[0];
 }
 
+// Block-wide maxima of two 64-bit keys at once (one pair of barriers); the
+// same contract as block_reduce_u64.
+__device__ __forceinline__ void block_reduce2_max_u64(unsigned long long& a, unsigned long long& b) {
+    __shared__ unsigned long long red2[2][16];
+    const int t = threadIdx.x;
+    const int n = blockDim.x;
+    if (n % 64 != 0) {
+        a = block_reduce_u64<true>(a);
+        b = block_reduce_u64<true>(b);
+        return;
+    }
+    auto mx = [](unsigned long long x, unsigned long long y) { return x > y ? x : y; };
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        a = mx(a, __shfl_xor(a, off, 64));
+        b = mx(b, __shfl_xor(b, off, 64));
+    }
+    __syncthreads();  // a previous call's readers are done with red2
+    if ((t & 63) == 0) {
+        red2[0][t >> 6] = a;
+        red2[1][t >> 6] = b;
+    }
+    __syncthreads();
+    a = red2[0][0];
+    b = red2[1][0];
+    for (int w = 1; w < n / 64; ++w) {
+        a = mx(a, red2[0][w]);
+        b = mx(b, red2[1][w]);
+    }
+}
+
 __device__ __forceinline__ double sech_d(double x) {
     double e = exp(-fabs(x));
     return 2.0 * e / (1.0 + e * e);
@@ -406,24 +437,23 @@ __global__ void __launch_bounds__(row_threads<NX>(), 3) k_row_sweep(const RowSwe
                     de = b > de ? b : de;
                 }
             }
-            nu = block_reduce_u64<true>(nu);
-            de = block_reduce_u64<true>(de);
+            block_reduce2_max_u64(nu, de);
             if (threadIdx.x == 0) {
                 atomicMax(&ctl->slots->num[p.slot], nu);
                 atomicMax(&ctl->slots->den[p.slot], de);
             }
         }
         if (!p.products) return;
-        // eta^j V: the power is rebuilt from V for each j (the same sequence
-        // of products as a running power); eta is re-read from the cache for
-        // each product rather than held across the transforms
+        // eta^j V as a running product (vv <- vv eta before each transform);
+        // eta is re-read from the cache for each product rather than held
+        // across the transforms
         for (int jj = 1; jj <= p.J; ++jj) {
             V w[E], ev[E];
             RW::load(ev, static_cast<const R*>(p.eta) + po, ri.j, ri.valid);
 #pragma unroll
             for (int q = 0; q < E; ++q) {
+                vv[q] = rmul(vv[q], ev[q]);
                 w[q] = vv[q];
-                for (int k = 0; k < jj; ++k) w[q] = rmul(w[q], ev[q]);
             }
             RW::forward(w, static_cast<V*>(p.h[jj - 1]) + hb, rc, lds_all, twN, twX);
         }
@@ -439,8 +469,8 @@ __global__ void __launch_bounds__(row_threads<NX>(), 3) k_row_sweep(const RowSwe
         RW::load(dv, static_cast<const R*>(p.delta) + po, ri.j, ri.valid);
 #pragma unroll
         for (int q = 0; q < E; ++q) {
+            gb[q] = rmul(gb[q], dv[q]);  // running product delta^j d phi_b
             w[q] = gb[q];
-            for (int k = 0; k < jj; ++k) w[q] = rmul(w[q], dv[q]);
         }
         RW::forward(w, static_cast<V*>(p.h[fam * p.J + jj - 1]) + hb, rc, lds_all, twN, twX);
     }
