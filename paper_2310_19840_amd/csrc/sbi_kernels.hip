@@ -411,9 +411,9 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupP
 template <typename R, int NX>
 __global__ void __launch_bounds__(row_threads<NX>(), 3) k_row_sweep(const RowSweepParams p, const typename cplx_of<R>::type* twN_tab,
                             const typename cplx_of<R>::type* twX_tab) {
+    Ctl* ctl = p.ctl + blockIdx.z;
+    if (ctl->done) return;  // block-uniform: the member's solve is decided
     ROW_PROLOGUE(R, NX)
-    Ctl* ctl = p.ctl + ri.mem;
-    if (ctl->done) return;  // block-uniform
     const int fam = blockIdx.y;  // product family of this workgroup
     if (fam == 0) {
         V vv[E];
@@ -1185,9 +1185,11 @@ k_colp(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     Ctl* ctl = p.ctl ? p.ctl + mem : nullptr;
 
     // tables and twiddles are requested before the sweep decision, whose
-    // chain of dependent control reads then overlaps them
+    // chain of dependent control reads then overlaps them; a launch after
+    // the member's solve was decided returns before any table work
     Twid<V, NH, E> twc;
     twc.load(twY, j, 2);  // the 512-point twiddles are every other 1024-point one
+    if (p.ctl_mode == CTL_SWEEP && ctl->done) return;
     const double href = g.href[mem];
     const double kx = 2.0 * M_PI * (double)mx / g.lx;
     int crow[E];  // compact row of mode 2 (j + qP) + h, -1 if not kept
