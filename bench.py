@@ -292,7 +292,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1024, help="grid size (1024 = the benchmark workload)")
     ap.add_argument("--max-sweeps", type=int, default=400)
-    ap.add_argument("--batch-sweeps", type=int, default=64, help="sweep budget per solve of the captured forms")
+    ap.add_argument("--batch-sweeps", type=int, default=48,
+                    help="sweep budget per solve of the captured forms (solves here need at most 33)")
     ap.add_argument("--members", type=int, default=2, help="realisations of the batched forms")
     ap.add_argument("--c4-steps", type=int, default=4)
     ap.add_argument("--c3-steps", type=int, default=32)
