@@ -444,12 +444,11 @@ __global__ void __launch_bounds__(row_threads<NX>(), 3) k_row_sweep(const RowSwe
             }
         }
         if (!p.products) return;
-        // eta^j V as a running product (vv <- vv eta before each transform);
-        // eta is re-read from the cache for each product rather than held
-        // across the transforms
+        // eta^j V as a running product (vv <- vv eta before each transform)
+        V ev[E];
+        RW::load(ev, static_cast<const R*>(p.eta) + po, ri.j, ri.valid);
         for (int jj = 1; jj <= p.J; ++jj) {
-            V w[E], ev[E];
-            RW::load(ev, static_cast<const R*>(p.eta) + po, ri.j, ri.valid);
+            V w[E];
 #pragma unroll
             for (int q = 0; q < E; ++q) {
                 vv[q] = rmul(vv[q], ev[q]);
@@ -464,9 +463,10 @@ __global__ void __launch_bounds__(row_threads<NX>(), 3) k_row_sweep(const RowSwe
     const int comp = fam - 1;
     V gb[E];
     RW::inverse(gb, static_cast<const V*>(comp == 0 ? p.gbx : p.gby) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+    V dv[E];
+    RW::load(dv, static_cast<const R*>(p.delta) + po, ri.j, ri.valid);
     for (int jj = 1; jj <= p.J; ++jj) {
-        V w[E], dv[E];
-        RW::load(dv, static_cast<const R*>(p.delta) + po, ri.j, ri.valid);
+        V w[E];
 #pragma unroll
         for (int q = 0; q < E; ++q) {
             gb[q] = rmul(gb[q], dv[q]);  // running product delta^j d phi_b
