@@ -6,7 +6,9 @@ whole solves or steps; instead it checks properties that hold at any size:
 
 * the W the GPU converged to is a fixed point of the oracle's own summed
   operator (App. C): seeded with the GPU's V and phi_b, the oracle's
-  iteration stops at once and moves W by no more than the tolerance;
+  iteration stops at once and moves W by no more than the tolerance (over
+  variable depth and over a flat bed);
+* in SA mode, which does not iterate, W equals the oracle's to 1e-10;
 * one step conserves the mean elevation (mass), and the energy of Sec. 2
   changes by far less than the scheme's dealiasing drift.
 """
@@ -54,6 +56,46 @@ def test_fullsize_w_is_an_oracle_fixed_point(gpu, tol):
     _say("gpu sweeps", info[0][0], "oracle sweeps from the gpu iterate", oi.sweeps, "residual", oi.residual)
     assert oi.status == 0 and oi.sweeps <= 2
     assert _rel(Wg, Wo) <= 3 * tol
+
+
+def test_fullsize_flat_bottom_w_is_an_oracle_fixed_point(gpu):
+    # flat bed: the sweep's column passes carry one accumulator (no phi_b)
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    cfg = _c5()
+    g = cfg["grid"]
+    flat = np.full_like(cfg["depth"], cfg["h_ref"])
+    _say("1024^2 fp64 flat-bottom fixed point")
+    s = Solver(g.nx, g.ny, g.lx, g.ly, flat, device=gpu, mode="iter", max_sweeps=200, seed="prev")
+    eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=gpu)
+    phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=gpu)
+    W, st, info = s.vertical_velocity(eta, phi, tol=1e-11)
+    assert st == 0 and info[0][0] > 5, info
+    Wg = W.cpu().numpy().reshape(g.ny, g.nx)
+    o = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), flat, mode="iter", max_sweeps=4)
+    Wo, oi = o.vertical_velocity(cfg["eta"], cfg["phi"], tol=1e-11, seed=Wg)
+    _say("gpu sweeps", info[0][0], "oracle sweeps from the gpu iterate", oi.sweeps)
+    assert oi.status == 0 and oi.sweeps <= 2
+    assert _rel(Wg, Wo) <= 3e-11
+
+
+def test_fullsize_sa_matches_oracle(gpu):
+    # the paper's order recursion (Appendix C) at full size: no iteration, so
+    # the oracle's W is computed outright
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    cfg = _c5()
+    g = cfg["grid"]
+    _say("1024^2 fp64 SA")
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=gpu, mode="sa")
+    eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=gpu)
+    phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=gpu)
+    W, st, _ = s.vertical_velocity(eta, phi)
+    o = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), cfg["depth"], mode="sa")
+    Wo, _ = o.vertical_velocity(cfg["eta"], cfg["phi"])
+    assert _rel(W.cpu().numpy().reshape(g.ny, g.nx), Wo) <= 1e-10
 
 
 def test_fullsize_fp32_w_is_near_the_oracle_fixed_point(gpu):
