@@ -145,3 +145,30 @@ def test_fullsize_step_conserves_mass_and_energy(gpu):
     # (about 1e-4 per 32 steps on this sea)
     assert abs(e1[0] - e0[0]) <= 1e-5 * abs(e0[0])
     assert np.isfinite(eta.cpu().numpy()).all()
+
+
+def test_fullsize_batch_in_graph_equals_single_contexts(gpu):
+    # two 1024^2 members in one captured graph (the column pass then runs with
+    # a member index): each equals its own eager single-context run bit for bit
+    import torch
+    from paper_2310_19840_amd import Batch, Solver
+    cfgs = [si.config_c5(seed=sd, n=1024) for sd in (0, 1)]
+    _say("1024^2 batch of two in a graph")
+    opts = [dict(nx=c["grid"].nx, ny=c["grid"].ny, lx=c["grid"].lx, ly=c["grid"].ly, depth=c["depth"],
+                 precision="fp64", mode="iter", max_sweeps=60, seed="prev") for c in cfgs]
+    b = Batch(opts, device=gpu, graph=True)
+    eb = [torch.tensor(c["eta"], dtype=torch.float64, device=gpu) for c in cfgs]
+    pb = [torch.tensor(c["phi"], dtype=torch.float64, device=gpu) for c in cfgs]
+    dt = cfgs[0]["dt"]
+    st, info = b.step(eb, pb, dt, 1, tol=1e-8)
+    assert st == 0
+    for i, c in enumerate(cfgs):
+        g = c["grid"]
+        s = Solver(g.nx, g.ny, g.lx, g.ly, c["depth"], device=gpu, mode="iter", max_sweeps=60, seed="prev")
+        e = torch.tensor(c["eta"][None], dtype=torch.float64, device=gpu)
+        ph = torch.tensor(c["phi"][None], dtype=torch.float64, device=gpu)
+        _, si_ = s.step(e, ph, dt, 1, tol=1e-8)
+        assert np.array_equal(eb[i].cpu().numpy(), e.cpu().numpy().reshape(g.ny, g.nx)), i
+        assert np.array_equal(pb[i].cpu().numpy(), ph.cpu().numpy().reshape(g.ny, g.nx)), i
+        assert info[i]["sweeps_total"] == si_["sweeps_total"], i
+
