@@ -1254,45 +1254,50 @@ k_colp(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         col_apply_terms<R, V, E, NACC>(s_toff, s_term, jb, v, acc, crow, geo, kxr);
     }
     // combine the pairs' partial sums into pair 0 (the same half of every pair
-    // holds the same modes)
+    // holds the same modes), every accumulator in one exchange: the kept slots
+    // of NACC <= 2 accumulators fill NACC * E/2 * P <= 512 of an area's slots
+    static_assert(NACC * (E / 2) * P <= REG, "the accumulators exceed an exchange area");
+    auto slot = [&](int a, int q) { return (a * (E / 2) + (q < E / 4 ? q : q - E / 2)) * P + j; };
     if (rounds > 0) {
+        lds_sync();
+        if (lane > 0) {
 #pragma unroll
-        for (int a = 0; a < NACC; ++a) {
-            lds_sync();
-            if (lane > 0) {
+            for (int a = 0; a < NACC; ++a)
 #pragma unroll
                 for (int q = 0; q < E; ++q)
-                    if (CF::keepable(q)) lds[j + q * P] = acc[a][q];
-            }
-            lds_sync();
-            if (lane == 0) {
+                    if (CF::keepable(q)) lds[slot(a, q)] = acc[a][q];
+        }
+        lds_sync();
+        if (lane == 0) {
 #pragma unroll
-                for (int l2 = 1; l2 < PL; ++l2) {
-                    const V* o = xch + (2 * l2 + h) * REG;
+            for (int l2 = 1; l2 < PL; ++l2) {
+                const V* o = xch + (2 * l2 + h) * REG;
+#pragma unroll
+                for (int a = 0; a < NACC; ++a)
 #pragma unroll
                     for (int q = 0; q < E; ++q)
-                        if (CF::keepable(q)) acc[a][q] = cadd(acc[a][q], o[j + q * P]);
-                }
+                        if (CF::keepable(q)) acc[a][q] = cadd(acc[a][q], o[slot(a, q)]);
             }
         }
     }
     // broadcast the final sums to every pair
     if (p.ninv > 1) {
+        lds_sync();
+        if (lane == 0) {
 #pragma unroll
-        for (int a = 0; a < NACC; ++a) {
-            lds_sync();
-            if (lane == 0) {
-#pragma unroll
-                for (int q = 0; q < E; ++q)
-                    if (CF::keepable(q)) lds[j + q * P] = acc[a][q];
-            }
-            lds_sync();
-            if (lane > 0) {
-                const V* o = xch + h * REG;
+            for (int a = 0; a < NACC; ++a)
 #pragma unroll
                 for (int q = 0; q < E; ++q)
-                    if (CF::keepable(q)) acc[a][q] = o[j + q * P];
-            }
+                    if (CF::keepable(q)) lds[slot(a, q)] = acc[a][q];
+        }
+        lds_sync();
+        if (lane > 0) {
+            const V* o = xch + h * REG;
+#pragma unroll
+            for (int a = 0; a < NACC; ++a)
+#pragma unroll
+                for (int q = 0; q < E; ++q)
+                    if (CF::keepable(q)) acc[a][q] = o[slot(a, q)];
         }
     }
     lds_sync();  // every pair is past the reads above before the areas are reused
