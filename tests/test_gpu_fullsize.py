@@ -172,3 +172,48 @@ def test_fullsize_batch_in_graph_equals_single_contexts(gpu):
         assert np.array_equal(pb[i].cpu().numpy(), ph.cpu().numpy().reshape(g.ny, g.nx)), i
         assert info[i]["sweeps_total"] == si_["sweeps_total"], i
 
+
+def test_fullsize_learned_seed_features_and_sampled_inference(gpu):
+    # the committed network on the learned-seed form at 1024^2: every feature
+    # against the oracle's, and the network output at sampled points, computed
+    # by the oracle on a wrapped 9x9 window of the GPU's features around each
+    # point (two 3x3 layers make the centre depend on its 5x5 neighbourhood
+    # only, so the window's own wrap never reaches it); tolerances as in the
+    # warm-start tests
+    import os
+    import torch
+    from oracle import Grid, Solver as OSolver, warmstart as ws
+    from paper_2310_19840_amd import Solver, net_blob_parts
+    cfg = _c5()
+    g = cfg["grid"]
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "..", "paper_2310_19840_amd", "weights",
+                        "warmstart_c5.sbiw")
+    blob = open(path, "rb").read()
+    th, in_scale, out_scale = net_blob_parts(blob)
+    _say("1024^2 learned seed")
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=gpu, mode="iter", seed="net")
+    s.net_load(blob)
+    eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=gpu)
+    phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=gpu)
+    feat, wlin = s.net_features(eta, phi)
+    seed, db = s.net_infer(feat, wlin)
+    o = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), cfg["depth"], mode="iter")
+    fo, wo = ws.features(o, cfg["eta"], cfg["phi"])
+    fo = fo * in_scale.astype(np.float64)
+    fg = feat.cpu().numpy()[0].astype(np.float64)
+    for c in range(8):
+        assert np.abs(fg[..., c] - fo[..., c]).max() <= 2e-7 * max(np.abs(fo[..., c]).max(), 1e-30), c
+    wl = wlin.cpu().numpy()[0]
+    assert np.abs(wl - wo).max() < 1e-12 * np.abs(wo).max()
+    ys = [(seed.cpu().numpy()[0] - wl) / float(out_scale[0]), db.cpu().numpy()[0] / float(out_scale[1])]
+    rng = np.random.default_rng(11)
+    pts = rng.integers(0, [g.ny, g.nx], size=(48, 2))
+    th64 = th.astype(np.float64)
+    for iy, ix in pts:
+        rows = (iy + np.arange(-4, 5)) % g.ny
+        cols = (ix + np.arange(-4, 5)) % g.nx
+        patch = fg[np.ix_(rows, cols)]
+        yo = ws.forward(th64, patch[None], bf16_weights=True, bf16_acts=True)[0][4, 4]
+        for k in range(2):
+            assert abs(ys[k][iy, ix] - yo[k]) <= 1e-2 * np.abs(ys[k]).max(), (iy, ix, k)
+
