@@ -4,7 +4,8 @@ Plain, slow, obviously-correct numpy implementation of what the GPU path
 computes, written from the paper (Wang, "An Enhanced Spectral Boundary Integral
 Method for Modeling Highly Nonlinear Water Waves in Variable Depth"):
 
-* Sec. 2.2, Eq. (prognostic) and its integrating-factor form: the time step;
+* Sec. 2.2, Eq. (prognostic) and its integrating-factor form: the time step
+  (fixed-step RK4, and the adaptive embedded fifth/fourth-order pair);
 * Sec. 2.4 (successive approximations) with Appendix C, Eqs. (v2)-(v7): the
   surface vertical velocity V;
 * Sec. 3.1, Eq. (energy): the total energy diagnostic;
@@ -20,6 +21,7 @@ from .sbi_oracle import (  # noqa: F401
     Grid,
     Solver,
     SolveInfo,
+    lawson_rk54,
     w_sa_appc,
 )
 from . import dft  # noqa: F401

@@ -19,7 +19,14 @@ notes of the repository):
 * the iteration mode solves the fixed point of the recursion summed over
   orders (same expansion, J = L-1 convolution orders in both equations);
 * time stepping is Lawson integrating-factor RK4 on the integrating-factor
-  form of Eq. (prognostic) with omega = sqrt(k tanh(kh)).
+  form of Eq. (prognostic) with omega = sqrt(k tanh(kh));
+* the adaptive step of Sec. 2.2 (a six-stage fifth-order pair with an
+  embedded fourth-order solution, coefficients not printed) uses the
+  Cash-Karp pair in the same Lawson form; the "difference between the fifth-
+  and fourth-order solutions" is measured in the linear-energy norm relative
+  to the new state, and the step size follows the standard controller
+  h <- h min(5, max(0.2, 0.9 (tol/err)^(1/5))) (no growth right after a
+  rejection; rejected when err > tol).
 """
 from __future__ import annotations
 
@@ -32,6 +39,7 @@ import numpy as np
 OK = 0
 WARN_NOT_CONVERGED = 1
 WARN_DEPTH_CRITERION = 2
+WARN_STEP_LIMIT = 4
 ERR_NONFINITE = -5
 ERR_DIVERGED = -6
 
@@ -472,6 +480,92 @@ class Solver:
         return g.ifft(eh), g.ifft(ph), stats
 
     # ------------------------------------------------------------------------
+    # Adaptive step (Sec. 2.2): embedded fifth/fourth-order pair, Lawson form
+    # ------------------------------------------------------------------------
+    def linear_energy(self, eh, ph):
+        """sum over the grid of eta^2 + phi D(phi), D the linear Dirichlet-to-
+        Neumann operator F^-1{k tanh(kh) F{.}}: twice the linear part of the
+        energy of Eq. (energy) per unit cell area."""
+        g = self.g
+        e = g.ifft(eh)
+        p = g.ifft(ph)
+        dp = g.ifft(self.om2 * ph)
+        return float(np.sum(e * e) + np.sum(p * dp))
+
+    def step_rk54_hat(self, eh, ph, dt, tol, stats=None):
+        """One step of the embedded pair on masked spectra.  Returns the
+        fifth-order state (masked, then filtered when the filter is on) and
+        the relative difference sqrt(E(u5 - u4) / E(u5)) of the unfiltered
+        solutions in the linear-energy norm (0 when both vanish)."""
+        def f(u):
+            r = self.rhs(u[0], u[1], tol)
+            if stats is not None:
+                stats.append(r[3])
+            return (r[0], r[1])
+
+        u5, u4 = lawson_rk54((eh, ph), dt, f, lambda u, tau: self.propagate(u[0], u[1], tau))
+        num = self.linear_energy(u5[0] - u4[0], u5[1] - u4[1])
+        den = self.linear_energy(u5[0], u5[1])
+        err = 0.0 if num == 0.0 else math.sqrt(num / den) if den > 0.0 else math.inf
+        en = self.g.mask * u5[0]
+        pn = self.g.mask * u5[1]
+        if self.filter_beta is not None:
+            b1, b2 = self.filter_beta
+            lam = np.exp(-np.abs(self.g.k / b1) ** b2)  # Eq. (filter)
+            en = lam * en
+            pn = lam * pn
+        return en, pn, err
+
+    def step_adaptive(self, eta, phi_s, t0, t_end, dt, rk_tol, tol=1e-10, max_steps=1000):
+        """Advance physical (eta, phi_s) from t0 to t_end with the adaptive pair.
+        dt is the first trial step.  Returns (eta, phi_s, info) with info keys
+        t, dt_next, accepted, rejected, status, history = [(h, err, accepted)].
+        A step whose trial size reaches t_end (within a relative 1e-9) is cut
+        to land on t_end exactly; dt_next after such a cut step is the larger
+        of the controller's proposal and the trial size before the cut."""
+        SAFETY, FAC_MIN, FAC_MAX = 0.9, 0.2, 5.0
+        g = self.g
+        eh = g.MF(np.asarray(eta, dtype=np.float64).reshape(g.ny, g.nx))
+        ph = g.MF(np.asarray(phi_s, dtype=np.float64).reshape(g.ny, g.nx))
+        t, h = float(t0), float(dt)
+        acc = rej = 0
+        last_rejected = False
+        status = OK
+        hist = []
+        while t < t_end:
+            if acc + rej >= max_steps:
+                status = WARN_STEP_LIMIT
+                break
+            final = t_end - t <= h * (1.0 + 1e-9)
+            hs = t_end - t if final else h
+            en, pn, err = self.step_rk54_hat(eh, ph, hs, tol)
+            fmax = 1.0 if last_rejected else FAC_MAX
+            if not math.isfinite(err):
+                fac = FAC_MIN
+            elif err == 0.0:
+                fac = fmax
+            else:
+                fac = min(fmax, max(FAC_MIN, SAFETY * (rk_tol / err) ** 0.2))
+            ok = err <= rk_tol
+            hist.append((hs, err, ok))
+            if ok:
+                eh, ph = en, pn
+                t = t_end if final else t + hs
+                acc += 1
+                last_rejected = False
+                if self.rz is not None:
+                    eh, ph = self.apply_relaxation(eh, ph, t)
+                h = max(hs * fac, h) if final else hs * fac
+            else:
+                rej += 1
+                last_rejected = True
+                h = hs * fac
+                if h < 1e-12 * max(abs(t_end - t0), abs(t)):
+                    raise FloatingPointError("step size underflow")
+        info = dict(t=t, dt_next=h, accepted=acc, rejected=rej, status=status, history=hist)
+        return g.ifft(eh), g.ifft(ph), info
+
+    # ------------------------------------------------------------------------
     # Diagnostics, Eq. (energy)
     # ------------------------------------------------------------------------
     def diagnostics(self, eta, phi_s, tol=1e-10):
@@ -486,6 +580,53 @@ class Solver:
         mass = g.dA * float(np.sum(e))
         energy = 0.5 * g.dA * float(np.sum(V * p + e * e))
         return mass, energy
+
+
+# ---------------------------------------------------------------------------
+# Six-stage fifth-order Runge-Kutta pair with an embedded fourth-order
+# solution (the integrator class of Sec. 2.2): the coefficients of Cash & Karp
+# (ACM TOMS 16, 1990), nodes CK_C, stage matrix CK_A (row i: a_i0 .. a_i,i-1),
+# weights CK_B5 (order 5) and CK_B4 (order 4).
+# ---------------------------------------------------------------------------
+CK_C = (0.0, 1 / 5, 3 / 10, 3 / 5, 1.0, 7 / 8)
+CK_A = (
+    (),
+    (1 / 5,),
+    (3 / 40, 9 / 40),
+    (3 / 10, -9 / 10, 6 / 5),
+    (-11 / 54, 5 / 2, -70 / 27, 35 / 27),
+    (1631 / 55296, 175 / 512, 575 / 13824, 44275 / 110592, 253 / 4096),
+)
+CK_B5 = (37 / 378, 0.0, 250 / 621, 125 / 594, 0.0, 512 / 1771)
+CK_B4 = (2825 / 27648, 0.0, 18575 / 48384, 13525 / 55296, 277 / 14336, 1 / 4)
+
+
+def lawson_rk54(u, h, f, E):
+    """One step of the pair in integrating-factor (Lawson) form for
+    u' = L u + f(u), with E(x, tau) = exp(L tau) x (Sec. 2.2's integrating
+    factor): in v = E(u, -(t - t_n)) the pair is applied to
+    v' = E(f(E(v, t - t_n)), -(t - t_n)), which written back in u reads
+        U_i = E(u, c_i h) + h sum_j a_ij E(N_j, (c_i - c_j) h),  N_i = f(U_i)
+        u_q = E(u, h)     + h sum_j b_j  E(N_j, (1 - c_j) h)     (q = 5, 4).
+    u and the values of f and E are tuples of arrays.  Returns (u5, u4)."""
+    def axpy(acc, a, x):
+        return tuple(ai + a * xi for ai, xi in zip(acc, x))
+
+    N = []
+    for i in range(6):
+        U = E(u, CK_C[i] * h)
+        for j, a in enumerate(CK_A[i]):
+            if a != 0.0:
+                U = axpy(U, h * a, E(N[j], (CK_C[i] - CK_C[j]) * h))
+        N.append(f(U))
+    out = []
+    for b in (CK_B5, CK_B4):
+        v = E(u, h)
+        for j in range(6):
+            if b[j] != 0.0:
+                v = axpy(v, h * b[j], E(N[j], (1.0 - CK_C[j]) * h))
+        out.append(v)
+    return out[0], out[1]
 
 
 # ---------------------------------------------------------------------------
