@@ -15,7 +15,9 @@
  *     or by iterating the same expansion summed over orders to a residual
  *     tolerance -- mode SBI_MODE_ITER;
  *   - the time step integrates Eq. (prognostic) in its integrating-factor form
- *     (Sec. 2.2) with the classical 4-stage Runge-Kutta scheme of Lawson type;
+ *     (Sec. 2.2) with the classical 4-stage Runge-Kutta scheme of Lawson type
+ *     (fixed step), or with the adaptive six-stage fifth-order pair with an
+ *     embedded fourth-order solution that Sec. 2.2 describes;
  *   - the total energy is Eq. (energy) of Sec. 3.1.
  *
  * Units: lengths scaled by the peak wavenumber, time by the peak angular
@@ -51,6 +53,7 @@ typedef enum sbi_status {
     SBI_WARN_NOT_CONVERGED = 1,   /* iteration hit max_sweeps; last iterate returned */
     SBI_WARN_DEPTH_CRITERION = 2, /* k_band*max(delta) > 2.4, validity limit of Sec. 5 */
     SBI_WARN_FALLBACK_USED = 3,   /* learned seed rejected; linear guess used instead */
+    SBI_WARN_STEP_LIMIT = 4,      /* adaptive stepping stopped at max_steps before t_end */
     SBI_ERR_INVALID_ARG = -1,
     SBI_ERR_UNSUPPORTED = -2,
     SBI_ERR_WORKSPACE = -3,
@@ -114,6 +117,15 @@ typedef struct sbi_step_info {
     double max_residual;   /* largest final residual of any solve */
 } sbi_step_info;
 
+typedef struct sbi_adapt_info {
+    int32_t accepted;      /* steps taken */
+    int32_t rejected;      /* attempts discarded and redone with a smaller step */
+    double dt_next;        /* step size proposed for a following call */
+    double err_last;       /* error estimate of the last attempt */
+    double err_max;        /* largest error estimate of an accepted step */
+    sbi_step_info solve;   /* W solves of every attempt (6 per attempt per member) */
+} sbi_adapt_info;
+
 /* Default options (FP64, iteration, L = 7, alpha = 1/2, 64 sweeps, relax on). */
 void sbi_grid_defaults(sbi_grid* g);
 
@@ -159,6 +171,37 @@ sbi_status sbi_vertical_velocity(sbi_ctx* ctx, const void* eta, const void* phi_
  */
 sbi_status sbi_step(sbi_ctx* ctx, sbi_state* state, double dt, int32_t n, double tol,
                     sbi_step_info* info);
+
+/*
+ * Adaptive integration of Eq. (prognostic) (Sec. 2.2): every member is advanced
+ * in place from state->t to t_end by a six-stage fifth-order Runge-Kutta pair
+ * with an embedded fourth-order solution (the Cash-Karp coefficients; the paper
+ * does not print its own), in the same integrating-factor (Lawson) form as
+ * sbi_step.  Each attempt performs 6 W solves with the context's mode and `tol`.
+ * The step size is controlled by the difference of the two solutions measured
+ * in the linear-energy norm, err = sqrt(sum |d eta_k|^2 + k tanh(kh)|d phi_k|^2
+ * / the same sum over the fifth-order state), the largest over the members
+ * (all members share one step size): an attempt with err <= rk_tol is
+ * accepted (the fifth-order state is kept, then band-limited, filtered and
+ * relaxed like sbi_step's), else redone; the next size is
+ * h * min(5, max(0.2, 0.9 (rk_tol/err)^(1/5))), without growth right after a
+ * rejection.  A step whose trial size reaches t_end (to a relative 1e-9) is
+ * cut to land on it.  The paper keeps the difference below 1e-2 (validation
+ * cases) or 1e-3 (long crossing-sea runs).
+ *   dt        first trial step, > 0.
+ *   rk_tol    > 0.
+ *   max_steps cap on attempts; reaching it returns SBI_WARN_STEP_LIMIT with
+ *             the state written at state->t < t_end.
+ *   info      host, may be NULL; dt_next carries the controller's proposal to
+ *             a following call (after a cut last step, the larger of the
+ *             proposal and the trial size before the cut).
+ * Errors: SBI_ERR_INVALID_ARG (t_end < state->t, dt or rk_tol not positive and
+ * finite, max_steps < 1); SBI_ERR_DIVERGED also when the step size falls below
+ * 1e-12 of the interval; the state is left unchanged on any error.  The call
+ * synchronises the stream after every attempt (no graph capture).
+ */
+sbi_status sbi_step_adaptive(sbi_ctx* ctx, sbi_state* state, double t_end, double dt, double rk_tol,
+                             double tol, int32_t max_steps, sbi_adapt_info* info);
 
 /*
  * FP64 mass  M = dA * sum(eta)  and energy  E = dA/2 * sum(W phi_s + eta^2)

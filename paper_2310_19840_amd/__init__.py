@@ -129,6 +129,18 @@ class Solver:
         return st, dict(t=s.t, solves=info.solves, sweeps_total=info.sweeps_total, sweeps_max=info.sweeps_max,
                         fallbacks=info.fallbacks, max_residual=info.max_residual)
 
+    def step_adaptive(self, eta, phi_s, t_end, dt, rk_tol, tol=1e-10, t=0.0, max_steps=1000):
+        s = _lib.sbi_state(self._dev(eta, "eta"), self._dev(phi_s, "phi_s"), float(t))
+        info = _lib.sbi_adapt_info()
+        st = self.lib.sbi_step_adaptive(self.ctx, C.byref(s), float(t_end), float(dt), float(rk_tol), float(tol),
+                                        int(max_steps), C.byref(info))
+        if st < 0:
+            raise SBIError(st, "sbi_step_adaptive")
+        v = info.solve
+        return st, dict(t=s.t, accepted=info.accepted, rejected=info.rejected, dt_next=info.dt_next,
+                        err_last=info.err_last, err_max=info.err_max, solves=v.solves, sweeps_total=v.sweeps_total,
+                        sweeps_max=v.sweeps_max, fallbacks=v.fallbacks, max_residual=v.max_residual)
+
     def diagnostics(self, eta, phi_s, tol=1e-10):
         s = _lib.sbi_state(self._dev(eta, "eta"), self._dev(phi_s, "phi_s"), 0.0)
         m = (C.c_double * self.batch)()

@@ -11,6 +11,7 @@ SBI_OK = 0
 SBI_WARN_NOT_CONVERGED = 1
 SBI_WARN_DEPTH_CRITERION = 2
 SBI_WARN_FALLBACK_USED = 3
+SBI_WARN_STEP_LIMIT = 4
 SBI_ERR_INVALID_ARG = -1
 SBI_ERR_UNSUPPORTED = -2
 SBI_ERR_WORKSPACE = -3
@@ -50,6 +51,11 @@ class sbi_step_info(C.Structure):
                 ("fallbacks", C.c_int32), ("max_residual", C.c_double)]
 
 
+class sbi_adapt_info(C.Structure):
+    _fields_ = [("accepted", C.c_int32), ("rejected", C.c_int32), ("dt_next", C.c_double),
+                ("err_last", C.c_double), ("err_max", C.c_double), ("solve", sbi_step_info)]
+
+
 # exported symbols and their signatures: (restype, argtypes)
 SIGNATURES = {
     "sbi_grid_defaults": (None, [C.POINTER(sbi_grid)]),
@@ -60,6 +66,8 @@ SIGNATURES = {
                                         C.c_void_p, C.c_void_p, C.POINTER(sbi_solve_info)]),
     "sbi_step": (C.c_int, [C.c_void_p, C.POINTER(sbi_state), C.c_double, C.c_int32, C.c_double,
                            C.POINTER(sbi_step_info)]),
+    "sbi_step_adaptive": (C.c_int, [C.c_void_p, C.POINTER(sbi_state), C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_int32, C.POINTER(sbi_adapt_info)]),
     "sbi_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(sbi_state), C.c_double, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double)]),
     "sbi_set_relaxation": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32]),

@@ -42,7 +42,9 @@ enum {
     C_VP,                // T(V_n): candidate answer of the iteration
     C_NP,                // nonlinear term of the potential equation
     C_DV, C_DB,          // nonlinear part (V* - kT phi, phi_b - S phi) of the last solve
-    C_COUNT
+    C_KE0,               // stage derivatives of the adaptive pair: eta part K_0..K_5
+    C_KP0 = C_KE0 + 6,   //   potential part
+    C_COUNT = C_KP0 + 6
 };
 // half-form buffers
 enum {
@@ -132,7 +134,8 @@ static void prof_flush(sbi_ctx* c);
 static const char* kStatusNames[] = {"SBI_OK",
                                      "SBI_WARN_NOT_CONVERGED: iteration reached max_sweeps",
                                      "SBI_WARN_DEPTH_CRITERION: k_band*max(delta) exceeds 2.4",
-                                     "SBI_WARN_FALLBACK_USED: learned seed rejected"};
+                                     "SBI_WARN_FALLBACK_USED: learned seed rejected",
+                                     "SBI_WARN_STEP_LIMIT: max_steps reached before t_end"};
 static const char* kErrNames[] = {"",
                                   "SBI_ERR_INVALID_ARG: invalid argument",
                                   "SBI_ERR_UNSUPPORTED: unsupported size or option",
@@ -245,7 +248,7 @@ extern "C" size_t sbi_workspace_bytes(const sbi_grid* g, int32_t batch) {
 }
 
 extern "C" const char* sbi_status_string(sbi_status s) {
-    if (s >= 0 && s <= 3) return kStatusNames[s];
+    if (s >= 0 && s <= 4) return kStatusNames[s];
     if (s <= -1 && s >= -6) return kErrNames[-s];
     return "unknown sbi_status";
 }
@@ -1215,8 +1218,8 @@ extern "C" sbi_status sbi_vertical_velocity(sbi_ctx* c, const void* eta, const v
     return st != SBI_OK ? st : warn;
 }
 
-// nonlinear term and RK stage update after a solve
-static sbi_status stage_update(sbi_ctx* c, int stage, double dt, int vh_buf) {
+// nonlinear term of the potential equation at the stage state -> C_NP
+static sbi_status nonlinear_term(sbi_ctx* c) {
     const bool iter = c->grid.mode == SBI_MODE_ITER;
     RowNphiParams np{};
     np.g = c->gd;
@@ -1237,7 +1240,12 @@ static sbi_status stage_update(sbi_ctx* c, int stage, double dt, int vh_buf) {
     int s = b.prod(HALF(H_PROD0));
     b.term(s, 0, 1.0, FN_ONE, 0, DV_NONE);
     b.cout(SRC_ACC0, CMP(C_NP));
-    SBI_TRY(run_col(c, b));
+    return run_col(c, b);
+}
+
+// nonlinear term and RK stage update after a solve
+static sbi_status stage_update(sbi_ctx* c, int stage, double dt, int vh_buf) {
+    SBI_TRY(nonlinear_term(c));
     RkParams rp{};
     rp.g = c->gd;
     rp.stage = stage;
@@ -1371,6 +1379,139 @@ extern "C" sbi_status sbi_step(sbi_ctx* c, sbi_state* state, double dt, int32_t 
     state->t = t;
     si.fallbacks = c->fallbacks;
     if (info) *info = si;
+    if (worst == SBI_OK && c->fallbacks > 0) worst = SBI_WARN_FALLBACK_USED;
+    return worst;
+}
+
+// stage `stage` of the embedded pair after its solve; the last stage leaves
+// the fifth-order candidate in (C_ES, C_PS) and returns the largest relative
+// difference of the two solutions over the members in *err
+static sbi_status pair_stage(sbi_ctx* c, int stage, double h, int vh_buf, double* err) {
+    SBI_TRY(nonlinear_term(c));
+    Rk54Params rp{};
+    rp.g = c->gd;
+    rp.stage = stage;
+    rp.h = h;
+    rp.eh = CMP(C_EH);
+    rp.ph = CMP(C_PH);
+    rp.es = CMP(C_ES);
+    rp.ps = CMP(C_PS);
+    rp.Vh = CMP(vh_buf);
+    rp.Nph = CMP(C_NP);
+    for (int j = 0; j < 6; ++j) {
+        rp.ke[j] = CMP(C_KE0 + j);
+        rp.kp[j] = CMP(C_KP0 + j);
+    }
+    rp.fb1 = c->grid.filter_beta1;
+    rp.fb2 = c->grid.filter_beta2;
+    rp.partial = c->diag_partial;
+    rp.nblk = c->diag_nblk;
+    c->st.launches += 1;
+    {
+        ProfScope ps_(c, K_RK);
+        SBI_TRY(hip_ok(launch_rk54(c->fp64, rp, c->batch, c->stream)));
+    }
+    if (stage < 5) return SBI_OK;
+    std::vector<double> part((size_t)c->batch * rp.nblk * 2);
+    SBI_HIP(hipMemcpyAsync(part.data(), c->diag_partial, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    c->st.syncs += 1;
+    double e = 0.0;
+    for (int b = 0; b < c->batch; ++b) {
+        double num = 0.0, den = 0.0;
+        for (int k = 0; k < rp.nblk; ++k) {
+            num += part[((size_t)b * rp.nblk + k) * 2];
+            den += part[((size_t)b * rp.nblk + k) * 2 + 1];
+        }
+        // both solutions vanish: nothing to control; a vanishing candidate alone: reject
+        const double eb = num == 0.0 ? 0.0 : den > 0.0 ? std::sqrt(num / den) : HUGE_VAL;
+        e = std::isnan(eb) || std::isnan(e) ? NAN : std::max(e, eb);
+    }
+    *err = e;
+    return SBI_OK;
+}
+
+static sbi_status copy_state(sbi_ctx* c, int de, int dp, int se, int sp) {
+    const size_t bytes = (size_t)c->gd.s_cmp * c->csz * c->batch;
+    SBI_HIP(hipMemcpyAsync(CMP(de), CMP(se), bytes, hipMemcpyDeviceToDevice, c->stream));
+    SBI_HIP(hipMemcpyAsync(CMP(dp), CMP(sp), bytes, hipMemcpyDeviceToDevice, c->stream));
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_step_adaptive(sbi_ctx* c, sbi_state* state, double t_end, double dt, double rk_tol,
+                                        double tol, int32_t max_steps, sbi_adapt_info* info) {
+    if (!c || !state || !state->eta || !state->phi_s || max_steps < 1) return SBI_ERR_INVALID_ARG;
+    if (!std::isfinite(state->t) || !std::isfinite(t_end) || !(t_end >= state->t)) return SBI_ERR_INVALID_ARG;
+    if (!(dt > 0.0) || !std::isfinite(dt) || !(rk_tol > 0.0) || !std::isfinite(rk_tol)) return SBI_ERR_INVALID_ARG;
+    if (c->grid.mode == SBI_MODE_ITER && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
+    // step-size controller: growth limits and safety factor of the usual
+    // embedded-pair control, exponent 1/5 (the local error of the fourth-order
+    // solution is O(h^5))
+    const double kSafety = 0.9, kFacMin = 0.2, kFacMax = 5.0;
+    c->st = Stats();
+    c->fallbacks = 0;
+    sbi_adapt_info ai{};
+    SBI_TRY(to_spectral(c, state->eta, state->phi_s, true));
+    sbi_status worst = SBI_OK;
+    const double t0 = state->t;
+    double t = t0, h = dt;
+    bool last_rejected = false;
+    while (t < t_end) {
+        if (ai.accepted + ai.rejected >= max_steps) {
+            worst = std::max(worst, SBI_WARN_STEP_LIMIT);
+            break;
+        }
+        // a step whose trial size reaches t_end (within a relative 1e-9) lands on it
+        const bool final = t_end - t <= h * (1.0 + 1e-9);
+        const double hs = final ? t_end - t : h;
+        double err = 0.0;
+        for (int stage = 0; stage < 6; ++stage) {
+            int vh = 0;
+            SBI_TRY(solve_stage(c, nullptr, tol, true, &vh));
+            if (c->grid.mode == SBI_MODE_ITER) {
+                sbi_status st = solve_status(c, nullptr, true);
+                if (st < 0) return st;
+                if (st > worst) worst = st;
+                acc_info(c, &ai.solve);
+            } else {
+                ai.solve.solves += c->batch;
+            }
+            SBI_TRY(pair_stage(c, stage, hs, vh, &err));
+        }
+        const double fmax = last_rejected ? 1.0 : kFacMax;
+        double fac;
+        if (!std::isfinite(err)) fac = kFacMin;
+        else if (err == 0.0) fac = fmax;
+        else fac = std::min(fmax, std::max(kFacMin, kSafety * std::pow(rk_tol / err, 0.2)));
+        ai.err_last = err;
+        if (err <= rk_tol) {
+            SBI_TRY(copy_state(c, C_EH, C_PH, C_ES, C_PS));
+            t = final ? t_end : t + hs;
+            ai.accepted += 1;
+            ai.err_max = std::max(ai.err_max, err);
+            last_rejected = false;
+            if (c->relax_on) SBI_TRY(relax_zone(c, t));
+            h = final ? std::max(hs * fac, h) : hs * fac;
+        } else {
+            SBI_TRY(copy_state(c, C_ES, C_PS, C_EH, C_PH));
+            ai.rejected += 1;
+            last_rejected = true;
+            h = hs * fac;
+            if (h < 1e-12 * std::max(t_end - t0, std::fabs(t))) return SBI_ERR_DIVERGED;
+        }
+    }
+    if (c->grid.mode == SBI_MODE_SA) {
+        SBI_TRY(read_heads(c));
+        for (int b = 0; b < c->batch; ++b)
+            if (c->head[b].nonfinite) return SBI_ERR_NONFINITE;
+    }
+    SBI_TRY(to_physical(c, state->eta, state->phi_s));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    state->t = t;
+    ai.dt_next = h;
+    ai.solve.fallbacks = c->fallbacks;
+    if (info) *info = ai;
     if (worst == SBI_OK && c->fallbacks > 0) worst = SBI_WARN_FALLBACK_USED;
     return worst;
 }

@@ -89,6 +89,9 @@ SBI_DISPATCH(launch_col, ColParams)
 hipError_t launch_rk(int fp64, const RkParams& p, int batch, hipStream_t s) {
     return fp64 ? launch_rk_t<double>(p, batch, s) : launch_rk_t<float>(p, batch, s);
 }
+hipError_t launch_rk54(int fp64, const Rk54Params& p, int batch, hipStream_t s) {
+    return fp64 ? launch_rk54_t<double>(p, batch, s) : launch_rk54_t<float>(p, batch, s);
+}
 hipError_t launch_diag(int fp64, const DiagParams& p, int batch, hipStream_t s) {
     return fp64 ? launch_diag_t<double>(p, batch, s) : launch_diag_t<float>(p, batch, s);
 }

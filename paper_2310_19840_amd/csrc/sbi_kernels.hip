@@ -1499,6 +1499,121 @@ __global__ void k_rk(const RkParams p) {
     ps[o] = cx<V>(R(n_pr), R(n_pi));
 }
 
+// Six-stage fifth-order pair with an embedded fourth-order solution (Sec. 2.2),
+// the coefficients of Cash & Karp (ACM TOMS 16, 1990): nodes, stage matrix,
+// fifth-order weights and the weight differences fifth minus fourth order.
+static __constant__ double kPairC[6] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0};
+static __constant__ double kPairA[6][5] = {
+    {0.0, 0.0, 0.0, 0.0, 0.0},
+    {1.0 / 5.0, 0.0, 0.0, 0.0, 0.0},
+    {3.0 / 40.0, 9.0 / 40.0, 0.0, 0.0, 0.0},
+    {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0.0, 0.0},
+    {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0.0},
+    {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0}};
+static __constant__ double kPairB[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0};
+static __constant__ double kPairE[6] = {37.0 / 378.0 - 2825.0 / 27648.0, 0.0,  250.0 / 621.0 - 18575.0 / 48384.0,
+                                 125.0 / 594.0 - 13525.0 / 55296.0, -277.0 / 14336.0, 512.0 / 1771.0 - 0.25};
+
+// One stage of the pair in Lawson form, per kept mode.  With E(tau) the exact
+// linear propagator (eta, phi) -> (cos eta + om sin phi, -sin/om eta + cos phi)
+// and N_i = (W - om^2 phi, N_phi) at stage state U_i, the stage derivative is
+// kept as K_i = E(-c_i h) N_i (carried back to t_n), so that
+//   U_{i+1} = E(c_{i+1} h) (u_n + h sum_j a_{i+1,j} K_j),
+//   u_5     = E(h) (u_n + h sum_j b_j K_j),   u_5 - u_4 = E(h) h sum_j e_j K_j.
+// E preserves |eta|^2 + om^2 |phi|^2 per mode, so the linear-energy norms of
+// the difference and of the candidate are summed in the frame of t_n; the last
+// stage writes per-block partial sums of both (weights 2 for m_x > 0: the half
+// spectrum stands for its conjugate).
+template <typename R>
+__global__ void k_rk54(const Rk54Params p) {
+    using V = typename cplx_of<R>::type;
+    __shared__ double red[2][256];
+    const int mem = blockIdx.y;
+    const int i = p.stage;
+    const double h = p.h;
+    const double href = p.g.href[mem];
+    double num = 0.0, den = 0.0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < p.g.s_cmp;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const ModeGeo m = mode_geo(p.g, idx);
+        if (!m.valid) continue;
+        const long long o = mem * p.g.s_cmp + idx;
+        const double om2 = m.k * tanh(m.k * href);
+        const double om = sqrt(om2);
+        // (er, ei, pr, pi) -> E(tau) applied
+        auto prop = [&](double tau, double& er, double& ei, double& pr, double& pi_) {
+            const double c = cos(om * tau), s = sin(om * tau);
+            const double sw = om > 0.0 ? s / om : tau;
+            const double a = c * er + om * s * pr, b = c * ei + om * s * pi_;
+            pr = -sw * er + c * pr;
+            pi_ = -sw * ei + c * pi_;
+            er = a;
+            ei = b;
+        };
+        const V vh = static_cast<const V*>(p.Vh)[o];
+        const V nph = static_cast<const V*>(p.Nph)[o];
+        const V psv = static_cast<const V*>(p.ps)[o];
+        double ker = (double)vh.x - om2 * (double)psv.x, kei = (double)vh.y - om2 * (double)psv.y;
+        double kpr = (double)nph.x, kpi = (double)nph.y;
+        prop(-kPairC[i] * h, ker, kei, kpr, kpi);
+        static_cast<V*>(p.ke[i])[o] = cx<V>(R(ker), R(kei));
+        static_cast<V*>(p.kp[i])[o] = cx<V>(R(kpr), R(kpi));
+        const V ue = static_cast<const V*>(p.eh)[o];
+        const V up = static_cast<const V*>(p.ph)[o];
+        // the stored value (rounded to R) enters the sums, as it does when read back
+        const V kse = cx<V>(R(ker), R(kei)), ksp = cx<V>(R(kpr), R(kpi));
+        const double* w = i < 5 ? kPairA[i + 1] : kPairB;
+        double ser = 0.0, sei = 0.0, spr = 0.0, spi = 0.0;   // sum_j w_j K_j
+        double der = 0.0, dei = 0.0, dpr = 0.0, dpi = 0.0;   // sum_j e_j K_j (last stage)
+        for (int j = 0; j <= i; ++j) {
+            const V ke = j == i ? kse : static_cast<const V*>(p.ke[j])[o];
+            const V kp = j == i ? ksp : static_cast<const V*>(p.kp[j])[o];
+            ser += w[j] * (double)ke.x;
+            sei += w[j] * (double)ke.y;
+            spr += w[j] * (double)kp.x;
+            spi += w[j] * (double)kp.y;
+            if (i == 5) {
+                der += kPairE[j] * (double)ke.x;
+                dei += kPairE[j] * (double)ke.y;
+                dpr += kPairE[j] * (double)kp.x;
+                dpi += kPairE[j] * (double)kp.y;
+            }
+        }
+        double ner = (double)ue.x + h * ser, nei = (double)ue.y + h * sei;
+        double npr = (double)up.x + h * spr, npi = (double)up.y + h * spi;
+        if (i == 5) {
+            const double wt = m.mx == 0 ? 1.0 : 2.0;
+            num += wt * h * h * (der * der + dei * dei + om2 * (dpr * dpr + dpi * dpi));
+            den += wt * (ner * ner + nei * nei + om2 * (npr * npr + npi * npi));
+        }
+        prop((i < 5 ? kPairC[i + 1] : 1.0) * h, ner, nei, npr, npi);
+        if (i == 5 && p.fb1 > 0.0 && p.fb2 > 0.0) {
+            const double lam = exp(-pow(fabs(m.k / p.fb1), p.fb2));
+            ner *= lam;
+            nei *= lam;
+            npr *= lam;
+            npi *= lam;
+        }
+        static_cast<V*>(p.es)[o] = cx<V>(R(ner), R(nei));
+        static_cast<V*>(p.ps)[o] = cx<V>(R(npr), R(npi));
+    }
+    if (i < 5) return;
+    red[0][threadIdx.x] = num;
+    red[1][threadIdx.x] = den;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        p.partial[((long long)mem * p.nblk + blockIdx.x) * 2 + 0] = red[0][0];
+        p.partial[((long long)mem * p.nblk + blockIdx.x) * 2 + 1] = red[1][0];
+    }
+}
+
 template <typename R>
 __global__ void k_diag(const DiagParams p) {
     using V = typename cplx_of<R>::type;
@@ -1678,6 +1793,13 @@ template <> hipError_t launch_col_t<Real>(const ColParams& p, int b, const Twidd
 template <> hipError_t launch_rk_t<Real>(const RkParams& p, int batch, hipStream_t s) {
     dim3 block(256), grid((unsigned)((p.g.s_cmp + 255) / 256), batch);
     hipLaunchKernelGGL(k_rk<Real>, grid, block, 0, s, p);
+    return hipGetLastError();
+}
+template <> hipError_t launch_rk54_t<Real>(const Rk54Params& p, int batch, hipStream_t s) {
+    // the last stage reduces over a fixed number of workgroups per member
+    const unsigned nb = p.stage == 5 ? (unsigned)p.nblk : (unsigned)((p.g.s_cmp + 255) / 256);
+    dim3 block(256), grid(nb, batch);
+    hipLaunchKernelGGL(k_rk54<Real>, grid, block, 0, s, p);
     return hipGetLastError();
 }
 template <> hipError_t launch_diag_t<Real>(const DiagParams& p, int batch, hipStream_t s) {

@@ -126,6 +126,24 @@ struct RkParams {
     double fb1, fb2; // filter
 };
 
+// one stage of the embedded fifth/fourth-order pair in integrating-factor form
+struct Rk54Params {
+    GridDev g;
+    int stage;       // 0..5: the stage whose W and N_phi are given
+    double h;
+    const void* eh;  // u_n
+    const void* ph;
+    void* es;        // stage state in / next stage state out (the fifth-order candidate after stage 5)
+    void* ps;
+    const void* Vh;  // W spectrum at the stage state
+    const void* Nph; // nonlinear term of the potential equation at the stage state
+    void* ke[6];     // stage derivatives carried back to t_n (written at their stage, read after)
+    void* kp[6];
+    double fb1, fb2; // filter (applied to the candidate)
+    double* partial; // [batch][nblk][2]: error and state norms (stage 5)
+    int nblk;
+};
+
 struct DiagParams {
     GridDev g;
     const void* eh;
@@ -155,6 +173,7 @@ template <typename R> hipError_t launch_row_blend_t(const RowBlendParams&, int, 
 template <typename R> hipError_t launch_row_feat_t(const RowFeatParams&, int, const Twiddles&, hipStream_t);
 template <typename R> hipError_t launch_col_t(const ColParams&, int, const Twiddles&, hipStream_t);
 template <typename R> hipError_t launch_rk_t(const RkParams&, int, hipStream_t);
+template <typename R> hipError_t launch_rk54_t(const Rk54Params&, int, hipStream_t);
 template <typename R> hipError_t launch_diag_t(const DiagParams&, int, hipStream_t);
 
 hipError_t launch_row_fwd(int fp64, const RowFwdParams& p, int batch, const Twiddles& tw, hipStream_t s);
@@ -167,6 +186,7 @@ hipError_t launch_row_blend(int fp64, const RowBlendParams& p, int batch, const 
 hipError_t launch_row_feat(int fp64, const RowFeatParams& p, int batch, const Twiddles& tw, hipStream_t s);
 hipError_t launch_col(int fp64, const ColParams& p, int batch, const Twiddles& tw, hipStream_t s);
 hipError_t launch_rk(int fp64, const RkParams& p, int batch, hipStream_t s);
+hipError_t launch_rk54(int fp64, const Rk54Params& p, int batch, hipStream_t s);
 hipError_t launch_diag(int fp64, const DiagParams& p, int batch, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* ctl, int batch, int slots, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);

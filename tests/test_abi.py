@@ -68,7 +68,7 @@ def test_invalid_grids_rejected(lib, bad):
 
 def test_status_strings(lib):
     from paper_2310_19840_amd import _lib
-    for code in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6):
+    for code in (0, 1, 2, 3, 4, -1, -2, -3, -4, -5, -6):
         s = _lib.status_string(code)
         assert s.startswith("SBI_")
     assert "unknown" in _lib.status_string(42)
@@ -84,6 +84,14 @@ def test_null_arguments_rejected(lib):
     assert lib.sbi_destroy(None) == _lib.SBI_ERR_INVALID_ARG
     assert lib.sbi_vertical_velocity(None, None, None, None, 1e-8, None, None, None) == _lib.SBI_ERR_INVALID_ARG
     assert lib.sbi_step(None, None, 0.1, 1, 1e-8, None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_step_adaptive(None, None, 1.0, 0.1, 1e-3, 1e-8, 10, None) == _lib.SBI_ERR_INVALID_ARG
+
+
+def test_adapt_info_layout():
+    # the ctypes mirror of sbi_adapt_info: two int32, three doubles, then sbi_step_info
+    from paper_2310_19840_amd import _lib
+    assert C.sizeof(_lib.sbi_adapt_info) == 8 + 3 * 8 + C.sizeof(_lib.sbi_step_info)
+    assert _lib.sbi_adapt_info.solve.offset == 32
 
 
 def test_product_path_has_no_cpu_fallback():
