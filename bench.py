@@ -12,7 +12,10 @@ resident in HBM before the timed region.
 HIP events bracket the sweep kernels of the last timed step only).  `forms` adds, at the same tolerance, two
 realisations stepped in one captured HIP graph with the previous-solve seed
 ("batched+prev") and with the learned warm start ("batched+learned"), the
-plain step in FP32 (tolerance 1e-6, the FP32 floor), the ragged C4
+plain step in FP32 (tolerance 1e-6, the FP32 floor), the adaptive
+fifth/fourth-order pair over four peak periods ("adaptive", at the error bound
+3e-7 that makes it at least as accurate as the fixed step; counted in
+fixed-step equivalents of T_p/64), the ragged C4
 ensemble (96 members, SA mode, FP32) in one graph, and the 512^2 flat
 crossing sea in FP32 beside FP64 with the FP32 error (max |eta|, energy drift).
 
@@ -226,6 +229,38 @@ def run_batched(args, dev, seed_mode, members):
                 first_step_sweeps_mean=sum(first) / len(first))
 
 
+def run_adaptive(args, dev, rk_tol):
+    """One C5 member advanced by the adaptive fifth/fourth-order pair over
+    `adaptive_periods` peak periods after one untimed period that lets the
+    controller reach its working step; same W tolerance.  `value` counts
+    fixed-step equivalents (grid points x simulated time / (T_p/64) per wall
+    second), comparable with the plain form's."""
+    import torch
+
+    from paper_2310_19840_amd import Solver
+
+    cfg = c5_members([0], args.n)[0]
+    g = cfg["grid"]
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="iter", max_sweeps=args.max_sweeps)
+    eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=dev)
+    phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=dev)
+    dt, tol, Tp = cfg["dt"], cfg["tol"], cfg["period"]
+    _, w = s.step_adaptive(eta, phi, Tp, dt, rk_tol, tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_end = w["t"] + args.adaptive_periods * Tp
+    st, info = s.step_adaptive(eta, phi, t_end, w["dt_next"], rk_tol, tol=tol, t=w["t"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    fixed = args.adaptive_periods * Tp / dt
+    att = info["accepted"] + info["rejected"]
+    return dict(value=g.nx * g.ny * fixed / el, ms_per_fixed_step=1e3 * el / fixed, status=st, rk_tol=rk_tol,
+                periods=args.adaptive_periods, accepted=info["accepted"], rejected=info["rejected"],
+                mean_dt_over_Tp=round(args.adaptive_periods / max(info["accepted"], 1), 4),
+                ms_per_attempt=round(1e3 * el / max(att, 1), 3), err_max=info["err_max"],
+                sweeps_mean=round(info["sweeps_total"] / max(info["solves"], 1), 2), sweeps_max=info["sweeps_max"])
+
+
 def run_c4(args, dev):
     """The ragged ensemble (32 x 128^2 + 48 x 256^2 + 16 x 512^2), SA mode, FP32, one graph."""
     import torch
@@ -297,7 +332,11 @@ def main():
     ap.add_argument("--members", type=int, default=2, help="realisations of the batched forms")
     ap.add_argument("--c4-steps", type=int, default=4)
     ap.add_argument("--c3-steps", type=int, default=32)
-    ap.add_argument("--forms", default="plain,batched+prev,batched+learned,plain-fp32,c4,c3-precision")
+    ap.add_argument("--forms", default="plain,batched+prev,batched+learned,plain-fp32,adaptive,c4,c3-precision")
+    ap.add_argument("--adaptive-periods", type=float, default=4.0)
+    ap.add_argument("--rk-tol", type=float, default=3e-7,
+                    help="error bound of the adaptive form; at 3e-7 its global error over two periods of a "
+                         "128^2 sample of the sea (1.9e-7) is below that of fixed RK4 at T_p/64 (4.9e-7)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -317,7 +356,7 @@ def main():
     traffic = measured_traffic(plain["dominant"]) if (g.nx, g.ny) == (1024, 1024) else None
     roofline = dict(plain["roofline"])
     roofline["traffic"] = round(traffic) if traffic is not None else None
-    out_forms = {"plain": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in plain.items()
+    out_forms = {"plain": {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in plain.items()
                            if k in ("value", "ms_per_step", "sweeps_mean", "sweeps_max", "max_residual", "status")}}
     if "batched+prev" in forms:
         out_forms["batched+prev"] = run_batched(args, dev, "prev", args.members)
@@ -330,6 +369,8 @@ def main():
                                                                           "sweeps_max", "max_residual", "status",
                                                                           "roofline")}
         out_forms["plain-fp32"]["tol"] = 1e-6
+    if "adaptive" in forms:
+        out_forms["adaptive"] = run_adaptive(args, dev, args.rk_tol)
     if "c4" in forms:
         out_forms["c4"] = run_c4(args, dev)
     if "c3-precision" in forms:

@@ -217,3 +217,53 @@ def test_fullsize_learned_seed_features_and_sampled_inference(gpu):
         for k in range(2):
             assert abs(ys[k][iy, ix] - yo[k]) <= 1e-2 * np.abs(ys[k]).max(), (iy, ix, k)
 
+
+
+def test_fullsize_adaptive_linear_waves_exact_and_sea_invariants(gpu):
+    # the adaptive pair at 1024^2: (a) waves of tiny amplitude over a flat bed
+    # are propagated exactly by the integrating factor whatever the step, and
+    # the controller grows every step by its largest factor; (b) on the
+    # crossing sea, steps of the pair conserve mass and move the energy by far
+    # less than the dealiasing drift
+    import math
+    import torch
+    from paper_2310_19840_amd import Solver
+    cfg = _c5()
+    g = cfg["grid"]
+    _say("1024^2 adaptive")
+    h0 = float(cfg["h_ref"])
+    s = Solver(g.nx, g.ny, g.lx, g.ly, np.full((g.ny, g.nx), h0), device=gpu, mode="iter", max_sweeps=200)
+    gs = si.GridSpec(g.nx, g.ny, g.lx, g.ly)
+    X, Y = np.meshgrid(gs.x(), gs.y())
+    a = 1e-9
+    modes = [(3, 5), (17, -9), (120, 64)]
+    eta0 = np.zeros((g.ny, g.nx))
+    phi0 = np.zeros((g.ny, g.nx))
+    t_end = 3 * cfg["period"]
+    exact = np.zeros((g.ny, g.nx))
+    for mx, my in modes:
+        kx, ky = 2 * math.pi * mx / g.lx, 2 * math.pi * my / g.ly
+        k = math.hypot(kx, ky)
+        om = math.sqrt(k * math.tanh(k * h0))
+        th = kx * X + ky * Y
+        eta0 += a * np.cos(th)
+        phi0 += (a / om) * np.sin(th)
+        exact += a * np.cos(th - om * t_end)
+    eta = torch.tensor(eta0[None], dtype=torch.float64, device=gpu)
+    phi = torch.tensor(phi0[None], dtype=torch.float64, device=gpu)
+    st, info = s.step_adaptive(eta, phi, t_end, cfg["dt"], 1e-6, tol=1e-8)
+    assert st == 0 and info["rejected"] == 0 and info["t"] == t_end, info
+    assert info["accepted"] >= 3 and info["err_max"] < 1e-6
+    assert np.abs(eta.cpu().numpy()[0] - exact).max() < 1e-7 * a
+
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=gpu, mode="iter", max_sweeps=200)
+    eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=gpu)
+    phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=gpu)
+    m0, e0 = s.diagnostics(eta, phi, tol=1e-11)
+    st, info = s.step_adaptive(eta, phi, 2 * cfg["dt"], cfg["dt"], 1e-3, tol=1e-8)
+    assert st == 0 and info["accepted"] >= 1 and info["solves"] == 6 * (info["accepted"] + info["rejected"])
+    m1, e1 = s.diagnostics(eta, phi, tol=1e-11)
+    amp = float(np.abs(cfg["eta"]).max())
+    assert abs(m1[0] - m0[0]) <= 1e-12 * amp * g.lx * g.ly
+    assert abs(e1[0] - e0[0]) <= 1e-5 * abs(e0[0])
+    assert np.isfinite(eta.cpu().numpy()).all()
