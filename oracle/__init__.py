@@ -10,6 +10,8 @@ Method for Modeling Highly Nonlinear Water Waves in Variable Depth"):
   surface vertical velocity V;
 * Sec. 3.1, Eq. (energy): the total energy diagnostic;
 * Sec. 3.3, Eq. (filter): the optional low-pass filter;
+* Sec. 3.2: the numerical wave tank's pneumatic wavemaker and damping
+  pressure (Eq. (pd));
 * ``warmstart``: the learned warm start of the W iteration (features, network
   forward and backward, Adam), defined in that module's header.
 

@@ -26,7 +26,13 @@ notes of the repository):
   and fourth-order solutions" is measured in the linear-energy norm relative
   to the new state, and the step size follows the standard controller
   h <- h min(5, max(0.2, 0.9 (tol/err)^(1/5))) (no growth right after a
-  rejection; rejected when err > tol).
+  rejection; rejected when err > tol);
+* the wave tank's surface pressure p = p_g + p_d enters the dynamic surface
+  condition as phi_t = ... - eta - p (the sign under which the generator's
+  prefactor yields waves of amplitude a_j); the bell of p_g is centred on
+  x = 0 (split over both ends of the periodic domain), the damping weight
+  exp(-((x - x0)/w)^2) uses the periodic distance, w = 4 pi by default, and
+  p_d's k = 0 mode is zero.
 """
 from __future__ import annotations
 
@@ -109,7 +115,7 @@ class Solver:
 
     def __init__(self, grid: Grid, depth, h_ref: float | None = None, order: int = 7,
                  mode: str = "iter", max_sweeps: int = 64, relax: bool = True,
-                 filter_beta=None, relaxation_zone=None, seed: str = "linear", net=None):
+                 filter_beta=None, relaxation_zone=None, seed: str = "linear", net=None, wavemaker=None):
         self.g = grid
         depth = np.asarray(depth, dtype=np.float64).reshape(grid.ny, grid.nx)
         if np.any(~np.isfinite(depth)) or np.any(depth <= 0):
@@ -132,6 +138,12 @@ class Solver:
         self.om = np.sqrt(self.om2)
         self.filter_beta = filter_beta
         self.rz = relaxation_zone
+        # numerical wave tank of Sec. 3.2: pneumatic wavemaker p_g and damping
+        # pressure p_d (Eq. pd) acting on the surface.  wavemaker = dict(
+        #   comps=[(a_j, k_j, omega_j, theta_j), ...]  (p_g components; may be empty),
+        #   h=depth in the generator's factor (default h_ref),
+        #   x0=centre of the damping weight (None: no damping), width=its length (default 4 pi))
+        self.wm = wavemaker
         # seed of the iteration:
         #   "linear": the initiation of Sec. 2.4;
         #   "prev":   the linear guess plus the nonlinear part left by this
@@ -367,9 +379,50 @@ class Solver:
     # ------------------------------------------------------------------------
     # Prognostic step: Eq. (prognostic) in integrating-factor form
     # ------------------------------------------------------------------------
-    def rhs(self, eh, ph, tol):
+    # ------------------------------------------------------------------------
+    # Surface pressures of the numerical wave tank (Sec. 3.2)
+    # ------------------------------------------------------------------------
+    def _x_periodic(self, x0):
+        """x - x0 of every grid column, wrapped to [-lx/2, lx/2)."""
+        g = self.g
+        x = np.arange(g.nx) * (g.lx / g.nx)
+        return (x - x0 + g.lx / 2) % g.lx - g.lx / 2
+
+    def wavemaker_pressure(self, t):
+        """p_g(x, t) of the pneumatic wavemaker: bell-shaped components centred
+        on x = 0, i.e. split in halves over both ends of the periodic domain,
+        uniform in y."""
+        wm = self.wm
+        h = wm.get("h") or self.h
+        xs = self._x_periodic(0.0)
+        p = np.zeros(self.g.nx)
+        for a, k, om, th in wm.get("comps", ()):
+            kh2 = 2.0 * k * h
+            G = kh2 / math.sinh(kh2) if kh2 < 700.0 else 0.0
+            p += a * math.sqrt(math.e / (2 * math.pi)) * (1.0 + G) * np.exp(-0.5 * (k * xs) ** 2) * math.sin(om * t + th)
+        return np.broadcast_to(p[None, :], (self.g.ny, self.g.nx))
+
+    def damping_weight(self):
+        wm = self.wm
+        w = wm.get("width") or 4 * math.pi
+        mu = np.exp(-(self._x_periodic(wm["x0"]) / w) ** 2)
+        return np.broadcast_to(mu[None, :], (self.g.ny, self.g.nx))
+
+    def damping_pressure_hat(self, ph, mu):
+        """Spectrum of p_d = F^-1{ ik/(-k^2) . MF{mu grad phi} } (Eq. pd), with the
+        weighted gradient dealiased like every product and the k = 0 mode 0."""
+        g = self.g
+        px, py = g.grad(ph)
+        num = g.ikdot(g.MF(mu * px), None if py is None else g.MF(mu * py))
+        k2 = g.k ** 2
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(k2 > 0, num / np.where(k2 > 0, -k2, 1.0), 0.0)
+
+    def rhs(self, eh, ph, tol, t=0.0):
         """N = (V_hat - omega^2 phi_hat, MF{ (V + grad eta.grad phi)^2/(2(1+|grad eta|^2))
-        - |grad phi|^2/2 })  for masked state spectra (eh, ph)."""
+        - |grad phi|^2/2 - p_g } - p_d_hat)  for masked state spectra (eh, ph) at time t;
+        the surface pressure p = p_g + p_d of the wave tank (zero without it)
+        enters the dynamic condition beside the elevation."""
         g = self.g
         eta = g.ifft(eh)
         Vh, info = self.solve_hat(eta, ph, tol)
@@ -387,7 +440,14 @@ class Solver:
             q = V + ex * px + ey * py
             pp = px * px + py * py
         nphi = 0.5 * (q * q / (1.0 + gg) - pp)
-        return Vh - self.om2 * ph, g.MF(nphi), Vh, info
+        Nphi = None
+        if self.wm is not None:
+            nphi = nphi - self.wavemaker_pressure(t)
+            if self.wm.get("x0") is not None:
+                Nphi = g.MF(nphi) - self.damping_pressure_hat(ph, self.damping_weight())
+        if Nphi is None:
+            Nphi = g.MF(nphi)
+        return Vh - self.om2 * ph, Nphi, Vh, info
 
     def propagate(self, a, b, tau):
         """E(tau) applied to the pair (a, b): exact linear propagator."""
@@ -398,21 +458,21 @@ class Solver:
             sw = np.where(om > 0, s / np.where(om > 0, om, 1.0), tau)
         return c * a + om * s * b, -sw * a + c * b
 
-    def step_hat(self, eh, ph, dt, tol, stats=None):
-        """One Lawson IF-RK4 step on masked spectra."""
+    def step_hat(self, eh, ph, dt, tol, stats=None, t=0.0):
+        """One Lawson IF-RK4 step on masked spectra from time t."""
         h = dt
-        a = self.rhs(eh, ph, tol)
+        a = self.rhs(eh, ph, tol, t)
         if stats is not None:
             stats.append(a[3])
         u2 = self.propagate(eh + h / 2 * a[0], ph + h / 2 * a[1], h / 2)
-        b = self.rhs(*u2, tol)
+        b = self.rhs(*u2, tol, t + h / 2)
         eh_h, ph_h = self.propagate(eh, ph, h / 2)
         u3 = (eh_h + h / 2 * b[0], ph_h + h / 2 * b[1])
-        c = self.rhs(*u3, tol)
+        c = self.rhs(*u3, tol, t + h / 2)
         ec, pc = self.propagate(c[0], c[1], h / 2)
         eh_f, ph_f = self.propagate(eh, ph, h)
         u4 = (eh_f + h * ec, ph_f + h * pc)
-        d = self.rhs(*u4, tol)
+        d = self.rhs(*u4, tol, t + h)
         if stats is not None:
             stats.extend([b[3], c[3], d[3]])
         ea, pa = self.propagate(a[0], a[1], h)
@@ -473,7 +533,7 @@ class Solver:
         stats = []
         t = t0
         for _ in range(n):
-            eh, ph = self.step_hat(eh, ph, dt, tol, stats)
+            eh, ph = self.step_hat(eh, ph, dt, tol, stats, t)
             t += dt
             if self.rz is not None:
                 eh, ph = self.apply_relaxation(eh, ph, t)
@@ -492,13 +552,13 @@ class Solver:
         dp = g.ifft(self.om2 * ph)
         return float(np.sum(e * e) + np.sum(p * dp))
 
-    def step_rk54_hat(self, eh, ph, dt, tol, stats=None):
+    def step_rk54_hat(self, eh, ph, dt, tol, stats=None, t=0.0):
         """One step of the embedded pair on masked spectra.  Returns the
         fifth-order state (masked, then filtered when the filter is on) and
         the relative difference sqrt(E(u5 - u4) / E(u5)) of the unfiltered
         solutions in the linear-energy norm (0 when both vanish)."""
-        def f(u):
-            r = self.rhs(u[0], u[1], tol)
+        def f(u, tau):
+            r = self.rhs(u[0], u[1], tol, t + tau)
             if stats is not None:
                 stats.append(r[3])
             return (r[0], r[1])
@@ -538,7 +598,7 @@ class Solver:
                 break
             final = t_end - t <= h * (1.0 + 1e-9)
             hs = t_end - t if final else h
-            en, pn, err = self.step_rk54_hat(eh, ph, hs, tol)
+            en, pn, err = self.step_rk54_hat(eh, ph, hs, tol, t=t)
             fmax = 1.0 if last_rejected else FAC_MAX
             if not math.isfinite(err):
                 fac = FAC_MIN
@@ -603,10 +663,10 @@ CK_B4 = (2825 / 27648, 0.0, 18575 / 48384, 13525 / 55296, 277 / 14336, 1 / 4)
 
 def lawson_rk54(u, h, f, E):
     """One step of the pair in integrating-factor (Lawson) form for
-    u' = L u + f(u), with E(x, tau) = exp(L tau) x (Sec. 2.2's integrating
-    factor): in v = E(u, -(t - t_n)) the pair is applied to
+    u' = L u + f(u, t - t_n), with E(x, tau) = exp(L tau) x (Sec. 2.2's
+    integrating factor): in v = E(u, -(t - t_n)) the pair is applied to
     v' = E(f(E(v, t - t_n)), -(t - t_n)), which written back in u reads
-        U_i = E(u, c_i h) + h sum_j a_ij E(N_j, (c_i - c_j) h),  N_i = f(U_i)
+        U_i = E(u, c_i h) + h sum_j a_ij E(N_j, (c_i - c_j) h),  N_i = f(U_i, c_i h)
         u_q = E(u, h)     + h sum_j b_j  E(N_j, (1 - c_j) h)     (q = 5, 4).
     u and the values of f and E are tuples of arrays.  Returns (u5, u4)."""
     def axpy(acc, a, x):
@@ -618,7 +678,7 @@ def lawson_rk54(u, h, f, E):
         for j, a in enumerate(CK_A[i]):
             if a != 0.0:
                 U = axpy(U, h * a, E(N[j], (CK_C[i] - CK_C[j]) * h))
-        N.append(f(U))
+        N.append(f(U, CK_C[i] * h))
     out = []
     for b in (CK_B5, CK_B4):
         v = E(u, h)

@@ -99,7 +99,7 @@ def _bernoulli(t):
 def _run(n, which, T=2.0):
     h = T / n
     y = (np.array([Y0], dtype=complex),)
-    f = lambda u: (BETA * u[0] * u[0],)
+    f = lambda u, tau: (BETA * u[0] * u[0],)
     E = lambda u, tau: (np.exp(ALPHA * tau) * u[0],)
     for _ in range(n):
         y5, y4 = lawson_rk54(y, h, f, E)
@@ -116,7 +116,7 @@ def test_lawson_pair_converges_at_orders_five_and_four():
 
 def test_lawson_pair_is_exact_without_nonlinear_term():
     y = (np.array([Y0], dtype=complex),)
-    f = lambda u: (0.0 * u[0],)
+    f = lambda u, tau: (0.0 * u[0],)
     E = lambda u, tau: (np.exp(ALPHA * tau) * u[0],)
     y5, y4 = lawson_rk54(y, 0.9, f, E)
     assert y5[0][0] == y4[0][0] == np.exp(ALPHA * 0.9) * Y0
@@ -124,7 +124,7 @@ def test_lawson_pair_is_exact_without_nonlinear_term():
 
 def test_local_error_estimate_scales_as_h5():
     y = (np.array([Y0], dtype=complex),)
-    f = lambda u: (BETA * u[0] * u[0],)
+    f = lambda u, tau: (BETA * u[0] * u[0],)
     E = lambda u, tau: (np.exp(ALPHA * tau) * u[0],)
     d = []
     for h in (0.2, 0.1):
