@@ -221,6 +221,31 @@ sbi_status sbi_diagnostics(sbi_ctx* ctx, const sbi_state* state, double tol,
  */
 sbi_status sbi_set_relaxation(sbi_ctx* ctx, const double* params, int32_t n);
 
+/*
+ * Numerical wave tank of Sec. 3.2: surface pressures p = p_g + p_d that enter
+ * the dynamic surface condition (phi_t = ... - eta - p) of every later step
+ * (sbi_step, sbi_step_adaptive) at each stage's time.
+ *   comps      host double [ncomp][4] = {a_j, k_j, omega_j, theta_j}, 0 <= ncomp
+ *              <= 8: the pneumatic wavemaker
+ *              p_g = sum_j a_j sqrt(e/(2 pi)) (1 + 2 k_j h/sinh(2 k_j h))
+ *                    exp(-(k_j x)^2/2) sin(omega_j t + theta_j),
+ *              a bell centred on x = 0, i.e. split in halves over both ends of
+ *              the periodic domain, uniform in y; to linear order it radiates
+ *              waves of amplitude a_j both ways (k_j > 0; omega_j >= 0, usually
+ *              sqrt(k_j tanh(k_j h))).
+ *   h_gen      the depth h of the generator's factor; <= 0: each member's h_ref.
+ *   damp_x0,   the damping pressure of Eq. (pd),
+ *   damp_width   p_d = F^-1{ i k/(-k^2) . MF{mu grad phi_s} } (k = 0 mode: 0),
+ *              mu = exp(-((x - damp_x0)/damp_width)^2) with x - damp_x0 taken
+ *              periodically; the paper uses damp_width = 4 pi and damp_x0 =
+ *              7/8 of the domain; damp_width <= 0 turns the damping off.
+ * ncomp = 0 with damp_width <= 0 removes the tank's pressures.  Settings are
+ * copied; errors (SBI_ERR_INVALID_ARG: ncomp out of range, non-finite values,
+ * k_j <= 0, omega_j < 0) leave the previous ones in place.
+ */
+sbi_status sbi_set_wavemaker(sbi_ctx* ctx, const double* comps, int32_t ncomp, double h_gen, double damp_x0,
+                             double damp_width);
+
 /* Replace the depth (host [batch][ny][nx]) and reference depth of a context. */
 sbi_status sbi_set_depth(sbi_ctx* ctx, const double* depth, double h_ref);
 

@@ -194,6 +194,18 @@ class Solver:
         if st < 0:
             raise SBIError(st, "sbi_set_relaxation")
 
+    def set_wavemaker(self, comps=(), x0=None, width=4 * np.pi, h=None):
+        """Wave-tank pressures: comps = [(a_j, k_j, omega_j, theta_j), ...] of the
+        pneumatic wavemaker; damping centred at x0 with the given width (x0 None:
+        no damping); h: depth of the generator's factor (None: h_ref)."""
+        flat = [float(v) for c in comps for v in c]
+        arr = (C.c_double * max(len(flat), 1))(*flat)
+        st = self.lib.sbi_set_wavemaker(self.ctx, arr, len(flat) // 4, float(h or 0.0),
+                                        float(x0 if x0 is not None else 0.0),
+                                        float(width) if x0 is not None else 0.0)
+        if st < 0:
+            raise SBIError(st, "sbi_set_wavemaker")
+
     def last_stats(self):
         out = (C.c_double * 3)()
         n = self.lib.sbi_last_stats(self.ctx, out, 3)

@@ -71,6 +71,8 @@ SIGNATURES = {
     "sbi_diagnostics": (C.c_int, [C.c_void_p, C.POINTER(sbi_state), C.c_double, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double)]),
     "sbi_set_relaxation": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32]),
+    "sbi_set_wavemaker": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_double, C.c_double,
+                                    C.c_double]),
     "sbi_set_depth": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_double]),
     "sbi_net_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "sbi_destroy": (C.c_int, [C.c_void_p]),

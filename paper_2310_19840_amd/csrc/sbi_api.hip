@@ -42,6 +42,7 @@ enum {
     C_VP,                // T(V_n): candidate answer of the iteration
     C_NP,                // nonlinear term of the potential equation
     C_DV, C_DB,          // nonlinear part (V* - kT phi, phi_b - S phi) of the last solve
+    C_PD,                // i k . MF{mu grad phi} of the wave tank's damping pressure
     C_KE0,               // stage derivatives of the adaptive pair: eta part K_0..K_5
     C_KP0 = C_KE0 + 6,   //   potential part
     C_COUNT = C_KP0 + 6
@@ -122,6 +123,11 @@ struct sbi_ctx {
     float* feat = nullptr;     // feature field [batch][ny][nx][8] (SBI_SEED_NET)
     int fallbacks = 0;         // solves of the current call restarted from the linear guess
     double rz[6] = {0, 0, 0, 0, 0, 0};
+    // wave tank (Sec. 3.2): pneumatic wavemaker components and damping pressure
+    int wm_n = 0;
+    double wm[kMaxWavemaker][4] = {};
+    double wm_h = 0.0;
+    double dmp_x0 = 0.0, dmp_w = 0.0;  // dmp_w <= 0: no damping
     Stats st;
     Profiler prof;
     Ctl* head = nullptr;     // pinned host copy of the control headers
@@ -473,6 +479,24 @@ extern "C" sbi_status sbi_set_relaxation(sbi_ctx* c, const double* params, int32
     }
     if (!(c->rz[2] > 0 && c->rz[3] > 0 && c->rz[4] > 0 && c->rz[5] > 0)) return SBI_ERR_INVALID_ARG;
     c->relax_on = true;
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_set_wavemaker(sbi_ctx* c, const double* comps, int32_t ncomp, double h_gen,
+                                        double damp_x0, double damp_width) {
+    if (!c || ncomp < 0 || ncomp > kMaxWavemaker || (ncomp > 0 && !comps)) return SBI_ERR_INVALID_ARG;
+    if (!std::isfinite(h_gen) || !std::isfinite(damp_x0) || !std::isfinite(damp_width)) return SBI_ERR_INVALID_ARG;
+    for (int j = 0; j < ncomp; ++j) {
+        for (int e = 0; e < 4; ++e)
+            if (!std::isfinite(comps[4 * j + e])) return SBI_ERR_INVALID_ARG;
+        if (!(comps[4 * j + 1] > 0.0) || comps[4 * j + 2] < 0.0) return SBI_ERR_INVALID_ARG;
+    }
+    c->wm_n = ncomp;
+    for (int j = 0; j < ncomp; ++j)
+        for (int e = 0; e < 4; ++e) c->wm[j][e] = comps[4 * j + e];
+    c->wm_h = h_gen;
+    c->dmp_x0 = damp_x0;
+    c->dmp_w = damp_width > 0.0 ? damp_width : 0.0;
     return SBI_OK;
 }
 
@@ -1218,9 +1242,11 @@ extern "C" sbi_status sbi_vertical_velocity(sbi_ctx* c, const void* eta, const v
     return st != SBI_OK ? st : warn;
 }
 
-// nonlinear term of the potential equation at the stage state -> C_NP
-static sbi_status nonlinear_term(sbi_ctx* c) {
+// nonlinear term of the potential equation at the stage state and time t -> C_NP
+// (with the wave tank's wavemaker pressure; its damping pressure -> C_PD)
+static sbi_status nonlinear_term(sbi_ctx* c, double t) {
     const bool iter = c->grid.mode == SBI_MODE_ITER;
+    const bool damp = c->dmp_w > 0.0;
     RowNphiParams np{};
     np.g = c->gd;
     np.gV = HALF(H_GV);
@@ -1231,6 +1257,14 @@ static sbi_status nonlinear_term(sbi_ctx* c) {
     np.gpy = HALF(H_PY);
     np.h = HALF(H_PROD0);
     np.ctl = c->ctl;
+    np.wm_n = c->wm_n;
+    std::memcpy(np.wm, c->wm, sizeof(np.wm));
+    np.wm_h = c->wm_h;
+    np.t = t;
+    np.dmp_x0 = c->dmp_x0;
+    np.dmp_w = damp ? c->dmp_w : 0.0;
+    np.hdx = damp ? HALF(H_PROD0 + 1) : nullptr;
+    np.hdy = damp && c->grid.ny > 1 ? HALF(H_PROD0 + 2) : nullptr;
     c->st.launches += 1;
     {
         ProfScope ps_(c, K_ROW_NPHI);
@@ -1240,12 +1274,23 @@ static sbi_status nonlinear_term(sbi_ctx* c) {
     int s = b.prod(HALF(H_PROD0));
     b.term(s, 0, 1.0, FN_ONE, 0, DV_NONE);
     b.cout(SRC_ACC0, CMP(C_NP));
+    if (damp) {
+        // divergence i k . MF{mu grad phi}; the stage kernels divide it by k^2
+        int sx = b.prod(HALF(H_PROD0 + 1));
+        b.term(sx, 1, 1.0, FN_ONE, 0, DV_X);
+        if (c->grid.ny > 1) {
+            int sy = b.prod(HALF(H_PROD0 + 2));
+            b.term(sy, 1, 1.0, FN_ONE, 0, DV_Y);
+        }
+        b.cout(SRC_ACC1, CMP(C_PD));
+    }
     return run_col(c, b);
 }
 
-// nonlinear term and RK stage update after a solve
-static sbi_status stage_update(sbi_ctx* c, int stage, double dt, int vh_buf) {
-    SBI_TRY(nonlinear_term(c));
+// nonlinear term and RK stage update after a solve; t: time at the start of the step
+static sbi_status stage_update(sbi_ctx* c, int stage, double dt, int vh_buf, double t) {
+    static const double kStageNode[4] = {0.0, 0.5, 0.5, 1.0};
+    SBI_TRY(nonlinear_term(c, t + kStageNode[stage] * dt));
     RkParams rp{};
     rp.g = c->gd;
     rp.stage = stage;
@@ -1256,6 +1301,7 @@ static sbi_status stage_update(sbi_ctx* c, int stage, double dt, int vh_buf) {
     rp.ps = CMP(C_PS);
     rp.Vh = CMP(vh_buf);
     rp.Nph = CMP(C_NP);
+    rp.Pdiv = c->dmp_w > 0.0 ? CMP(C_PD) : nullptr;
     rp.ae = CMP(C_AE);
     rp.ap = CMP(C_AP);
     rp.fb1 = c->grid.filter_beta1;
@@ -1363,7 +1409,7 @@ extern "C" sbi_status sbi_step(sbi_ctx* c, sbi_state* state, double dt, int32_t 
             } else {
                 si.solves += c->batch;
             }
-            SBI_TRY(stage_update(c, stage, dt, vh));
+            SBI_TRY(stage_update(c, stage, dt, vh, t));
         }
         t += dt;
         if (c->relax_on) SBI_TRY(relax_zone(c, t));
@@ -1383,11 +1429,14 @@ extern "C" sbi_status sbi_step(sbi_ctx* c, sbi_state* state, double dt, int32_t 
     return worst;
 }
 
-// stage `stage` of the embedded pair after its solve; the last stage leaves
-// the fifth-order candidate in (C_ES, C_PS) and returns the largest relative
-// difference of the two solutions over the members in *err
-static sbi_status pair_stage(sbi_ctx* c, int stage, double h, int vh_buf, double* err) {
-    SBI_TRY(nonlinear_term(c));
+// stage `stage` of the embedded pair after its solve (t: time at the start of
+// the step); the last stage leaves the fifth-order candidate in (C_ES, C_PS)
+// and returns the largest relative difference of the two solutions over the
+// members in *err
+static sbi_status pair_stage(sbi_ctx* c, int stage, double h, int vh_buf, double t, double* err) {
+    // nodes of the Cash-Karp pair (the stage kernel holds the whole table)
+    static const double kPairNode[6] = {0.0, 1.0 / 5.0, 3.0 / 10.0, 3.0 / 5.0, 1.0, 7.0 / 8.0};
+    SBI_TRY(nonlinear_term(c, t + kPairNode[stage] * h));
     Rk54Params rp{};
     rp.g = c->gd;
     rp.stage = stage;
@@ -1398,6 +1447,7 @@ static sbi_status pair_stage(sbi_ctx* c, int stage, double h, int vh_buf, double
     rp.ps = CMP(C_PS);
     rp.Vh = CMP(vh_buf);
     rp.Nph = CMP(C_NP);
+    rp.Pdiv = c->dmp_w > 0.0 ? CMP(C_PD) : nullptr;
     for (int j = 0; j < 6; ++j) {
         rp.ke[j] = CMP(C_KE0 + j);
         rp.kp[j] = CMP(C_KP0 + j);
@@ -1477,7 +1527,7 @@ extern "C" sbi_status sbi_step_adaptive(sbi_ctx* c, sbi_state* state, double t_e
             } else {
                 ai.solve.solves += c->batch;
             }
-            SBI_TRY(pair_stage(c, stage, hs, vh, &err));
+            SBI_TRY(pair_stage(c, stage, hs, vh, t, &err));
         }
         const double fmax = last_rejected ? 1.0 : kFacMax;
         double fac;
@@ -1888,7 +1938,7 @@ static sbi_status batch_enqueue(sbi_batch* b, sbi_state* states, double dt, int 
             for (int stage = 0; stage < 4; ++stage) {
                 int vh = 0;
                 SBI_TRY(solve_stage(c, nullptr, tol, true, &vh, nullptr, true));
-                SBI_TRY(stage_update(c, stage, dt, vh));
+                SBI_TRY(stage_update(c, stage, dt, vh, t));
             }
             t += dt;
             if (c->relax_on) SBI_TRY(relax_zone(c, t));

@@ -549,9 +549,11 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_sa(const RowSaParams 
     }
 }
 
-template <typename R, int NX>
-__global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi(const RowNphiParams p, const typename cplx_of<R>::type* twN_tab,
-                           const typename cplx_of<R>::type* twX_tab) {
+// nonlinear term of the potential equation; TANK adds the wave tank's surface
+// pressures (a separate instance, so that the plain one keeps its registers)
+template <typename R, int NX, bool TANK>
+__device__ __forceinline__ void row_nphi_body(const RowNphiParams& p, const typename cplx_of<R>::type* twN_tab,
+                                              const typename cplx_of<R>::type* twX_tab) {
     ROW_PROLOGUE(R, NX)
     V q[E], gg[E], pp[E], a[E], b[E];
     const V* gD = p.gD ? static_cast<const V*>(p.gD) + hb : nullptr;
@@ -559,6 +561,25 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi(const RowNphiPar
     RW::inverse(q, static_cast<const V*>(p.gV) + hb, gD, c2, rc, lds_all, twN, twX, iscale);
     RW::inverse(a, static_cast<const V*>(p.gex) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
     RW::inverse(b, static_cast<const V*>(p.gpx) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+    const double dx = p.g.lx / p.g.nx;
+    // damping weight mu(x) of the wave tank times a potential gradient -> forward half form
+    auto damped = [&](const V (&grad)[E], void* out) {
+        V m[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const int n = ri.j + k * RW::P;
+            double mv[2];
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const double d = fmod((2 * n + hh) * dx - p.dmp_x0 + 1.5 * p.g.lx, p.g.lx) - 0.5 * p.g.lx;
+                mv[hh] = exp(-(d / p.dmp_w) * (d / p.dmp_w));
+            }
+            m[k] = cx<V>(R(mv[0] * (double)grad[k].x), R(mv[1] * (double)grad[k].y));
+        }
+        RW::forward(m, static_cast<V*>(out) + hb, rc, lds_all, twN, twX);
+    };
+    if constexpr (TANK)
+        if (p.dmp_w > 0.0) damped(b, p.hdx);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         q[k] = cx<V>(q[k].x + a[k].x * b[k].x, q[k].y + a[k].y * b[k].y);
@@ -568,6 +589,8 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi(const RowNphiPar
     if (p.g.ny > 1) {
         RW::inverse(a, static_cast<const V*>(p.gey) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
         RW::inverse(b, static_cast<const V*>(p.gpy) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+        if constexpr (TANK)
+            if (p.dmp_w > 0.0) damped(b, p.hdy);
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             q[k] = cx<V>(q[k].x + a[k].x * b[k].x, q[k].y + a[k].y * b[k].y);
@@ -580,7 +603,54 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi(const RowNphiPar
         q[k] = cx<V>(R(0.5) * (q[k].x * q[k].x / (R(1) + gg[k].x) - pp[k].x),
                      R(0.5) * (q[k].y * q[k].y / (R(1) + gg[k].y) - pp[k].y));
     }
+    if (TANK && p.wm_n > 0) {
+        // pneumatic wavemaker: bell-shaped pressures centred on x = 0, i.e. split
+        // over both ends of the periodic domain; the prefactor
+        // a_j sqrt(e/(2 pi)) (1 + 2 k_j h / sinh(2 k_j h)) radiates waves of amplitude a_j
+        const double hg = p.wm_h > 0.0 ? p.wm_h : p.g.href[ri.mem];
+        double amp[kMaxWavemaker];
+#pragma unroll
+        for (int c = 0; c < kMaxWavemaker; ++c) {
+            amp[c] = 0.0;
+            if (c < p.wm_n) {
+                const double kh2 = 2.0 * p.wm[c][1] * hg;
+                const double G = kh2 < 700.0 ? kh2 / sinh(kh2) : 0.0;
+                amp[c] = p.wm[c][0] * sqrt(M_E / (2.0 * M_PI)) * (1.0 + G) * sin(p.wm[c][2] * p.t + p.wm[c][3]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const int n = ri.j + k * RW::P;
+            double pg[2] = {0.0, 0.0};
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const double x = (2 * n + hh) * dx;
+                const double xs = x < 0.5 * p.g.lx ? x : x - p.g.lx;
+#pragma unroll
+                for (int c = 0; c < kMaxWavemaker; ++c) {
+                    if (c < p.wm_n) {
+                        const double kx = p.wm[c][1] * xs;
+                        pg[hh] += amp[c] * exp(-0.5 * kx * kx);
+                    }
+                }
+            }
+            q[k] = cx<V>(R((double)q[k].x - pg[0]), R((double)q[k].y - pg[1]));
+        }
+    }
     RW::forward(q, static_cast<V*>(p.h) + hb, rc, lds_all, twN, twX);
+}
+
+template <typename R, int NX>
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi(const RowNphiParams p, const typename cplx_of<R>::type* twN_tab,
+                           const typename cplx_of<R>::type* twX_tab) {
+    row_nphi_body<R, NX, false>(p, twN_tab, twX_tab);
+}
+
+template <typename R, int NX>
+__global__ void __launch_bounds__(row_threads<NX>()) k_row_nphi_tank(const RowNphiParams p,
+                                                                     const typename cplx_of<R>::type* twN_tab,
+                                                                     const typename cplx_of<R>::type* twX_tab) {
+    row_nphi_body<R, NX, true>(p, twN_tab, twX_tab);
 }
 
 template <typename R, int NX>
@@ -1434,9 +1504,14 @@ __global__ void k_rk(const RkParams p) {
     const V vh = static_cast<const V*>(p.Vh)[o];
     const V nph = static_cast<const V*>(p.Nph)[o];
     const V psv = ps[o];
-    // derivative of the stage: (W_hat - omega^2 phi_hat, N_phi)
+    // derivative of the stage: (W_hat - omega^2 phi_hat, N_phi [- p_d_hat])
     const double de_r = (double)vh.x - om2 * (double)psv.x, de_i = (double)vh.y - om2 * (double)psv.y;
-    const double dp_r = (double)nph.x, dp_i = (double)nph.y;
+    double dp_r = (double)nph.x, dp_i = (double)nph.y;
+    if (p.Pdiv && m.k > 0.0) {
+        const V pd = static_cast<const V*>(p.Pdiv)[o];
+        dp_r += (double)pd.x / (m.k * m.k);
+        dp_i += (double)pd.y / (m.k * m.k);
+    }
     const double u_er = (double)eh[o].x, u_ei = (double)eh[o].y;
     const double u_pr = (double)ph[o].x, u_pi = (double)ph[o].y;
     auto prop = [&](double tau, double er, double ei, double pr, double pi_, double* oer, double* oei, double* opr,
@@ -1516,7 +1591,7 @@ static __constant__ double kPairE[6] = {37.0 / 378.0 - 2825.0 / 27648.0, 0.0,  2
 
 // One stage of the pair in Lawson form, per kept mode.  With E(tau) the exact
 // linear propagator (eta, phi) -> (cos eta + om sin phi, -sin/om eta + cos phi)
-// and N_i = (W - om^2 phi, N_phi) at stage state U_i, the stage derivative is
+// and N_i = (W - om^2 phi, N_phi [- p_d]) at stage state U_i, the stage derivative is
 // kept as K_i = E(-c_i h) N_i (carried back to t_n), so that
 //   U_{i+1} = E(c_{i+1} h) (u_n + h sum_j a_{i+1,j} K_j),
 //   u_5     = E(h) (u_n + h sum_j b_j K_j),   u_5 - u_4 = E(h) h sum_j e_j K_j.
@@ -1555,6 +1630,12 @@ __global__ void k_rk54(const Rk54Params p) {
         const V psv = static_cast<const V*>(p.ps)[o];
         double ker = (double)vh.x - om2 * (double)psv.x, kei = (double)vh.y - om2 * (double)psv.y;
         double kpr = (double)nph.x, kpi = (double)nph.y;
+        if (p.Pdiv && m.k > 0.0) {
+            // damping pressure of the wave tank: -p_d_hat = i k . MF{mu grad phi} / k^2
+            const V pd = static_cast<const V*>(p.Pdiv)[o];
+            kpr += (double)pd.x / (m.k * m.k);
+            kpi += (double)pd.y / (m.k * m.k);
+        }
         prop(-kPairC[i] * h, ker, kei, kpr, kpi);
         static_cast<V*>(p.ke[i])[o] = cx<V>(R(ker), R(kei));
         static_cast<V*>(p.kp[i])[o] = cx<V>(R(kpr), R(kpi));
@@ -1704,6 +1785,7 @@ SBI_ROW_LAUNCH(k_row_setup, RowSetupParams)
 SBI_ROW_LAUNCH(k_row_sweep, RowSweepParams)
 SBI_ROW_LAUNCH(k_row_sa, RowSaParams)
 SBI_ROW_LAUNCH(k_row_nphi, RowNphiParams)
+SBI_ROW_LAUNCH(k_row_nphi_tank, RowNphiParams)
 SBI_ROW_LAUNCH(k_row_blend, RowBlendParams)
 SBI_ROW_LAUNCH(k_row_feat, RowFeatParams)
 
@@ -1779,7 +1861,7 @@ template <> hipError_t launch_row_sa_t<Real>(const RowSaParams& p, int b, const 
     return k_row_sa_nx<Real>(p, b, tw, s);
 }
 template <> hipError_t launch_row_nphi_t<Real>(const RowNphiParams& p, int b, const Twiddles& tw, hipStream_t s) {
-    return k_row_nphi_nx<Real>(p, b, tw, s);
+    return (p.wm_n > 0 || p.dmp_w > 0.0) ? k_row_nphi_tank_nx<Real>(p, b, tw, s) : k_row_nphi_nx<Real>(p, b, tw, s);
 }
 template <> hipError_t launch_row_blend_t<Real>(const RowBlendParams& p, int b, const Twiddles& tw, hipStream_t s) {
     return k_row_blend_nx<Real>(p, b, tw, s);

@@ -74,6 +74,8 @@ struct RowSaParams {
     void* h[kMaxProd];
 };
 
+constexpr int kMaxWavemaker = 8;   // pneumatic wavemaker components
+
 struct RowNphiParams {
     GridDev g;
     const void* gV;
@@ -84,6 +86,14 @@ struct RowNphiParams {
     const void* gpy;
     void* h;
     Ctl* ctl;
+    // surface pressure of the wave tank (Sec. 3.2), subtracted in the dynamic condition
+    int wm_n;                       // wavemaker components (0: none)
+    double wm[kMaxWavemaker][4];    // a_j, k_j, omega_j, theta_j
+    double wm_h;                    // depth of the generator's factor (<= 0: the member's reference depth)
+    double t;                       // stage time
+    double dmp_x0, dmp_w;           // damping weight exp(-((x - x0)/w)^2) (periodic distance); w <= 0: none
+    void* hdx;                      // forward half forms of mu d_x phi, mu d_y phi (damping only)
+    void* hdy;
 };
 
 // features of the learned warm start (channel-last, FP32, scaled per channel):
@@ -121,6 +131,7 @@ struct RkParams {
     void* ps;
     const void* Vh;  // W spectrum at the stage state
     const void* Nph; // nonlinear term of the potential equation
+    const void* Pdiv;// optional: i k . MF{mu grad phi} of the damping pressure (added as Pdiv / k^2)
     void* ae;        // accumulator
     void* ap;
     double fb1, fb2; // filter
@@ -137,6 +148,7 @@ struct Rk54Params {
     void* ps;
     const void* Vh;  // W spectrum at the stage state
     const void* Nph; // nonlinear term of the potential equation at the stage state
+    const void* Pdiv;// optional: i k . MF{mu grad phi} of the damping pressure (added as Pdiv / k^2)
     void* ke[6];     // stage derivatives carried back to t_n (written at their stage, read after)
     void* kp[6];
     double fb1, fb2; // filter (applied to the candidate)
