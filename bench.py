@@ -15,7 +15,9 @@ realisations stepped in one captured HIP graph with the previous-solve seed
 plain step in FP32 (tolerance 1e-6, the FP32 floor), the adaptive
 fifth/fourth-order pair over four peak periods ("adaptive", at the error bound
 3e-7 that makes it at least as accurate as the fixed step; counted in
-fixed-step equivalents of T_p/64), the ragged C4
+fixed-step equivalents of T_p/64), the 1D submerged-bar tank driven by
+the pneumatic wavemaker and damping pressure ("c2-tank", beside relaxation
+zones), the ragged C4
 ensemble (96 members, SA mode, FP32) in one graph, and the 512^2 flat
 crossing sea in FP32 beside FP64 with the FP32 error (max |eta|, energy drift).
 
@@ -261,6 +263,43 @@ def run_adaptive(args, dev, rk_tol):
                 sweeps_mean=round(info["sweeps_total"] / max(info["solves"], 1), 2), sweeps_max=info["sweeps_max"])
 
 
+def run_c2_tank(args, dev):
+    """The 1D submerged-bar tank (N=4096, 160 h0, short-wave case), SA mode, FP64,
+    eager steps of T/64: waves made by the pneumatic wavemaker and absorbed by
+    the damping pressure (the tank of Sec. 3.2), beside the same tank driven by
+    relaxation zones."""
+    import numpy as np
+    import torch
+
+    from paper_2310_19840_amd import Solver
+    from sbi_inputs import config_c2
+
+    cfg = config_c2(case=2)
+    g = cfg["grid"]
+    rz = cfg["relax"]
+    out = {}
+    for kind in ("tank", "relaxation"):
+        s = Solver(g.nx, 1, g.lx, 1.0, cfg["depth"], h_ref=cfg["h_ref"], device=dev, mode="sa")
+        if kind == "tank":
+            s.set_wavemaker([(rz["a"], rz["k"], rz["omega"], 0.0)], x0=7 * g.lx / 8, width=4 * math.pi)
+        else:
+            s.set_relaxation(rz["a"], rz["k"], rz["omega"], rz["gen_len"], rz["abs_len"], rz["ramp_periods"])
+        eta = torch.zeros((1, 1, g.nx), dtype=torch.float64, device=dev)
+        phi = torch.zeros((1, 1, g.nx), dtype=torch.float64, device=dev)
+        s.step(eta, phi, cfg["dt"], args.c2_steps // 4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, _ = s.step(eta, phi, cfg["dt"], args.c2_steps, t=cfg["dt"] * (args.c2_steps // 4))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[kind] = dict(value=g.nx * args.c2_steps / el, ms_per_step=1e3 * el / args.c2_steps, status=st,
+                         max_eta=float(np.abs(eta.cpu().numpy()).max()))
+    r = dict(out["tank"])
+    r.update(points=g.nx, steps=args.c2_steps, relaxation_value=out["relaxation"]["value"],
+             relaxation_ms_per_step=out["relaxation"]["ms_per_step"])
+    return r
+
+
 def run_c4(args, dev):
     """The ragged ensemble (32 x 128^2 + 48 x 256^2 + 16 x 512^2), SA mode, FP32, one graph."""
     import torch
@@ -332,7 +371,9 @@ def main():
     ap.add_argument("--members", type=int, default=2, help="realisations of the batched forms")
     ap.add_argument("--c4-steps", type=int, default=4)
     ap.add_argument("--c3-steps", type=int, default=32)
-    ap.add_argument("--forms", default="plain,batched+prev,batched+learned,plain-fp32,adaptive,c4,c3-precision")
+    ap.add_argument("--c2-steps", type=int, default=256)
+    ap.add_argument("--forms",
+                    default="plain,batched+prev,batched+learned,plain-fp32,adaptive,c2-tank,c4,c3-precision")
     ap.add_argument("--adaptive-periods", type=float, default=4.0)
     ap.add_argument("--rk-tol", type=float, default=3e-7,
                     help="error bound of the adaptive form; at 3e-7 its global error over two periods of a "
@@ -371,6 +412,8 @@ def main():
         out_forms["plain-fp32"]["tol"] = 1e-6
     if "adaptive" in forms:
         out_forms["adaptive"] = run_adaptive(args, dev, args.rk_tol)
+    if "c2-tank" in forms:
+        out_forms["c2-tank"] = run_c2_tank(args, dev)
     if "c4" in forms:
         out_forms["c4"] = run_c4(args, dev)
     if "c3-precision" in forms:

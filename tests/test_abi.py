@@ -85,6 +85,7 @@ def test_null_arguments_rejected(lib):
     assert lib.sbi_vertical_velocity(None, None, None, None, 1e-8, None, None, None) == _lib.SBI_ERR_INVALID_ARG
     assert lib.sbi_step(None, None, 0.1, 1, 1e-8, None) == _lib.SBI_ERR_INVALID_ARG
     assert lib.sbi_step_adaptive(None, None, 1.0, 0.1, 1e-3, 1e-8, 10, None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_set_wavemaker(None, None, 0, 0.0, 0.0, 0.0) == _lib.SBI_ERR_INVALID_ARG
 
 
 def test_adapt_info_layout():
