@@ -12,6 +12,8 @@ Method for Modeling Highly Nonlinear Water Waves in Variable Depth"):
 * Sec. 3.3, Eq. (filter): the optional low-pass filter;
 * Sec. 3.2: the numerical wave tank's pneumatic wavemaker and damping
   pressure (Eq. (pd));
+* ``fenton``: exact steady (Stokes) waves in deep water by the stream-function
+  method, the reference of Sec. 4's accuracy study;
 * ``warmstart``: the learned warm start of the W iteration (features, network
   forward and backward, Adam), defined in that module's header.
 
@@ -27,4 +29,5 @@ from .sbi_oracle import (  # noqa: F401
     w_sa_appc,
 )
 from . import dft  # noqa: F401
+from . import fenton  # noqa: F401
 from . import warmstart  # noqa: F401

@@ -1,0 +1,80 @@
+"""The accuracy study of Sec. 4 against exact steady waves: the oracle's
+surface vertical velocity for Stokes waves computed by the stream-function
+method (oracle/fenton.py) on one wavelength of 64 points in deep water (16
+alias-free modes).  Steepness eps = kH/2; error = max|V - V_exact| / max|V_exact|.
+
+The paper prints, for this setting: at 7th order the error stays below 0.5%
+up to eps = 0.35; at eps = 0.35 the 4th order already meets 0.5%, and beyond
+5th order the error no longer decreases; errors fall quickly with steepness."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Grid, Solver
+from oracle.fenton import SteadyWave
+
+
+def _wave(eps):
+    w = SteadyWave(2 * eps)
+    x = np.arange(64) * 2 * math.pi / 64
+    eta, eta_x, phi, V = w.surface(x)
+    return w, eta, phi, V
+
+
+def _sa_errors(eps):
+    _, eta, phi, V = _wave(eps)
+    g = Grid(64, 1, 2 * math.pi)
+    errs = []
+    for L in range(1, 8):
+        s = Solver(g, np.full((1, 64), 60.0), order=L, mode="sa")
+        W, _ = s.vertical_velocity(eta[None], phi[None])
+        errs.append(float(np.abs(W[0] - V).max() / np.abs(V).max()))
+    return errs
+
+
+@pytest.mark.parametrize("eps", [0.2, 0.35])
+def test_steady_wave_satisfies_its_conditions_between_collocation_points(eps):
+    w = SteadyWave(2 * eps)
+    x = (np.arange(200) + 0.37) * math.pi / 100
+    eta, eta_x, _, V = w.surface(x)
+    j = np.arange(1, w.N + 1)
+    E = np.exp(np.outer(eta, j))
+    C, S = np.cos(np.outer(x, j)), np.sin(np.outer(x, j))
+    psi = -w.c * eta + (E * C) @ w.B
+    u = -w.c + (E * C) @ (j * w.B)
+    wv = (E * S) @ (j * w.B)
+    assert np.abs(psi - w.Q).max() < 1e-8                             # the surface is a streamline
+    assert np.abs(0.5 * (u * u + wv * wv) + eta - w.R).max() < 1e-8  # Bernoulli
+    assert np.abs(V + w.c * eta_x).max() < 1e-7                       # rigid translation
+    ct = w.surface([0.0, math.pi])[0]                                 # crest and trough
+    assert abs(ct[0] - ct[1] - 2 * eps) < 1e-10 and ct[0] > eta.max() and ct[1] < eta.min()
+
+
+def test_steady_wave_speed_small_amplitude():
+    # Stokes: c = 1 + (ka)^2/2 + O(eps^4), and ka = kH/2 + O(eps^3)
+    for eps in (0.02, 0.05):
+        w = SteadyWave(2 * eps)
+        assert abs(w.c - (1 + 0.5 * eps * eps)) < eps ** 4, (eps, w.c)
+
+
+def test_sa_orders_reproduce_the_accuracy_study():
+    e35 = _sa_errors(0.35)
+    assert e35[6] < 5e-3                      # 7th order below 0.5% at the largest steepness
+    assert e35[3] < 5e-3                      # converged to 0.5% by the 4th order
+    assert e35[1] > 1e-2 and e35[0] > e35[1]  # low orders are not
+    assert min(e35[5], e35[6]) > 0.5 * e35[4]  # no further gain beyond the 5th order
+    e10 = _sa_errors(0.1)
+    assert e10[6] < 1e-7 and all(e10[i + 1] < e10[i] for i in range(6))   # fast convergence when mild
+    assert e10[6] < e35[6] / 1000
+
+
+def test_iteration_converges_on_a_mild_steady_wave():
+    # the iteration's fixed point (the expansion summed over orders) matches the
+    # exact wave at eps = 0.1; on steep waves (eps >= 0.2) it needs strong
+    # under-relaxation and stalls, where the successive approximation does not
+    _, eta, phi, V = _wave(0.1)
+    s = Solver(Grid(64, 1, 2 * math.pi), np.full((1, 64), 60.0), mode="iter", max_sweeps=200)
+    W, info = s.vertical_velocity(eta[None], phi[None], tol=1e-12)
+    assert info.status == 0
+    assert np.abs(W[0] - V).max() / np.abs(V).max() < 1e-6
