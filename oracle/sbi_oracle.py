@@ -32,7 +32,10 @@ notes of the repository):
   prefactor yields waves of amplitude a_j); the bell of p_g is centred on
   x = 0 (split over both ends of the periodic domain), the damping weight
   exp(-((x - x0)/w)^2) uses the periodic distance, w = 4 pi by default, and
-  p_d's k = 0 mode is zero.
+  p_d's k = 0 mode is zero;
+* the Anderson-accelerated iteration (an option of the build, not the
+  paper's) mixes the relaxed sweep over the last two residual differences,
+  with the residual, stopping rules and fixed point of the relaxed sweeps.
 """
 from __future__ import annotations
 
@@ -115,7 +118,8 @@ class Solver:
 
     def __init__(self, grid: Grid, depth, h_ref: float | None = None, order: int = 7,
                  mode: str = "iter", max_sweeps: int = 64, relax: bool = True,
-                 filter_beta=None, relaxation_zone=None, seed: str = "linear", net=None, wavemaker=None):
+                 filter_beta=None, relaxation_zone=None, seed: str = "linear", net=None, wavemaker=None,
+                 accel: str | None = None, aa_depth: int = 2):
         self.g = grid
         depth = np.asarray(depth, dtype=np.float64).reshape(grid.ny, grid.nx)
         if np.any(~np.isfinite(depth)) or np.any(depth <= 0):
@@ -144,6 +148,12 @@ class Solver:
         #   h=depth in the generator's factor (default h_ref),
         #   x0=centre of the damping weight (None: no damping), width=its length (default 4 pi))
         self.wm = wavemaker
+        # acceleration of the iteration: None (relaxed sweeps) or "anderson"
+        # (Anderson mixing of the relaxed sweep over the last aa_depth differences)
+        if accel not in (None, "anderson"):
+            raise ValueError("accel must be None or 'anderson'")
+        self.accel = accel
+        self.aa_depth = int(aa_depth)
         # seed of the iteration:
         #   "linear": the initiation of Sec. 2.4;
         #   "prev":   the linear guess plus the nonlinear part left by this
@@ -327,6 +337,82 @@ class Solver:
         info.status = WARN_NOT_CONVERGED
         return Vn, Bh, info
 
+    def _wdot(self, a, b):
+        """Real inner product of two masked half spectra, each mode weighted
+        by the number of modes of the full spectrum it stands for (Parseval)."""
+        g = self.g
+        w = np.where(np.arange(a.shape[1])[None, :] == 0, 1.0, 2.0) * g.mask
+        return float(np.sum(w * (a.real * b.real + a.imag * b.imag)))
+
+    def _sweeps_anderson(self, eta, bV, bB, Vh, Bh, w, tol):
+        """Sweeps with Anderson mixing (type II, depth m = aa_depth) of the
+        relaxed sweep G(x) = x + w (T(x) - x), x = (V, phi_b) (phi_b only over
+        a variable bed): with f_i = T(x_i) - x_i and g_i = G(x_i) over the last
+        k <= m + 1 sweeps, gamma minimises |f_n - sum_i gamma_i (f_(i+1) - f_i)|
+        in the inner product of _wdot (normal equations, regularised by
+        1e-12 trace / k; gamma = 0 if they fail), and
+        x_(n+1) = g_n - sum_i gamma_i (g_(i+1) - g_i).
+        Same residual, stopping rules and returned values as _sweeps."""
+        g = self.g
+        info = SolveInfo()
+        info.omega = w
+        rmin = np.inf
+        use_b = not self.flat
+        F, G = [], []
+        Vn = Vh
+        for n in range(self.max_sweeps):
+            Vn, Bn = self.apply_T(eta, bV, bB, Vh, Bh)
+            Vnew = g.ifft(Vn)
+            dif = g.ifft(Vn - Vh)
+            num = float(np.max(np.abs(dif)))
+            den = float(np.max(np.abs(Vnew)))
+            if not (np.isfinite(num) and np.isfinite(den)):
+                info.status = ERR_NONFINITE
+                info.sweeps = n + 1
+                info.residual = float("nan")
+                return Vn, Bn, info
+            r = 0.0 if num == 0.0 else (num / den if den > 0 else np.inf)
+            info.history.append(r)
+            info.sweeps = n + 1
+            info.residual = r
+            # the next iterate (formed before the decision, as the device does)
+            f = (Vn - Vh, Bn - Bh)
+            F.append(f)
+            G.append((Vh + w * f[0], Bh + w * f[1]))
+            if len(F) > self.aa_depth + 1:
+                F.pop(0)
+                G.pop(0)
+            k = len(F) - 1
+            gam = np.zeros(k)
+            if k > 0:
+                dF = [(F[i + 1][0] - F[i][0], F[i + 1][1] - F[i][1]) for i in range(k)]
+
+                def dot(a, b):
+                    return self._wdot(a[0], b[0]) + (self._wdot(a[1], b[1]) if use_b else 0.0)
+
+                A = np.array([[dot(dF[i], dF[j]) for j in range(k)] for i in range(k)])
+                y = np.array([dot(dF[i], f) for i in range(k)])
+                tr = np.trace(A)
+                try:
+                    gam = np.linalg.solve(A + (1e-12 * tr / k) * np.eye(k), y)
+                    if not np.all(np.isfinite(gam)) or not tr > 0:
+                        gam = np.zeros(k)
+                except np.linalg.LinAlgError:
+                    gam = np.zeros(k)
+            Vx, Bx = G[-1]
+            for i in range(k):
+                Vx = Vx - gam[i] * (G[i + 1][0] - G[i][0])
+                Bx = Bx - gam[i] * (G[i + 1][1] - G[i][1])
+            if r <= tol:
+                return Vn, Bx, info
+            rmin = min(rmin, r)
+            if r > 1e6 or (n >= 3 and r > 10.0 * rmin):
+                info.status = ERR_DIVERGED
+                return Vn, Bn, info
+            Vh, Bh = Vx, Bx
+        info.status = WARN_NOT_CONVERGED
+        return Vn, Bh, info
+
     def w_iter_hat(self, eta, ph, tol, seed_hat=None, seed_b_hat=None):
         """Iteration on the summed operator from the solver's seed (see the
         constructor), or from the seed spectrum seed_hat of V (and the
@@ -350,10 +436,11 @@ class Solver:
             Bh = Blin + self._prev[1]
         else:
             Vh, Bh = Vlin, Blin
-        Vn, Bl, info = self._sweeps(eta, bV, bB, Vh, Bh, w, tol)
+        sweeps = self._sweeps_anderson if self.accel == "anderson" else self._sweeps
+        Vn, Bl, info = sweeps(eta, bV, bB, Vh, Bh, w, tol)
         if net and info.status < 0:
             # the linear guess is the fallback of the learned seed
-            Vn, Bl, info = self._sweeps(eta, bV, bB, Vlin, Blin, w, tol)
+            Vn, Bl, info = sweeps(eta, bV, bB, Vlin, Blin, w, tol)
             info.fallback = True
         # nonlinear part of this solve: the seed of the next one
         self._prev = (Vn - Vlin, Bl - Blin) if info.status >= 0 else None
