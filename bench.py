@@ -141,7 +141,7 @@ def dominant(prof, sweeps_total, solves, g, vd, csz, rsz):
                  "avg_launch_us": round(avg_s * 1e6, 2), "launches_working": working, "launches_total": cnt}
 
 
-def run_plain(args, dev, precision, tol):
+def run_plain(args, dev, precision, tol, accel=None):
     """One C5 member, linear-guess seed, eager steps.  The sweep kernels of the
     last timed step are bracketed by HIP events (each bracket idles the device
     for a few microseconds, so the other steps run without them)."""
@@ -154,7 +154,7 @@ def run_plain(args, dev, precision, tol):
     g = cfg["grid"]
     dtype = torch.float64 if precision == "fp64" else torch.float32
     s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="iter", precision=precision,
-               max_sweeps=args.max_sweeps)
+               max_sweeps=args.max_sweeps, accel=accel)
     eta = torch.tensor(cfg["eta"][None], dtype=dtype, device=dev)
     phi = torch.tensor(cfg["phi"][None], dtype=dtype, device=dev)
     dt = cfg["dt"]
@@ -410,6 +410,12 @@ def main():
                                                                           "sweeps_max", "max_residual", "status",
                                                                           "roofline")}
         out_forms["plain-fp32"]["tol"] = 1e-6
+    if "plain-anderson" in forms:
+        aa = run_plain(args, dev, "fp64", 1e-8, accel="anderson")
+        aa.pop("cfg")
+        out_forms["plain-anderson"] = {k: v for k, v in aa.items() if k in ("value", "ms_per_step", "sweeps_mean",
+                                                                             "sweeps_max", "max_residual", "status",
+                                                                             "roofline", "kernel_ms")}
     if "adaptive" in forms:
         out_forms["adaptive"] = run_adaptive(args, dev, args.rk_tol)
     if "c2-tank" in forms:

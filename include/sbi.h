@@ -65,6 +65,7 @@ typedef enum sbi_status {
 enum { SBI_FP64 = 0, SBI_FP32 = 1 };
 enum { SBI_MODE_ITER = 0, SBI_MODE_SA = 1 };
 enum { SBI_SEED_LINEAR = 0, SBI_SEED_PREV = 1, SBI_SEED_NET = 2, SBI_SEED_USER = 3 };
+enum { SBI_ACCEL_NONE = 0, SBI_ACCEL_ANDERSON = 1 };
 
 /* Grid and solver options.  Fill with sbi_grid_defaults() first. */
 typedef struct sbi_grid {
@@ -93,6 +94,12 @@ typedef struct sbi_grid {
                               expand (default); 0: plain sweeps */
     double filter_beta1;   /* low-pass filter of Eq. (filter) applied each step when */
     double filter_beta2;   /* both are > 0; default 0 (off) */
+    int32_t accel;         /* iteration mode: SBI_ACCEL_NONE (default) sweeps
+                              V <- V + w (T(V) - V); SBI_ACCEL_ANDERSON mixes these
+                              relaxed sweeps over the last two residual differences
+                              (Anderson mixing, least squares in the inner product
+                              of the real fields), same residual, stopping rules and
+                              fixed point, typically half the sweeps */
 } sbi_grid;
 
 /* A batch of surface states: eta and phi_s are device arrays [batch][ny][nx]. */

@@ -19,8 +19,11 @@ _SEED = {"linear": _lib.SBI_SEED_LINEAR, "prev": _lib.SBI_SEED_PREV, "net": _lib
          "user": _lib.SBI_SEED_USER}
 
 
+_ACCEL = {None: _lib.SBI_ACCEL_NONE, "none": _lib.SBI_ACCEL_NONE, "anderson": _lib.SBI_ACCEL_ANDERSON}
+
+
 def make_grid(nx, ny, lx, ly=1.0, order=7, dealias=0.5, precision="fp64", mode="iter", seed="linear",
-              max_sweeps=64, relax=True, filter_beta=None) -> _lib.sbi_grid:
+              max_sweeps=64, relax=True, filter_beta=None, accel=None) -> _lib.sbi_grid:
     lib = _lib.load()
     g = _lib.sbi_grid()
     lib.sbi_grid_defaults(C.byref(g))
@@ -30,6 +33,7 @@ def make_grid(nx, ny, lx, ly=1.0, order=7, dealias=0.5, precision="fp64", mode="
     g.max_sweeps, g.relax = int(max_sweeps), int(bool(relax))
     if filter_beta is not None:
         g.filter_beta1, g.filter_beta2 = float(filter_beta[0]), float(filter_beta[1])
+    g.accel = _ACCEL[accel]
     return g
 
 

@@ -24,6 +24,7 @@ SBI_PROFILE_OFF, SBI_PROFILE_ALL, SBI_PROFILE_SWEEPS = 0, 1, 2
 SBI_FP64, SBI_FP32 = 0, 1
 SBI_MODE_ITER, SBI_MODE_SA = 0, 1
 SBI_SEED_LINEAR, SBI_SEED_PREV, SBI_SEED_NET, SBI_SEED_USER = 0, 1, 2, 3
+SBI_ACCEL_NONE, SBI_ACCEL_ANDERSON = 0, 1
 
 
 class sbi_grid(C.Structure):
@@ -35,6 +36,7 @@ class sbi_grid(C.Structure):
         ("precision", C.c_int32), ("mode", C.c_int32), ("seed", C.c_int32),
         ("max_sweeps", C.c_int32), ("relax", C.c_int32),
         ("filter_beta1", C.c_double), ("filter_beta2", C.c_double),
+        ("accel", C.c_int32),
     ]
 
 

@@ -43,7 +43,12 @@ enum {
     C_NP,                // nonlinear term of the potential equation
     C_DV, C_DB,          // nonlinear part (V* - kT phi, phi_b - S phi) of the last solve
     C_PD,                // i k . MF{mu grad phi} of the wave tank's damping pressure
-    C_KE0,               // stage derivatives of the adaptive pair: eta part K_0..K_5
+    C_TB,                // T_phi_b(x_n) of the Anderson-mixed iteration
+    C_AFV0,              // residual history f_i (V part), kAASlots ring slots
+    C_AFB0 = C_AFV0 + kAASlots,  //   (phi_b part)
+    C_AGV0 = C_AFB0 + kAASlots,  // relaxed-sweep history g_i (V part)
+    C_AGB0 = C_AGV0 + kAASlots,  //   (phi_b part)
+    C_KE0 = C_AGB0 + kAASlots,  // stage derivatives of the adaptive pair: eta part K_0..K_5
     C_KP0 = C_KE0 + 6,   //   potential part
     C_COUNT = C_KP0 + 6
 };
@@ -51,6 +56,7 @@ enum {
 enum {
     H_ETA, H_EX, H_EY, H_PX, H_PY,  // state and its gradients
     H_GV, H_GD, H_GBX, H_GBY,       // iterate / order fields
+    H_GT,                           // T(V_n) of the Anderson-mixed iteration (residual denominator)
     H_PROD0,                        // products H_PROD0 .. H_PROD0 + kMaxProd - 1
     H_COUNT = H_PROD0 + kMaxProd
 };
@@ -62,6 +68,8 @@ enum {
     P_BY0 = P_BX0 + 7,
     P_COUNT = P_BY0 + 7
 };
+
+constexpr int kAABlocks = 256;  // workgroups per member of the Anderson inner products
 
 struct Stats {
     double launches = 0, syncs = 0, sweeps = 0;
@@ -107,6 +115,7 @@ struct sbi_ctx {
     double* href_dev = nullptr;
     Ctl* ctl = nullptr;
     double* diag_partial = nullptr;
+    double* aa_partial = nullptr;   // [batch][kAABlocks][kAASlots] inner-product partials
     void* part = nullptr;    // partial sums of grouped column passes
     int* cnt = nullptr;      // tile tickets of grouped column passes
     int col_C = 1;
@@ -186,6 +195,7 @@ static bool grid_valid(const sbi_grid* g) {
     if (g->mode != SBI_MODE_ITER && g->mode != SBI_MODE_SA) return false;
     if (g->max_sweeps < 1 || g->max_sweeps > 1000) return false;
     if (g->seed < SBI_SEED_LINEAR || g->seed > SBI_SEED_USER) return false;
+    if (g->accel != SBI_ACCEL_NONE && g->accel != SBI_ACCEL_ANDERSON) return false;
     return true;
 }
 
@@ -221,7 +231,7 @@ static Layout layout(const sbi_grid* g, int batch) {
     L.bytes_phys = al((size_t)L.s_phys * L.rsz * batch) * P_COUNT;
     L.bytes_tw = al((size_t)g->nx * L.csz) + al((size_t)(g->nx / 2) * L.csz) + al((size_t)g->ny * L.csz);
     L.bytes_misc = al(sizeof(double) * batch) + al(sizeof(Ctl) * batch) + al(sizeof(CtlSlots) * batch) +
-                   al(sizeof(double) * 2 * 64 * batch) +
+                   al(sizeof(double) * 2 * 64 * batch) + al(sizeof(double) * kAASlots * kAABlocks * batch) +
                    al((size_t)L.s_cmp * L.csz * batch * kMaxGroups * 4) + al(sizeof(int) * (size_t)kMaxTiles * batch);
     // learned warm start: packed weights, and the feature field when it seeds the iteration
     L.bytes_net = al(sizeof(NetPacked)) +
@@ -246,6 +256,7 @@ extern "C" void sbi_grid_defaults(sbi_grid* g) {
     g->relax = 1;
     g->filter_beta1 = 0.0;
     g->filter_beta2 = 0.0;
+    g->accel = SBI_ACCEL_NONE;
 }
 
 extern "C" size_t sbi_workspace_bytes(const sbi_grid* g, int32_t batch) {
@@ -385,6 +396,8 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
     p += al(sizeof(CtlSlots) * batch);
     c->diag_partial = reinterpret_cast<double*>(p);
     p += al(sizeof(double) * 2 * 64 * batch);
+    c->aa_partial = reinterpret_cast<double*>(p);
+    p += al(sizeof(double) * kAASlots * kAABlocks * batch);
     c->part = p;
     p += al((size_t)L.s_cmp * L.csz * batch * kMaxGroups * 4);
     c->cnt = reinterpret_cast<int*>(p);
@@ -784,14 +797,62 @@ static sbi_status col_forcing(sbi_ctx* c) {
     return run_col(c, b, K_COL_FORCING);
 }
 
+// Anderson mixing after the column pass of sweep n: residual and relaxed sweep
+// into the history ring with their inner products, the next iterate x_(n+1)
+// (compact), then the inverse column transforms of x_(n+1) (V, grad phi_b)
+// that the next row pass reads
+static sbi_status anderson_mix(sbi_ctx* c, int n) {
+    const bool two_d = c->grid.ny > 1;
+    const int s = n % kAASlots;
+    AaParams ap{};
+    ap.g = c->gd;
+    ap.ctl = c->ctl;
+    ap.sweep = n;
+    ap.vd = c->vd;
+    ap.xv = CMP(C_VN);
+    ap.xb = CMP(C_BN);
+    ap.tv = CMP(C_VP);
+    ap.tb = CMP(C_TB);
+    for (int i = 0; i < kAASlots; ++i) {
+        ap.fv[i] = CMP(C_AFV0 + i);
+        ap.fb[i] = CMP(C_AFB0 + i);
+        ap.gv[i] = CMP(C_AGV0 + i);
+        ap.gb[i] = CMP(C_AGB0 + i);
+    }
+    ap.partial = c->aa_partial;
+    ap.nblk = kAABlocks;
+    c->st.launches += 2;
+    {
+        ProfScope ps_(c, K_COL_OTHER);
+        SBI_TRY(hip_ok(launch_aa_dot(c->fp64, ap, c->batch, c->stream)));
+        SBI_TRY(hip_ok(launch_aa_mix(c->fp64, ap, c->batch, c->stream)));
+    }
+    (void)s;
+    ColBuilder b(c->gd);
+    const int sx = b.cin(CMP(C_VN));
+    b.term(sx, 0, 1.0, FN_ONE, 0, DV_NONE);
+    b.inv(SRC_ACC0, DV_NONE, HALF(H_GV));
+    if (c->vd) {
+        const int sb = b.cin(CMP(C_BN));
+        b.term(sb, 1, 1.0, FN_ONE, 0, DV_NONE);
+        b.inv(SRC_ACC1, DV_X, HALF(H_GBX));
+        if (two_d) b.inv(SRC_ACC1, DV_Y, HALF(H_GBY));
+    }
+    b.p.ctl = c->ctl;
+    b.p.ctl_mode = CTL_SKIP;
+    return run_col(c, b, K_COL_OTHER);
+}
+
 static sbi_status launch_sweep(sbi_ctx* c, const void* eta_phys, int n, double tol) {
     const bool two_d = c->grid.ny > 1;
     const int J = c->grid.order - 1;
     const int M = c->grid.max_sweeps;
+    const bool aa = c->grid.accel == SBI_ACCEL_ANDERSON;
     RowSweepParams rp{};
     rp.g = c->gd;
     rp.gV = HALF(H_GV);
     rp.gD = HALF(H_GD);
+    rp.gT = aa ? HALF(H_GT) : nullptr;
     rp.gbx = HALF(H_GBX);
     rp.gby = HALF(H_GBY);
     rp.eta = eta_phys;
@@ -852,16 +913,28 @@ static sbi_status launch_sweep(sbi_ctx* c, const void* eta_phys, int n, double t
             }
         }
     }
-    b.p.relax_prev[0] = -cvn - 1;  // resolved in build(): encoded as cin index
-    if (c->vd) b.p.relax_prev[1] = -cbn - 1;
-    b.cout(SRC_ACC0, CMP(C_VP));
-    b.cout(SRC_NEW0, CMP(C_VN));
-    if (c->vd) b.cout(SRC_NEW1, CMP(C_BN));
-    b.inv(SRC_NEW0, DV_NONE, HALF(H_GV));
-    b.inv(SRC_DIFF0, DV_NONE, HALF(H_GD));
-    if (c->vd) {
-        b.inv(SRC_NEW1, DV_X, HALF(H_GBX));
-        if (two_d) b.inv(SRC_NEW1, DV_Y, HALF(H_GBY));
+    if (aa) {
+        // T(x_n), and the half forms of the residual test (f_n and T(V_n));
+        // the next iterate follows once the inner products over the whole
+        // spectrum are known
+        (void)cbn;
+        b.p.relax_prev[0] = -cvn - 1;
+        b.cout(SRC_ACC0, CMP(C_VP));
+        if (c->vd) b.cout(SRC_ACC1, CMP(C_TB));
+        b.inv(SRC_DIFF0, DV_NONE, HALF(H_GD));
+        b.inv(SRC_ACC0, DV_NONE, HALF(H_GT));
+    } else {
+        b.p.relax_prev[0] = -cvn - 1;  // resolved in build(): encoded as cin index
+        if (c->vd) b.p.relax_prev[1] = -cbn - 1;
+        b.cout(SRC_ACC0, CMP(C_VP));
+        b.cout(SRC_NEW0, CMP(C_VN));
+        if (c->vd) b.cout(SRC_NEW1, CMP(C_BN));
+        b.inv(SRC_NEW0, DV_NONE, HALF(H_GV));
+        b.inv(SRC_DIFF0, DV_NONE, HALF(H_GD));
+        if (c->vd) {
+            b.inv(SRC_NEW1, DV_X, HALF(H_GBX));
+            if (two_d) b.inv(SRC_NEW1, DV_Y, HALF(H_GBY));
+        }
     }
     b.p.ctl = c->ctl;
     b.p.ctl_mode = CTL_SWEEP;
@@ -869,7 +942,9 @@ static sbi_status launch_sweep(sbi_ctx* c, const void* eta_phys, int n, double t
     b.p.max_sweeps = M;
     b.p.tol = tol;
     if (b.p.nacc < (c->vd ? 2 : 1)) b.p.nacc = c->vd ? 2 : 1;
-    return run_col(c, b, K_COL_SWEEP);
+    SBI_TRY(run_col(c, b, K_COL_SWEEP));
+    if (!aa || !rp.products) return SBI_OK;
+    return anderson_mix(c, n);
 }
 
 static sbi_status read_heads(sbi_ctx* c) {

@@ -37,6 +37,9 @@ struct CtlSlots {
     unsigned long long num[kMaxSweepSlots];  // bits of max|W'-W| (non-negative doubles)
     unsigned long long den[kMaxSweepSlots];  // bits of max|W'|
 };
+constexpr int kAADepth = 2;              // residual differences kept by the Anderson mixing
+constexpr int kAASlots = kAADepth + 1;   // history ring of residuals and relaxed sweeps
+
 struct Ctl {
     int done;                                // iteration finished (any reason)
     int status;                              // sbi_status of the solve
@@ -53,6 +56,8 @@ struct Ctl {
     long long acc_solves, acc_sweeps;
     int acc_sweeps_max, acc_worst;
     double acc_residual_max;
+    // Anderson mixing: inner products of the residual history (ring slots)
+    double aa_gram[kAASlots][kAASlots];
 };
 
 struct GridDev {
@@ -84,7 +89,7 @@ enum { DV_NONE = 0, DV_X = 1, DV_Y = 2 };
 enum { SRC_ACC0 = 0, SRC_ACC1 = 1, SRC_ACC2 = 2, SRC_ACC3 = 3, SRC_NEW0 = 4, SRC_NEW1 = 5,
        SRC_DIFF0 = 6, SRC_DIFF1 = 7 };
 // control modes of a column pass
-enum { CTL_NONE = 0, CTL_OMEGA = 1, CTL_SWEEP = 2 };
+enum { CTL_NONE = 0, CTL_OMEGA = 1, CTL_SWEEP = 2, CTL_SKIP = 3 };  // CTL_SKIP: return once the solve is decided
 
 struct ColParams {
     GridDev g;

@@ -40,6 +40,7 @@ struct RowSweepParams {
     GridDev g;
     const void* gV;     // half form of the current iterate V_n
     const void* gD;     // half form of D_(n-1) = T(V_(n-1)) - V_(n-1)
+    const void* gT;     // half form of T(V_(n-1)) (Anderson mixing; NULL: V_n + (1 - omega) D_(n-1))
     const void* gbx;    // half forms of grad phi_b,n (variable depth)
     const void* gby;
     const void* eta;    // physical
@@ -156,6 +157,26 @@ struct Rk54Params {
     int nblk;
 };
 
+// Anderson mixing of the relaxed sweep (iteration mode): residual and relaxed
+// sweep of sweep n into the history ring, inner products (k_aa_dot), then the
+// next iterate as a combination of the relaxed sweeps (k_aa_mix)
+struct AaParams {
+    GridDev g;
+    Ctl* ctl;
+    int sweep;                 // n
+    int vd;                    // phi_b is iterated too (variable bed)
+    void* xv;                  // x_n (k_aa_dot) / x_(n+1) (k_aa_mix): V and phi_b parts
+    void* xb;
+    const void* tv;            // T(x_n)
+    const void* tb;
+    void* fv[kAASlots];        // residual history f_i = T(x_i) - x_i
+    void* fb[kAASlots];
+    void* gv[kAASlots];        // relaxed-sweep history g_i = x_i + omega f_i
+    void* gb[kAASlots];
+    double* partial;           // [batch][nblk][kAASlots]
+    int nblk;
+};
+
 struct DiagParams {
     GridDev g;
     const void* eh;
@@ -186,6 +207,8 @@ template <typename R> hipError_t launch_row_feat_t(const RowFeatParams&, int, co
 template <typename R> hipError_t launch_col_t(const ColParams&, int, const Twiddles&, hipStream_t);
 template <typename R> hipError_t launch_rk_t(const RkParams&, int, hipStream_t);
 template <typename R> hipError_t launch_rk54_t(const Rk54Params&, int, hipStream_t);
+template <typename R> hipError_t launch_aa_dot_t(const AaParams&, int, hipStream_t);
+template <typename R> hipError_t launch_aa_mix_t(const AaParams&, int, hipStream_t);
 template <typename R> hipError_t launch_diag_t(const DiagParams&, int, hipStream_t);
 
 hipError_t launch_row_fwd(int fp64, const RowFwdParams& p, int batch, const Twiddles& tw, hipStream_t s);
@@ -199,6 +222,8 @@ hipError_t launch_row_feat(int fp64, const RowFeatParams& p, int batch, const Tw
 hipError_t launch_col(int fp64, const ColParams& p, int batch, const Twiddles& tw, hipStream_t s);
 hipError_t launch_rk(int fp64, const RkParams& p, int batch, hipStream_t s);
 hipError_t launch_rk54(int fp64, const Rk54Params& p, int batch, hipStream_t s);
+hipError_t launch_aa_dot(int fp64, const AaParams& p, int batch, hipStream_t s);
+hipError_t launch_aa_mix(int fp64, const AaParams& p, int batch, hipStream_t s);
 hipError_t launch_diag(int fp64, const DiagParams& p, int batch, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* ctl, int batch, int slots, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);

@@ -1,0 +1,151 @@
+"""Parity of the Anderson-mixed iteration (SBI_ACCEL_ANDERSON) with the
+oracle's (same mixing, residual and stopping rules): identical sweep counts,
+status and W to 1e-11 relative (FP64); steps to 1e-10."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import sbi_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _t(x, dtype, dev):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=dev)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+CASES = {
+    "c5 128 variable bed": lambda: si.config_c5(seed=1, n=128),
+    "c5 64x? variable bed": lambda: si.config_c5(seed=2, n=64),
+    "c3 128 flat": lambda: si.config_c3(n=128),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_anderson_w_matches_oracle(gpu, name):
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    cfg = CASES[name]()
+    g = cfg["grid"]
+    _say("anderson W", name)
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=gpu, mode="iter", max_sweeps=200, accel="anderson")
+    W, st, info = s.vertical_velocity(_t(cfg["eta"][None], torch.float64, gpu), _t(cfg["phi"][None], torch.float64, gpu),
+                                      tol=1e-11)
+    o = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), cfg["depth"], mode="iter", max_sweeps=200, accel="anderson")
+    Wo, oi = o.vertical_velocity(cfg["eta"], cfg["phi"], tol=1e-11)
+    r = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), cfg["depth"], mode="iter", max_sweeps=200)
+    _, ri = r.vertical_velocity(cfg["eta"], cfg["phi"], tol=1e-11)
+    _say("  sweeps gpu", info[0][0], "oracle", oi.sweeps, "relaxed sweeps", ri.sweeps)
+    assert st == 0 and info[0][1] == oi.status == 0
+    assert info[0][0] == oi.sweeps
+    assert oi.sweeps < ri.sweeps
+    assert _rel(W.cpu().numpy().reshape(Wo.shape), Wo) < 1e-11
+
+
+def test_anderson_1d_matches_oracle(gpu):
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    cfg = si.config_c1()
+    g = cfg["grid"]
+    _say("anderson 1D")
+    s = Solver(g.nx, 1, g.lx, 1.0, cfg["depth"], h_ref=cfg["h_ref"], device=gpu, mode="iter", max_sweeps=200,
+               accel="anderson")
+    W, st, info = s.vertical_velocity(_t(cfg["eta"], torch.float64, gpu), _t(cfg["phi"], torch.float64, gpu),
+                                      tol=1e-12)
+    o = OSolver(Grid(g.nx, 1, g.lx), cfg["depth"], h_ref=cfg["h_ref"], mode="iter", max_sweeps=200, accel="anderson")
+    Wo, oi = o.vertical_velocity(cfg["eta"], cfg["phi"], tol=1e-12)
+    assert info[0][0] == oi.sweeps and info[0][1] == oi.status
+    assert _rel(W.cpu().numpy().reshape(Wo.shape), Wo) < 1e-11
+
+
+def test_anderson_steps_match_oracle(gpu):
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    nx, ny = 64, 32
+    lx, ly = 8 * math.pi, 4 * math.pi
+    gs = si.GridSpec(nx, ny, lx, ly)
+    eta, phi = si.jonswap_crossing_sea(gs, 1.0, seed=5, hs_half=0.03)
+    X, Y = np.meshgrid(gs.x(), gs.y())
+    depth = 1.0 - 0.15 * np.exp(-((X - lx / 2) ** 2 + (Y - ly / 2) ** 2) / 20.0)
+    dt = 2 * math.pi / math.sqrt(math.tanh(1.0)) / 64
+    _say("anderson steps")
+    for seed in ("linear", "prev"):
+        s = Solver(nx, ny, lx, ly, depth, device=gpu, mode="iter", max_sweeps=200, accel="anderson", seed=seed)
+        e = _t(eta, torch.float64, gpu)
+        p = _t(phi, torch.float64, gpu)
+        st, info = s.step(e, p, dt, 3, tol=1e-11)
+        o = OSolver(Grid(nx, ny, lx, ly), depth, mode="iter", max_sweeps=200, accel="anderson", seed=seed)
+        eo, po, stats = o.step(eta, phi, dt, 3, tol=1e-11)
+        assert info["sweeps_total"] == sum(x.sweeps for x in stats), seed
+        assert _rel(e.cpu().numpy().reshape(eo.shape), eo) < 1e-10
+        assert _rel(p.cpu().numpy().reshape(po.shape), po) < 1e-10
+
+
+def test_anderson_batch_member_equals_single_run(gpu):
+    import torch
+    from paper_2310_19840_amd import Solver
+    cfgs = [si.config_c5(seed=sd, n=64) for sd in (4, 5)]
+    g = cfgs[0]["grid"]
+    _say("anderson batch")
+    depth = np.stack([c["depth"] for c in cfgs])
+    s2 = Solver(g.nx, g.ny, g.lx, g.ly, depth, batch=2, device=gpu, mode="iter", max_sweeps=200, accel="anderson")
+    e2 = _t(np.stack([c["eta"] for c in cfgs]), torch.float64, gpu)
+    p2 = _t(np.stack([c["phi"] for c in cfgs]), torch.float64, gpu)
+    W2, _, i2 = s2.vertical_velocity(e2, p2, tol=1e-10)
+    for b, c in enumerate(cfgs):
+        s1 = Solver(g.nx, g.ny, g.lx, g.ly, c["depth"], device=gpu, mode="iter", max_sweeps=200, accel="anderson")
+        W1, _, i1 = s1.vertical_velocity(_t(c["eta"][None], torch.float64, gpu), _t(c["phi"][None], torch.float64, gpu),
+                                         tol=1e-10)
+        assert i1[0][0] == i2[b][0]
+        assert torch.equal(W1[0], W2[b])
+
+
+def test_anderson_batch_graph_equals_eager(gpu):
+    import torch
+    from paper_2310_19840_amd import Batch
+    cfgs = [si.config_c5(seed=sd, n=n) for sd, n in ((6, 64), (7, 128), (8, 64))]
+    _say("anderson graph batch")
+    mem = [dict(nx=c["grid"].nx, ny=c["grid"].ny, lx=c["grid"].lx, ly=c["grid"].ly, depth=c["depth"],
+                precision="fp64", mode="iter", max_sweeps=64, accel="anderson") for c in cfgs]
+    outs = []
+    for graph in (False, True):
+        b = Batch(mem, device=gpu, graph=graph)
+        etas = [_t(c["eta"], torch.float64, gpu) for c in cfgs]
+        phis = [_t(c["phi"], torch.float64, gpu) for c in cfgs]
+        for _ in range(2):
+            b.step(etas, phis, cfgs[0]["dt"], 2, tol=1e-9)
+        outs.append([e.cpu().numpy() for e in etas])
+    for a, bb in zip(*outs):
+        assert np.array_equal(a, bb)
+
+
+def test_anderson_fp32_near_the_oracle_fixed_point(gpu):
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    cfg = si.config_c5(seed=1, n=128)
+    g = cfg["grid"]
+    _say("anderson fp32")
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=gpu, mode="iter", max_sweeps=200, accel="anderson",
+               precision="fp32")
+    W, st, info = s.vertical_velocity(_t(cfg["eta"][None], torch.float32, gpu), _t(cfg["phi"][None], torch.float32, gpu),
+                                      tol=1e-6)
+    o = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), cfg["depth"], mode="iter", max_sweeps=200)
+    Wo, _ = o.vertical_velocity(cfg["eta"], cfg["phi"], tol=1e-12)
+    assert st == 0
+    assert _rel(W.cpu().numpy().reshape(Wo.shape).astype(np.float64), Wo) < 1e-5

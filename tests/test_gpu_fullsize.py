@@ -267,3 +267,49 @@ def test_fullsize_adaptive_linear_waves_exact_and_sea_invariants(gpu):
     assert abs(m1[0] - m0[0]) <= 1e-12 * amp * g.lx * g.ly
     assert abs(e1[0] - e0[0]) <= 1e-5 * abs(e0[0])
     assert np.isfinite(eta.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("tol", [1e-8, 1e-11])
+def test_fullsize_anderson_w_is_an_oracle_fixed_point(gpu, tol):
+    # the Anderson-mixed iteration at 1024^2 stops at the fixed point of the
+    # same summed operator: the oracle's relaxed sweeps, seeded with the GPU's
+    # V and phi_b, stop within two sweeps and move W by <= 3 tol
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    cfg = _c5()
+    g = cfg["grid"]
+    _say("1024^2 anderson fixed point, tol", tol)
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=gpu, mode="iter", max_sweeps=200, seed="prev",
+               accel="anderson")
+    eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=gpu)
+    phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=gpu)
+    W, st, info = s.vertical_velocity(eta, phi, tol=tol)
+    assert st == 0 and info[0][0] > 5, info
+    dv, db = s.last_correction()
+    Wg = W.cpu().numpy().reshape(g.ny, g.nx)
+    dbg = db.cpu().numpy().reshape(g.ny, g.nx)
+    o = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), cfg["depth"], mode="iter", max_sweeps=4)
+    Wo, oi = o.vertical_velocity(cfg["eta"], cfg["phi"], tol=tol, seed=Wg, seed_b=dbg)
+    _say("gpu sweeps", info[0][0], "oracle sweeps from the gpu iterate", oi.sweeps, "residual", oi.residual)
+    assert oi.status == 0 and oi.sweeps <= 2
+    assert _rel(Wg, Wo) <= 3 * tol
+
+
+def test_fullsize_anderson_steps_equal_relaxed_steps(gpu):
+    # two RK4 steps at 1024^2 with either iteration agree to the solve tolerance
+    import torch
+    from paper_2310_19840_amd import Solver
+    cfg = _c5()
+    g = cfg["grid"]
+    _say("1024^2 anderson steps")
+    out = []
+    for accel in (None, "anderson"):
+        s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=gpu, mode="iter", max_sweeps=200, accel=accel)
+        eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=gpu)
+        phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=gpu)
+        st, info = s.step(eta, phi, cfg["dt"], 2, tol=1e-10)
+        assert st == 0
+        out.append((eta.cpu().numpy(), info["sweeps_total"]))
+    assert out[1][1] < 0.6 * out[0][1], (out[0][1], out[1][1])
+    assert _rel(out[1][0], out[0][0]) < 1e-8
