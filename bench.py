@@ -9,7 +9,10 @@ grid-point RK4 steps per second (points x steps / wall seconds), inputs
 resident in HBM before the timed region.
 
 `value` is the plain form (one realisation, linear-guess seed, eager launches;
-HIP events bracket the sweep kernels of the last timed step only).  `forms` adds, at the same tolerance, two
+HIP events bracket the sweep kernels of the last timed step only), whose W
+iteration mixes its relaxed sweeps by Anderson's method (same residual test
+and fixed point, about half the sweeps; `--accel none` and the
+"plain-relaxed" form give the relaxed sweeps alone).  `forms` adds, at the same tolerance, two
 realisations stepped in one captured HIP graph with the previous-solve seed
 ("batched+prev") and with the learned warm start ("batched+learned"), the
 plain step in FP32 (tolerance 1e-6, the FP32 floor), the adaptive
@@ -43,10 +46,12 @@ HBM_PEAK_GBS = 8000.0
 
 
 def algorithmic_bytes(kind: str, nx: int, ny: int, Kx: int, Ky: int, csz: int, rsz: int, vd: bool, J: int,
-                      two_d: bool) -> float:
+                      two_d: bool, aa: bool = False) -> float:
     """Minimum HBM bytes of one working launch of a sweep kernel (one member).
 
     half-form array: ny*Kx complex; compact array: Ky*Kx complex; physical: nx*ny real.
+    aa: the Anderson-mixed iteration, whose row pass also reads T(V_(n-1)) and
+    whose column pass writes T(x_n) and the residual's half forms only.
     """
     half = ny * Kx * csz
     comp = Ky * Kx * csz
@@ -54,12 +59,15 @@ def algorithmic_bytes(kind: str, nx: int, ny: int, Kx: int, Ky: int, csz: int, r
     ncomp = (2 if two_d else 1) if vd else 0
     nprod = J * (1 + ncomp)
     if kind == "row_sweep":
-        # read G_V, G_D (+ grad phi_b components) and eta (+ delta); write the products
-        return (2 + ncomp) * half + (1 + (1 if vd else 0)) * phys + nprod * half
+        # read G_V, G_D [, G_T] (+ grad phi_b components) and eta (+ delta); write the products
+        return (2 + (1 if aa else 0) + ncomp) * half + (1 + (1 if vd else 0)) * phys + nprod * half
     if kind == "col_sweep":
         # read the products and b_V, V_n (+ b_phi, phi_b,n); write G_V, G_D (+ grad phi_b)
         # and T(V_n), V_(n+1) (+ phi_b,(n+1))
         nin_c = 2 + (2 if vd else 0)
+        if aa:
+            # write T_V, T_phi_b (compact) and the half forms of f_n and T_V(x_n)
+            return nprod * half + nin_c * comp + 2 * half + (1 + (1 if vd else 0)) * comp
         nout_c = 2 + (1 if vd else 0)
         return nprod * half + nin_c * comp + (2 + ncomp) * half + nout_c * comp
     raise ValueError(kind)
@@ -119,7 +127,7 @@ def c5_members(seeds, n):
     return [config_c5(seed=sd, n=n) for sd in seeds]
 
 
-def dominant(prof, sweeps_total, solves, g, vd, csz, rsz):
+def dominant(prof, sweeps_total, solves, g, vd, csz, rsz, aa=False):
     """Dominant sweep kernel and its algorithmic bandwidth from the live profile."""
     Mx = int(math.ceil(0.5 * g.nx / 2 - 1e-9)) - 1
     My = int(math.ceil(0.5 * g.ny / 2 - 1e-9)) - 1
@@ -130,7 +138,7 @@ def dominant(prof, sweeps_total, solves, g, vd, csz, rsz):
         if tot_ms <= 0:
             continue
         working = sweeps_total + (solves if kind == "row_sweep" else 0)
-        b = algorithmic_bytes(kind, g.nx, g.ny, Kx, Ky, csz, rsz, vd, 6, g.ny > 1)
+        b = algorithmic_bytes(kind, g.nx, g.ny, Kx, Ky, csz, rsz, vd, 6, g.ny > 1, aa)
         avg_s = tot_ms * 1e-3 / max(working, 1)
         cand[kind] = (tot_ms, b, avg_s, cnt, working)
     dom = max(cand, key=lambda k: cand[k][0])
@@ -182,14 +190,14 @@ def run_plain(args, dev, precision, tol, accel=None):
     vd = bool(np.any(cfg["depth"] != cfg["depth"].max()))
     csz, rsz = (16, 8) if precision == "fp64" else (8, 4)
     # the profiled step's own launches decide which of them did work
-    dom, roof = dominant(prof, info1["sweeps_total"], max(info1["solves"], 1), g, vd, csz, rsz)
+    dom, roof = dominant(prof, info1["sweeps_total"], max(info1["solves"], 1), g, vd, csz, rsz, accel == "anderson")
     return dict(value=g.nx * g.ny * args.steps / el, ms_per_step=1e3 * el / max(args.steps, 1), status=st,
                 sweeps_mean=info["sweeps_total"] / solves, sweeps_max=info["sweeps_max"],
                 max_residual=info["max_residual"], roofline=roof, dominant=dom,
                 kernel_ms={k: round(v[0], 3) for k, v in prof.items() if v[1] > 0}, cfg=cfg)
 
 
-def run_batched(args, dev, seed_mode, members):
+def run_batched(args, dev, seed_mode, members, accel=None):
     """B C5 realisations in one captured graph, previous-solve or learned seed."""
     import torch
 
@@ -203,7 +211,8 @@ def run_batched(args, dev, seed_mode, members):
             return dict(skipped=f"no trained weights at {os.path.relpath(path, ROOT)}")
         blob = open(path, "rb").read()
     mem = [dict(nx=c["grid"].nx, ny=c["grid"].ny, lx=c["grid"].lx, ly=c["grid"].ly, depth=c["depth"],
-                precision="fp64", mode="iter", seed=seed_mode, max_sweeps=args.batch_sweeps) for c in cfgs]
+                precision="fp64", mode="iter", seed=seed_mode, max_sweeps=args.batch_sweeps, accel=accel)
+           for c in cfgs]
     b = Batch(mem, device=dev, graph=True)
     if blob is not None:
         b.net_load(blob)
@@ -243,7 +252,8 @@ def run_adaptive(args, dev, rk_tol):
 
     cfg = c5_members([0], args.n)[0]
     g = cfg["grid"]
-    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="iter", max_sweeps=args.max_sweeps)
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="iter", max_sweeps=args.max_sweeps,
+               accel=None if args.accel == "none" else args.accel)
     eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=dev)
     phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=dev)
     dt, tol, Tp = cfg["dt"], cfg["tol"], cfg["period"]
@@ -366,14 +376,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1024, help="grid size (1024 = the benchmark workload)")
     ap.add_argument("--max-sweeps", type=int, default=400)
-    ap.add_argument("--batch-sweeps", type=int, default=48,
-                    help="sweep budget per solve of the captured forms (solves here need at most 33)")
+    ap.add_argument("--batch-sweeps", type=int, default=None,
+                    help="sweep budget per solve of the captured forms (default 24 with Anderson mixing, 48 "
+                         "without; solves here need at most 15 and 33)")
     ap.add_argument("--members", type=int, default=2, help="realisations of the batched forms")
     ap.add_argument("--c4-steps", type=int, default=4)
     ap.add_argument("--c3-steps", type=int, default=32)
     ap.add_argument("--c2-steps", type=int, default=256)
     ap.add_argument("--forms",
-                    default="plain,batched+prev,batched+learned,plain-fp32,adaptive,c2-tank,c4,c3-precision")
+                    default="plain,plain-relaxed,batched+prev,batched+learned,plain-fp32,adaptive,c2-tank,c4,"
+                            "c3-precision")
+    ap.add_argument("--accel", default="anderson", choices=["anderson", "none"],
+                    help="iteration of the W solves: Anderson-mixed (default) or plain relaxed sweeps")
     ap.add_argument("--adaptive-periods", type=float, default=4.0)
     ap.add_argument("--rk-tol", type=float, default=3e-7,
                     help="error bound of the adaptive form; at 3e-7 its global error over two periods of a "
@@ -391,31 +405,35 @@ def main():
 
     dev = torch.device("cuda:0")
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-    plain = run_plain(args, dev, "fp64", 1e-8)
+    accel = None if args.accel == "none" else args.accel
+    if args.batch_sweeps is None:
+        args.batch_sweeps = 24 if accel else 48
+    plain = run_plain(args, dev, "fp64", 1e-8, accel=accel)
     cfg = plain.pop("cfg")
     g = cfg["grid"]
-    traffic = measured_traffic(plain["dominant"]) if (g.nx, g.ny) == (1024, 1024) else None
+    tkey = plain["dominant"] + ("_aa" if accel == "anderson" else "")
+    traffic = measured_traffic(tkey) if (g.nx, g.ny) == (1024, 1024) else None
     roofline = dict(plain["roofline"])
     roofline["traffic"] = round(traffic) if traffic is not None else None
     out_forms = {"plain": {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in plain.items()
                            if k in ("value", "ms_per_step", "sweeps_mean", "sweeps_max", "max_residual", "status")}}
     if "batched+prev" in forms:
-        out_forms["batched+prev"] = run_batched(args, dev, "prev", args.members)
+        out_forms["batched+prev"] = run_batched(args, dev, "prev", args.members, accel)
     if "batched+learned" in forms:
-        out_forms["batched+learned"] = run_batched(args, dev, "net", args.members)
+        out_forms["batched+learned"] = run_batched(args, dev, "net", args.members, accel)
     if "plain-fp32" in forms:
-        f32 = run_plain(args, dev, "fp32", 1e-6)
+        f32 = run_plain(args, dev, "fp32", 1e-6, accel=accel)
         f32.pop("cfg")
         out_forms["plain-fp32"] = {k: v for k, v in f32.items() if k in ("value", "ms_per_step", "sweeps_mean",
                                                                           "sweeps_max", "max_residual", "status",
                                                                           "roofline")}
         out_forms["plain-fp32"]["tol"] = 1e-6
-    if "plain-anderson" in forms:
-        aa = run_plain(args, dev, "fp64", 1e-8, accel="anderson")
-        aa.pop("cfg")
-        out_forms["plain-anderson"] = {k: v for k, v in aa.items() if k in ("value", "ms_per_step", "sweeps_mean",
-                                                                             "sweeps_max", "max_residual", "status",
-                                                                             "roofline", "kernel_ms")}
+    if "plain-relaxed" in forms:
+        rx = run_plain(args, dev, "fp64", 1e-8, accel=None)
+        rx.pop("cfg")
+        out_forms["plain-relaxed"] = {k: v for k, v in rx.items() if k in ("value", "ms_per_step", "sweeps_mean",
+                                                                            "sweeps_max", "max_residual", "status",
+                                                                            "roofline", "kernel_ms")}
     if "adaptive" in forms:
         out_forms["adaptive"] = run_adaptive(args, dev, args.rk_tol)
     if "c2-tank" in forms:
@@ -443,8 +461,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"crossing JONSWAP seas {g.nx}x{g.ny}, 128 lambda_p, Gaussian-bump bathymetry, "
                                f"k_p h_ref={cfg['h_ref']:.3f}, IF-RK4 dt=T_p/64, W iteration tol 1e-08 FP64 "
+                               f"with {'Anderson-mixed' if accel else 'relaxed'} sweeps "
                                f"(plain: linear-guess seed, single member; other forms under 'forms')",
-                   "grid": [g.ny, g.nx], "form": "plain"},
+                   "grid": [g.ny, g.nx], "form": "plain", "iteration": accel or "relaxed"},
         "sweeps_per_solve_mean": round(plain["sweeps_mean"], 2),
         "sweeps_per_solve_max": plain["sweeps_max"],
         "max_residual": plain["max_residual"],
