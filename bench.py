@@ -51,7 +51,8 @@ def algorithmic_bytes(kind: str, nx: int, ny: int, Kx: int, Ky: int, csz: int, r
 
     half-form array: ny*Kx complex; compact array: Ky*Kx complex; physical: nx*ny real.
     aa: the Anderson-mixed iteration, whose row pass also reads T(V_(n-1)) and
-    whose column pass writes T(x_n) and the residual's half forms only.
+    whose column pass writes T_V(x_n), f_n and g_n (compact) and the residual's
+    half forms, not the next iterate.
     """
     half = ny * Kx * csz
     comp = Ky * Kx * csz
@@ -66,8 +67,9 @@ def algorithmic_bytes(kind: str, nx: int, ny: int, Kx: int, Ky: int, csz: int, r
         # and T(V_n), V_(n+1) (+ phi_b,(n+1))
         nin_c = 2 + (2 if vd else 0)
         if aa:
-            # write T_V, T_phi_b (compact) and the half forms of f_n and T_V(x_n)
-            return nprod * half + nin_c * comp + 2 * half + (1 + (1 if vd else 0)) * comp
+            # write T_V(x_n), the residual f_n and relaxed sweep g_n (compact, V and phi_b parts) and the half
+            # forms of f_n and T_V(x_n)
+            return nprod * half + nin_c * comp + 2 * half + (1 + 2 * (1 + (1 if vd else 0))) * comp
         nout_c = 2 + (1 if vd else 0)
         return nprod * half + nin_c * comp + (2 + ncomp) * half + nout_c * comp
     raise ValueError(kind)

@@ -43,7 +43,6 @@ enum {
     C_NP,                // nonlinear term of the potential equation
     C_DV, C_DB,          // nonlinear part (V* - kT phi, phi_b - S phi) of the last solve
     C_PD,                // i k . MF{mu grad phi} of the wave tank's damping pressure
-    C_TB,                // T_phi_b(x_n) of the Anderson-mixed iteration
     C_AFV0,              // residual history f_i (V part), kAASlots ring slots
     C_AFB0 = C_AFV0 + kAASlots,  //   (phi_b part)
     C_AGV0 = C_AFB0 + kAASlots,  // relaxed-sweep history g_i (V part)
@@ -116,6 +115,7 @@ struct sbi_ctx {
     Ctl* ctl = nullptr;
     double* diag_partial = nullptr;
     double* aa_partial = nullptr;   // [batch][kAABlocks][kAASlots] inner-product partials
+    double* aa_w = nullptr;         // [batch][kAASlots] weights of the next iterate on the history
     void* part = nullptr;    // partial sums of grouped column passes
     int* cnt = nullptr;      // tile tickets of grouped column passes
     int col_C = 1;
@@ -232,6 +232,7 @@ static Layout layout(const sbi_grid* g, int batch) {
     L.bytes_tw = al((size_t)g->nx * L.csz) + al((size_t)(g->nx / 2) * L.csz) + al((size_t)g->ny * L.csz);
     L.bytes_misc = al(sizeof(double) * batch) + al(sizeof(Ctl) * batch) + al(sizeof(CtlSlots) * batch) +
                    al(sizeof(double) * 2 * 64 * batch) + al(sizeof(double) * kAASlots * kAABlocks * batch) +
+                   al(sizeof(double) * kAASlots * batch) +
                    al((size_t)L.s_cmp * L.csz * batch * kMaxGroups * 4) + al(sizeof(int) * (size_t)kMaxTiles * batch);
     // learned warm start: packed weights, and the feature field when it seeds the iteration
     L.bytes_net = al(sizeof(NetPacked)) +
@@ -398,6 +399,8 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
     p += al(sizeof(double) * 2 * 64 * batch);
     c->aa_partial = reinterpret_cast<double*>(p);
     p += al(sizeof(double) * kAASlots * kAABlocks * batch);
+    c->aa_w = reinterpret_cast<double*>(p);
+    p += al(sizeof(double) * kAASlots * batch);
     c->part = p;
     p += al((size_t)L.s_cmp * L.csz * batch * kMaxGroups * 4);
     c->cnt = reinterpret_cast<int*>(p);
@@ -528,6 +531,7 @@ struct ColBuilder {
     ColParams p{};
     std::vector<ColTerm> terms;
     std::vector<const void*> prods, cins;
+    std::vector<int> cin_w;
     std::vector<long long> prod_stride;
     explicit ColBuilder(const GridDev& g) {
         p.g = g;
@@ -539,8 +543,10 @@ struct ColBuilder {
         prod_stride.push_back(stride);
         return (int)prods.size() - 1;
     }
-    int cin(const void* c) {
+    // widx >= 0: the input is scaled by the per-member device weight p.cin_w[widx]
+    int cin(const void* c, int widx = -1) {
         cins.push_back(c);
+        cin_w.push_back(widx);
         return -(int)cins.size();  // resolved at build: nprod + index
     }
     void term(int src, int acc, double coef, int fn, int pw, int dv) {
@@ -574,6 +580,7 @@ struct ColBuilder {
             p.hin_stride[i] = prod_stride[i];
         }
         for (int i = 0; i < p.ncin; ++i) p.cin[i] = cins[i];
+        for (int i = 0; i < kMaxCin; ++i) p.cin_widx[i] = (signed char)(i < p.ncin ? cin_w[i] : -1);
         for (auto& t : terms)
             if (t.src < 0) t.src = (short)(p.nprod + (-t.src - 1));
         std::stable_sort(terms.begin(), terms.end(), [](const ColTerm& a, const ColTerm& b) { return a.src < b.src; });
@@ -797,44 +804,47 @@ static sbi_status col_forcing(sbi_ctx* c) {
     return run_col(c, b, K_COL_FORCING);
 }
 
-// Anderson mixing after the column pass of sweep n: residual and relaxed sweep
-// into the history ring with their inner products, the next iterate x_(n+1)
-// (compact), then the inverse column transforms of x_(n+1) (V, grad phi_b)
-// that the next row pass reads
+// Anderson mixing after the column pass of sweep n (which stored f_n and g_n
+// in the history ring): inner products and the weights of the next iterate,
+// then one column pass that forms x_(n+1) = sum_i w_i g_i from the history
+// (compact) and its inverse column transforms (V, grad phi_b) for the next row
+// pass
 static sbi_status anderson_mix(sbi_ctx* c, int n) {
     const bool two_d = c->grid.ny > 1;
-    const int s = n % kAASlots;
+    const int k = std::min(n, kAADepth);
     AaParams ap{};
     ap.g = c->gd;
     ap.ctl = c->ctl;
     ap.sweep = n;
     ap.vd = c->vd;
-    ap.xv = CMP(C_VN);
-    ap.xb = CMP(C_BN);
-    ap.tv = CMP(C_VP);
-    ap.tb = CMP(C_TB);
     for (int i = 0; i < kAASlots; ++i) {
         ap.fv[i] = CMP(C_AFV0 + i);
         ap.fb[i] = CMP(C_AFB0 + i);
-        ap.gv[i] = CMP(C_AGV0 + i);
-        ap.gb[i] = CMP(C_AGB0 + i);
     }
     ap.partial = c->aa_partial;
     ap.nblk = kAABlocks;
+    ap.weights = c->aa_w;
     c->st.launches += 2;
     {
         ProfScope ps_(c, K_COL_OTHER);
         SBI_TRY(hip_ok(launch_aa_dot(c->fp64, ap, c->batch, c->stream)));
-        SBI_TRY(hip_ok(launch_aa_mix(c->fp64, ap, c->batch, c->stream)));
+        SBI_TRY(hip_ok(launch_aa_solve(c->fp64, ap, c->batch, c->stream)));
     }
-    (void)s;
     ColBuilder b(c->gd);
-    const int sx = b.cin(CMP(C_VN));
-    b.term(sx, 0, 1.0, FN_ONE, 0, DV_NONE);
+    for (int a = 0; a <= k; ++a) {
+        const int si = (n - k + a) % kAASlots;
+        const int sv = b.cin(CMP(C_AGV0 + si), si);
+        b.term(sv, 0, 1.0, FN_ONE, 0, DV_NONE);
+        if (c->vd) {
+            const int sb = b.cin(CMP(C_AGB0 + si), si);
+            b.term(sb, 1, 1.0, FN_ONE, 0, DV_NONE);
+        }
+    }
+    b.p.cin_w = c->aa_w;
+    b.cout(SRC_ACC0, CMP(C_VN));
     b.inv(SRC_ACC0, DV_NONE, HALF(H_GV));
     if (c->vd) {
-        const int sb = b.cin(CMP(C_BN));
-        b.term(sb, 1, 1.0, FN_ONE, 0, DV_NONE);
+        b.cout(SRC_ACC1, CMP(C_BN));
         b.inv(SRC_ACC1, DV_X, HALF(H_GBX));
         if (two_d) b.inv(SRC_ACC1, DV_Y, HALF(H_GBY));
     }
@@ -914,13 +924,20 @@ static sbi_status launch_sweep(sbi_ctx* c, const void* eta_phys, int n, double t
         }
     }
     if (aa) {
-        // T(x_n), and the half forms of the residual test (f_n and T(V_n));
-        // the next iterate follows once the inner products over the whole
-        // spectrum are known
-        (void)cbn;
+        // T_V(x_n); the residual f_n and the relaxed sweep g_n into the history
+        // ring; the half forms of the residual test (f_n and T_V(x_n)).  The
+        // next iterate follows once the inner products over the whole spectrum
+        // are known.
+        const int s = n % kAASlots;
         b.p.relax_prev[0] = -cvn - 1;
+        if (c->vd) b.p.relax_prev[1] = -cbn - 1;
         b.cout(SRC_ACC0, CMP(C_VP));
-        if (c->vd) b.cout(SRC_ACC1, CMP(C_TB));
+        b.cout(SRC_DIFF0, CMP(C_AFV0 + s));
+        b.cout(SRC_NEW0, CMP(C_AGV0 + s));
+        if (c->vd) {
+            b.cout(SRC_DIFF1, CMP(C_AFB0 + s));
+            b.cout(SRC_NEW1, CMP(C_AGB0 + s));
+        }
         b.inv(SRC_DIFF0, DV_NONE, HALF(H_GD));
         b.inv(SRC_ACC0, DV_NONE, HALF(H_GT));
     } else {

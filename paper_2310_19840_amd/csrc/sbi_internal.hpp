@@ -97,6 +97,8 @@ struct ColParams {
     const void* hin[kMaxProd];
     long long hin_stride[kMaxProd];   // per-member stride override (0 = g.s_half)
     const void* cin[kMaxCin];
+    const double* cin_w;               // [batch][kAASlots] device weights of compact inputs (Anderson mixing)
+    signed char cin_widx[kMaxCin];     // weight index of each compact input, -1: none
     short toff[kMaxProd + kMaxCin + 1]; // terms sorted by source: [toff[s], toff[s+1])
     ColTerm term[kMaxTerms];
     int relax_prev[2];                 // compact-input index of the previous iterate of acc0/acc1, -1 none

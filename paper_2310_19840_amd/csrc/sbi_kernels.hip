@@ -1075,8 +1075,10 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         if (prod || !CF::WAVE) fft<V, N, false, 1, CE, CF::WAVE>(v, lds, 0, j, twc);
         if (live && !prod) {
             const V* Ci = static_cast<const V*>(p.cin[jb - nps]) + mem * g.s_cmp + (long long)mx * g.Ky;
+            const int wi = p.cin_widx[jb - nps];
+            const R cw = wi >= 0 ? R(p.cin_w[mem * kAASlots + wi]) : R(1);
 #pragma unroll
-            for (int q = 0; q < E; ++q) v[q] = crow[q] >= 0 ? Ci[crow[q]] : cx<V>(R(0), R(0));
+            for (int q = 0; q < E; ++q) v[q] = crow[q] >= 0 ? cscale(Ci[crow[q]], cw) : cx<V>(R(0), R(0));
         }
         if (live) col_apply_terms<R, V, E, NACC>(s_toff, s_term, src, v, acc, crow, geo, kxr);
         if constexpr (CF::PREFETCH) {
@@ -1349,8 +1351,10 @@ k_colp(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
             fft<V, NH, false, 1, E, true>(v, lds, 0, j, twc);
         } else {
             const V* Ci = static_cast<const V*>(p.cin[jb - nps]) + mem * g.s_cmp + (long long)mx * g.Ky;
+            const int wi = p.cin_widx[jb - nps];
+            const R cw = wi >= 0 ? R(p.cin_w[mem * kAASlots + wi]) : R(1);
 #pragma unroll
-            for (int q = 0; q < E; ++q) v[q] = crow[q] >= 0 ? Ci[crow[q]] : cx<V>(R(0), R(0));
+            for (int q = 0; q < E; ++q) v[q] = crow[q] >= 0 ? cscale(Ci[crow[q]], cw) : cx<V>(R(0), R(0));
         }
         col_apply_terms<R, V, E, NACC>(s_toff, s_term, jb, v, acc, crow, geo, kxr);
     }
@@ -1729,16 +1733,16 @@ __global__ void k_rk54(const Rk54Params p) {
 // ---------------------------------------------------------------------------
 // Anderson mixing of the relaxed sweep (iteration mode)
 // ---------------------------------------------------------------------------
-// Sweep n stores f_n = T(x_n) - x_n and g_n = x_n + omega f_n in ring slot
-// n mod kAASlots and forms per-workgroup partial sums of <F_i, f_n> for the
-// k + 1 = min(n, kAADepth) + 1 history slots (real inner product of the real
-// fields: half-spectrum modes weighted 2 for m_x > 0).  k_aa_mix then adds
-// the partials in workgroup order (every workgroup alike, so no workgroup
-// waits for another), completes the Gram matrix of the history (workgroup 0
-// stores the new row), solves the normal equations of
-// min |f_n - sum_a gamma_a dF_a|, dF_a = F_(a+1) - F_a over the history in
-// sweep order (regularised by 1e-12 trace / k; gamma = 0 when they fail), and
-// forms x_(n+1) = g_n - sum_a gamma_a (G_(a+1) - G_a).
+// The sweep's column pass stores f_n = T(x_n) - x_n and g_n = x_n + omega f_n
+// in ring slot n mod kAASlots; k_aa_dot forms per-workgroup partial sums of
+// <F_i, f_n> over the k + 1 = min(n, kAADepth) + 1 history slots (real inner
+// product of the real fields: half-spectrum modes weighted 2 for m_x > 0).
+// k_aa_solve adds them in workgroup order, completes the Gram matrix of the
+// history, solves the normal equations of min |f_n - sum_a gamma_a dF_a|,
+// dF_a = F_(a+1) - F_a over the history in sweep order (regularised by
+// 1e-12 trace / k; gamma = 0 when they fail), and leaves the weights of
+// x_(n+1) = g_n - sum_a gamma_a (G_(a+1) - G_a) on the history slots, which
+// the next column pass applies to its compact inputs.
 template <typename R>
 __global__ void __launch_bounds__(256) k_aa_dot(const AaParams p) {
     using V = typename cplx_of<R>::type;
@@ -1747,41 +1751,31 @@ __global__ void __launch_bounds__(256) k_aa_dot(const AaParams p) {
     const Ctl* ctl = p.ctl + mem;
     if (ctl->done) return;
     const GridDev& g = p.g;
-    const int n = p.sweep, s = n % kAASlots, k = n < kAADepth ? n : kAADepth;
-    const double om = ctl->omega;
+    const int n = p.sweep, k = n < kAADepth ? n : kAADepth;
     const int ncmp = (int)g.s_cmp;
     double d[kAASlots];
 #pragma unroll
     for (int i = 0; i < kAASlots; ++i) d[i] = 0.0;
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ncmp; idx += gridDim.x * blockDim.x) {
-        const int mx = idx / g.Ky, r = idx - mx * g.Ky;
+        const int mx = idx / g.Ky;
         if (mx >= g.Kx) continue;
         const long long o = mem * g.s_cmp + idx;
         const double wt = mx == 0 ? 1.0 : 2.0;
-        (void)r;
 #pragma unroll
         for (int part = 0; part < 2; ++part) {
             if (part == 1 && !p.vd) break;
-            const V x = static_cast<const V*>(part ? p.xb : p.xv)[o];
-            const V t = static_cast<const V*>(part ? p.tb : p.tv)[o];
-            const double fr = (double)t.x - (double)x.x, fi = (double)t.y - (double)x.y;
-            // the stored (rounded) residual enters every inner product, as it does when read back
-            const V fs = cx<V>(R(fr), R(fi));
-            static_cast<V*>(part ? p.fb[s] : p.fv[s])[o] = fs;
-            static_cast<V*>(part ? p.gb[s] : p.gv[s])[o] = cx<V>(R((double)x.x + om * fr), R((double)x.y + om * fi));
             V fo[kAASlots];
 #pragma unroll
-            for (int j = 1; j <= kAADepth; ++j)
+            for (int j = 0; j <= kAADepth; ++j)
                 if (j <= k) {
                     const int si = (n - j) % kAASlots;
                     fo[j] = static_cast<const V*>(part ? p.fb[si] : p.fv[si])[o];
                 }
-            fo[0] = fs;
 #pragma unroll
             for (int j = 0; j <= kAADepth; ++j) {
                 if (j > k) break;
                 const int si = (n - j) % kAASlots;
-                const double v = wt * ((double)fo[j].x * (double)fs.x + (double)fo[j].y * (double)fs.y);
+                const double v = wt * ((double)fo[j].x * (double)fo[0].x + (double)fo[j].y * (double)fo[0].y);
 #pragma unroll
                 for (int i = 0; i < kAASlots; ++i)
                     if (i == si) d[i] += v;
@@ -1802,19 +1796,20 @@ __global__ void __launch_bounds__(256) k_aa_dot(const AaParams p) {
         for (int i = 0; i < kAASlots; ++i) p.partial[((long long)mem * p.nblk + blockIdx.x) * kAASlots + i] = red[i][0];
 }
 
+// one workgroup per member
 template <typename R>
-__global__ void __launch_bounds__(256) k_aa_mix(const AaParams p) {
-    using V = typename cplx_of<R>::type;
+__global__ void __launch_bounds__(256) k_aa_solve(const AaParams p) {
     __shared__ double red[kAASlots][256];
-    __shared__ double cw[kAASlots];
-    const int mem = blockIdx.y;
+    const int mem = blockIdx.x;
     Ctl* ctl = p.ctl + mem;
     if (ctl->done) return;
     const int n = p.sweep, s = n % kAASlots, k = n < kAADepth ? n : kAADepth;
-    // inner products of this sweep: the partials added by the tree of k_aa_dot
 #pragma unroll
-    for (int i = 0; i < kAASlots; ++i)
-        red[i][threadIdx.x] = p.partial[((long long)mem * p.nblk + threadIdx.x) * kAASlots + i];
+    for (int i = 0; i < kAASlots; ++i) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < p.nblk; b += blockDim.x) v += p.partial[((long long)mem * p.nblk + b) * kAASlots + i];
+        red[i][threadIdx.x] = v;
+    }
     __syncthreads();
     for (int w = blockDim.x / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
@@ -1822,96 +1817,77 @@ __global__ void __launch_bounds__(256) k_aa_mix(const AaParams p) {
             for (int i = 0; i < kAASlots; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        // history slots in sweep order: H[a] holds sweep n - k + a
-        int H[kAASlots];
-        for (int a = 0; a <= k; ++a) H[a] = (n - k + a) % kAASlots;
-        double Mg[kAASlots][kAASlots];
-        for (int a = 0; a < kAASlots; ++a)
-            for (int b = 0; b < kAASlots; ++b) Mg[a][b] = ctl->aa_gram[a][b];
-        for (int a = 0; a <= k; ++a) {
-            Mg[s][H[a]] = red[H[a]][0];
-            Mg[H[a]][s] = red[H[a]][0];
-        }
-        if (blockIdx.x == 0)
-            for (int a = 0; a <= k; ++a) {
-                ctl->aa_gram[s][H[a]] = Mg[s][H[a]];
-                ctl->aa_gram[H[a]][s] = Mg[H[a]][s];
-            }
-        double gam[kAADepth];
-        for (int a = 0; a < kAADepth; ++a) gam[a] = 0.0;
-        if (k > 0) {
-            double A[kAADepth][kAADepth], y[kAADepth];
-            auto M = [&](int a, int b) { return Mg[H[a]][H[b]]; };
-            double tr = 0.0;
-            for (int a = 0; a < k; ++a) {
-                for (int b = 0; b < k; ++b) A[a][b] = M(a + 1, b + 1) - M(a + 1, b) - M(a, b + 1) + M(a, b);
-                y[a] = M(a + 1, k) - M(a, k);
-                tr += A[a][a];
-            }
-            const double reg = 1e-12 * tr / k;
-            for (int a = 0; a < k; ++a) A[a][a] += reg;
-            // Gaussian elimination with partial pivoting (k <= kAADepth)
-            bool ok = tr > 0.0 && isfinite(tr);
-            for (int c = 0; c < k && ok; ++c) {
-                int pv = c;
-                for (int r = c + 1; r < k; ++r)
-                    if (fabs(A[r][c]) > fabs(A[pv][c])) pv = r;
-                if (!(fabs(A[pv][c]) > 0.0)) {
-                    ok = false;
-                    break;
-                }
-                if (pv != c) {
-                    for (int b = 0; b < k; ++b) {
-                        const double t = A[c][b];
-                        A[c][b] = A[pv][b];
-                        A[pv][b] = t;
-                    }
-                    const double t = y[c];
-                    y[c] = y[pv];
-                    y[pv] = t;
-                }
-                for (int r = c + 1; r < k; ++r) {
-                    const double f = A[r][c] / A[c][c];
-                    for (int b = c; b < k; ++b) A[r][b] -= f * A[c][b];
-                    y[r] -= f * y[c];
-                }
-            }
-            if (ok) {
-                for (int c = k - 1; c >= 0; --c) {
-                    double v = y[c];
-                    for (int b = c + 1; b < k; ++b) v -= A[c][b] * gam[b];
-                    gam[c] = v / A[c][c];
-                }
-                for (int a = 0; a < k; ++a) ok = ok && isfinite(gam[a]);
-            }
-            if (!ok)
-                for (int a = 0; a < kAADepth; ++a) gam[a] = 0.0;
-        }
-        // x_(n+1) = G_k - sum_a gamma_a (G_(a+1) - G_a): weights of the history in sweep order
-        for (int a = 0; a <= k; ++a) {
-            double c = a == k ? 1.0 : 0.0;
-            if (a < k) c += gam[a];
-            if (a >= 1) c -= gam[a - 1];
-            cw[a] = c;
-        }
+    if (threadIdx.x != 0) return;
+    // history slots in sweep order: H[a] holds sweep n - k + a
+    int H[kAASlots];
+    for (int a = 0; a <= k; ++a) H[a] = (n - k + a) % kAASlots;
+    double Mg[kAASlots][kAASlots];
+    for (int a = 0; a < kAASlots; ++a)
+        for (int b = 0; b < kAASlots; ++b) Mg[a][b] = ctl->aa_gram[a][b];
+    for (int a = 0; a <= k; ++a) {
+        Mg[s][H[a]] = red[H[a]][0];
+        Mg[H[a]][s] = red[H[a]][0];
+        ctl->aa_gram[s][H[a]] = red[H[a]][0];
+        ctl->aa_gram[H[a]][s] = red[H[a]][0];
     }
-    __syncthreads();
-    const int ncmp = (int)p.g.s_cmp;
-    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < ncmp; idx += gridDim.x * blockDim.x) {
-        const int mx = idx / p.g.Ky;
-        if (mx >= p.g.Kx) continue;
-        const long long o = mem * p.g.s_cmp + idx;
-        for (int part = 0; part < (p.vd ? 2 : 1); ++part) {
-            double xr = 0.0, xi = 0.0;
-            for (int a = k; a >= 0; --a) {
-                const int si = (n - k + a) % kAASlots;
-                const V gv = static_cast<const V*>(part ? p.gb[si] : p.gv[si])[o];
-                xr += cw[a] * (double)gv.x;
-                xi += cw[a] * (double)gv.y;
-            }
-            static_cast<V*>(part ? p.xb : p.xv)[o] = cx<V>(R(xr), R(xi));
+    double gam[kAADepth];
+    for (int a = 0; a < kAADepth; ++a) gam[a] = 0.0;
+    if (k > 0) {
+        double A[kAADepth][kAADepth], y[kAADepth];
+        auto M = [&](int a, int b) { return Mg[H[a]][H[b]]; };
+        double tr = 0.0;
+        for (int a = 0; a < k; ++a) {
+            for (int b = 0; b < k; ++b) A[a][b] = M(a + 1, b + 1) - M(a + 1, b) - M(a, b + 1) + M(a, b);
+            y[a] = M(a + 1, k) - M(a, k);
+            tr += A[a][a];
         }
+        const double reg = 1e-12 * tr / k;
+        for (int a = 0; a < k; ++a) A[a][a] += reg;
+        // Gaussian elimination with partial pivoting (k <= kAADepth)
+        bool ok = tr > 0.0 && isfinite(tr);
+        for (int c = 0; c < k && ok; ++c) {
+            int pv = c;
+            for (int r = c + 1; r < k; ++r)
+                if (fabs(A[r][c]) > fabs(A[pv][c])) pv = r;
+            if (!(fabs(A[pv][c]) > 0.0)) {
+                ok = false;
+                break;
+            }
+            if (pv != c) {
+                for (int b = 0; b < k; ++b) {
+                    const double t = A[c][b];
+                    A[c][b] = A[pv][b];
+                    A[pv][b] = t;
+                }
+                const double t = y[c];
+                y[c] = y[pv];
+                y[pv] = t;
+            }
+            for (int r = c + 1; r < k; ++r) {
+                const double f = A[r][c] / A[c][c];
+                for (int b = c; b < k; ++b) A[r][b] -= f * A[c][b];
+                y[r] -= f * y[c];
+            }
+        }
+        if (ok) {
+            for (int c = k - 1; c >= 0; --c) {
+                double v = y[c];
+                for (int b = c + 1; b < k; ++b) v -= A[c][b] * gam[b];
+                gam[c] = v / A[c][c];
+            }
+            for (int a = 0; a < k; ++a) ok = ok && isfinite(gam[a]);
+        }
+        if (!ok)
+            for (int a = 0; a < kAADepth; ++a) gam[a] = 0.0;
+    }
+    // x_(n+1) = G_k - sum_a gamma_a (G_(a+1) - G_a): weights of the history slots
+    double* wout = p.weights + (long long)mem * kAASlots;
+    for (int i = 0; i < kAASlots; ++i) wout[i] = 0.0;
+    for (int a = 0; a <= k; ++a) {
+        double c = a == k ? 1.0 : 0.0;
+        if (a < k) c += gam[a];
+        if (a >= 1) c -= gam[a - 1];
+        wout[H[a]] = c;
     }
 }
 
@@ -2106,16 +2082,12 @@ template <> hipError_t launch_rk54_t<Real>(const Rk54Params& p, int batch, hipSt
     return hipGetLastError();
 }
 template <> hipError_t launch_aa_dot_t<Real>(const AaParams& p, int batch, hipStream_t s) {
-    if (p.nblk != 256) return hipErrorInvalidValue;
     dim3 block(256), grid((unsigned)p.nblk, batch);
     hipLaunchKernelGGL(k_aa_dot<Real>, grid, block, 0, s, p);
     return hipGetLastError();
 }
-template <> hipError_t launch_aa_mix_t<Real>(const AaParams& p, int batch, hipStream_t s) {
-    // each workgroup adds the nblk == 256 partials of k_aa_dot, one per thread
-    if (p.nblk != 256) return hipErrorInvalidValue;
-    dim3 block(256), grid((unsigned)std::min<long long>((p.g.s_cmp + 255) / 256, 256), batch);
-    hipLaunchKernelGGL(k_aa_mix<Real>, grid, block, 0, s, p);
+template <> hipError_t launch_aa_solve_t<Real>(const AaParams& p, int batch, hipStream_t s) {
+    hipLaunchKernelGGL(k_aa_solve<Real>, dim3(batch), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 template <> hipError_t launch_diag_t<Real>(const DiagParams& p, int batch, hipStream_t s) {

@@ -157,24 +157,19 @@ struct Rk54Params {
     int nblk;
 };
 
-// Anderson mixing of the relaxed sweep (iteration mode): residual and relaxed
-// sweep of sweep n into the history ring, inner products (k_aa_dot), then the
-// next iterate as a combination of the relaxed sweeps (k_aa_mix)
+// Anderson mixing of the relaxed sweep (iteration mode): inner products of the
+// residual history (k_aa_dot) and the weights of the next iterate on the
+// history of relaxed sweeps (k_aa_solve)
 struct AaParams {
     GridDev g;
     Ctl* ctl;
     int sweep;                 // n
     int vd;                    // phi_b is iterated too (variable bed)
-    void* xv;                  // x_n (k_aa_dot) / x_(n+1) (k_aa_mix): V and phi_b parts
-    void* xb;
-    const void* tv;            // T(x_n)
-    const void* tb;
-    void* fv[kAASlots];        // residual history f_i = T(x_i) - x_i
-    void* fb[kAASlots];
-    void* gv[kAASlots];        // relaxed-sweep history g_i = x_i + omega f_i
-    void* gb[kAASlots];
+    const void* fv[kAASlots];  // residual history f_i = T(x_i) - x_i (V and phi_b parts)
+    const void* fb[kAASlots];
     double* partial;           // [batch][nblk][kAASlots]
     int nblk;
+    double* weights;           // [batch][kAASlots]: x_(n+1) = sum_i weights[i] g_i
 };
 
 struct DiagParams {
@@ -208,7 +203,7 @@ template <typename R> hipError_t launch_col_t(const ColParams&, int, const Twidd
 template <typename R> hipError_t launch_rk_t(const RkParams&, int, hipStream_t);
 template <typename R> hipError_t launch_rk54_t(const Rk54Params&, int, hipStream_t);
 template <typename R> hipError_t launch_aa_dot_t(const AaParams&, int, hipStream_t);
-template <typename R> hipError_t launch_aa_mix_t(const AaParams&, int, hipStream_t);
+template <typename R> hipError_t launch_aa_solve_t(const AaParams&, int, hipStream_t);
 template <typename R> hipError_t launch_diag_t(const DiagParams&, int, hipStream_t);
 
 hipError_t launch_row_fwd(int fp64, const RowFwdParams& p, int batch, const Twiddles& tw, hipStream_t s);
@@ -223,7 +218,7 @@ hipError_t launch_col(int fp64, const ColParams& p, int batch, const Twiddles& t
 hipError_t launch_rk(int fp64, const RkParams& p, int batch, hipStream_t s);
 hipError_t launch_rk54(int fp64, const Rk54Params& p, int batch, hipStream_t s);
 hipError_t launch_aa_dot(int fp64, const AaParams& p, int batch, hipStream_t s);
-hipError_t launch_aa_mix(int fp64, const AaParams& p, int batch, hipStream_t s);
+hipError_t launch_aa_solve(int fp64, const AaParams& p, int batch, hipStream_t s);
 hipError_t launch_diag(int fp64, const DiagParams& p, int batch, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* ctl, int batch, int slots, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
