@@ -154,3 +154,23 @@ def test_tank_settings_checked(gpu):
     s.set_wavemaker([], x0=None)
     s.step(e, p, 0.1, 4)
     assert float(e.abs().max()) == 0.0
+
+
+def test_tank_2d_with_anderson_mixed_solves(gpu):
+    import torch
+    nx, ny = 64, 32
+    lx, ly = 16 * math.pi, 4 * math.pi
+    gs = si.GridSpec(nx, ny, lx, ly)
+    eta, phi = si.jonswap_crossing_sea(gs, 1.0, seed=7, hs_half=0.03)
+    X, Y = np.meshgrid(gs.x(), gs.y())
+    depth = 1.0 - 0.15 * np.exp(-((X - lx / 2) ** 2 + (Y - ly / 2) ** 2) / 20.0)
+    wm = dict(comps=[(0.01, 1.0, math.sqrt(math.tanh(1.0)), 0.0)], x0=0.75 * lx, width=2.0)
+    s, o = _pair(gpu, nx, ny, lx, ly, depth, wm, mode="iter", accel="anderson")
+    dt = 2 * math.pi / 32
+    _say("tank 2D anderson")
+    e = _t(eta, torch.float64, gpu)
+    p = _t(phi, torch.float64, gpu)
+    st, info = s.step(e, p, dt, 4, tol=1e-12, t=0.5)
+    eo, po, stats = o.step(eta, phi, dt, 4, tol=1e-12, t0=0.5)
+    assert info["sweeps_total"] == sum(x.sweeps for x in stats)
+    assert _rel(e.cpu().numpy().reshape(eo.shape), eo) < 1e-10
