@@ -1317,11 +1317,15 @@ extern "C" sbi_status sbi_vertical_velocity(sbi_ctx* c, const void* eta, const v
                         (c->grid.seed == SBI_SEED_USER && c->grid.mode == SBI_MODE_ITER) ? w_seed : nullptr));
     sbi_status st = solve_status(c, info, false);
     if (st < 0) return st;
+    // W = T_V(V_n) of the deciding sweep: in half form for the mixed iteration,
+    // else V_(n+1) + (1 - omega) D_n from the relaxed update
+    const bool iter = c->grid.mode == SBI_MODE_ITER;
+    const bool aa = iter && c->grid.accel == SBI_ACCEL_ANDERSON;
     RowInvParams ip{};
     ip.g = c->gd;
     ip.nf = 1;
-    ip.in[0] = HALF(H_GV);
-    ip.in2[0] = c->grid.mode == SBI_MODE_ITER ? HALF(H_GD) : nullptr;
+    ip.in[0] = aa ? HALF(H_GT) : HALF(H_GV);
+    ip.in2[0] = iter && !aa ? HALF(H_GD) : nullptr;
     ip.out[0] = w_out;
     ip.ctl = c->ctl;
     c->st.launches += 1;
@@ -1339,10 +1343,12 @@ extern "C" sbi_status sbi_vertical_velocity(sbi_ctx* c, const void* eta, const v
 static sbi_status nonlinear_term(sbi_ctx* c, double t) {
     const bool iter = c->grid.mode == SBI_MODE_ITER;
     const bool damp = c->dmp_w > 0.0;
+    // W at the stage state as in sbi_vertical_velocity
+    const bool aa = iter && c->grid.accel == SBI_ACCEL_ANDERSON;
     RowNphiParams np{};
     np.g = c->gd;
-    np.gV = HALF(H_GV);
-    np.gD = iter ? HALF(H_GD) : nullptr;
+    np.gV = aa ? HALF(H_GT) : HALF(H_GV);
+    np.gD = iter && !aa ? HALF(H_GD) : nullptr;
     np.gex = HALF(H_EX);
     np.gey = HALF(H_EY);
     np.gpx = HALF(H_PX);

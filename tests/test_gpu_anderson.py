@@ -149,3 +149,51 @@ def test_anderson_fp32_near_the_oracle_fixed_point(gpu):
     Wo, _ = o.vertical_velocity(cfg["eta"], cfg["phi"], tol=1e-12)
     assert st == 0
     assert _rel(W.cpu().numpy().reshape(Wo.shape).astype(np.float64), Wo) < 1e-5
+
+
+def test_anderson_status_codes(gpu):
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import SBIError, Solver, _lib
+    cfg = si.config_c1()
+    g = cfg["grid"]
+    _say("anderson status codes")
+    e = _t(cfg["eta"], torch.float64, gpu)
+    p = _t(cfg["phi"], torch.float64, gpu)
+    for m in (1, 2, 3):
+        s = Solver(g.nx, 1, g.lx, 1.0, cfg["depth"], h_ref=cfg["h_ref"], device=gpu, mode="iter", max_sweeps=m,
+                   accel="anderson")
+        W, st, info = s.vertical_velocity(e, p, tol=1e-14)
+        o = OSolver(Grid(g.nx, 1, g.lx), cfg["depth"], h_ref=cfg["h_ref"], mode="iter", max_sweeps=m, accel="anderson")
+        Wo, oi = o.vertical_velocity(cfg["eta"], cfg["phi"], tol=1e-14)
+        assert st == _lib.SBI_WARN_NOT_CONVERGED and oi.status == _lib.SBI_WARN_NOT_CONVERGED and info[0][0] == m
+        assert _rel(W.cpu().numpy().reshape(Wo.shape), Wo) < 1e-11
+    s = Solver(g.nx, 1, g.lx, 1.0, cfg["depth"], h_ref=cfg["h_ref"], device=gpu, mode="iter", accel="anderson")
+    e2 = cfg["eta"].copy()
+    e2[0, 5] = np.nan
+    with pytest.raises(SBIError) as ex:
+        s.vertical_velocity(_t(e2, torch.float64, gpu), p, tol=1e-12)
+    assert ex.value.code == _lib.SBI_ERR_NONFINITE
+    # a later solve on the same context is unaffected
+    W, st, info = s.vertical_velocity(e, p, tol=1e-12)
+    assert st == 0
+
+
+def test_anderson_steep_steady_wave_matches_oracle(gpu):
+    # where relaxed sweeps stall, the mixed iteration converges on both sides with the same sweep count
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from oracle.fenton import SteadyWave
+    from paper_2310_19840_amd import Solver
+    _say("anderson steep wave")
+    w = SteadyWave(0.4)
+    x = np.arange(64) * 2 * math.pi / 64
+    eta, _, phi, _ = w.surface(x)
+    s = Solver(64, 1, 2 * math.pi, 1.0, np.full((1, 64), 60.0), device=gpu, mode="iter", max_sweeps=300,
+               accel="anderson")
+    W, st, info = s.vertical_velocity(_t(eta[None], torch.float64, gpu), _t(phi[None], torch.float64, gpu), tol=1e-12)
+    o = OSolver(Grid(64, 1, 2 * math.pi), np.full((1, 64), 60.0), mode="iter", max_sweeps=300, accel="anderson")
+    Wo, oi = o.vertical_velocity(eta[None], phi[None], tol=1e-12)
+    assert st == 0 and oi.status == 0
+    assert abs(info[0][0] - oi.sweeps) <= 2, (info[0][0], oi.sweeps)
+    assert _rel(W.cpu().numpy().reshape(Wo.shape), Wo) < 1e-10
