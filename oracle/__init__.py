@@ -12,8 +12,9 @@ Method for Modeling Highly Nonlinear Water Waves in Variable Depth"):
 * Sec. 3.3, Eq. (filter): the optional low-pass filter;
 * Sec. 3.2: the numerical wave tank's pneumatic wavemaker and damping
   pressure (Eq. (pd));
-* ``fenton``: exact steady (Stokes) waves in deep water by the stream-function
-  method, the reference of Sec. 4's accuracy study;
+* ``fenton``: exact steady (Stokes) waves in deep water and finite depth by the
+  stream-function method, the reference of the accuracy studies of Sec. 4 and
+  Sec. 5;
 * ``warmstart``: the learned warm start of the W iteration (features, network
   forward and backward, Adam), defined in that module's header.
 

@@ -43,3 +43,28 @@ def test_steady_wave_orders_match_oracle_and_exact(gpu, eps):
         assert errs[6] < 5e-3 and errs[3] < 5e-3 and min(errs[5], errs[6]) > 0.5 * errs[4]
     else:
         assert errs[6] < 1e-7
+
+
+@pytest.mark.parametrize("dl", [2.4, 2.6])
+def test_depth_criterion_on_the_gpu(gpu, dl):
+    # Sec. 5: Stokes wave eps = kH/2 = 0.1 over depth d = h - delta, h = pi, order 7;
+    # the GPU's W equals the oracle's, so its error against the exact wave is the
+    # oracle's: below 10% at delta = 2.4, above 9% at 2.6
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from oracle.fenton import SteadyWave
+    from paper_2310_19840_amd import Solver
+    _say("depth criterion", dl)
+    h = math.pi
+    w = SteadyWave(0.2, depth=h - dl, steps=16)
+    x = np.arange(64) * 2 * math.pi / 64
+    eta, _, phi, V = w.surface(x)
+    s = Solver(64, 1, 2 * math.pi, 1.0, np.full((1, 64), h - dl), h_ref=h, device=gpu, mode="sa")
+    W, st, _ = s.vertical_velocity(torch.tensor(eta[None], dtype=torch.float64, device=gpu),
+                                   torch.tensor(phi[None], dtype=torch.float64, device=gpu))
+    Wg = W.cpu().numpy().reshape(64)
+    o = OSolver(Grid(64, 1, 2 * math.pi), np.full((1, 64), h - dl), h_ref=h, mode="sa")
+    Wo, _ = o.vertical_velocity(eta[None], phi[None])
+    assert np.abs(Wg - Wo[0]).max() <= 1e-10 * np.abs(Wo).max()
+    err = math.sqrt(np.mean((Wg - V) ** 2)) / math.sqrt(np.mean(V ** 2))
+    assert (err < 0.1) if dl <= 2.4 else (err > 0.09), err

@@ -94,3 +94,36 @@ def test_anderson_mixing_converges_where_relaxed_sweeps_stall():
     assert ir.status != 0 and ia.status == 0
     err = np.abs(Wa[0] - V).max() / np.abs(V).max()
     assert 1e-5 < err < 1e-4
+
+
+# -- Sec. 5: the depth criterion, Stokes waves in finite depth d = h - delta --
+def _sec5_error(eps, dl, h=math.pi):
+    w = SteadyWave(2 * eps, depth=h - dl, steps=16)
+    x = np.arange(64) * 2 * math.pi / 64
+    eta, eta_x, phi, V = w.surface(x)
+    assert np.abs(V + w.c * eta_x).max() < 1e-4 * np.abs(V).max()   # the reference itself, far below the errors measured
+    s = Solver(Grid(64, 1, 2 * math.pi), np.full((1, 64), h - dl), h_ref=h, mode="sa")
+    W, _ = s.vertical_velocity(eta[None], phi[None])
+    return math.sqrt(np.mean((W[0] - V) ** 2)) / math.sqrt(np.mean(V ** 2))
+
+
+def test_finite_depth_steady_wave_speed():
+    # linear limit c^2 = tanh(kd), and the bed is a streamline
+    w = SteadyWave(0.002, depth=1.0)
+    assert abs(w.c ** 2 - math.tanh(1.0)) < 1e-5
+    x = np.linspace(0, 2 * math.pi, 50)
+    j = np.arange(1, w.N + 1)
+    Zs, _ = w._basis(np.full(x.shape, -1.0), j)
+    assert np.abs((Zs * np.cos(np.outer(x, j))) @ w.B).max() < 1e-14
+
+
+def test_depth_criterion_of_section_5():
+    # relative RMS error of V (order 7, h = pi, 64 points per wavelength) against
+    # the exact wave over the depth d = h - delta: below 10% for delta <= 2.4
+    # whatever the steepness, growing with delta, and above it at eps = 0.1,
+    # delta = 2.6 (the paper's example beyond the criterion)
+    e1 = [_sec5_error(0.1, dl) for dl in (1.0, 1.8, 2.4, 2.6)]
+    e2 = [_sec5_error(0.2, dl) for dl in (1.0, 1.8, 2.4)]
+    assert all(e < 0.1 for e in e1[:3] + e2), (e1, e2)
+    assert all(e1[i] < e1[i + 1] for i in range(3)) and all(e2[i] < e2[i + 1] for i in range(2))
+    assert e1[3] > 0.09 and e1[3] > 2 * e1[2], e1
