@@ -68,3 +68,29 @@ def test_depth_criterion_on_the_gpu(gpu, dl):
     assert np.abs(Wg - Wo[0]).max() <= 1e-10 * np.abs(Wo).max()
     err = math.sqrt(np.mean((Wg - V) ** 2)) / math.sqrt(np.mean(V ** 2))
     assert (err < 0.1) if dl <= 2.4 else (err > 0.09), err
+
+
+@pytest.mark.parametrize("mode,accel,eps,bound", [("sa", None, 0.2, 2e-6), ("iter", None, 0.1, 3e-7),
+                                                   ("iter", "anderson", 0.1, 3e-7)])
+def test_steady_wave_returns_after_one_period_on_the_gpu(gpu, mode, accel, eps, bound):
+    # the GPU's step carries an exact deep-water Stokes wave through one period
+    # back onto itself, to the model's truncation (eps = 0.2, 7th order) or the
+    # time integrator's error (eps = 0.1, iteration to 1e-13); the relaxed
+    # iteration itself stalls on waves as steep as eps = 0.2
+    import torch
+    from oracle.fenton import SteadyWave
+    from paper_2310_19840_amd import Solver
+    _say("steady wave period", mode, accel)
+    w = SteadyWave(2 * eps)
+    x = np.arange(64) * 2 * math.pi / 64
+    eta, _, phi, _ = w.surface(x)
+    T = 2 * math.pi / w.c
+    s = Solver(64, 1, 2 * math.pi, 1.0, np.full((1, 64), 60.0), device=gpu, mode=mode, max_sweeps=200, accel=accel)
+    e = torch.tensor(eta[None], dtype=torch.float64, device=gpu)
+    p = torch.tensor(phi[None], dtype=torch.float64, device=gpu)
+    st, info = s.step(e, p, T / 64, 64, tol=1e-13)
+    assert st == 0
+    eg = e.cpu().numpy().reshape(64)
+    pg = p.cpu().numpy().reshape(64)
+    assert np.abs(eg - eta).max() < bound * np.abs(eta).max()
+    assert np.abs((pg - pg.mean()) - (phi - phi.mean())).max() < bound * np.abs(phi).max()

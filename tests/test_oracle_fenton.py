@@ -127,3 +127,33 @@ def test_depth_criterion_of_section_5():
     assert all(e < 0.1 for e in e1[:3] + e2), (e1, e2)
     assert all(e1[i] < e1[i + 1] for i in range(3)) and all(e2[i] < e2[i + 1] for i in range(2))
     assert e1[3] > 0.09 and e1[3] > 2 * e1[2], e1
+
+
+# -- time stepping against exact nonlinear waves: a steady wave returns after one period
+def _translate(eps, depth, n, mode="sa", href=60.0):
+    w = SteadyWave(2 * eps, depth=depth)
+    x = np.arange(64) * 2 * math.pi / 64
+    eta, _, phi, _ = w.surface(x)
+    T = 2 * math.pi / w.c
+    d = href if depth is None else depth
+    s = Solver(Grid(64, 1, 2 * math.pi), np.full((1, 64), d), mode=mode)
+    e, p, _ = s.step(eta[None], phi[None], T / n, n, tol=1e-13)
+    pm, p0 = p[0] - p[0].mean(), phi - phi.mean()   # the mean of phi_s drifts with the Bernoulli constant (a gauge)
+    return (np.abs(e[0] - eta).max() / np.abs(eta).max(), np.abs(pm - p0).max() / np.abs(p0).max())
+
+
+def test_steady_waves_return_after_one_period():
+    # deep water, eps = 0.1: the error is the time integrator's (RK4: ~16x per halving of dt)
+    a64, b64 = _translate(0.1, None, 64)
+    a128, b128 = _translate(0.1, None, 128)
+    assert a64 < 3e-7 and b64 < 3e-7 and a128 < 3e-8 and a64 / a128 > 8, (a64, a128)
+    # eps = 0.2 and 0.3: the model's own truncation sets the floor
+    a, b = _translate(0.2, None, 64)
+    assert a < 2e-6 and b < 2e-6
+    a, b = _translate(0.3, None, 64)
+    assert a < 3e-5 and b < 3e-5
+    # finite depth kd = 1 over the reference depth itself (delta = 0), and with the iteration
+    a, b = _translate(0.15, 1.0, 64)
+    assert a < 1e-6 and b < 1e-6
+    a, b = _translate(0.1, None, 64, mode="iter")
+    assert a < 3e-7 and b < 3e-7
