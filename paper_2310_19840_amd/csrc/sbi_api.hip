@@ -115,7 +115,6 @@ struct sbi_ctx {
     Ctl* ctl = nullptr;
     double* diag_partial = nullptr;
     double* aa_partial = nullptr;   // [batch][kAABlocks][kAASlots] inner-product partials
-    double* aa_w = nullptr;         // [batch][kAASlots] weights of the next iterate on the history
     void* part = nullptr;    // partial sums of grouped column passes
     int* cnt = nullptr;      // tile tickets of grouped column passes
     int col_C = 1;
@@ -399,8 +398,6 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
     p += al(sizeof(double) * 2 * 64 * batch);
     c->aa_partial = reinterpret_cast<double*>(p);
     p += al(sizeof(double) * kAASlots * kAABlocks * batch);
-    c->aa_w = reinterpret_cast<double*>(p);
-    p += al(sizeof(double) * kAASlots * batch);
     c->part = p;
     p += al((size_t)L.s_cmp * L.csz * batch * kMaxGroups * 4);
     c->cnt = reinterpret_cast<int*>(p);
@@ -543,7 +540,8 @@ struct ColBuilder {
         prod_stride.push_back(stride);
         return (int)prods.size() - 1;
     }
-    // widx >= 0: the input is scaled by the per-member device weight p.cin_w[widx]
+    // widx >= 0: the input is scaled by the Anderson weight of history slot
+    // widx, which the pass solves for itself (p.aa_partial must be set)
     int cin(const void* c, int widx = -1) {
         cins.push_back(c);
         cin_w.push_back(widx);
@@ -580,7 +578,10 @@ struct ColBuilder {
             p.hin_stride[i] = prod_stride[i];
         }
         for (int i = 0; i < p.ncin; ++i) p.cin[i] = cins[i];
-        for (int i = 0; i < kMaxCin; ++i) p.cin_widx[i] = (signed char)(i < p.ncin ? cin_w[i] : -1);
+        for (int i = 0; i < kMaxCin; ++i) {
+            p.cin_widx[i] = (signed char)(i < p.ncin ? cin_w[i] : -1);
+            if (p.cin_widx[i] >= kAASlots || (p.cin_widx[i] >= 0 && !p.aa_partial)) return false;
+        }
         for (auto& t : terms)
             if (t.src < 0) t.src = (short)(p.nprod + (-t.src - 1));
         std::stable_sort(terms.begin(), terms.end(), [](const ColTerm& a, const ColTerm& b) { return a.src < b.src; });
@@ -805,10 +806,10 @@ static sbi_status col_forcing(sbi_ctx* c) {
 }
 
 // Anderson mixing after the column pass of sweep n (which stored f_n and g_n
-// in the history ring): inner products and the weights of the next iterate,
-// then one column pass that forms x_(n+1) = sum_i w_i g_i from the history
-// (compact) and its inverse column transforms (V, grad phi_b) for the next row
-// pass
+// in the history ring): partial inner products, then one column pass whose
+// workgroups each solve for the weights w_i of the next iterate and form
+// x_(n+1) = sum_i w_i g_i from the history (compact) and its inverse column
+// transforms (V, grad phi_b) for the next row pass
 static sbi_status anderson_mix(sbi_ctx* c, int n) {
     const bool two_d = c->grid.ny > 1;
     const int k = std::min(n, kAADepth);
@@ -823,12 +824,10 @@ static sbi_status anderson_mix(sbi_ctx* c, int n) {
     }
     ap.partial = c->aa_partial;
     ap.nblk = kAABlocks;
-    ap.weights = c->aa_w;
-    c->st.launches += 2;
+    c->st.launches += 1;
     {
         ProfScope ps_(c, K_COL_OTHER);
         SBI_TRY(hip_ok(launch_aa_dot(c->fp64, ap, c->batch, c->stream)));
-        SBI_TRY(hip_ok(launch_aa_solve(c->fp64, ap, c->batch, c->stream)));
     }
     ColBuilder b(c->gd);
     for (int a = 0; a <= k; ++a) {
@@ -840,7 +839,10 @@ static sbi_status anderson_mix(sbi_ctx* c, int n) {
             b.term(sb, 1, 1.0, FN_ONE, 0, DV_NONE);
         }
     }
-    b.p.cin_w = c->aa_w;
+    // every workgroup of the pass adds the partials and solves for the weights
+    b.p.aa_partial = c->aa_partial;
+    b.p.aa_nblk = kAABlocks;
+    b.p.aa_sweep = n;
     b.cout(SRC_ACC0, CMP(C_VN));
     b.inv(SRC_ACC0, DV_NONE, HALF(H_GV));
     if (c->vd) {

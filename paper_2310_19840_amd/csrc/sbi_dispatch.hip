@@ -95,9 +95,6 @@ hipError_t launch_rk54(int fp64, const Rk54Params& p, int batch, hipStream_t s) 
 hipError_t launch_aa_dot(int fp64, const AaParams& p, int batch, hipStream_t s) {
     return fp64 ? launch_aa_dot_t<double>(p, batch, s) : launch_aa_dot_t<float>(p, batch, s);
 }
-hipError_t launch_aa_solve(int fp64, const AaParams& p, int batch, hipStream_t s) {
-    return fp64 ? launch_aa_solve_t<double>(p, batch, s) : launch_aa_solve_t<float>(p, batch, s);
-}
 hipError_t launch_diag(int fp64, const DiagParams& p, int batch, hipStream_t s) {
     return fp64 ? launch_diag_t<double>(p, batch, s) : launch_diag_t<float>(p, batch, s);
 }

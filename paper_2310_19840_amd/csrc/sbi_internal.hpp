@@ -97,8 +97,13 @@ struct ColParams {
     const void* hin[kMaxProd];
     long long hin_stride[kMaxProd];   // per-member stride override (0 = g.s_half)
     const void* cin[kMaxCin];
-    const double* cin_w;               // [batch][kAASlots] device weights of compact inputs (Anderson mixing)
-    signed char cin_widx[kMaxCin];     // weight index of each compact input, -1: none
+    signed char cin_widx[kMaxCin];     // Anderson weight (history slot) scaling each compact input, -1: none
+    // Anderson weights formed in the pass itself: when aa_partial is set, each
+    // workgroup adds the inner-product partials of sweep aa_sweep
+    // ([batch][aa_nblk][kAASlots]) and solves for the weights of the history
+    // slots; the first workgroup of a member stores the new Gram entries
+    const double* aa_partial;
+    int aa_nblk, aa_sweep;
     short toff[kMaxProd + kMaxCin + 1]; // terms sorted by source: [toff[s], toff[s+1])
     ColTerm term[kMaxTerms];
     int relax_prev[2];                 // compact-input index of the previous iterate of acc0/acc1, -1 none

@@ -966,6 +966,123 @@ __device__ __forceinline__ V col_source(const ColParams& p, int src, int q, cons
     return cadd(pv, cscale(d, R(omega)));
 }
 
+// Anderson mixing of the relaxed sweep: from dots[i] = <F_i, f_n> over the
+// ring slots of sweep n, complete the Gram matrix of the residual history,
+// solve the normal equations of min |f_n - sum_a gamma_a dF_a|,
+// dF_a = F_(a+1) - F_a over the history in sweep order (regularised by
+// 1e-12 trace / k; gamma = 0 when they fail), and write to w the weights of
+// x_(n+1) = g_n - sum_a gamma_a (G_(a+1) - G_a) on the history slots.
+// commit: store the new Gram entries (row and column of slot n) in the
+// control block.  The entries read here that are not in that row and column
+// were stored by earlier sweeps, so workgroups of one pass that solve
+// side by side while one of them commits read the same values.
+static __device__ void aa_weights(Ctl* ctl, int n, const double* dots, double* w, bool commit) {
+    const int s = n % kAASlots, k = n < kAADepth ? n : kAADepth;
+    // history slots in sweep order: H[a] holds sweep n - k + a
+    int H[kAASlots];
+    for (int a = 0; a <= k; ++a) H[a] = (n - k + a) % kAASlots;
+    double Mg[kAASlots][kAASlots];
+    for (int a = 0; a < kAASlots; ++a)
+        for (int b = 0; b < kAASlots; ++b) Mg[a][b] = ctl->aa_gram[a][b];
+    for (int a = 0; a <= k; ++a) {
+        Mg[s][H[a]] = dots[H[a]];
+        Mg[H[a]][s] = dots[H[a]];
+        if (commit) {
+            ctl->aa_gram[s][H[a]] = dots[H[a]];
+            ctl->aa_gram[H[a]][s] = dots[H[a]];
+        }
+    }
+    double gam[kAADepth];
+    for (int a = 0; a < kAADepth; ++a) gam[a] = 0.0;
+    if (k > 0) {
+        double A[kAADepth][kAADepth], y[kAADepth];
+        auto M = [&](int a, int b) { return Mg[H[a]][H[b]]; };
+        double tr = 0.0;
+        for (int a = 0; a < k; ++a) {
+            for (int b = 0; b < k; ++b) A[a][b] = M(a + 1, b + 1) - M(a + 1, b) - M(a, b + 1) + M(a, b);
+            y[a] = M(a + 1, k) - M(a, k);
+            tr += A[a][a];
+        }
+        const double reg = 1e-12 * tr / k;
+        for (int a = 0; a < k; ++a) A[a][a] += reg;
+        // Gaussian elimination with partial pivoting (k <= kAADepth)
+        bool ok = tr > 0.0 && isfinite(tr);
+        for (int c = 0; c < k && ok; ++c) {
+            int pv = c;
+            for (int r = c + 1; r < k; ++r)
+                if (fabs(A[r][c]) > fabs(A[pv][c])) pv = r;
+            if (!(fabs(A[pv][c]) > 0.0)) {
+                ok = false;
+                break;
+            }
+            if (pv != c) {
+                for (int b = 0; b < k; ++b) {
+                    const double t = A[c][b];
+                    A[c][b] = A[pv][b];
+                    A[pv][b] = t;
+                }
+                const double t = y[c];
+                y[c] = y[pv];
+                y[pv] = t;
+            }
+            for (int r = c + 1; r < k; ++r) {
+                const double f = A[r][c] / A[c][c];
+                for (int b = c; b < k; ++b) A[r][b] -= f * A[c][b];
+                y[r] -= f * y[c];
+            }
+        }
+        if (ok) {
+            for (int c = k - 1; c >= 0; --c) {
+                double v = y[c];
+                for (int b = c + 1; b < k; ++b) v -= A[c][b] * gam[b];
+                gam[c] = v / A[c][c];
+            }
+            for (int a = 0; a < k; ++a) ok = ok && isfinite(gam[a]);
+        }
+        if (!ok)
+            for (int a = 0; a < kAADepth; ++a) gam[a] = 0.0;
+    }
+    // x_(n+1) = G_k - sum_a gamma_a (G_(a+1) - G_a): weights of the history slots
+    for (int i = 0; i < kAASlots; ++i) w[i] = 0.0;
+    for (int a = 0; a <= k; ++a) {
+        double c = a == k ? 1.0 : 0.0;
+        if (a < k) c += gam[a];
+        if (a >= 1) c -= gam[a - 1];
+        w[H[a]] = c;
+    }
+}
+
+// the weights inside a column-pass workgroup: the partials of the member are
+// added in a fixed order (strided per thread, then across the wavefront, then
+// wavefront by wavefront), so every workgroup forms the same weights; s_red
+// holds kAASlots reals per wavefront (<= 16), s_w receives the weights
+static __device__ void aa_block_weights(const ColParams& p, Ctl* ctl, int mem, bool commit, double* s_red, double* s_w) {
+    double d[kAASlots];
+#pragma unroll
+    for (int i = 0; i < kAASlots; ++i) d[i] = 0.0;
+    const double* part = p.aa_partial + (long long)mem * p.aa_nblk * kAASlots;
+    for (int b = threadIdx.x; b < p.aa_nblk; b += blockDim.x)
+#pragma unroll
+        for (int i = 0; i < kAASlots; ++i) d[i] += part[b * kAASlots + i];
+#pragma unroll
+    for (int i = 0; i < kAASlots; ++i)
+        for (int off = 32; off > 0; off >>= 1) d[i] += __shfl_xor(d[i], off, 64);
+    const int wv = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < kAASlots; ++i) s_red[wv * kAASlots + i] = d[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot[kAASlots];
+        for (int i = 0; i < kAASlots; ++i) tot[i] = 0.0;
+        const int nw = (blockDim.x + 63) / 64;
+        for (int v = 0; v < nw; ++v)
+            for (int i = 0; i < kAASlots; ++i) tot[i] += s_red[v * kAASlots + i];
+        aa_weights(ctl, p.aa_sweep, tot, s_w, commit);
+    }
+    __syncthreads();
+}
+
 // product lanes of a column-pass workgroup: independent thread groups that
 // transform alternate products of the same columns (more waves per CU to hide
 // memory latency); their partial sums are combined through LDS
@@ -1000,6 +1117,8 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
 
     double omega = 1.0;
     if (!col_control(p, ctl, blockIdx.x == 0 && grp == 0 && t == 0, &omega)) return;
+    __shared__ double s_aa[(16 + 1) * kAASlots];  // wavefront sums, then the Anderson weights
+    if (p.aa_partial) aa_block_weights(p, ctl, mem, blockIdx.x == 0 && grp == 0, s_aa, s_aa + 16 * kAASlots);
 
     Twid<V, N, E> twc;
     twc.load(twY, j);
@@ -1076,7 +1195,7 @@ k_col(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         if (live && !prod) {
             const V* Ci = static_cast<const V*>(p.cin[jb - nps]) + mem * g.s_cmp + (long long)mx * g.Ky;
             const int wi = p.cin_widx[jb - nps];
-            const R cw = wi >= 0 ? R(p.cin_w[mem * kAASlots + wi]) : R(1);
+            const R cw = wi >= 0 ? R(s_aa[16 * kAASlots + wi]) : R(1);
 #pragma unroll
             for (int q = 0; q < E; ++q) v[q] = crow[q] >= 0 ? cscale(Ci[crow[q]], cw) : cx<V>(R(0), R(0));
         }
@@ -1312,6 +1431,8 @@ k_colp(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
     // the decision is the same in every thread (the leader's header updates
     // cannot change it), so the workgroup returns as a whole
     if (!col_control(p, ctl, blockIdx.x == 0 && t == 0, &omega)) return;
+    __shared__ double s_aa[(16 + 1) * kAASlots];  // wavefront sums, then the Anderson weights
+    if (p.aa_partial) aa_block_weights(p, ctl, mem, blockIdx.x == 0, s_aa, s_aa + 16 * kAASlots);
     __syncthreads();
     const R kxr = R(kx);
 
@@ -1352,7 +1473,7 @@ k_colp(const ColParams p, const typename cplx_of<R>::type* __restrict__ twY) {
         } else {
             const V* Ci = static_cast<const V*>(p.cin[jb - nps]) + mem * g.s_cmp + (long long)mx * g.Ky;
             const int wi = p.cin_widx[jb - nps];
-            const R cw = wi >= 0 ? R(p.cin_w[mem * kAASlots + wi]) : R(1);
+            const R cw = wi >= 0 ? R(s_aa[16 * kAASlots + wi]) : R(1);
 #pragma unroll
             for (int q = 0; q < E; ++q) v[q] = crow[q] >= 0 ? cscale(Ci[crow[q]], cw) : cx<V>(R(0), R(0));
         }
@@ -1737,12 +1858,8 @@ __global__ void k_rk54(const Rk54Params p) {
 // in ring slot n mod kAASlots; k_aa_dot forms per-workgroup partial sums of
 // <F_i, f_n> over the k + 1 = min(n, kAADepth) + 1 history slots (real inner
 // product of the real fields: half-spectrum modes weighted 2 for m_x > 0).
-// k_aa_solve adds them in workgroup order, completes the Gram matrix of the
-// history, solves the normal equations of min |f_n - sum_a gamma_a dF_a|,
-// dF_a = F_(a+1) - F_a over the history in sweep order (regularised by
-// 1e-12 trace / k; gamma = 0 when they fail), and leaves the weights of
-// x_(n+1) = g_n - sum_a gamma_a (G_(a+1) - G_a) on the history slots, which
-// the next column pass applies to its compact inputs.
+// The column pass that forms the next iterate adds them and solves for its
+// weights in every workgroup (aa_block_weights).
 template <typename R>
 __global__ void __launch_bounds__(256) k_aa_dot(const AaParams p) {
     using V = typename cplx_of<R>::type;
@@ -1794,101 +1911,6 @@ __global__ void __launch_bounds__(256) k_aa_dot(const AaParams p) {
     if (threadIdx.x == 0)
 #pragma unroll
         for (int i = 0; i < kAASlots; ++i) p.partial[((long long)mem * p.nblk + blockIdx.x) * kAASlots + i] = red[i][0];
-}
-
-// one workgroup per member
-template <typename R>
-__global__ void __launch_bounds__(256) k_aa_solve(const AaParams p) {
-    __shared__ double red[kAASlots][256];
-    const int mem = blockIdx.x;
-    Ctl* ctl = p.ctl + mem;
-    if (ctl->done) return;
-    const int n = p.sweep, s = n % kAASlots, k = n < kAADepth ? n : kAADepth;
-#pragma unroll
-    for (int i = 0; i < kAASlots; ++i) {
-        double v = 0.0;
-        for (int b = threadIdx.x; b < p.nblk; b += blockDim.x) v += p.partial[((long long)mem * p.nblk + b) * kAASlots + i];
-        red[i][threadIdx.x] = v;
-    }
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-#pragma unroll
-            for (int i = 0; i < kAASlots; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x != 0) return;
-    // history slots in sweep order: H[a] holds sweep n - k + a
-    int H[kAASlots];
-    for (int a = 0; a <= k; ++a) H[a] = (n - k + a) % kAASlots;
-    double Mg[kAASlots][kAASlots];
-    for (int a = 0; a < kAASlots; ++a)
-        for (int b = 0; b < kAASlots; ++b) Mg[a][b] = ctl->aa_gram[a][b];
-    for (int a = 0; a <= k; ++a) {
-        Mg[s][H[a]] = red[H[a]][0];
-        Mg[H[a]][s] = red[H[a]][0];
-        ctl->aa_gram[s][H[a]] = red[H[a]][0];
-        ctl->aa_gram[H[a]][s] = red[H[a]][0];
-    }
-    double gam[kAADepth];
-    for (int a = 0; a < kAADepth; ++a) gam[a] = 0.0;
-    if (k > 0) {
-        double A[kAADepth][kAADepth], y[kAADepth];
-        auto M = [&](int a, int b) { return Mg[H[a]][H[b]]; };
-        double tr = 0.0;
-        for (int a = 0; a < k; ++a) {
-            for (int b = 0; b < k; ++b) A[a][b] = M(a + 1, b + 1) - M(a + 1, b) - M(a, b + 1) + M(a, b);
-            y[a] = M(a + 1, k) - M(a, k);
-            tr += A[a][a];
-        }
-        const double reg = 1e-12 * tr / k;
-        for (int a = 0; a < k; ++a) A[a][a] += reg;
-        // Gaussian elimination with partial pivoting (k <= kAADepth)
-        bool ok = tr > 0.0 && isfinite(tr);
-        for (int c = 0; c < k && ok; ++c) {
-            int pv = c;
-            for (int r = c + 1; r < k; ++r)
-                if (fabs(A[r][c]) > fabs(A[pv][c])) pv = r;
-            if (!(fabs(A[pv][c]) > 0.0)) {
-                ok = false;
-                break;
-            }
-            if (pv != c) {
-                for (int b = 0; b < k; ++b) {
-                    const double t = A[c][b];
-                    A[c][b] = A[pv][b];
-                    A[pv][b] = t;
-                }
-                const double t = y[c];
-                y[c] = y[pv];
-                y[pv] = t;
-            }
-            for (int r = c + 1; r < k; ++r) {
-                const double f = A[r][c] / A[c][c];
-                for (int b = c; b < k; ++b) A[r][b] -= f * A[c][b];
-                y[r] -= f * y[c];
-            }
-        }
-        if (ok) {
-            for (int c = k - 1; c >= 0; --c) {
-                double v = y[c];
-                for (int b = c + 1; b < k; ++b) v -= A[c][b] * gam[b];
-                gam[c] = v / A[c][c];
-            }
-            for (int a = 0; a < k; ++a) ok = ok && isfinite(gam[a]);
-        }
-        if (!ok)
-            for (int a = 0; a < kAADepth; ++a) gam[a] = 0.0;
-    }
-    // x_(n+1) = G_k - sum_a gamma_a (G_(a+1) - G_a): weights of the history slots
-    double* wout = p.weights + (long long)mem * kAASlots;
-    for (int i = 0; i < kAASlots; ++i) wout[i] = 0.0;
-    for (int a = 0; a <= k; ++a) {
-        double c = a == k ? 1.0 : 0.0;
-        if (a < k) c += gam[a];
-        if (a >= 1) c -= gam[a - 1];
-        wout[H[a]] = c;
-    }
 }
 
 template <typename R>
@@ -2084,10 +2106,6 @@ template <> hipError_t launch_rk54_t<Real>(const Rk54Params& p, int batch, hipSt
 template <> hipError_t launch_aa_dot_t<Real>(const AaParams& p, int batch, hipStream_t s) {
     dim3 block(256), grid((unsigned)p.nblk, batch);
     hipLaunchKernelGGL(k_aa_dot<Real>, grid, block, 0, s, p);
-    return hipGetLastError();
-}
-template <> hipError_t launch_aa_solve_t<Real>(const AaParams& p, int batch, hipStream_t s) {
-    hipLaunchKernelGGL(k_aa_solve<Real>, dim3(batch), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 template <> hipError_t launch_diag_t<Real>(const DiagParams& p, int batch, hipStream_t s) {

@@ -157,9 +157,9 @@ struct Rk54Params {
     int nblk;
 };
 
-// Anderson mixing of the relaxed sweep (iteration mode): inner products of the
-// residual history (k_aa_dot) and the weights of the next iterate on the
-// history of relaxed sweeps (k_aa_solve)
+// Anderson mixing of the relaxed sweep (iteration mode): partial inner
+// products of the residual history (k_aa_dot), which the next column pass
+// turns into the weights of the next iterate
 struct AaParams {
     GridDev g;
     Ctl* ctl;
@@ -169,7 +169,6 @@ struct AaParams {
     const void* fb[kAASlots];
     double* partial;           // [batch][nblk][kAASlots]
     int nblk;
-    double* weights;           // [batch][kAASlots]: x_(n+1) = sum_i weights[i] g_i
 };
 
 struct DiagParams {
@@ -203,7 +202,6 @@ template <typename R> hipError_t launch_col_t(const ColParams&, int, const Twidd
 template <typename R> hipError_t launch_rk_t(const RkParams&, int, hipStream_t);
 template <typename R> hipError_t launch_rk54_t(const Rk54Params&, int, hipStream_t);
 template <typename R> hipError_t launch_aa_dot_t(const AaParams&, int, hipStream_t);
-template <typename R> hipError_t launch_aa_solve_t(const AaParams&, int, hipStream_t);
 template <typename R> hipError_t launch_diag_t(const DiagParams&, int, hipStream_t);
 
 hipError_t launch_row_fwd(int fp64, const RowFwdParams& p, int batch, const Twiddles& tw, hipStream_t s);
@@ -218,7 +216,6 @@ hipError_t launch_col(int fp64, const ColParams& p, int batch, const Twiddles& t
 hipError_t launch_rk(int fp64, const RkParams& p, int batch, hipStream_t s);
 hipError_t launch_rk54(int fp64, const Rk54Params& p, int batch, hipStream_t s);
 hipError_t launch_aa_dot(int fp64, const AaParams& p, int batch, hipStream_t s);
-hipError_t launch_aa_solve(int fp64, const AaParams& p, int batch, hipStream_t s);
 hipError_t launch_diag(int fp64, const DiagParams& p, int batch, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* ctl, int batch, int slots, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
