@@ -39,6 +39,7 @@ struct CtlSlots {
 };
 constexpr int kAADepth = 2;              // residual differences kept by the Anderson mixing
 constexpr int kAASlots = kAADepth + 1;   // history ring of residuals and relaxed sweeps
+constexpr int kAADotThreads = 512;       // threads of an inner-product workgroup (<= 1024)
 
 struct Ctl {
     int done;                                // iteration finished (any reason)

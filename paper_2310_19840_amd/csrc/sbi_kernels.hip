@@ -1861,9 +1861,9 @@ __global__ void k_rk54(const Rk54Params p) {
 // The column pass that forms the next iterate adds them and solves for its
 // weights in every workgroup (aa_block_weights).
 template <typename R>
-__global__ void __launch_bounds__(256) k_aa_dot(const AaParams p) {
+__global__ void __launch_bounds__(kAADotThreads) k_aa_dot(const AaParams p) {
     using V = typename cplx_of<R>::type;
-    __shared__ double red[kAASlots][256];
+    __shared__ double red[kAASlots][16];
     const int mem = blockIdx.y;
     const Ctl* ctl = p.ctl + mem;
     if (ctl->done) return;
@@ -1899,18 +1899,21 @@ __global__ void __launch_bounds__(256) k_aa_dot(const AaParams p) {
             }
         }
     }
+    // across the wavefront, then wavefront by wavefront (<= 16 of them)
 #pragma unroll
-    for (int i = 0; i < kAASlots; ++i) red[i][threadIdx.x] = d[i];
+    for (int i = 0; i < kAASlots; ++i)
+        for (int off = 32; off > 0; off >>= 1) d[i] += __shfl_xor(d[i], off, 64);
+    const int wv = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < kAASlots; ++i) red[i][wv] = d[i];
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-#pragma unroll
-            for (int i = 0; i < kAASlots; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + w];
-        __syncthreads();
+    if (threadIdx.x < kAASlots) {
+        double v = 0.0;
+        const int nw = (blockDim.x + 63) / 64;
+        for (int w = 0; w < nw; ++w) v += red[threadIdx.x][w];
+        p.partial[((long long)mem * p.nblk + blockIdx.x) * kAASlots + threadIdx.x] = v;
     }
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int i = 0; i < kAASlots; ++i) p.partial[((long long)mem * p.nblk + blockIdx.x) * kAASlots + i] = red[i][0];
 }
 
 template <typename R>
@@ -2104,7 +2107,7 @@ template <> hipError_t launch_rk54_t<Real>(const Rk54Params& p, int batch, hipSt
     return hipGetLastError();
 }
 template <> hipError_t launch_aa_dot_t<Real>(const AaParams& p, int batch, hipStream_t s) {
-    dim3 block(256), grid((unsigned)p.nblk, batch);
+    dim3 block(kAADotThreads), grid((unsigned)p.nblk, batch);
     hipLaunchKernelGGL(k_aa_dot<Real>, grid, block, 0, s, p);
     return hipGetLastError();
 }
