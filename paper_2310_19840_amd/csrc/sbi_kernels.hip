@@ -966,6 +966,15 @@ __device__ __forceinline__ V col_source(const ColParams& p, int src, int q, cons
     return cadd(pv, cscale(d, R(omega)));
 }
 
+// entry i of a register array, with i known only at run time: a chain of
+// selects, so the array is never placed in memory
+static __device__ __forceinline__ double aa_sel(const double (&v)[kAASlots], int i) {
+    double r = 0.0;
+#pragma unroll
+    for (int q = 0; q < kAASlots; ++q) r = q == i ? v[q] : r;
+    return r;
+}
+
 // Anderson mixing of the relaxed sweep: from dots[i] = <F_i, f_n> over the
 // ring slots of sweep n, complete the Gram matrix of the residual history,
 // solve the normal equations of min |f_n - sum_a gamma_a dF_a|,
@@ -976,80 +985,78 @@ __device__ __forceinline__ V col_source(const ColParams& p, int src, int q, cons
 // control block.  The entries read here that are not in that row and column
 // were stored by earlier sweeps, so workgroups of one pass that solve
 // side by side while one of them commits read the same values.
-static __device__ void aa_weights(Ctl* ctl, int n, const double* dots, double* w, bool commit) {
+// dots and w are indexed with compile-time indices only (registers); the
+// history slots in sweep order are H_a = (n - k + a) mod kAASlots, a <= k
+static __device__ void aa_weights(Ctl* ctl, int n, const double (&dots)[kAASlots], double (&w)[kAASlots],
+                                  bool commit) {
+    static_assert(kAADepth == 2, "the elimination below is written out for two residual differences");
     const int s = n % kAASlots, k = n < kAADepth ? n : kAADepth;
-    // history slots in sweep order: H[a] holds sweep n - k + a
-    int H[kAASlots];
-    for (int a = 0; a <= k; ++a) H[a] = (n - k + a) % kAASlots;
-    double Mg[kAASlots][kAASlots];
-    for (int a = 0; a < kAASlots; ++a)
-        for (int b = 0; b < kAASlots; ++b) Mg[a][b] = ctl->aa_gram[a][b];
-    for (int a = 0; a <= k; ++a) {
-        Mg[s][H[a]] = dots[H[a]];
-        Mg[H[a]][s] = dots[H[a]];
-        if (commit) {
-            ctl->aa_gram[s][H[a]] = dots[H[a]];
-            ctl->aa_gram[H[a]][s] = dots[H[a]];
+    const int H0 = (n - k) % kAASlots, H1 = (n - k + 1) % kAASlots, H2 = (n - k + 2) % kAASlots;
+    // the new row and column of slot s (over the slots of the history) come
+    // from dots; the other entries were stored by earlier sweeps
+    if (commit) {
+#pragma unroll
+        for (int i = 0; i < kAASlots; ++i) {
+            const bool hi = i == H0 || (k >= 1 && i == H1) || (k >= 2 && i == H2);
+            if (hi) {
+                ctl->aa_gram[s][i] = aa_sel(dots, i);
+                ctl->aa_gram[i][s] = aa_sel(dots, i);
+            }
         }
     }
-    double gam[kAADepth];
-    for (int a = 0; a < kAADepth; ++a) gam[a] = 0.0;
-    if (k > 0) {
-        double A[kAADepth][kAADepth], y[kAADepth];
-        auto M = [&](int a, int b) { return Mg[H[a]][H[b]]; };
-        double tr = 0.0;
-        for (int a = 0; a < k; ++a) {
-            for (int b = 0; b < k; ++b) A[a][b] = M(a + 1, b + 1) - M(a + 1, b) - M(a, b + 1) + M(a, b);
-            y[a] = M(a + 1, k) - M(a, k);
-            tr += A[a][a];
-        }
-        const double reg = 1e-12 * tr / k;
-        for (int a = 0; a < k; ++a) A[a][a] += reg;
-        // Gaussian elimination with partial pivoting (k <= kAADepth)
+    auto M = [&](int a, int b) {
+        const int r = a == 0 ? H0 : (a == 1 ? H1 : H2), c = b == 0 ? H0 : (b == 1 ? H1 : H2);
+        if (r == s) return aa_sel(dots, c);
+        if (c == s) return aa_sel(dots, r);
+        return ctl->aa_gram[r][c];
+    };
+    double gam0 = 0.0, gam1 = 0.0;
+    if (k == 1) {
+        double A00 = M(1, 1) - M(1, 0) - M(0, 1) + M(0, 0);
+        const double y0 = M(1, 1) - M(0, 1);
+        const double tr = A00;
+        A00 += 1e-12 * tr;
+        const bool ok = tr > 0.0 && isfinite(tr) && fabs(A00) > 0.0;
+        gam0 = ok ? y0 / A00 : 0.0;
+        if (!isfinite(gam0)) gam0 = 0.0;
+    } else if (k == 2) {
+        double A00 = M(1, 1) - M(1, 0) - M(0, 1) + M(0, 0);
+        double A01 = M(1, 2) - M(1, 1) - M(0, 2) + M(0, 1);
+        double A10 = M(2, 1) - M(2, 0) - M(1, 1) + M(1, 0);
+        double A11 = M(2, 2) - M(2, 1) - M(1, 2) + M(1, 1);
+        double y0 = M(1, 2) - M(0, 2), y1 = M(2, 2) - M(1, 2);
+        const double tr = A00 + A11;
+        const double reg = 1e-12 * tr / 2;
+        A00 += reg;
+        A11 += reg;
         bool ok = tr > 0.0 && isfinite(tr);
-        for (int c = 0; c < k && ok; ++c) {
-            int pv = c;
-            for (int r = c + 1; r < k; ++r)
-                if (fabs(A[r][c]) > fabs(A[pv][c])) pv = r;
-            if (!(fabs(A[pv][c]) > 0.0)) {
-                ok = false;
-                break;
-            }
-            if (pv != c) {
-                for (int b = 0; b < k; ++b) {
-                    const double t = A[c][b];
-                    A[c][b] = A[pv][b];
-                    A[pv][b] = t;
-                }
-                const double t = y[c];
-                y[c] = y[pv];
-                y[pv] = t;
-            }
-            for (int r = c + 1; r < k; ++r) {
-                const double f = A[r][c] / A[c][c];
-                for (int b = c; b < k; ++b) A[r][b] -= f * A[c][b];
-                y[r] -= f * y[c];
-            }
+        // Gaussian elimination with partial pivoting on the first column
+        if (fabs(A10) > fabs(A00)) {
+            double t = A00; A00 = A10; A10 = t;
+            t = A01; A01 = A11; A11 = t;
+            t = y0; y0 = y1; y1 = t;
+        }
+        ok = ok && fabs(A00) > 0.0;
+        if (ok) {
+            const double f = A10 / A00;
+            A11 -= f * A01;
+            y1 -= f * y0;
+            ok = fabs(A11) > 0.0;
         }
         if (ok) {
-            for (int c = k - 1; c >= 0; --c) {
-                double v = y[c];
-                for (int b = c + 1; b < k; ++b) v -= A[c][b] * gam[b];
-                gam[c] = v / A[c][c];
-            }
-            for (int a = 0; a < k; ++a) ok = ok && isfinite(gam[a]);
+            gam1 = y1 / A11;
+            gam0 = (y0 - A01 * gam1) / A00;
+            ok = isfinite(gam0) && isfinite(gam1);
         }
-        if (!ok)
-            for (int a = 0; a < kAADepth; ++a) gam[a] = 0.0;
+        if (!ok) gam0 = gam1 = 0.0;
     }
     // x_(n+1) = G_k - sum_a gamma_a (G_(a+1) - G_a): weights of the history slots
-    for (int i = 0; i < kAASlots; ++i) w[i] = 0.0;
-    for (int a = 0; a <= k; ++a) {
-        double c = a == k ? 1.0 : 0.0;
-        if (a < k) c += gam[a];
-        if (a >= 1) c -= gam[a - 1];
-        w[H[a]] = c;
-    }
+    const double c0 = k == 0 ? 1.0 : gam0;
+    const double c1 = k == 1 ? 1.0 - gam0 : gam1 - gam0;
+    const double c2 = 1.0 - gam1;
+#pragma unroll
+    for (int i = 0; i < kAASlots; ++i)
+        w[i] = i == H0 ? c0 : ((k >= 1 && i == H1) ? c1 : ((k >= 2 && i == H2) ? c2 : 0.0));
 }
 
 // the weights inside a column-pass workgroup: the partials of the member are
@@ -1073,12 +1080,16 @@ static __device__ void aa_block_weights(const ColParams& p, Ctl* ctl, int mem, b
         for (int i = 0; i < kAASlots; ++i) s_red[wv * kAASlots + i] = d[i];
     __syncthreads();
     if (threadIdx.x == 0) {
-        double tot[kAASlots];
+        double tot[kAASlots], w[kAASlots];
+#pragma unroll
         for (int i = 0; i < kAASlots; ++i) tot[i] = 0.0;
         const int nw = (blockDim.x + 63) / 64;
         for (int v = 0; v < nw; ++v)
+#pragma unroll
             for (int i = 0; i < kAASlots; ++i) tot[i] += s_red[v * kAASlots + i];
-        aa_weights(ctl, p.aa_sweep, tot, s_w, commit);
+        aa_weights(ctl, p.aa_sweep, tot, w, commit);
+#pragma unroll
+        for (int i = 0; i < kAASlots; ++i) s_w[i] = w[i];
     }
     __syncthreads();
 }
