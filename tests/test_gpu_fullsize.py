@@ -147,15 +147,18 @@ def test_fullsize_step_conserves_mass_and_energy(gpu):
     assert np.isfinite(eta.cpu().numpy()).all()
 
 
-def test_fullsize_batch_in_graph_equals_single_contexts(gpu):
+@pytest.mark.parametrize("accel", [None, "anderson"])
+def test_fullsize_batch_in_graph_equals_single_contexts(gpu, accel):
     # two 1024^2 members in one captured graph (the column pass then runs with
-    # a member index): each equals its own eager single-context run bit for bit
+    # a member index; with Anderson mixing each member's workgroups solve for
+    # that member's weights): each equals its own eager single-context run bit
+    # for bit
     import torch
     from paper_2310_19840_amd import Batch, Solver
     cfgs = [si.config_c5(seed=sd, n=1024) for sd in (0, 1)]
-    _say("1024^2 batch of two in a graph")
+    _say("1024^2 batch of two in a graph", accel)
     opts = [dict(nx=c["grid"].nx, ny=c["grid"].ny, lx=c["grid"].lx, ly=c["grid"].ly, depth=c["depth"],
-                 precision="fp64", mode="iter", max_sweeps=60, seed="prev") for c in cfgs]
+                 precision="fp64", mode="iter", max_sweeps=60, seed="prev", accel=accel) for c in cfgs]
     b = Batch(opts, device=gpu, graph=True)
     eb = [torch.tensor(c["eta"], dtype=torch.float64, device=gpu) for c in cfgs]
     pb = [torch.tensor(c["phi"], dtype=torch.float64, device=gpu) for c in cfgs]
@@ -164,7 +167,8 @@ def test_fullsize_batch_in_graph_equals_single_contexts(gpu):
     assert st == 0
     for i, c in enumerate(cfgs):
         g = c["grid"]
-        s = Solver(g.nx, g.ny, g.lx, g.ly, c["depth"], device=gpu, mode="iter", max_sweeps=60, seed="prev")
+        s = Solver(g.nx, g.ny, g.lx, g.ly, c["depth"], device=gpu, mode="iter", max_sweeps=60, seed="prev",
+                   accel=accel)
         e = torch.tensor(c["eta"][None], dtype=torch.float64, device=gpu)
         ph = torch.tensor(c["phi"][None], dtype=torch.float64, device=gpu)
         _, si_ = s.step(e, ph, dt, 1, tol=1e-8)
