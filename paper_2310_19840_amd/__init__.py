@@ -120,9 +120,10 @@ class Solver:
         seed = self._dev(w_seed, "w_seed") if w_seed is not None else None
         st = self.lib.sbi_vertical_velocity(self.ctx, self._dev(eta, "eta"), self._dev(phi_s, "phi_s"), hp,
                                             float(tol), seed, self._dev(out, "w_out"), infos)
+        res = [(i.sweeps, i.status, i.residual, i.omega) for i in infos]
         if st < 0:
-            raise SBIError(st, "sbi_vertical_velocity")
-        return out, st, [(i.sweeps, i.status, i.residual, i.omega) for i in infos]
+            raise SBIError(st, "sbi_vertical_velocity", res)
+        return out, st, res
 
     def step(self, eta, phi_s, dt, n, tol=1e-10, t=0.0):
         s = _lib.sbi_state(self._dev(eta, "eta"), self._dev(phi_s, "phi_s"), float(t))

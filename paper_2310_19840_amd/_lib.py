@@ -146,6 +146,7 @@ def status_string(code: int) -> str:
 
 
 class SBIError(RuntimeError):
-    def __init__(self, code: int, where: str):
+    def __init__(self, code: int, where: str, info=None):
         super().__init__(f"{where}: {status_string(code)} ({code})")
         self.code = code
+        self.info = info  # per-member solve info the call reported with the error, if any

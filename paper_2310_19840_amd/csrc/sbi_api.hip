@@ -962,7 +962,9 @@ static sbi_status launch_sweep(sbi_ctx* c, const void* eta_phys, int n, double t
     b.p.tol = tol;
     if (b.p.nacc < (c->vd ? 2 : 1)) b.p.nacc = c->vd ? 2 : 1;
     SBI_TRY(run_col(c, b, K_COL_SWEEP));
-    if (!aa || !rp.products) return SBI_OK;
+    // the next iterate is mixed after every sweep but the last, also when the
+    // sweep forms no products (order 1: T is the constant b_V)
+    if (!aa || n >= M) return SBI_OK;
     return anderson_mix(c, n);
 }
 

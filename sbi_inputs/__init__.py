@@ -15,6 +15,7 @@ from .generators import (  # noqa: F401
     undulating_bars_depth,
     random_bumps_depth,
     band_limited_random,
+    narrowband_random,
     config_c1,
     config_c2,
     config_c3,

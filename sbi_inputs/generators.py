@@ -82,6 +82,28 @@ def band_limited_random(grid: GridSpec, seed: int, amp: float = 1.0, slope: floa
     return f
 
 
+def narrowband_random(grid: GridSpec, seed: int, amp: float = 1.0, k0: float = 1.0, width: float = 0.5):
+    """Random real field inside the retained rectangle whose modal amplitudes
+    fall off as exp(-((|k| - k0)/width)^2) around |k| = k0 (in 1/length units,
+    so the content sits near k0 whatever the domain size), with uniform random
+    phases; scaled so that max |f| = amp."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ny, nx = grid.ny, grid.nx
+    c = np.zeros((ny, nx), dtype=np.complex128)
+    mx_max, my_max = grid.mx_max, grid.my_max
+    for my in range(-my_max, my_max + 1):
+        for mx in range(-mx_max, mx_max + 1):
+            if mx == 0 and my == 0:
+                continue
+            kx = 2 * math.pi * mx / grid.lx
+            ky = 0.0 if ny == 1 else 2 * math.pi * my / grid.ly
+            a = math.exp(-((math.hypot(kx, ky) - k0) / width) ** 2)
+            ph = rng.uniform(0, 2 * math.pi)
+            c[my % ny, mx % nx] += a * np.exp(1j * ph)
+    f = np.real(np.fft.ifft2(c))
+    return f * (amp / np.abs(f).max())
+
+
 def jonswap_crossing_sea(grid: GridSpec, h: float, seed: int, gamma: float = 3.3,
                          hs_half: float = 0.1, directions_deg=(20.0, -20.0), s: float = 10.0,
                          sigma_a: float = 0.07, sigma_b: float = 0.09):

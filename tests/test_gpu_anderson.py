@@ -197,3 +197,28 @@ def test_anderson_steep_steady_wave_matches_oracle(gpu):
     assert st == 0 and oi.status == 0
     assert abs(info[0][0] - oi.sweeps) <= 2, (info[0][0], oi.sweeps)
     assert _rel(W.cpu().numpy().reshape(Wo.shape), Wo) < 1e-10
+
+
+def test_order_one_user_seed_is_mixed(gpu):
+    """Order 1 (T is the constant k tanh(kh) phi_hat, no products): a user seed
+    away from it converges in two mixed sweeps, as in the oracle."""
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    nx, ny = 64, 32
+    lx, ly = 8 * math.pi, 4 * math.pi
+    gs = si.GridSpec(nx, ny, lx, ly)
+    eta, phi = si.jonswap_crossing_sea(gs, 1.0, seed=13, hs_half=0.03)
+    seed = si.narrowband_random(gs, 99, amp=0.1)
+    X, Y = np.meshgrid(gs.x(), gs.y())
+    depth = 1.0 - 0.15 * np.exp(-((X - lx / 2) ** 2 + (Y - ly / 2) ** 2) / 20.0)
+    for vd in (False, True):
+        d = depth if vd else np.full((ny, nx), 1.0)
+        o = OSolver(Grid(nx, ny, lx, ly), d, order=1, mode="iter", accel="anderson", max_sweeps=50)
+        Wo, oi = o.vertical_velocity(eta, phi, tol=1e-12, seed=seed)
+        s = Solver(nx, ny, lx, ly, d, device=gpu, order=1, mode="iter", accel="anderson", seed="user",
+                   max_sweeps=50)
+        dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=gpu)
+        W, st, info = s.vertical_velocity(dev(eta), dev(phi), tol=1e-12, w_seed=dev(seed[None]))
+        assert oi.sweeps == 2 and info[0][0] == 2 and info[0][1] == 0, (oi.sweeps, info)
+        assert np.abs(W.cpu().numpy()[0] - Wo).max() <= 1e-12 * np.abs(Wo).max()

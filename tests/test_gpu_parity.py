@@ -284,3 +284,77 @@ def test_relaxation_zone_matches_oracle(gpu):
     eo, po, _ = o.step(cfg["eta"], cfg["phi"], dt, cfg["steps"])
     assert np.abs(eo).max() > 1e-4
     assert _rel(e.cpu().numpy().reshape(eo.shape), eo) < 1e-10
+
+
+def _steep_1d():
+    nx = 64
+    lx = 4 * math.pi
+    x = np.arange(nx) * lx / nx
+    eta = (0.15 * np.cos(2 * math.pi * 3 * x / lx) + 0.02 * np.cos(2 * math.pi * 11 * x / lx + 1.0))[None]
+    phi = (0.5 * np.sin(2 * math.pi * 3 * x / lx) + 0.1 * np.sin(2 * math.pi * 7 * x / lx))[None]
+    return nx, lx, eta, phi
+
+
+@pytest.mark.parametrize("accel", [None, "anderson"])
+def test_divergence_status_matches_oracle(gpu, accel):
+    """Plain sweeps (relax off) on a crest beyond the contraction range: the
+    residual first falls, then grows from round-off in the short waves; both
+    sides stop with SBI_ERR_DIVERGED at the same sweep (or, mixed, reach the
+    same outcome)."""
+    import torch
+    from paper_2310_19840_amd import SBIError, _lib
+    Grid, Solver = _oracle()
+    nx, lx, eta, phi = _steep_1d()
+    depth = np.full((1, nx), 1.0)
+    _say("divergence", accel)
+    o = Solver(Grid(nx, 1, lx), depth, mode="iter", max_sweeps=500, relax=False, accel=accel)
+    Wo, oi = o.vertical_velocity(eta, phi, tol=1e-12)
+    s = _solver(gpu, nx, 1, lx, 1.0, depth, mode="iter", max_sweeps=500, relax=False, accel=accel)
+    if oi.status < 0:
+        with pytest.raises(SBIError) as ex:
+            s.vertical_velocity(_t(eta, torch.float64, gpu), _t(phi, torch.float64, gpu), tol=1e-12)
+        assert ex.value.code == oi.status == _lib.SBI_ERR_DIVERGED
+        assert ex.value.info[0][0] == oi.sweeps, (ex.value.info, oi.sweeps)
+    else:
+        W, st, info = s.vertical_velocity(_t(eta, torch.float64, gpu), _t(phi, torch.float64, gpu), tol=1e-12)
+        assert info[0][0] == oi.sweeps and info[0][1] == oi.status
+        assert _rel(W.cpu().numpy()[0], Wo) < 1e-10
+    if accel is None:
+        assert oi.status == _lib.SBI_ERR_DIVERGED
+    # a step that meets a diverged solve reports the error and leaves the state untouched
+    if oi.status < 0:
+        e = _t(eta, torch.float64, gpu)
+        p = _t(phi, torch.float64, gpu)
+        e0, p0 = e.clone(), p.clone()
+        with pytest.raises(SBIError) as ex:
+            s.step(e, p, 0.05, 1, tol=1e-12)
+        assert ex.value.code == _lib.SBI_ERR_DIVERGED
+        assert torch.equal(e, e0) and torch.equal(p, p0)
+
+
+def test_depth_criterion_warning_matches_oracle(gpu):
+    """Sec. 5: k_band max|delta| > 2.4 makes sbi_init warn (context usable),
+    exactly where the oracle sets its depth warning."""
+    import torch
+    from paper_2310_19840_amd import _lib
+    Grid, Solver = _oracle()
+    nx = 64
+    lx = 8 * math.pi
+    g = Grid(nx, 1, lx)
+    x = np.arange(nx) * lx / nx
+    bump = np.exp(-((x - lx / 2) / 2.0) ** 2)[None]
+    eta = 0.01 * np.cos(2 * math.pi * 4 * x / lx)[None]
+    phi = 0.05 * np.sin(2 * math.pi * 4 * x / lx)[None]
+    _say("depth criterion")
+    for kd, warn in ((2.3, False), (2.5, True)):
+        depth = 2.0 - (kd / g.kband) * bump
+        o = Solver(g, depth, h_ref=2.0, mode="sa")
+        assert o.depth_warning == warn
+        s = _solver(gpu, nx, 1, lx, 1.0, depth, h_ref=2.0, mode="sa")
+        assert s.init_status == (_lib.SBI_WARN_DEPTH_CRITERION if warn else _lib.SBI_OK)
+        W, st, _ = s.vertical_velocity(_t(eta, torch.float64, gpu), _t(phi, torch.float64, gpu))
+        Wo, _ = o.vertical_velocity(eta, phi)
+        assert _rel(W.cpu().numpy()[0], Wo) < 1e-12
+        # a new depth passed to the solve re-checks the criterion
+        W, st, _ = s.vertical_velocity(_t(eta, torch.float64, gpu), _t(phi, torch.float64, gpu), h=depth)
+        assert st == (_lib.SBI_WARN_DEPTH_CRITERION if warn else _lib.SBI_OK)
