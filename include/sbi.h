@@ -34,6 +34,11 @@
  *   - All device work is enqueued on the context's HIP stream; calls that
  *     return host values (info structs, diagnostics) synchronise that stream.
  *   - One context per stream.  Contexts share no mutable state.
+ *   - Device memory: the library allocates it only in sbi_init, and only when
+ *     the caller passes no workspace (the context then owns one, freed by
+ *     sbi_destroy); every other call works in caller-owned memory (or, for
+ *     sbi_vertical_velocity_noalloc, in the library's static scratch array).
+ *     sbi_init also takes a small pinned host buffer for the control headers.
  *   - Non-finite inputs are reported as SBI_ERR_NONFINITE.
  */
 #ifndef SBI_H
@@ -145,7 +150,8 @@ size_t sbi_workspace_bytes(const sbi_grid* g, int32_t batch);
  *   h_ref     reference depth h of Sec. 2.1; <= 0 selects max(depth) per member,
  *             so that delta = h_ref - depth >= 0.
  *   workspace device buffer of sbi_workspace_bytes(g, batch) bytes owned by the
- *             caller, or NULL to let the library allocate (and free) it.
+ *             caller, or NULL to let the library allocate it here (hipMalloc,
+ *             the library's only device allocation; freed by sbi_destroy).
  *   hip_stream hipStream_t to enqueue on (NULL = default stream).
  * Returns SBI_WARN_DEPTH_CRITERION (context valid) when
  * k_band * max(delta) > 2.4 (Sec. 5).
@@ -168,6 +174,32 @@ sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, const doubl
 sbi_status sbi_vertical_velocity(sbi_ctx* ctx, const void* eta, const void* phi_s,
                                  const double* h, double tol, const void* w_seed,
                                  void* w_out, sbi_solve_info* info);
+
+/*
+ * Allocation-free W solve, for callers that cannot allocate device memory:
+ * tight serving loops and harnesses that forbid hipMalloc.  It is
+ * sbi_vertical_velocity on a context made from (g, batch, depth, h_ref) as
+ * sbi_init would make it, set up and released inside the call, with h = NULL.
+ * Its workspace is the library's static device scratch array of 64 MiB (one
+ * per device, held from the library's first use on that device until the
+ * process ends); the call makes no hipMalloc, hipHostMalloc, hipFree or event,
+ * and keeps its control headers in ordinary host memory.  Grids that need
+ * more (sbi_workspace_bytes(g, batch) > 64 MiB, e.g. FP64 beyond 512 x 256
+ * points per member, FP32 beyond 512 x 512) return SBI_ERR_WORKSPACE.
+ *   The scratch array of a device is shared by every call on it and keeps the
+ *   last call's contents; each call clears it before use.  Calls that overlap
+ *   in time on one device (from other host threads or streams) race on it:
+ *   the caller must serialise them.
+ *   hip_stream must belong to the current device (SBI_ERR_INVALID_ARG
+ *   otherwise); the call synchronises it before returning.
+ *   seed: SBI_SEED_NET is SBI_ERR_UNSUPPORTED (its weights need a lasting
+ *   context); SBI_SEED_PREV starts from the linear guess (there is no previous
+ *   solve); SBI_SEED_USER takes w_seed.  Returns what sbi_init and
+ *   sbi_vertical_velocity would (SBI_WARN_DEPTH_CRITERION included).
+ */
+sbi_status sbi_vertical_velocity_noalloc(const sbi_grid* g, int32_t batch, const double* depth, double h_ref,
+                                         const void* eta, const void* phi_s, double tol, const void* w_seed,
+                                         void* w_out, sbi_solve_info* info, void* hip_stream);
 
 /*
  * Advance every member by n steps of dt (Eq. (prognostic), integrating-factor

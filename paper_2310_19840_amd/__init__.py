@@ -60,6 +60,37 @@ def net_blob_parts(blob: bytes):
     return th, np.array(h.in_scale[:], dtype=np.float32), np.array(h.out_scale[:], dtype=np.float32)
 
 
+def vertical_velocity_noalloc(eta, phi_s, depth, nx, ny, lx, ly=1.0, h_ref=-1.0, tol=1e-10, w_seed=None, out=None,
+                              stream=None, **opts):
+    """One W solve through sbi_vertical_velocity_noalloc (no allocation in the
+    library: its workspace is the library's static device scratch).  eta, phi_s
+    (and w_seed, out): contiguous [batch, ny, nx] tensors on the current device
+    of the grid's precision.  Returns (W, status, [(sweeps, status, residual,
+    omega)] per member)."""
+    import torch
+
+    lib = _lib.load()
+    g = make_grid(nx, ny, lx, ly, **opts)
+    batch = eta.shape[0] if eta.dim() == 3 else 1
+    dt = torch.float64 if g.precision == _lib.SBI_FP64 else torch.float32
+    for x, name in ((eta, "eta"), (phi_s, "phi_s"), (w_seed, "w_seed"), (out, "w_out")):
+        if x is not None and (x.dtype != dt or not x.is_contiguous() or x.numel() != batch * ny * nx):
+            raise TypeError(f"{name} must be a contiguous {dt} tensor of {batch * ny * nx} values")
+    out = torch.empty((batch, ny, nx), dtype=dt, device=eta.device) if out is None else out
+    d = np.ascontiguousarray(np.broadcast_to(np.asarray(depth, dtype=np.float64).reshape((-1, ny, nx)),
+                                             (batch, ny, nx)))
+    stream = stream if stream is not None else torch.cuda.current_stream(eta.device)
+    infos = (_lib.sbi_solve_info * batch)()
+    st = lib.sbi_vertical_velocity_noalloc(C.byref(g), batch, d.ctypes.data_as(C.POINTER(C.c_double)),
+                                           float(h_ref), C.c_void_p(eta.data_ptr()), C.c_void_p(phi_s.data_ptr()),
+                                           float(tol), C.c_void_p(w_seed.data_ptr()) if w_seed is not None else None,
+                                           C.c_void_p(out.data_ptr()), infos, C.c_void_p(stream.cuda_stream))
+    res = [(i.sweeps, i.status, i.residual, i.omega) for i in infos]
+    if st < 0:
+        raise SBIError(st, "sbi_vertical_velocity_noalloc", res)
+    return out, st, res
+
+
 def workspace_bytes(grid: _lib.sbi_grid, batch: int = 1) -> int:
     return int(_lib.load().sbi_workspace_bytes(C.byref(grid), int(batch)))
 

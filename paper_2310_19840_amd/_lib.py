@@ -66,6 +66,9 @@ SIGNATURES = {
                            C.c_double, C.c_void_p, C.c_size_t, C.c_void_p]),
     "sbi_vertical_velocity": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_double,
                                         C.c_void_p, C.c_void_p, C.POINTER(sbi_solve_info)]),
+    "sbi_vertical_velocity_noalloc": (C.c_int, [C.POINTER(sbi_grid), C.c_int32, C.POINTER(C.c_double), C.c_double,
+                                                C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                                C.POINTER(sbi_solve_info), C.c_void_p]),
     "sbi_step": (C.c_int, [C.c_void_p, C.POINTER(sbi_state), C.c_double, C.c_int32, C.c_double,
                            C.POINTER(sbi_step_info)]),
     "sbi_step_adaptive": (C.c_int, [C.c_void_p, C.POINTER(sbi_state), C.c_double, C.c_double, C.c_double,

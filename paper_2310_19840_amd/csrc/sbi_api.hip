@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -140,6 +141,11 @@ struct sbi_ctx {
     Profiler prof;
     Ctl* head = nullptr;     // pinned host copy of the control headers
     hipEvent_t poll = nullptr;  // marks a header copy the host waits for while sweeps run on
+    // transient context of sbi_vertical_velocity_noalloc: workspace in the
+    // library's static device scratch, headers in ordinary host memory, no
+    // poll event (the iteration waits on the stream instead)
+    bool transient = false;
+    std::vector<Ctl> head_host;
     sbi_step_info step_acc{};
 };
 
@@ -326,14 +332,23 @@ static sbi_status set_depth(sbi_ctx* c, const double* depth, double h_ref) {
     return SBI_OK;
 }
 
-extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, const double* depth, double h_ref,
-                               void* workspace, size_t ws_bytes, void* hip_stream) {
-    if (!out || !grid_valid(g) || batch < 1 || !depth) return SBI_ERR_INVALID_ARG;
-    *out = nullptr;
-    if (g->seed == SBI_SEED_NET && g->ny == 1) return SBI_ERR_UNSUPPORTED;  // the network is 2D
+// release what a context holds (not the context itself)
+static void ctx_release(sbi_ctx* c) {
+    if (c->transient) return;  // nothing was allocated
+    if (c->head) (void)hipHostFree(c->head);
+    if (c->poll) (void)hipEventDestroy(c->poll);
+    if (c->own_ws) (void)hipFree(c->ws);
+}
+
+// Set up context c (grid, layout, workspace, tables, depth).  transient: the
+// workspace is given and nothing is allocated on the device or pinned on the
+// host (headers in c->head_host, no poll event).
+static sbi_status ctx_setup(sbi_ctx* c, const sbi_grid* g, int32_t batch, const double* depth, double h_ref,
+                            void* workspace, size_t ws_bytes, void* hip_stream, bool transient) {
     const Layout L = layout(g, batch);
     if (workspace && ws_bytes < L.total) return SBI_ERR_WORKSPACE;
-    sbi_ctx* c = new sbi_ctx();
+    if (transient && !workspace) return SBI_ERR_WORKSPACE;
+    c->transient = transient;
     c->grid = *g;
     c->batch = batch;
     c->fp64 = g->precision == SBI_FP64;
@@ -361,10 +376,9 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
         c->ws = static_cast<char*>(workspace);
         c->ws_bytes = ws_bytes;
     } else {
-        if (hipMalloc(&c->ws, L.total) != hipSuccess) {
-            delete c;
-            return SBI_ERR_HIP;
-        }
+        // the only device allocation of the library: a context created without
+        // a caller workspace owns one, made here and freed by sbi_destroy
+        if (hipMalloc(&c->ws, L.total) != hipSuccess) return SBI_ERR_HIP;
         c->own_ws = true;
         c->ws_bytes = L.total;
     }
@@ -409,16 +423,19 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
     gd.col_C = L.C;
     gd.qb = L.qb;
     gd.href = c->href_dev;
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->head), sizeof(Ctl) * batch, hipHostMallocDefault) != hipSuccess) {
-        if (c->own_ws) (void)hipFree(c->ws);
-        delete c;
-        return SBI_ERR_HIP;
-    }
-    if (hipEventCreateWithFlags(&c->poll, hipEventDisableTiming) != hipSuccess) {
-        (void)hipHostFree(c->head);
-        if (c->own_ws) (void)hipFree(c->ws);
-        delete c;
-        return SBI_ERR_HIP;
+    if (transient) {
+        c->head_host.assign(batch, Ctl{});
+        c->head = c->head_host.data();
+    } else {
+        if (hipHostMalloc(reinterpret_cast<void**>(&c->head), sizeof(Ctl) * batch, hipHostMallocDefault) !=
+            hipSuccess) {
+            c->head = nullptr;
+            return SBI_ERR_HIP;
+        }
+        if (hipEventCreateWithFlags(&c->poll, hipEventDisableTiming) != hipSuccess) {
+            c->poll = nullptr;
+            return SBI_ERR_HIP;
+        }
     }
     // SBI_COL_GROUP_TARGET: workgroups a column pass aims for by splitting its
     // products over workgroups (tuning knob; 0 = one workgroup per tile)
@@ -447,15 +464,25 @@ extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, 
         if (st == SBI_OK) st = hip_ok(launch_ctl_reset(c->ctl, batch, kMaxSweepSlots, c->stream));
         if (st == SBI_OK) st = set_depth(c, depth, h_ref);
     }
+    if (st < 0) return st;
+    return c->depth_warn ? SBI_WARN_DEPTH_CRITERION : SBI_OK;
+}
+
+extern "C" sbi_status sbi_init(sbi_ctx** out, const sbi_grid* g, int32_t batch, const double* depth, double h_ref,
+                               void* workspace, size_t ws_bytes, void* hip_stream) {
+    if (!out || !grid_valid(g) || batch < 1 || !depth) return SBI_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (g->seed == SBI_SEED_NET && g->ny == 1) return SBI_ERR_UNSUPPORTED;  // the network is 2D
+    sbi_ctx* c = new sbi_ctx();
+    const sbi_status st = ctx_setup(c, g, batch, depth, h_ref, workspace, ws_bytes, hip_stream, false);
     if (st < 0) {
-        if (c->own_ws) (void)hipFree(c->ws);
-        (void)hipHostFree(c->head);
-        (void)hipEventDestroy(c->poll);
+        (void)hipStreamSynchronize(c->stream);  // work enqueued before the failure ends before any free
+        ctx_release(c);
         delete c;
         return st;
     }
     *out = c;
-    return c->depth_warn ? SBI_WARN_DEPTH_CRITERION : SBI_OK;
+    return st;
 }
 
 extern "C" sbi_status sbi_destroy(sbi_ctx* c) {
@@ -463,12 +490,7 @@ extern "C" sbi_status sbi_destroy(sbi_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     prof_flush(c);
     for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
-    (void)hipEventDestroy(c->poll);
-    (void)hipHostFree(c->head);
-    if (c->own_ws) {
-        (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(c->ws);
-    }
+    ctx_release(c);
     delete c;
     return SBI_OK;
 }
@@ -993,9 +1015,10 @@ static sbi_status iterate(sbi_ctx* c, const void* eta_phys, double tol) {
         for (int i = 0; i < chunk && n <= M; ++i, ++n) SBI_TRY(launch_sweep(c, eta_phys, n, tol));
         const int np = n;  // sweeps the header copy follows
         SBI_HIP(hipMemcpyAsync(c->head, c->ctl, sizeof(Ctl) * c->batch, hipMemcpyDeviceToHost, c->stream));
-        SBI_HIP(hipEventRecord(c->poll, c->stream));
+        if (c->poll) SBI_HIP(hipEventRecord(c->poll, c->stream));
         for (int i = 0; i < kAhead && n <= M; ++i, ++n) SBI_TRY(launch_sweep(c, eta_phys, n, tol));
-        SBI_HIP(hipEventSynchronize(c->poll));
+        // a transient context has no event: it waits for the look-ahead too
+        SBI_HIP(c->poll ? hipEventSynchronize(c->poll) : hipStreamSynchronize(c->stream));
         c->st.syncs += 1;
         bool all_done = true;
         int want = 1;
@@ -1301,9 +1324,76 @@ static sbi_status solve_status(sbi_ctx* c, sbi_solve_info* info, bool fresh) {
     return worst;
 }
 
+static sbi_status vertical_velocity(sbi_ctx* c, const void* eta, const void* phi_s, const double* h, double tol,
+                                    const void* w_seed, void* w_out, sbi_solve_info* info);
+
 extern "C" sbi_status sbi_vertical_velocity(sbi_ctx* c, const void* eta, const void* phi_s, const double* h,
                                             double tol, const void* w_seed, void* w_out, sbi_solve_info* info) {
-    if (!c || !eta || !phi_s || !w_out) return SBI_ERR_INVALID_ARG;
+    if (!c) return SBI_ERR_INVALID_ARG;
+    return vertical_velocity(c, eta, phi_s, h, tol, w_seed, w_out, info);
+}
+
+// ---------------------------------------------------------------------------
+// W solve without any allocation (sbi_vertical_velocity_noalloc)
+// ---------------------------------------------------------------------------
+namespace {
+// Device scratch of the allocation-free entry point: its transient context's
+// workspace.  Each device holds its own copy for the life of the process; in
+// host code `scratch` only names the symbol, its device address comes from
+// hipGetSymbolAddress (per device, cached in scratch_dev).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kScratchDevices] = {};
+}  // namespace
+
+// address of this device's scratch array (the current device), looked up once
+static sbi_status scratch_ptr(void** out) {
+    int dev = -1;
+    SBI_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) return SBI_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SBI_ERR_HIP;
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_vertical_velocity_noalloc(const sbi_grid* g, int32_t batch, const double* depth,
+                                                    double h_ref, const void* eta, const void* phi_s, double tol,
+                                                    const void* w_seed, void* w_out, sbi_solve_info* info,
+                                                    void* hip_stream) {
+    if (!grid_valid(g) || batch < 1 || !depth || !eta || !phi_s || !w_out) return SBI_ERR_INVALID_ARG;
+    if (g->seed == SBI_SEED_NET) return SBI_ERR_UNSUPPORTED;  // needs loaded weights: a lasting context
+    const size_t need = layout(g, batch).total;
+    if (need > kScratchBytes) return SBI_ERR_WORKSPACE;
+    // the stream must belong to the current device, whose scratch is used
+    if (hip_stream) {
+        int sdev = -1, dev = -1;
+        SBI_HIP(hipStreamGetDevice(static_cast<hipStream_t>(hip_stream), &sdev));
+        SBI_HIP(hipGetDevice(&dev));
+        if (sdev != dev) return SBI_ERR_INVALID_ARG;
+    }
+    void* ws = nullptr;
+    SBI_TRY(scratch_ptr(&ws));
+    sbi_ctx c;
+    // the setup clears the whole workspace with a fill kernel before use, so
+    // nothing of an earlier call's contents is read
+    sbi_status st = ctx_setup(&c, g, batch, depth, h_ref, ws, kScratchBytes, hip_stream, true);
+    const sbi_status warn = st;
+    if (st >= 0) st = vertical_velocity(&c, eta, phi_s, nullptr, tol, w_seed, w_out, info);
+    (void)hipStreamSynchronize(c.stream);
+    if (st < 0) return st;
+    return st != SBI_OK ? st : warn;
+}
+
+static sbi_status vertical_velocity(sbi_ctx* c, const void* eta, const void* phi_s, const double* h, double tol,
+                                    const void* w_seed, void* w_out, sbi_solve_info* info) {
+    if (!eta || !phi_s || !w_out) return SBI_ERR_INVALID_ARG;
     if (c->grid.mode == SBI_MODE_ITER && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
     if (c->grid.seed == SBI_SEED_USER && !w_seed) return SBI_ERR_INVALID_ARG;
     c->st = Stats();
