@@ -293,8 +293,10 @@ def config_c2(case: int = 1, nx: int = 4096, steps: int = 20000):
     phi = np.zeros((1, nx))
     lam = 2 * math.pi
     relax = dict(a=ka, k=1.0, omega=om, gen_len=2 * lam, abs_len=3 * lam, ramp_periods=3.0)
+    # the low-pass filter the paper applies at every step of its tank runs
+    # (beta1 = 8, beta2 = 30, wavenumbers in units of the incident one)
     return dict(grid=g, depth=depth, eta=eta, phi=phi, dt=T / 64, steps=steps, period=T,
-                mode="sa", tol=0.0, precision="fp64", h_ref=h0, relax=relax)
+                mode="sa", tol=0.0, precision="fp64", h_ref=h0, relax=relax, filter_beta=(8.0, 30.0))
 
 
 def config_c3(seed: int = 3, n: int = 512):
