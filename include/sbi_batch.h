@@ -17,6 +17,11 @@
  * solve return at once; sweep statistics are accumulated on the device.  A
  * learned seed (SBI_SEED_NET) that fails is reported, not redone.
  *
+ * Nothing a batch step computes depends on the state time t (each member's
+ * t is only advanced by n*dt): time-dependent forcing -- the wave tank's
+ * pressures and relaxation zones of sbi.h -- is not available to ensembles,
+ * which is what lets a captured graph be replayed at any later time.
+ *
  * Conventions are those of sbi.h.
  */
 #ifndef SBI_BATCH_H
@@ -56,6 +61,10 @@ sbi_status sbi_batch_step(sbi_batch* b, sbi_state* states, double dt, int32_t n,
 /* Load the learned warm start (sbi_net.h blob) into every group whose seed is
    SBI_SEED_NET; SBI_ERR_INVALID_ARG if the blob is rejected. */
 sbi_status sbi_batch_net_load(sbi_batch* b, const void* weights, size_t bytes);
+
+/* Load the learned history layer (sbi_net_hist_load) into every group whose
+   seed is SBI_SEED_NET. */
+sbi_status sbi_batch_net_hist_load(sbi_batch* b, int32_t taps, int32_t bins, double dk, const float* w);
 
 /* Number of member groups and, per group (g < groups), its member count and
    the column-pass split the autotuner chose (0: none). */

@@ -11,7 +11,9 @@
  * A context with seed SBI_SEED_NET uses it for solves that have no previous
  * solve to start from (the first one, and any after a failed one); later
  * solves start from the SBI_SEED_PREV seed, which carries the previous
- * converged nonlinear parts and is the better start in time stepping.
+ * converged nonlinear parts -- or, in fixed-step time stepping once the
+ * learned history layer is loaded and has K solves behind it, from that
+ * layer's prediction (below).
  * The iteration itself, and its residual test, are unchanged: the seed affects
  * the number of sweeps, never the converged answer.  When a solve started from the learned
  * seed fails (divergence, non-finite values) it is redone from the linear
@@ -100,6 +102,75 @@ sbi_status sbi_net_infer(sbi_ctx* ctx, const float* feat, const void* wlin, void
  * yet.
  */
 sbi_status sbi_last_correction(sbi_ctx* ctx, void* dv_out, void* dphib_out);
+
+/*
+ * Learned history layer (the second, spectral layer of the learned warm
+ * start).  In fixed-step stepping (sbi_step, sbi_batch_step: integrating-
+ * factor RK4, Sec. 2.2) each step makes four W solves, at stages s = 0..3.
+ * The nonlinear part of a converged solve is the pair of kept-mode spectra
+ *   N_V = V* - k tanh(kh) phi_hat,   N_B = phi_b - sech(kh) phi_hat
+ * (N_B only over a variable bed).  The layer predicts the nonlinear part of
+ * the solve at stage s from those of the K fixed-step solves before it
+ * (h_0 the most recent) through their backward differences
+ * d_q = sum_{j<=q} (-1)^j C(q, j) h_j, mode by mode:
+ *   pred_P(k) = sum_{q<K} w[P][s][b(k)][q] d_q,P(k),  b(k) = min(floor(|k|/dk), nb - 1),
+ * complex weights per part P (0: V, 1: phi_b), stage, radial bin and tap, and
+ * the iteration starts from V0 = k tanh(kh) phi_hat + pred_V, phi_b0 =
+ * sech(kh) phi_hat + pred_B.  Only successful fixed-step solves enter the
+ * history; any other solve of the context (sbi_vertical_velocity,
+ * sbi_diagnostics, sbi_step_adaptive) or a failed one empties it.  A solve
+ * started from the prediction that fails is redone from the linear guess
+ * (SBI_WARN_FALLBACK_USED), except inside captured ensembles (sbi_batch.h),
+ * which report the failure.  With w[.][.][.][0] = 1 and the other taps 0 the
+ * layer is the SBI_SEED_PREV seed; w = 1 for every q is Newton's backward-
+ * difference extrapolation one step ahead.
+ * Weights: host FP32 [2][4][nb][K][2] (re, im), sbi_net_hist_param_count()
+ * values, K <= SBI_HIST_MAX_TAPS, nb <= SBI_HIST_MAX_BINS.
+ * Training (on the device, per context): with training on, every fixed-step
+ * solve with a full history adds to an accumulator the gradient of its loss
+ *   L = sum_P sum_k c_k |pred_P - N_P|^2 / sum_k c_k |N_P|^2
+ * (kept modes, c_k = 1 at m_x = 0 else 2; parts with N_P = 0 skipped) with
+ * respect to the real and imaginary parts of its stage's weights (the
+ * weights it was seeded with), and the Gram matrices G = sum c conj(d) d^T / D
+ * of each (part, stage, bin).  Two optimisers: sbi_net_hist_adam (one Adam
+ * step with the mean accumulated gradient) and sbi_net_hist_newton (the
+ * Gauss-Newton step w <- w - (G + lam tr(G)/K I)^-1 gamma, gamma = gradient/2
+ * as the complex derivative; the loss is quadratic in w, so one step lands on
+ * the ridge-regularised least-squares weights of the accumulated solves).
+ */
+#define SBI_HIST_MAX_TAPS 8
+#define SBI_HIST_MAX_BINS 32
+
+/* FP32 values of a layer of `taps` taps and `bins` bins (0 when out of range). */
+int32_t sbi_net_hist_param_count(int32_t taps, int32_t bins);
+
+/* Load the layer into an SBI_SEED_NET context (weights copied; Adam moments
+   and the gradient accumulator cleared; history emptied).  dk > 0: bin width
+   in 1/length units.  Errors: SBI_ERR_INVALID_ARG. */
+sbi_status sbi_net_hist_load(sbi_ctx* ctx, int32_t taps, int32_t bins, double dk, const float* w);
+
+/* Accumulate the loss gradient of each later fixed-step solve (enable != 0). */
+sbi_status sbi_net_hist_train(sbi_ctx* ctx, int32_t enable);
+
+/* The accumulated sums since the last optimiser step: loss sum, solves, and
+   (each optional) the gradient sum, host double [param count], and the Gram
+   sums, host double [2][4][nb][K][K][2] (re, im). */
+sbi_status sbi_net_hist_gradient(sbi_ctx* ctx, double* loss_sum, int32_t* samples, double* grad_sum,
+                                 double* gram_sum);
+
+/* One Gauss-Newton step (ridge lam >= 0, relative to tr(G)/K) of every
+   (part, stage, bin) with accumulated solves, by complex Cholesky in FP64;
+   clears the accumulators; loss_mean/samples as for sbi_net_hist_adam. */
+sbi_status sbi_net_hist_newton(sbi_ctx* ctx, double lam, double* loss_mean, int32_t* samples);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; FP64
+   moments, FP32 weights) with the mean accumulated gradient, which is then
+   cleared; loss_mean/samples (host, optional) describe the accumulated solves.
+   With no solve accumulated the weights are unchanged. */
+sbi_status sbi_net_hist_adam(sbi_ctx* ctx, float lr, double* loss_mean, int32_t* samples);
+
+/* Copy the layer's current weights to host w_out [param count]. */
+sbi_status sbi_net_hist_params(sbi_ctx* ctx, float* w_out);
 
 /*
  * Trainer: FP32 master parameters, Adam moments, the BF16-rounded copy used

@@ -32,3 +32,4 @@ from .sbi_oracle import (  # noqa: F401
 from . import dft  # noqa: F401
 from . import fenton  # noqa: F401
 from . import warmstart  # noqa: F401
+from . import history_seed  # noqa: F401

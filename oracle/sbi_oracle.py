@@ -119,7 +119,7 @@ class Solver:
     def __init__(self, grid: Grid, depth, h_ref: float | None = None, order: int = 7,
                  mode: str = "iter", max_sweeps: int = 64, relax: bool = True,
                  filter_beta=None, relaxation_zone=None, seed: str = "linear", net=None, wavemaker=None,
-                 accel: str | None = None, aa_depth: int = 2):
+                 accel: str | None = None, aa_depth: int = 2, hist=None):
         self.g = grid
         depth = np.asarray(depth, dtype=np.float64).reshape(grid.ny, grid.nx)
         if np.any(~np.isfinite(depth)) or np.any(depth <= 0):
@@ -165,11 +165,24 @@ class Solver:
         #             from the network's seed is redone from the linear guess.
         if seed not in ("linear", "prev", "net"):
             raise ValueError("seed must be 'linear', 'prev' or 'net'")
-        if seed == "net" and net is None:
-            raise ValueError("seed 'net' needs the network (theta, in_scale, out_scale)")
+        #   with hist = (K, nb, dk, theta): the learned history seed of
+        #             oracle.history_seed for fixed-step solves that have K
+        #             earlier fixed-step solves behind them (seed "net" only).
+        if seed == "net" and net is None and hist is None:
+            raise ValueError("seed 'net' needs the network (theta, in_scale, out_scale) or the history layer")
         self.seed = seed
         self.net = net
         self._prev = None
+        self.hist = None
+        if hist is not None:
+            from . import history_seed as hs
+            K, nb, dk, theta = hist
+            self.hist = dict(K=int(K), nb=int(nb), dk=float(dk), theta=np.asarray(theta, dtype=np.float32).copy(),
+                             b=hs.bins(grid, float(dk), int(nb)), c=hs.mode_weights(grid))
+        self._hist = []           # nonlinear parts (N_V, N_B) of the last fixed-step solves, newest first
+        self.hist_train = False   # accumulate the history layer's loss gradient over fixed-step solves
+        self._hist_acc = None     # sums over solves: grad (2, 4, nb, K), gram (2, 4, nb, K, K), loss, samples
+        self._hist_adam = None    # [m, v, step]
         # depth-validity criterion of Sec. 5: k |delta| < 2.4 at the largest wavenumber
         self.depth_warning = grid.kband * float(np.abs(self.delta).max()) > 2.4
 
@@ -413,20 +426,31 @@ class Solver:
         info.status = WARN_NOT_CONVERGED
         return Vn, Bh, info
 
-    def w_iter_hat(self, eta, ph, tol, seed_hat=None, seed_b_hat=None):
+    def w_iter_hat(self, eta, ph, tol, seed_hat=None, seed_b_hat=None, stage=None):
         """Iteration on the summed operator from the solver's seed (see the
         constructor), or from the seed spectrum seed_hat of V (and the
-        bottom-potential correction seed_b_hat added to its linear guess)."""
+        bottom-potential correction seed_b_hat added to its linear guess).
+        stage: the RK4 stage (0..3) of a fixed-step solve, None otherwise."""
+        from . import history_seed as hs
         g = self.g
         bV, bB = self.forcing(eta, ph)
         Vlin = g.k * self.T * ph
         Blin = self.S * ph
         w = self.relax_factor(eta)
         net = False
-        if seed_hat is not None:
+        H = self.hist
+        use_hist = (seed_hat is None and self.seed == "net" and H is not None and stage is not None
+                    and len(self._hist) >= H["K"])
+        if use_hist:
+            net = True
+            W = hs.to_complex(H["theta"], H["K"], H["nb"])
+            pV, pB = hs.predict(W, self._hist[:H["K"]], stage, H["b"])
+            Vh = Vlin + g.mask * pV
+            Bh = Blin if pB is None else Blin + g.mask * pB
+        elif seed_hat is not None:
             Vh = g.mask * seed_hat
             Bh = Blin if seed_b_hat is None else Blin + g.mask * seed_b_hat
-        elif self.seed == "net" and self._prev is None:
+        elif self.seed == "net" and self._prev is None and self.net is not None:
             net = True
             nV, nB = self._net_corrections(eta, ph)
             Vh = Vlin + g.MF(nV)
@@ -444,13 +468,68 @@ class Solver:
             info.fallback = True
         # nonlinear part of this solve: the seed of the next one
         self._prev = (Vn - Vlin, Bl - Blin) if info.status >= 0 else None
+        if self._prev is None or stage is None:
+            # only successful fixed-step solves form the history layer's input
+            self._hist = []
+        else:
+            part = (self._prev[0], None if self.flat else self._prev[1])
+            if H is not None and self.hist_train and len(self._hist) >= H["K"]:
+                W = hs.to_complex(H["theta"], H["K"], H["nb"])
+                loss, grad, gram = hs.loss_grad(W, self._hist[:H["K"]], part, stage, H["b"], H["c"], H["nb"])
+                if self._hist_acc is None:
+                    K_, nb_ = H["K"], H["nb"]
+                    self._hist_acc = dict(grad=np.zeros((2, hs.STAGES, nb_, K_), complex),
+                                          gram=np.zeros((2, hs.STAGES, nb_, K_, K_), complex), loss=0.0, n=0)
+                self._hist_acc["grad"][:, stage] += grad
+                self._hist_acc["gram"][:, stage] += gram
+                self._hist_acc["loss"] += loss
+                self._hist_acc["n"] += 1
+            self._hist.insert(0, part)
+            del self._hist[max(H["K"], 1) if H is not None else 1:]
         return Vn, info
 
+    def hist_adam(self, lr):
+        """One Adam step of the history layer with the mean gradient of the
+        solves accumulated since the last step; returns (mean loss, samples)."""
+        from . import history_seed as hs
+        H = self.hist
+        acc = self._hist_acc
+        if acc is None or acc["n"] == 0:
+            return 0.0, 0
+        g = acc["grad"] / acc["n"]
+        gflat = np.stack([g.real, g.imag], axis=-1).ravel()
+        if self._hist_adam is None:
+            self._hist_adam = [np.zeros_like(gflat), np.zeros_like(gflat), 0]
+        m, v, step = self._hist_adam
+        step += 1
+        th, m, v = hs.adam_step(H["theta"].astype(np.float64), m, v, gflat, step, lr)
+        H["theta"] = th.astype(np.float32)
+        self._hist_adam = [m, v, step]
+        out = (acc["loss"] / acc["n"], acc["n"])
+        self._hist_acc = None
+        return out
+
+    def hist_newton(self, lam=1e-9):
+        """Gauss-Newton step of the history layer on the solves accumulated
+        since the last step (oracle.history_seed.newton); returns (mean loss,
+        samples)."""
+        from . import history_seed as hs
+        H = self.hist
+        acc = self._hist_acc
+        if acc is None or acc["n"] == 0:
+            return 0.0, 0
+        W = hs.to_complex(H["theta"], H["K"], H["nb"])
+        W = hs.newton(W, acc["grad"], acc["gram"], lam)
+        H["theta"] = hs.to_flat(W).astype(np.float32)
+        out = (acc["loss"] / acc["n"], acc["n"])
+        self._hist_acc = None
+        return out
+
     # ------------------------------------------------------------------------
-    def solve_hat(self, eta, ph, tol=1e-10, seed_hat=None, seed_b_hat=None):
+    def solve_hat(self, eta, ph, tol=1e-10, seed_hat=None, seed_b_hat=None, stage=None):
         if self.mode == "sa":
             return self.w_sa_hat(eta, ph), SolveInfo(sweeps=0)
-        return self.w_iter_hat(eta, ph, tol, seed_hat, seed_b_hat)
+        return self.w_iter_hat(eta, ph, tol, seed_hat, seed_b_hat, stage)
 
     def vertical_velocity(self, eta, phi_s, tol=1e-10, seed=None, seed_b=None):
         """W = V at z = eta for physical (eta, phi_s); phi_s is band-limited by the mask.
@@ -505,14 +584,14 @@ class Solver:
         with np.errstate(divide="ignore", invalid="ignore"):
             return np.where(k2 > 0, num / np.where(k2 > 0, -k2, 1.0), 0.0)
 
-    def rhs(self, eh, ph, tol, t=0.0):
+    def rhs(self, eh, ph, tol, t=0.0, stage=None):
         """N = (V_hat - omega^2 phi_hat, MF{ (V + grad eta.grad phi)^2/(2(1+|grad eta|^2))
         - |grad phi|^2/2 - p_g } - p_d_hat)  for masked state spectra (eh, ph) at time t;
         the surface pressure p = p_g + p_d of the wave tank (zero without it)
         enters the dynamic condition beside the elevation."""
         g = self.g
         eta = g.ifft(eh)
-        Vh, info = self.solve_hat(eta, ph, tol)
+        Vh, info = self.solve_hat(eta, ph, tol, stage=stage)
         if info.status < 0:
             raise FloatingPointError(f"W solve failed with status {info.status}")
         V = g.ifft(Vh)
@@ -548,18 +627,18 @@ class Solver:
     def step_hat(self, eh, ph, dt, tol, stats=None, t=0.0):
         """One Lawson IF-RK4 step on masked spectra from time t."""
         h = dt
-        a = self.rhs(eh, ph, tol, t)
+        a = self.rhs(eh, ph, tol, t, stage=0)
         if stats is not None:
             stats.append(a[3])
         u2 = self.propagate(eh + h / 2 * a[0], ph + h / 2 * a[1], h / 2)
-        b = self.rhs(*u2, tol, t + h / 2)
+        b = self.rhs(*u2, tol, t + h / 2, stage=1)
         eh_h, ph_h = self.propagate(eh, ph, h / 2)
         u3 = (eh_h + h / 2 * b[0], ph_h + h / 2 * b[1])
-        c = self.rhs(*u3, tol, t + h / 2)
+        c = self.rhs(*u3, tol, t + h / 2, stage=2)
         ec, pc = self.propagate(c[0], c[1], h / 2)
         eh_f, ph_f = self.propagate(eh, ph, h)
         u4 = (eh_f + h * ec, ph_f + h * pc)
-        d = self.rhs(*u4, tol, t + h)
+        d = self.rhs(*u4, tol, t + h, stage=3)
         if stats is not None:
             stats.extend([b[3], c[3], d[3]])
         ea, pa = self.propagate(a[0], a[1], h)

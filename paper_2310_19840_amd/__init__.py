@@ -216,6 +216,60 @@ class Solver:
             raise SBIError(st, "sbi_net_infer")
         return out, outb
 
+    # -- learned history layer ------------------------------------------------
+    def hist_load(self, taps, bins, dk, w):
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float32).ravel())
+        if w.size != self.lib.sbi_net_hist_param_count(int(taps), int(bins)):
+            raise ValueError("wrong number of history-layer weights")
+        st = self.lib.sbi_net_hist_load(self.ctx, int(taps), int(bins), float(dk),
+                                        w.ctypes.data_as(C.POINTER(C.c_float)))
+        if st < 0:
+            raise SBIError(st, "sbi_net_hist_load")
+        self._hist_n = w.size
+        self._hist_shape = (int(taps), int(bins))
+
+    def hist_train(self, enable=True):
+        st = self.lib.sbi_net_hist_train(self.ctx, int(bool(enable)))
+        if st < 0:
+            raise SBIError(st, "sbi_net_hist_train")
+
+    def hist_gradient(self):
+        """(loss sum, solves, gradient sum, Gram sums) accumulated since the last optimiser step."""
+        loss = C.c_double()
+        n = C.c_int32()
+        g = np.zeros(self._hist_n, dtype=np.float64)
+        K, nb = self._hist_shape
+        gm = np.zeros(2 * 4 * nb * K * K * 2, dtype=np.float64)
+        st = self.lib.sbi_net_hist_gradient(self.ctx, C.byref(loss), C.byref(n),
+                                            g.ctypes.data_as(C.POINTER(C.c_double)),
+                                            gm.ctypes.data_as(C.POINTER(C.c_double)))
+        if st < 0:
+            raise SBIError(st, "sbi_net_hist_gradient")
+        return loss.value, n.value, g, gm
+
+    def hist_newton(self, lam=1e-9):
+        loss = C.c_double()
+        n = C.c_int32()
+        st = self.lib.sbi_net_hist_newton(self.ctx, float(lam), C.byref(loss), C.byref(n))
+        if st < 0:
+            raise SBIError(st, "sbi_net_hist_newton")
+        return loss.value, n.value
+
+    def hist_adam(self, lr):
+        loss = C.c_double()
+        n = C.c_int32()
+        st = self.lib.sbi_net_hist_adam(self.ctx, C.c_float(lr), C.byref(loss), C.byref(n))
+        if st < 0:
+            raise SBIError(st, "sbi_net_hist_adam")
+        return loss.value, n.value
+
+    def hist_params(self):
+        w = np.zeros(self._hist_n, dtype=np.float32)
+        st = self.lib.sbi_net_hist_params(self.ctx, w.ctypes.data_as(C.POINTER(C.c_float)))
+        if st < 0:
+            raise SBIError(st, "sbi_net_hist_params")
+        return w
+
     def last_correction(self):
         """(V* - W_lin, phi_b - phi_b,lin) left by the last solve (seed="prev" contexts)."""
         dv, db = self.empty(), self.empty()
@@ -414,6 +468,13 @@ class Batch:
         st = self.lib.sbi_batch_net_load(self.b, C.cast(buf, C.c_void_p), len(blob))
         if st < 0:
             raise SBIError(st, "sbi_batch_net_load")
+
+    def hist_load(self, taps, bins, dk, w):
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float32).ravel())
+        st = self.lib.sbi_batch_net_hist_load(self.b, int(taps), int(bins), float(dk),
+                                              w.ctypes.data_as(C.POINTER(C.c_float)))
+        if st < 0:
+            raise SBIError(st, "sbi_batch_net_hist_load")
 
     def groups(self):
         mem = (C.c_int32 * 64)()

@@ -92,6 +92,14 @@ SIGNATURES = {
     "sbi_net_features": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sbi_net_infer": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sbi_last_correction": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sbi_net_hist_param_count": (C.c_int32, [C.c_int32, C.c_int32]),
+    "sbi_net_hist_load": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_float)]),
+    "sbi_net_hist_train": (C.c_int, [C.c_void_p, C.c_int32]),
+    "sbi_net_hist_gradient": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "sbi_net_hist_newton": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "sbi_net_hist_adam": (C.c_int, [C.c_void_p, C.c_float, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "sbi_net_hist_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
     "sbi_net_trainer_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
     "sbi_net_trainer_init": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32,
                                        C.POINTER(C.c_float), C.c_void_p, C.c_size_t, C.c_void_p]),
@@ -111,6 +119,7 @@ SIGNATURES = {
     "sbi_batch_groups": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]),
     "sbi_batch_destroy": (C.c_int, [C.c_void_p]),
     "sbi_batch_net_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "sbi_batch_net_hist_load": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_float)]),
 }
 
 SBI_BATCH_GRAPH, SBI_BATCH_AUTOTUNE = 1, 2

@@ -50,7 +50,11 @@ enum {
     C_AGB0 = C_AGV0 + kAASlots,  //   (phi_b part)
     C_KE0 = C_AGB0 + kAASlots,  // stage derivatives of the adaptive pair: eta part K_0..K_5
     C_KP0 = C_KE0 + 6,   //   potential part
-    C_COUNT = C_KP0 + 6
+    C_HV0 = C_KP0 + 6,   // learned history seed: nonlinear parts of the last fixed-step solves, newest first (V)
+    C_HB0 = C_HV0 + kHistTaps,  //   (phi_b)
+    C_PV = C_HB0 + kHistTaps,   // its prediction for the current solve (V, phi_b)
+    C_PB,
+    C_COUNT
 };
 // half-form buffers
 enum {
@@ -131,6 +135,15 @@ struct sbi_ctx {
     float net_scale[8] = {1, 1, 1, 1, 1, 1, 1, 1};
     float* feat = nullptr;     // feature field [batch][ny][nx][8] (SBI_SEED_NET)
     int fallbacks = 0;         // solves of the current call restarted from the linear guess
+    // learned history seed (SBI_SEED_NET): weights and training state in
+    // hist_dev; hist_count fixed-step solves are held in C_HV/C_HB
+    HistDev* hist_dev = nullptr;
+    double* hist_partial = nullptr;
+    int hist_K = 0, hist_nb = 0;
+    double hist_dk = 0.0;
+    bool hist_loaded = false;
+    bool hist_train = false;
+    int hist_count = 0;
     double rz[6] = {0, 0, 0, 0, 0, 0};
     // wave tank (Sec. 3.2): pneumatic wavemaker components and damping pressure
     int wm_n = 0;
@@ -241,7 +254,10 @@ static Layout layout(const sbi_grid* g, int batch) {
                    al((size_t)L.s_cmp * L.csz * batch * kMaxGroups * 4) + al(sizeof(int) * (size_t)kMaxTiles * batch);
     // learned warm start: packed weights, and the feature field when it seeds the iteration
     L.bytes_net = al(sizeof(NetPacked)) +
-                  ((g->seed == SBI_SEED_NET && g->ny > 1) ? al((size_t)L.s_phys * 8 * sizeof(float) * batch) : 0);
+                  ((g->seed == SBI_SEED_NET && g->ny > 1) ? al((size_t)L.s_phys * 8 * sizeof(float) * batch) : 0) +
+                  (g->seed == SBI_SEED_NET
+                       ? al(sizeof(HistDev)) + al(sizeof(double) * kHistPart * kHistBlocks * (size_t)batch)
+                       : 0);
     L.total = L.bytes_comp + L.bytes_half + L.bytes_phys + L.bytes_tw + L.bytes_misc + L.bytes_net;
     return L;
 }
@@ -418,7 +434,15 @@ static sbi_status ctx_setup(sbi_ctx* c, const sbi_grid* g, int32_t batch, const 
     p += al(sizeof(int) * (size_t)kMaxTiles * batch);
     c->net = reinterpret_cast<NetPacked*>(p);
     p += al(sizeof(NetPacked));
-    if (g->seed == SBI_SEED_NET && g->ny > 1) c->feat = reinterpret_cast<float*>(p);
+    if (g->seed == SBI_SEED_NET && g->ny > 1) {
+        c->feat = reinterpret_cast<float*>(p);
+        p += al((size_t)L.s_phys * 8 * sizeof(float) * batch);
+    }
+    if (g->seed == SBI_SEED_NET) {
+        c->hist_dev = reinterpret_cast<HistDev*>(p);
+        p += al(sizeof(HistDev));
+        c->hist_partial = reinterpret_cast<double*>(p);
+    }
     c->col_C = L.C;
     gd.col_C = L.C;
     gd.qb = L.qb;
@@ -739,7 +763,7 @@ static sbi_status to_spectral(sbi_ctx* c, const void* eta, const void* phi, bool
 
 // compact stage state (C_ES, C_PS) -> half forms of eta, grad eta, grad phi, and
 // the linear-guess seeds (Sec. 2.4 initiation) of the iteration / SA order 1.
-static sbi_status stage_state_pass(sbi_ctx* c, bool need_eta, bool allow_prev = true) {
+static sbi_status stage_state_pass(sbi_ctx* c, bool need_eta, bool allow_prev = true, bool hist_seed = false) {
     const bool two_d = c->grid.ny > 1;
     ColBuilder b(c->gd);
     int se = b.cin(CMP(C_ES));
@@ -763,7 +787,11 @@ static sbi_status stage_state_pass(sbi_ctx* c, bool need_eta, bool allow_prev = 
     if (c->grid.mode == SBI_MODE_SA) {
         b.cout(SRC_ACC2, CMP(C_VH));
     } else {
-        if (allow_prev && (c->grid.seed == SBI_SEED_PREV || c->grid.seed == SBI_SEED_NET) && c->have_prev) {
+        if (hist_seed) {
+            // learned history seed: linear guess + the layer's prediction
+            b.term(b.cin(CMP(C_PV)), 2, 1.0, FN_ONE, 0, DV_NONE);
+            if (c->vd) b.term(b.cin(CMP(C_PB)), 3, 1.0, FN_ONE, 0, DV_NONE);
+        } else if (allow_prev && (c->grid.seed == SBI_SEED_PREV || c->grid.seed == SBI_SEED_NET) && c->have_prev) {
             // previous-solve seed: linear guess + the last solve's nonlinear part
             b.term(b.cin(CMP(C_DV)), 2, 1.0, FN_ONE, 0, DV_NONE);
             if (c->vd) b.term(b.cin(CMP(C_DB)), 3, 1.0, FN_ONE, 0, DV_NONE);
@@ -1261,15 +1289,68 @@ static sbi_status save_nonlinear_part(sbi_ctx* c) {
     return SBI_OK;
 }
 
-// capture_safe: no host synchronisation (fixed sweep launches, no fallback
-// from a failed learned seed)
+static HistParams hist_params(sbi_ctx* c, int stage) {
+    HistParams hp{};
+    hp.g = c->gd;
+    hp.K = c->hist_K;
+    hp.nb = c->hist_nb;
+    hp.dk = c->hist_dk;
+    hp.stage = stage;
+    hp.vd = c->vd;
+    hp.dev = c->hist_dev;
+    for (int q = 0; q < kHistTaps; ++q) {
+        hp.hv[q] = CMP(C_HV0 + q);
+        hp.hb[q] = CMP(C_HB0 + q);
+    }
+    hp.tv = CMP(C_DV);
+    hp.tb = CMP(C_DB);
+    hp.pv = CMP(C_PV);
+    hp.pb = CMP(C_PB);
+    hp.partial = c->hist_partial;
+    return hp;
+}
+
+// After a solve of a context with the learned history layer: a fixed-step
+// solve (stage >= 0) adds its nonlinear part (C_DV, C_DB) to the history --
+// first, when training, accumulating the gradient of predicting it from the
+// history; any other solve empties the history.
+static sbi_status hist_after_solve(sbi_ctx* c, int stage, bool capture_safe) {
+    if (!c->hist_loaded || c->grid.mode != SBI_MODE_ITER) return SBI_OK;
+    if (stage < 0) {
+        c->hist_count = 0;
+        return SBI_OK;
+    }
+    const HistParams hp = hist_params(c, stage);
+    if (c->hist_train && !capture_safe && c->hist_count >= c->hist_K) {
+        c->st.launches += 2;
+        SBI_TRY(hip_ok(launch_hist_grad(c->fp64, hp, c->batch, c->stream)));
+        SBI_TRY(hip_ok(launch_hist_reduce(hp, c->batch, c->stream)));
+    }
+    c->st.launches += 1;
+    SBI_TRY(hip_ok(launch_hist_push(c->fp64, hp, c->batch, c->stream)));
+    c->hist_count = std::min(c->hist_count + 1, kHistTaps);
+    return SBI_OK;
+}
+
+// W solve at the stage state.  stage: the RK4 stage (0..3) of a fixed-step
+// solve, -1 for any other solve.  capture_safe: no host synchronisation
+// (fixed sweep launches, no fallback from a failed learned seed).
 static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool need_eta_grad, int* vh_buf,
-                              const void* w_seed = nullptr, bool capture_safe = false) {
+                              const void* w_seed = nullptr, bool capture_safe = false, int stage = -1) {
     SBI_TRY(hip_ok(launch_ctl_reset(c->ctl, c->batch, c->grid.max_sweeps + 2, c->stream)));
     c->st.launches += 1;
-    // the learned seed starts solves that have no previous solve to start from
-    const bool net = c->grid.seed == SBI_SEED_NET && c->grid.mode == SBI_MODE_ITER && !c->have_prev;
-    SBI_TRY(stage_state_pass(c, need_eta_grad || !eta_user || net));
+    const bool iter = c->grid.mode == SBI_MODE_ITER;
+    const bool netseed = iter && c->grid.seed == SBI_SEED_NET;
+    // the learned history layer seeds fixed-step solves with a full history;
+    // the network seeds solves that have no previous solve to start from
+    const bool hist = netseed && c->hist_loaded && stage >= 0 && c->hist_count >= c->hist_K && !w_seed;
+    const bool net = netseed && c->net_loaded && !hist && !c->have_prev && !w_seed;
+    if (hist) {
+        c->st.launches += 1;
+        ProfScope ps_(c, K_NET);
+        SBI_TRY(hip_ok(launch_hist_seed(c->fp64, hist_params(c, stage), c->batch, c->stream)));
+    }
+    SBI_TRY(stage_state_pass(c, need_eta_grad || !eta_user || net, true, hist));
     SBI_TRY(row_setup(c, eta_user));
     const void* eta_phys = eta_user ? eta_user : PHYS(P_ETA);
     if (c->grid.mode == SBI_MODE_SA) {
@@ -1284,14 +1365,14 @@ static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool
         } else {
             SBI_TRY(iterate(c, eta_phys, tol));
         }
-        if (net && !capture_safe) {
-            // the linear guess is the fallback when the learned seed fails
+        if ((net || hist) && !capture_safe) {
+            // the linear guess is the fallback when a learned seed fails
             bool failed = false;
             for (int b = 0; b < c->batch; ++b) failed |= c->head[b].status < 0 || c->head[b].nonfinite;
             if (failed) {
                 c->fallbacks += 1;
                 SBI_TRY(hip_ok(launch_ctl_reset(c->ctl, c->batch, c->grid.max_sweeps + 2, c->stream)));
-                SBI_TRY(stage_state_pass(c, false));
+                SBI_TRY(stage_state_pass(c, false, false, false));
                 SBI_TRY(row_setup(c, eta_user));
                 SBI_TRY(col_forcing(c));
                 SBI_TRY(iterate(c, eta_phys, tol));
@@ -1299,6 +1380,7 @@ static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool
         }
         *vh_buf = C_VP;
         if (c->grid.seed == SBI_SEED_PREV || c->grid.seed == SBI_SEED_NET) SBI_TRY(save_nonlinear_part(c));
+        SBI_TRY(hist_after_solve(c, stage, capture_safe));
     }
     return SBI_OK;
 }
@@ -1320,7 +1402,10 @@ static sbi_status solve_status(sbi_ctx* c, sbi_solve_info* info, bool fresh) {
         if (s < 0) worst = (worst < 0) ? worst : (sbi_status)s;
         else if (worst >= 0 && s > worst) worst = (sbi_status)s;
     }
-    if (worst < 0) c->have_prev = false;  // a failed solve seeds nothing
+    if (worst < 0) {
+        c->have_prev = false;  // a failed solve seeds nothing
+        c->hist_count = 0;
+    }
     return worst;
 }
 
@@ -1403,7 +1488,8 @@ static sbi_status vertical_velocity(sbi_ctx* c, const void* eta, const void* phi
         if (c->depth_warn) warn = SBI_WARN_DEPTH_CRITERION;
     }
     // the learned seed needs the masked spectrum of eta for its gradient features
-    const bool net = c->grid.seed == SBI_SEED_NET && c->grid.mode == SBI_MODE_ITER && !c->have_prev;
+    const bool net = c->grid.seed == SBI_SEED_NET && c->grid.mode == SBI_MODE_ITER && !c->have_prev &&
+                     c->net_loaded;
     c->fallbacks = 0;
     SBI_TRY(to_spectral(c, net ? eta : nullptr, phi_s, false));
     int vh = 0;
@@ -1591,7 +1677,7 @@ extern "C" sbi_status sbi_step(sbi_ctx* c, sbi_state* state, double dt, int32_t 
     for (int s = 0; s < n; ++s) {
         for (int stage = 0; stage < 4; ++stage) {
             int vh = 0;
-            SBI_TRY(solve_stage(c, nullptr, tol, true, &vh));
+            SBI_TRY(solve_stage(c, nullptr, tol, true, &vh, nullptr, false, stage));
             if (c->grid.mode == SBI_MODE_ITER) {
                 // the iteration already read the control headers at its last poll
                 sbi_status st = solve_status(c, nullptr, true);
@@ -1873,6 +1959,91 @@ extern "C" sbi_status sbi_net_load(sbi_ctx* c, const void* weights, size_t bytes
     return SBI_OK;
 }
 
+extern "C" int32_t sbi_net_hist_param_count(int32_t taps, int32_t bins) {
+    if (taps < 1 || taps > kHistTaps || bins < 1 || bins > kHistBins) return 0;
+    return 2 * kHistStages * bins * taps * 2;
+}
+
+extern "C" sbi_status sbi_net_hist_load(sbi_ctx* c, int32_t taps, int32_t bins, double dk, const float* w) {
+    if (!c || !w || sbi_net_hist_param_count(taps, bins) == 0 || !(dk > 0.0) || !std::isfinite(dk))
+        return SBI_ERR_INVALID_ARG;
+    if (c->grid.seed != SBI_SEED_NET || !c->hist_dev) return SBI_ERR_INVALID_ARG;
+    const int n = sbi_net_hist_param_count(taps, bins);
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(w[i])) return SBI_ERR_INVALID_ARG;
+    // weights, cleared moments and accumulators
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    auto hd = std::make_unique<HistDev>();
+    std::memset(hd.get(), 0, sizeof(HistDev));
+    std::memcpy(hd->w, w, sizeof(float) * n);
+    SBI_HIP(hipMemcpyAsync(c->hist_dev, hd.get(), sizeof(HistDev), hipMemcpyHostToDevice, c->stream));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    c->hist_K = taps;
+    c->hist_nb = bins;
+    c->hist_dk = dk;
+    c->hist_loaded = true;
+    c->hist_count = 0;
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_net_hist_train(sbi_ctx* c, int32_t enable) {
+    if (!c || !c->hist_loaded) return SBI_ERR_INVALID_ARG;
+    c->hist_train = enable != 0;
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_net_hist_gradient(sbi_ctx* c, double* loss_sum, int32_t* samples, double* grad_sum,
+                                            double* gram_sum) {
+    if (!c || !c->hist_loaded) return SBI_ERR_INVALID_ARG;
+    auto hd = std::make_unique<HistDev>();
+    SBI_HIP(hipMemcpyAsync(hd.get(), c->hist_dev, sizeof(HistDev), hipMemcpyDeviceToHost, c->stream));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    if (loss_sum) *loss_sum = hd->loss;
+    if (samples) *samples = (int32_t)hd->samples;
+    if (grad_sum) {
+        const int n = sbi_net_hist_param_count(c->hist_K, c->hist_nb);
+        for (int i = 0; i < n; ++i) grad_sum[i] = hd->acc[i];
+    }
+    if (gram_sum) {
+        const int n = 2 * kHistStages * c->hist_nb * c->hist_K * c->hist_K * 2;
+        for (int i = 0; i < n; ++i) gram_sum[i] = hd->gram[i];
+    }
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_net_hist_newton(sbi_ctx* c, double lam, double* loss_mean, int32_t* samples) {
+    if (!c || !c->hist_loaded || !(lam >= 0.0) || !std::isfinite(lam)) return SBI_ERR_INVALID_ARG;
+    const HistParams hp = hist_params(c, 0);
+    SBI_TRY(hip_ok(launch_hist_newton(hp, lam, c->stream)));
+    double out[2] = {0.0, 0.0};
+    SBI_HIP(hipMemcpyAsync(out, c->hist_dev->out, sizeof(out), hipMemcpyDeviceToHost, c->stream));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    if (loss_mean) *loss_mean = out[0];
+    if (samples) *samples = (int32_t)out[1];
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_net_hist_adam(sbi_ctx* c, float lr, double* loss_mean, int32_t* samples) {
+    if (!c || !c->hist_loaded || !(lr >= 0.0f) || !std::isfinite(lr)) return SBI_ERR_INVALID_ARG;
+    HistParams hp = hist_params(c, 0);
+    hp.lr = lr;
+    SBI_TRY(hip_ok(launch_hist_adam(hp, c->stream)));
+    double out[2] = {0.0, 0.0};
+    SBI_HIP(hipMemcpyAsync(out, c->hist_dev->out, sizeof(out), hipMemcpyDeviceToHost, c->stream));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    if (loss_mean) *loss_mean = out[0];
+    if (samples) *samples = (int32_t)out[1];
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_net_hist_params(sbi_ctx* c, float* w_out) {
+    if (!c || !c->hist_loaded || !w_out) return SBI_ERR_INVALID_ARG;
+    const int n = sbi_net_hist_param_count(c->hist_K, c->hist_nb);
+    SBI_HIP(hipMemcpyAsync(w_out, c->hist_dev->w, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+    SBI_HIP(hipStreamSynchronize(c->stream));
+    return SBI_OK;
+}
+
 extern "C" sbi_status sbi_net_features(sbi_ctx* c, const void* eta, const void* phi_s, float* feat_out,
                                        void* wlin_out) {
     if (!c || !eta || !phi_s || !feat_out) return SBI_ERR_INVALID_ARG;
@@ -2112,6 +2283,12 @@ extern "C" sbi_status sbi_batch_init(sbi_batch** out, int32_t m, const sbi_grid*
 // enqueue n steps of every group on streams forked from b->cap and joined
 // back to it (capture-safe: no host synchronisation)
 static sbi_status batch_enqueue(sbi_batch* b, sbi_state* states, double dt, int n, double tol) {
+    // nothing enqueued here may depend on the state time: a captured graph is
+    // replayed at later times, and a group's members need not share one t.
+    // Time-dependent forcing (wavemaker, relaxation zones) is therefore not
+    // available to ensembles (no setter reaches a group's context).
+    for (auto& gr : b->g)
+        if (gr.c->relax_on || gr.c->wm_n > 0 || gr.c->dmp_w > 0.0) return SBI_ERR_UNSUPPORTED;
     SBI_HIP(hipEventRecord(b->fork, b->cap));
     for (auto& gr : b->g) {
         sbi_ctx* c = gr.c;
@@ -2129,7 +2306,7 @@ static sbi_status batch_enqueue(sbi_batch* b, sbi_state* states, double dt, int 
         for (int step = 0; step < n; ++step) {
             for (int stage = 0; stage < 4; ++stage) {
                 int vh = 0;
-                SBI_TRY(solve_stage(c, nullptr, tol, true, &vh, nullptr, true));
+                SBI_TRY(solve_stage(c, nullptr, tol, true, &vh, nullptr, true, stage));
                 SBI_TRY(stage_update(c, stage, dt, vh, t));
             }
             t += dt;
@@ -2156,7 +2333,7 @@ extern "C" sbi_status sbi_batch_step(sbi_batch* b, sbi_state* states, double dt,
         if (!states[i].eta || !states[i].phi_s) return SBI_ERR_INVALID_ARG;
     for (auto& gr : b->g) {
         if (gr.c->grid.mode == SBI_MODE_ITER && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
-        if (gr.c->grid.seed == SBI_SEED_NET && !gr.c->net_loaded) return SBI_ERR_INVALID_ARG;
+        if (gr.c->grid.seed == SBI_SEED_NET && !gr.c->net_loaded && !gr.c->hist_loaded) return SBI_ERR_INVALID_ARG;
         gr.c->st = Stats();
         gr.c->fallbacks = 0;
     }
@@ -2170,7 +2347,9 @@ extern "C" sbi_status sbi_batch_step(sbi_batch* b, sbi_state* states, double dt,
             ptrs.push_back(states[i].eta);
             ptrs.push_back(states[i].phi_s);
         }
-        for (auto& gr : b->g) prev.push_back(gr.c->have_prev ? 1 : 0);
+        // what the captured solves are seeded from: the previous solve, and
+        // how many history entries the learned layer holds
+        for (auto& gr : b->g) prev.push_back((gr.c->have_prev ? 1 : 0) + 2 * std::min(gr.c->hist_count, gr.c->hist_K));
         const bool hit = b->exec && b->key_dt == dt && b->key_tol == tol && b->key_n == n && b->key_ptrs == ptrs &&
                          b->key_prev == prev;
         if (!hit) {
@@ -2234,7 +2413,10 @@ extern "C" sbi_status sbi_batch_step(sbi_batch* b, sbi_state* states, double dt,
             if (st < 0) worst = (worst < 0 && worst < st) ? worst : (sbi_status)st;
             else if (worst >= 0 && st > worst) worst = (sbi_status)st;
         }
-        if (worst < 0) c->have_prev = false;
+        if (worst < 0) {
+            c->have_prev = false;
+            c->hist_count = 0;
+        }
     }
     return worst;
 }
@@ -2243,6 +2425,13 @@ extern "C" sbi_status sbi_batch_net_load(sbi_batch* b, const void* weights, size
     if (!b || !weights) return SBI_ERR_INVALID_ARG;
     for (auto& gr : b->g)
         if (gr.c->grid.seed == SBI_SEED_NET) SBI_TRY(sbi_net_load(gr.c, weights, bytes));
+    return SBI_OK;
+}
+
+extern "C" sbi_status sbi_batch_net_hist_load(sbi_batch* b, int32_t taps, int32_t bins, double dk, const float* w) {
+    if (!b || !w) return SBI_ERR_INVALID_ARG;
+    for (auto& gr : b->g)
+        if (gr.c->grid.seed == SBI_SEED_NET) SBI_TRY(sbi_net_hist_load(gr.c, taps, bins, dk, w));
     return SBI_OK;
 }
 

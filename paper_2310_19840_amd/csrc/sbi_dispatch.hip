@@ -98,5 +98,198 @@ hipError_t launch_aa_dot(int fp64, const AaParams& p, int batch, hipStream_t s) 
 hipError_t launch_diag(int fp64, const DiagParams& p, int batch, hipStream_t s) {
     return fp64 ? launch_diag_t<double>(p, batch, s) : launch_diag_t<float>(p, batch, s);
 }
+hipError_t launch_hist_seed(int fp64, const HistParams& p, int batch, hipStream_t s) {
+    return fp64 ? launch_hist_seed_t<double>(p, batch, s) : launch_hist_seed_t<float>(p, batch, s);
+}
+hipError_t launch_hist_push(int fp64, const HistParams& p, int batch, hipStream_t s) {
+    return fp64 ? launch_hist_push_t<double>(p, batch, s) : launch_hist_push_t<float>(p, batch, s);
+}
+hipError_t launch_hist_grad(int fp64, const HistParams& p, int batch, hipStream_t s) {
+    return fp64 ? launch_hist_grad_t<double>(p, batch, s) : launch_hist_grad_t<float>(p, batch, s);
+}
+
+// Gradient and Gram accumulation of the history layer: per entry (thread),
+// the sums of the members' workgroup partials in a fixed order, each member's
+// parts normalised by its D_P (parts with D_P = 0 contribute nothing), added
+// into the accumulators of the pass's stage (Gram triangles expanded to the
+// full Hermitian matrices); the loss and sample counts likewise.
+__global__ void k_hist_reduce(const HistParams p, int batch) {
+    const int K = p.K, nb = p.nb;
+    const int ntri = K * (K + 1) / 2;
+    const int nS = 2 * nb * K * 2;
+    const int oT = nS, oE = nS + 2 * nb * ntri * 2;
+    const int nall = nS + 2 * nb * ntri * 2;
+    for (int e = threadIdx.x; e < nall; e += blockDim.x) {
+        const bool tri = e >= oT;
+        const int f = tri ? e - oT : e;
+        const int P = tri ? f / (nb * ntri * 2) : f / (nb * K * 2);
+        double tot = 0.0;
+        for (int mem = 0; mem < batch; ++mem) {
+            const double* base = p.partial + (long long)mem * kHistBlocks * kHistPart;
+            double S = 0.0, D = 0.0;
+            for (int blk = 0; blk < kHistBlocks; ++blk) {
+                S += base[blk * kHistPart + e];
+                D += base[blk * kHistPart + oE + 2 + P];
+            }
+            if (D > 0.0) tot += S / D;
+        }
+        if (!tri) {
+            const int rest = f % (nb * K * 2);
+            const int b = rest / (K * 2), q = (rest / 2) % K, ri = rest & 1;
+            p.dev->acc[(((P * kHistStages + p.stage) * nb + b) * K + q) * 2 + ri] += 2.0 * tot;
+        } else {
+            const int rest = f % (nb * ntri * 2);
+            const int b = rest / (ntri * 2), t = (rest / 2) % ntri, ri = rest & 1;
+            int q = 0, rem = t;
+            while (rem >= K - q) {
+                rem -= K - q;
+                ++q;
+            }
+            const int r = q + rem;
+            const long long base = ((long long)(P * kHistStages + p.stage) * nb + b) * K * K;
+            p.dev->gram[(base + q * K + r) * 2 + ri] += tot;
+            if (r != q) p.dev->gram[(base + r * K + q) * 2 + ri] += ri ? -tot : tot;  // conj
+        }
+    }
+    if (threadIdx.x == 0) {
+        for (int mem = 0; mem < batch; ++mem) {
+            const double* base = p.partial + (long long)mem * kHistBlocks * kHistPart;
+            for (int P = 0; P < (p.vd ? 2 : 1); ++P) {
+                double E = 0.0, D = 0.0;
+                for (int blk = 0; blk < kHistBlocks; ++blk) {
+                    E += base[blk * kHistPart + oE + P];
+                    D += base[blk * kHistPart + oE + 2 + P];
+                }
+                if (D > 0.0) p.dev->loss += E / D;
+            }
+            p.dev->samples += 1.0;
+        }
+    }
+}
+
+hipError_t launch_hist_reduce(const HistParams& p, int batch, hipStream_t s) {
+    hipLaunchKernelGGL(k_hist_reduce, dim3(1), dim3(1024), 0, s, p, batch);
+    return hipGetLastError();
+}
+
+// clear the accumulators and leave (mean loss, samples) of what they held in
+// dev->out (a single workgroup; every thread has read what it needs)
+__device__ __forceinline__ void hist_clear(HistDev* d, int np, int ng, double n) {
+    for (int i = threadIdx.x; i < np; i += blockDim.x) d->acc[i] = 0.0;
+    for (int i = threadIdx.x; i < ng; i += blockDim.x) d->gram[i] = 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        d->out[0] = n > 0.0 ? d->loss / n : 0.0;
+        d->out[1] = n;
+        d->loss = 0.0;
+        d->samples = 0.0;
+    }
+}
+
+// Gauss-Newton step of the layer: per (part, stage, bin) system (one thread
+// each), w <- w - (G + lam tr(G)/K I)^-1 gamma with G the accumulated Gram
+// matrix and gamma = acc/2 the complex derivative, by a complex Cholesky
+// factorisation; systems with tr(G) = 0 (no samples) keep their weights.
+__global__ void k_hist_newton(const HistParams p, double lam) {
+    HistDev* d = p.dev;
+    const int K = p.K, nb = p.nb;
+    const double n = d->samples;
+    const int nsys = 2 * kHistStages * nb;
+    for (int sys = threadIdx.x; sys < nsys && n > 0.0; sys += blockDim.x) {
+        const double* G = d->gram + (long long)sys * K * K * 2;
+        double tr = 0.0;
+        for (int q = 0; q < K; ++q) tr += G[(q * K + q) * 2];
+        if (!(tr > 0.0)) continue;
+        // lower factor L (complex), A = L L^H
+        double Lr[kHistTaps][kHistTaps], Li[kHistTaps][kHistTaps];
+        bool ok = true;
+        for (int i = 0; i < K && ok; ++i) {
+            for (int j = 0; j <= i; ++j) {
+                // A_ij - sum_k L_ik conj(L_jk)
+                double ar = G[(i * K + j) * 2] + (i == j ? lam * tr / K : 0.0);
+                double ai = G[(i * K + j) * 2 + 1];
+                for (int k = 0; k < j; ++k) {
+                    ar -= Lr[i][k] * Lr[j][k] + Li[i][k] * Li[j][k];
+                    ai -= Li[i][k] * Lr[j][k] - Lr[i][k] * Li[j][k];
+                }
+                if (i == j) {
+                    if (!(ar > 0.0)) {
+                        ok = false;
+                        break;
+                    }
+                    Lr[i][i] = sqrt(ar);
+                    Li[i][i] = 0.0;
+                } else {
+                    Lr[i][j] = ar / Lr[j][j];
+                    Li[i][j] = ai / Lr[j][j];
+                }
+            }
+        }
+        if (!ok) continue;
+        // gamma = acc / 2; solve L y = gamma, then L^H x = y
+        const int w0 = sys * K * 2;
+        double yr[kHistTaps], yi[kHistTaps];
+        for (int i = 0; i < K; ++i) {
+            double br = 0.5 * d->acc[w0 + 2 * i], bi = 0.5 * d->acc[w0 + 2 * i + 1];
+            for (int k = 0; k < i; ++k) {
+                br -= Lr[i][k] * yr[k] - Li[i][k] * yi[k];
+                bi -= Lr[i][k] * yi[k] + Li[i][k] * yr[k];
+            }
+            yr[i] = br / Lr[i][i];
+            yi[i] = bi / Lr[i][i];
+        }
+        for (int i = K - 1; i >= 0; --i) {
+            double br = yr[i], bi = yi[i];
+            for (int k = i + 1; k < K; ++k) {
+                // conj(L_ki) x_k
+                br -= Lr[k][i] * yr[k] + Li[k][i] * yi[k];
+                bi -= Lr[k][i] * yi[k] - Li[k][i] * yr[k];
+            }
+            yr[i] = br / Lr[i][i];
+            yi[i] = bi / Lr[i][i];
+        }
+        for (int i = 0; i < K; ++i) {
+            d->w[w0 + 2 * i] = (float)((double)d->w[w0 + 2 * i] - yr[i]);
+            d->w[w0 + 2 * i + 1] = (float)((double)d->w[w0 + 2 * i + 1] - yi[i]);
+        }
+    }
+    __syncthreads();
+    hist_clear(d, 2 * kHistStages * nb * K * 2, 2 * kHistStages * nb * K * K * 2, n);
+}
+
+hipError_t launch_hist_newton(const HistParams& p, double lam, hipStream_t s) {
+    hipLaunchKernelGGL(k_hist_newton, dim3(1), dim3(256), 0, s, p, lam);
+    return hipGetLastError();
+}
+
+// One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) of the
+// layer's weights with the mean accumulated gradient; clears the accumulator
+// and leaves (mean loss, samples) in dev->out.  A single workgroup.
+__global__ void k_hist_adam(const HistParams p) {
+    HistDev* d = p.dev;
+    const double n = d->samples;
+    const int t = d->adam_t + 1;
+    const int np = 2 * kHistStages * p.nb * p.K * 2;
+    if (n > 0.0) {
+        const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+        const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+        for (int i = threadIdx.x; i < np; i += blockDim.x) {
+            const double g = d->acc[i] / n;
+            const double m = b1 * d->m[i] + (1.0 - b1) * g;
+            const double v = b2 * d->v[i] + (1.0 - b2) * g * g;
+            d->m[i] = m;
+            d->v[i] = v;
+            d->w[i] = (float)((double)d->w[i] - p.lr * (m / c1) / (sqrt(v / c2) + eps));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && n > 0.0) d->adam_t = t;
+    hist_clear(d, np, 2 * kHistStages * p.nb * p.K * p.K * 2, n);
+}
+
+hipError_t launch_hist_adam(const HistParams& p, hipStream_t s) {
+    hipLaunchKernelGGL(k_hist_adam, dim3(1), dim3(1024), 0, s, p);
+    return hipGetLastError();
+}
 
 }  // namespace sbi

@@ -41,6 +41,35 @@ constexpr int kAADepth = 2;              // residual differences kept by the And
 constexpr int kAASlots = kAADepth + 1;   // history ring of residuals and relaxed sweeps
 constexpr int kAADotThreads = 512;       // threads of an inner-product workgroup (<= 1024)
 
+// Learned history seed (a spectral layer of the learned warm start): the
+// nonlinear part of a fixed-step solve at RK stage s is predicted from the
+// backward differences d_q = sum_(j<=q) (-1)^j C(q, j) h_j of those of the K
+// solves before it (h_0 newest), pred(k) = sum_q w[P][s][bin(|k|)][q] d_q(k),
+// with complex weights per part P (V, phi_b), stage, radial bin and order.
+constexpr int kHistTaps = 8;                                   // K <= kHistTaps
+constexpr int kHistBins = 32;                                  // nb <= kHistBins
+constexpr int kHistStages = 4;
+constexpr int kHistParams = 2 * kHistStages * kHistBins * kHistTaps * 2;  // FP32 values, [P][s][b][q][re,im]
+constexpr int kHistTri = kHistTaps * (kHistTaps + 1) / 2;       // upper triangle of a K x K Gram matrix
+constexpr int kHistGram = 2 * kHistStages * kHistBins * kHistTaps * kHistTaps * 2;  // [P][s][b][q][r][re,im]
+constexpr int kHistBlocks = 64;                                // workgroups per member of the gradient pass
+// per-block partials of one member's gradient pass (layout for K, nb):
+// S[P][b][q] (re, im) = sum c conj(d_q) r, the Gram triangles
+// T[P][b][q <= r] (re, im) = sum c conj(d_q) d_r, then E_P = sum c |r|^2 and
+// D_P = sum c |y|^2 for both parts
+constexpr int kHistPart = 2 * kHistBins * kHistTaps * 2 + 2 * kHistBins * kHistTri * 2 + 4;
+// weights, optimiser state and accumulators of the layer (device)
+struct HistDev {
+    float w[kHistParams];
+    double m[kHistParams], v[kHistParams];  // Adam moments
+    double acc[kHistParams];   // gradient sums over the accumulated solves
+    double gram[kHistGram];    // Gram sums (full Hermitian matrices)
+    double loss;               // loss sum
+    double samples;            // solves accumulated
+    double out[2];             // mean loss and samples of the last optimiser step
+    int adam_t;
+};
+
 struct Ctl {
     int done;                                // iteration finished (any reason)
     int status;                              // sbi_status of the solve

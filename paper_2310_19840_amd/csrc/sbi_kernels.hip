@@ -2074,6 +2074,147 @@ static hipError_t col_ny(const ColParams& p, int batch, const Twiddles& tw, hipS
     }
 }
 // ---------------------------------------------------------------------------
+// Learned history seed: per mode, the nonlinear part of the solve at RK stage
+// s is predicted from the backward differences d_q of the last K fixed-step
+// solves' parts (newest first) with complex weights w[P][s][b][q] of the
+// mode's radial bin b = min(floor(|k| / dk), nb - 1); FP32 weights,
+// arithmetic in FP64.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int hist_bin(double k, double dk, int nb) {
+    const double f = floor(k / dk);
+    return f >= (double)(nb - 1) ? nb - 1 : (int)f;
+}
+__device__ __forceinline__ int hist_widx(int P, int s, int b, int q, int nb, int K) {
+    return (((P * kHistStages + s) * nb + b) * K + q) * 2;
+}
+// backward differences of the history of part P at element o: d_q = sum_(j<=q) (-1)^j C(q, j) h_j
+template <typename V>
+__device__ __forceinline__ void hist_diffs(const HistParams& p, int P, long long o, double (&dr)[kHistTaps],
+                                           double (&di)[kHistTaps]) {
+    double hr[kHistTaps], hi[kHistTaps];
+    for (int q = 0; q < p.K; ++q) {
+        const V h = static_cast<const V*>(P == 0 ? p.hv[q] : p.hb[q])[o];
+        hr[q] = (double)h.x;
+        hi[q] = (double)h.y;
+    }
+    for (int q = 0; q < p.K; ++q) {
+        double c = 1.0, ar = 0.0, ai = 0.0;  // c = (-1)^j C(q, j)
+        for (int j = 0; j <= q; ++j) {
+            ar += c * hr[j];
+            ai += c * hi[j];
+            c = -c * (double)(q - j) / (double)(j + 1);
+        }
+        dr[q] = ar;
+        di[q] = ai;
+    }
+}
+
+// pv/pb <- predictions of the V and phi_b parts (zero outside the kept modes)
+template <typename R>
+__global__ void k_hist_seed(const HistParams p) {
+    using V = typename cplx_of<R>::type;
+    const int mem = blockIdx.y;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= p.g.s_cmp) return;
+    const long long o = mem * p.g.s_cmp + idx;
+    const ModeGeo m = mode_geo(p.g, idx);
+    const int nparts = p.vd ? 2 : 1;
+    for (int P = 0; P < nparts; ++P) {
+        double re = 0.0, im = 0.0;
+        if (m.valid) {
+            const int b = hist_bin(m.k, p.dk, p.nb);
+            double dr[kHistTaps], di[kHistTaps];
+            hist_diffs<V>(p, P, o, dr, di);
+            for (int q = 0; q < p.K; ++q) {
+                const int wi = hist_widx(P, p.stage, b, q, p.nb, p.K);
+                const double wr = (double)p.dev->w[wi], wm = (double)p.dev->w[wi + 1];
+                re += wr * dr[q] - wm * di[q];
+                im += wr * di[q] + wm * dr[q];
+            }
+        }
+        static_cast<V*>(P == 0 ? p.pv : p.pb)[o] = cx<V>(R(re), R(im));
+    }
+}
+
+// history shift: h_q <- h_(q-1) for q = K-1 .. 1, h_0 <- the new entry
+template <typename R>
+__global__ void k_hist_push(const HistParams p) {
+    using V = typename cplx_of<R>::type;
+    const int mem = blockIdx.y;
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= p.g.s_cmp) return;
+    const long long o = mem * p.g.s_cmp + idx;
+    const int nparts = p.vd ? 2 : 1;
+    for (int P = 0; P < nparts; ++P) {
+        void* const* h = P == 0 ? p.hv : p.hb;
+        for (int q = p.K - 1; q >= 1; --q) static_cast<V*>(h[q])[o] = static_cast<const V*>(h[q - 1])[o];
+        static_cast<V*>(h[0])[o] = static_cast<const V*>(P == 0 ? p.tv : p.tb)[o];
+    }
+}
+
+// offsets of a member's per-block partials (layout for the pass's K and nb)
+__device__ __forceinline__ int hist_part_tri(const HistParams& p) { return 2 * p.nb * p.K * 2; }
+__device__ __forceinline__ int hist_part_ed(const HistParams& p) {
+    return hist_part_tri(p) + 2 * p.nb * (p.K * (p.K + 1) / 2) * 2;
+}
+
+// loss gradient and Gram sums of predicting the target (tv, tb) from the
+// history at stage s: per workgroup, S[P][b][q] = sum c conj(d_q) r,
+// T[P][b][q <= r] = sum c conj(d_q) d_r, E_P = sum c |r|^2, D_P = sum c |y|^2
+// over its modes (r = pred - y, c = 1 at m_x = 0 else 2), summed in LDS and
+// written as the workgroup's partials
+template <typename R>
+__global__ void __launch_bounds__(256) k_hist_grad(const HistParams p) {
+    using V = typename cplx_of<R>::type;
+    __shared__ double acc[kHistPart];
+    const int mem = blockIdx.y;
+    const int oT = hist_part_tri(p), oE = hist_part_ed(p);
+    const int ntri = p.K * (p.K + 1) / 2;
+    for (int i = threadIdx.x; i < kHistPart; i += blockDim.x) acc[i] = 0.0;
+    __syncthreads();
+    const int nparts = p.vd ? 2 : 1;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < p.g.s_cmp;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const ModeGeo m = mode_geo(p.g, idx);
+        if (!m.valid) continue;
+        const long long o = mem * p.g.s_cmp + idx;
+        const int b = hist_bin(m.k, p.dk, p.nb);
+        const double c = m.mx == 0 ? 1.0 : 2.0;
+        for (int P = 0; P < nparts; ++P) {
+            const V y = static_cast<const V*>(P == 0 ? p.tv : p.tb)[o];
+            double dr[kHistTaps], di[kHistTaps];
+            hist_diffs<V>(p, P, o, dr, di);
+            double re = 0.0, im = 0.0;
+            for (int q = 0; q < p.K; ++q) {
+                const int wi = hist_widx(P, p.stage, b, q, p.nb, p.K);
+                const double wr = (double)p.dev->w[wi], wm = (double)p.dev->w[wi + 1];
+                re += wr * dr[q] - wm * di[q];
+                im += wr * di[q] + wm * dr[q];
+            }
+            const double rr = re - (double)y.x, ri = im - (double)y.y;
+            atomicAdd(&acc[oE + P], c * (rr * rr + ri * ri));
+            atomicAdd(&acc[oE + 2 + P], c * ((double)y.x * y.x + (double)y.y * y.y));
+            int t = 0;
+            for (int q = 0; q < p.K; ++q) {
+                // conj(d_q) r
+                const int si = ((P * p.nb + b) * p.K + q) * 2;
+                atomicAdd(&acc[si], c * (dr[q] * rr + di[q] * ri));
+                atomicAdd(&acc[si + 1], c * (dr[q] * ri - di[q] * rr));
+                for (int r = q; r < p.K; ++r, ++t) {
+                    // conj(d_q) d_r
+                    const int ti = oT + ((P * p.nb + b) * ntri + t) * 2;
+                    atomicAdd(&acc[ti], c * (dr[q] * dr[r] + di[q] * di[r]));
+                    atomicAdd(&acc[ti + 1], c * (dr[q] * di[r] - di[q] * dr[r]));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    double* out = p.partial + ((long long)mem * gridDim.x + blockIdx.x) * kHistPart;
+    for (int i = threadIdx.x; i < kHistPart; i += blockDim.x) out[i] = acc[i];
+}
+
+// ---------------------------------------------------------------------------
 // per-precision entry points (this file is compiled once per precision with
 // SBI_REAL defined; sbi_dispatch.hip selects between them)
 // ---------------------------------------------------------------------------
@@ -2120,6 +2261,21 @@ template <> hipError_t launch_rk54_t<Real>(const Rk54Params& p, int batch, hipSt
 template <> hipError_t launch_aa_dot_t<Real>(const AaParams& p, int batch, hipStream_t s) {
     dim3 block(kAADotThreads), grid((unsigned)p.nblk, batch);
     hipLaunchKernelGGL(k_aa_dot<Real>, grid, block, 0, s, p);
+    return hipGetLastError();
+}
+template <> hipError_t launch_hist_seed_t<Real>(const HistParams& p, int batch, hipStream_t s) {
+    dim3 block(256), grid((unsigned)((p.g.s_cmp + 255) / 256), batch);
+    hipLaunchKernelGGL(k_hist_seed<Real>, grid, block, 0, s, p);
+    return hipGetLastError();
+}
+template <> hipError_t launch_hist_push_t<Real>(const HistParams& p, int batch, hipStream_t s) {
+    dim3 block(256), grid((unsigned)((p.g.s_cmp + 255) / 256), batch);
+    hipLaunchKernelGGL(k_hist_push<Real>, grid, block, 0, s, p);
+    return hipGetLastError();
+}
+template <> hipError_t launch_hist_grad_t<Real>(const HistParams& p, int batch, hipStream_t s) {
+    dim3 block(256), grid(kHistBlocks, batch);
+    hipLaunchKernelGGL(k_hist_grad<Real>, grid, block, 0, s, p);
     return hipGetLastError();
 }
 template <> hipError_t launch_diag_t<Real>(const DiagParams& p, int batch, hipStream_t s) {

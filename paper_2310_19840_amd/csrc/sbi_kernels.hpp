@@ -171,6 +171,22 @@ struct AaParams {
     int nblk;
 };
 
+// learned history seed: prediction, history push, loss gradient, reduction, Adam
+struct HistParams {
+    GridDev g;
+    int K, nb, stage, vd;
+    double dk;                      // radial bin width: bin = min(floor(|k| / dk), nb - 1)
+    HistDev* dev;                   // weights, moments, accumulators
+    void* hv[kHistTaps];            // history of the V part, newest first (compact)
+    void* hb[kHistTaps];            // history of the phi_b part
+    const void* tv;                 // new entry / target: V part (compact)
+    const void* tb;                 //   phi_b part
+    void* pv;                       // prediction out (compact)
+    void* pb;
+    double* partial;                // [batch][kHistBlocks][kHistPart]
+    double lr;                      // Adam step size
+};
+
 struct DiagParams {
     GridDev g;
     const void* eh;
@@ -203,6 +219,9 @@ template <typename R> hipError_t launch_rk_t(const RkParams&, int, hipStream_t);
 template <typename R> hipError_t launch_rk54_t(const Rk54Params&, int, hipStream_t);
 template <typename R> hipError_t launch_aa_dot_t(const AaParams&, int, hipStream_t);
 template <typename R> hipError_t launch_diag_t(const DiagParams&, int, hipStream_t);
+template <typename R> hipError_t launch_hist_seed_t(const HistParams&, int, hipStream_t);
+template <typename R> hipError_t launch_hist_push_t(const HistParams&, int, hipStream_t);
+template <typename R> hipError_t launch_hist_grad_t(const HistParams&, int, hipStream_t);
 
 hipError_t launch_row_fwd(int fp64, const RowFwdParams& p, int batch, const Twiddles& tw, hipStream_t s);
 hipError_t launch_row_inv(int fp64, const RowInvParams& p, int batch, const Twiddles& tw, hipStream_t s);
@@ -217,6 +236,12 @@ hipError_t launch_rk(int fp64, const RkParams& p, int batch, hipStream_t s);
 hipError_t launch_rk54(int fp64, const Rk54Params& p, int batch, hipStream_t s);
 hipError_t launch_aa_dot(int fp64, const AaParams& p, int batch, hipStream_t s);
 hipError_t launch_diag(int fp64, const DiagParams& p, int batch, hipStream_t s);
+hipError_t launch_hist_seed(int fp64, const HistParams& p, int batch, hipStream_t s);
+hipError_t launch_hist_push(int fp64, const HistParams& p, int batch, hipStream_t s);
+hipError_t launch_hist_grad(int fp64, const HistParams& p, int batch, hipStream_t s);
+hipError_t launch_hist_reduce(const HistParams& p, int batch, hipStream_t s);
+hipError_t launch_hist_adam(const HistParams& p, hipStream_t s);
+hipError_t launch_hist_newton(const HistParams& p, double lam, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* ctl, int batch, int slots, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
 hipError_t launch_ctl_acc_reset(Ctl* ctl, int batch, hipStream_t s);
