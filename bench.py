@@ -14,7 +14,12 @@ iteration mixes its relaxed sweeps by Anderson's method (same residual test
 and fixed point, about half the sweeps; `--accel none` and the
 "plain-relaxed" form give the relaxed sweeps alone).  `forms` adds, at the same tolerance, two
 realisations stepped in one captured HIP graph with the previous-solve seed
-("batched+prev") and with the learned warm start ("batched+learned"), the
+("batched+prev") and with the learned warm start ("batched+learned": the
+network starts the first solve and the trained history layer predicts every
+later stepping solve from the last eight, its inference inside the timed
+region); both graphs enqueue a speculative sweep budget (the largest recent
+sweep count + 3, redone exactly with a larger budget if a solve outruns it),
+with the plain form's sweep cap; the
 plain step in FP32 (tolerance 1e-6, the FP32 floor), the adaptive
 fifth/fourth-order pair over four peak periods ("adaptive", at the error bound
 3e-7 that makes it at least as accurate as the fixed step; counted in
@@ -27,7 +32,9 @@ crossing sea in FP32 beside FP64 with the FP32 error (max |eta|, energy drift).
 Prints ONE JSON line.  `roofline` is for the dominant kernel of the plain
 form, its algorithmic bytes per launch divided by its average launch time from
 HIP events recorded on the library's stream during the timed region.
-`cpu_baseline` times the FP64 oracle on a bounded sample of the same workload.
+`cpu_baseline` times the FP64 oracle in the headline's mode (Anderson-mixed
+iteration, tol 1e-8) on a bounded sample of the same workload, on one core and
+on one member per usable core (at most 16).
 """
 from __future__ import annotations
 
@@ -101,15 +108,17 @@ def measured_traffic(kernel: str):
         return None
 
 
-def cpu_baseline(n_sample: int = 256, max_sweeps: int = 200, min_seconds: float = 10.0, max_steps: int = 8):
-    """Oracle (numpy FP64, single thread) on a bounded sample of the workload:
-    consecutive RK4 steps until `min_seconds` of CPU work (at most `max_steps`)."""
+def _oracle_member_rate(job):
+    """Worker of cpu_baseline: consecutive RK4 steps of one sample member with
+    the oracle (single-threaded numpy) until `min_seconds` of work (at most
+    `max_steps`).  Returns (grid-point-steps, seconds, steps, sweeps)."""
+    seed, n, min_seconds, max_steps, accel = job
     from oracle import Grid, Solver as OSolver
     from sbi_inputs import config_c5
 
-    cfg = config_c5(seed=0, n=n_sample)
+    cfg = config_c5(seed=seed, n=n)
     g = cfg["grid"]
-    o = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), cfg["depth"], mode="iter", max_sweeps=max_sweeps)
+    o = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), cfg["depth"], mode="iter", max_sweeps=400, accel=accel)
     eta, phi = cfg["eta"], cfg["phi"]
     sweeps, steps = 0, 0
     t0 = time.perf_counter()
@@ -117,15 +126,63 @@ def cpu_baseline(n_sample: int = 256, max_sweeps: int = 200, min_seconds: float 
         eta, phi, stats = o.step(eta, phi, cfg["dt"], 1, tol=cfg["tol"])
         sweeps += sum(s.sweeps for s in stats)
         steps += 1
-    el = time.perf_counter() - t0
+    return g.nx * g.ny * steps, time.perf_counter() - t0, steps, sweeps
+
+
+def _host_cpu():
+    model = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return model, os.cpu_count() or 1, usable
+
+
+def cpu_baseline(n_sample: int = 256, min_seconds: float = 10.0, max_steps: int = 8, accel: str = "anderson",
+                 max_workers: int = 16):
+    """The FP64 oracle in the headline's mode (W iteration to tol 1e-8 with
+    Anderson-mixed sweeps) on a bounded sample of the workload: 256^2 members
+    of the same recipe (same dx, depth draw and sea statistics; 1/16 of the
+    1024^2 points), each stepped for about `min_seconds`.  First one member on
+    one core alone, then one member per usable core (at most `max_workers`
+    processes, numpy single-threaded in each) at once; `value` is the
+    all-core figure."""
+    import multiprocessing as mp
+
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+    model, ncpu, usable = _host_cpu()
+    ctx = mp.get_context("spawn")  # fresh interpreters: nothing of the GPU process is inherited
+    with ctx.Pool(1) as pool:
+        pts1, el1, st1, sw1 = pool.map(_oracle_member_rate, [(0, n_sample, min_seconds, max_steps, accel)])[0]
+    workers = max(1, min(usable, max_workers))
+    jobs = [(sd, n_sample, min_seconds, max_steps, accel) for sd in range(workers)]
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_member_rate, jobs)
+    wall = time.perf_counter() - t0
+    pts = sum(r[0] for r in res)
+    span = max(r[1] for r in res)
+    steps = sum(r[2] for r in res)
+    sweeps = sum(r[3] for r in res)
     return {
-        "value": g.nx * g.ny * steps / el,
+        "value": pts / span,
         "unit": "grid-point-steps/s",
-        "cores": 1,
+        "cores": workers,
         "kind": "oracle",
-        "sample": (f"{steps} consecutive RK4 steps ({4 * steps} W solves, tol 1e-8, {sweeps} sweeps) of the same "
-                   f"workload on a {g.nx}x{g.ny} grid with the same dx, depth draw and sea statistics; numpy FFT "
-                   f"single-threaded; {el:.1f} s on {os.cpu_count()} visible host cores"),
+        "value_1core": pts1 / el1,
+        "host": f"{model}; {ncpu} logical CPUs, {usable} usable by this process",
+        "sample": (f"{workers} members at {n_sample}x{n_sample} (the 1024^2 recipe at 1/16 of the points: same dx, "
+                   f"depth draw and sea statistics, seeds 0..{workers - 1}), each stepped alone in its own "
+                   f"single-threaded process for ~{min_seconds:.0f} s: {steps} RK4 steps, {4 * steps} W solves, "
+                   f"{sweeps} sweeps ({sweeps / max(4 * steps, 1):.1f} per solve), W iteration tol 1e-8 with "
+                   f"Anderson-mixed sweeps as in the headline; value = all members' grid-point-steps / the "
+                   f"longest member's time ({span:.1f} s; {wall:.1f} s with process start-up). One core alone: "
+                   f"{st1} steps of member 0 in {el1:.1f} s ({sw1} sweeps) -> value_1core"),
     }
 
 
@@ -205,24 +262,29 @@ def run_plain(args, dev, precision, tol, accel=None):
 
 
 def run_batched(args, dev, seed_mode, members, accel=None):
-    """B C5 realisations in one captured graph, previous-solve or learned seed."""
+    """B C5 realisations in one captured graph, with the previous-solve seed
+    ("prev") or the learned warm start ("net": the network starts the first
+    solve, the trained history layer predicts every later stepping solve, so
+    the layer's inference runs inside the timed region)."""
     import torch
 
-    from paper_2310_19840_amd import Batch
+    from paper_2310_19840_amd import Batch, warmstart
 
     cfgs = c5_members(range(members), args.n)
-    blob = None
+    blob = hist = None
     if seed_mode == "net":
         path = os.path.join(ROOT, "paper_2310_19840_amd", "weights", "warmstart_c5.sbiw")
-        if not os.path.exists(path):
-            return dict(skipped=f"no trained weights at {os.path.relpath(path, ROOT)}")
+        if not os.path.exists(path) or not os.path.exists(warmstart.HISTORY_WEIGHTS):
+            return dict(skipped="no trained weights under paper_2310_19840_amd/weights")
         blob = open(path, "rb").read()
+        hist = warmstart.load_history()
     mem = [dict(nx=c["grid"].nx, ny=c["grid"].ny, lx=c["grid"].lx, ly=c["grid"].ly, depth=c["depth"],
                 precision="fp64", mode="iter", seed=seed_mode, max_sweeps=args.batch_sweeps, accel=accel)
            for c in cfgs]
     b = Batch(mem, device=dev, graph=True)
     if blob is not None:
         b.net_load(blob)
+        b.hist_load(*hist)
     etas = [torch.tensor(c["eta"], dtype=torch.float64, device=dev) for c in cfgs]
     phis = [torch.tensor(c["phi"], dtype=torch.float64, device=dev) for c in cfgs]
     dt = cfgs[0]["dt"]
@@ -240,11 +302,12 @@ def run_batched(args, dev, seed_mode, members, accel=None):
     el = time.perf_counter() - t0
     npts = sum(c["grid"].nx * c["grid"].ny for c in cfgs)
     solves = sum(x["solves"] for x in info)
+    budgets, redos = b.budgets()
     return dict(value=npts * args.steps / el, ms_per_step=1e3 * el / max(args.steps, 1), status=st, members=members,
                 sweeps_mean=sum(x["sweeps_total"] for x in info) / max(solves, 1),
                 sweeps_max=max(x["sweeps_max"] for x in info),
                 max_residual=max(x["max_residual"] for x in info),
-                first_step_sweeps_mean=sum(first) / len(first))
+                first_step_sweeps_mean=sum(first) / len(first), sweep_budget=budgets, redone_calls=redos)
 
 
 def run_adaptive(args, dev, rk_tol):
@@ -282,7 +345,8 @@ def run_adaptive(args, dev, rk_tol):
 
 def run_c2_tank(args, dev):
     """The 1D submerged-bar tank (N=4096, 160 h0, short-wave case), SA mode, FP64,
-    eager steps of T/64: waves made by the pneumatic wavemaker and absorbed by
+    the paper's low-pass filter, eager steps of T/64: waves made by the
+    pneumatic wavemaker and absorbed by
     the damping pressure (the tank of Sec. 3.2), beside the same tank driven by
     relaxation zones."""
     import numpy as np
@@ -296,7 +360,8 @@ def run_c2_tank(args, dev):
     rz = cfg["relax"]
     out = {}
     for kind in ("tank", "relaxation"):
-        s = Solver(g.nx, 1, g.lx, 1.0, cfg["depth"], h_ref=cfg["h_ref"], device=dev, mode="sa")
+        s = Solver(g.nx, 1, g.lx, 1.0, cfg["depth"], h_ref=cfg["h_ref"], device=dev, mode="sa",
+                   filter_beta=cfg["filter_beta"])
         if kind == "tank":
             s.set_wavemaker([(rz["a"], rz["k"], rz["omega"], 0.0)], x0=7 * g.lx / 8, width=4 * math.pi)
         else:
@@ -384,8 +449,8 @@ def main():
     ap.add_argument("--n", type=int, default=1024, help="grid size (1024 = the benchmark workload)")
     ap.add_argument("--max-sweeps", type=int, default=400)
     ap.add_argument("--batch-sweeps", type=int, default=None,
-                    help="sweep budget per solve of the captured forms (default 24 with Anderson mixing, 48 "
-                         "without; solves here need at most 15 and 33)")
+                    help="sweep cap (max_sweeps) of the captured forms; default: that of the plain form.  Their "
+                         "launches follow the speculative budget (largest recent sweep count + 3), not the cap")
     ap.add_argument("--members", type=int, default=2, help="realisations of the batched forms")
     ap.add_argument("--c4-steps", type=int, default=4)
     ap.add_argument("--c3-steps", type=int, default=32)
@@ -414,7 +479,7 @@ def main():
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     accel = None if args.accel == "none" else args.accel
     if args.batch_sweeps is None:
-        args.batch_sweeps = 24 if accel else 48
+        args.batch_sweeps = args.max_sweeps
     plain = run_plain(args, dev, "fp64", 1e-8, accel=accel)
     cfg = plain.pop("cfg")
     g = cfg["grid"]

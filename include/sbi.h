@@ -285,7 +285,9 @@ sbi_status sbi_set_relaxation(sbi_ctx* ctx, const double* params, int32_t n);
 sbi_status sbi_set_wavemaker(sbi_ctx* ctx, const double* comps, int32_t ncomp, double h_gen, double damp_x0,
                              double damp_width);
 
-/* Replace the depth (host [batch][ny][nx]) and reference depth of a context. */
+/* Replace the depth (host [batch][ny][nx]) and reference depth of a context;
+   empties the history of the learned history layer (sbi_net.h), not its
+   training sums. */
 sbi_status sbi_set_depth(sbi_ctx* ctx, const double* depth, double h_ref);
 
 /*

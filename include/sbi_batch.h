@@ -12,10 +12,17 @@
  * column-pass layout of each group (how a pass's products are split over
  * workgroups) is chosen by timing the candidates on the device at init.
  *
- * Iterations run without host polling: each solve enqueues max_sweeps + 1
- * sweep launches and a member's launches after the pass that decides its
- * solve return at once; sweep statistics are accumulated on the device.  A
- * learned seed (SBI_SEED_NET) that fails is reported, not redone.
+ * Iterations run without host polling: each solve enqueues the sweep
+ * launches of a budget B and a member's launches after the pass that decides
+ * its solve return at once; sweep statistics are accumulated on the device.
+ * The first call of a group uses B = max_sweeps; later calls use the largest
+ * sweep count of the previous call plus a margin of 3 (changed only when it
+ * moves by more than the margin, each change being a new capture).  When a
+ * solve outruns B the device statistics show it undecided, and the call is
+ * redone from a device copy of its inputs and of the carried seeds with B
+ * doubled, until every solve is decided, so results equal those of the full
+ * max_sweeps budget while the launches scale with the sweeps the solves need.
+ * A learned seed (SBI_SEED_NET) that fails is reported, not redone.
  *
  * Nothing a batch step computes depends on the state time t (each member's
  * t is only advanced by n*dt): time-dependent forcing -- the wave tank's
@@ -69,6 +76,11 @@ sbi_status sbi_batch_net_hist_load(sbi_batch* b, int32_t taps, int32_t bins, dou
 /* Number of member groups and, per group (g < groups), its member count and
    the column-pass split the autotuner chose (0: none). */
 int32_t sbi_batch_groups(const sbi_batch* b, int32_t* members_out, int32_t* split_out, int32_t n);
+
+/* Current sweep budget of each group (host int32 [n]; max_sweeps when none is
+   set); returns the number of step calls redone with a larger budget since
+   init. */
+int32_t sbi_batch_budgets(const sbi_batch* b, int32_t* budget_out, int32_t n);
 
 sbi_status sbi_batch_destroy(sbi_batch* b);
 

@@ -278,6 +278,13 @@ class Solver:
             raise SBIError(st, "sbi_last_correction")
         return dv, db
 
+    def set_depth(self, depth, h_ref=-1.0):
+        d = self._host_depth(depth)
+        st = self.lib.sbi_set_depth(self.ctx, d.ctypes.data_as(C.POINTER(C.c_double)), float(h_ref))
+        if st < 0:
+            raise SBIError(st, "sbi_set_depth")
+        return st
+
     def set_relaxation(self, a, k, omega, gen_len, abs_len, ramp_periods):
         arr = (C.c_double * 6)(a, k, omega, gen_len, abs_len, ramp_periods)
         st = self.lib.sbi_set_relaxation(self.ctx, arr, 6)
@@ -475,6 +482,12 @@ class Batch:
                                               w.ctypes.data_as(C.POINTER(C.c_float)))
         if st < 0:
             raise SBIError(st, "sbi_batch_net_hist_load")
+
+    def budgets(self):
+        """(sweep budget of each group, step calls redone with a larger budget)."""
+        bud = (C.c_int32 * 64)()
+        redos = self.lib.sbi_batch_budgets(self.b, bud, 64)
+        return list(bud[:len(self.groups())]), redos
 
     def groups(self):
         mem = (C.c_int32 * 64)()

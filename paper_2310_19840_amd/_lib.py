@@ -117,6 +117,7 @@ SIGNATURES = {
     "sbi_batch_step": (C.c_int, [C.c_void_p, C.POINTER(sbi_state), C.c_double, C.c_int32, C.c_double,
                                  C.POINTER(sbi_step_info)]),
     "sbi_batch_groups": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]),
+    "sbi_batch_budgets": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32]),
     "sbi_batch_destroy": (C.c_int, [C.c_void_p]),
     "sbi_batch_net_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "sbi_batch_net_hist_load": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_float)]),

@@ -144,6 +144,9 @@ struct sbi_ctx {
     bool hist_loaded = false;
     bool hist_train = false;
     int hist_count = 0;
+    // sweeps enqueued per solve by an iteration without host polling
+    // (iterate_fixed); 0 or >= max_sweeps: the full max_sweeps + 1 launches
+    int budget = 0;
     double rz[6] = {0, 0, 0, 0, 0, 0};
     // wave tank (Sec. 3.2): pneumatic wavemaker components and damping pressure
     int wm_n = 0;
@@ -522,6 +525,7 @@ extern "C" sbi_status sbi_destroy(sbi_ctx* c) {
 extern "C" sbi_status sbi_set_depth(sbi_ctx* c, const double* depth, double h_ref) {
     if (!c || !depth) return SBI_ERR_INVALID_ARG;
     SBI_TRY(set_depth(c, depth, h_ref));
+    c->hist_count = 0;  // the learned history belongs to the old bed
     return c->depth_warn ? SBI_WARN_DEPTH_CRITERION : SBI_OK;
 }
 
@@ -1076,11 +1080,15 @@ static sbi_status iterate(sbi_ctx* c, const void* eta_phys, double tol) {
     return SBI_OK;
 }
 
-// iteration without host polling (capturable): all max_sweeps + 1 sweep
-// launches are enqueued; after the column pass that decides a member's solve,
-// that member's later launches return at once
+// iteration without host polling (capturable): sweep launches 0..B are
+// enqueued, B = the context's budget (max_sweeps when unset); after the column
+// pass that decides a member's solve, that member's later launches return at
+// once.  A solve that needs more than B sweeps stays undecided (its device
+// statistics do not count it), which the ensemble step detects and redoes.
 static sbi_status iterate_fixed(sbi_ctx* c, const void* eta_phys, double tol) {
-    for (int n = 0; n <= c->grid.max_sweeps; ++n) SBI_TRY(launch_sweep(c, eta_phys, n, tol));
+    const int M = c->grid.max_sweeps;
+    const int B = (c->budget > 0 && c->budget < M) ? c->budget : M;
+    for (int n = 0; n <= B; ++n) SBI_TRY(launch_sweep(c, eta_phys, n, tol));
     return SBI_OK;
 }
 
@@ -2125,9 +2133,19 @@ std::vector<std::vector<int>> group_members(int m, const sbi_grid* grids) {
 
 size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
+// compact buffers a context carries from one call to the next: the
+// previous-solve parts (C_DV, C_DB) and the learned history (C_HV0 .. C_HB0 +
+// kHistTaps - 1), two contiguous runs of the workspace
+constexpr int kCarriedCmp = 2 + 2 * kHistTaps;
+constexpr int kBudgetMargin = 3;  // sweeps beyond the largest count seen, in a speculative budget
+
 size_t staging_bytes(const sbi_grid& g, int count) {
     const size_t rsz = g.precision == SBI_FP64 ? 8 : 4;
-    return 2 * al256((size_t)g.nx * g.ny * rsz * count);
+    const Layout L = layout(&g, count);
+    // staging of the members' states, a backup of them and of the carried
+    // compact buffers (for the redo of a step whose sweep budget ran out)
+    return 4 * al256((size_t)g.nx * g.ny * rsz * count) +
+           (size_t)kCarriedCmp * al256((size_t)L.s_cmp * L.csz * count);
 }
 
 }  // namespace
@@ -2141,6 +2159,11 @@ struct sbi_batch {
         char* st_eta = nullptr;  // contiguous [count][ny][nx] staging of the members' states
         char* st_phi = nullptr;
         size_t field_bytes = 0;  // one member's field
+        char* bk_state = nullptr;  // backup of the members' (eta, phi) at the start of a step call
+        char* bk_cmp = nullptr;    // backup of the carried compact buffers
+        size_t cmp_bytes = 0;      // one compact buffer of the group (all members)
+        bool bk_have_prev = false;
+        int bk_hist_count = 0;
     };
     int m = 0;
     int flags = 0;
@@ -2155,6 +2178,8 @@ struct sbi_batch {
     int key_n = -1;
     std::vector<const void*> key_ptrs;
     std::vector<int> key_prev;
+    std::vector<int> key_budget;
+    int redos = 0;  // step calls redone with a larger sweep budget (since init)
 };
 
 static void batch_free(sbi_batch* b) {
@@ -2261,6 +2286,8 @@ extern "C" sbi_status sbi_batch_init(sbi_batch** out, int32_t m, const sbi_grid*
         p += wsb;
         gr.st_eta = p;
         gr.st_phi = p + al256(gr.field_bytes * count);
+        gr.bk_state = p + 2 * al256(gr.field_bytes * count);
+        gr.bk_cmp = p + 4 * al256(gr.field_bytes * count);
         p += staging_bytes(g, count);
         b->g.push_back(gr);
         if (st < 0) {
@@ -2268,6 +2295,8 @@ extern "C" sbi_status sbi_batch_init(sbi_batch** out, int32_t m, const sbi_grid*
             return st;
         }
         if (st == SBI_WARN_DEPTH_CRITERION) warn = st;
+        b->g.back().cmp_bytes = (size_t)(static_cast<char*>(b->g.back().c->comp[C_DB]) -
+                                         static_cast<char*>(b->g.back().c->comp[C_DV]));
         if ((flags & SBI_BATCH_AUTOTUNE) && g.mode == SBI_MODE_ITER) {
             st = autotune_split(b->g.back().c);
             if (st < 0) {
@@ -2326,6 +2355,95 @@ static sbi_status batch_enqueue(sbi_batch* b, sbi_state* states, double dt, int 
     return SBI_OK;
 }
 
+// backup (save) or restore of what a step call changes: the members' states
+// and the carried compact buffers (previous-solve parts, learned history),
+// plus their host-side flags; on the batch's stream
+static sbi_status batch_keep(sbi_batch* b, sbi_state* states, bool save) {
+    for (auto& gr : b->g) {
+        sbi_ctx* c = gr.c;
+        for (size_t k = 0; k < gr.members.size(); ++k) {
+            const sbi_state& st = states[gr.members[k]];
+            char* be = gr.bk_state + (2 * k) * gr.field_bytes;
+            char* bp = gr.bk_state + (2 * k + 1) * gr.field_bytes;
+            SBI_HIP(hipMemcpyAsync(save ? be : st.eta, save ? st.eta : be, gr.field_bytes, hipMemcpyDeviceToDevice,
+                                   b->cap));
+            SBI_HIP(hipMemcpyAsync(save ? bp : st.phi_s, save ? st.phi_s : bp, gr.field_bytes,
+                                   hipMemcpyDeviceToDevice, b->cap));
+        }
+        if (c->grid.seed == SBI_SEED_PREV || c->grid.seed == SBI_SEED_NET) {
+            char* d0 = static_cast<char*>(c->comp[C_DV]);   // C_DV, C_DB
+            char* h0 = static_cast<char*>(c->comp[C_HV0]);  // C_HV0 .. C_HB0 + kHistTaps - 1
+            SBI_HIP(hipMemcpyAsync(save ? gr.bk_cmp : d0, save ? d0 : gr.bk_cmp, 2 * gr.cmp_bytes,
+                                   hipMemcpyDeviceToDevice, b->cap));
+            SBI_HIP(hipMemcpyAsync(save ? gr.bk_cmp + 2 * gr.cmp_bytes : h0, save ? h0 : gr.bk_cmp + 2 * gr.cmp_bytes,
+                                   2 * kHistTaps * gr.cmp_bytes, hipMemcpyDeviceToDevice, b->cap));
+        }
+        if (save) {
+            gr.bk_have_prev = c->have_prev;
+            gr.bk_hist_count = c->hist_count;
+        } else {
+            c->have_prev = gr.bk_have_prev;
+            c->hist_count = gr.bk_hist_count;
+        }
+    }
+    return SBI_OK;
+}
+
+// enqueue one step call on the batch's stream: replay the instantiated graph
+// (captured again when its key changed) or the eager launches
+static sbi_status batch_launch(sbi_batch* b, sbi_state* states, double dt, int n, double tol) {
+    if (!(b->flags & SBI_BATCH_GRAPH)) return batch_enqueue(b, states, dt, n, tol);
+    std::vector<const void*> ptrs;
+    std::vector<int> prev, budget;
+    for (int i = 0; i < b->m; ++i) {
+        ptrs.push_back(states[i].eta);
+        ptrs.push_back(states[i].phi_s);
+    }
+    // what the captured solves are seeded from: the previous solve, and how
+    // many history entries the learned layer holds; and the sweep budgets
+    for (auto& gr : b->g) {
+        prev.push_back((gr.c->have_prev ? 1 : 0) + 2 * std::min(gr.c->hist_count, gr.c->hist_K));
+        budget.push_back(gr.c->budget);
+    }
+    const bool hit = b->exec && b->key_dt == dt && b->key_tol == tol && b->key_n == n && b->key_ptrs == ptrs &&
+                     b->key_prev == prev && b->key_budget == budget;
+    if (!hit) {
+        if (b->exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        std::vector<int> saved_prof;
+        for (auto& gr : b->g) {
+            saved_prof.push_back(gr.c->prof.on ? 1 : 0);
+            gr.c->prof.on = false;  // no timing events inside a capture
+        }
+        SBI_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        sbi_status st = batch_enqueue(b, states, dt, n, tol);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(b->cap, &graph);
+        for (size_t k = 0; k < b->g.size(); ++k) b->g[k].c->prof.on = saved_prof[k] != 0;
+        if (st < 0) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (e != hipSuccess) return SBI_ERR_HIP;
+        e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            b->exec = nullptr;
+            return SBI_ERR_HIP;
+        }
+        b->key_dt = dt;
+        b->key_tol = tol;
+        b->key_n = n;
+        b->key_ptrs = ptrs;
+        b->key_prev = prev;
+        b->key_budget = budget;
+    }
+    SBI_HIP(hipGraphLaunch(b->exec, b->cap));
+    return SBI_OK;
+}
+
 extern "C" sbi_status sbi_batch_step(sbi_batch* b, sbi_state* states, double dt, int32_t n, double tol,
                                      sbi_step_info* info) {
     if (!b || !states || n < 0 || !std::isfinite(dt)) return SBI_ERR_INVALID_ARG;
@@ -2340,64 +2458,44 @@ extern "C" sbi_status sbi_batch_step(sbi_batch* b, sbi_state* states, double dt,
     // the caller's work before this call happens first
     SBI_HIP(hipEventRecord(b->in, b->stream));
     SBI_HIP(hipStreamWaitEvent(b->cap, b->in, 0));
-    if (b->flags & SBI_BATCH_GRAPH) {
-        std::vector<const void*> ptrs;
-        std::vector<int> prev;
-        for (int i = 0; i < b->m; ++i) {
-            ptrs.push_back(states[i].eta);
-            ptrs.push_back(states[i].phi_s);
+    // Iterations run on a speculative sweep budget (the largest sweep count
+    // of the last call plus a margin): when a solve outruns it, the call is
+    // redone from its saved inputs with the budget doubled, so the results
+    // are those of the full max_sweeps budget.
+    bool speculative = false;
+    for (auto& gr : b->g)
+        speculative |= gr.c->grid.mode == SBI_MODE_ITER && gr.c->budget > 0 && gr.c->budget < gr.c->grid.max_sweeps;
+    for (;;) {
+        if (speculative) SBI_TRY(batch_keep(b, states, true));
+        SBI_TRY(batch_launch(b, states, dt, n, tol));
+        SBI_HIP(hipStreamSynchronize(b->cap));
+        bool redo = false;
+        for (auto& gr : b->g) {
+            sbi_ctx* c = gr.c;
+            SBI_HIP(hipMemcpy(c->head, c->ctl, sizeof(Ctl) * c->batch, hipMemcpyDeviceToHost));
+            if (c->grid.mode != SBI_MODE_ITER) continue;
+            bool undecided = false;
+            for (size_t k = 0; k < gr.members.size(); ++k) undecided |= c->head[k].acc_solves < 4ll * n;
+            if (undecided) {
+                // only a budget below max_sweeps leaves a solve undecided
+                c->budget = std::min(2 * c->budget, c->grid.max_sweeps);
+                redo = true;
+            }
         }
-        // what the captured solves are seeded from: the previous solve, and
-        // how many history entries the learned layer holds
-        for (auto& gr : b->g) prev.push_back((gr.c->have_prev ? 1 : 0) + 2 * std::min(gr.c->hist_count, gr.c->hist_K));
-        const bool hit = b->exec && b->key_dt == dt && b->key_tol == tol && b->key_n == n && b->key_ptrs == ptrs &&
-                         b->key_prev == prev;
-        if (!hit) {
-            if (b->exec) {
-                (void)hipGraphExecDestroy(b->exec);
-                b->exec = nullptr;
-            }
-            std::vector<int> saved_prof;
-            for (auto& gr : b->g) {
-                saved_prof.push_back(gr.c->prof.on ? 1 : 0);
-                gr.c->prof.on = false;  // no timing events inside a capture
-            }
-            SBI_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-            sbi_status st = batch_enqueue(b, states, dt, n, tol);
-            hipGraph_t graph = nullptr;
-            hipError_t e = hipStreamEndCapture(b->cap, &graph);
-            for (size_t k = 0; k < b->g.size(); ++k) b->g[k].c->prof.on = saved_prof[k] != 0;
-            if (st < 0) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return st;
-            }
-            if (e != hipSuccess) return SBI_ERR_HIP;
-            e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) {
-                b->exec = nullptr;
-                return SBI_ERR_HIP;
-            }
-            b->key_dt = dt;
-            b->key_tol = tol;
-            b->key_n = n;
-            b->key_ptrs = ptrs;
-            b->key_prev = prev;
-        }
-        SBI_HIP(hipGraphLaunch(b->exec, b->cap));
-    } else {
-        SBI_TRY(batch_enqueue(b, states, dt, n, tol));
+        if (!redo) break;
+        b->redos += 1;
+        SBI_TRY(batch_keep(b, states, false));
+        speculative = true;
     }
     SBI_HIP(hipEventRecord(b->out, b->cap));
     SBI_HIP(hipStreamWaitEvent(b->stream, b->out, 0));
-    SBI_HIP(hipStreamSynchronize(b->cap));
     sbi_status worst = SBI_OK;
     for (auto& gr : b->g) {
         sbi_ctx* c = gr.c;
-        SBI_HIP(hipMemcpy(c->head, c->ctl, sizeof(Ctl) * c->batch, hipMemcpyDeviceToHost));
+        const bool iter = c->grid.mode == SBI_MODE_ITER;
+        int smax = 0;
         for (size_t k = 0; k < gr.members.size(); ++k) {
             const Ctl& h = c->head[k];
-            const bool iter = c->grid.mode == SBI_MODE_ITER;
             int st = iter ? h.acc_worst : 0;
             if (h.nonfinite) st = SBI_ERR_NONFINITE;
             const int mi = gr.members[k];
@@ -2410,12 +2508,20 @@ extern "C" sbi_status sbi_batch_step(sbi_batch* b, sbi_state* states, double dt,
                 si.sweeps_max = iter ? h.acc_sweeps_max : 0;
                 si.max_residual = iter ? h.acc_residual_max : 0.0;
             }
+            smax = std::max(smax, h.acc_sweeps_max);
             if (st < 0) worst = (worst < 0 && worst < st) ? worst : (sbi_status)st;
             else if (worst >= 0 && st > worst) worst = (sbi_status)st;
         }
         if (worst < 0) {
             c->have_prev = false;
             c->hist_count = 0;
+        }
+        // next budget: the largest sweep count of this call plus a margin;
+        // changed only when it moves by more than the margin (each change is
+        // a new capture)
+        if (iter && n > 0) {
+            const int want = std::min(c->grid.max_sweeps, smax + kBudgetMargin);
+            if (c->budget <= 0 || want > c->budget || want + kBudgetMargin < c->budget) c->budget = want;
         }
     }
     return worst;
@@ -2443,6 +2549,17 @@ extern "C" int32_t sbi_batch_groups(const sbi_batch* b, int32_t* members_out, in
         if (split_out) split_out[i] = b->g[i].c->group_target;
     }
     return ng;
+}
+
+extern "C" int32_t sbi_batch_budgets(const sbi_batch* b, int32_t* budget_out, int32_t n) {
+    if (!b) return 0;
+    const int ng = (int)b->g.size();
+    for (int i = 0; i < ng && i < n; ++i)
+        if (budget_out) {
+            const sbi_ctx* c = b->g[i].c;
+            budget_out[i] = (c->budget > 0 && c->budget < c->grid.max_sweeps) ? c->budget : c->grid.max_sweeps;
+        }
+    return b->redos;
 }
 
 extern "C" sbi_status sbi_batch_destroy(sbi_batch* b) {

@@ -10,6 +10,12 @@ this module only moves tensors and schedules the steps.
 
     python -m paper_2310_19840_amd.warmstart --n 256 --samples 96 --steps 3000 \\
         --out paper_2310_19840_amd/weights/warmstart_c5.sbiw
+
+The history layer (sbi_net.h) is trained by stepping the workload's seas with
+its gradient and Gram sums accumulating in the library, then one Gauss-Newton
+step in the library:
+
+    python -m paper_2310_19840_amd.warmstart history --n 1024 --seeds 10 --steps 500
 """
 from __future__ import annotations
 
@@ -134,6 +140,138 @@ def sweeps_with(blob, seeds, n, device, tol=1e-8, seed_mode="net"):
     return out
 
 
+# ---------------------------------------------------------------------------
+# the learned history layer (sbi_net.h): trained on the GPU by the library's
+# gradient and Gram kernels and its Gauss-Newton step
+# ---------------------------------------------------------------------------
+HISTORY_WEIGHTS = os.path.join(os.path.dirname(__file__), "weights", "history_c5.npz")
+
+
+def history_identity(K: int, nb: int) -> np.ndarray:
+    """Weights of the previous-solve seed (w_0 = 1)."""
+    w = np.zeros((2, 4, nb, K, 2), dtype=np.float32)
+    w[:, :, :, 0, 0] = 1.0
+    return w.ravel()
+
+
+def history_dk(n: int, nb: int) -> float:
+    """Bin width covering the kept band of the workload's grid (dx = lambda_p/8,
+    the same for every n of the recipe) with nb bins."""
+    from sbi_inputs import config_c5
+
+    g = config_c5(seed=0, n=n)["grid"]
+    kband = math.hypot(2 * math.pi * g.mx_max / g.lx, 2 * math.pi * g.my_max / g.ly)
+    return kband / nb * (1.0 + 1e-6)
+
+
+def train_history(n, seeds, steps, K, nb, dk, members, device, tol=1e-10, lam=1e-9, log=None):
+    """Step the workload's seas (groups of `members` in one context) with the
+    layer's gradient and Gram sums accumulating over every stepping solve, then
+    take one Gauss-Newton step.  Returns (weights, mean loss of the identity
+    seed, solves)."""
+    import torch
+
+    from sbi_inputs import config_c5
+
+    seeds = list(seeds)
+    cfgs0 = [config_c5(seed=sd, n=n) for sd in seeds[:members]]
+    g = cfgs0[0]["grid"]
+    s = Solver(g.nx, g.ny, g.lx, g.ly, np.stack([c["depth"] for c in cfgs0]), h_ref=-1.0, batch=members,
+               device=device, mode="iter", precision="fp64", seed="net", accel="anderson", max_sweeps=400)
+    s.hist_load(K, nb, dk, history_identity(K, nb))
+    s.hist_train(True)
+    for i0 in range(0, len(seeds), members):
+        cfgs = [config_c5(seed=sd, n=n) for sd in seeds[i0:i0 + members]]
+        if len(cfgs) < members:
+            break
+        s.set_depth(np.stack([c["depth"] for c in cfgs]))
+        eta = torch.tensor(np.stack([c["eta"] for c in cfgs]), dtype=torch.float64, device=device)
+        phi = torch.tensor(np.stack([c["phi"] for c in cfgs]), dtype=torch.float64, device=device)
+        done = 0
+        while done < steps:
+            k = min(100, steps - done)
+            st, info = s.step(eta, phi, cfgs[0]["dt"], k, tol=tol, t=done * cfgs[0]["dt"])
+            if st < 0:
+                raise RuntimeError(f"training run failed with status {st}")
+            done += k
+        if log:
+            lsum, nsol, _, _ = s.hist_gradient()
+            log(f"history samples after seeds {seeds[i0]}..{seeds[i0] + members - 1}: {nsol} solves, "
+                f"mean loss of the previous-solve seed {lsum / max(nsol, 1):.3e}")
+    loss, nsol = s.hist_newton(lam)
+    w = s.hist_params()
+    s.close()
+    return w, loss, nsol
+
+
+def history_sweeps(w, K, nb, dk, seeds, n, steps, device, tol=1e-8, members=2):
+    """Sweeps per solve over `steps` steps (after one step that fills the
+    history) for the previous-solve seed and the trained layer."""
+    import torch
+
+    from sbi_inputs import config_c5
+
+    out = {}
+    for mode in ("prev", "net"):
+        tot = solves = 0
+        for i0 in range(0, len(seeds), members):
+            cfgs = [config_c5(seed=sd, n=n) for sd in seeds[i0:i0 + members]]
+            g = cfgs[0]["grid"]
+            s = Solver(g.nx, g.ny, g.lx, g.ly, np.stack([c["depth"] for c in cfgs]), h_ref=-1.0, batch=len(cfgs),
+                       device=device, mode="iter", seed=mode, accel="anderson", max_sweeps=400)
+            if mode == "net":
+                s.hist_load(K, nb, dk, w)
+            eta = torch.tensor(np.stack([c["eta"] for c in cfgs]), dtype=torch.float64, device=device)
+            phi = torch.tensor(np.stack([c["phi"] for c in cfgs]), dtype=torch.float64, device=device)
+            s.step(eta, phi, cfgs[0]["dt"], 2, tol=tol)
+            _, info = s.step(eta, phi, cfgs[0]["dt"], steps, tol=tol, t=2 * cfgs[0]["dt"])
+            tot += info["sweeps_total"]
+            solves += info["solves"]
+            s.close()
+        out[mode] = tot / max(solves, 1)
+    return out
+
+
+def main_history(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--seeds", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=500, help="steps per sea (4 solves each)")
+    ap.add_argument("--members", type=int, default=2)
+    ap.add_argument("--taps", type=int, default=8)
+    ap.add_argument("--bins", type=int, default=32)
+    ap.add_argument("--lam", type=float, default=1e-9)
+    ap.add_argument("--eval-steps", type=int, default=16)
+    ap.add_argument("--out", default=HISTORY_WEIGHTS)
+    a = ap.parse_args(argv)
+    import torch
+
+    dev = torch.device("cuda:0")
+
+    def log(m):
+        print(m, flush=True)
+
+    dk = history_dk(a.n, a.bins)
+    t0 = time.time()
+    w, loss, nsol = train_history(a.n, range(2000, 2000 + a.seeds), a.steps, a.taps, a.bins, dk, a.members, dev,
+                                  lam=a.lam, log=log)
+    log(f"trained on {nsol} solves ({a.seeds} seas at {a.n}^2) in {time.time() - t0:.1f} s")
+    held = list(range(6000, 6000 + 2 * a.members))
+    sw = history_sweeps(w, a.taps, a.bins, dk, held, a.n, a.eval_steps, dev, members=a.members)
+    log(f"held-out sweeps per solve at tol 1e-8: previous-solve seed {sw['prev']:.2f}, learned {sw['net']:.2f}")
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    np.savez(a.out, w=w, taps=a.taps, bins=a.bins, dk=dk, solves=nsol, n=a.n, seeds=a.seeds, steps=a.steps,
+             loss_identity=loss, heldout_prev=sw["prev"], heldout_learned=sw["net"])
+    log(f"wrote {a.out}")
+    return 0
+
+
+def load_history(path=HISTORY_WEIGHTS):
+    """(taps, bins, dk, weights) of a trained history layer."""
+    d = np.load(path, allow_pickle=False)
+    return int(d["taps"]), int(d["bins"]), float(d["dk"]), d["w"].astype(np.float32)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=256)
@@ -168,4 +306,6 @@ def main(argv=None):
 
 
 if __name__ == "__main__":
+    if len(sys.argv) > 1 and sys.argv[1] == "history":
+        sys.exit(main_history(sys.argv[2:]))
     sys.exit(main())

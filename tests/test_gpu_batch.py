@@ -136,3 +136,38 @@ def test_autotuned_batch_matches_oracle(gpu):
         o = OSolver(Grid(m["nx"], m["ny"], m["lx"], m["ly"]), m["depth"], mode="iter", max_sweeps=120)
         eo, po, _ = o.step(e, p, DT, 1, tol=1e-11)
         assert np.abs(et[i].cpu().numpy() - eo).max() < 1e-10 * np.abs(eo).max(), i
+
+
+def test_speculative_budget_redo_is_exact(gpu):
+    """Captured iterations run on a sweep budget taken from the previous call;
+    a call whose solves outrun it (here: a tighter tolerance) is redone with a
+    larger budget, and every call equals the eager single-context run bit for
+    bit."""
+    import torch
+    from paper_2310_19840_amd import Batch, Solver
+    mems = [_member(64, 64, 11, seed_mode="prev"), _member(128, 64, 12, seed_mode="prev")]
+    for m, _, _ in mems:
+        m["max_sweeps"] = 200
+        m["accel"] = "anderson"
+    _say("speculative sweep budget")
+    b = Batch([m for m, _, _ in mems], device=gpu, graph=True)
+    et, pt = _tensors(mems, gpu)
+    singles = []
+    for m, e, p in mems:
+        s = Solver(m["nx"], m["ny"], m["lx"], m["ly"], m["depth"], device=gpu, mode="iter", seed="prev",
+                   max_sweeps=200, accel="anderson")
+        singles.append((s, torch.tensor(e, dtype=torch.float64, device=gpu), torch.tensor(p, dtype=torch.float64,
+                                                                                          device=gpu)))
+    budgets = []
+    for call, tol in enumerate((1e-8, 1e-8, 1e-8, 1e-12, 1e-12)):
+        b.step(et, pt, DT, 1, tol=tol)
+        for s, e, p in singles:
+            s.step(e, p, DT, 1, tol=tol)
+        for (s, e, p), eb, pb in zip(singles, et, pt):
+            assert torch.equal(e, eb) and torch.equal(p, pb), call
+        budgets.append(b.budgets())
+    _say("   budgets per call:", budgets)
+    # after the first call the budget follows the sweeps needed, far below the cap
+    assert all(x < 200 for x in budgets[1][0])
+    # the tighter tolerance outran it at least once, and was redone
+    assert budgets[-1][1] >= 1
