@@ -383,7 +383,8 @@ def run_c2_tank(args, dev):
 
 
 def run_c4(args, dev):
-    """The ragged ensemble (32 x 128^2 + 48 x 256^2 + 16 x 512^2), SA mode, FP32, one graph."""
+    """The ragged ensemble (32 x 128^2 + 48 x 256^2 + 16 x 512^2), SA mode, FP32: its 64-step window as one
+    captured graph per call, launch shapes chosen by the autotuner at set-up."""
     import torch
 
     from paper_2310_19840_amd import Batch
@@ -392,7 +393,7 @@ def run_c4(args, dev):
     cfgs = [config_c4_member(m) for m in range(96)]
     mem = [dict(nx=c["grid"].nx, ny=c["grid"].ny, lx=c["grid"].lx, ly=c["grid"].ly, depth=c["depth"],
                 precision="fp32", mode="sa") for c in cfgs]
-    b = Batch(mem, device=dev, graph=True)
+    b = Batch(mem, device=dev, graph=True, autotune=True)
     etas = [torch.tensor(c["eta"], dtype=torch.float32, device=dev) for c in cfgs]
     phis = [torch.tensor(c["phi"], dtype=torch.float32, device=dev) for c in cfgs]
     dt = cfgs[0]["dt"]
@@ -452,7 +453,7 @@ def main():
                     help="sweep cap (max_sweeps) of the captured forms; default: that of the plain form.  Their "
                          "launches follow the speculative budget (largest recent sweep count + 3), not the cap")
     ap.add_argument("--members", type=int, default=2, help="realisations of the batched forms")
-    ap.add_argument("--c4-steps", type=int, default=4)
+    ap.add_argument("--c4-steps", type=int, default=64)
     ap.add_argument("--c3-steps", type=int, default=32)
     ap.add_argument("--c2-steps", type=int, default=256)
     ap.add_argument("--forms",
