@@ -227,6 +227,8 @@ def run_plain(args, dev, precision, tol, accel=None):
     dtype = torch.float64 if precision == "fp64" else torch.float32
     s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="iter", precision=precision,
                max_sweeps=args.max_sweeps, accel=accel)
+    # launch plan from the autotuner (set-up, before the timed region)
+    plan = s.autotune() if args.autotune else s.plan()
     eta = torch.tensor(cfg["eta"][None], dtype=dtype, device=dev)
     phi = torch.tensor(cfg["phi"][None], dtype=dtype, device=dev)
     dt = cfg["dt"]
@@ -258,7 +260,7 @@ def run_plain(args, dev, precision, tol, accel=None):
     return dict(value=g.nx * g.ny * args.steps / el, ms_per_step=1e3 * el / max(args.steps, 1), status=st,
                 sweeps_mean=info["sweeps_total"] / solves, sweeps_max=info["sweeps_max"],
                 max_residual=info["max_residual"], roofline=roof, dominant=dom,
-                kernel_ms={k: round(v[0], 3) for k, v in prof.items() if v[1] > 0}, cfg=cfg)
+                kernel_ms={k: round(v[0], 3) for k, v in prof.items() if v[1] > 0}, plan=plan, cfg=cfg)
 
 
 def run_batched(args, dev, seed_mode, members, accel=None):
@@ -281,7 +283,7 @@ def run_batched(args, dev, seed_mode, members, accel=None):
     mem = [dict(nx=c["grid"].nx, ny=c["grid"].ny, lx=c["grid"].lx, ly=c["grid"].ly, depth=c["depth"],
                 precision="fp64", mode="iter", seed=seed_mode, max_sweeps=args.batch_sweeps, accel=accel)
            for c in cfgs]
-    b = Batch(mem, device=dev, graph=True)
+    b = Batch(mem, device=dev, graph=True, autotune=args.autotune)
     if blob is not None:
         b.net_load(blob)
         b.hist_load(*hist)
@@ -307,7 +309,8 @@ def run_batched(args, dev, seed_mode, members, accel=None):
                 sweeps_mean=sum(x["sweeps_total"] for x in info) / max(solves, 1),
                 sweeps_max=max(x["sweeps_max"] for x in info),
                 max_residual=max(x["max_residual"] for x in info),
-                first_step_sweeps_mean=sum(first) / len(first), sweep_budget=budgets, redone_calls=redos)
+                first_step_sweeps_mean=sum(first) / len(first), sweep_budget=budgets, redone_calls=redos,
+                plans=b.plans())
 
 
 def run_adaptive(args, dev, rk_tol):
@@ -324,6 +327,8 @@ def run_adaptive(args, dev, rk_tol):
     g = cfg["grid"]
     s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="iter", max_sweeps=args.max_sweeps,
                accel=None if args.accel == "none" else args.accel)
+    if args.autotune:
+        s.autotune()
     eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=dev)
     phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=dev)
     dt, tol, Tp = cfg["dt"], cfg["tol"], cfg["period"]
@@ -393,7 +398,7 @@ def run_c4(args, dev):
     cfgs = [config_c4_member(m) for m in range(96)]
     mem = [dict(nx=c["grid"].nx, ny=c["grid"].ny, lx=c["grid"].lx, ly=c["grid"].ly, depth=c["depth"],
                 precision="fp32", mode="sa") for c in cfgs]
-    b = Batch(mem, device=dev, graph=True, autotune=True)
+    b = Batch(mem, device=dev, graph=True, autotune=args.autotune)
     etas = [torch.tensor(c["eta"], dtype=torch.float32, device=dev) for c in cfgs]
     phis = [torch.tensor(c["phi"], dtype=torch.float32, device=dev) for c in cfgs]
     dt = cfgs[0]["dt"]
@@ -405,7 +410,7 @@ def run_c4(args, dev):
     el = time.perf_counter() - t0
     npts = sum(c["grid"].nx * c["grid"].ny for c in cfgs)
     return dict(value=npts * args.c4_steps / el, ms_per_step=1e3 * el / args.c4_steps, status=st, members=96,
-                points=npts, steps=args.c4_steps, groups=b.groups())
+                points=npts, steps=args.c4_steps, groups=b.groups(), plans=b.plans())
 
 
 def run_c3_precision(args, dev):
@@ -424,6 +429,7 @@ def run_c3_precision(args, dev):
     fields = {}
     for prec, dt_ in (("fp64", torch.float64), ("fp32", torch.float32)):
         s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="sa", precision=prec)
+        plan = s.autotune() if args.autotune else s.plan()
         eta = torch.tensor(cfg["eta"][None], dtype=dt_, device=dev)
         phi = torch.tensor(cfg["phi"][None], dtype=dt_, device=dev)
         m0, e0 = s.diagnostics(eta, phi)
@@ -434,7 +440,7 @@ def run_c3_precision(args, dev):
         el = time.perf_counter() - t0
         m1, e1 = s.diagnostics(eta, phi)
         fields[prec] = eta.double().cpu().numpy()[0]
-        out[prec] = dict(value=g.nx * g.ny * args.c3_steps / el, ms_per_step=1e3 * el / args.c3_steps,
+        out[prec] = dict(value=g.nx * g.ny * args.c3_steps / el, ms_per_step=1e3 * el / args.c3_steps, plan=plan,
                          energy_drift=float(abs(e1[0] - e0[0]) / abs(e0[0])),
                          mass_change=float(abs(m1[0] - m0[0])))
     err = float(np.abs(fields["fp32"] - fields["fp64"]).max() / np.abs(fields["fp64"]).max())
@@ -466,6 +472,8 @@ def main():
                     help="error bound of the adaptive form; at 3e-7 its global error over two periods of a "
                          "128^2 sample of the sea (1.9e-7) is below that of fixed RK4 at T_p/64 (4.9e-7)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the default launch plans instead of the autotuner's")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -489,7 +497,8 @@ def main():
     roofline = dict(plain["roofline"])
     roofline["traffic"] = round(traffic) if traffic is not None else None
     out_forms = {"plain": {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in plain.items()
-                           if k in ("value", "ms_per_step", "sweeps_mean", "sweeps_max", "max_residual", "status")}}
+                           if k in ("value", "ms_per_step", "sweeps_mean", "sweeps_max", "max_residual", "status",
+                                    "plan")}}
     if "batched+prev" in forms:
         out_forms["batched+prev"] = run_batched(args, dev, "prev", args.members, accel)
     if "batched+learned" in forms:
@@ -499,7 +508,7 @@ def main():
         f32.pop("cfg")
         out_forms["plain-fp32"] = {k: v for k, v in f32.items() if k in ("value", "ms_per_step", "sweeps_mean",
                                                                           "sweeps_max", "max_residual", "status",
-                                                                          "roofline")}
+                                                                          "roofline", "plan")}
         out_forms["plain-fp32"]["tol"] = 1e-6
     if "plain-relaxed" in forms:
         rx = run_plain(args, dev, "fp64", 1e-8, accel=None)

@@ -322,6 +322,72 @@ int32_t sbi_profile_read(sbi_ctx* ctx, const char** names, double* total_ms, int
  * number of doubles written (<= n): {kernel launches, host syncs, sweeps}. */
 int32_t sbi_last_stats(const sbi_ctx* ctx, double* out, int32_t n);
 
+/*
+ * Launch plans and the autotuner.  A plan fixes, for one context, how its
+ * transforms are launched; it changes rounding order only, never what is
+ * computed (every plan meets the same parity bars against the FP64 oracle).
+ *   row_variant  radix sequence and twiddle mode of the row sweep (iteration)
+ *                or row SA kernels: 0 radix-8 passes with twiddle powers by
+ *                recurrence (the default); 1 radix-8 with every twiddle power
+ *                cached in registers; 2 radix-16 passes.  Which variants are
+ *                built depends on precision and row length (only variants that
+ *                compile without register spills): sbi_plan_variants().
+ *   row_rows     rows of the grid per row-pass workgroup (a power of two; 0:
+ *                as many as fill 256 threads, the default).
+ *   col_split    workgroups a column pass should reach by splitting its
+ *                products over workgroups along y (0: no split, the default;
+ *                only 2D grids split).
+ *   us           time of the tuned unit under this plan in microseconds (one
+ *                sweep in iteration mode, one W solve in SA mode), 0 when the
+ *                plan was set rather than measured.
+ *   cached       1 when sbi_autotune took the plan from the plan cache.
+ */
+typedef struct sbi_plan {
+    int32_t row_variant;
+    int32_t row_rows;
+    int32_t col_split;
+    float us;
+    int32_t cached;
+} sbi_plan;
+
+/* Bit v of the result is set when row variant v is built for the context's
+   precision, mode and row length. */
+int32_t sbi_plan_variants(const sbi_ctx* ctx);
+
+sbi_status sbi_plan_get(const sbi_ctx* ctx, sbi_plan* out);
+
+/* Use the given plan from the next call on.  Errors (plan unchanged):
+   SBI_ERR_UNSUPPORTED for a variant not built here; SBI_ERR_INVALID_ARG for
+   row_rows that is negative or not a power of two, or a negative col_split. */
+sbi_status sbi_plan_set(sbi_ctx* ctx, const sbi_plan* plan);
+
+/*
+ * Autotuner: times every built row variant, rows per workgroup from the
+ * launch bound down to a quarter of it, and column splits {0, 1024, 2048,
+ * 4096} (2D grids), each on the context's own kernels and workspace (5 units
+ * after 2 of warm-up, best of two rounds, HIP events on the context's
+ * stream), and keeps the fastest.  The plan cache, a process-wide table keyed
+ * by device (name and architecture), grid size, batch, precision, mode,
+ * acceleration, order and whether the bed varies, is consulted first: a hit
+ * is applied without timing unless flags has SBI_TUNE_FORCE, and every search
+ * stores its result there.  Running the kernels overwrites the iteration's
+ * carried state: the previous-solve seed and the history layer's history are
+ * emptied, as after sbi_set_depth.  Synchronises the stream.  out may be NULL.
+ */
+enum { SBI_TUNE_FORCE = 1 };
+sbi_status sbi_autotune(sbi_ctx* ctx, int32_t flags, sbi_plan* out);
+
+/*
+ * The plan cache as a text file: a header line, then one line per entry
+ * "<key> <row_variant> <row_rows> <col_split> <us>" (the key has no spaces).
+ * Load merges a file into the table (entries of the file win; lines that do
+ * not parse are skipped; a missing file is SBI_ERR_INVALID_ARG); save writes
+ * the whole table.  Both are host-only and take no context; they return the
+ * number of entries read or written through *count when count is not NULL.
+ */
+sbi_status sbi_tune_cache_load(const char* path, int32_t* count);
+sbi_status sbi_tune_cache_save(const char* path, int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

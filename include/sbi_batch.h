@@ -6,11 +6,18 @@
  * state); nothing couples members.  Members with identical grids are grouped
  * into one context whose kernels carry the members along their batch
  * dimension; the groups run concurrently on streams forked from the caller's
- * stream.  With SBI_BATCH_GRAPH the whole n-step call is captured once into a
- * HIP graph and replayed: later calls with the same (dt, n, tol, state
- * pointers) launch the instantiated graph.  With SBI_BATCH_AUTOTUNE the
- * column-pass layout of each group (how a pass's products are split over
- * workgroups) is chosen by timing the candidates on the device at init.
+ * stream.  With SBI_BATCH_GRAPH a step call runs as captured HIP graphs: a
+ * prologue (states in, to spectral space), the steps in parts of at most 4
+ * (short graphs replay faster per step than one long graph), and an epilogue
+ * (back to physical space, states out); the spectral states stay in the
+ * workspace between parts, so the result does not depend on the split.  Each
+ * part is captured once and replayed by later calls with the same (dt, n,
+ * tol, state pointers, seeds and sweep budgets); up to 8 instantiated graphs
+ * are kept, least recently used first out.  With SBI_BATCH_AUTOTUNE each
+ * group's launch plan (row-transform radix and twiddle mode, rows per row
+ * workgroup, column-pass product split; sbi.h, sbi_plan) is chosen at init by
+ * sbi_autotune on the group's context, consulting the process's plan cache
+ * first (sbi_tune_cache_load / _save persist it).
  *
  * Iterations run without host polling: each solve enqueues the sweep
  * launches of a budget B and a member's launches after the pass that decides
@@ -74,8 +81,11 @@ sbi_status sbi_batch_net_load(sbi_batch* b, const void* weights, size_t bytes);
 sbi_status sbi_batch_net_hist_load(sbi_batch* b, int32_t taps, int32_t bins, double dk, const float* w);
 
 /* Number of member groups and, per group (g < groups), its member count and
-   the column-pass split the autotuner chose (0: none). */
+   the column-pass split of its plan (0: none). */
 int32_t sbi_batch_groups(const sbi_batch* b, int32_t* members_out, int32_t* split_out, int32_t n);
+
+/* Launch plan of group g (sbi.h, sbi_plan; us and cached are 0). */
+sbi_status sbi_batch_plan(const sbi_batch* b, int32_t g, sbi_plan* out);
 
 /* Current sweep budget of each group (host int32 [n]; max_sweeps when none is
    set); returns the number of step calls redone with a larger budget since

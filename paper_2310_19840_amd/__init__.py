@@ -7,6 +7,7 @@ computation runs in the library's HIP kernels.
 from __future__ import annotations
 
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -89,6 +90,28 @@ def vertical_velocity_noalloc(eta, phi_s, depth, nx, ny, lx, ly=1.0, h_ref=-1.0,
     if st < 0:
         raise SBIError(st, "sbi_vertical_velocity_noalloc", res)
     return out, st, res
+
+
+def _plan_dict(p):
+    return dict(row_variant=p.row_variant, row_rows=p.row_rows, col_split=p.col_split, us=p.us, cached=bool(p.cached))
+
+
+def tune_cache_load(path: str) -> int:
+    """Merge a plan-cache file into the process's plan cache; returns the entries read."""
+    n = C.c_int32(0)
+    st = _lib.load().sbi_tune_cache_load(os.fsencode(path), C.byref(n))
+    if st < 0:
+        raise SBIError(st, "sbi_tune_cache_load")
+    return n.value
+
+
+def tune_cache_save(path: str) -> int:
+    """Write the process's plan cache to a file; returns the entries written."""
+    n = C.c_int32(0)
+    st = _lib.load().sbi_tune_cache_save(os.fsencode(path), C.byref(n))
+    if st < 0:
+        raise SBIError(st, "sbi_tune_cache_save")
+    return n.value
 
 
 def workspace_bytes(grid: _lib.sbi_grid, batch: int = 1) -> int:
@@ -185,6 +208,32 @@ class Solver:
         if st < 0:
             raise SBIError(st, "sbi_diagnostics")
         return np.array(m[:]), np.array(e[:])
+
+    # -- launch plans -----------------------------------------------------------
+    def plan_variants(self):
+        """Row variants built for this context (list of variant numbers)."""
+        m = self.lib.sbi_plan_variants(self.ctx)
+        return [v for v in range(3) if (m >> v) & 1]
+
+    def plan(self):
+        p = _lib.sbi_plan()
+        st = self.lib.sbi_plan_get(self.ctx, C.byref(p))
+        if st < 0:
+            raise SBIError(st, "sbi_plan_get")
+        return _plan_dict(p)
+
+    def set_plan(self, row_variant=0, row_rows=0, col_split=0):
+        p = _lib.sbi_plan(int(row_variant), int(row_rows), int(col_split), 0.0, 0)
+        st = self.lib.sbi_plan_set(self.ctx, C.byref(p))
+        if st < 0:
+            raise SBIError(st, "sbi_plan_set")
+
+    def autotune(self, force=False):
+        p = _lib.sbi_plan()
+        st = self.lib.sbi_autotune(self.ctx, _lib.SBI_TUNE_FORCE if force else 0, C.byref(p))
+        if st < 0:
+            raise SBIError(st, "sbi_autotune")
+        return _plan_dict(p)
 
     # -- learned warm start ----------------------------------------------------
     def net_load(self, blob: bytes):
@@ -494,6 +543,17 @@ class Batch:
         spl = (C.c_int32 * 64)()
         k = self.lib.sbi_batch_groups(self.b, mem, spl, 64)
         return [(mem[i], spl[i]) for i in range(min(k, 64))]
+
+    def plans(self):
+        """Launch plan of each group."""
+        out = []
+        for g in range(len(self.groups())):
+            p = _lib.sbi_plan()
+            st = self.lib.sbi_batch_plan(self.b, g, C.byref(p))
+            if st < 0:
+                raise SBIError(st, "sbi_batch_plan")
+            out.append(_plan_dict(p))
+        return out
 
     def close(self):
         if getattr(self, "b", None):

@@ -58,6 +58,13 @@ class sbi_adapt_info(C.Structure):
                 ("err_last", C.c_double), ("err_max", C.c_double), ("solve", sbi_step_info)]
 
 
+class sbi_plan(C.Structure):
+    _fields_ = [("row_variant", C.c_int32), ("row_rows", C.c_int32), ("col_split", C.c_int32), ("us", C.c_float),
+                ("cached", C.c_int32)]
+
+
+SBI_TUNE_FORCE = 1
+
 # exported symbols and their signatures: (restype, argtypes)
 SIGNATURES = {
     "sbi_grid_defaults": (None, [C.POINTER(sbi_grid)]),
@@ -109,6 +116,13 @@ SIGNATURES = {
     "sbi_net_trainer_adam": (C.c_int, [C.c_void_p, C.c_float]),
     "sbi_net_trainer_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
     "sbi_net_trainer_destroy": (C.c_int, [C.c_void_p]),
+    # launch plans and the autotuner (sbi.h)
+    "sbi_plan_variants": (C.c_int32, [C.c_void_p]),
+    "sbi_plan_get": (C.c_int, [C.c_void_p, C.POINTER(sbi_plan)]),
+    "sbi_plan_set": (C.c_int, [C.c_void_p, C.POINTER(sbi_plan)]),
+    "sbi_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(sbi_plan)]),
+    "sbi_tune_cache_load": (C.c_int, [C.c_char_p, C.POINTER(C.c_int32)]),
+    "sbi_tune_cache_save": (C.c_int, [C.c_char_p, C.POINTER(C.c_int32)]),
     # ensembles of uneven grids (sbi_batch.h)
     "sbi_batch_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(sbi_grid)]),
     "sbi_batch_init": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(sbi_grid),
@@ -118,6 +132,7 @@ SIGNATURES = {
                                  C.POINTER(sbi_step_info)]),
     "sbi_batch_groups": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32]),
     "sbi_batch_budgets": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32]),
+    "sbi_batch_plan": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(sbi_plan)]),
     "sbi_batch_destroy": (C.c_int, [C.c_void_p]),
     "sbi_batch_net_load": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "sbi_batch_net_hist_load": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_double, C.POINTER(C.c_float)]),

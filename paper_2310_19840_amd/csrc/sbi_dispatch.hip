@@ -86,6 +86,13 @@ SBI_DISPATCH(launch_row_blend, RowBlendParams)
 SBI_DISPATCH(launch_row_feat, RowFeatParams)
 SBI_DISPATCH(launch_col, ColParams)
 
+int row_var_mask(int fp64, int sweep, int nx) {
+    return fp64 ? row_var_mask_t<double>(sweep, nx) : row_var_mask_t<float>(sweep, nx);
+}
+int row_rows_cap(int fp64, int nx, int var) {
+    return fp64 ? row_rows_cap_t<double>(nx, var) : row_rows_cap_t<float>(nx, var);
+}
+
 hipError_t launch_rk(int fp64, const RkParams& p, int batch, hipStream_t s) {
     return fp64 ? launch_rk_t<double>(p, batch, s) : launch_rk_t<float>(p, batch, s);
 }

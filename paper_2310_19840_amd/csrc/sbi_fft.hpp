@@ -189,6 +189,7 @@ template <int N, int E, int Ns, int Cur> struct TwOffset<N, E, Ns, Cur, true> {
 // Per-thread twiddle cache: the base twiddles of every pass for thread j,
 // loaded once and reused by every transform of the same length.
 template <typename V, int N, int E> struct Twid {
+    static constexpr bool ALL = false;
     static constexpr int NT = TwCountFrom<N, E, 1>::value;
     V w[NT > 0 ? NT : 1];
     // tw: table of exp(-2 pi i m / (N stride)), read at every stride-th entry
@@ -211,6 +212,49 @@ template <typename V, int N, int E> struct Twid {
     __device__ __forceinline__ void load(const V* __restrict__ tw, int j, int stride = 1) { load_from<1>(tw, j, stride); }
 };
 
+// Per-thread cache of every twiddle power a pass uses: for each butterfly of
+// each pass with Ns > 1, the R - 1 powers w^1 .. w^(R-1) of its base twiddle,
+// read from the table rather than formed by recurrence.  It takes R - 1 times
+// the registers of Twid and saves the R - 2 complex products per butterfly
+// that the recurrence spends; a launch plan chooses between the two.
+template <int N, int E, int Ns, bool DONE = (Ns >= N)> struct TwAllCountFrom {
+    using PI = PassInfo<N, E, Ns>;
+    static constexpr int value = (Ns > 1 ? PI::B * (PI::R - 1) : 0) + TwAllCountFrom<N, E, PI::NEXT>::value;
+};
+template <int N, int E, int Ns> struct TwAllCountFrom<N, E, Ns, true> {
+    static constexpr int value = 0;
+};
+template <int N, int E, int Ns, int Cur = 1, bool AT = (Cur == Ns)> struct TwAllOffset {
+    using PI = PassInfo<N, E, Cur>;
+    static constexpr int value = (Cur > 1 ? PI::B * (PI::R - 1) : 0) + TwAllOffset<N, E, Ns, PI::NEXT>::value;
+};
+template <int N, int E, int Ns, int Cur> struct TwAllOffset<N, E, Ns, Cur, true> {
+    static constexpr int value = 0;
+};
+template <typename V, int N, int E> struct TwidAll {
+    static constexpr bool ALL = true;
+    static constexpr int NT = TwAllCountFrom<N, E, 1>::value;
+    V w[NT > 0 ? NT : 1];
+    template <int Ns> __device__ __forceinline__ void load_from(const V* __restrict__ tw, int j, int stride) {
+        if constexpr (Ns < N) {
+            using PI = PassInfo<N, E, Ns>;
+            if constexpr (Ns > 1) {
+                constexpr int off = TwAllOffset<N, E, Ns>::value;
+                constexpr int P = N / E;
+#pragma unroll
+                for (int s = 0; s < PI::B; ++s) {
+                    const int k = (j + s * P) & (Ns - 1);
+                    // r k < R Ns, so the index stays inside the length-N table
+#pragma unroll
+                    for (int r = 1; r < PI::R; ++r) w[off + s * (PI::R - 1) + r - 1] = tw[stride * r * k * (N / (Ns * PI::R))];
+                }
+            }
+            load_from<PI::NEXT>(tw, j, stride);
+        }
+    }
+    __device__ __forceinline__ void load(const V* __restrict__ tw, int j, int stride = 1) { load_from<1>(tw, j, stride); }
+};
+
 // LDS slot of transform element idx: the first Stockham pass writes with a
 // stride of E elements (E x 16 B in FP64), which folds a wavefront onto a few
 // LDS banks; one pad slot per E elements spreads every pass over all banks.
@@ -221,8 +265,8 @@ template <int N, int E> __host__ __device__ constexpr int fft_lds_elems() { retu
 // One Stockham pass of radix R with current span Ns (product of earlier radices).
 // WAVE: all threads of the transform are in one wavefront (exchanges need no
 // workgroup barrier).
-template <typename V, int N, int E, int R, int Ns, bool INV, bool LAST, int LS, bool WAVE>
-__device__ __forceinline__ void stockham_pass(V (&v)[E], V* lds, int lo, int j, const Twid<V, N, E>& tw) {
+template <typename V, int N, int E, int R, int Ns, bool INV, bool LAST, int LS, bool WAVE, typename TW>
+__device__ __forceinline__ void stockham_pass(V (&v)[E], V* lds, int lo, int j, const TW& tw) {
     constexpr int P = N / E;
     constexpr int B = E / R;
 #pragma unroll
@@ -232,7 +276,16 @@ __device__ __forceinline__ void stockham_pass(V (&v)[E], V* lds, int lo, int j, 
         V u[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) u[r] = v[s + r * B];
-        if constexpr (Ns > 1) {
+        if constexpr (Ns > 1 && TW::ALL) {
+            // every power from the cache
+            constexpr int off = TwAllOffset<N, E, Ns>::value;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                V wr = tw.w[off + s * (R - 1) + r - 1];
+                if (INV) wr.y = -wr.y;
+                u[r] = cmul(u[r], wr);
+            }
+        } else if constexpr (Ns > 1) {
             // base twiddle from the cache; higher powers by recurrence
             V w1 = tw.w[TwOffset<N, E, Ns>::value + s];
             if constexpr (E >= 8) {
@@ -271,7 +324,8 @@ __device__ __forceinline__ void stockham_pass(V (&v)[E], V* lds, int lo, int j, 
 template <typename V, int N, int E, int Ns, bool INV, int LS, bool WAVE>
 struct StockhamRun {
     using PI = PassInfo<N, E, Ns>;
-    static __device__ __forceinline__ void run(V (&v)[E], V* lds, int lo, int j, const Twid<V, N, E>& tw) {
+    template <typename TW>
+    static __device__ __forceinline__ void run(V (&v)[E], V* lds, int lo, int j, const TW& tw) {
         stockham_pass<V, N, E, PI::R, Ns, INV, PI::LAST, LS, WAVE>(v, lds, lo, j, tw);
         if constexpr (!PI::LAST) StockhamRun<V, N, E, PI::NEXT, INV, LS, WAVE>::run(v, lds, lo, j, tw);
     }
@@ -281,9 +335,8 @@ struct StockhamRun {
 // with WAVE only the wavefront holding the transform does).  On return every
 // thread of the transform has passed the last read of its exchange area only
 // when WAVE is false.
-template <typename V, int N, bool INV, int LS, int EMAX = 8, bool WAVE = false>
-__device__ __forceinline__ void fft(V (&v)[(FftShape<N, EMAX>::E)], V* lds, int lo, int j,
-                                    const Twid<V, N, FftShape<N, EMAX>::E>& tw) {
+template <typename V, int N, bool INV, int LS, int EMAX = 8, bool WAVE = false, typename TW>
+__device__ __forceinline__ void fft(V (&v)[(FftShape<N, EMAX>::E)], V* lds, int lo, int j, const TW& tw) {
     if constexpr (N > 1) StockhamRun<V, N, FftShape<N, EMAX>::E, 1, INV, LS, WAVE>::run(v, lds, lo, j, tw);
 }
 

@@ -101,6 +101,11 @@ struct GridDev {
     int relax;
     int qb;             // kept band below ny/4 and ny >= 128: the quarter-band column pass
     int col_C;          // columns per column-pass workgroup (Kxp is a multiple)
+    // launch plan of the row sweep and SA kernels (the autotuner's choice):
+    // row_var 0 radix-8 with twiddle recurrence, 1 radix-8 with every twiddle
+    // power cached, 2 radix-16 (FP32, rows of 512 or more); row_rpw rows per
+    // workgroup (0: as many as fit 256 threads)
+    int row_var, row_rpw;
 };
 
 // Multiplier of one contribution to a column-pass accumulator:

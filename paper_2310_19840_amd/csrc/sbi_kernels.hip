@@ -10,6 +10,7 @@
 // iterate directly from registers.  Only kept modes are ever written, so the
 // spectra in memory are 1/4 (2D) of the full size.
 #include <math.h>
+#include <type_traits>
 #include "sbi_fft.hpp"
 #include "sbi_kernels.hpp"
 
@@ -127,11 +128,14 @@ constexpr int row_pitch(int e0, int vbytes) {
     return ls;
 }
 
-template <typename R, int NX> struct Row {
+// EM: elements per thread of the row transform (its radix sequence: 8 gives
+// radix-8 passes, 16 radix-16 ones); TWC: every twiddle power held in
+// registers instead of formed by recurrence.  Both are launch-plan choices.
+template <typename R, int NX, int EM = 8, bool TWC = false> struct Row {
     using V = typename cplx_of<R>::type;
     static constexpr int N = NX / 2;
-    static constexpr int E = FftShape<N>::E;
-    static constexpr int P = FftShape<N>::P;
+    static constexpr int E = FftShape<N, EM>::E;
+    static constexpr int P = FftShape<N, EM>::P;
     static constexpr int LS = row_pitch(fft_lds_elems<N, E>(), (int)sizeof(V));
     // a row of up to 64 threads lies in one wavefront: its transform's LDS
     // exchanges need only wave-level ordering
@@ -142,7 +146,7 @@ template <typename R, int NX> struct Row {
     // stage their kept spectra through LDS with coalesced column segments.
     // z[n] = f[2n] + i f[2n+1] has Z[m] = (F[m] + conj F[N-m]) / 2
     //   + i (F[m] - conj F[N-m]) / 2 * exp(+2 pi i m / NX).
-    using TW = Twid<V, N, E>;
+    using TW = typename std::conditional<TWC, TwidAll<V, N, E>, Twid<V, N, E>>::type;
     static __device__ __forceinline__ void inverse(V (&v)[E], const V* __restrict__ G, const V* __restrict__ G2,
                                                    R c2, const RowCtx& rc, V* lds_all,
                                                    const TW& twN, const V* __restrict__ twX, R scale) {
@@ -204,7 +208,7 @@ template <typename R, int NX> struct Row {
             }
         }
         xfer_sync<WAVE>();  // the row's staged values are in registers before the exchanges reuse them
-        fft<V, N, true, 1, 8, WAVE>(v, lds, 0, rc.j, twN);
+        fft<V, N, true, 1, EM, WAVE>(v, lds, 0, rc.j, twN);
 #pragma unroll
         for (int q = 0; q < E; ++q) v[q] = cscale(v[q], scale);
     }
@@ -217,7 +221,7 @@ template <typename R, int NX> struct Row {
         V* lds = lds_all + rc.rl * LS;
         // other rows touch this row's LDS only in the staging and store loops,
         // each closed by a workgroup barrier
-        fft<V, N, false, 1, 8, WAVE>(v, lds, 0, rc.j, twN);
+        fft<V, N, false, 1, EM, WAVE>(v, lds, 0, rc.j, twN);
         xfer_sync<WAVE>();  // the row's last exchange reads are done before it is overwritten
 #pragma unroll
         for (int q = 0; q < E; ++q) lds[rc.j + q * P] = v[q];
@@ -252,9 +256,17 @@ template <typename R, int NX> struct Row {
 };
 
 // threads per row-pass workgroup: rows of P threads packed up to 256 threads
-template <int NX> __host__ __device__ constexpr int row_threads() {
-    return FftShape<NX / 2>::P > 256 ? FftShape<NX / 2>::P : 256;
+template <int NX, int EM = 8> __host__ __device__ constexpr int row_threads() {
+    return FftShape<NX / 2, EM>::P > 256 ? FftShape<NX / 2, EM>::P : 256;
 }
+
+// Row transform of launch-plan variant VAR of the sweep and SA kernels:
+// 0 radix-8 passes with twiddle recurrence, 1 the same with every twiddle
+// power cached, 2 radix-16 passes
+template <typename R, int NX, int VAR> struct RowVarT {
+    using type = Row<R, NX, VAR == 2 ? 16 : 8, VAR == 1>;
+};
+template <typename R, int NX, int VAR> using RowVar = typename RowVarT<R, NX, VAR>::type;
 
 // Workgroups are dealt to the 8 XCDs round-robin by launch order, and each
 // XCD has its own L2.  Neighbouring row groups read neighbouring pieces of the
@@ -282,8 +294,8 @@ template <int P> __device__ __forceinline__ RowCtx row_ctx(const GridDev& g) {
     return r;
 }
 
-#define ROW_PROLOGUE(R, NX)                                              \
-    using RW = Row<R, NX>;                                               \
+#define ROW_PROLOGUE_T(...)                                              \
+    using RW = __VA_ARGS__;                                              \
     using V = typename RW::V;                                            \
     constexpr int E = RW::E;                                             \
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];                          \
@@ -304,6 +316,7 @@ template <int P> __device__ __forceinline__ RowCtx row_ctx(const GridDev& g) {
     V* const twX = lds_all + rc.rpw * RW::LS;                            \
     for (int i_ = rc.t; i_ < RW::N; i_ += rc.nthr) twX[i_] = twX_tab[i_]; \
     (void)po; (void)iscale; (void)hb;
+#define ROW_PROLOGUE(R, NX) ROW_PROLOGUE_T(Row<R, NX>)
 
 // ---------------------------------------------------------------------------
 // Row kernels
@@ -408,12 +421,12 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupP
     }
 }
 
-template <typename R, int NX, bool AA>
+template <typename R, int NX, bool AA, int VAR>
 __device__ __forceinline__ void row_sweep_body(const RowSweepParams& p, const typename cplx_of<R>::type* twN_tab,
                                                const typename cplx_of<R>::type* twX_tab) {
     Ctl* ctl = p.ctl + blockIdx.z;
     if (ctl->done) return;  // block-uniform: the member's solve is decided
-    ROW_PROLOGUE(R, NX)
+    ROW_PROLOGUE_T(RowVar<R, NX, VAR>)
     const int fam = blockIdx.y;  // product family of this workgroup
     if (fam == 0) {
         V vv[E];
@@ -490,24 +503,26 @@ __device__ __forceinline__ void row_sweep_body(const RowSweepParams& p, const ty
     }
 }
 
-template <typename R, int NX>
-__global__ void __launch_bounds__(row_threads<NX>(), 3) k_row_sweep(const RowSweepParams p, const typename cplx_of<R>::type* twN_tab,
-                            const typename cplx_of<R>::type* twX_tab) {
-    row_sweep_body<R, NX, false>(p, twN_tab, twX_tab);
+template <typename R, int NX, int VAR>
+__global__ void __launch_bounds__((row_threads<NX, RowVar<R, NX, VAR>::E>()), 3)
+    k_row_sweep(const RowSweepParams p, const typename cplx_of<R>::type* twN_tab,
+                const typename cplx_of<R>::type* twX_tab) {
+    row_sweep_body<R, NX, false, VAR>(p, twN_tab, twX_tab);
 }
 
 // the same with the residual's denominator given as a third half form (Anderson mixing)
-template <typename R, int NX>
-__global__ void __launch_bounds__(row_threads<NX>(), 3) k_row_sweep_aa(const RowSweepParams p,
-                                                                       const typename cplx_of<R>::type* twN_tab,
-                                                                       const typename cplx_of<R>::type* twX_tab) {
-    row_sweep_body<R, NX, true>(p, twN_tab, twX_tab);
+template <typename R, int NX, int VAR>
+__global__ void __launch_bounds__((row_threads<NX, RowVar<R, NX, VAR>::E>()), 3)
+    k_row_sweep_aa(const RowSweepParams p, const typename cplx_of<R>::type* twN_tab,
+                   const typename cplx_of<R>::type* twX_tab) {
+    row_sweep_body<R, NX, true, VAR>(p, twN_tab, twX_tab);
 }
 
-template <typename R, int NX>
-__global__ void __launch_bounds__(row_threads<NX>()) k_row_sa(const RowSaParams p, const typename cplx_of<R>::type* twN_tab,
-                         const typename cplx_of<R>::type* twX_tab) {
-    ROW_PROLOGUE(R, NX)
+template <typename R, int NX, int VAR>
+__global__ void __launch_bounds__((row_threads<NX, RowVar<R, NX, VAR>::E>()))
+    k_row_sa(const RowSaParams p, const typename cplx_of<R>::type* twN_tab,
+             const typename cplx_of<R>::type* twX_tab) {
+    ROW_PROLOGUE_T(RowVar<R, NX, VAR>)
     const int l = p.l;
     int idx = 0;
     V a[E], base[E], pw[E];
@@ -1969,31 +1984,23 @@ __global__ void k_diag(const DiagParams p) {
 template <typename PT> static int row_families(const PT&) { return 1; }
 static int row_families(const RowSweepParams& p) { return p.nfam > 0 ? p.nfam : 1; }
 
-template <typename R, int NX> struct RowLaunch {
-    using V = typename cplx_of<R>::type;
-    static void shape(int ny, dim3* grid, dim3* block, size_t* lds, int batch, int nfam) {
-        constexpr int P = Row<R, NX>::P;
-        // rows per workgroup: a power of two dividing ny (sizes are powers of
-        // two), which the row kernels rely on
-        int rpw = 256 / P;
-        if (rpw < 1) rpw = 1;
+template <typename RWT> struct RowLaunch {
+    using V = typename RWT::V;
+    // rpw_req: rows per workgroup asked for by the launch plan (0: as many as
+    // fit 256 threads); it is a power of two, as ny is, which the row
+    // kernels rely on, and capped by the kernels' launch bounds
+    static void shape(int ny, dim3* grid, dim3* block, size_t* lds, int batch, int nfam, int rpw_req = 0) {
+        constexpr int P = RWT::P;
+        const int cap = P >= 256 ? 1 : 256 / P;
+        int rpw = (rpw_req > 0 && rpw_req < cap) ? rpw_req : cap;
         if (rpw > ny) rpw = ny;
         *block = dim3(P * rpw);
         *grid = dim3((ny + rpw - 1) / rpw, nfam, batch);
-        *lds = ((size_t)rpw * Row<R, NX>::LS + Row<R, NX>::N) * sizeof(V);
+        *lds = ((size_t)rpw * RWT::LS + RWT::N) * sizeof(V);
     }
 };
 
-#define SBI_ROW_LAUNCH(KNAME, PTYPE)                                                                       \
-    template <typename R, int NX>                                                                          \
-    static hipError_t KNAME##_go(const PTYPE& p, int batch, const Twiddles& tw, hipStream_t s) {           \
-        using V = typename cplx_of<R>::type;                                                               \
-        dim3 grid, block;                                                                                  \
-        size_t lds;                                                                                        \
-        RowLaunch<R, NX>::shape(p.g.ny, &grid, &block, &lds, batch, row_families(p));                      \
-        hipLaunchKernelGGL((KNAME<R, NX>), grid, block, lds, s, p, (const V*)tw.tn, (const V*)tw.tx);      \
-        return hipGetLastError();                                                                          \
-    }                                                                                                      \
+#define SBI_ROW_NX_SWITCH(KNAME, PTYPE)                                                                    \
     template <typename R>                                                                                  \
     static hipError_t KNAME##_nx(const PTYPE& p, int batch, const Twiddles& tw, hipStream_t s) {           \
         switch (p.g.nx) {                                                                                  \
@@ -2011,12 +2018,65 @@ template <typename R, int NX> struct RowLaunch {
         }                                                                                                  \
     }
 
+#define SBI_ROW_LAUNCH(KNAME, PTYPE)                                                                       \
+    template <typename R, int NX>                                                                          \
+    static hipError_t KNAME##_go(const PTYPE& p, int batch, const Twiddles& tw, hipStream_t s) {           \
+        using V = typename cplx_of<R>::type;                                                               \
+        dim3 grid, block;                                                                                  \
+        size_t lds;                                                                                        \
+        RowLaunch<Row<R, NX>>::shape(p.g.ny, &grid, &block, &lds, batch, row_families(p));                  \
+        hipLaunchKernelGGL((KNAME<R, NX>), grid, block, lds, s, p, (const V*)tw.tn, (const V*)tw.tx);      \
+        return hipGetLastError();                                                                          \
+    }                                                                                                      \
+    SBI_ROW_NX_SWITCH(KNAME, PTYPE)
+
+// kernels with launch-plan variants: p.g.row_var picks the transform's
+// radix and twiddle mode, p.g.row_rpw the rows per workgroup
+// Only variants that compile without register spills are built: the sweep
+// kernels (three workgroups per CU) take the cached twiddle powers in FP32
+// only and radix-16 rows only at 512 points; the SA kernel takes both in
+// FP32 from 512 points (radix 16 needs two radix-16 passes in the
+// half-length row) and the cached powers in FP64 too.
+template <typename R, int NX, int VAR, bool SWEEP> constexpr bool row_var_built() {
+    constexpr bool f32 = std::is_same<R, float>::value;
+    if constexpr (VAR == 0) return true;
+    if constexpr (VAR == 1) return f32 || !SWEEP;
+    if constexpr (VAR == 2) return f32 && (SWEEP ? NX == 512 : NX >= 512);
+    return false;
+}
+#define SBI_ROW_LAUNCH_VAR(KNAME, PTYPE, SWEEP)                                                            \
+    template <typename R, int NX, int VAR>                                                                 \
+    static hipError_t KNAME##_gv(const PTYPE& p, int batch, const Twiddles& tw, hipStream_t s) {           \
+        if constexpr (!row_var_built<R, NX, VAR, SWEEP>()) {                                               \
+            return hipErrorInvalidValue;                                                                   \
+        } else {                                                                                           \
+            using V = typename cplx_of<R>::type;                                                           \
+            dim3 grid, block;                                                                              \
+            size_t lds;                                                                                    \
+            RowLaunch<RowVar<R, NX, VAR>>::shape(p.g.ny, &grid, &block, &lds, batch, row_families(p),      \
+                                                 p.g.row_rpw);                                             \
+            hipLaunchKernelGGL((KNAME<R, NX, VAR>), grid, block, lds, s, p, (const V*)tw.tn,               \
+                               (const V*)tw.tx);                                                           \
+            return hipGetLastError();                                                                      \
+        }                                                                                                  \
+    }                                                                                                      \
+    template <typename R, int NX>                                                                          \
+    static hipError_t KNAME##_go(const PTYPE& p, int batch, const Twiddles& tw, hipStream_t s) {           \
+        switch (p.g.row_var) {                                                                             \
+            case 0: return KNAME##_gv<R, NX, 0>(p, batch, tw, s);                                          \
+            case 1: return KNAME##_gv<R, NX, 1>(p, batch, tw, s);                                          \
+            case 2: return KNAME##_gv<R, NX, 2>(p, batch, tw, s);                                          \
+            default: return hipErrorInvalidValue;                                                          \
+        }                                                                                                  \
+    }                                                                                                      \
+    SBI_ROW_NX_SWITCH(KNAME, PTYPE)
+
 SBI_ROW_LAUNCH(k_row_fwd, RowFwdParams)
 SBI_ROW_LAUNCH(k_row_inv, RowInvParams)
 SBI_ROW_LAUNCH(k_row_setup, RowSetupParams)
-SBI_ROW_LAUNCH(k_row_sweep, RowSweepParams)
-SBI_ROW_LAUNCH(k_row_sweep_aa, RowSweepParams)
-SBI_ROW_LAUNCH(k_row_sa, RowSaParams)
+SBI_ROW_LAUNCH_VAR(k_row_sweep, RowSweepParams, true)
+SBI_ROW_LAUNCH_VAR(k_row_sweep_aa, RowSweepParams, true)
+SBI_ROW_LAUNCH_VAR(k_row_sa, RowSaParams, false)
 SBI_ROW_LAUNCH(k_row_nphi, RowNphiParams)
 SBI_ROW_LAUNCH(k_row_nphi_tank, RowNphiParams)
 SBI_ROW_LAUNCH(k_row_blend, RowBlendParams)
@@ -2227,6 +2287,36 @@ template <> hipError_t launch_row_inv_t<Real>(const RowInvParams& p, int b, cons
 }
 template <> hipError_t launch_row_setup_t<Real>(const RowSetupParams& p, int b, const Twiddles& tw, hipStream_t s) {
     return k_row_setup_nx<Real>(p, b, tw, s);
+}
+template <typename R, int NX, bool SWEEP> static int row_var_mask_nx() {
+    return (row_var_built<R, NX, 0, SWEEP>() ? 1 : 0) | (row_var_built<R, NX, 1, SWEEP>() ? 2 : 0) |
+           (row_var_built<R, NX, 2, SWEEP>() ? 4 : 0);
+}
+template <typename R, int NX> static int row_var_mask_k(int sweep) {
+    return sweep ? row_var_mask_nx<R, NX, true>() : row_var_mask_nx<R, NX, false>();
+}
+template <> int row_var_mask_t<Real>(int sweep, int nx) {
+    switch (nx) {
+        case 16: return row_var_mask_k<Real, 16>(sweep);
+        case 32: return row_var_mask_k<Real, 32>(sweep);
+        case 64: return row_var_mask_k<Real, 64>(sweep);
+        case 128: return row_var_mask_k<Real, 128>(sweep);
+        case 256: return row_var_mask_k<Real, 256>(sweep);
+        case 512: return row_var_mask_k<Real, 512>(sweep);
+        case 1024: return row_var_mask_k<Real, 1024>(sweep);
+        case 2048: return row_var_mask_k<Real, 2048>(sweep);
+        case 4096: return row_var_mask_k<Real, 4096>(sweep);
+        case 8192: return row_var_mask_k<Real, 8192>(sweep);
+        default: return 0;
+    }
+}
+template <> int row_rows_cap_t<Real>(int nx, int var) {
+    // rows per workgroup that fill 256 threads (the launch bound)
+    const int n = nx / 2;
+    const int em = var == 2 ? 16 : 8;
+    const int e = n >= em ? em : n;
+    const int P = n / e;
+    return P >= 256 ? 1 : 256 / P;
 }
 template <> hipError_t launch_row_sweep_t<Real>(const RowSweepParams& p, int b, const Twiddles& tw, hipStream_t s) {
     return p.gT ? k_row_sweep_aa_nx<Real>(p, b, tw, s) : k_row_sweep_nx<Real>(p, b, tw, s);

@@ -222,6 +222,13 @@ template <typename R> hipError_t launch_diag_t(const DiagParams&, int, hipStream
 template <typename R> hipError_t launch_hist_seed_t(const HistParams&, int, hipStream_t);
 template <typename R> hipError_t launch_hist_push_t(const HistParams&, int, hipStream_t);
 template <typename R> hipError_t launch_hist_grad_t(const HistParams&, int, hipStream_t);
+// launch-plan variants of the row sweep (sweep = 1) or SA (sweep = 0) kernels
+// built for a row length: bit v set when variant v is available
+template <typename R> int row_var_mask_t(int sweep, int nx);
+// rows per workgroup of a row variant at its 256-thread launch bound
+template <typename R> int row_rows_cap_t(int nx, int var);
+int row_var_mask(int fp64, int sweep, int nx);
+int row_rows_cap(int fp64, int nx, int var);
 
 hipError_t launch_row_fwd(int fp64, const RowFwdParams& p, int batch, const Twiddles& tw, hipStream_t s);
 hipError_t launch_row_inv(int fp64, const RowInvParams& p, int batch, const Twiddles& tw, hipStream_t s);

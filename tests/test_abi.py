@@ -141,3 +141,34 @@ def test_batch_interface_host_checks(lib):
     assert lib.sbi_batch_destroy(None) == _lib.SBI_ERR_INVALID_ARG
     assert lib.sbi_batch_groups(None, None, None, 0) == 0
     assert lib.sbi_batch_net_load(None, None, 0) == _lib.SBI_ERR_INVALID_ARG
+
+
+def test_plan_interface_host_checks(lib, tmp_path):
+    """The plan cache as a file (host only): entries that parse are merged,
+    junk lines are skipped, a save writes back every entry; the plan calls
+    reject null contexts."""
+    from paper_2310_19840_amd import _lib
+    src = tmp_path / "plans_in.txt"
+    src.write_text("# sbi launch plans: key row_variant row_rows col_split us\n"
+                   "devA/gfx950|1024x1024|b1|fp64|iter|a1|o7|vd1 0 4 0 97.500\n"
+                   "this line does not parse\n"
+                   "devA/gfx950|512x512|b16|fp32|sa|a0|o7|vd1 2 16 2048 512.250\n"
+                   "devA/gfx950|64x64|b1|fp32|sa|a0|o7|vd0 7 1 0 1.0\n")  # variant out of range: skipped
+    n = C.c_int32(-1)
+    assert lib.sbi_tune_cache_load(str(src).encode(), C.byref(n)) == _lib.SBI_OK
+    assert n.value == 2
+    out = tmp_path / "plans_out.txt"
+    assert lib.sbi_tune_cache_save(str(out).encode(), C.byref(n)) == _lib.SBI_OK
+    lines = out.read_text().splitlines()
+    assert lines[0].startswith("#") and n.value == len(lines) - 1 >= 2
+    body = {ln.split()[0]: ln.split()[1:] for ln in lines[1:]}
+    assert body["devA/gfx950|1024x1024|b1|fp64|iter|a1|o7|vd1"] == ["0", "4", "0", "97.500"]
+    assert body["devA/gfx950|512x512|b16|fp32|sa|a0|o7|vd1"] == ["2", "16", "2048", "512.250"]
+    assert lib.sbi_tune_cache_load(str(tmp_path / "missing.txt").encode(), None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_tune_cache_load(None, None) == _lib.SBI_ERR_INVALID_ARG
+    p = _lib.sbi_plan()
+    assert lib.sbi_plan_get(None, C.byref(p)) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_plan_set(None, C.byref(p)) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_autotune(None, 0, None) == _lib.SBI_ERR_INVALID_ARG
+    assert lib.sbi_plan_variants(None) == 0
+    assert lib.sbi_batch_plan(None, 0, C.byref(p)) == _lib.SBI_ERR_INVALID_ARG

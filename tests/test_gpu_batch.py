@@ -171,3 +171,32 @@ def test_speculative_budget_redo_is_exact(gpu):
     assert all(x < 200 for x in budgets[1][0])
     # the tighter tolerance outran it at least once, and was redone
     assert budgets[-1][1] >= 1
+
+
+@pytest.mark.parametrize("mode,seed_mode", [("iter", "prev"), ("sa", "linear")])
+def test_long_graph_calls_split_into_parts_equal_single_contexts(gpu, mode, seed_mode):
+    """A captured call of 9 steps runs as a prologue, parts of 4, 4 and 1
+    steps and an epilogue; the spectral state stays on the device between the
+    parts, so every member equals its single-context 9-step call bit for bit,
+    on the first call (seeds change between the parts) and on a replay."""
+    from paper_2310_19840_amd import Batch, Solver
+    mems = _ragged(mode=mode, seed_mode=seed_mode)[:3]
+    _say("9-step graph calls vs single contexts", mode, seed_mode)
+    b = Batch([m for m, _, _ in mems], device=gpu, graph=True)
+    et, pt = _tensors(mems, gpu)
+    singles = []
+    for m, e, p in mems:
+        s = Solver(m["nx"], m["ny"], m["lx"], m["ly"], m["depth"], device=gpu, mode=mode, max_sweeps=120,
+                   seed=seed_mode)
+        es, ps = _tensors([(m, e, p)], gpu)
+        singles.append((s, es[0], ps[0]))
+    for call in range(2):
+        st, info = b.step(et, pt, DT, 9, tol=1e-11)
+        assert st == 0
+        for i, (s, es, ps) in enumerate(singles):
+            _, si_ = s.step(es, ps, DT, 9, tol=1e-11)
+            assert np.array_equal(et[i].cpu().numpy(), es.cpu().numpy().reshape(et[i].shape)), (call, i)
+            assert np.array_equal(pt[i].cpu().numpy(), ps.cpu().numpy().reshape(pt[i].shape)), (call, i)
+            if mode == "iter":
+                assert info[i]["solves"] == 36
+                assert info[i]["sweeps_total"] == si_["sweeps_total"], (call, i)
