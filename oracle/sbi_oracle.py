@@ -132,6 +132,12 @@ class Solver:
         if not 1 <= self.L <= 7:
             raise ValueError("order must be in 1..7")
         self.mode = mode
+        if mode not in ("sa", "iter", "full"):
+            raise ValueError("mode must be 'sa', 'iter' or 'full'")
+        if mode == "full" and (grid.ny != 1 or not self.flat):
+            # the exact boundary-integral solve (oracle.full_bie) covers one
+            # horizontal dimension over a flat bed
+            raise ValueError("mode 'full' needs a one-dimensional grid and a flat bed")
         self.max_sweeps = int(max_sweeps)
         self.relax = relax
         k = grid.k
@@ -526,9 +532,19 @@ class Solver:
         return out
 
     # ------------------------------------------------------------------------
+    def w_full_hat(self, eta, ph, tol):
+        """W with the remaining integrals of App. A kept (oracle.full_bie), masked."""
+        from . import full_bie
+        g = self.g
+        V, sweeps, status, r = full_bie.vertical_velocity(np.asarray(eta).ravel(), g.ifft(ph).ravel(), g.lx,
+                                                          self.h, tol, self.max_sweeps)
+        return g.MF(V.reshape(1, g.nx)), SolveInfo(sweeps=sweeps, residual=r, status=status)
+
     def solve_hat(self, eta, ph, tol=1e-10, seed_hat=None, seed_b_hat=None, stage=None):
         if self.mode == "sa":
             return self.w_sa_hat(eta, ph), SolveInfo(sweeps=0)
+        if self.mode == "full":
+            return self.w_full_hat(eta, ph, tol)
         return self.w_iter_hat(eta, ph, tol, seed_hat, seed_b_hat, stage)
 
     def vertical_velocity(self, eta, phi_s, tol=1e-10, seed=None, seed_b=None):
