@@ -387,6 +387,47 @@ def run_c2_tank(args, dev):
     return r
 
 
+def run_full_1d(args, dev):
+    """The fully nonlinear W (the remaining integrals of App. A kept) stepping a
+    steep one-dimensional random sea: N = 4096 over a flat bed (k_p h = 1, 32
+    points per peak wavelength, k_p a up to ~0.25), FP64, W tol 1e-10, eager
+    steps of T_p/64 after one warm-up step; every pair pass evaluates the
+    single-layer kernel at N^2 point pairs."""
+    import numpy as np
+    import torch
+
+    import sbi_inputs as si
+    from paper_2310_19840_amd import Solver
+
+    n = 4096
+    lx = 2 * math.pi * n / 32
+    gs = si.GridSpec(n, 1, lx, 1.0)
+    eta0 = si.narrowband_random(gs, 4096, amp=0.12)
+    phi0 = si.narrowband_random(gs, 4097, amp=0.24)
+    depth = np.ones((1, n))
+    dt = 2 * math.pi / math.sqrt(math.tanh(1.0)) / 64
+    s = Solver(n, 1, lx, 1.0, depth, device=dev, mode="full", max_sweeps=100)
+    eta = torch.tensor(eta0[None], dtype=torch.float64, device=dev)
+    phi = torch.tensor(phi0[None], dtype=torch.float64, device=dev)
+    s.step(eta, phi, dt, 1, tol=1e-10)
+    torch.cuda.synchronize()
+    s.profile(True)
+    t0 = time.perf_counter()
+    st, info = s.step(eta, phi, dt, args.full_steps, tol=1e-10, t=dt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = s.profile_read()
+    s.profile(False)
+    pairs_ms, pairs_n = prof.get("full_pairs", (0.0, 0))
+    apply_ms, apply_n = prof.get("full_apply", (0.0, 0))
+    return dict(value=n * args.full_steps / el, ms_per_step=1e3 * el / args.full_steps, status=st, points=n,
+                steps=args.full_steps, sweeps_mean=info["sweeps_total"] / max(info["solves"], 1),
+                pair_pass_us=round(1e3 * pairs_ms / max(pairs_n, 1), 2),
+                apply_pass_us=round(1e3 * apply_ms / max(apply_n, 1), 2),
+                pairs_per_s=float(f"{n * n / max(1e-3 * pairs_ms / max(pairs_n, 1), 1e-12):.4g}"),
+                max_eta=float(np.abs(eta.cpu().numpy()).max()))
+
+
 def run_c4(args, dev):
     """The ragged ensemble (32 x 128^2 + 48 x 256^2 + 16 x 512^2), SA mode, FP32: its 64-step window as one
     captured graph per call, launch shapes chosen by the autotuner at set-up."""
@@ -462,9 +503,10 @@ def main():
     ap.add_argument("--c4-steps", type=int, default=64)
     ap.add_argument("--c3-steps", type=int, default=32)
     ap.add_argument("--c2-steps", type=int, default=256)
+    ap.add_argument("--full-steps", type=int, default=8)
     ap.add_argument("--forms",
                     default="plain,plain-relaxed,batched+prev,batched+learned,plain-fp32,adaptive,c2-tank,c4,"
-                            "c3-precision")
+                            "c3-precision,full-1d")
     ap.add_argument("--accel", default="anderson", choices=["anderson", "none"],
                     help="iteration of the W solves: Anderson-mixed (default) or plain relaxed sweeps")
     ap.add_argument("--adaptive-periods", type=float, default=4.0)
@@ -522,6 +564,8 @@ def main():
         out_forms["c2-tank"] = run_c2_tank(args, dev)
     if "c4" in forms:
         out_forms["c4"] = run_c4(args, dev)
+    if "full-1d" in forms:
+        out_forms["full-1d"] = run_full_1d(args, dev)
     if "c3-precision" in forms:
         out_forms["c3-precision"] = run_c3_precision(args, dev)
     for f, d in out_forms.items():

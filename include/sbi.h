@@ -13,7 +13,14 @@
  *   - W is evaluated by the successive approximation of Sec. 2.4 with the
  *     explicit orders of Appendix C (Eqs. (v2)-(v7)) -- mode SBI_MODE_SA --
  *     or by iterating the same expansion summed over orders to a residual
- *     tolerance -- mode SBI_MODE_ITER;
+ *     tolerance -- mode SBI_MODE_ITER -- or, on one-dimensional grids over a
+ *     flat bed, fully nonlinearly: the surface boundary-integral equation of
+ *     Sec. 2.3 with the remaining integrals I^(S) of App. A kept
+ *     (Eq. (con-V): the expansion plus I^(S) is the exact equation), in its
+ *     two-dimensional-flow form (Green function -ln r, image in the bed),
+ *     iterated to the residual tolerance with O(nx^2) quadrature per sweep --
+ *     mode SBI_MODE_FULL (sbi_init returns SBI_ERR_UNSUPPORTED for a
+ *     variable bed, and ensembles do not take it);
  *   - the time step integrates Eq. (prognostic) in its integrating-factor form
  *     (Sec. 2.2) with the classical 4-stage Runge-Kutta scheme of Lawson type
  *     (fixed step), or with the adaptive six-stage fifth-order pair with an
@@ -68,7 +75,7 @@ typedef enum sbi_status {
 } sbi_status;
 
 enum { SBI_FP64 = 0, SBI_FP32 = 1 };
-enum { SBI_MODE_ITER = 0, SBI_MODE_SA = 1 };
+enum { SBI_MODE_ITER = 0, SBI_MODE_SA = 1, SBI_MODE_FULL = 2 };
 enum { SBI_SEED_LINEAR = 0, SBI_SEED_PREV = 1, SBI_SEED_NET = 2, SBI_SEED_USER = 3 };
 enum { SBI_ACCEL_NONE = 0, SBI_ACCEL_ANDERSON = 1 };
 
@@ -83,7 +90,7 @@ typedef struct sbi_grid {
                               Sec. 2.4 read as alpha = 1/2); 0 < alpha < 1; default 0.5 */
     int32_t precision;     /* SBI_FP64 (default) or SBI_FP32 (FP64 residual norms and
                               diagnostics are kept either way) */
-    int32_t mode;          /* SBI_MODE_ITER (default) or SBI_MODE_SA */
+    int32_t mode;          /* SBI_MODE_ITER (default), SBI_MODE_SA or SBI_MODE_FULL (1D, flat bed) */
     int32_t seed;          /* SBI_SEED_* for the iteration; default SBI_SEED_LINEAR,
                               the initiation of Sec. 2.4.  SBI_SEED_PREV: the linear
                               guess plus the nonlinear part (V* - k tanh(kh) phi_hat,

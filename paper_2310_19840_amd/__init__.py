@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import SBIError  # noqa: F401
 
 _PREC = {"fp64": _lib.SBI_FP64, "fp32": _lib.SBI_FP32}
-_MODE = {"iter": _lib.SBI_MODE_ITER, "sa": _lib.SBI_MODE_SA}
+_MODE = {"iter": _lib.SBI_MODE_ITER, "sa": _lib.SBI_MODE_SA, "full": _lib.SBI_MODE_FULL}
 _SEED = {"linear": _lib.SBI_SEED_LINEAR, "prev": _lib.SBI_SEED_PREV, "net": _lib.SBI_SEED_NET,
          "user": _lib.SBI_SEED_USER}
 

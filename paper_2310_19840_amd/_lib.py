@@ -22,7 +22,7 @@ SBI_ERR_DIVERGED = -6
 SBI_PROFILE_OFF, SBI_PROFILE_ALL, SBI_PROFILE_SWEEPS = 0, 1, 2
 
 SBI_FP64, SBI_FP32 = 0, 1
-SBI_MODE_ITER, SBI_MODE_SA = 0, 1
+SBI_MODE_ITER, SBI_MODE_SA, SBI_MODE_FULL = 0, 1, 2
 SBI_SEED_LINEAR, SBI_SEED_PREV, SBI_SEED_NET, SBI_SEED_USER = 0, 1, 2, 3
 SBI_ACCEL_NONE, SBI_ACCEL_ANDERSON = 0, 1
 

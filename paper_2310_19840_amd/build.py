@@ -27,6 +27,8 @@ FLAGS = [
 UNITS = [
     ("sbi_kernels.hip", "sbi_k64.o", ["-DSBI_REAL=double"]),
     ("sbi_kernels.hip", "sbi_k32.o", ["-DSBI_REAL=float"]),
+    ("sbi_full.hip", "sbi_full64.o", ["-DSBI_REAL=double"]),
+    ("sbi_full.hip", "sbi_full32.o", ["-DSBI_REAL=float"]),
     ("sbi_dispatch.hip", "sbi_dispatch.o", []),
     ("sbi_api.hip", "sbi_api.o", []),
     ("sbi_net.hip", "sbi_net.o", []),

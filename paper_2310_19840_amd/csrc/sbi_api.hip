@@ -84,11 +84,13 @@ struct Stats {
 // kernel classes timed by the optional profiler
 enum {
     K_ROW_FWD, K_ROW_INV, K_ROW_SETUP, K_ROW_SWEEP, K_ROW_SA, K_ROW_NPHI, K_ROW_BLEND,
-    K_COL_STATE, K_COL_FORCING, K_COL_SWEEP, K_COL_SA, K_COL_OTHER, K_RK, K_DIAG, K_NET, K_COUNT
+    K_COL_STATE, K_COL_FORCING, K_COL_SWEEP, K_COL_SA, K_COL_OTHER, K_RK, K_DIAG, K_NET, K_FULL_PAIRS,
+    K_FULL_APPLY, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {
     "row_fwd", "row_inv", "row_setup", "row_sweep", "row_sa", "row_nphi", "row_blend",
-    "col_state", "col_forcing", "col_sweep", "col_sa", "col_other", "rk", "diag", "net"};
+    "col_state", "col_forcing", "col_sweep", "col_sa", "col_other", "rk", "diag", "net", "full_pairs",
+    "full_apply"};
 
 struct Profiler {
     bool on = false;
@@ -141,6 +143,16 @@ struct sbi_ctx {
     // hist_dev; hist_count fixed-step solves are held in C_HV/C_HB
     HistDev* hist_dev = nullptr;
     double* hist_partial = nullptr;
+    // fully nonlinear solve (SBI_MODE_FULL): tables (S0^-1 per member, eta_x
+    // and eta_xx circulants, sin^2) and the slices of its pair passes
+    void* full_c0 = nullptr;
+    void* full_d1 = nullptr;
+    void* full_d2 = nullptr;
+    void* full_s2 = nullptr;
+    void* full_rhs = nullptr;
+    void* full_lfl = nullptr;
+    void* full_w = nullptr;
+    void* full_part = nullptr;
     int hist_K = 0, hist_nb = 0;
     double hist_dk = 0.0;
     bool hist_loaded = false;
@@ -204,8 +216,10 @@ struct Layout {
     int Mx, My, Kx, Kxp, Ky, C, qb, ldh;
     size_t rsz, csz;
     long long s_phys, s_half, s_cmp;
-    size_t bytes_comp, bytes_half, bytes_phys, bytes_tw, bytes_misc, bytes_net, total;
+    size_t bytes_comp, bytes_half, bytes_phys, bytes_tw, bytes_misc, bytes_net, bytes_full, total;
 };
+
+constexpr int kFullSplitMax = 16;  // source-point slices of a pair pass of the fully nonlinear solve
 
 static bool grid_valid(const sbi_grid* g) {
     if (!g) return false;
@@ -215,7 +229,8 @@ static bool grid_valid(const sbi_grid* g) {
     if (g->order < 1 || g->order > 7) return false;
     if (!(g->dealias > 0.0 && g->dealias < 1.0)) return false;
     if (g->precision != SBI_FP64 && g->precision != SBI_FP32) return false;
-    if (g->mode != SBI_MODE_ITER && g->mode != SBI_MODE_SA) return false;
+    if (g->mode != SBI_MODE_ITER && g->mode != SBI_MODE_SA && g->mode != SBI_MODE_FULL) return false;
+    if (g->mode == SBI_MODE_FULL && g->ny != 1) return false;  // the exact surface equation: one dimension
     if (g->max_sweeps < 1 || g->max_sweeps > 1000) return false;
     if (g->seed < SBI_SEED_LINEAR || g->seed > SBI_SEED_USER) return false;
     if (g->accel != SBI_ACCEL_NONE && g->accel != SBI_ACCEL_ANDERSON) return false;
@@ -263,7 +278,13 @@ static Layout layout(const sbi_grid* g, int batch) {
                   (g->seed == SBI_SEED_NET
                        ? al(sizeof(HistDev)) + al(sizeof(double) * kHistPart * kHistBlocks * (size_t)batch)
                        : 0);
-    L.total = L.bytes_comp + L.bytes_half + L.bytes_phys + L.bytes_tw + L.bytes_misc + L.bytes_net;
+    // fully nonlinear solve (FP64 in both precisions): tables [batch + 3][nx]
+    // and [batch][nx], right-hand side and source term [batch][nx], pair
+    // slices [kFullSplitMax][batch][nx]
+    L.bytes_full = g->mode == SBI_MODE_FULL
+                       ? 7 * al((size_t)g->nx * 8 * batch) + al((size_t)kFullSplitMax * g->nx * 8 * batch)
+                       : 0;
+    L.total = L.bytes_comp + L.bytes_half + L.bytes_phys + L.bytes_tw + L.bytes_misc + L.bytes_net + L.bytes_full;
     return L;
 }
 
@@ -321,9 +342,25 @@ static std::vector<double> twiddle_table(int n) {
     return t;
 }
 
+static sbi_status full_tables(sbi_ctx* c);
+
 static sbi_status set_depth(sbi_ctx* c, const double* depth, double h_ref) {
     const sbi_grid& g = c->grid;
     const size_t npt = (size_t)g.nx * g.ny;
+    if (g.mode == SBI_MODE_FULL) {
+        // the fully nonlinear solve covers flat beds only: refuse a variable
+        // one before anything changes
+        for (int b = 0; b < c->batch; ++b) {
+            const double* d = depth + b * npt;
+            for (size_t i = 0; i < npt; ++i)
+                if (!std::isfinite(d[i]) || !(d[i] > 0.0)) return std::isfinite(d[i]) ? SBI_ERR_INVALID_ARG
+                                                                                      : SBI_ERR_NONFINITE;
+            const double dmax = *std::max_element(d, d + npt);
+            const double h = h_ref > 0.0 ? h_ref : dmax;
+            for (size_t i = 0; i < npt; ++i)
+                if (d[i] != h) return SBI_ERR_UNSUPPORTED;
+        }
+    }
     std::vector<double> delta(npt * c->batch);
     c->href.assign(c->batch, 0.0);
     c->vd = false;
@@ -349,6 +386,7 @@ static sbi_status set_depth(sbi_ctx* c, const double* depth, double h_ref) {
     std::vector<char> dv = to_prec(delta.data(), delta.size(), c->fp64);
     SBI_HIP(hipMemcpyAsync(c->phys[P_DELTA], dv.data(), dv.size(), hipMemcpyHostToDevice, c->stream));
     SBI_HIP(hipMemcpyAsync(c->href_dev, c->href.data(), sizeof(double) * c->batch, hipMemcpyHostToDevice, c->stream));
+    if (g.mode == SBI_MODE_FULL) SBI_TRY(full_tables(c));
     SBI_HIP(hipStreamSynchronize(c->stream));
     return SBI_OK;
 }
@@ -447,6 +485,18 @@ static sbi_status ctx_setup(sbi_ctx* c, const sbi_grid* g, int32_t batch, const 
         c->hist_dev = reinterpret_cast<HistDev*>(p);
         p += al(sizeof(HistDev));
         c->hist_partial = reinterpret_cast<double*>(p);
+        p += al(sizeof(double) * kHistPart * kHistBlocks * (size_t)batch);
+    }
+    if (g->mode == SBI_MODE_FULL) {
+        const size_t tb = al((size_t)g->nx * 8 * batch);
+        c->full_c0 = p;
+        c->full_d1 = p + tb;
+        c->full_d2 = p + 2 * tb;
+        c->full_s2 = p + 3 * tb;
+        c->full_rhs = p + 4 * tb;
+        c->full_lfl = p + 5 * tb;
+        c->full_w = p + 6 * tb;
+        c->full_part = p + 7 * tb;
     }
     c->col_C = L.C;
     gd.col_C = L.C;
@@ -812,6 +862,7 @@ static sbi_status stage_state_pass(sbi_ctx* c, bool need_eta, bool allow_prev = 
 static sbi_status row_setup(sbi_ctx* c, const void* eta_user) {
     const bool two_d = c->grid.ny > 1;
     const bool sa = c->grid.mode == SBI_MODE_SA;
+    const bool iter = c->grid.mode == SBI_MODE_ITER;
     RowSetupParams rp{};
     rp.g = c->gd;
     rp.g_eta = eta_user ? nullptr : HALF(H_ETA);
@@ -821,7 +872,7 @@ static sbi_status row_setup(sbi_ctx* c, const void* eta_user) {
     rp.g_py = HALF(H_PY);
     rp.px_out = sa ? PHYS(P_PX) : nullptr;
     rp.py_out = (sa && two_d) ? PHYS(P_PY) : nullptr;
-    rp.nprod = sa ? 0 : (c->grid.order - 1) * (two_d ? 2 : 1);
+    rp.nprod = iter ? (c->grid.order - 1) * (two_d ? 2 : 1) : 0;
     for (int i = 0; i < rp.nprod; ++i) rp.h[i] = HALF(H_PROD0 + i);
     rp.ctl = c->ctl;
     c->st.launches += 1;
@@ -1345,6 +1396,116 @@ static sbi_status hist_after_solve(sbi_ctx* c, int stage, bool capture_safe) {
 // W solve at the stage state.  stage: the RK4 stage (0..3) of a fixed-step
 // solve, -1 for any other solve.  capture_safe: no host synchronisation
 // (fixed sweep launches, no fallback from a failed learned seed).
+// ---------------------------------------------------------------------------
+// Fully nonlinear W (SBI_MODE_FULL, one dimension, flat bed): the surface
+// boundary-integral equation with the remaining integrals kept (sbi_full.hip)
+// ---------------------------------------------------------------------------
+// physical work fields of the solve (the SA order slots, unused in this mode)
+enum { PF_PHI = P_V0, PF_EX, PF_EXX, PF_V, PF_B0, PF_B1 };
+
+static FullParams full_params(sbi_ctx* c) {
+    FullParams p{};
+    p.n = c->grid.nx;
+    p.batch = c->batch;
+    p.lx = c->grid.lx;
+    p.s_phys = c->gd.s_phys;
+    p.href = c->href_dev;
+    p.c0 = c->full_c0;
+    p.d1 = c->full_d1;
+    p.d2 = c->full_d2;
+    p.s2 = c->full_s2;
+    p.part = c->full_part;
+    p.phi = PHYS(PF_PHI);
+    p.ex = PHYS(PF_EX);
+    p.exx = PHYS(PF_EXX);
+    p.rhs = c->full_rhs;
+    p.lfl = c->full_lfl;
+    p.w = c->full_w;
+    p.vbuf[0] = PHYS(PF_B0);
+    p.vbuf[1] = PHYS(PF_B1);
+    p.vfinal = PHYS(PF_V);
+    p.ctl = c->ctl;
+    p.max_sweeps = c->grid.max_sweeps;
+    // source-point slices: enough workgroups to fill the GPU (about 256)
+    const int tiles = (p.n + 255) / 256;
+    p.nsplit = std::max(1, std::min(kFullSplitMax, 256 / std::max(1, tiles * c->batch)));
+    return p;
+}
+
+static sbi_status full_tables(sbi_ctx* c) {
+    FullParams p = full_params(c);
+    c->st.launches += 1;
+    return hip_ok(launch_full(c->fp64, p, FULL_TABLES, c->stream));
+}
+
+static sbi_status full_solve(sbi_ctx* c, const void* eta_phys, double tol) {
+    // phi_s at the points (the band-limited stage potential)
+    {
+        ColBuilder b(c->gd);
+        b.term(b.cin(CMP(C_PS)), 0, 1.0, FN_ONE, 0, DV_NONE);
+        b.inv(SRC_ACC0, DV_NONE, HALF(H_PROD0));
+        SBI_TRY(run_col(c, b));
+        RowInvParams ip{};
+        ip.g = c->gd;
+        ip.nf = 1;
+        ip.in[0] = HALF(H_PROD0);
+        ip.out[0] = PHYS(PF_PHI);
+        ip.ctl = c->ctl;
+        c->st.launches += 1;
+        ProfScope ps_(c, K_ROW_INV);
+        SBI_TRY(hip_ok(launch_row_inv(c->fp64, ip, c->batch, tw_of(c), c->stream)));
+    }
+    FullParams p = full_params(c);
+    p.eta = eta_phys;
+    p.tol = tol;
+    c->st.launches += 3;
+    SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_GEOM, c->stream)));
+    SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_DOUBLE, c->stream)));
+    SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_RHS, c->stream)));
+    // launch n: the pair pass decides from the residual of launch n - 1 and
+    // forms (S - S0)[V_n]; the apply pass forms V_(n+1) and its residual.
+    // V_0 = 0, V_n lives in vbuf[n & 1]; the host polls every few launches.
+    const int M = c->grid.max_sweeps;
+    constexpr int kChunk = 8;
+    for (int n0 = 0; n0 <= M; n0 += kChunk) {
+        for (int n = n0; n <= M && n < n0 + kChunk; ++n) {
+            p.sweep = n;
+            p.vin = n == 0 ? nullptr : p.vbuf[n & 1];
+            p.vout = const_cast<void*>(p.vbuf[(n + 1) & 1]);
+            c->st.launches += n == 0 ? 2 : 3;
+            if (n > 0) {
+                ProfScope ps_(c, K_FULL_PAIRS);
+                SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_SINGLE, c->stream)));
+            }
+            ProfScope ps2_(c, K_FULL_APPLY);
+            SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_COMBINE, c->stream)));
+            SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_APPLY, c->stream)));
+        }
+        SBI_TRY(read_heads(c));
+        bool all = true;
+        for (int b = 0; b < c->batch; ++b) all = all && c->head[b].done;
+        if (all) break;
+    }
+    c->st.launches += 1;
+    SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_SELECT, c->stream)));
+    // the spectrum of W (kept band) and its half form
+    RowFwdParams rp{};
+    rp.g = c->gd;
+    rp.nf = 1;
+    rp.in[0] = PHYS(PF_V);
+    rp.out[0] = HALF(H_PROD0);
+    c->st.launches += 1;
+    {
+        ProfScope ps_(c, K_ROW_FWD);
+        SBI_TRY(hip_ok(launch_row_fwd(c->fp64, rp, c->batch, tw_of(c), c->stream)));
+    }
+    ColBuilder b(c->gd);
+    b.term(b.prod(HALF(H_PROD0)), 0, 1.0, FN_ONE, 0, DV_NONE);
+    b.cout(SRC_ACC0, CMP(C_VH));
+    b.inv(SRC_ACC0, DV_NONE, HALF(H_GV));
+    return run_col(c, b);
+}
+
 static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool need_eta_grad, int* vh_buf,
                               const void* w_seed = nullptr, bool capture_safe = false, int stage = -1) {
     SBI_TRY(hip_ok(launch_ctl_reset(c->ctl, c->batch, c->grid.max_sweeps + 2, c->stream)));
@@ -1365,6 +1526,9 @@ static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool
     const void* eta_phys = eta_user ? eta_user : PHYS(P_ETA);
     if (c->grid.mode == SBI_MODE_SA) {
         SBI_TRY(run_sa(c, eta_phys));
+        *vh_buf = C_VH;
+    } else if (c->grid.mode == SBI_MODE_FULL) {
+        SBI_TRY(full_solve(c, eta_phys, tol));
         *vh_buf = C_VH;
     } else {
         SBI_TRY(col_forcing(c));
@@ -1489,7 +1653,7 @@ extern "C" sbi_status sbi_vertical_velocity_noalloc(const sbi_grid* g, int32_t b
 static sbi_status vertical_velocity(sbi_ctx* c, const void* eta, const void* phi_s, const double* h, double tol,
                                     const void* w_seed, void* w_out, sbi_solve_info* info) {
     if (!eta || !phi_s || !w_out) return SBI_ERR_INVALID_ARG;
-    if (c->grid.mode == SBI_MODE_ITER && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
+    if (c->grid.mode != SBI_MODE_SA && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
     if (c->grid.seed == SBI_SEED_USER && !w_seed) return SBI_ERR_INVALID_ARG;
     c->st = Stats();
     sbi_status warn = SBI_OK;
@@ -1677,7 +1841,7 @@ static void acc_info(sbi_ctx* c, sbi_step_info* si) {
 
 extern "C" sbi_status sbi_step(sbi_ctx* c, sbi_state* state, double dt, int32_t n, double tol, sbi_step_info* info) {
     if (!c || !state || !state->eta || !state->phi_s || n < 0 || !std::isfinite(dt)) return SBI_ERR_INVALID_ARG;
-    if (c->grid.mode == SBI_MODE_ITER && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
+    if (c->grid.mode != SBI_MODE_SA && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
     c->st = Stats();
     c->fallbacks = 0;
     sbi_step_info si{};
@@ -1688,7 +1852,7 @@ extern "C" sbi_status sbi_step(sbi_ctx* c, sbi_state* state, double dt, int32_t 
         for (int stage = 0; stage < 4; ++stage) {
             int vh = 0;
             SBI_TRY(solve_stage(c, nullptr, tol, true, &vh, nullptr, false, stage));
-            if (c->grid.mode == SBI_MODE_ITER) {
+            if (c->grid.mode != SBI_MODE_SA) {
                 // the iteration already read the control headers at its last poll
                 sbi_status st = solve_status(c, nullptr, true);
                 if (st < 0) return st;
@@ -1782,7 +1946,7 @@ extern "C" sbi_status sbi_step_adaptive(sbi_ctx* c, sbi_state* state, double t_e
     if (!c || !state || !state->eta || !state->phi_s || max_steps < 1) return SBI_ERR_INVALID_ARG;
     if (!std::isfinite(state->t) || !std::isfinite(t_end) || !(t_end >= state->t)) return SBI_ERR_INVALID_ARG;
     if (!(dt > 0.0) || !std::isfinite(dt) || !(rk_tol > 0.0) || !std::isfinite(rk_tol)) return SBI_ERR_INVALID_ARG;
-    if (c->grid.mode == SBI_MODE_ITER && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
+    if (c->grid.mode != SBI_MODE_SA && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
     // step-size controller: growth limits and safety factor of the usual
     // embedded-pair control, exponent 1/5 (the local error of the fourth-order
     // solution is O(h^5))
@@ -1807,7 +1971,7 @@ extern "C" sbi_status sbi_step_adaptive(sbi_ctx* c, sbi_state* state, double t_e
         for (int stage = 0; stage < 6; ++stage) {
             int vh = 0;
             SBI_TRY(solve_stage(c, nullptr, tol, true, &vh));
-            if (c->grid.mode == SBI_MODE_ITER) {
+            if (c->grid.mode != SBI_MODE_SA) {
                 sbi_status st = solve_status(c, nullptr, true);
                 if (st < 0) return st;
                 if (st > worst) worst = st;
@@ -1860,7 +2024,7 @@ extern "C" sbi_status sbi_diagnostics(sbi_ctx* c, const sbi_state* state, double
     SBI_TRY(to_spectral(c, state->eta, state->phi_s, false));
     int vh = 0;
     SBI_TRY(solve_stage(c, nullptr, tol, false, &vh));
-    sbi_status st = solve_status(c, nullptr, c->grid.mode == SBI_MODE_ITER);
+    sbi_status st = solve_status(c, nullptr, c->grid.mode != SBI_MODE_SA);
     if (st < 0) return st;
     DiagParams dp{};
     dp.g = c->gd;
@@ -2292,6 +2456,11 @@ static sbi_status tune_key(const sbi_ctx* c, std::string* key) {
 }
 
 static sbi_status autotune(sbi_ctx* c, int32_t flags, sbi_plan* out) {
+    if (c->grid.mode == SBI_MODE_FULL) {
+        // its pair kernels have no launch-plan choices: the default plan stays
+        if (out) *out = sbi_plan{c->gd.row_var, c->gd.row_rpw, c->group_target, 0.f, 0};
+        return SBI_OK;
+    }
     std::string key;
     SBI_TRY(tune_key(c, &key));
     if (!(flags & SBI_TUNE_FORCE)) {
@@ -2421,6 +2590,8 @@ extern "C" sbi_status sbi_batch_init(sbi_batch** out, int32_t m, const sbi_grid*
     *out = nullptr;
     for (int i = 0; i < m; ++i)
         if (!grid_valid(&grids[i]) || !depths[i]) return SBI_ERR_INVALID_ARG;
+    for (int i = 0; i < m; ++i)
+        if (grids[i].mode == SBI_MODE_FULL) return SBI_ERR_UNSUPPORTED;  // its solve polls the host
     const size_t need = sbi_batch_workspace_bytes(m, grids);
     if (ws_bytes < need) return SBI_ERR_WORKSPACE;
     auto* b = new sbi_batch();
@@ -2667,7 +2838,7 @@ extern "C" sbi_status sbi_batch_step(sbi_batch* b, sbi_state* states, double dt,
     for (int i = 0; i < b->m; ++i)
         if (!states[i].eta || !states[i].phi_s) return SBI_ERR_INVALID_ARG;
     for (auto& gr : b->g) {
-        if (gr.c->grid.mode == SBI_MODE_ITER && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
+        if (gr.c->grid.mode != SBI_MODE_SA && !(tol >= 0.0)) return SBI_ERR_INVALID_ARG;
         if (gr.c->grid.seed == SBI_SEED_NET && !gr.c->net_loaded && !gr.c->hist_loaded) return SBI_ERR_INVALID_ARG;
         gr.c->st = Stats();
         gr.c->fallbacks = 0;

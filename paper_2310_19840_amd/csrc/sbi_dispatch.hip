@@ -86,6 +86,9 @@ SBI_DISPATCH(launch_row_blend, RowBlendParams)
 SBI_DISPATCH(launch_row_feat, RowFeatParams)
 SBI_DISPATCH(launch_col, ColParams)
 
+hipError_t launch_full(int fp64, const FullParams& p, int what, hipStream_t s) {
+    return fp64 ? launch_full_t<double>(p, what, s) : launch_full_t<float>(p, what, s);
+}
 int row_var_mask(int fp64, int sweep, int nx) {
     return fp64 ? row_var_mask_t<double>(sweep, nx) : row_var_mask_t<float>(sweep, nx);
 }

@@ -1,0 +1,362 @@
+// sbi_full.hip -- the fully nonlinear W solve of one-dimensional grids over a
+// flat bed: the surface boundary-integral equation of Sec. 2.3 with the
+// remaining integrals I^(S) of App. A kept (Eq. con-V: V = sum_j V^(j) +
+// I^(S), whose sum is the exact equation).
+//
+// Two-dimensional flow (one horizontal dimension): Green function -ln r with
+// the image of the source in the bed z = -h, jump coefficient pi; for the
+// periodic surface z = x + i eta(x), 0 <= x < L,
+//
+//   S[V] = pi phi_s + D[phi_s],
+//   S[V](x_i) = int V(x') G dx',  D[f](x_i) = int f(x') dG/dn' sqrt(1 + eta_x'^2) dx',
+//   G = -ln|2 sin(pi (z - z') / L)| - ln|2 sin(pi (z - conj(z') + 2 i h) / L)|.
+//
+// The solve iterates V_(n+1) = S0^-1 [pi phi_s + D[phi_s] - (S - S0)[V_n]]
+// from V_0 = 0, where S0 is S on the undisturbed surface (Fourier multiplier
+// (pi / |k|) (1 + exp(-2 |k| h))).  The kernels of S - S0 and D are smooth and
+// periodic, so the trapezoidal rule over the grid is spectrally accurate;
+// S0^-1 and the derivatives eta_x, eta_xx are circulant matrices on the grid
+// (their discrete Fourier multipliers), applied by direct summation.  The work
+// is O(n^2) per application: every kernel evaluates point pairs, split over
+// workgroups along both the evaluation and the source points.  Deep water
+// (k_1 h > 18, k_1 = 2 pi / L) drops the image terms.
+//
+// One object per precision (SBI_REAL): fields and the pair arithmetic run in
+// that type; the circulant tables, the slices of the pair sums and every
+// accumulation are FP64 (the direct sums over n points would otherwise lose
+// about log10(sqrt(n)) digits in FP32).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "sbi_device.hpp"
+#include "sbi_kernels.hpp"
+
+#ifndef SBI_REAL
+#define SBI_REAL double
+#endif
+
+namespace sbi {
+
+using Real = SBI_REAL;
+
+constexpr int kFullThreads = 256;       // evaluation points per workgroup
+constexpr double kDeepK1H = 18.0;       // exp(-2 k_1 h) < 1e-15 beyond this
+
+__device__ __forceinline__ bool full_deep(const FullParams& p, int m) {
+    return (2.0 * M_PI / p.lx) * p.href[m] > kDeepK1H;
+}
+
+// --- tables: S0^-1 (per member: its depth), eta_x and eta_xx circulants,
+// sin^2(pi j / n).  c[j] = (1/n) sum_m s(k_m) cos(2 pi m j / n) with
+// s = |k| / (pi (1 + exp(-2 |k| h))), k_m the m-th discrete wavenumber (the
+// Nyquist mode included); d1[j] = (1/n) sum_(0<m<n/2) (-2 k_m) sin(2 pi m j / n)
+// (the Nyquist mode drops out of a first derivative of a real field);
+// d2[j] = (1/n) sum_m (-k_m^2) cos(2 pi m j / n).
+template <typename R>
+__global__ void __launch_bounds__(kFullThreads) k_full_tables(const FullParams p) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    const int n = p.n;
+    if (j >= n) return;
+    const double dk = 2.0 * M_PI / p.lx;
+    const bool deep = full_deep(p, m);
+    const double h = p.href[m];
+    double c = 0.0, d1 = 0.0, d2 = 0.0;
+    for (int q = 1; q < n; ++q) {
+        const int qq = q <= n / 2 ? q : n - q;
+        const double k = dk * qq;
+        // angle 2 pi q j / n reduced exactly in integers
+        const long long r = ((long long)q * j) % n;
+        const double cs = cospi(2.0 * (double)r / n);
+        const double s = k / (M_PI * (1.0 + (deep ? 0.0 : exp(-2.0 * k * h))));
+        c += s * cs;
+        if (m == 0) {
+            d2 -= k * k * cs;
+            if (q < n / 2) d1 -= 2.0 * k * sinpi(2.0 * (double)r / n);
+        }
+    }
+    static_cast<double*>(p.c0)[(long long)m * n + j] = c / n;
+    {
+        // the flat image's single-layer term 1/2 ln(sin^2(pi j / n) + sinh^2(2 pi h / L)) of this member
+        const double sn = sinpi((double)j / n), sh = deep ? 0.0 : sinh(2.0 * M_PI * h / p.lx);
+        static_cast<double*>(p.lfl)[(long long)m * n + j] = deep ? 0.0 : 0.5 * log(sn * sn + sh * sh);
+    }
+    if (m == 0) {
+        static_cast<double*>(p.d1)[j] = d1 / n;
+        static_cast<double*>(p.d2)[j] = d2 / n;
+        const double sn = sinpi((double)j / n);
+        static_cast<double*>(p.s2)[j] = sn * sn;
+    }
+}
+
+// Circulant sums are split over kLanes lanes per output point (the lanes of
+// an output take every kLanes-th source point, so the lanes of a wavefront
+// read consecutive table and source entries) and folded by lane exchanges.
+constexpr int kLanes = 16;
+constexpr int kOutPerBlock = kFullThreads / kLanes;
+
+__device__ __forceinline__ double lane_fold(double v) {
+#pragma unroll
+    for (int off = kLanes / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kLanes);
+    return v;
+}
+
+// --- eta_x, eta_xx at every point: circulant sums over the member's eta
+template <typename R>
+__global__ void __launch_bounds__(kFullThreads) k_full_geom(const FullParams p) {
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * kOutPerBlock + t / kLanes;
+    const int l = t % kLanes;
+    const int m = blockIdx.z;
+    const int n = p.n;
+    const R* eta = static_cast<const R*>(p.eta) + m * p.s_phys;
+    const double* d1 = static_cast<const double*>(p.d1);
+    const double* d2 = static_cast<const double*>(p.d2);
+    double a1 = 0.0, a2 = 0.0;
+    if (i < n)
+        for (int j = l; j < n; j += kLanes) {
+            const int d = (i - j + n) & (n - 1);  // n is a power of two
+            const double e = (double)eta[j];
+            a1 += d1[d] * e;
+            a2 += d2[d] * e;
+        }
+    a1 = lane_fold(a1);
+    a2 = lane_fold(a2);
+    if (i < n && l == 0) {
+        static_cast<R*>(p.ex)[m * p.s_phys + i] = R(a1);
+        static_cast<R*>(p.exx)[m * p.s_phys + i] = R(a2);
+    }
+}
+
+// Decision of launch `sweep` from the residual of the previous one (the
+// iteration mode's rules); every workgroup decides alike, the leader records.
+__device__ __forceinline__ bool full_decided(const FullParams& p, Ctl* ctl, bool leader) {
+    if (ctl->done) return true;
+    double r, rmin;
+    const int dec = sweep_decision(ctl, p.sweep, p.max_sweeps, p.tol, &r, &rmin);
+    if (dec) {
+        if (leader) {
+            const int st = dec - 100;
+            ctl->status = st;
+            ctl->sweeps = p.sweep;
+            ctl->residual = r;
+            ctl->done = 1;
+            ctl->acc_solves += 1;
+            ctl->acc_sweeps += p.sweep;
+            ctl->acc_sweeps_max = max(ctl->acc_sweeps_max, p.sweep);
+            ctl->acc_residual_max = fmax(ctl->acc_residual_max, r);
+            const int w = ctl->acc_worst;
+            if (st < 0 ? (w >= 0 || st < w) : (w >= 0 && st > w)) ctl->acc_worst = st;
+        }
+        return true;
+    }
+    if (leader) {
+        ctl->rmin = rmin;
+        ctl->residual = r;
+    }
+    return false;
+}
+
+// --- pair sums over a slice of the source points.  KIND 0: the double layer
+// D[phi_s]; KIND 1: the single layer (S - S0)[V].  Partial sums go to
+// part[split][member][point]; the consumer adds the slices in order.
+template <typename R, int KIND>
+__global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p) {
+    __shared__ R te[kFullThreads], tex[kFullThreads], tsrc[kFullThreads];
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * kFullThreads + t;
+    const int split = blockIdx.y;
+    const int m = blockIdx.z;
+    const int n = p.n;
+    if (KIND == 1) {
+        Ctl* ctl = p.ctl + m;
+        const bool leader = blockIdx.x == 0 && blockIdx.y == 0 && t == 0;
+        if (full_decided(p, ctl, leader)) return;  // workgroup-uniform
+    }
+    const long long mo = m * p.s_phys;
+    const R* eta = static_cast<const R*>(p.eta) + mo;
+    const R* ex = static_cast<const R*>(p.ex) + mo;
+    const R* src = static_cast<const R*>(KIND == 0 ? p.phi : p.vin) + mo;
+    const double* s2 = static_cast<const double*>(p.s2);
+    const double* lfl = static_cast<const double*>(p.lfl) + (long long)m * n;
+    const R pl = R(M_PI / p.lx);
+    const bool deep = full_deep(p, m);
+    const R b2h = R(2.0 * M_PI * p.href[m] / p.lx);  // 2 pi h / L
+    // this point's values
+    const bool on = i < n;
+    const R etai = on ? eta[i] : R(0);
+    const R exi = on ? ex[i] : R(0);
+    double acc = 0.0;
+    const int chunk = (n + gridDim.y - 1) / gridDim.y;
+    const int jbeg = split * chunk, jend = min(n, jbeg + chunk);
+    for (int j0 = jbeg; j0 < jend; j0 += kFullThreads) {
+        __syncthreads();
+        const int jl = j0 + t;
+        if (jl < jend) {
+            te[t] = eta[jl];
+            tex[t] = ex[jl];
+            tsrc[t] = src[jl];
+        }
+        __syncthreads();
+        const int jn = min(kFullThreads, jend - j0);
+        if (!on) continue;
+        for (int jj = 0; jj < jn; ++jj) {
+            const int j = j0 + jj;
+            const int d = (j - i + n) & (n - 1);
+            const R sa2 = R(s2[d]);                       // sin^2(pi (x_j - x_i) / L)
+            // sinh of the scaled elevation difference, formed from the difference
+            // itself (from exponentials of each point it would lose all relative
+            // accuracy for nearby points)
+            const R shb = sinh(pl * (te[jj] - etai));     // sinh(pi (eta_j - eta_i) / L)
+            R kv;
+            if (KIND == 1) {
+                // -1/2 ln(1 + sinh^2 / sin^2); its limit -1/2 ln(1 + eta_x^2) at j = i
+                kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb / sa2);
+                if (!deep) {
+                    // image minus flat image: -1/2 ln(sin^2 + sinh^2(pi (eta_i + eta_j + 2h) / L))
+                    // + 1/2 ln(sin^2 + sinh^2(2 pi h / L))
+                    const R shp = sinh(pl * (te[jj] + etai) + b2h);
+                    kv += R(-0.5) * log(sa2 + shp * shp) + R(lfl[d]);
+                }
+            } else {
+                // Im[(pi/L) cot(a + i b) (1 + i eta_x,j)], a = pi (x_j - x_i)/L, b = pi (eta_j - eta_i)/L:
+                // cot(a + i b) = (sin 2a - i sinh 2b) / (2 (sin^2 a + sinh^2 b))
+                const R s2a = sinpi(R(2) * R(d) / R(n));  // sin 2a
+                if (j == i) {
+                    kv = R(0);  // the curvature limit is added below
+                } else {
+                    const R chb = sqrt(R(1) + shb * shb);
+                    const R den = R(2) * (sa2 + shb * shb);
+                    kv = pl * (R(-2) * shb * chb + s2a * tex[jj]) / den;
+                }
+                if (!deep) {
+                    // the image partner: b' = pi (eta_i + eta_j + 2h) / L
+                    const R shp = sinh(pl * (te[jj] + etai) + b2h);
+                    const R chp = sqrt(R(1) + shp * shp);
+                    const R den = R(2) * (sa2 + shp * shp);
+                    kv += pl * (R(-2) * shp * chp + s2a * tex[jj]) / den;
+                }
+            }
+            acc += (double)kv * (double)tsrc[jj];
+        }
+    }
+    if (!on) return;
+    const double dx = p.lx / n;
+    double out = acc * dx;
+    if (KIND == 0 && i >= jbeg && i < jend) {
+        // the diagonal of the direct double layer: eta_xx / (2 (1 + eta_x^2))
+        const double exx = (double)static_cast<const R*>(p.exx)[mo + i];
+        out += dx * exx / (2.0 * (1.0 + (double)exi * (double)exi)) * (double)src[i];
+    }
+    static_cast<double*>(p.part)[((long long)split * p.batch + m) * n + i] = out;
+}
+
+// --- rhs = pi phi_s + D[phi_s] (slices added in order)
+template <typename R>
+__global__ void k_full_rhs(const FullParams p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.z;
+    if (i >= p.n) return;
+    const long long mo = m * p.s_phys;
+    double a = M_PI * (double)static_cast<const R*>(p.phi)[mo + i];
+    for (int s = 0; s < p.nsplit; ++s) a += static_cast<const double*>(p.part)[((long long)s * p.batch + m) * p.n + i];
+    static_cast<double*>(p.rhs)[(long long)m * p.n + i] = a;
+}
+
+// --- w = rhs - (S - S0)[V_n] (the slices of the pair pass, in order; w = rhs
+// at the first sweep, from V_0 = 0)
+template <typename R>
+__global__ void k_full_combine(const FullParams p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.z;
+    if (i >= p.n) return;
+    if (p.ctl[m].done) return;  // decided by this sweep's pair pass
+    const long long o = (long long)m * p.n + i;
+    double w = static_cast<const double*>(p.rhs)[o];
+    if (p.vin)
+        for (int s = 0; s < p.nsplit; ++s) w -= static_cast<const double*>(p.part)[((long long)s * p.batch + m) * p.n + i];
+    static_cast<double*>(p.w)[o] = w;
+}
+
+// --- V_(n+1) = S0^-1 w and the residual maxima max|V_(n+1) - V_n|,
+// max|V_(n+1)| into the member's slot `sweep`
+template <typename R>
+__global__ void __launch_bounds__(kFullThreads) k_full_apply(const FullParams p) {
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * kOutPerBlock + t / kLanes;
+    const int l = t % kLanes;
+    const int m = blockIdx.z;
+    const int n = p.n;
+    Ctl* ctl = p.ctl + m;
+    if (ctl->done) return;  // decided by this sweep's pair pass (workgroup-uniform)
+    const long long mo = m * p.s_phys;
+    const double* w = static_cast<const double*>(p.w) + (long long)m * n;
+    const double* c = static_cast<const double*>(p.c0) + (long long)m * n;
+    double acc = 0.0;
+    if (i < n)
+        for (int j = l; j < n; j += kLanes) acc += c[(i - j + n) & (n - 1)] * w[j];
+    acc = lane_fold(acc);
+    unsigned long long nu = 0ull, de = 0ull;
+    if (i < n && l == 0) {
+        const R v = R(acc);
+        static_cast<R*>(p.vout)[mo + i] = v;
+        const double vold = p.vin ? (double)static_cast<const R*>(p.vin)[mo + i] : 0.0;
+        nu = abs_bits((double)v - vold);
+        de = abs_bits((double)v);
+        if (!isfinite((double)v)) nu = de = 0x7ff8000000000000ull;  // a NaN key outranks every finite one
+    }
+    block_reduce2_max_u64(nu, de);
+    if (t == 0) {
+        atomicMax(&ctl->slots->num[p.sweep], nu);
+        atomicMax(&ctl->slots->den[p.sweep], de);
+    }
+}
+
+// --- the decided iterate V_s of every member (s = its sweep count) -> out
+template <typename R>
+__global__ void k_full_select(const FullParams p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.z;
+    if (i >= p.n) return;
+    const int s = p.ctl[m].sweeps;
+    const long long mo = m * p.s_phys;
+    static_cast<R*>(p.vfinal)[mo + i] = static_cast<const R*>(p.vbuf[s & 1])[mo + i];
+}
+
+// ---------------------------------------------------------------------------
+template <> hipError_t launch_full_t<Real>(const FullParams& p, int what, hipStream_t s) {
+    const int n = p.n;
+    const int tiles = (n + kFullThreads - 1) / kFullThreads;
+    const int outs = (n + kOutPerBlock - 1) / kOutPerBlock;
+    switch (what) {
+        case FULL_TABLES:
+            hipLaunchKernelGGL(k_full_tables<Real>, dim3(tiles, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_GEOM:
+            hipLaunchKernelGGL(k_full_geom<Real>, dim3(outs, 1, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_DOUBLE:
+            hipLaunchKernelGGL((k_full_pairs<Real, 0>), dim3(tiles, p.nsplit, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_RHS:
+            hipLaunchKernelGGL(k_full_rhs<Real>, dim3(tiles, 1, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_SINGLE:
+            hipLaunchKernelGGL((k_full_pairs<Real, 1>), dim3(tiles, p.nsplit, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_COMBINE:
+            hipLaunchKernelGGL(k_full_combine<Real>, dim3(tiles, 1, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_APPLY:
+            hipLaunchKernelGGL(k_full_apply<Real>, dim3(outs, 1, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_SELECT:
+            hipLaunchKernelGGL(k_full_select<Real>, dim3(tiles, 1, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sbi

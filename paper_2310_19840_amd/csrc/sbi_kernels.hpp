@@ -196,6 +196,38 @@ struct DiagParams {
     int nblk;
 };
 
+// Fully nonlinear W solve of one-dimensional flat-bed grids (sbi_full.hip):
+// the operands of its kernels.  Physical fields are [batch][n] with member
+// stride s_phys; FP64 tables: c0 [batch][n] (S0^-1 circulant per member), d1,
+// d2, s2 [n]; FP64 part [nsplit][batch][n] holds the slices of a pair pass and
+// rhs [batch][n] the right-hand side.
+struct FullParams {
+    int n, batch, nsplit;
+    double lx;
+    long long s_phys;
+    const double* href;   // [batch] depth of each member's flat bed
+    const void* eta;      // physical eta
+    const void* phi;      // physical phi_s
+    void* ex;             // eta_x
+    void* exx;            // eta_xx
+    void* rhs;            // pi phi_s + D[phi_s] (FP64, [batch][n])
+    void* part;           // pair-pass slices
+    void* c0;
+    void* d1;
+    void* d2;
+    void* s2;
+    void* lfl;            // [batch][n] the flat image's single-layer term per member
+    void* w;              // FP64 [batch][n]: rhs - (S - S0)[V_n]
+    const void* vin;      // V_n (null: V_0 = 0)
+    void* vout;           // V_(n+1)
+    const void* vbuf[2];  // the two iterate buffers (V_s is in vbuf[s & 1])
+    void* vfinal;         // the decided iterate of each member
+    Ctl* ctl;
+    int sweep, max_sweeps;
+    double tol;
+};
+enum { FULL_TABLES = 0, FULL_GEOM, FULL_DOUBLE, FULL_RHS, FULL_SINGLE, FULL_COMBINE, FULL_APPLY, FULL_SELECT };
+
 struct Twiddles {
     const void* tx;   // length nx
     const void* tn;   // length nx/2
@@ -228,6 +260,8 @@ template <typename R> int row_var_mask_t(int sweep, int nx);
 // rows per workgroup of a row variant at its 256-thread launch bound
 template <typename R> int row_rows_cap_t(int nx, int var);
 int row_var_mask(int fp64, int sweep, int nx);
+template <typename R> hipError_t launch_full_t(const FullParams&, int what, hipStream_t);
+hipError_t launch_full(int fp64, const FullParams& p, int what, hipStream_t s);
 int row_rows_cap(int fp64, int nx, int var);
 
 hipError_t launch_row_fwd(int fp64, const RowFwdParams& p, int batch, const Twiddles& tw, hipStream_t s);

@@ -172,3 +172,15 @@ def test_plan_interface_host_checks(lib, tmp_path):
     assert lib.sbi_autotune(None, 0, None) == _lib.SBI_ERR_INVALID_ARG
     assert lib.sbi_plan_variants(None) == 0
     assert lib.sbi_batch_plan(None, 0, C.byref(p)) == _lib.SBI_ERR_INVALID_ARG
+
+
+def test_full_mode_grids(lib):
+    """The fully nonlinear mode takes one-dimensional grids only and sizes its
+    FP64 tables and pair slices into the workspace."""
+    from paper_2310_19840_amd import _lib, make_grid
+    g1 = make_grid(1024, 1, 50.0, mode="full")
+    gi = make_grid(1024, 1, 50.0, mode="iter")
+    assert lib.sbi_workspace_bytes(C.byref(g1), 1) > lib.sbi_workspace_bytes(C.byref(gi), 1)
+    g2 = make_grid(64, 64, 50.0, 50.0, mode="full")
+    assert lib.sbi_workspace_bytes(C.byref(g2), 1) == 0
+    assert _lib.SBI_MODE_FULL == 2

@@ -1,0 +1,130 @@
+"""The fully nonlinear W solve (SBI_MODE_FULL: the surface boundary-integral
+equation with the remaining integrals I^(S) kept; one dimension, flat bed) on
+the GPU against the oracle (oracle/full_bie.py): W with the same sweep count
+(FP64 within 1e-11, FP32 within 1e-5 of the oracle fed FP32-rounded inputs),
+exact Stokes waves, time steps, and what the mode refuses."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import sbi_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _t(x, dtype, dev):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=dev)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _sea(nx, seed, amp):
+    lx = 2 * math.pi * nx / 32          # 32 points per wavelength of the peak (k = 1)
+    gs = si.GridSpec(nx, 1, lx, 1.0)
+    eta = si.narrowband_random(gs, seed, amp=amp)
+    phi = si.narrowband_random(gs, seed + 1, amp=2 * amp)
+    return lx, eta, phi
+
+
+@pytest.mark.parametrize("nx", [64, 256, 1024, 4096])
+@pytest.mark.parametrize("depth", [1.0, 50.0])
+def test_full_w_matches_oracle(gpu, nx, depth):
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    lx, eta, phi = _sea(nx, nx + 3, 0.12)
+    _say("full W", nx, "depth", depth)
+    g = Grid(nx, 1, lx)
+    dep = np.full((1, nx), depth)
+    o = OSolver(g, dep, mode="full", max_sweeps=100)
+    Wo, oi = o.vertical_velocity(eta, phi, tol=1e-12)
+    s = Solver(nx, 1, lx, 1.0, dep, device=gpu, mode="full", max_sweeps=100)
+    W, st, info = s.vertical_velocity(_t(eta, torch.float64, gpu), _t(phi, torch.float64, gpu), tol=1e-12)
+    err = _rel(W.cpu().numpy()[0], Wo)
+    _say(f"   W err {err:.2e}, sweeps {info[0][0]}/{oi.sweeps}")
+    assert st == 0 and info[0][0] == oi.sweeps
+    assert err < 1e-11
+    # FP32 against the oracle on the same FP32-rounded inputs
+    e32, p32 = eta.astype(np.float32), phi.astype(np.float32)
+    Wo32, _ = OSolver(g, dep, mode="full", max_sweeps=100).vertical_velocity(
+        e32.astype(np.float64), p32.astype(np.float64), tol=1e-12)
+    s32 = Solver(nx, 1, lx, 1.0, dep, device=gpu, mode="full", max_sweeps=100, precision="fp32")
+    W32, st32, _ = s32.vertical_velocity(_t(e32, torch.float32, gpu), _t(p32, torch.float32, gpu), tol=1e-6)
+    err32 = _rel(W32.cpu().numpy()[0].astype(np.float64), Wo32)
+    _say(f"   FP32 W err {err32:.2e}")
+    assert st32 >= 0 and err32 < 1e-5
+
+
+@pytest.mark.parametrize("eps,bar", [(0.3, 1e-10), (0.35, 5e-9)])
+def test_full_w_of_exact_stokes_waves(gpu, eps, bar):
+    """Deep-water Stokes waves from the stream-function method: the GPU's
+    fully nonlinear W equals the exact one on the kept band (all modes but
+    Nyquist), where the expansion of order 7 is off by 1e-5 (eps = 0.3) and
+    7e-4 (eps = 0.35)."""
+    import torch
+    from oracle import Grid
+    from oracle.fenton import SteadyWave
+    from paper_2310_19840_amd import Solver
+    w = SteadyWave(2 * eps)
+    x = np.arange(64) * 2 * math.pi / 64
+    eta, _, phi, V = w.surface(x)
+    g = Grid(64, 1, 2 * math.pi, dealias=0.99)
+    Vm = g.ifft(g.MF(V[None]))[0]
+    s = Solver(64, 1, 2 * math.pi, 1.0, np.full((1, 64), 60.0), device=gpu, mode="full", max_sweeps=100,
+               dealias=0.99)
+    W, st, info = s.vertical_velocity(_t(eta, torch.float64, gpu), _t(phi, torch.float64, gpu), tol=1e-13)
+    err = _rel(W.cpu().numpy()[0], Vm)
+    sa = Solver(64, 1, 2 * math.pi, 1.0, np.full((1, 64), 60.0), device=gpu, mode="sa")
+    W7, _, _ = sa.vertical_velocity(_t(eta, torch.float64, gpu), _t(phi, torch.float64, gpu))
+    err7 = _rel(W7.cpu().numpy()[0], V)
+    _say(f"eps {eps}: full {err:.2e} ({info[0][0]} sweeps), order 7 {err7:.2e}")
+    assert st == 0 and err < bar and err7 > 1e3 * err
+
+
+@pytest.mark.parametrize("depth", [1.0, 50.0])
+def test_full_steps_match_oracle(gpu, depth):
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    nx = 256
+    lx, eta, phi = _sea(nx, 17, 0.1)
+    dep = np.full((1, nx), depth)
+    om = math.sqrt(math.tanh(depth))
+    dt = 2 * math.pi / om / 32
+    o = OSolver(Grid(nx, 1, lx), dep, mode="full", max_sweeps=100)
+    eo, po, sto = o.step(eta, phi, dt, 4, tol=1e-12)
+    s = Solver(nx, 1, lx, 1.0, dep, device=gpu, mode="full", max_sweeps=100)
+    e = _t(eta[None], torch.float64, gpu)
+    p = _t(phi[None], torch.float64, gpu)
+    st, info = s.step(e, p, dt, 4, tol=1e-12)
+    _say(f"full steps depth {depth}: sweeps {info['sweeps_total']}/{sum(i.sweeps for i in sto)}")
+    assert st == 0 and info["solves"] == 16
+    assert info["sweeps_total"] == sum(i.sweeps for i in sto)
+    assert _rel(e.cpu().numpy().reshape(eo.shape), eo) < 1e-10
+    assert _rel(p.cpu().numpy().reshape(po.shape), po) < 1e-10
+
+
+def test_full_mode_refusals(gpu):
+    from paper_2310_19840_amd import Batch, SBIError, Solver, _lib
+    # two-dimensional grids: not a valid grid for the mode
+    with pytest.raises(SBIError):
+        Solver(32, 32, 10.0, 10.0, np.ones((32, 32)), device=gpu, mode="full")
+    # a variable bed
+    x = np.arange(64) * 10.0 / 64
+    with pytest.raises(SBIError) as ex:
+        Solver(64, 1, 10.0, 1.0, (1.0 - 0.1 * np.cos(2 * math.pi * x / 10.0))[None], device=gpu, mode="full")
+    assert ex.value.code == _lib.SBI_ERR_UNSUPPORTED
+    # ensembles
+    with pytest.raises(SBIError) as ex:
+        Batch([dict(nx=64, ny=1, lx=10.0, ly=1.0, depth=np.ones((1, 64)), mode="full")], device=gpu)
+    assert ex.value.code == _lib.SBI_ERR_UNSUPPORTED
