@@ -15,9 +15,13 @@
  * tol, state pointers, seeds and sweep budgets); up to 8 instantiated graphs
  * are kept, least recently used first out.  With SBI_BATCH_AUTOTUNE each
  * group's launch plan (row-transform radix and twiddle mode, rows per row
- * workgroup, column-pass product split; sbi.h, sbi_plan) is chosen at init by
- * sbi_autotune on the group's context, consulting the process's plan cache
- * first (sbi_tune_cache_load / _save persist it).
+ * workgroup, column-pass product split; sbi.h, sbi_plan) is chosen at init:
+ * one group is tuned like a context (sbi_autotune); with several, each
+ * group's candidates are timed while every group runs its unit of work
+ * concurrently (group by group, from the default plans), since the fastest
+ * plan of a group alone need not be the fastest beside the others.  The
+ * process's plan cache is consulted first (sbi_tune_cache_load / _save
+ * persist it; an ensemble's entries are keyed by all its groups).
  *
  * Iterations run without host polling: each solve enqueues the sweep
  * launches of a budget B and a member's launches after the pass that decides

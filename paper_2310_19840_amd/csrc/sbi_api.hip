@@ -2455,6 +2455,22 @@ static sbi_status tune_key(const sbi_ctx* c, std::string* key) {
     return SBI_OK;
 }
 
+// the plans the tuner tries: every built row variant, rows per workgroup from
+// the launch bound down to a quarter of it, column splits of 2D grids
+static std::vector<sbi_plan> plan_candidates(const sbi_ctx* c) {
+    std::vector<sbi_plan> out;
+    const int mask = plan_variants(c);
+    std::vector<int> splits = {0};
+    if (c->grid.ny > 1) splits = {0, 1024, 2048, 4096};
+    for (int v = 0; v < 3; ++v) {
+        if (!((mask >> v) & 1)) continue;
+        const int cap = std::min(row_rows_cap(c->fp64, c->grid.nx, v), c->grid.ny);
+        for (int rows = cap; rows >= 1 && rows * 4 >= cap; rows /= 2)
+            for (int sp : splits) out.push_back(sbi_plan{v, rows, sp, 0.f, 0});
+    }
+    return out;
+}
+
 static sbi_status autotune(sbi_ctx* c, int32_t flags, sbi_plan* out) {
     if (c->grid.mode == SBI_MODE_FULL) {
         // its pair kernels have no launch-plan choices: the default plan stays
@@ -2475,9 +2491,6 @@ static sbi_status autotune(sbi_ctx* c, int32_t flags, sbi_plan* out) {
             return SBI_OK;
         }
     }
-    const int mask = plan_variants(c);
-    std::vector<int> splits = {0};
-    if (c->grid.ny > 1) splits = {0, 1024, 2048, 4096};
     hipEvent_t e0, e1;
     SBI_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -2488,21 +2501,14 @@ static sbi_status autotune(sbi_ctx* c, int32_t flags, sbi_plan* out) {
     sbi_plan best = before;
     best.us = 1e30f;
     sbi_status st = SBI_OK;
-    for (int v = 0; v < 3 && st == SBI_OK; ++v) {
-        if (!((mask >> v) & 1)) continue;
-        const int cap = std::min(row_rows_cap(c->fp64, c->grid.nx, v), c->grid.ny);
-        for (int rows = cap; rows >= 1 && rows * 4 >= cap && st == SBI_OK; rows /= 2) {
-            for (int sp : splits) {
-                const sbi_plan cand = {v, rows, sp, 0.f, 0};
-                st = plan_apply(c, cand);
-                float us = 0.f;
-                if (st == SBI_OK) st = tune_time(c, e0, e1, &us);
-                if (st != SBI_OK) break;
-                if (us < best.us) {
-                    best = cand;
-                    best.us = us;
-                }
-            }
+    for (const sbi_plan& cand : plan_candidates(c)) {
+        st = plan_apply(c, cand);
+        float us = 0.f;
+        if (st == SBI_OK) st = tune_time(c, e0, e1, &us);
+        if (st != SBI_OK) break;
+        if (us < best.us) {
+            best = cand;
+            best.us = us;
         }
     }
     (void)hipEventDestroy(e0);
@@ -2583,6 +2589,106 @@ extern "C" sbi_status sbi_tune_cache_save(const char* path, int32_t* count) {
     return SBI_OK;
 }
 
+// Plans of an ensemble: its groups run concurrently, so a group's plan is
+// timed with every group running (one unit of each on its own stream, forked
+// from and joined to the batch's stream), group by group (coordinate
+// descent from the default plans).  A single group is the context's own
+// tuning.  The plan cache keys an ensemble's plans by all its groups' keys.
+static sbi_status ensemble_time(sbi_batch* b, hipEvent_t e0, hipEvent_t e1, float* us) {
+    constexpr int kRounds = 2, kReps = 3;
+    auto unit = [&]() -> sbi_status {
+        SBI_HIP(hipEventRecord(b->fork, b->cap));
+        for (auto& gr : b->g) {
+            SBI_HIP(hipStreamWaitEvent(gr.s, b->fork, 0));
+            SBI_TRY(hip_ok(launch_ctl_reset(gr.c->ctl, gr.c->batch, gr.c->grid.max_sweeps + 2, gr.s)));
+            SBI_TRY(tune_unit(gr.c));
+            SBI_HIP(hipEventRecord(gr.done, gr.s));
+            SBI_HIP(hipStreamWaitEvent(b->cap, gr.done, 0));
+        }
+        return SBI_OK;
+    };
+    SBI_TRY(unit());  // warm-up
+    float best = 1e30f;
+    for (int r = 0; r < kRounds; ++r) {
+        SBI_HIP(hipEventRecord(e0, b->cap));
+        for (int k = 0; k < kReps; ++k) SBI_TRY(unit());
+        SBI_HIP(hipEventRecord(e1, b->cap));
+        SBI_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        SBI_HIP(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, 1e3f * ms / kReps);
+    }
+    *us = best;
+    return SBI_OK;
+}
+
+static sbi_status batch_autotune(sbi_batch* b) {
+    if (b->g.size() == 1) return autotune(b->g[0].c, 0, nullptr);
+    std::string ens = "ens";
+    std::vector<std::string> keys;
+    for (auto& gr : b->g) {
+        std::string k;
+        SBI_TRY(tune_key(gr.c, &k));
+        keys.push_back(k);
+        ens += ";" + k;
+    }
+    auto gkey = [&](size_t i) { return ens + "#g" + std::to_string(i); };
+    {
+        TuneCache& tc = tune_cache();
+        std::lock_guard<std::mutex> lk(tc.mu);
+        bool all = true;
+        for (size_t i = 0; i < b->g.size() && all; ++i) all = tc.plans.count(gkey(i)) > 0;
+        if (all) {
+            bool ok = true;
+            for (size_t i = 0; i < b->g.size(); ++i) ok = ok && plan_apply(b->g[i].c, tc.plans[gkey(i)]) == SBI_OK;
+            if (ok) return SBI_OK;
+        }
+    }
+    hipEvent_t e0, e1;
+    SBI_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SBI_ERR_HIP;
+    }
+    sbi_status st = SBI_OK;
+    std::vector<sbi_plan> best(b->g.size());
+    for (size_t i = 0; i < b->g.size(); ++i) {
+        sbi_ctx* c = b->g[i].c;
+        best[i] = sbi_plan{c->gd.row_var, c->gd.row_rpw, c->group_target, 0.f, 0};
+    }
+    float cur = 0.f;
+    if (st == SBI_OK) st = ensemble_time(b, e0, e1, &cur);
+    for (size_t i = 0; i < b->g.size() && st == SBI_OK; ++i) {
+        sbi_ctx* c = b->g[i].c;
+        if (c->grid.mode == SBI_MODE_FULL) continue;
+        for (const sbi_plan& cand : plan_candidates(c)) {
+            st = plan_apply(c, cand);
+            float us = 0.f;
+            if (st == SBI_OK) st = ensemble_time(b, e0, e1, &us);
+            if (st != SBI_OK) break;
+            if (us < cur) {
+                cur = us;
+                best[i] = cand;
+            }
+        }
+        if (st == SBI_OK) st = plan_apply(c, best[i]);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != SBI_OK) return st;
+    for (size_t i = 0; i < b->g.size(); ++i) {
+        sbi_ctx* c = b->g[i].c;
+        c->have_prev = false;
+        c->hist_count = 0;
+        best[i].us = cur;
+        SBI_TRY(hip_ok(launch_ctl_reset(c->ctl, c->batch, c->grid.max_sweeps + 2, c->stream)));
+    }
+    TuneCache& tc = tune_cache();
+    std::lock_guard<std::mutex> lk(tc.mu);
+    for (size_t i = 0; i < b->g.size(); ++i) tc.plans[gkey(i)] = best[i];
+    return SBI_OK;
+}
+
 extern "C" sbi_status sbi_batch_init(sbi_batch** out, int32_t m, const sbi_grid* grids, const double* const* depths,
                                      double h_ref, void* workspace, size_t ws_bytes, void* hip_stream,
                                      int32_t flags) {
@@ -2638,12 +2744,12 @@ extern "C" sbi_status sbi_batch_init(sbi_batch** out, int32_t m, const sbi_grid*
         if (st == SBI_WARN_DEPTH_CRITERION) warn = st;
         b->g.back().cmp_bytes = (size_t)(static_cast<char*>(b->g.back().c->comp[C_DB]) -
                                          static_cast<char*>(b->g.back().c->comp[C_DV]));
-        if (flags & SBI_BATCH_AUTOTUNE) {
-            st = autotune(b->g.back().c, 0, nullptr);
-            if (st < 0) {
-                batch_free(b);
-                return st;
-            }
+    }
+    if (flags & SBI_BATCH_AUTOTUNE) {
+        const sbi_status st = batch_autotune(b);
+        if (st < 0) {
+            batch_free(b);
+            return st;
         }
     }
     *out = b;
