@@ -336,7 +336,8 @@ int32_t sbi_last_stats(const sbi_ctx* ctx, double* out, int32_t n);
  *   row_variant  radix sequence and twiddle mode of the row sweep (iteration)
  *                or row SA kernels: 0 radix-8 passes with twiddle powers by
  *                recurrence (the default); 1 radix-8 with every twiddle power
- *                cached in registers; 2 radix-16 passes.  Which variants are
+ *                cached in registers; 2 radix-16 passes; 3 radix-4 passes (a
+ *                row spread over twice the threads).  Which variants are
  *                built depends on precision and row length (only variants that
  *                compile without register spills): sbi_plan_variants().
  *   row_rows     rows of the grid per row-pass workgroup (a power of two; 0:

@@ -213,7 +213,7 @@ class Solver:
     def plan_variants(self):
         """Row variants built for this context (list of variant numbers)."""
         m = self.lib.sbi_plan_variants(self.ctx)
-        return [v for v in range(3) if (m >> v) & 1]
+        return [v for v in range(4) if (m >> v) & 1]
 
     def plan(self):
         p = _lib.sbi_plan()

@@ -2391,7 +2391,7 @@ static int plan_variants(const sbi_ctx* c) {
 static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 static sbi_status plan_apply(sbi_ctx* c, const sbi_plan& p) {
-    if (p.row_variant < 0 || p.row_variant > 2 || !((plan_variants(c) >> p.row_variant) & 1))
+    if (p.row_variant < 0 || p.row_variant > 3 || !((plan_variants(c) >> p.row_variant) & 1))
         return SBI_ERR_UNSUPPORTED;
     if (p.row_rows < 0 || (p.row_rows > 0 && !pow2(p.row_rows)) || p.col_split < 0) return SBI_ERR_INVALID_ARG;
     c->gd.row_var = p.row_variant;
@@ -2462,7 +2462,7 @@ static std::vector<sbi_plan> plan_candidates(const sbi_ctx* c) {
     const int mask = plan_variants(c);
     std::vector<int> splits = {0};
     if (c->grid.ny > 1) splits = {0, 1024, 2048, 4096};
-    for (int v = 0; v < 3; ++v) {
+    for (int v = 0; v < 4; ++v) {
         if (!((mask >> v) & 1)) continue;
         const int cap = std::min(row_rows_cap(c->fp64, c->grid.nx, v), c->grid.ny);
         for (int rows = cap; rows >= 1 && rows * 4 >= cap; rows /= 2)
@@ -2561,7 +2561,7 @@ extern "C" sbi_status sbi_tune_cache_load(const char* path, int32_t* count) {
         sbi_plan p{};
         if (std::sscanf(line, "%511s %d %d %d %f", key, &p.row_variant, &p.row_rows, &p.col_split, &p.us) != 5)
             continue;
-        if (p.row_variant < 0 || p.row_variant > 2 || p.row_rows < 0 || p.col_split < 0) continue;
+        if (p.row_variant < 0 || p.row_variant > 3 || p.row_rows < 0 || p.col_split < 0) continue;
         got[key] = p;
     }
     std::fclose(f);

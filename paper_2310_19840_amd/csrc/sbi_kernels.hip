@@ -189,9 +189,9 @@ template <int NX, int EM = 8> __host__ __device__ constexpr int row_threads() {
 
 // Row transform of launch-plan variant VAR of the sweep and SA kernels:
 // 0 radix-8 passes with twiddle recurrence, 1 the same with every twiddle
-// power cached, 2 radix-16 passes
+// power cached, 2 radix-16 passes, 3 radix-4 passes
 template <typename R, int NX, int VAR> struct RowVarT {
-    using type = Row<R, NX, VAR == 2 ? 16 : 8, VAR == 1>;
+    using type = Row<R, NX, VAR == 2 ? 16 : (VAR == 3 ? 4 : 8), VAR == 1>;
 };
 template <typename R, int NX, int VAR> using RowVar = typename RowVarT<R, NX, VAR>::type;
 
@@ -1948,6 +1948,9 @@ template <typename R, int NX, int VAR, bool SWEEP> constexpr bool row_var_built(
     if constexpr (VAR == 0) return true;
     if constexpr (VAR == 1) return f32 || !SWEEP;
     if constexpr (VAR == 2) return f32 && (SWEEP ? NX == 512 : NX >= 512);
+    // radix 4 (4 values per thread): a row spans two or more wavefronts, so
+    // its exchanges take workgroup barriers; from 256-point rows
+    if constexpr (VAR == 3) return NX >= 256 && NX <= 4096;
     return false;
 }
 #define SBI_ROW_LAUNCH_VAR(KNAME, PTYPE, SWEEP)                                                            \
@@ -1972,6 +1975,7 @@ template <typename R, int NX, int VAR, bool SWEEP> constexpr bool row_var_built(
             case 0: return KNAME##_gv<R, NX, 0>(p, batch, tw, s);                                          \
             case 1: return KNAME##_gv<R, NX, 1>(p, batch, tw, s);                                          \
             case 2: return KNAME##_gv<R, NX, 2>(p, batch, tw, s);                                          \
+            case 3: return KNAME##_gv<R, NX, 3>(p, batch, tw, s);                                          \
             default: return hipErrorInvalidValue;                                                          \
         }                                                                                                  \
     }                                                                                                      \
@@ -2196,7 +2200,7 @@ template <> hipError_t launch_row_setup_t<Real>(const RowSetupParams& p, int b, 
 }
 template <typename R, int NX, bool SWEEP> static int row_var_mask_nx() {
     return (row_var_built<R, NX, 0, SWEEP>() ? 1 : 0) | (row_var_built<R, NX, 1, SWEEP>() ? 2 : 0) |
-           (row_var_built<R, NX, 2, SWEEP>() ? 4 : 0);
+           (row_var_built<R, NX, 2, SWEEP>() ? 4 : 0) | (row_var_built<R, NX, 3, SWEEP>() ? 8 : 0);
 }
 template <typename R, int NX> static int row_var_mask_k(int sweep) {
     return sweep ? row_var_mask_nx<R, NX, true>() : row_var_mask_nx<R, NX, false>();
@@ -2219,7 +2223,7 @@ template <> int row_var_mask_t<Real>(int sweep, int nx) {
 template <> int row_rows_cap_t<Real>(int nx, int var) {
     // rows per workgroup that fill 256 threads (the launch bound)
     const int n = nx / 2;
-    const int em = var == 2 ? 16 : 8;
+    const int em = var == 2 ? 16 : (var == 3 ? 4 : 8);
     const int e = n >= em ? em : n;
     const int P = n / e;
     return P >= 256 ? 1 : 256 / P;

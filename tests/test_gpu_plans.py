@@ -68,7 +68,8 @@ def test_every_plan_matches_oracle(gpu, nx, ny, precision):
         s = Solver(nx, ny, lx, ly, depth, device=gpu, mode=mode, max_sweeps=200, accel=accel, precision=precision)
         variants = s.plan_variants()
         assert 0 in variants
-        caps = {0: 256 // (nx // 2 // 8), 1: 256 // (nx // 2 // 8), 2: 256 // (nx // 2 // 16)}
+        elems = {0: 8, 1: 8, 2: 16, 3: 4}   # values per thread of each row variant
+        caps = {v: max(1, 256 // (nx // 2 // e)) for v, e in elems.items()}
         plans = [(v, r, 0) for v in variants for r in _rows_candidates(caps[v], ny)] + [(0, 0, 2048)]
         for v, r, sp in plans:
             s.set_plan(v, r, sp)
@@ -81,7 +82,7 @@ def test_every_plan_matches_oracle(gpu, nx, ny, precision):
             if mode == "iter" and not fp32:
                 assert info[0][0] == oi.sweeps
         # variants that are not built are refused and leave the plan alone
-        for v in range(3):
+        for v in range(4):
             if v not in variants:
                 from paper_2310_19840_amd import SBIError
                 before = s.plan()
@@ -89,13 +90,14 @@ def test_every_plan_matches_oracle(gpu, nx, ny, precision):
                     s.set_plan(v, 0, 0)
                 assert s.plan() == before
     # precision-specific availability: radix 16 only in FP32, cached powers in
-    # the FP64 sweep never (it would spill)
+    # the FP64 sweep never (it would spill); radix 4 in both
     s_it = Solver(nx, ny, lx, ly, depth, device=gpu, mode="iter", accel="anderson", precision=precision)
     s_sa = Solver(nx, ny, lx, ly, depth, device=gpu, mode="sa", precision=precision)
     if fp32:
         assert 1 in s_it.plan_variants() and 2 in s_sa.plan_variants()
     else:
-        assert s_it.plan_variants() == [0] and 2 not in s_sa.plan_variants()
+        assert 1 not in s_it.plan_variants() and 2 not in s_sa.plan_variants()
+    assert 3 in s_it.plan_variants() and 3 in s_sa.plan_variants()
 
 
 def test_autotune_picks_a_built_plan_and_caches_it(gpu, tmp_path):
