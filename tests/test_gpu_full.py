@@ -128,3 +128,48 @@ def test_full_mode_refusals(gpu):
     with pytest.raises(SBIError) as ex:
         Batch([dict(nx=64, ny=1, lx=10.0, ly=1.0, depth=np.ones((1, 64)), mode="full")], device=gpu)
     assert ex.value.code == _lib.SBI_ERR_UNSUPPORTED
+
+
+def test_full_two_members_with_their_own_depths(gpu):
+    """One context of two members, one over a finite flat bed and one in deep
+    water: each member's W equals its own oracle solve."""
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    nx = 512
+    lx, e0, p0 = _sea(nx, 31, 0.12)
+    _, e1, p1 = _sea(nx, 41, 0.08)
+    dep = np.stack([np.full((1, nx), 1.0), np.full((1, nx), 1000.0)])
+    s = Solver(nx, 1, lx, 1.0, dep, batch=2, device=gpu, mode="full", max_sweeps=100)
+    W, st, info = s.vertical_velocity(_t(np.stack([e0, e1]), torch.float64, gpu), _t(np.stack([p0, p1]), torch.float64, gpu),
+                                      tol=1e-12)
+    assert st == 0
+    for k, (e, p) in enumerate(((e0, p0), (e1, p1))):
+        o = OSolver(Grid(nx, 1, lx), dep[k], mode="full", max_sweeps=100)
+        Wo, oi = o.vertical_velocity(e, p, tol=1e-12)
+        err = _rel(W.cpu().numpy()[k], Wo)
+        _say(f"member {k}: W err {err:.2e}, sweeps {info[k][0]}/{oi.sweeps}")
+        assert info[k][0] == oi.sweeps and err < 1e-11
+
+
+def test_full_adaptive_pair_matches_oracle(gpu):
+    """The adaptive fifth/fourth-order pair with the fully nonlinear W: the same
+    accepted and rejected steps as the oracle and the end state within 1e-10."""
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    nx = 128
+    lx, eta, phi = _sea(nx, 53, 0.1)
+    dep = np.full((1, nx), 1.0)
+    T = 2 * math.pi / math.sqrt(math.tanh(1.0))
+    o = OSolver(Grid(nx, 1, lx), dep, mode="full", max_sweeps=100)
+    eo, po, oinfo = o.step_adaptive(eta, phi, 0.0, T, T / 16, 1e-6, tol=1e-12)
+    s = Solver(nx, 1, lx, 1.0, dep, device=gpu, mode="full", max_sweeps=100)
+    e = _t(eta[None], torch.float64, gpu)
+    p = _t(phi[None], torch.float64, gpu)
+    st, info = s.step_adaptive(e, p, T, T / 16, 1e-6, tol=1e-12)
+    _say(f"adaptive full: accepted {info['accepted']}/{oinfo['accepted']}, rejected {info['rejected']}/{oinfo['rejected']}")
+    assert st >= 0
+    assert (info["accepted"], info["rejected"]) == (oinfo["accepted"], oinfo["rejected"])
+    assert _rel(e.cpu().numpy().reshape(eo.shape), eo) < 1e-10
+    assert _rel(p.cpu().numpy().reshape(po.shape), po) < 1e-10
