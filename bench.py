@@ -20,7 +20,10 @@ later stepping solve from the last eight, its inference inside the timed
 region); both graphs enqueue a speculative sweep budget (the largest recent
 sweep count + 3, redone exactly with a larger budget if a solve outruns it),
 with the plain form's sweep cap; the
-plain step in FP32 (tolerance 1e-6, the FP32 floor), the adaptive
+plain step in FP32 (tolerance 1e-6, the FP32 floor), the plain step in mixed
+precision ("plain-mixed": FP32 sweeps on the correction equation between FP64
+residual sweeps, at the headline's tolerance 1e-8, with its end state and
+energy against the FP64 form's), the adaptive
 fifth/fourth-order pair over four peak periods ("adaptive", at the error bound
 3e-7 that makes it at least as accurate as the fixed step; counted in
 fixed-step equivalents of T_p/64), the 1D submerged-bar tank driven by
@@ -214,10 +217,12 @@ def dominant(prof, sweeps_total, solves, g, vd, csz, rsz, aa=False):
                  "avg_launch_us": round(avg_s * 1e6, 2), "launches_working": working, "launches_total": cnt}
 
 
-def run_plain(args, dev, precision, tol, accel=None):
+def run_plain(args, dev, precision, tol, accel=None, keep_state=False):
     """One C5 member, linear-guess seed, eager steps.  The sweep kernels of the
     last timed step are bracketed by HIP events (each bracket idles the device
-    for a few microseconds, so the other steps run without them)."""
+    for a few microseconds, so the other steps run without them).  keep_state:
+    also return the end state and its energy (Eq. (energy), FP64, after the
+    timed region)."""
     import numpy as np
     import torch
 
@@ -225,7 +230,7 @@ def run_plain(args, dev, precision, tol, accel=None):
 
     cfg = c5_members([0], args.n)[0]
     g = cfg["grid"]
-    dtype = torch.float64 if precision == "fp64" else torch.float32
+    dtype = torch.float32 if precision == "fp32" else torch.float64
     s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=dev, mode="iter", precision=precision,
                max_sweeps=args.max_sweeps, accel=accel)
     # launch plan from the autotuner (set-up, before the timed region)
@@ -249,19 +254,37 @@ def run_plain(args, dev, precision, tol, accel=None):
     st = max(st0, st1) if min(st0, st1) >= 0 else min(st0, st1)
     info = dict(info1)
     if info0 is not None:
-        for k in ("solves", "sweeps_total", "fallbacks"):
+        for k in ("solves", "sweeps_total", "fallbacks", "sweeps_fp32_total"):
             info[k] = info0[k] + info1[k]
         info["sweeps_max"] = max(info0["sweeps_max"], info1["sweeps_max"])
         info["max_residual"] = max(info0["max_residual"], info1["max_residual"])
     solves = max(info["solves"], 1)
     vd = bool(np.any(cfg["depth"] != cfg["depth"].max()))
-    csz, rsz = (16, 8) if precision == "fp64" else (8, 4)
-    # the profiled step's own launches decide which of them did work
-    dom, roof = dominant(prof, info1["sweeps_total"], max(info1["solves"], 1), g, vd, csz, rsz, accel == "anderson")
-    return dict(value=g.nx * g.ny * args.steps / el, ms_per_step=1e3 * el / max(args.steps, 1), status=st,
-                sweeps_mean=info["sweeps_total"] / solves, sweeps_max=info["sweeps_max"],
-                max_residual=info["max_residual"], roofline=roof, dominant=dom,
-                kernel_ms={k: round(v[0], 3) for k, v in prof.items() if v[1] > 0}, plan=plan, cfg=cfg)
+    csz, rsz = (8, 4) if precision == "fp32" else (16, 8)
+    if precision == "mixed":
+        # the FP32 correction sweeps: a W solve of K FP64 sweeps runs K - 1
+        # correction solves, each with one working row launch per sweep plus
+        # the one whose column pass decides it
+        sw32 = info1["sweeps_fp32_total"]
+        corr = info1["sweeps_total"] - sw32 - info1["solves"]
+        dom, roof = dominant({"row_sweep": prof.get("row_sweep_fp32", (0.0, 0))}, sw32, max(corr, 1), g, vd, 8, 4,
+                             accel == "anderson")
+        dom = "row_sweep_fp32"
+        roof["kernel"] = dom
+    else:
+        # the profiled step's own launches decide which of them did work
+        dom, roof = dominant(prof, info1["sweeps_total"], max(info1["solves"], 1), g, vd, csz, rsz,
+                             accel == "anderson")
+    out = dict(value=g.nx * g.ny * args.steps / el, ms_per_step=1e3 * el / max(args.steps, 1), status=st,
+               sweeps_mean=info["sweeps_total"] / solves, sweeps_max=info["sweeps_max"],
+               max_residual=info["max_residual"], roofline=roof, dominant=dom,
+               kernel_ms={k: round(v[0], 3) for k, v in prof.items() if v[1] > 0}, plan=plan, cfg=cfg)
+    if precision == "mixed":
+        out["sweeps_fp32_mean"] = info["sweeps_fp32_total"] / solves
+    if keep_state:
+        _, energy = s.diagnostics(eta, phi, tol=tol)
+        out["end"] = (eta.double().cpu().numpy(), float(energy[0]))
+    return out
 
 
 def run_batched(args, dev, seed_mode, members, accel=None):
@@ -511,8 +534,8 @@ def main():
     ap.add_argument("--c2-steps", type=int, default=256)
     ap.add_argument("--full-steps", type=int, default=8)
     ap.add_argument("--forms",
-                    default="plain,plain-relaxed,batched+prev,batched+learned,plain-fp32,adaptive,c2-tank,c4,"
-                            "c3-precision,full-1d")
+                    default="plain,plain-relaxed,batched+prev,batched+learned,plain-fp32,plain-mixed,adaptive,"
+                            "c2-tank,c4,c3-precision,full-1d")
     ap.add_argument("--accel", default="anderson", choices=["anderson", "none"],
                     help="iteration of the W solves: Anderson-mixed (default) or plain relaxed sweeps")
     ap.add_argument("--adaptive-periods", type=float, default=4.0)
@@ -530,6 +553,7 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     dev = torch.device("cuda:0")
@@ -537,7 +561,8 @@ def main():
     accel = None if args.accel == "none" else args.accel
     if args.batch_sweeps is None:
         args.batch_sweeps = args.max_sweeps
-    plain = run_plain(args, dev, "fp64", 1e-8, accel=accel)
+    plain = run_plain(args, dev, "fp64", 1e-8, accel=accel, keep_state="plain-mixed" in forms)
+    plain_end = plain.pop("end", None)
     cfg = plain.pop("cfg")
     g = cfg["grid"]
     tkey = plain["dominant"] + ("_aa" if accel == "anderson" else "")
@@ -558,6 +583,20 @@ def main():
                                                                           "sweeps_max", "max_residual", "status",
                                                                           "roofline", "plan")}
         out_forms["plain-fp32"]["tol"] = 1e-6
+    if "plain-mixed" in forms:
+        mx = run_plain(args, dev, "mixed", 1e-8, accel=accel, keep_state=True)
+        mx.pop("cfg")
+        eta_m, en_m = mx.pop("end")
+        eta_p, en_p = plain_end
+        out_forms["plain-mixed"] = {k: v for k, v in mx.items() if k in ("value", "ms_per_step", "sweeps_mean",
+                                                                          "sweeps_fp32_mean", "sweeps_max",
+                                                                          "max_residual", "status", "roofline",
+                                                                          "kernel_ms")}
+        # against the FP64 form after the same steps (warm-up included)
+        out_forms["plain-mixed"]["vs_fp64"] = {
+            "max_eta_rel_diff": float(f"{float(np.abs(eta_m - eta_p).max() / np.abs(eta_p).max()):.3g}"),
+            "energy_rel_diff": float(f"{abs(en_m - en_p) / abs(en_p):.3g}"),
+            "steps": args.warmup + args.steps}
     if "plain-relaxed" in forms:
         rx = run_plain(args, dev, "fp64", 1e-8, accel=None)
         rx.pop("cfg")

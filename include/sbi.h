@@ -35,7 +35,7 @@
  *   - Returns sbi_status: 0 success, > 0 warning (outputs are written and
  *     usable), < 0 error (no output written; sbi_status_string() explains).
  *   - Field pointers are DEVICE pointers to row-major [batch][ny][nx] arrays
- *     of the context's precision (double for SBI_FP64, float for SBI_FP32),
+ *     of the context's precision (double for SBI_FP64 and SBI_MIXED, float for SBI_FP32),
  *     contiguous, owned by the caller.  The library never frees them.
  *   - Depth arrays are HOST pointers to double [batch][ny][nx], depth > 0.
  *   - All device work is enqueued on the context's HIP stream; calls that
@@ -74,7 +74,7 @@ typedef enum sbi_status {
     SBI_ERR_DIVERGED = -6
 } sbi_status;
 
-enum { SBI_FP64 = 0, SBI_FP32 = 1 };
+enum { SBI_FP64 = 0, SBI_FP32 = 1, SBI_MIXED = 2 };
 enum { SBI_MODE_ITER = 0, SBI_MODE_SA = 1, SBI_MODE_FULL = 2 };
 enum { SBI_SEED_LINEAR = 0, SBI_SEED_PREV = 1, SBI_SEED_NET = 2, SBI_SEED_USER = 3 };
 enum { SBI_ACCEL_NONE = 0, SBI_ACCEL_ANDERSON = 1 };
@@ -89,7 +89,22 @@ typedef struct sbi_grid {
                               modes |m| < alpha n/2 are kept (the "2/(l+1) rule" of
                               Sec. 2.4 read as alpha = 1/2); 0 < alpha < 1; default 0.5 */
     int32_t precision;     /* SBI_FP64 (default) or SBI_FP32 (FP64 residual norms and
-                              diagnostics are kept either way) */
+                              diagnostics are kept either way), or SBI_MIXED (mode
+                              SBI_MODE_ITER only; fields in double): iterative
+                              refinement of the iteration's fixed point x = T(x) =
+                              A x + b.  An FP64 sweep forms the residual
+                              r = T(x) - x and takes the stopping decision of the
+                              FP64 iteration on it (same test, same tolerance);
+                              between two such sweeps FP32 sweeps (relaxed or
+                              Anderson-mixed, as accel says) solve the correction
+                              equation d = A d + r from d = r to a relative
+                              residual between 1e-5 and 0.1, chosen so that the
+                              next FP64 test can pass, and x += d in FP64.
+                              Reaches the FP64 tolerances (1e-8 and tighter)
+                              where SBI_FP32 stops near 1e-6; at most 10 FP64
+                              sweeps per solve (then SBI_WARN_NOT_CONVERGED).
+                              Not for ensembles (sbi_batch_init) or
+                              sbi_vertical_velocity_noalloc (SBI_ERR_UNSUPPORTED) */
     int32_t mode;          /* SBI_MODE_ITER (default), SBI_MODE_SA or SBI_MODE_FULL (1D, flat bed) */
     int32_t seed;          /* SBI_SEED_* for the iteration; default SBI_SEED_LINEAR,
                               the initiation of Sec. 2.4.  SBI_SEED_PREV: the linear
@@ -122,10 +137,12 @@ typedef struct sbi_state {
 } sbi_state;
 
 typedef struct sbi_solve_info {
-    int32_t sweeps;        /* applications of the sweep operator (0 in SA mode) */
+    int32_t sweeps;        /* applications of the sweep operator (0 in SA mode);
+                              SBI_MIXED: FP64 and FP32 sweeps together */
     int32_t status;        /* per-member sbi_status of the solve */
     double residual;       /* max|T(W)-W| / max|T(W)| of the last sweep, FP64 */
     double omega;          /* relaxation weight used */
+    int32_t sweeps_fp32;   /* SBI_MIXED: the FP32 sweeps among sweeps; else 0 */
 } sbi_solve_info;
 
 typedef struct sbi_step_info {
@@ -134,6 +151,7 @@ typedef struct sbi_step_info {
     int32_t sweeps_max;    /* largest sweep count of one solve */
     int32_t fallbacks;     /* solves that fell back to the linear guess */
     double max_residual;   /* largest final residual of any solve */
+    int64_t sweeps_fp32_total; /* SBI_MIXED: the FP32 sweeps among sweeps_total; else 0 */
 } sbi_step_info;
 
 typedef struct sbi_adapt_info {
@@ -200,6 +218,7 @@ sbi_status sbi_vertical_velocity(sbi_ctx* ctx, const void* eta, const void* phi_
  *   hip_stream must belong to the current device (SBI_ERR_INVALID_ARG
  *   otherwise); the call synchronises it before returning.
  *   seed: SBI_SEED_NET is SBI_ERR_UNSUPPORTED (its weights need a lasting
+ *   context), and so is precision SBI_MIXED (its FP32 sweeps run in a second
  *   context); SBI_SEED_PREV starts from the linear guess (there is no previous
  *   solve); SBI_SEED_USER takes w_seed.  Returns what sbi_init and
  *   sbi_vertical_velocity would (SBI_WARN_DEPTH_CRITERION included).
@@ -319,7 +338,9 @@ const char* sbi_status_string(sbi_status s);
  * SBI_PROFILE_OFF.  Synchronises the stream and clears the totals.
  * sbi_profile_read writes, per kernel class, its name (static string), summed
  * device time in ms and launch count since the last enable, and returns the
- * number of classes.
+ * number of classes.  In SBI_MIXED contexts the FP32 correction sweeps count
+ * as "row_sweep_fp32" and "col_sweep_fp32", the FP64 refinement sweeps as
+ * "row_sweep" and "col_sweep".
  */
 enum { SBI_PROFILE_OFF = 0, SBI_PROFILE_ALL = 1, SBI_PROFILE_SWEEPS = 2 };
 sbi_status sbi_profile_enable(sbi_ctx* ctx, int32_t enable);

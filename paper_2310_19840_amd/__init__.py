@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import SBIError  # noqa: F401
 
-_PREC = {"fp64": _lib.SBI_FP64, "fp32": _lib.SBI_FP32}
+_PREC = {"fp64": _lib.SBI_FP64, "fp32": _lib.SBI_FP32, "mixed": _lib.SBI_MIXED}
 _MODE = {"iter": _lib.SBI_MODE_ITER, "sa": _lib.SBI_MODE_SA, "full": _lib.SBI_MODE_FULL}
 _SEED = {"linear": _lib.SBI_SEED_LINEAR, "prev": _lib.SBI_SEED_PREV, "net": _lib.SBI_SEED_NET,
          "user": _lib.SBI_SEED_USER}
@@ -67,13 +67,13 @@ def vertical_velocity_noalloc(eta, phi_s, depth, nx, ny, lx, ly=1.0, h_ref=-1.0,
     library: its workspace is the library's static device scratch).  eta, phi_s
     (and w_seed, out): contiguous [batch, ny, nx] tensors on the current device
     of the grid's precision.  Returns (W, status, [(sweeps, status, residual,
-    omega)] per member)."""
+    omega, FP32 sweeps)] per member)."""
     import torch
 
     lib = _lib.load()
     g = make_grid(nx, ny, lx, ly, **opts)
     batch = eta.shape[0] if eta.dim() == 3 else 1
-    dt = torch.float64 if g.precision == _lib.SBI_FP64 else torch.float32
+    dt = torch.float32 if g.precision == _lib.SBI_FP32 else torch.float64
     for x, name in ((eta, "eta"), (phi_s, "phi_s"), (w_seed, "w_seed"), (out, "w_out")):
         if x is not None and (x.dtype != dt or not x.is_contiguous() or x.numel() != batch * ny * nx):
             raise TypeError(f"{name} must be a contiguous {dt} tensor of {batch * ny * nx} values")
@@ -86,7 +86,7 @@ def vertical_velocity_noalloc(eta, phi_s, depth, nx, ny, lx, ly=1.0, h_ref=-1.0,
                                            float(h_ref), C.c_void_p(eta.data_ptr()), C.c_void_p(phi_s.data_ptr()),
                                            float(tol), C.c_void_p(w_seed.data_ptr()) if w_seed is not None else None,
                                            C.c_void_p(out.data_ptr()), infos, C.c_void_p(stream.cuda_stream))
-    res = [(i.sweeps, i.status, i.residual, i.omega) for i in infos]
+    res = [(i.sweeps, i.status, i.residual, i.omega, i.sweeps_fp32) for i in infos]
     if st < 0:
         raise SBIError(st, "sbi_vertical_velocity_noalloc", res)
     return out, st, res
@@ -129,7 +129,7 @@ class Solver:
         self.grid = make_grid(nx, ny, lx, ly, **opts)
         self.batch = int(batch)
         self.nx, self.ny = int(nx), int(ny)
-        self.dtype = torch.float64 if self.grid.precision == _lib.SBI_FP64 else torch.float32
+        self.dtype = torch.float32 if self.grid.precision == _lib.SBI_FP32 else torch.float64
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         nbytes = workspace_bytes(self.grid, self.batch)
         if nbytes == 0:
@@ -174,7 +174,7 @@ class Solver:
         seed = self._dev(w_seed, "w_seed") if w_seed is not None else None
         st = self.lib.sbi_vertical_velocity(self.ctx, self._dev(eta, "eta"), self._dev(phi_s, "phi_s"), hp,
                                             float(tol), seed, self._dev(out, "w_out"), infos)
-        res = [(i.sweeps, i.status, i.residual, i.omega) for i in infos]
+        res = [(i.sweeps, i.status, i.residual, i.omega, i.sweeps_fp32) for i in infos]
         if st < 0:
             raise SBIError(st, "sbi_vertical_velocity", res)
         return out, st, res
@@ -186,7 +186,8 @@ class Solver:
         if st < 0:
             raise SBIError(st, "sbi_step")
         return st, dict(t=s.t, solves=info.solves, sweeps_total=info.sweeps_total, sweeps_max=info.sweeps_max,
-                        fallbacks=info.fallbacks, max_residual=info.max_residual)
+                        fallbacks=info.fallbacks, max_residual=info.max_residual,
+                        sweeps_fp32_total=info.sweeps_fp32_total)
 
     def step_adaptive(self, eta, phi_s, t_end, dt, rk_tol, tol=1e-10, t=0.0, max_steps=1000):
         s = _lib.sbi_state(self._dev(eta, "eta"), self._dev(phi_s, "phi_s"), float(t))
@@ -198,7 +199,8 @@ class Solver:
         v = info.solve
         return st, dict(t=s.t, accepted=info.accepted, rejected=info.rejected, dt_next=info.dt_next,
                         err_last=info.err_last, err_max=info.err_max, solves=v.solves, sweeps_total=v.sweeps_total,
-                        sweeps_max=v.sweeps_max, fallbacks=v.fallbacks, max_residual=v.max_residual)
+                        sweeps_max=v.sweeps_max, fallbacks=v.fallbacks, max_residual=v.max_residual,
+                        sweeps_fp32_total=v.sweeps_fp32_total)
 
     def diagnostics(self, eta, phi_s, tol=1e-10):
         s = _lib.sbi_state(self._dev(eta, "eta"), self._dev(phi_s, "phi_s"), 0.0)
@@ -482,7 +484,7 @@ class Batch:
             opts = {k: v for k, v in mb.items() if k not in ("nx", "ny", "lx", "ly", "depth")}
             grids[i] = make_grid(mb["nx"], mb["ny"], mb["lx"], mb.get("ly", 1.0), **opts)
             self.shapes.append((int(mb["ny"]), int(mb["nx"])))
-            self.dtypes.append(torch.float64 if grids[i].precision == _lib.SBI_FP64 else torch.float32)
+            self.dtypes.append(torch.float32 if grids[i].precision == _lib.SBI_FP32 else torch.float64)
             d = np.ascontiguousarray(np.asarray(mb["depth"], dtype=np.float64).reshape(self.shapes[-1]))
             deps.append(d)
         self._deps = deps

@@ -21,7 +21,7 @@ SBI_ERR_DIVERGED = -6
 
 SBI_PROFILE_OFF, SBI_PROFILE_ALL, SBI_PROFILE_SWEEPS = 0, 1, 2
 
-SBI_FP64, SBI_FP32 = 0, 1
+SBI_FP64, SBI_FP32, SBI_MIXED = 0, 1, 2
 SBI_MODE_ITER, SBI_MODE_SA, SBI_MODE_FULL = 0, 1, 2
 SBI_SEED_LINEAR, SBI_SEED_PREV, SBI_SEED_NET, SBI_SEED_USER = 0, 1, 2, 3
 SBI_ACCEL_NONE, SBI_ACCEL_ANDERSON = 0, 1
@@ -45,12 +45,13 @@ class sbi_state(C.Structure):
 
 
 class sbi_solve_info(C.Structure):
-    _fields_ = [("sweeps", C.c_int32), ("status", C.c_int32), ("residual", C.c_double), ("omega", C.c_double)]
+    _fields_ = [("sweeps", C.c_int32), ("status", C.c_int32), ("residual", C.c_double), ("omega", C.c_double),
+                ("sweeps_fp32", C.c_int32)]
 
 
 class sbi_step_info(C.Structure):
     _fields_ = [("solves", C.c_int64), ("sweeps_total", C.c_int64), ("sweeps_max", C.c_int32),
-                ("fallbacks", C.c_int32), ("max_residual", C.c_double)]
+                ("fallbacks", C.c_int32), ("max_residual", C.c_double), ("sweeps_fp32_total", C.c_int64)]
 
 
 class sbi_adapt_info(C.Structure):

@@ -85,12 +85,12 @@ struct Stats {
 enum {
     K_ROW_FWD, K_ROW_INV, K_ROW_SETUP, K_ROW_SWEEP, K_ROW_SA, K_ROW_NPHI, K_ROW_BLEND,
     K_COL_STATE, K_COL_FORCING, K_COL_SWEEP, K_COL_SA, K_COL_OTHER, K_RK, K_DIAG, K_NET, K_FULL_PAIRS,
-    K_FULL_APPLY, K_COUNT
+    K_FULL_APPLY, K_ROW_SWEEP32, K_COL_SWEEP32, K_COUNT
 };
 const char* const kKernelNames[K_COUNT] = {
     "row_fwd", "row_inv", "row_setup", "row_sweep", "row_sa", "row_nphi", "row_blend",
     "col_state", "col_forcing", "col_sweep", "col_sa", "col_other", "rk", "diag", "net", "full_pairs",
-    "full_apply"};
+    "full_apply", "row_sweep_fp32", "col_sweep_fp32"};
 
 struct Profiler {
     bool on = false;
@@ -153,6 +153,9 @@ struct sbi_ctx {
     void* full_lfl = nullptr;
     void* full_w = nullptr;
     void* full_part = nullptr;
+    // mixed precision (SBI_MIXED): the FP32 context that solves the correction
+    // equations, in the tail of this context's workspace, on the same stream
+    sbi_ctx* inner = nullptr;
     int hist_K = 0, hist_nb = 0;
     double hist_dk = 0.0;
     bool hist_loaded = false;
@@ -216,8 +219,17 @@ struct Layout {
     int Mx, My, Kx, Kxp, Ky, C, qb, ldh;
     size_t rsz, csz;
     long long s_phys, s_half, s_cmp;
-    size_t bytes_comp, bytes_half, bytes_phys, bytes_tw, bytes_misc, bytes_net, bytes_full, total;
+    size_t bytes_comp, bytes_half, bytes_phys, bytes_tw, bytes_misc, bytes_net, bytes_full, bytes_inner, total;
 };
+
+// the FP32 context of a mixed-precision context: same grid and options, FP32
+// fields; seeds come from the FP64 side
+static sbi_grid inner_grid(const sbi_grid* g) {
+    sbi_grid gi = *g;
+    gi.precision = SBI_FP32;
+    gi.seed = SBI_SEED_LINEAR;
+    return gi;
+}
 
 constexpr int kFullSplitMax = 16;  // source-point slices of a pair pass of the fully nonlinear solve
 
@@ -228,7 +240,8 @@ static bool grid_valid(const sbi_grid* g) {
     if (!(g->lx > 0) || (g->ny > 1 && !(g->ly > 0))) return false;
     if (g->order < 1 || g->order > 7) return false;
     if (!(g->dealias > 0.0 && g->dealias < 1.0)) return false;
-    if (g->precision != SBI_FP64 && g->precision != SBI_FP32) return false;
+    if (g->precision != SBI_FP64 && g->precision != SBI_FP32 && g->precision != SBI_MIXED) return false;
+    if (g->precision == SBI_MIXED && g->mode != SBI_MODE_ITER) return false;  // refines an iteration
     if (g->mode != SBI_MODE_ITER && g->mode != SBI_MODE_SA && g->mode != SBI_MODE_FULL) return false;
     if (g->mode == SBI_MODE_FULL && g->ny != 1) return false;  // the exact surface equation: one dimension
     if (g->max_sweeps < 1 || g->max_sweeps > 1000) return false;
@@ -248,7 +261,7 @@ static int half_pad_bytes() {
 
 static Layout layout(const sbi_grid* g, int batch) {
     Layout L{};
-    const bool f64 = g->precision == SBI_FP64;
+    const bool f64 = g->precision != SBI_FP32;
     L.rsz = f64 ? 8 : 4;
     L.csz = 2 * L.rsz;
     // kept modes |m| < alpha n / 2 (strict)
@@ -284,7 +297,13 @@ static Layout layout(const sbi_grid* g, int batch) {
     L.bytes_full = g->mode == SBI_MODE_FULL
                        ? 7 * al((size_t)g->nx * 8 * batch) + al((size_t)kFullSplitMax * g->nx * 8 * batch)
                        : 0;
-    L.total = L.bytes_comp + L.bytes_half + L.bytes_phys + L.bytes_tw + L.bytes_misc + L.bytes_net + L.bytes_full;
+    // mixed precision: the FP32 context's workspace at the end
+    if (g->precision == SBI_MIXED) {
+        const sbi_grid gi = inner_grid(g);
+        L.bytes_inner = layout(&gi, batch).total;
+    }
+    L.total = L.bytes_comp + L.bytes_half + L.bytes_phys + L.bytes_tw + L.bytes_misc + L.bytes_net + L.bytes_full +
+              L.bytes_inner;
     return L;
 }
 
@@ -388,11 +407,19 @@ static sbi_status set_depth(sbi_ctx* c, const double* depth, double h_ref) {
     SBI_HIP(hipMemcpyAsync(c->href_dev, c->href.data(), sizeof(double) * c->batch, hipMemcpyHostToDevice, c->stream));
     if (g.mode == SBI_MODE_FULL) SBI_TRY(full_tables(c));
     SBI_HIP(hipStreamSynchronize(c->stream));
+    if (c->inner) SBI_TRY(set_depth(c->inner, depth, h_ref));
     return SBI_OK;
 }
 
 // release what a context holds (not the context itself)
 static void ctx_release(sbi_ctx* c) {
+    if (c->inner) {
+        prof_flush(c->inner);
+        for (hipEvent_t e : c->inner->prof.pool) (void)hipEventDestroy(e);
+        ctx_release(c->inner);
+        delete c->inner;
+        c->inner = nullptr;
+    }
     if (c->transient) return;  // nothing was allocated
     if (c->head) (void)hipHostFree(c->head);
     if (c->poll) (void)hipEventDestroy(c->poll);
@@ -407,10 +434,11 @@ static sbi_status ctx_setup(sbi_ctx* c, const sbi_grid* g, int32_t batch, const 
     const Layout L = layout(g, batch);
     if (workspace && ws_bytes < L.total) return SBI_ERR_WORKSPACE;
     if (transient && !workspace) return SBI_ERR_WORKSPACE;
+    if (transient && g->precision == SBI_MIXED) return SBI_ERR_UNSUPPORTED;
     c->transient = transient;
     c->grid = *g;
     c->batch = batch;
-    c->fp64 = g->precision == SBI_FP64;
+    c->fp64 = g->precision != SBI_FP32;
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->rsz = L.rsz;
     c->csz = L.csz;
@@ -542,6 +570,13 @@ static sbi_status ctx_setup(sbi_ctx* c, const sbi_grid* g, int32_t batch, const 
         }
         if (st == SBI_OK) st = hip_ok(launch_ctl_reset(c->ctl, batch, kMaxSweepSlots, c->stream));
         if (st == SBI_OK) st = set_depth(c, depth, h_ref);
+    }
+    if (st >= 0 && g->precision == SBI_MIXED) {
+        const sbi_grid gi = inner_grid(g);
+        c->inner = new sbi_ctx();
+        const sbi_status si = ctx_setup(c->inner, &gi, batch, depth, h_ref, c->ws + (L.total - L.bytes_inner),
+                                        L.bytes_inner, hip_stream, false);
+        if (si < 0) st = si;
     }
     if (st < 0) return st;
     return c->depth_warn ? SBI_WARN_DEPTH_CRITERION : SBI_OK;
@@ -962,41 +997,50 @@ static sbi_status anderson_mix(sbi_ctx* c, int n) {
     return run_col(c, b, K_COL_OTHER);
 }
 
-static sbi_status launch_sweep(sbi_ctx* c, const void* eta_phys, int n, double tol) {
+// row pass of a sweep: the residual norms of the previous sweep into slot
+// `slot` (residual), and the products of the iterate (products); gT selects
+// the residual whose denominator is given as a half form
+static RowSweepParams sweep_row_params(sbi_ctx* c, const void* eta_phys, bool residual, bool products, int slot,
+                                       bool gT) {
     const bool two_d = c->grid.ny > 1;
     const int J = c->grid.order - 1;
-    const int M = c->grid.max_sweeps;
-    const bool aa = c->grid.accel == SBI_ACCEL_ANDERSON;
     RowSweepParams rp{};
     rp.g = c->gd;
     rp.gV = HALF(H_GV);
     rp.gD = HALF(H_GD);
-    rp.gT = aa ? HALF(H_GT) : nullptr;
+    rp.gT = gT ? HALF(H_GT) : nullptr;
     rp.gbx = HALF(H_GBX);
     rp.gby = HALF(H_GBY);
     rp.eta = eta_phys;
     rp.delta = PHYS(P_DELTA);
     rp.J = J;
-    rp.residual = n >= 1;
-    rp.products = n < M && J >= 1;
+    rp.residual = residual;
+    rp.products = products && J >= 1;
     rp.vd = c->vd;
-    rp.slot = n >= 1 ? n - 1 : 0;
+    rp.slot = slot;
     rp.nfam = rp.products ? 1 + (c->vd ? (two_d ? 2 : 1) : 0) : 1;
-    int np = 0;
     if (rp.products) {
-        np = J * (1 + (c->vd ? (two_d ? 2 : 1) : 0));
+        const int np = J * (1 + (c->vd ? (two_d ? 2 : 1) : 0));
         for (int i = 0; i < np; ++i) rp.h[i] = HALF(H_PROD0 + i);
     }
     rp.ctl = c->ctl;
-    c->st.launches += 1;
-    {
-        ProfScope ps_(c, K_ROW_SWEEP);
-        SBI_TRY(hip_ok(launch_row_sweep(c->fp64, rp, c->batch, tw_of(c), c->stream)));
-    }
+    return rp;
+}
 
-    ColBuilder b(c->gd);
+static sbi_status run_row_sweep(sbi_ctx* c, const RowSweepParams& rp) {
+    c->st.launches += 1;
+    ProfScope ps_(c, K_ROW_SWEEP);
+    return hip_ok(launch_row_sweep(c->fp64, rp, c->batch, tw_of(c), c->stream));
+}
+
+// terms of T(x) = b + A x in a column pass: the forcing (C_BV, C_BB) and, with
+// products, the summed operator applied to the iterate's products; *cvn and
+// *cbn are the inputs that hold the iterate x itself (C_VN, C_BN)
+static void sweep_col_terms(sbi_ctx* c, ColBuilder& b, bool products, int* cvn, int* cbn) {
+    const bool two_d = c->grid.ny > 1;
+    const int J = c->grid.order - 1;
     std::vector<int> se(J + 1), sbx(J + 1), sby(J + 1);
-    if (rp.products) {
+    if (products) {
         int idx = 0;
         for (int j = 1; j <= J; ++j) se[j] = b.prod(HALF(H_PROD0 + idx++));
         if (c->vd) {
@@ -1006,15 +1050,16 @@ static sbi_status launch_sweep(sbi_ctx* c, const void* eta_phys, int n, double t
         }
     }
     int cbv = b.cin(CMP(C_BV));
-    int cvn = b.cin(CMP(C_VN));
-    int cbb = -1, cbn = -1;
+    *cvn = b.cin(CMP(C_VN));
+    int cbb = -1;
+    *cbn = -1;
     if (c->vd) {
         cbb = b.cin(CMP(C_BB));
-        cbn = b.cin(CMP(C_BN));
+        *cbn = b.cin(CMP(C_BN));
     }
     b.term(cbv, 0, 1.0, FN_ONE, 0, DV_NONE);
     if (c->vd) b.term(cbb, 1, 1.0, FN_ONE, 0, DV_NONE);
-    if (rp.products) {
+    if (products) {
         for (int j = 1; j <= J; ++j) {
             const double f = 1.0 / fact(j);
             // V equation: -T_j k^j/j! F{eta^j V} + <j> S k^(j-1)/j! ik.F{delta^j grad phi_b}
@@ -1032,6 +1077,18 @@ static sbi_status launch_sweep(sbi_ctx* c, const void* eta_phys, int n, double t
             }
         }
     }
+}
+
+static sbi_status launch_sweep(sbi_ctx* c, const void* eta_phys, int n, double tol) {
+    const bool two_d = c->grid.ny > 1;
+    const int M = c->grid.max_sweeps;
+    const bool aa = c->grid.accel == SBI_ACCEL_ANDERSON;
+    const RowSweepParams rp = sweep_row_params(c, eta_phys, n >= 1, n < M, n >= 1 ? n - 1 : 0, aa);
+    SBI_TRY(run_row_sweep(c, rp));
+
+    ColBuilder b(c->gd);
+    int cvn, cbn;
+    sweep_col_terms(c, b, rp.products, &cvn, &cbn);
     if (aa) {
         // T_V(x_n); the residual f_n and the relaxed sweep g_n into the history
         // ring; the half forms of the residual test (f_n and T_V(x_n)).  The
@@ -1142,6 +1199,121 @@ static sbi_status iterate_fixed(sbi_ctx* c, const void* eta_phys, double tol) {
     const int M = c->grid.max_sweeps;
     const int B = (c->budget > 0 && c->budget < M) ? c->budget : M;
     for (int n = 0; n <= B; ++n) SBI_TRY(launch_sweep(c, eta_phys, n, tol));
+    return SBI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// mixed precision (SBI_MIXED): iterative refinement of the fixed point
+// x = T(x) = A x + b of the iteration (x = (V, phi_b), T affine).  FP64 sweeps
+// form r_k = T(x_k) - x_k and take the iteration's stopping decision on it;
+// between them the FP32 context solves d = A d + r_k -- the same sweeps with
+// the forcing b replaced by r_k, from d = r_k -- and x_(k+1) = x_k + d in
+// FP64.  The new residual r_(k+1) = T(x_k + d) - x_k - d = A d + r_k - d is
+// the correction solve's own residual, so a correction solved to relative
+// residual tau leaves |r_(k+1)| ~ tau |d|: each FP64 sweep gains what the FP32
+// sweeps reached, and the FP64 test ends the solve at the FP64 tolerance.
+// ---------------------------------------------------------------------------
+constexpr int kMixedRefine = 10;        // FP64 sweeps per solve at most
+constexpr double kMixedTauMin = 1e-5;   // correction tolerances: above the FP32 floor (~1e-6)
+constexpr double kMixedTauMax = 0.1;
+constexpr double kMixedHalfAdd = 1e4;   // residuals up to this * tol update the half forms by addition
+
+// half forms of the iterate (C_VN, C_BN) for the next row pass
+static sbi_status iterate_half_forms(sbi_ctx* c) {
+    const bool two_d = c->grid.ny > 1;
+    ColBuilder b(c->gd);
+    b.term(b.cin(CMP(C_VN)), 0, 1.0, FN_ONE, 0, DV_NONE);
+    b.inv(SRC_ACC0, DV_NONE, HALF(H_GV));
+    if (c->vd) {
+        b.term(b.cin(CMP(C_BN)), 1, 1.0, FN_ONE, 0, DV_NONE);
+        b.inv(SRC_ACC1, DV_X, HALF(H_GBX));
+        if (two_d) b.inv(SRC_ACC1, DV_Y, HALF(H_GBY));
+    }
+    return run_col(c, b, K_COL_OTHER);
+}
+
+// FP64 sweep k of the refinement from the iterate x_k (C_VN, C_BN and their
+// half forms): T_V(x_k) into C_VP, r_k into C_AFV0 / C_AFB0 (the Anderson ring
+// is free: the FP64 side does not mix), the half forms of the residual test,
+// and the row pass that reduces the test's norms into slot k
+static sbi_status refine_sweep(sbi_ctx* c, const void* eta_phys, int k) {
+    SBI_TRY(run_row_sweep(c, sweep_row_params(c, eta_phys, false, true, 0, false)));
+    ColBuilder b(c->gd);
+    int cvn, cbn;
+    sweep_col_terms(c, b, c->grid.order > 1, &cvn, &cbn);
+    b.p.relax_prev[0] = -cvn - 1;
+    if (c->vd) b.p.relax_prev[1] = -cbn - 1;
+    b.cout(SRC_ACC0, CMP(C_VP));
+    b.cout(SRC_DIFF0, CMP(C_AFV0));
+    if (c->vd) b.cout(SRC_DIFF1, CMP(C_AFB0));
+    b.inv(SRC_DIFF0, DV_NONE, HALF(H_GD));
+    b.inv(SRC_ACC0, DV_NONE, HALF(H_GT));
+    b.p.ctl = c->ctl;
+    b.p.ctl_mode = CTL_SKIP;  // decided members keep their result
+    if (b.p.nacc < (c->vd ? 2 : 1)) b.p.nacc = c->vd ? 2 : 1;
+    SBI_TRY(run_col(c, b, K_COL_SWEEP));
+    return run_row_sweep(c, sweep_row_params(c, eta_phys, true, false, k, true));
+}
+
+static sbi_status iterate_mixed(sbi_ctx* c, const void* eta_phys, double tol) {
+    sbi_ctx* in = c->inner;
+    const bool two_d = c->grid.ny > 1;
+    const int R = std::min(c->grid.max_sweeps, kMixedRefine);
+    const long long nk = (long long)c->gd.Kx * c->gd.Ky;  // kept modes per member
+    // the half forms the FP64 row pass reads, and their FP32 counterparts
+    void* hout[3] = {HALF(H_GV), HALF(H_GBX), HALF(H_GBY)};
+    const void* hin[3] = {in->half[H_GV], in->half[H_GBX], in->half[H_GBY]};
+    const int nf = c->vd ? (two_d ? 3 : 2) : 1;
+    // the FP32 sweeps' eta (fixed over the solve)
+    c->st.launches += 1;
+    SBI_TRY(hip_ok(launch_to_float(eta_phys, in->phys[P_ETA], c->gd.s_phys * c->batch, c->stream)));
+    for (int k = 0;; ++k) {
+        SBI_TRY(refine_sweep(c, eta_phys, k));
+        c->st.launches += 1;
+        SBI_TRY(hip_ok(launch_ctl_decide(c->ctl, c->batch, k + 1, R, tol, c->stream)));
+        SBI_HIP(hipMemcpyAsync(c->head, c->ctl, sizeof(Ctl) * c->batch, hipMemcpyDeviceToHost, c->stream));
+        if (c->poll) SBI_HIP(hipEventRecord(c->poll, c->stream));
+        // while the host waits for the decision, the next correction solve is
+        // set up (members the decision ended are skipped)
+        SBI_TRY(hip_ok(launch_ctl_reset(in->ctl, in->batch, in->grid.max_sweeps + 2, c->stream)));
+        SBI_TRY(hip_ok(launch_mixed_down(c->ctl, in->ctl, c->batch, CMP(C_AFV0), CMP(C_AFB0), in->comp[C_BV],
+                                         in->comp[C_VN], in->comp[C_BB], in->comp[C_BN], nk, c->gd.s_cmp,
+                                         in->gd.s_cmp, c->vd, c->stream)));
+        SBI_TRY(iterate_half_forms(in));
+        SBI_HIP(c->poll ? hipEventSynchronize(c->poll) : hipStreamSynchronize(c->stream));
+        c->st.syncs += 1;
+        if (c->prof.on) prof_flush(c);
+        double rho = 0.0;
+        bool all_done = true;
+        for (int b = 0; b < c->batch; ++b) {
+            if (c->head[b].done) continue;
+            all_done = false;
+            rho = std::max(rho, c->head[b].residual);
+        }
+        if (all_done) break;
+        // a correction solved to tau leaves a residual ~ tau rho: aim below
+        // tol, within what the FP32 sweeps reach
+        const double tau = std::min(kMixedTauMax, std::max(kMixedTauMin, 0.3 * tol / rho));
+        SBI_TRY(iterate(in, in->phys[P_ETA], tau));
+        SBI_TRY(hip_ok(launch_mixed_up(c->ctl, in->ctl, c->batch, CMP(C_VN), CMP(C_BN), in->comp[C_VN],
+                                       in->comp[C_BN], nk, c->gd.s_cmp, in->gd.s_cmp, c->vd, k + 1, c->stream)));
+        // the half forms of x + d: the FP32 half forms of d carry FP32 rounding
+        // of the column transforms, ~1e-7 |d| ~ 1e-7 rho |V|, which the
+        // iteration never removes -- taken only when that is far below tol
+        // (late corrections); early ones transform x + d again in FP64
+        if (rho > kMixedHalfAdd * tol) {
+            SBI_TRY(iterate_half_forms(c));
+        } else {
+            c->st.launches += 1;
+            SBI_TRY(hip_ok(launch_mixed_up_half(in->ctl, c->batch, hout, hin, nf, c->gd.Kx, c->grid.ny, c->gd.ldh,
+                                                in->gd.ldh, c->gd.s_half, in->gd.s_half, c->stream)));
+        }
+        c->st.launches += 3 + in->st.launches;
+        c->st.syncs += in->st.syncs;
+        in->st = Stats();
+    }
+    c->st.launches += 2 + in->st.launches;  // the set-up enqueued behind the last decision
+    in->st = Stats();
     return SBI_OK;
 }
 
@@ -1536,6 +1708,8 @@ static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool
         if (w_seed) SBI_TRY(seed_from_physical(c, w_seed));
         if (capture_safe) {
             SBI_TRY(iterate_fixed(c, eta_phys, tol));
+        } else if (c->inner) {
+            SBI_TRY(iterate_mixed(c, eta_phys, tol));
         } else {
             SBI_TRY(iterate(c, eta_phys, tol));
         }
@@ -1549,7 +1723,7 @@ static sbi_status solve_stage(sbi_ctx* c, const void* eta_user, double tol, bool
                 SBI_TRY(stage_state_pass(c, false, false, false));
                 SBI_TRY(row_setup(c, eta_user));
                 SBI_TRY(col_forcing(c));
-                SBI_TRY(iterate(c, eta_phys, tol));
+                SBI_TRY(c->inner ? iterate_mixed(c, eta_phys, tol) : iterate(c, eta_phys, tol));
             }
         }
         *vh_buf = C_VP;
@@ -1571,6 +1745,7 @@ static sbi_status solve_status(sbi_ctx* c, sbi_solve_info* info, bool fresh) {
             info[b].status = s;
             info[b].residual = h.residual;
             info[b].omega = h.omega;
+            info[b].sweeps_fp32 = c->grid.mode == SBI_MODE_SA ? 0 : h.sweeps_inner;
         }
         c->st.sweeps += c->grid.mode == SBI_MODE_SA ? 0 : h.sweeps;
         if (s < 0) worst = (worst < 0) ? worst : (sbi_status)s;
@@ -1628,6 +1803,7 @@ extern "C" sbi_status sbi_vertical_velocity_noalloc(const sbi_grid* g, int32_t b
                                                     void* hip_stream) {
     if (!grid_valid(g) || batch < 1 || !depth || !eta || !phi_s || !w_out) return SBI_ERR_INVALID_ARG;
     if (g->seed == SBI_SEED_NET) return SBI_ERR_UNSUPPORTED;  // needs loaded weights: a lasting context
+    if (g->precision == SBI_MIXED) return SBI_ERR_UNSUPPORTED;  // a second context for the FP32 sweeps
     const size_t need = layout(g, batch).total;
     if (need > kScratchBytes) return SBI_ERR_WORKSPACE;
     // the stream must belong to the current device, whose scratch is used
@@ -1835,6 +2011,7 @@ static void acc_info(sbi_ctx* c, sbi_step_info* si) {
         const int sw = c->grid.mode == SBI_MODE_SA ? 0 : h.sweeps;
         si->sweeps_total += sw;
         si->sweeps_max = std::max(si->sweeps_max, sw);
+        si->sweeps_fp32_total += c->grid.mode == SBI_MODE_SA ? 0 : h.sweeps_inner;
         si->max_residual = std::max(si->max_residual, c->grid.mode == SBI_MODE_SA ? 0.0 : h.residual);
     }
 }
@@ -2068,6 +2245,7 @@ extern "C" sbi_status sbi_profile_enable(sbi_ctx* c, int32_t enable) {
         c->prof.total_ms[k] = 0.0;
         c->prof.count[k] = 0;
     }
+    if (c->inner) return sbi_profile_enable(c->inner, enable);
     return SBI_OK;
 }
 
@@ -2075,11 +2253,28 @@ extern "C" int32_t sbi_profile_read(sbi_ctx* c, const char** names, double* tota
     if (!c) return 0;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return 0;
     prof_flush(c);
+    double tot[K_COUNT];
+    long long cnt[K_COUNT];
+    for (int i = 0; i < K_COUNT; ++i) {
+        tot[i] = c->prof.total_ms[i];
+        cnt[i] = c->prof.count[i];
+    }
+    if (c->inner) {
+        // the FP32 correction sweeps under their own names, the rest of the
+        // FP32 context's kernels with their classes
+        sbi_ctx* in = c->inner;
+        prof_flush(in);
+        for (int i = 0; i < K_COUNT; ++i) {
+            const int j = i == K_ROW_SWEEP ? K_ROW_SWEEP32 : (i == K_COL_SWEEP ? K_COL_SWEEP32 : i);
+            tot[j] += in->prof.total_ms[i];
+            cnt[j] += in->prof.count[i];
+        }
+    }
     const int k = std::min<int>(n, K_COUNT);
     for (int i = 0; i < k; ++i) {
         if (names) names[i] = kKernelNames[i];
-        if (total_ms) total_ms[i] = c->prof.total_ms[i];
-        if (launches) launches[i] = c->prof.count[i];
+        if (total_ms) total_ms[i] = tot[i];
+        if (launches) launches[i] = cnt[i];
     }
     return k;
 }
@@ -2477,6 +2672,8 @@ static sbi_status autotune(sbi_ctx* c, int32_t flags, sbi_plan* out) {
         if (out) *out = sbi_plan{c->gd.row_var, c->gd.row_rpw, c->group_target, 0.f, 0};
         return SBI_OK;
     }
+    // mixed precision: the FP32 correction sweeps have plans of their own
+    if (c->inner) SBI_TRY(autotune(c->inner, flags, nullptr));
     std::string key;
     SBI_TRY(tune_key(c, &key));
     if (!(flags & SBI_TUNE_FORCE)) {
@@ -2697,7 +2894,8 @@ extern "C" sbi_status sbi_batch_init(sbi_batch** out, int32_t m, const sbi_grid*
     for (int i = 0; i < m; ++i)
         if (!grid_valid(&grids[i]) || !depths[i]) return SBI_ERR_INVALID_ARG;
     for (int i = 0; i < m; ++i)
-        if (grids[i].mode == SBI_MODE_FULL) return SBI_ERR_UNSUPPORTED;  // its solve polls the host
+        // the fully nonlinear solve and the mixed-precision refinement poll the host
+        if (grids[i].mode == SBI_MODE_FULL || grids[i].precision == SBI_MIXED) return SBI_ERR_UNSUPPORTED;
     const size_t need = sbi_batch_workspace_bytes(m, grids);
     if (ws_bytes < need) return SBI_ERR_WORKSPACE;
     auto* b = new sbi_batch();

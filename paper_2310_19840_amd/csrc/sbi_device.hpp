@@ -83,6 +83,21 @@ __device__ __forceinline__ void block_reduce2_max_u64(unsigned long long& a, uns
     }
 }
 
+// record the end of a member's solve: status, sweeps, last residual, and the
+// totals of the captured-run statistics
+__device__ __forceinline__ void ctl_commit(Ctl* ctl, int st, int sweeps, double r) {
+    ctl->status = st;
+    ctl->sweeps = sweeps;
+    ctl->residual = r;
+    ctl->done = 1;
+    ctl->acc_solves += 1;
+    ctl->acc_sweeps += sweeps;
+    ctl->acc_sweeps_max = max(ctl->acc_sweeps_max, sweeps);
+    ctl->acc_residual_max = fmax(ctl->acc_residual_max, r);
+    const int w = ctl->acc_worst;
+    if (st < 0 ? (w >= 0 || st < w) : (w >= 0 && st > w)) ctl->acc_worst = st;
+}
+
 // decision of a sweep pass from the completed residual of the previous sweep.
 // returns 0 to continue, else the terminating sbi_status + 100 (so 0 is free).
 __device__ __forceinline__ int sweep_decision(Ctl* ctl, int n, int M, double tol, double* r_out, double* rmin_out) {

@@ -1,5 +1,6 @@
 // sbi_dispatch.hip -- precision dispatch of the kernel launchers and the
 // precision-independent control kernels.
+#include "sbi_device.hpp"
 #include "sbi_kernels.hpp"
 
 namespace sbi {
@@ -31,6 +32,7 @@ __global__ void k_ctl_reset(Ctl* ctl, int slots) {
         c->done = 0;
         c->status = 0;
         c->sweeps = 0;
+        c->sweeps_inner = 0;
         c->omega = 1.0;
         c->residual = 0.0;
         c->rmin = INFINITY;
@@ -56,6 +58,170 @@ hipError_t launch_ctl_acc_reset(Ctl* ctl, int batch, hipStream_t s) {
 __global__ void k_fill_zero(uint4* p, size_t n16) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
         p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// ---------------------------------------------------------------------------
+// mixed precision (SBI_MIXED): the hand-over between the FP64 refinement of
+// x = T(x) and the FP32 solve of its correction equation d = A d + r
+// ---------------------------------------------------------------------------
+// stopping decision after FP64 refinement sweep n (its residual norms in slot
+// n - 1), with the rules of the plain iteration; the sweeps counted are the
+// FP64 ones plus the FP32 correction sweeps so far
+__global__ void k_ctl_decide(Ctl* ctl, int n, int M, double tol) {
+    Ctl* c = ctl + blockIdx.x;
+    if (threadIdx.x != 0 || c->done) return;
+    double r, rmin;
+    const int dec = sweep_decision(c, n, M, tol, &r, &rmin);
+    if (dec) {
+        ctl_commit(c, dec - 100, n + c->sweeps_inner, r);
+    } else {
+        c->rmin = rmin;
+        c->residual = r;
+    }
+}
+
+// FP64 residual r (compact spectra of its V and phi_b parts) -> forcing b and
+// first iterate d = r of the FP32 correction solve (d = T_r(0)); the
+// relaxation weight carries over, and members already decided stay decided.
+// The n = Kx*Ky kept modes of a member come first in either layout (columns
+// of Ky modes); so and si are the member strides of the FP64 and FP32 sides.
+__global__ void k_mixed_down(const Ctl* outer, Ctl* inner, const double2* rv, const double2* rb, float2* bv,
+                             float2* vn, float2* bb, float2* bn, long long n, long long so, long long si, int vd) {
+    const int m = blockIdx.y;
+    const Ctl* o = outer + m;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        inner[m].omega = o->omega;
+        inner[m].done = o->done;
+    }
+    if (o->done) return;
+    const long long oo = (long long)m * so, oi = (long long)m * si;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const double2 a = rv[oo + i];
+        const float2 f = make_float2((float)a.x, (float)a.y);
+        bv[oi + i] = f;
+        vn[oi + i] = f;
+        if (vd) {
+            const double2 q = rb[oo + i];
+            const float2 g = make_float2((float)q.x, (float)q.y);
+            bb[oi + i] = g;
+            bn[oi + i] = g;
+        }
+    }
+}
+
+// x += d (FP64 += FP32) for the members the correction solve ran for; a
+// correction solve that failed (diverged, non-finite) ends the member's solve
+// with its status after n FP64 sweeps
+__global__ void k_mixed_up(Ctl* outer, const Ctl* inner, double2* vn, double2* bn, const float2* dv,
+                           const float2* db, long long n, long long so, long long si, int vd, int nsweep) {
+    const int m = blockIdx.y;
+    const Ctl* in = inner + m;
+    if (in->sweeps == 0) return;  // decided before this correction solve
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Ctl* o = outer + m;
+        o->sweeps_inner += in->sweeps;
+        const int st = in->nonfinite ? -5 : in->status;
+        if (st < 0) ctl_commit(o, st, nsweep + o->sweeps_inner, in->residual);
+    }
+    const long long oo = (long long)m * so, oi = (long long)m * si;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const float2 d = dv[oi + i];
+        double2 x = vn[oo + i];
+        x.x += (double)d.x;
+        x.y += (double)d.y;
+        vn[oo + i] = x;
+        if (vd) {
+            const float2 e = db[oi + i];
+            double2 y = bn[oo + i];
+            y.x += (double)e.x;
+            y.y += (double)e.y;
+            bn[oo + i] = y;
+        }
+    }
+}
+
+// the same update for the half forms the next row pass reads (they are
+// linear in the iterate: half(x + d) = half(x) + half(d)); a half form holds
+// column k < kx of row y at k * ldh + y, ldh and the member stride differ
+// between the two sides; nf fields (V, d_x phi_b, d_y phi_b)
+struct MixedHalf {
+    double2* out[3];
+    const float2* in[3];
+    int nf, kx, ny, ldh_o, ldh_i;
+    long long so, si;
+};
+__global__ void k_mixed_up_half(const Ctl* inner, const MixedHalf h) {
+    const int m = blockIdx.y;
+    if (inner[m].sweeps == 0) return;  // decided before this correction solve
+    const long long n = (long long)h.kx * h.ny;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long k = i / h.ny, y = i - k * h.ny;
+        const long long oo = m * h.so + k * h.ldh_o + y, oi = m * h.si + k * h.ldh_i + y;
+        for (int f = 0; f < h.nf; ++f) {
+            const float2 d = h.in[f][oi];
+            double2 x = h.out[f][oo];
+            x.x += (double)d.x;
+            x.y += (double)d.y;
+            h.out[f][oo] = x;
+        }
+    }
+}
+
+__global__ void k_to_float(const double* src, float* dst, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+static unsigned elem_blocks(long long n) {
+    long long nb = (n + 255) / 256;
+    return (unsigned)(nb < 1 ? 1 : (nb > 1024 ? 1024 : nb));
+}
+
+hipError_t launch_ctl_decide(Ctl* ctl, int batch, int n, int M, double tol, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_decide, dim3(batch), dim3(64), 0, s, ctl, n, M, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_mixed_down(const Ctl* outer, Ctl* inner, int batch, const void* rv, const void* rb, void* bv,
+                             void* vn, void* bb, void* bn, long long n, long long so, long long si, int vd,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_mixed_down, dim3(elem_blocks(n), batch), dim3(256), 0, s, outer, inner,
+                       static_cast<const double2*>(rv), static_cast<const double2*>(rb), static_cast<float2*>(bv),
+                       static_cast<float2*>(vn), static_cast<float2*>(bb), static_cast<float2*>(bn), n, so, si, vd);
+    return hipGetLastError();
+}
+
+hipError_t launch_mixed_up(Ctl* outer, const Ctl* inner, int batch, void* vn, void* bn, const void* dv,
+                           const void* db, long long n, long long so, long long si, int vd, int nsweep,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_mixed_up, dim3(elem_blocks(n), batch), dim3(256), 0, s, outer, inner,
+                       static_cast<double2*>(vn), static_cast<double2*>(bn), static_cast<const float2*>(dv),
+                       static_cast<const float2*>(db), n, so, si, vd, nsweep);
+    return hipGetLastError();
+}
+
+hipError_t launch_mixed_up_half(const Ctl* inner, int batch, void* const* out, const void* const* in, int nf, int kx,
+                                int ny, int ldh_o, int ldh_i, long long so, long long si, hipStream_t s) {
+    MixedHalf h{};
+    for (int f = 0; f < nf && f < 3; ++f) {
+        h.out[f] = static_cast<double2*>(out[f]);
+        h.in[f] = static_cast<const float2*>(in[f]);
+    }
+    h.nf = nf < 3 ? nf : 3;
+    h.kx = kx;
+    h.ny = ny;
+    h.ldh_o = ldh_o;
+    h.ldh_i = ldh_i;
+    h.so = so;
+    h.si = si;
+    hipLaunchKernelGGL(k_mixed_up_half, dim3(elem_blocks((long long)kx * ny), batch), dim3(256), 0, s, inner, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_float(const void* src, void* dst, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_float, dim3(elem_blocks(n)), dim3(256), 0, s, static_cast<const double*>(src),
+                       static_cast<float*>(dst), n);
+    return hipGetLastError();
 }
 
 hipError_t launch_ctl_reset(Ctl* ctl, int batch, int slots, hipStream_t s) {

@@ -135,19 +135,7 @@ __device__ __forceinline__ bool full_decided(const FullParams& p, Ctl* ctl, bool
     double r, rmin;
     const int dec = sweep_decision(ctl, p.sweep, p.max_sweeps, p.tol, &r, &rmin);
     if (dec) {
-        if (leader) {
-            const int st = dec - 100;
-            ctl->status = st;
-            ctl->sweeps = p.sweep;
-            ctl->residual = r;
-            ctl->done = 1;
-            ctl->acc_solves += 1;
-            ctl->acc_sweeps += p.sweep;
-            ctl->acc_sweeps_max = max(ctl->acc_sweeps_max, p.sweep);
-            ctl->acc_residual_max = fmax(ctl->acc_residual_max, r);
-            const int w = ctl->acc_worst;
-            if (st < 0 ? (w >= 0 || st < w) : (w >= 0 && st > w)) ctl->acc_worst = st;
-        }
+        if (leader) ctl_commit(ctl, dec - 100, p.sweep, r);
         return true;
     }
     if (leader) {

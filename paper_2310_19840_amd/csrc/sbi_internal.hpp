@@ -75,6 +75,7 @@ struct Ctl {
     int status;                              // sbi_status of the solve
     int sweeps;                              // sweep-operator applications
     int nonfinite;                           // a non-finite input value was seen
+    int sweeps_inner;                        // FP32 correction sweeps of a mixed-precision solve
     double omega;                            // relaxation weight
     double residual;                         // last residual
     double rmin;                             // smallest residual seen so far

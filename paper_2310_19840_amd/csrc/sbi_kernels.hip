@@ -357,7 +357,10 @@ __device__ __forceinline__ void row_sweep_body(const RowSweepParams& p, const ty
     const int fam = blockIdx.y;  // product family of this workgroup
     if (fam == 0) {
         V vv[E];
-        RW::inverse(vv, static_cast<const V*>(p.gV) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+        // the iterate: for its products, and for the residual's denominator
+        // of the relaxed update (a residual-only Anderson pass needs neither)
+        if (!AA || p.products)
+            RW::inverse(vv, static_cast<const V*>(p.gV) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
         if (p.residual) {
             V dd[E];
             RW::inverse(dd, static_cast<const V*>(p.gD) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
@@ -755,19 +758,7 @@ __device__ __forceinline__ bool col_control(const ColParams& p, Ctl* ctl, bool l
         double r, rmin;
         const int dec = sweep_decision(ctl, p.sweep, p.max_sweeps, p.tol, &r, &rmin);
         if (dec) {
-            if (leader) {
-                const int st = dec - 100;
-                ctl->status = st;
-                ctl->sweeps = p.sweep;
-                ctl->residual = r;
-                ctl->done = 1;
-                ctl->acc_solves += 1;
-                ctl->acc_sweeps += p.sweep;
-                ctl->acc_sweeps_max = max(ctl->acc_sweeps_max, p.sweep);
-                ctl->acc_residual_max = fmax(ctl->acc_residual_max, r);
-                const int w = ctl->acc_worst;
-                if (st < 0 ? (w >= 0 || st < w) : (w >= 0 && st > w)) ctl->acc_worst = st;
-            }
+            if (leader) ctl_commit(ctl, dec - 100, p.sweep, r);
             return false;
         }
         if (leader) {

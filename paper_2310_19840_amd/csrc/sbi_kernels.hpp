@@ -286,5 +286,19 @@ hipError_t launch_hist_newton(const HistParams& p, double lam, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* ctl, int batch, int slots, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, size_t bytes, hipStream_t s);
 hipError_t launch_ctl_acc_reset(Ctl* ctl, int batch, hipStream_t s);
+// mixed precision: decision of an FP64 refinement sweep, the hand-over of its
+// residual to the FP32 correction solve (rv, rb FP64 compact -> bv, vn, bb, bn
+// FP32 compact; the n kept modes per member, member strides so (FP64) and si
+// (FP32)), the FP64 update x += d, and eta -> FP32
+hipError_t launch_ctl_decide(Ctl* ctl, int batch, int n, int M, double tol, hipStream_t s);
+hipError_t launch_mixed_down(const Ctl* outer, Ctl* inner, int batch, const void* rv, const void* rb, void* bv,
+                             void* vn, void* bb, void* bn, long long n, long long so, long long si, int vd,
+                             hipStream_t s);
+hipError_t launch_mixed_up(Ctl* outer, const Ctl* inner, int batch, void* vn, void* bn, const void* dv,
+                           const void* db, long long n, long long so, long long si, int vd, int nsweep,
+                           hipStream_t s);
+hipError_t launch_mixed_up_half(const Ctl* inner, int batch, void* const* out, const void* const* in, int nf, int kx,
+                                int ny, int ldh_o, int ldh_i, long long so, long long si, hipStream_t s);
+hipError_t launch_to_float(const void* src, void* dst, long long n, hipStream_t s);
 
 }  // namespace sbi

@@ -184,3 +184,22 @@ def test_full_mode_grids(lib):
     g2 = make_grid(64, 64, 50.0, 50.0, mode="full")
     assert lib.sbi_workspace_bytes(C.byref(g2), 1) == 0
     assert _lib.SBI_MODE_FULL == 2
+
+
+def test_mixed_precision_grids(lib):
+    """SBI_MIXED refines an iteration: its workspace holds the FP64 context and
+    the FP32 one of the correction sweeps; SA and fully nonlinear grids refuse it."""
+    from paper_2310_19840_amd import _lib, make_grid
+    for nx, ny in ((256, 1), (128, 64)):
+        gm = make_grid(nx, ny, 50.0, 50.0, precision="mixed")
+        g64 = make_grid(nx, ny, 50.0, 50.0, precision="fp64")
+        g32 = make_grid(nx, ny, 50.0, 50.0, precision="fp32")
+        bm = lib.sbi_workspace_bytes(C.byref(gm), 2)
+        assert bm == lib.sbi_workspace_bytes(C.byref(g64), 2) + lib.sbi_workspace_bytes(C.byref(g32), 2)
+    for mode in ("sa", "full"):
+        g = make_grid(256, 1, 50.0, precision="mixed", mode=mode)
+        assert lib.sbi_workspace_bytes(C.byref(g), 1) == 0
+    assert _lib.SBI_MIXED == 2
+    # the solve info carries the FP32 share after the FP64 fields
+    assert _lib.sbi_solve_info.sweeps_fp32.offset == 24
+    assert _lib.sbi_step_info.sweeps_fp32_total.offset == 32

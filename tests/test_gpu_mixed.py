@@ -1,0 +1,159 @@
+"""Mixed precision (SBI_MIXED): FP32 sweeps on the correction equation between
+FP64 residual sweeps.  The FP64 test decides the solve, so the W it returns
+is the FP64 iteration's fixed point to the FP64 tolerance -- checked against
+the oracle (oracle/sbi_oracle.py, FP64) at 1e-8 and tighter, where an FP32
+context stalls near 1e-6 -- and steps agree with the oracle's FP64 steps."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import sbi_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _t(x, dtype, dev):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device=dev)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _case(nx, ny, seed, bed=True, amp=0.06):
+    lx = 2 * math.pi * nx / 16
+    ly = 2 * math.pi * ny / 16 if ny > 1 else 1.0
+    gs = si.GridSpec(nx, ny, lx, ly)
+    eta = si.narrowband_random(gs, seed, amp=amp)
+    phi = si.narrowband_random(gs, seed + 1, amp=5 * amp)
+    if ny > 1:
+        X, Y = np.meshgrid(gs.x(), gs.y())
+        bump = np.exp(-((X - lx / 3) ** 2 / (0.02 * lx * lx) + (Y - ly / 2) ** 2 / (0.02 * ly * ly)))
+    else:
+        x = gs.x()[None, :]
+        bump = np.exp(-((x - lx / 3) ** 2) / (0.02 * lx * lx))
+    depth = 1.5 - (0.4 * bump if bed else 0.0 * bump)
+    return lx, ly, eta, phi, depth
+
+
+@pytest.mark.parametrize("accel", [None, "anderson"])
+@pytest.mark.parametrize("nx,ny,bed", [(256, 1, True), (512, 1, False), (64, 64, True), (128, 32, False)])
+def test_mixed_w_matches_oracle(gpu, nx, ny, bed, accel):
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    lx, ly, eta, phi, depth = _case(nx, ny, nx + ny + 7, bed)
+    o = OSolver(Grid(nx, ny, lx, ly), depth, mode="iter", max_sweeps=300, accel=accel)
+    s = Solver(nx, ny, lx, ly, depth, device=gpu, mode="iter", max_sweeps=300, accel=accel, precision="mixed")
+    e, p = _t(eta, torch.float64, gpu), _t(phi, torch.float64, gpu)
+    for tol in (1e-8, 1e-12):
+        Wo, oi = o.vertical_velocity(eta, phi, tol=min(tol, 1e-13))
+        W, st, info = s.vertical_velocity(e, p, tol=tol)
+        sw, _, res, _, sw32 = info[0]
+        err = _rel(W.cpu().numpy()[0], Wo)
+        _say(f"mixed {nx}x{ny} bed={bed} accel={accel} tol {tol:.0e}: W err {err:.2e}, "
+             f"sweeps {sw} ({sw - sw32} FP64, {sw32} FP32), residual {res:.1e}")
+        assert st == 0 and res <= tol
+        assert sw32 > 0 and 1 <= sw - sw32 <= 4
+        assert err < 10 * tol
+
+
+def test_mixed_reaches_tolerances_where_fp32_stalls(gpu):
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    nx, ny = 128, 64
+    lx, ly, eta, phi, depth = _case(nx, ny, 5, True, amp=0.08)
+    Wo, _ = OSolver(Grid(nx, ny, lx, ly), depth, mode="iter", max_sweeps=300).vertical_velocity(eta, phi, tol=1e-14)
+    # FP32 sweeps alone stop at their floor (~1e-6): 1e-9 is out of reach
+    s32 = Solver(nx, ny, lx, ly, depth, device=gpu, mode="iter", max_sweeps=120, precision="fp32")
+    _, st32, info32 = s32.vertical_velocity(_t(eta, torch.float32, gpu), _t(phi, torch.float32, gpu), tol=1e-9)
+    _say(f"fp32 at 1e-9: status {st32}, residual {info32[0][2]:.1e}")
+    assert st32 != 0 and info32[0][2] > 1e-9
+    s = Solver(nx, ny, lx, ly, depth, device=gpu, mode="iter", max_sweeps=120, precision="mixed",
+               accel="anderson")
+    for tol in (1e-9, 1e-11, 1e-13):
+        W, st, info = s.vertical_velocity(_t(eta, torch.float64, gpu), _t(phi, torch.float64, gpu), tol=tol)
+        err = _rel(W.cpu().numpy()[0], Wo)
+        _say(f"mixed at {tol:.0e}: status {st}, residual {info[0][2]:.1e}, err {err:.1e}, "
+             f"FP64 sweeps {info[0][0] - info[0][4]}")
+        assert st == 0 and info[0][2] <= tol and err < 10 * tol + 1e-14
+
+
+def test_mixed_members_and_steps_match_oracle(gpu):
+    """Two members with their own states and beds in one context, W and two
+    RK4 steps against the oracle's FP64 solves and steps."""
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    nx, ny = 64, 32
+    cases = [_case(nx, ny, 11, True), _case(nx, ny, 23, False)]
+    lx, ly = cases[0][0], cases[0][1]
+    dep = np.stack([c[4] for c in cases])
+    s = Solver(nx, ny, lx, ly, dep, batch=2, device=gpu, mode="iter", max_sweeps=200, precision="mixed",
+               accel="anderson")
+    e = _t(np.stack([c[2] for c in cases]), torch.float64, gpu)
+    p = _t(np.stack([c[3] for c in cases]), torch.float64, gpu)
+    W, st, info = s.vertical_velocity(e, p, tol=1e-11)
+    assert st == 0
+    for k, c in enumerate(cases):
+        Wo, _ = OSolver(Grid(nx, ny, lx, ly), c[4], mode="iter", max_sweeps=300).vertical_velocity(c[2], c[3], tol=1e-14)
+        err = _rel(W.cpu().numpy()[k], Wo)
+        _say(f"member {k}: W err {err:.1e}, sweeps {info[k]}")
+        assert err < 1e-10
+    dt = 2 * math.pi / 24
+    st, sinfo = s.step(e, p, dt, 2, tol=1e-12)
+    _say("steps:", sinfo)
+    assert st == 0 and sinfo["solves"] == 16 and 0 < sinfo["sweeps_fp32_total"] < sinfo["sweeps_total"]
+    for k, c in enumerate(cases):
+        o = OSolver(Grid(nx, ny, lx, ly), c[4], mode="iter", max_sweeps=300)
+        eo, po, _ = o.step(c[2], c[3], dt, 2, tol=1e-13)
+        assert _rel(e.cpu().numpy()[k], eo) < 1e-10
+        assert _rel(p.cpu().numpy()[k], po) < 1e-10
+
+
+def test_mixed_adaptive_pair_and_diagnostics(gpu):
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    nx = 256
+    lx, _, eta, phi, depth = _case(nx, 1, 41, True, amp=0.05)
+    T = 2 * math.pi / math.sqrt(math.tanh(1.5))
+    o = OSolver(Grid(nx, 1, lx), depth, mode="iter", max_sweeps=300)
+    eo, po, oinfo = o.step_adaptive(eta, phi, 0.0, T, T / 16, 1e-6, tol=1e-13)
+    s = Solver(nx, 1, lx, 1.0, depth, device=gpu, mode="iter", max_sweeps=300, precision="mixed")
+    e, p = _t(eta[None], torch.float64, gpu), _t(phi[None], torch.float64, gpu)
+    st, info = s.step_adaptive(e, p, T, T / 16, 1e-6, tol=1e-12)
+    _say(f"adaptive mixed: accepted {info['accepted']}/{oinfo['accepted']}, rejected {info['rejected']}/{oinfo['rejected']}")
+    assert st >= 0 and (info["accepted"], info["rejected"]) == (oinfo["accepted"], oinfo["rejected"])
+    assert _rel(e.cpu().numpy().reshape(eo.shape), eo) < 1e-10
+    assert _rel(p.cpu().numpy().reshape(po.shape), po) < 1e-10
+    m, en = s.diagnostics(e, p, tol=1e-12)
+    mo, eno = o.diagnostics(eo, po, tol=1e-13)
+    assert abs(en[0] - eno) <= 1e-10 * abs(eno) and abs(m[0] - mo) <= 1e-10 * max(abs(mo), 1e-3)
+
+
+def test_mixed_refusals(gpu):
+    from paper_2310_19840_amd import Batch, SBIError, Solver, _lib, vertical_velocity_noalloc
+    import torch
+    d = np.ones((1, 64))
+    # the refinement refines an iteration: SA and the fully nonlinear mode refuse it
+    for mode in ("sa", "full"):
+        with pytest.raises(SBIError) as ex:
+            Solver(64, 1, 10.0, 1.0, d, device=gpu, mode=mode, precision="mixed")
+        assert ex.value.code == _lib.SBI_ERR_INVALID_ARG
+    with pytest.raises(SBIError) as ex:
+        Batch([dict(nx=64, ny=1, lx=10.0, ly=1.0, depth=d, precision="mixed")], device=gpu)
+    assert ex.value.code == _lib.SBI_ERR_UNSUPPORTED
+    z = torch.zeros((1, 1, 64), dtype=torch.float64, device=gpu)
+    with pytest.raises(SBIError) as ex:
+        vertical_velocity_noalloc(z, z, d, 64, 1, 10.0, precision="mixed")
+    assert ex.value.code == _lib.SBI_ERR_UNSUPPORTED
