@@ -300,6 +300,34 @@ def test_fullsize_anderson_w_is_an_oracle_fixed_point(gpu, tol):
     assert _rel(Wg, Wo) <= 3 * tol
 
 
+@pytest.mark.parametrize("tol", [1e-8, 1e-11])
+def test_fullsize_mixed_w_is_an_oracle_fixed_point(gpu, tol):
+    # mixed precision at 1024^2 (FP32 correction sweeps, FP64 residual test)
+    # stops at the FP64 iteration's fixed point: the oracle's sweeps, seeded
+    # with the GPU's V and phi_b, stop within two sweeps and move W by <= 3 tol
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    cfg = _c5()
+    g = cfg["grid"]
+    _say("1024^2 mixed-precision fixed point, tol", tol)
+    s = Solver(g.nx, g.ny, g.lx, g.ly, cfg["depth"], device=gpu, mode="iter", max_sweeps=200, seed="prev",
+               accel="anderson", precision="mixed")
+    eta = torch.tensor(cfg["eta"][None], dtype=torch.float64, device=gpu)
+    phi = torch.tensor(cfg["phi"][None], dtype=torch.float64, device=gpu)
+    W, st, info = s.vertical_velocity(eta, phi, tol=tol)
+    _say("mixed sweeps (total, FP32):", info[0][0], info[0][4], "residual", info[0][2])
+    assert st == 0 and info[0][4] > 0 and info[0][2] <= tol, info
+    dv, db = s.last_correction()
+    Wg = W.cpu().numpy().reshape(g.ny, g.nx)
+    dbg = db.cpu().numpy().reshape(g.ny, g.nx)
+    o = OSolver(Grid(g.nx, g.ny, g.lx, g.ly), cfg["depth"], mode="iter", max_sweeps=4)
+    Wo, oi = o.vertical_velocity(cfg["eta"], cfg["phi"], tol=tol, seed=Wg, seed_b=dbg)
+    _say("oracle sweeps from the gpu iterate", oi.sweeps, "residual", oi.residual)
+    assert oi.status == 0 and oi.sweeps <= 2
+    assert _rel(Wg, Wo) <= 3 * tol
+
+
 def test_fullsize_anderson_steps_equal_relaxed_steps(gpu):
     # two RK4 steps at 1024^2 with either iteration agree to the solve tolerance
     import torch
