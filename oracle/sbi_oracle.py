@@ -134,10 +134,10 @@ class Solver:
         self.mode = mode
         if mode not in ("sa", "iter", "full"):
             raise ValueError("mode must be 'sa', 'iter' or 'full'")
-        if mode == "full" and (grid.ny != 1 or not self.flat):
+        if mode == "full" and grid.ny != 1:
             # the exact boundary-integral solve (oracle.full_bie) covers one
-            # horizontal dimension over a flat bed
-            raise ValueError("mode 'full' needs a one-dimensional grid and a flat bed")
+            # horizontal dimension
+            raise ValueError("mode 'full' needs a one-dimensional grid")
         self.max_sweeps = int(max_sweeps)
         self.relax = relax
         k = grid.k
@@ -533,11 +533,20 @@ class Solver:
 
     # ------------------------------------------------------------------------
     def w_full_hat(self, eta, ph, tol):
-        """W with the remaining integrals of App. A kept (oracle.full_bie), masked."""
+        """W with the remaining integrals of App. A and App. B kept
+        (oracle.full_bie), masked: the image form over a flat bed, or a bed so
+        deep that it is invisible (k_1 times the smallest depth beyond 18); the
+        two-boundary form over any other bed."""
         from . import full_bie
         g = self.g
-        V, sweeps, status, r = full_bie.vertical_velocity(np.asarray(eta).ravel(), g.ifft(ph).ravel(), g.lx,
-                                                          self.h, tol, self.max_sweeps)
+        e = np.asarray(eta).ravel()
+        p = g.ifft(ph).ravel()
+        dmin = self.h - float(self.delta.max())
+        if self.flat or full_bie.is_deep(g.lx, dmin):
+            V, sweeps, status, r = full_bie.vertical_velocity(e, p, g.lx, self.h, tol, self.max_sweeps)
+        else:
+            V, sweeps, status, r = full_bie.vertical_velocity_bed(e, p, g.lx, self.h, self.delta.ravel(), tol,
+                                                                  self.max_sweeps)
         return g.MF(V.reshape(1, g.nx)), SolveInfo(sweeps=sweeps, residual=r, status=status)
 
     def solve_hat(self, eta, ph, tol=1e-10, seed_hat=None, seed_b_hat=None, stage=None):

@@ -1,6 +1,7 @@
 """Pins of the fully nonlinear W solve (oracle.full_bie): the boundary-
-integral equation of Sec. 2.3 with the remaining integrals I^(S) of App. A
-kept, one horizontal dimension, flat bed.
+integral equations of Sec. 2.3 with the remaining integrals I^(S) of App. A
+kept, one horizontal dimension -- over a flat bed (image form) and, with the
+bed's own remainder I^(B) of App. B, over a variable bed (two-boundary form).
 
 Pinned against what fixes it independently: the linear flat-surface limit
 V = k tanh(kh) phi_hat, the limits of the quadrature kernels on their
@@ -114,6 +115,118 @@ def test_remaining_integral_is_of_eighth_order():
     assert 200 < ratio < 330, ratio
 
 
+# --- the two-boundary solve over a variable bed (I^(B) kept) ---------------
+
+def _bed(x, A):
+    return A * (1 + np.cos(x)) / 2 + 0.3 * A * (1 + np.sin(2 * x)) / 2
+
+
+@pytest.mark.parametrize("h", [0.7, 1.0, 3.0])
+def test_bed_solve_linear_flat_limit(h):
+    # with the bed as a boundary of its own (no image), a flat bed under a
+    # flat surface still gives k tanh(kh) phi_hat, exactly after one sweep
+    x = _x(64)
+    phi = np.cos(3 * x) + 0.5 * np.sin(5 * x) - 0.2 * np.cos(11 * x)
+    V, n, st, r = full_bie.vertical_velocity_bed(np.zeros(64), phi, L2PI, h, np.zeros(64), tol=1e-13)
+    T = lambda k: math.tanh(k * h)
+    exact = 3 * T(3) * np.cos(3 * x) + 2.5 * T(5) * np.sin(5 * x) - 2.2 * T(11) * np.cos(11 * x)
+    assert st == 0 and n == 2
+    assert np.abs(V - exact).max() < 1e-12
+
+
+def test_bed_solve_equals_image_solve_over_flat_beds():
+    # a flat bed as a second boundary against its image: the same V with the
+    # same sweeps; a constant delta = c is the flat bed at depth h - c
+    x = _x(64)
+    eta = 0.1 * np.cos(x) + 0.03 * np.sin(2 * x + 0.3)
+    phi = np.cos(x) + 0.4 * np.sin(2 * x) - 0.1 * np.cos(5 * x)
+    for h in (1.0, 2.0):
+        V1, n1, _, _ = full_bie.vertical_velocity(eta, phi, L2PI, h, tol=1e-14, max_sweeps=200)
+        V2, n2, st, _ = full_bie.vertical_velocity_bed(eta, phi, L2PI, h, np.zeros(64), tol=1e-14, max_sweeps=200)
+        assert st == 0 and n1 == n2
+        assert np.abs(V1 - V2).max() / np.abs(V1).max() < 1e-13
+    V1, _, _, _ = full_bie.vertical_velocity(eta, phi, L2PI, 0.8, tol=1e-14, max_sweeps=200)
+    V2, _, st, _ = full_bie.vertical_velocity_bed(eta, phi, L2PI, 1.0, np.full(64, 0.2), tol=1e-14, max_sweeps=200)
+    assert st == 0 and np.abs(V1 - V2).max() / np.abs(V1).max() < 1e-13
+
+
+@pytest.mark.parametrize("eps,d", [(0.1, 1.0), (0.2, 2.0)])
+def test_bed_solve_of_finite_depth_steady_waves_is_exact(eps, d):
+    # exact steady waves over a flat bed, the bed kept as a boundary of its own
+    w = SteadyWave(2 * eps, depth=d)
+    x = _x(64)
+    eta, _, phi, V = w.surface(x)
+    Vb, _, st, _ = full_bie.vertical_velocity_bed(eta, phi, L2PI, d, np.zeros(64), tol=1e-14, max_sweeps=100)
+    assert st == 0 and np.abs(Vb - V).max() / np.abs(V).max() < 1e-12
+
+
+def test_bed_double_layer_diagonal_is_its_limit():
+    # the bed's double layer (outward normal pointing down) at x' = x + t tends
+    # to -b_xx / (2 (1 + b_x^2)) as t -> 0, the value on the quadrature's diagonal
+    lx = 3.0
+    a1, a2 = 0.2, 0.07
+
+    def b(x):
+        return -1.0 + a1 * np.cos(2 * np.pi * x / lx) + a2 * np.sin(6 * np.pi * x / lx)
+
+    def bx(x):
+        return -a1 * (2 * np.pi / lx) * np.sin(2 * np.pi * x / lx) + a2 * (6 * np.pi / lx) * np.cos(6 * np.pi * x / lx)
+
+    def bxx(x):
+        return (-a1 * (2 * np.pi / lx) ** 2 * np.cos(2 * np.pi * x / lx)
+                - a2 * (6 * np.pi / lx) ** 2 * np.sin(6 * np.pi * x / lx))
+
+    x0 = 0.61
+    lim = -bxx(x0) / (2 * (1 + bx(x0) ** 2))
+    for t in (1e-3, 1e-4):
+        xs = x0 + t
+        u = t + 1j * (b(xs) - b(x0))
+        kd = -((np.pi / lx) / np.tan(np.pi * u / lx) * (1 + 1j * bx(xs))).imag
+        assert abs(kd - lim) < 50 * t
+    n = 256
+    xg = _x(n, lx)
+    *_, DBB = full_bie.bed_kernels(np.zeros(n), b(xg), lx)
+    i = 77
+    assert abs(DBB[i, i] / (lx / n) + bxx(xg[i]) / (2 * (1 + bx(xg[i]) ** 2))) < 1e-8
+
+
+def test_bed_solve_is_reciprocal():
+    # Green's reciprocity: the Dirichlet-Neumann map of a steep surface over a
+    # variable bed is symmetric, int phi_1 V[phi_2] dx = int phi_2 V[phi_1] dx
+    # (a wrong sign or a missing term in any bed kernel breaks it), and
+    # positive, int phi V[phi] dx > 0
+    x = _x(128)
+    eta = 0.15 * np.cos(x) + 0.05 * np.cos(2 * x - 0.4)
+    delta = _bed(x, 0.4)
+    p1 = np.cos(x) + 0.3 * np.sin(3 * x)
+    p2 = np.sin(2 * x) - 0.5 * np.cos(4 * x + 0.1)
+    V1, _, s1, _ = full_bie.vertical_velocity_bed(eta, p1, L2PI, 1.0, delta, tol=1e-14, max_sweeps=300)
+    V2, _, s2, _ = full_bie.vertical_velocity_bed(eta, p2, L2PI, 1.0, delta, tol=1e-14, max_sweeps=300)
+    assert s1 == 0 and s2 == 0
+    a12, a21 = float(np.dot(p1, V2)), float(np.dot(p2, V1))
+    assert abs(a12 - a21) < 1e-10 * max(abs(a12), 1.0)
+    assert np.dot(p1, V1) > 0 and np.dot(p2, V2) > 0
+
+
+def test_bed_remainder_is_of_seventh_order():
+    # I^(B): under a linear surface the expansion of order 7 keeps the bed
+    # terms up to delta^6, so V - V_SA7 shrinks by about 2^7 when the bed's
+    # amplitude halves (a dropped or mis-signed bed term would leave a lower
+    # power)
+    x = _x(64)
+    phi = np.cos(2 * x) + 0.5 * np.sin(3 * x + 0.2)
+    eta = 1e-6 * np.cos(x)
+    d = []
+    for A in (0.1, 0.2):
+        delta = _bed(x, A)
+        V, _, st, _ = full_bie.vertical_velocity_bed(eta, phi, L2PI, 1.0, delta, tol=1e-14, max_sweeps=300)
+        s = Solver(Grid(64, 1, L2PI, dealias=0.99), (1.0 - delta)[None], h_ref=1.0, mode="sa")
+        W7, _ = s.vertical_velocity(eta[None], phi[None])
+        assert st == 0
+        d.append(np.abs(V - W7[0]).max())
+    assert 110 < d[1] / d[0] < 180, d
+
+
 def test_solver_mode_full():
     # the solver's mode returns the masked W of the exact solve and refuses
     # what it does not cover
@@ -129,8 +242,18 @@ def test_solver_mode_full():
     assert np.abs(W - g.ifft(g.MF(Vf[None]))).max() < 1e-14
     with pytest.raises(ValueError):
         Solver(Grid(16, 16, L2PI, L2PI), np.ones((16, 16)), mode="full")
-    with pytest.raises(ValueError):
-        Solver(g, 1.0 - 0.1 * np.cos(x)[None], mode="full")
+    # over a variable bed the mode takes the two-boundary solve; over a bed
+    # too deep to matter (k_1 times the smallest depth beyond 18), the image one
+    d = 1.0 - 0.1 * np.cos(x)
+    W, info = Solver(g, d[None], mode="full", max_sweeps=200).vertical_velocity(eta[None], phi[None], tol=1e-13)
+    Vb, n, _, _ = full_bie.vertical_velocity_bed(eta, g.ifft(g.MF(phi[None]))[0], L2PI, 1.1, 1.1 - d, tol=1e-13,
+                                                  max_sweeps=200)
+    assert info.status == 0 and info.sweeps == n
+    assert np.abs(W - g.ifft(g.MF(Vb[None]))).max() < 1e-14
+    dd = 30.0 - 0.1 * np.cos(x)
+    W, info = Solver(g, dd[None], mode="full", max_sweeps=200).vertical_velocity(eta[None], phi[None], tol=1e-13)
+    Vd, n, _, _ = full_bie.vertical_velocity(eta, g.ifft(g.MF(phi[None]))[0], L2PI, 30.0, tol=1e-13, max_sweeps=200)
+    assert info.sweeps == n and np.abs(W - g.ifft(g.MF(Vd[None]))).max() < 1e-14
 
 
 def test_full_mode_carries_a_steep_wave_over_a_period():
