@@ -13,14 +13,16 @@
  *   - W is evaluated by the successive approximation of Sec. 2.4 with the
  *     explicit orders of Appendix C (Eqs. (v2)-(v7)) -- mode SBI_MODE_SA --
  *     or by iterating the same expansion summed over orders to a residual
- *     tolerance -- mode SBI_MODE_ITER -- or, on one-dimensional grids over a
- *     flat bed, fully nonlinearly: the surface boundary-integral equation of
- *     Sec. 2.3 with the remaining integrals I^(S) of App. A kept
- *     (Eq. (con-V): the expansion plus I^(S) is the exact equation), in its
- *     two-dimensional-flow form (Green function -ln r, image in the bed),
- *     iterated to the residual tolerance with O(nx^2) quadrature per sweep --
- *     mode SBI_MODE_FULL (sbi_init returns SBI_ERR_UNSUPPORTED for a
- *     variable bed, and ensembles do not take it);
+ *     tolerance -- mode SBI_MODE_ITER -- or, on one-dimensional grids,
+ *     fully nonlinearly: the boundary-integral equations of Sec. 2.3 with the
+ *     remaining integrals I^(S) of App. A kept (Eq. (con-V): the expansion
+ *     plus I^(S) is the exact equation) and, over a variable bed, the bed's
+ *     remainder I^(B) of App. B, in their two-dimensional-flow form (Green
+ *     function -ln r; over a flat bed its image, over a variable bed the bed
+ *     as a second boundary with the potential phi_b on it, unless it lies too
+ *     deep to matter: k_1 times the smallest depth beyond 18), iterated to the
+ *     residual tolerance with O(nx^2) quadrature per sweep -- mode
+ *     SBI_MODE_FULL (ensembles do not take it);
  *   - the time step integrates Eq. (prognostic) in its integrating-factor form
  *     (Sec. 2.2) with the classical 4-stage Runge-Kutta scheme of Lawson type
  *     (fixed step), or with the adaptive six-stage fifth-order pair with an
@@ -105,7 +107,7 @@ typedef struct sbi_grid {
                               sweeps per solve (then SBI_WARN_NOT_CONVERGED).
                               Not for ensembles (sbi_batch_init) or
                               sbi_vertical_velocity_noalloc (SBI_ERR_UNSUPPORTED) */
-    int32_t mode;          /* SBI_MODE_ITER (default), SBI_MODE_SA or SBI_MODE_FULL (1D, flat bed) */
+    int32_t mode;          /* SBI_MODE_ITER (default), SBI_MODE_SA or SBI_MODE_FULL (1D) */
     int32_t seed;          /* SBI_SEED_* for the iteration; default SBI_SEED_LINEAR,
                               the initiation of Sec. 2.4.  SBI_SEED_PREV: the linear
                               guess plus the nonlinear part (V* - k tanh(kh) phi_hat,

@@ -153,6 +153,15 @@ struct sbi_ctx {
     void* full_lfl = nullptr;
     void* full_w = nullptr;
     void* full_part = nullptr;
+    // two-boundary form of the fully nonlinear solve (variable beds)
+    void* full_bz = nullptr;
+    void* full_bx = nullptr;
+    void* full_bxx = nullptr;
+    void* full_cm = nullptr;
+    void* full_rb = nullptr;
+    void* full_pb[2] = {nullptr, nullptr};
+    int* full_bed = nullptr;    // [batch] device flags
+    bool full_bed_any = false;
     // mixed precision (SBI_MIXED): the FP32 context that solves the correction
     // equations, in the tail of this context's workspace, on the same stream
     sbi_ctx* inner = nullptr;
@@ -293,9 +302,12 @@ static Layout layout(const sbi_grid* g, int batch) {
                        : 0);
     // fully nonlinear solve (FP64 in both precisions): tables [batch + 3][nx]
     // and [batch][nx], right-hand side and source term [batch][nx], pair
-    // slices [kFullSplitMax][batch][nx]
+    // slices [kFullSplitMax][batch][nx]; for beds kept as a boundary, the bed
+    // geometry (3 tables), its circulant, its right-hand side and two phi_b
+    // iterates [batch][nx], and the per-member flags
     L.bytes_full = g->mode == SBI_MODE_FULL
-                       ? 7 * al((size_t)g->nx * 8 * batch) + al((size_t)kFullSplitMax * g->nx * 8 * batch)
+                       ? 14 * al((size_t)g->nx * 8 * batch) + al((size_t)kFullSplitMax * g->nx * 8 * batch) +
+                             al(sizeof(int) * batch)
                        : 0;
     // mixed precision: the FP32 context's workspace at the end
     if (g->precision == SBI_MIXED) {
@@ -366,20 +378,6 @@ static sbi_status full_tables(sbi_ctx* c);
 static sbi_status set_depth(sbi_ctx* c, const double* depth, double h_ref) {
     const sbi_grid& g = c->grid;
     const size_t npt = (size_t)g.nx * g.ny;
-    if (g.mode == SBI_MODE_FULL) {
-        // the fully nonlinear solve covers flat beds only: refuse a variable
-        // one before anything changes
-        for (int b = 0; b < c->batch; ++b) {
-            const double* d = depth + b * npt;
-            for (size_t i = 0; i < npt; ++i)
-                if (!std::isfinite(d[i]) || !(d[i] > 0.0)) return std::isfinite(d[i]) ? SBI_ERR_INVALID_ARG
-                                                                                      : SBI_ERR_NONFINITE;
-            const double dmax = *std::max_element(d, d + npt);
-            const double h = h_ref > 0.0 ? h_ref : dmax;
-            for (size_t i = 0; i < npt; ++i)
-                if (d[i] != h) return SBI_ERR_UNSUPPORTED;
-        }
-    }
     std::vector<double> delta(npt * c->batch);
     c->href.assign(c->batch, 0.0);
     c->vd = false;
@@ -405,7 +403,31 @@ static sbi_status set_depth(sbi_ctx* c, const double* depth, double h_ref) {
     std::vector<char> dv = to_prec(delta.data(), delta.size(), c->fp64);
     SBI_HIP(hipMemcpyAsync(c->phys[P_DELTA], dv.data(), dv.size(), hipMemcpyHostToDevice, c->stream));
     SBI_HIP(hipMemcpyAsync(c->href_dev, c->href.data(), sizeof(double) * c->batch, hipMemcpyHostToDevice, c->stream));
-    if (g.mode == SBI_MODE_FULL) SBI_TRY(full_tables(c));
+    if (g.mode == SBI_MODE_FULL) {
+        // the fully nonlinear solve keeps a variable bed as a boundary of its
+        // own unless it is too deep to matter (k_1 times the smallest depth
+        // beyond 18, where the image form drops the image); heights b = -h + delta
+        std::vector<int> bed(c->batch, 0);
+        std::vector<double> bz(npt * c->batch);
+        const double k1 = 2.0 * M_PI / g.lx;
+        c->full_bed_any = false;
+        for (int b = 0; b < c->batch; ++b) {
+            bool var = false;
+            double dmax = 0.0;
+            for (size_t i = 0; i < npt; ++i) {
+                const double dl = delta[b * npt + i];
+                var = var || dl != 0.0;
+                dmax = std::max(dmax, dl);
+                bz[b * npt + i] = -c->href[b] + dl;
+            }
+            bed[b] = var && !(k1 * (c->href[b] - dmax) > 18.0);
+            c->full_bed_any = c->full_bed_any || bed[b];
+        }
+        SBI_HIP(hipMemcpyAsync(c->full_bz, bz.data(), sizeof(double) * bz.size(), hipMemcpyHostToDevice, c->stream));
+        SBI_HIP(hipMemcpyAsync(c->full_bed, bed.data(), sizeof(int) * c->batch, hipMemcpyHostToDevice, c->stream));
+        SBI_TRY(full_tables(c));
+        SBI_HIP(hipStreamSynchronize(c->stream));  // the host vectors above go out of scope
+    }
     SBI_HIP(hipStreamSynchronize(c->stream));
     if (c->inner) SBI_TRY(set_depth(c->inner, depth, h_ref));
     return SBI_OK;
@@ -524,7 +546,15 @@ static sbi_status ctx_setup(sbi_ctx* c, const sbi_grid* g, int32_t batch, const 
         c->full_rhs = p + 4 * tb;
         c->full_lfl = p + 5 * tb;
         c->full_w = p + 6 * tb;
-        c->full_part = p + 7 * tb;
+        c->full_bz = p + 7 * tb;
+        c->full_bx = p + 8 * tb;
+        c->full_bxx = p + 9 * tb;
+        c->full_cm = p + 10 * tb;
+        c->full_rb = p + 11 * tb;
+        c->full_pb[0] = p + 12 * tb;
+        c->full_pb[1] = p + 13 * tb;
+        c->full_part = p + 14 * tb;
+        c->full_bed = reinterpret_cast<int*>(p + 14 * tb + al((size_t)kFullSplitMax * g->nx * 8 * batch));
     }
     c->col_C = L.C;
     gd.col_C = L.C;
@@ -1598,6 +1628,12 @@ static FullParams full_params(sbi_ctx* c) {
     p.vfinal = PHYS(PF_V);
     p.ctl = c->ctl;
     p.max_sweeps = c->grid.max_sweeps;
+    p.bed = c->full_bed_any ? c->full_bed : nullptr;
+    p.bz = c->full_bz;
+    p.bx = c->full_bx;
+    p.bxx = c->full_bxx;
+    p.cm = c->full_cm;
+    p.rb = c->full_rb;
     // source-point slices: enough workgroups to fill the GPU (about 256)
     const int tiles = (p.n + 255) / 256;
     p.nsplit = std::max(1, std::min(kFullSplitMax, 256 / std::max(1, tiles * c->batch)));
@@ -1607,7 +1643,10 @@ static FullParams full_params(sbi_ctx* c) {
 static sbi_status full_tables(sbi_ctx* c) {
     FullParams p = full_params(c);
     c->st.launches += 1;
-    return hip_ok(launch_full(c->fp64, p, FULL_TABLES, c->stream));
+    SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_TABLES, c->stream)));
+    if (!c->full_bed_any) return SBI_OK;
+    c->st.launches += 1;
+    return hip_ok(launch_full(c->fp64, p, FULL_BEDGEOM, c->stream));  // b_x, b_xx from the d1, d2 tables
 }
 
 static sbi_status full_solve(sbi_ctx* c, const void* eta_phys, double tol) {
@@ -1634,9 +1673,19 @@ static sbi_status full_solve(sbi_ctx* c, const void* eta_phys, double tol) {
     SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_GEOM, c->stream)));
     SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_DOUBLE, c->stream)));
     SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_RHS, c->stream)));
+    const bool bed = c->full_bed_any;
+    if (bed) {
+        // the bed's right-hand side -D_BS[phi_s] of the two-boundary members
+        c->st.launches += 2;
+        SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_RHSB, c->stream)));
+        SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_RB, c->stream)));
+    }
     // launch n: the pair pass decides from the residual of launch n - 1 and
     // forms (S - S0)[V_n]; the apply pass forms V_(n+1) and its residual.
-    // V_0 = 0, V_n lives in vbuf[n & 1]; the host polls every few launches.
+    // Two-boundary members first update phi_b (the bed pass, which then
+    // decides, and the phi_b pass), and their surface pass runs from the first
+    // launch (phi_b is not zero there).  V_0 = 0, V_n lives in vbuf[n & 1],
+    // phi_b of launch n in pb[n & 1]; the host polls every few launches.
     const int M = c->grid.max_sweeps;
     constexpr int kChunk = 8;
     for (int n0 = 0; n0 <= M; n0 += kChunk) {
@@ -1644,11 +1693,24 @@ static sbi_status full_solve(sbi_ctx* c, const void* eta_phys, double tol) {
             p.sweep = n;
             p.vin = n == 0 ? nullptr : p.vbuf[n & 1];
             p.vout = const_cast<void*>(p.vbuf[(n + 1) & 1]);
-            c->st.launches += n == 0 ? 2 : 3;
-            if (n > 0) {
+            p.pbin = n == 0 ? nullptr : c->full_pb[n & 1];
+            p.pbout = c->full_pb[(n + 1) & 1];
+            p.slices = n > 0 || bed;
+            if (bed) {
                 ProfScope ps_(c, K_FULL_PAIRS);
+                if (n > 0) {
+                    c->st.launches += 1;
+                    SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_BED, c->stream)));
+                }
+                c->st.launches += 1;
+                SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_PB, c->stream)));
+            }
+            if (p.slices) {
+                ProfScope ps_(c, K_FULL_PAIRS);
+                c->st.launches += 1;
                 SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_SINGLE, c->stream)));
             }
+            c->st.launches += 2;
             ProfScope ps2_(c, K_FULL_APPLY);
             SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_COMBINE, c->stream)));
             SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_APPLY, c->stream)));

@@ -1,7 +1,7 @@
-// sbi_full.hip -- the fully nonlinear W solve of one-dimensional grids over a
-// flat bed: the surface boundary-integral equation of Sec. 2.3 with the
-// remaining integrals I^(S) of App. A kept (Eq. con-V: V = sum_j V^(j) +
-// I^(S), whose sum is the exact equation).
+// sbi_full.hip -- the fully nonlinear W solve of one-dimensional grids: the
+// boundary-integral equations of Sec. 2.3 with the remaining integrals I^(S)
+// of App. A kept (Eq. con-V: V = sum_j V^(j) + I^(S), whose sum is the exact
+// equation) and, over a variable bed, the bed's remainder I^(B) of App. B.
 //
 // Two-dimensional flow (one horizontal dimension): Green function -ln r with
 // the image of the source in the bed z = -h, jump coefficient pi; for the
@@ -20,6 +20,21 @@
 // is O(n^2) per application: every kernel evaluates point pairs, split over
 // workgroups along both the evaluation and the source points.  Deep water
 // (k_1 h > 18, k_1 = 2 pi / L) drops the image terms.
+//
+// Over a variable bed z = b(x) = -h + delta(x) the image no longer applies; the
+// bed is a boundary of its own with the potential phi_b on it (dphi/dn = 0):
+//
+//   S[V] = pi phi_s + D_SS[phi_s] + D_SB[phi_b]       at the surface points,
+//   pi phi_b = S_BS[V] - D_BS[phi_s] - D_BB[phi_b]     at the bed points,
+//
+// (S, D without image; D_XY the double layer of boundary Y seen from the
+// points of X, outward normals (-eta_x, 1) and (b_x, -1) times ds/dx).  A
+// sweep updates phi_b from the bed equation with V_n, then
+// V_(n+1) = S0^-1 [pi phi_s + D_SS[phi_s] + D_SB[phi_b] - (S - S_flat)[V_n]]
+//           + S0^-1 (S0 - S_flat)[V_n],
+// S0 the image form's flat operator, S_flat = pi / |k| that of the flat surface
+// alone.  A bed too deep to matter (k_1 times the smallest depth beyond 18)
+// keeps the image form, which then drops the image.
 //
 // One object per precision (SBI_REAL): fields and the pair arithmetic run in
 // that type; the circulant tables, the slices of the pair sums and every
@@ -47,7 +62,8 @@ __device__ __forceinline__ bool full_deep(const FullParams& p, int m) {
 }
 
 // --- tables: S0^-1 (per member: its depth), eta_x and eta_xx circulants,
-// sin^2(pi j / n).  c[j] = (1/n) sum_m s(k_m) cos(2 pi m j / n) with
+// sin^2(pi j / n), and the circulant cm of S0^-1 (S0 - S_flat) (multiplier
+// exp(-2|k|h) / (1 + exp(-2|k|h))).  c[j] = (1/n) sum_m s(k_m) cos(2 pi m j / n) with
 // s = |k| / (pi (1 + exp(-2 |k| h))), k_m the m-th discrete wavenumber (the
 // Nyquist mode included); d1[j] = (1/n) sum_(0<m<n/2) (-2 k_m) sin(2 pi m j / n)
 // (the Nyquist mode drops out of a first derivative of a real field);
@@ -61,21 +77,24 @@ __global__ void __launch_bounds__(kFullThreads) k_full_tables(const FullParams p
     const double dk = 2.0 * M_PI / p.lx;
     const bool deep = full_deep(p, m);
     const double h = p.href[m];
-    double c = 0.0, d1 = 0.0, d2 = 0.0;
+    double c = 0.0, cm = 0.0, d1 = 0.0, d2 = 0.0;
     for (int q = 1; q < n; ++q) {
         const int qq = q <= n / 2 ? q : n - q;
         const double k = dk * qq;
         // angle 2 pi q j / n reduced exactly in integers
         const long long r = ((long long)q * j) % n;
         const double cs = cospi(2.0 * (double)r / n);
-        const double s = k / (M_PI * (1.0 + (deep ? 0.0 : exp(-2.0 * k * h))));
+        const double e2 = deep ? 0.0 : exp(-2.0 * k * h);
+        const double s = k / (M_PI * (1.0 + e2));
         c += s * cs;
+        cm += e2 / (1.0 + e2) * cs;  // S0^-1 (S0 - S_flat): exp(-2|k|h) / (1 + exp(-2|k|h))
         if (m == 0) {
             d2 -= k * k * cs;
             if (q < n / 2) d1 -= 2.0 * k * sinpi(2.0 * (double)r / n);
         }
     }
     static_cast<double*>(p.c0)[(long long)m * n + j] = c / n;
+    if (p.cm) static_cast<double*>(p.cm)[(long long)m * n + j] = cm / n;
     {
         // the flat image's single-layer term 1/2 ln(sin^2(pi j / n) + sinh^2(2 pi h / L)) of this member
         const double sn = sinpi((double)j / n), sh = deep ? 0.0 : sinh(2.0 * M_PI * h / p.lx);
@@ -128,6 +147,34 @@ __global__ void __launch_bounds__(kFullThreads) k_full_geom(const FullParams p) 
     }
 }
 
+// --- b_x, b_xx of each member's bed (FP64 heights bz) at set-up
+template <typename R>
+__global__ void __launch_bounds__(kFullThreads) k_full_bedgeom(const FullParams p) {
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * kOutPerBlock + t / kLanes;
+    const int l = t % kLanes;
+    const int m = blockIdx.z;
+    const int n = p.n;
+    const double* bz = static_cast<const double*>(p.bz) + (long long)m * n;
+    const double* d1 = static_cast<const double*>(p.d1);
+    const double* d2 = static_cast<const double*>(p.d2);
+    double a1 = 0.0, a2 = 0.0;
+    if (i < n)
+        for (int j = l; j < n; j += kLanes) {
+            const int d = (i - j + n) & (n - 1);
+            a1 += d1[d] * bz[j];
+            a2 += d2[d] * bz[j];
+        }
+    a1 = lane_fold(a1);
+    a2 = lane_fold(a2);
+    if (i < n && l == 0) {
+        static_cast<double*>(p.bx)[(long long)m * n + i] = a1;
+        static_cast<double*>(p.bxx)[(long long)m * n + i] = a2;
+    }
+}
+
+__device__ __forceinline__ bool full_bed(const FullParams& p, int m) { return p.bed && p.bed[m]; }
+
 // Decision of launch `sweep` from the residual of the previous one (the
 // iteration mode's rules); every workgroup decides alike, the leader records.
 __device__ __forceinline__ bool full_decided(const FullParams& p, Ctl* ctl, bool leader) {
@@ -145,12 +192,15 @@ __device__ __forceinline__ bool full_decided(const FullParams& p, Ctl* ctl, bool
     return false;
 }
 
-// --- pair sums over a slice of the source points.  KIND 0: the double layer
-// D[phi_s]; KIND 1: the single layer (S - S0)[V].  Partial sums go to
-// part[split][member][point]; the consumer adds the slices in order.
+// --- pair sums over a slice of the source points, at the surface points.
+// KIND 0: the double layer D[phi_s]; KIND 1: the single layer (S - S0)[V_n]
+// (image form) or (S - S_flat)[V_n] - D_SB[phi_b] with the phi_b of this
+// sweep (two-boundary form; V_n may be absent at the first sweep).  Partial
+// sums go to part[split][member][point]; the consumer adds the slices in order.
 template <typename R, int KIND>
 __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p) {
     __shared__ R te[kFullThreads], tex[kFullThreads], tsrc[kFullThreads];
+    __shared__ double tbz[kFullThreads], tbx[kFullThreads], tpb[kFullThreads];
     const int t = threadIdx.x;
     const int i = blockIdx.x * kFullThreads + t;
     const int split = blockIdx.y;
@@ -164,11 +214,21 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
     const long long mo = m * p.s_phys;
     const R* eta = static_cast<const R*>(p.eta) + mo;
     const R* ex = static_cast<const R*>(p.ex) + mo;
-    const R* src = static_cast<const R*>(KIND == 0 ? p.phi : p.vin) + mo;
+    const void* sv = KIND == 0 ? p.phi : p.vin;
+    const bool hasv = sv != nullptr;
+    const R* src = hasv ? static_cast<const R*>(sv) + mo : nullptr;
     const double* s2 = static_cast<const double*>(p.s2);
     const double* lfl = static_cast<const double*>(p.lfl) + (long long)m * n;
     const R pl = R(M_PI / p.lx);
+    const double pld = M_PI / p.lx;
     const bool deep = full_deep(p, m);
+    const bool bedm = full_bed(p, m);
+    const bool img = !deep && !bedm;                 // the image form keeps the bed's image
+    const bool hasb = KIND == 1 && bedm;             // -D_SB[phi_b] of the two-boundary form
+    const long long mb = (long long)m * n;
+    const double* bz = hasb ? static_cast<const double*>(p.bz) + mb : nullptr;
+    const double* bxs = hasb ? static_cast<const double*>(p.bx) + mb : nullptr;
+    const double* pbs = hasb ? static_cast<const double*>(p.pbout) + mb : nullptr;
     const R b2h = R(2.0 * M_PI * p.href[m] / p.lx);  // 2 pi h / L
     // this point's values
     const bool on = i < n;
@@ -183,7 +243,12 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
         if (jl < jend) {
             te[t] = eta[jl];
             tex[t] = ex[jl];
-            tsrc[t] = src[jl];
+            tsrc[t] = hasv ? src[jl] : R(0);
+            if (hasb) {
+                tbz[t] = bz[jl];
+                tbx[t] = bxs[jl];
+                tpb[t] = pbs[jl];
+            }
         }
         __syncthreads();
         const int jn = min(kFullThreads, jend - j0);
@@ -192,6 +257,16 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
             const int j = j0 + jj;
             const int d = (j - i + n) & (n - 1);
             const R sa2 = R(s2[d]);                       // sin^2(pi (x_j - x_i) / L)
+            if (hasb) {
+                // the bed source (x_j, b_j): -D_SB = Im[(pi/L) cot(a + i b) (1 + i b_x,j)],
+                // b = pi (b_j - eta_i) / L (the bed lies below every surface point)
+                const R sh = sinh(R(pld * (tbz[jj] - (double)etai)));
+                const R ch = sqrt(R(1) + sh * sh);
+                const R s2a = sinpi(R(2) * R(d) / R(n));
+                const R kb = pl * (R(-2) * sh * ch + s2a * R(tbx[jj])) / (R(2) * (sa2 + sh * sh));
+                acc += (double)kb * tpb[jj];
+            }
+            if (KIND == 1 && !hasv) continue;
             // sinh of the scaled elevation difference, formed from the difference
             // itself (from exponentials of each point it would lose all relative
             // accuracy for nearby points)
@@ -200,7 +275,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
             if (KIND == 1) {
                 // -1/2 ln(1 + sinh^2 / sin^2); its limit -1/2 ln(1 + eta_x^2) at j = i
                 kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb / sa2);
-                if (!deep) {
+                if (img) {
                     // image minus flat image: -1/2 ln(sin^2 + sinh^2(pi (eta_i + eta_j + 2h) / L))
                     // + 1/2 ln(sin^2 + sinh^2(2 pi h / L))
                     const R shp = sinh(pl * (te[jj] + etai) + b2h);
@@ -217,7 +292,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
                     const R den = R(2) * (sa2 + shb * shb);
                     kv = pl * (R(-2) * shb * chb + s2a * tex[jj]) / den;
                 }
-                if (!deep) {
+                if (img) {
                     // the image partner: b' = pi (eta_i + eta_j + 2h) / L
                     const R shp = sinh(pl * (te[jj] + etai) + b2h);
                     const R chp = sqrt(R(1) + shp * shp);
@@ -239,6 +314,121 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
     static_cast<double*>(p.part)[((long long)split * p.batch + m) * n + i] = out;
 }
 
+// --- pair sums at the bed points of two-boundary members, over a slice of
+// the source points.  KIND 2: D_BS[phi_s] (surface sources); KIND 3:
+// S_BS[V_n] - D_BB[phi_b] (surface and bed sources, phi_b of this sweep),
+// which also decides the sweep.  With a = pi (x_j - x_i) / L and b the scaled
+// height difference pi (y_j - y_i) / L of source and evaluation point:
+// G = -1/2 ln(4 (sin^2 a + sinh^2 b)); the double layer of a surface source is
+// Im[(pi/L) cot(a + i b) (1 + i eta_x,j)], that of a bed source
+// -Im[(pi/L) cot(a + i b) (1 + i b_x,j)], with the curvature limit
+// -b_xx / (2 (1 + b_x^2)) at coincident bed points.
+template <typename R, int KIND>
+__global__ void __launch_bounds__(kFullThreads) k_full_bpairs(const FullParams p) {
+    __shared__ R te[kFullThreads], tex[kFullThreads], tsrc[kFullThreads];
+    __shared__ double tbz[kFullThreads], tbx[kFullThreads], tpb[kFullThreads];
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * kFullThreads + t;
+    const int split = blockIdx.y;
+    const int m = blockIdx.z;
+    const int n = p.n;
+    if (KIND == 3) {
+        Ctl* ctl = p.ctl + m;
+        const bool leader = blockIdx.x == 0 && blockIdx.y == 0 && t == 0;
+        if (full_decided(p, ctl, leader)) return;  // workgroup-uniform
+    }
+    if (!full_bed(p, m)) return;
+    const long long mo = m * p.s_phys, mb = (long long)m * n;
+    const R* eta = static_cast<const R*>(p.eta) + mo;
+    const R* ex = static_cast<const R*>(p.ex) + mo;
+    const R* src = static_cast<const R*>(KIND == 2 ? p.phi : p.vin) + mo;
+    const double* bz = static_cast<const double*>(p.bz) + mb;
+    const double* bxs = static_cast<const double*>(p.bx) + mb;
+    const double* pbs = KIND == 3 ? static_cast<const double*>(p.pbin) + mb : nullptr;
+    const double* s2 = static_cast<const double*>(p.s2);
+    const R pl = R(M_PI / p.lx);
+    const double pld = M_PI / p.lx;
+    const bool on = i < n;
+    const double bzi = on ? bz[i] : 0.0;
+    double acc = 0.0;
+    const int chunk = (n + gridDim.y - 1) / gridDim.y;
+    const int jbeg = split * chunk, jend = min(n, jbeg + chunk);
+    for (int j0 = jbeg; j0 < jend; j0 += kFullThreads) {
+        __syncthreads();
+        const int jl = j0 + t;
+        if (jl < jend) {
+            te[t] = eta[jl];
+            tex[t] = ex[jl];
+            tsrc[t] = src[jl];
+            if (KIND == 3) {
+                tbz[t] = bz[jl];
+                tbx[t] = bxs[jl];
+                tpb[t] = pbs[jl];
+            }
+        }
+        __syncthreads();
+        const int jn = min(kFullThreads, jend - j0);
+        if (!on) continue;
+        for (int jj = 0; jj < jn; ++jj) {
+            const int j = j0 + jj;
+            const int d = (j - i + n) & (n - 1);
+            const R sa2 = R(s2[d]);
+            const R s2a = sinpi(R(2) * R(d) / R(n));
+            // the surface source (x_j, eta_j) seen from the bed point (x_i, b_i)
+            const R sh = sinh(R(pld * ((double)te[jj] - bzi)));
+            const R den = R(2) * (sa2 + sh * sh);
+            if (KIND == 2) {
+                const R ch = sqrt(R(1) + sh * sh);
+                acc += (double)(pl * (R(-2) * sh * ch + s2a * tex[jj]) / den) * (double)tsrc[jj];
+            } else {
+                acc += (double)(R(-0.5) * log(R(2) * den)) * (double)tsrc[jj];
+                if (j != i) {
+                    // minus the bed's double layer at (x_j, b_j)
+                    const R shb = sinh(R(pld * (tbz[jj] - bzi)));
+                    const R chb = sqrt(R(1) + shb * shb);
+                    const R denb = R(2) * (sa2 + shb * shb);
+                    acc += (double)(pl * (R(-2) * shb * chb + s2a * R(tbx[jj])) / denb) * tpb[jj];
+                }
+            }
+        }
+    }
+    if (!on) return;
+    const double dx = p.lx / n;
+    double out = acc * dx;
+    if (KIND == 3 && i >= jbeg && i < jend) {
+        // minus the diagonal of the bed's double layer: + b_xx / (2 (1 + b_x^2)) phi_b
+        const double bxi = bxs[i], bxxi = static_cast<const double*>(p.bxx)[mb + i];
+        out += dx * bxxi / (2.0 * (1.0 + bxi * bxi)) * pbs[i];
+    }
+    static_cast<double*>(p.part)[((long long)split * p.batch + m) * n + i] = out;
+}
+
+// --- rb = -D_BS[phi_s] of the two-boundary members (slices added in order)
+template <typename R>
+__global__ void k_full_rb(const FullParams p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.z;
+    if (i >= p.n || !full_bed(p, m)) return;
+    double a = 0.0;
+    for (int s = 0; s < p.nsplit; ++s) a -= static_cast<const double*>(p.part)[((long long)s * p.batch + m) * p.n + i];
+    static_cast<double*>(p.rb)[(long long)m * p.n + i] = a;
+}
+
+// --- phi_b of the next sweep, (rb + S_BS[V_n] - D_BB[phi_b]) / pi, for the
+// undecided two-boundary members (no bed pass at the first sweep: V_0 = 0,
+// phi_b = 0)
+template <typename R>
+__global__ void k_full_pb(const FullParams p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.z;
+    if (i >= p.n || !full_bed(p, m) || p.ctl[m].done) return;
+    const long long o = (long long)m * p.n + i;
+    double a = static_cast<const double*>(p.rb)[o];
+    if (p.pbin)
+        for (int s = 0; s < p.nsplit; ++s) a += static_cast<const double*>(p.part)[((long long)s * p.batch + m) * p.n + i];
+    static_cast<double*>(p.pbout)[o] = a / M_PI;
+}
+
 // --- rhs = pi phi_s + D[phi_s] (slices added in order)
 template <typename R>
 __global__ void k_full_rhs(const FullParams p) {
@@ -251,8 +441,9 @@ __global__ void k_full_rhs(const FullParams p) {
     static_cast<double*>(p.rhs)[(long long)m * p.n + i] = a;
 }
 
-// --- w = rhs - (S - S0)[V_n] (the slices of the pair pass, in order; w = rhs
-// at the first sweep, from V_0 = 0)
+// --- w = rhs - (S - S0)[V_n], or rhs - (S - S_flat)[V_n] + D_SB[phi_b] (the
+// slices of the surface pass, in order; w = rhs at the first sweep of the
+// image form, from V_0 = 0)
 template <typename R>
 __global__ void k_full_combine(const FullParams p) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -261,12 +452,13 @@ __global__ void k_full_combine(const FullParams p) {
     if (p.ctl[m].done) return;  // decided by this sweep's pair pass
     const long long o = (long long)m * p.n + i;
     double w = static_cast<const double*>(p.rhs)[o];
-    if (p.vin)
+    if (p.slices)
         for (int s = 0; s < p.nsplit; ++s) w -= static_cast<const double*>(p.part)[((long long)s * p.batch + m) * p.n + i];
     static_cast<double*>(p.w)[o] = w;
 }
 
-// --- V_(n+1) = S0^-1 w and the residual maxima max|V_(n+1) - V_n|,
+// --- V_(n+1) = S0^-1 w (+ S0^-1 (S0 - S_flat)[V_n] in the two-boundary form)
+// and the residual maxima max|V_(n+1) - V_n|,
 // max|V_(n+1)| into the member's slot `sweep`
 template <typename R>
 __global__ void __launch_bounds__(kFullThreads) k_full_apply(const FullParams p) {
@@ -283,6 +475,12 @@ __global__ void __launch_bounds__(kFullThreads) k_full_apply(const FullParams p)
     double acc = 0.0;
     if (i < n)
         for (int j = l; j < n; j += kLanes) acc += c[(i - j + n) & (n - 1)] * w[j];
+    if (i < n && p.vin && full_bed(p, m)) {
+        // + S0^-1 (S0 - S_flat)[V_n] of the two-boundary form
+        const double* cm = static_cast<const double*>(p.cm) + (long long)m * n;
+        const R* vn = static_cast<const R*>(p.vin) + mo;
+        for (int j = l; j < n; j += kLanes) acc += cm[(i - j + n) & (n - 1)] * (double)vn[j];
+    }
     acc = lane_fold(acc);
     unsigned long long nu = 0ull, de = 0ull;
     if (i < n && l == 0) {
@@ -340,6 +538,21 @@ template <> hipError_t launch_full_t<Real>(const FullParams& p, int what, hipStr
             break;
         case FULL_SELECT:
             hipLaunchKernelGGL(k_full_select<Real>, dim3(tiles, 1, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_BEDGEOM:
+            hipLaunchKernelGGL(k_full_bedgeom<Real>, dim3(outs, 1, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_RHSB:
+            hipLaunchKernelGGL((k_full_bpairs<Real, 2>), dim3(tiles, p.nsplit, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_RB:
+            hipLaunchKernelGGL(k_full_rb<Real>, dim3(tiles, 1, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_BED:
+            hipLaunchKernelGGL((k_full_bpairs<Real, 3>), dim3(tiles, p.nsplit, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_PB:
+            hipLaunchKernelGGL(k_full_pb<Real>, dim3(tiles, 1, p.batch), dim3(kFullThreads), 0, s, p);
             break;
         default:
             return hipErrorInvalidValue;

@@ -196,11 +196,15 @@ struct DiagParams {
     int nblk;
 };
 
-// Fully nonlinear W solve of one-dimensional flat-bed grids (sbi_full.hip):
-// the operands of its kernels.  Physical fields are [batch][n] with member
+// Fully nonlinear W solve of one-dimensional grids (sbi_full.hip): the
+// operands of its kernels.  Physical fields are [batch][n] with member
 // stride s_phys; FP64 tables: c0 [batch][n] (S0^-1 circulant per member), d1,
 // d2, s2 [n]; FP64 part [nsplit][batch][n] holds the slices of a pair pass and
-// rhs [batch][n] the right-hand side.
+// rhs [batch][n] the right-hand side.  Members whose bed is kept as a boundary
+// of its own (bed[m] = 1: a variable bed not too deep to matter) use the
+// two-boundary form: bed geometry bz, bx, bxx, the circulant cm of
+// S0^-1 (S0 - S_flat), the bed right-hand side rb = -D_BS[phi_s] and the bed
+// potential phi_b of the sweeps in pbuf (all FP64 [batch][n]).
 struct FullParams {
     int n, batch, nsplit;
     double lx;
@@ -225,8 +229,20 @@ struct FullParams {
     Ctl* ctl;
     int sweep, max_sweeps;
     double tol;
+    const int* bed;       // [batch] 1: two-boundary form (null: no member)
+    void* bz;
+    void* bx;
+    void* bxx;
+    void* cm;
+    void* rb;
+    const void* pbin;     // phi_b of this sweep (null: phi_b = 0)
+    void* pbout;          // phi_b of the next sweep
+    int slices;           // the combine pass subtracts the slices of this sweep's surface pass
 };
-enum { FULL_TABLES = 0, FULL_GEOM, FULL_DOUBLE, FULL_RHS, FULL_SINGLE, FULL_COMBINE, FULL_APPLY, FULL_SELECT };
+enum {
+    FULL_TABLES = 0, FULL_GEOM, FULL_DOUBLE, FULL_RHS, FULL_SINGLE, FULL_COMBINE, FULL_APPLY, FULL_SELECT,
+    FULL_BEDGEOM, FULL_RHSB, FULL_RB, FULL_BED, FULL_PB
+};
 
 struct Twiddles {
     const void* tx;   // length nx
