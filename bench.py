@@ -29,8 +29,10 @@ fifth/fourth-order pair over four peak periods ("adaptive", at the error bound
 fixed-step equivalents of T_p/64), the 1D submerged-bar tank driven by
 the pneumatic wavemaker and damping pressure ("c2-tank", beside relaxation
 zones), the ragged C4
-ensemble (96 members, SA mode, FP32) in one graph, and the 512^2 flat
-crossing sea in FP32 beside FP64 with the FP32 error (max |eta|, energy drift).
+ensemble (96 members, SA mode, FP32) in one graph, the 512^2 flat
+crossing sea in FP32 beside FP64 with the FP32 error (max |eta|, energy drift),
+and the fully nonlinear W (remaining integrals kept) stepping a steep 1D sea of
+4096 points over a flat bed ("full-1d") and over two bars ("full-1d-bed").
 
 Prints ONE JSON line.  `roofline` is for the dominant kernel of the plain
 form, its algorithmic bytes per launch divided by its average launch time from
@@ -411,12 +413,15 @@ def run_c2_tank(args, dev):
     return r
 
 
-def run_full_1d(args, dev):
+def run_full_1d(args, dev, bed=False):
     """The fully nonlinear W (the remaining integrals of App. A kept) stepping a
     steep one-dimensional random sea: N = 4096 over a flat bed (k_p h = 1, 32
     points per peak wavelength, k_p a up to ~0.25), FP64, W tol 1e-10, eager
     steps of T_p/64 after one warm-up step; every pair pass evaluates the
-    single-layer kernel at N^2 point pairs."""
+    single-layer kernel at N^2 point pairs.  bed: over two Gaussian bars
+    (depth down to 0.5, the bed's remainder I^(B) kept as well): a sweep then
+    evaluates 4 N^2 pairs (bed and surface passes, each over surface and bed
+    sources), the first of a solve N^2."""
     import numpy as np
     import torch
 
@@ -429,6 +434,10 @@ def run_full_1d(args, dev):
     eta0 = si.narrowband_random(gs, 4096, amp=0.12)
     phi0 = si.narrowband_random(gs, 4097, amp=0.24)
     depth = np.ones((1, n))
+    if bed:
+        x = np.arange(n) * lx / n
+        depth = (1.0 - 0.5 * (np.exp(-((x - 0.3 * lx) / (0.08 * lx)) ** 2)
+                              + 0.5 * np.exp(-((x - 0.7 * lx) / (0.12 * lx)) ** 2)))[None]
     dt = 2 * math.pi / math.sqrt(math.tanh(1.0)) / 64
     s = Solver(n, 1, lx, 1.0, depth, device=dev, mode="full", max_sweeps=100)
     eta = torch.tensor(eta0[None], dtype=torch.float64, device=dev)
@@ -447,12 +456,13 @@ def run_full_1d(args, dev):
     # a solve of s sweeps runs s - 1 working pair passes (the launch that
     # decides returns at once): each evaluates the kernel at n^2 point pairs
     working = info["sweeps_total"] - info["solves"]
+    pairs = (4 * working + info["solves"]) * n * n if bed else working * n * n
     return dict(value=n * args.full_steps / el, ms_per_step=1e3 * el / args.full_steps, status=st, points=n,
                 steps=args.full_steps, sweeps_mean=info["sweeps_total"] / max(info["solves"], 1),
                 pair_pass_us=round(1e3 * pairs_ms / max(working, 1), 2),
                 apply_ms_per_step=round(apply_ms / args.full_steps, 3),
-                pairs_per_s=float(f"{working * n * n / max(1e-3 * pairs_ms, 1e-12):.4g}"),
-                max_eta=float(np.abs(eta.cpu().numpy()).max()))
+                pairs_per_s=float(f"{pairs / max(1e-3 * pairs_ms, 1e-12):.4g}"),
+                max_eta=float(np.abs(eta.cpu().numpy()).max()), bed="two bars, depth 0.5-1" if bed else "flat")
 
 
 def run_c4(args, dev):
@@ -535,7 +545,7 @@ def main():
     ap.add_argument("--full-steps", type=int, default=8)
     ap.add_argument("--forms",
                     default="plain,plain-relaxed,batched+prev,batched+learned,plain-fp32,plain-mixed,adaptive,"
-                            "c2-tank,c4,c3-precision,full-1d")
+                            "c2-tank,c4,c3-precision,full-1d,full-1d-bed")
     ap.add_argument("--accel", default="anderson", choices=["anderson", "none"],
                     help="iteration of the W solves: Anderson-mixed (default) or plain relaxed sweeps")
     ap.add_argument("--adaptive-periods", type=float, default=4.0)
@@ -611,6 +621,8 @@ def main():
         out_forms["c4"] = run_c4(args, dev)
     if "full-1d" in forms:
         out_forms["full-1d"] = run_full_1d(args, dev)
+    if "full-1d-bed" in forms:
+        out_forms["full-1d-bed"] = run_full_1d(args, dev, bed=True)
     if "c3-precision" in forms:
         out_forms["c3-precision"] = run_c3_precision(args, dev)
     for f, d in out_forms.items():

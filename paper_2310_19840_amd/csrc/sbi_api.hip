@@ -162,6 +162,7 @@ struct sbi_ctx {
     void* full_pb[2] = {nullptr, nullptr};
     int* full_bed = nullptr;    // [batch] device flags
     bool full_bed_any = false;
+    bool full_bed_all = false;  // every member two-boundary: no image-form surface pass
     // mixed precision (SBI_MIXED): the FP32 context that solves the correction
     // equations, in the tail of this context's workspace, on the same stream
     sbi_ctx* inner = nullptr;
@@ -411,6 +412,7 @@ static sbi_status set_depth(sbi_ctx* c, const double* depth, double h_ref) {
         std::vector<double> bz(npt * c->batch);
         const double k1 = 2.0 * M_PI / g.lx;
         c->full_bed_any = false;
+        c->full_bed_all = true;
         for (int b = 0; b < c->batch; ++b) {
             bool var = false;
             double dmax = 0.0;
@@ -422,6 +424,7 @@ static sbi_status set_depth(sbi_ctx* c, const double* depth, double h_ref) {
             }
             bed[b] = var && !(k1 * (c->href[b] - dmax) > 18.0);
             c->full_bed_any = c->full_bed_any || bed[b];
+            c->full_bed_all = c->full_bed_all && bed[b];
         }
         SBI_HIP(hipMemcpyAsync(c->full_bz, bz.data(), sizeof(double) * bz.size(), hipMemcpyHostToDevice, c->stream));
         SBI_HIP(hipMemcpyAsync(c->full_bed, bed.data(), sizeof(int) * c->batch, hipMemcpyHostToDevice, c->stream));
@@ -1695,17 +1698,17 @@ static sbi_status full_solve(sbi_ctx* c, const void* eta_phys, double tol) {
             p.vout = const_cast<void*>(p.vbuf[(n + 1) & 1]);
             p.pbin = n == 0 ? nullptr : c->full_pb[n & 1];
             p.pbout = c->full_pb[(n + 1) & 1];
-            p.slices = n > 0 || bed;
             if (bed) {
                 ProfScope ps_(c, K_FULL_PAIRS);
                 if (n > 0) {
                     c->st.launches += 1;
                     SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_BED, c->stream)));
                 }
-                c->st.launches += 1;
+                c->st.launches += 2;
                 SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_PB, c->stream)));
+                SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_SURF, c->stream)));
             }
-            if (p.slices) {
+            if (n > 0 && !c->full_bed_all) {
                 ProfScope ps_(c, K_FULL_PAIRS);
                 c->st.launches += 1;
                 SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_SINGLE, c->stream)));

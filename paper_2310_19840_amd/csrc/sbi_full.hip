@@ -193,14 +193,12 @@ __device__ __forceinline__ bool full_decided(const FullParams& p, Ctl* ctl, bool
 }
 
 // --- pair sums over a slice of the source points, at the surface points.
-// KIND 0: the double layer D[phi_s]; KIND 1: the single layer (S - S0)[V_n]
-// (image form) or (S - S_flat)[V_n] - D_SB[phi_b] with the phi_b of this
-// sweep (two-boundary form; V_n may be absent at the first sweep).  Partial
-// sums go to part[split][member][point]; the consumer adds the slices in order.
+// KIND 0: the double layer D[phi_s] (every member); KIND 1: the single layer
+// (S - S0)[V_n] of the image-form members.  Partial sums go to
+// part[split][member][point]; the consumer adds the slices in order.
 template <typename R, int KIND>
 __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p) {
     __shared__ R te[kFullThreads], tex[kFullThreads], tsrc[kFullThreads];
-    __shared__ double tbz[kFullThreads], tbx[kFullThreads], tpb[kFullThreads];
     const int t = threadIdx.x;
     const int i = blockIdx.x * kFullThreads + t;
     const int split = blockIdx.y;
@@ -214,21 +212,13 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
     const long long mo = m * p.s_phys;
     const R* eta = static_cast<const R*>(p.eta) + mo;
     const R* ex = static_cast<const R*>(p.ex) + mo;
-    const void* sv = KIND == 0 ? p.phi : p.vin;
-    const bool hasv = sv != nullptr;
-    const R* src = hasv ? static_cast<const R*>(sv) + mo : nullptr;
+    if (KIND == 1 && full_bed(p, m)) return;  // the two-boundary surface pass serves it
+    const R* src = static_cast<const R*>(KIND == 0 ? p.phi : p.vin) + mo;
     const double* s2 = static_cast<const double*>(p.s2);
     const double* lfl = static_cast<const double*>(p.lfl) + (long long)m * n;
     const R pl = R(M_PI / p.lx);
-    const double pld = M_PI / p.lx;
     const bool deep = full_deep(p, m);
-    const bool bedm = full_bed(p, m);
-    const bool img = !deep && !bedm;                 // the image form keeps the bed's image
-    const bool hasb = KIND == 1 && bedm;             // -D_SB[phi_b] of the two-boundary form
-    const long long mb = (long long)m * n;
-    const double* bz = hasb ? static_cast<const double*>(p.bz) + mb : nullptr;
-    const double* bxs = hasb ? static_cast<const double*>(p.bx) + mb : nullptr;
-    const double* pbs = hasb ? static_cast<const double*>(p.pbout) + mb : nullptr;
+    const bool img = !deep && !full_bed(p, m);       // the image form keeps the bed's image
     const R b2h = R(2.0 * M_PI * p.href[m] / p.lx);  // 2 pi h / L
     // this point's values
     const bool on = i < n;
@@ -243,12 +233,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
         if (jl < jend) {
             te[t] = eta[jl];
             tex[t] = ex[jl];
-            tsrc[t] = hasv ? src[jl] : R(0);
-            if (hasb) {
-                tbz[t] = bz[jl];
-                tbx[t] = bxs[jl];
-                tpb[t] = pbs[jl];
-            }
+            tsrc[t] = src[jl];
         }
         __syncthreads();
         const int jn = min(kFullThreads, jend - j0);
@@ -257,16 +242,6 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
             const int j = j0 + jj;
             const int d = (j - i + n) & (n - 1);
             const R sa2 = R(s2[d]);                       // sin^2(pi (x_j - x_i) / L)
-            if (hasb) {
-                // the bed source (x_j, b_j): -D_SB = Im[(pi/L) cot(a + i b) (1 + i b_x,j)],
-                // b = pi (b_j - eta_i) / L (the bed lies below every surface point)
-                const R sh = sinh(R(pld * (tbz[jj] - (double)etai)));
-                const R ch = sqrt(R(1) + sh * sh);
-                const R s2a = sinpi(R(2) * R(d) / R(n));
-                const R kb = pl * (R(-2) * sh * ch + s2a * R(tbx[jj])) / (R(2) * (sa2 + sh * sh));
-                acc += (double)kb * tpb[jj];
-            }
-            if (KIND == 1 && !hasv) continue;
             // sinh of the scaled elevation difference, formed from the difference
             // itself (from exponentials of each point it would lose all relative
             // accuracy for nearby points)
@@ -312,6 +287,76 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
         out += dx * exx / (2.0 * (1.0 + (double)exi * (double)exi)) * (double)src[i];
     }
     static_cast<double*>(p.part)[((long long)split * p.batch + m) * n + i] = out;
+}
+
+// --- the surface pass of the two-boundary members: (S - S_flat)[V_n] (no
+// image; V_n absent at the first sweep) minus D_SB[phi_b] with the phi_b of
+// this sweep, at the surface points over a slice of the source points
+template <typename R>
+__global__ void __launch_bounds__(kFullThreads) k_full_spairs(const FullParams p) {
+    __shared__ R te[kFullThreads], tsrc[kFullThreads];
+    __shared__ double tbz[kFullThreads], tbx[kFullThreads], tpb[kFullThreads];
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * kFullThreads + t;
+    const int split = blockIdx.y;
+    const int m = blockIdx.z;
+    const int n = p.n;
+    {
+        Ctl* ctl = p.ctl + m;
+        const bool leader = blockIdx.x == 0 && blockIdx.y == 0 && t == 0;
+        if (full_decided(p, ctl, leader)) return;  // workgroup-uniform
+    }
+    if (!full_bed(p, m)) return;
+    const long long mo = m * p.s_phys, mb = (long long)m * n;
+    const R* eta = static_cast<const R*>(p.eta) + mo;
+    const R* ex = static_cast<const R*>(p.ex) + mo;
+    const bool hasv = p.vin != nullptr;
+    const R* src = hasv ? static_cast<const R*>(p.vin) + mo : nullptr;
+    const double* bz = static_cast<const double*>(p.bz) + mb;
+    const double* bxs = static_cast<const double*>(p.bx) + mb;
+    const double* pbs = static_cast<const double*>(p.pbout) + mb;
+    const double* s2 = static_cast<const double*>(p.s2);
+    const R pl = R(M_PI / p.lx);
+    const double pld = M_PI / p.lx;
+    const bool on = i < n;
+    const R etai = on ? eta[i] : R(0);
+    const R exi = on ? ex[i] : R(0);
+    double acc = 0.0;
+    const int chunk = (n + gridDim.y - 1) / gridDim.y;
+    const int jbeg = split * chunk, jend = min(n, jbeg + chunk);
+    for (int j0 = jbeg; j0 < jend; j0 += kFullThreads) {
+        __syncthreads();
+        const int jl = j0 + t;
+        if (jl < jend) {
+            te[t] = eta[jl];
+            tsrc[t] = hasv ? src[jl] : R(0);
+            tbz[t] = bz[jl];
+            tbx[t] = bxs[jl];
+            tpb[t] = pbs[jl];
+        }
+        __syncthreads();
+        const int jn = min(kFullThreads, jend - j0);
+        if (!on) continue;
+        for (int jj = 0; jj < jn; ++jj) {
+            const int j = j0 + jj;
+            const int d = (j - i + n) & (n - 1);
+            const R sa2 = R(s2[d]);
+            const R s2a = sinpi(R(2) * R(d) / R(n));
+            // the bed source (x_j, b_j): -D_SB = Im[(pi/L) cot(a + i b) (1 + i b_x,j)],
+            // b = pi (b_j - eta_i) / L (the bed lies below every surface point)
+            const R sh = sinh(R(pld * (tbz[jj] - (double)etai)));
+            const R ch = sqrt(R(1) + sh * sh);
+            acc += (double)(pl * (R(-2) * sh * ch + s2a * R(tbx[jj])) / (R(2) * (sa2 + sh * sh))) * tpb[jj];
+            if (hasv) {
+                // the direct single layer minus the flat one, as in the image form
+                const R shb = sinh(pl * (te[jj] - etai));
+                const R kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb / sa2);
+                acc += (double)kv * (double)tsrc[jj];
+            }
+        }
+    }
+    if (!on) return;
+    static_cast<double*>(p.part)[((long long)split * p.batch + m) * n + i] = acc * (p.lx / n);
 }
 
 // --- pair sums at the bed points of two-boundary members, over a slice of
@@ -452,7 +497,7 @@ __global__ void k_full_combine(const FullParams p) {
     if (p.ctl[m].done) return;  // decided by this sweep's pair pass
     const long long o = (long long)m * p.n + i;
     double w = static_cast<const double*>(p.rhs)[o];
-    if (p.slices)
+    if (p.vin || full_bed(p, m))
         for (int s = 0; s < p.nsplit; ++s) w -= static_cast<const double*>(p.part)[((long long)s * p.batch + m) * p.n + i];
     static_cast<double*>(p.w)[o] = w;
 }
@@ -550,6 +595,9 @@ template <> hipError_t launch_full_t<Real>(const FullParams& p, int what, hipStr
             break;
         case FULL_BED:
             hipLaunchKernelGGL((k_full_bpairs<Real, 3>), dim3(tiles, p.nsplit, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_SURF:
+            hipLaunchKernelGGL(k_full_spairs<Real>, dim3(tiles, p.nsplit, p.batch), dim3(kFullThreads), 0, s, p);
             break;
         case FULL_PB:
             hipLaunchKernelGGL(k_full_pb<Real>, dim3(tiles, 1, p.batch), dim3(kFullThreads), 0, s, p);

@@ -237,11 +237,10 @@ struct FullParams {
     void* rb;
     const void* pbin;     // phi_b of this sweep (null: phi_b = 0)
     void* pbout;          // phi_b of the next sweep
-    int slices;           // the combine pass subtracts the slices of this sweep's surface pass
 };
 enum {
     FULL_TABLES = 0, FULL_GEOM, FULL_DOUBLE, FULL_RHS, FULL_SINGLE, FULL_COMBINE, FULL_APPLY, FULL_SELECT,
-    FULL_BEDGEOM, FULL_RHSB, FULL_RB, FULL_BED, FULL_PB
+    FULL_BEDGEOM, FULL_RHSB, FULL_RB, FULL_BED, FULL_PB, FULL_SURF
 };
 
 struct Twiddles {
