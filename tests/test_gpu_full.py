@@ -192,6 +192,28 @@ def test_full_steps_over_a_bar_match_oracle(gpu):
     assert _rel(p.cpu().numpy().reshape(po.shape), po) < 1e-10
 
 
+def test_full_c1_over_one_period_matches_oracle(gpu):
+    """The Gaussian-bump configuration (N = 256, bump 0.3 h0, Stokes wave
+    k0 a = 0.05) stepped one wave period (64 RK4 steps) with the fully
+    nonlinear W over its variable bed: the oracle's sweeps and end state."""
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    cfg = si.config_c1()
+    g = cfg["grid"]
+    dep = cfg["depth"].reshape(1, g.nx)
+    o = OSolver(Grid(g.nx, 1, g.lx), dep, h_ref=cfg["h_ref"], mode="full", max_sweeps=200)
+    eo, po, sto = o.step(cfg["eta"].reshape(1, -1), cfg["phi"].reshape(1, -1), cfg["dt"], 64, tol=1e-11)
+    s = Solver(g.nx, 1, g.lx, 1.0, dep, h_ref=cfg["h_ref"], device=gpu, mode="full", max_sweeps=200)
+    e = _t(cfg["eta"].reshape(1, 1, -1), torch.float64, gpu)
+    p = _t(cfg["phi"].reshape(1, 1, -1), torch.float64, gpu)
+    st, info = s.step(e, p, cfg["dt"], 64, tol=1e-11)
+    err = _rel(e.cpu().numpy().reshape(eo.shape), eo)
+    _say(f"C1 full, one period: sweeps {info['sweeps_total']}/{sum(i.sweeps for i in sto)}, eta err {err:.2e}")
+    assert st == 0 and info["sweeps_total"] == sum(i.sweeps for i in sto)
+    assert err < 1e-10 and _rel(p.cpu().numpy().reshape(po.shape), po) < 1e-10
+
+
 def test_full_mode_refusals(gpu):
     from paper_2310_19840_amd import Batch, SBIError, Solver, _lib
     # two-dimensional grids: not a valid grid for the mode
