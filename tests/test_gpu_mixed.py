@@ -141,6 +141,30 @@ def test_mixed_adaptive_pair_and_diagnostics(gpu):
     assert abs(en[0] - eno) <= 1e-10 * abs(eno) and abs(m[0] - mo) <= 1e-10 * max(abs(mo), 1e-3)
 
 
+def test_mixed_tuned_new_bed_and_user_seed(gpu):
+    """The context's other calls reach its FP32 side too: after autotuning
+    (which tunes the FP32 correction sweeps' plans as well) and a new bed,
+    and from a user seed, W is the oracle's FP64 fixed point over the new bed."""
+    import torch
+    from oracle import Grid, Solver as OSolver
+    from paper_2310_19840_amd import Solver
+    nx, ny = 128, 64
+    lx, ly, eta, phi, depth = _case(nx, ny, 91, True)
+    s = Solver(nx, ny, lx, ly, depth, device=gpu, mode="iter", max_sweeps=200, precision="mixed", accel="anderson",
+               seed="user")
+    plan = s.autotune(force=True)
+    assert plan["us"] > 0
+    depth2 = 1.5 - 0.6 * (1.5 - depth)   # a gentler bump
+    s.set_depth(depth2)
+    Wo, _ = OSolver(Grid(nx, ny, lx, ly), depth2, mode="iter", max_sweeps=300).vertical_velocity(eta, phi, tol=1e-14)
+    e, p = _t(eta, torch.float64, gpu), _t(phi, torch.float64, gpu)
+    for name, seed in (("zero", np.zeros_like(Wo)), ("0.9 W", Wo * 0.9)):
+        W, st, info = s.vertical_velocity(e, p, tol=1e-11, w_seed=_t(seed[None], torch.float64, gpu))
+        err = _rel(W.cpu().numpy()[0], Wo)
+        _say(f"tuned, new bed, seed {name}: err {err:.1e}, sweeps {info[0]}")
+        assert st == 0 and err < 1e-10
+
+
 def test_mixed_refusals(gpu):
     from paper_2310_19840_amd import Batch, SBIError, Solver, _lib, vertical_velocity_noalloc
     import torch
