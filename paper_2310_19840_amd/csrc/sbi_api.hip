@@ -27,6 +27,7 @@
 #include "../../include/sbi.h"
 #include "../../include/sbi_batch.h"
 #include "../../include/sbi_net.h"
+#include "sbi_full.hpp"
 #include "sbi_kernels.hpp"
 #include "sbi_net.hpp"
 
@@ -242,6 +243,9 @@ static sbi_grid inner_grid(const sbi_grid* g) {
 }
 
 constexpr int kFullSplitMax = 16;  // source-point slices of a pair pass of the fully nonlinear solve
+// slices the pair passes of a fully nonlinear solve may write: the split passes'
+// and the symmetric single-layer pass's (one per tile block)
+static int full_slices(int nx) { return std::max(kFullSplitMax, nx / kFullSymTile); }
 
 static bool grid_valid(const sbi_grid* g) {
     if (!g) return false;
@@ -307,7 +311,7 @@ static Layout layout(const sbi_grid* g, int batch) {
     // geometry (3 tables), its circulant, its right-hand side and two phi_b
     // iterates [batch][nx], and the per-member flags
     L.bytes_full = g->mode == SBI_MODE_FULL
-                       ? 14 * al((size_t)g->nx * 8 * batch) + al((size_t)kFullSplitMax * g->nx * 8 * batch) +
+                       ? 14 * al((size_t)g->nx * 8 * batch) + al((size_t)full_slices(g->nx) * g->nx * 8 * batch) +
                              al(sizeof(int) * batch)
                        : 0;
     // mixed precision: the FP32 context's workspace at the end
@@ -557,7 +561,7 @@ static sbi_status ctx_setup(sbi_ctx* c, const sbi_grid* g, int32_t batch, const 
         c->full_pb[0] = p + 12 * tb;
         c->full_pb[1] = p + 13 * tb;
         c->full_part = p + 14 * tb;
-        c->full_bed = reinterpret_cast<int*>(p + 14 * tb + al((size_t)kFullSplitMax * g->nx * 8 * batch));
+        c->full_bed = reinterpret_cast<int*>(p + 14 * tb + al((size_t)full_slices(g->nx) * g->nx * 8 * batch));
     }
     c->col_C = L.C;
     gd.col_C = L.C;
@@ -1677,6 +1681,10 @@ static sbi_status full_solve(sbi_ctx* c, const void* eta_phys, double tol) {
     SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_DOUBLE, c->stream)));
     SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_RHS, c->stream)));
     const bool bed = c->full_bed_any;
+    // the image form's single layer by its symmetric pass (each pair once) where
+    // the grid holds two tiles or more
+    const bool sym = p.n >= 2 * kFullSymTile;
+    p.nsym = sym ? p.n / kFullSymTile : 0;
     if (bed) {
         // the bed's right-hand side -D_BS[phi_s] of the two-boundary members
         c->st.launches += 2;
@@ -1711,7 +1719,7 @@ static sbi_status full_solve(sbi_ctx* c, const void* eta_phys, double tol) {
             if (n > 0 && !c->full_bed_all) {
                 ProfScope ps_(c, K_FULL_PAIRS);
                 c->st.launches += 1;
-                SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_SINGLE, c->stream)));
+                SBI_TRY(hip_ok(launch_full(c->fp64, p, sym ? FULL_SYM : FULL_SINGLE, c->stream)));
             }
             c->st.launches += 2;
             ProfScope ps2_(c, K_FULL_APPLY);

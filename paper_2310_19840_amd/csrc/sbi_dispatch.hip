@@ -1,6 +1,7 @@
 // sbi_dispatch.hip -- precision dispatch of the kernel launchers and the
 // precision-independent control kernels.
 #include "sbi_device.hpp"
+#include "sbi_full.hpp"
 #include "sbi_kernels.hpp"
 
 namespace sbi {

@@ -44,6 +44,7 @@
 #include <math.h>
 
 #include "sbi_device.hpp"
+#include "sbi_full.hpp"
 #include "sbi_kernels.hpp"
 
 #ifndef SBI_REAL
@@ -289,6 +290,97 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
     static_cast<double*>(p.part)[((long long)split * p.batch + m) * n + i] = out;
 }
 
+// --- the single layer (S - S0)[V_n] of the image-form members from the
+// symmetry of its kernel: K(i, j) = K(j, i) (both the direct part and the
+// image depend on |eta_j - eta_i|, eta_i + eta_j and sin^2(pi (x_j - x_i)/L)).
+// The n x n pairs split into tiles of kSymT x kSymT points; a workgroup takes
+// tile (I, J), I <= J, evaluates each of its pairs once and adds K V_j to the
+// row sums of its points i in block I and K V_i (reduced over a wavefront's
+// rows) to the column sums of its points j in block J.  Row sums go to slice J
+// of the points of block I, column sums to slice I of those of block J, so
+// every point receives n / kSymT slices, one from each block, each written
+// once; a diagonal tile (I = I) evaluates all its pairs and writes rows only.
+constexpr int kSymT = kFullSymTile;
+constexpr int kSymThreads = 2 * kSymT;  // two threads per row, each over half the tile's columns
+
+template <typename R>
+__global__ void __launch_bounds__(kSymThreads) k_full_sympairs(const FullParams p) {
+    __shared__ R tej[kSymT], tvj[kSymT];
+    __shared__ double colp[kSymThreads / 64][kSymT / 2];
+    __shared__ double rowp[2][kSymT];
+    const int t = threadIdx.x;
+    const int m = blockIdx.z;
+    const int n = p.n;
+    const int nb = n / kSymT;
+    {
+        Ctl* ctl = p.ctl + m;
+        const bool leader = blockIdx.x == 0 && t == 0;
+        if (full_decided(p, ctl, leader)) return;  // workgroup-uniform
+    }
+    if (full_bed(p, m)) return;
+    // tile (I, J), I <= J, of this workgroup's linear index (row-major upper triangle)
+    int L = blockIdx.x, I = 0;
+    while (L >= nb - I) {
+        L -= nb - I;
+        ++I;
+    }
+    const int J = I + L;
+    const bool diag = I == J;
+    const long long mo = m * p.s_phys;
+    const R* eta = static_cast<const R*>(p.eta) + mo;
+    const R* ex = static_cast<const R*>(p.ex) + mo;
+    const R* v = static_cast<const R*>(p.vin) + mo;
+    const double* s2 = static_cast<const double*>(p.s2);
+    const double* lfl = static_cast<const double*>(p.lfl) + (long long)m * n;
+    const R pl = R(M_PI / p.lx);
+    const bool img = !full_deep(p, m);
+    const R b2h = R(2.0 * M_PI * p.href[m] / p.lx);
+    const int il = t % kSymT, hf = t / kSymT;
+    const int i = I * kSymT + il;
+    const R etai = eta[i], exi = ex[i];
+    const double vi = (double)v[i];
+    if (t < kSymT) {
+        tej[t] = eta[J * kSymT + t];
+        tvj[t] = v[J * kSymT + t];
+    }
+    __syncthreads();
+    const int wv = t / 64;
+    double acc = 0.0;
+    for (int jj = 0; jj < kSymT / 2; ++jj) {
+        const int jl = hf * (kSymT / 2) + jj;
+        const int j = J * kSymT + jl;
+        const int d = (j - i + n) & (n - 1);
+        const R sa2 = R(s2[d]);
+        const R shb = sinh(pl * (tej[jl] - etai));  // as in k_full_pairs
+        R kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb / sa2);
+        if (img) {
+            const R shp = sinh(pl * (tej[jl] + etai) + b2h);
+            kv += R(-0.5) * log(sa2 + shp * shp) + R(lfl[d]);
+        }
+        acc += (double)kv * (double)tvj[jl];
+        if (!diag) {
+            // the pair seen from j: K V_i summed over this wavefront's rows
+            double c = (double)kv * vi;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+            if ((t & 63) == 0) colp[wv][jj] = c;
+        }
+    }
+    rowp[hf][il] = acc;
+    __syncthreads();
+    if (t < kSymT) {
+        const double dx = p.lx / n;
+        double* part = static_cast<double*>(p.part);
+        // rows of block I: slice J
+        part[((long long)J * p.batch + m) * n + I * kSymT + t] = (rowp[0][t] + rowp[1][t]) * dx;
+        if (!diag) {
+            // columns of block J: slice I; column jl collects the two wavefronts of its half
+            const int h2 = t / (kSymT / 2), q = t % (kSymT / 2);
+            part[((long long)I * p.batch + m) * n + J * kSymT + t] = (colp[2 * h2][q] + colp[2 * h2 + 1][q]) * dx;
+        }
+    }
+}
+
 // --- the surface pass of the two-boundary members: (S - S_flat)[V_n] (no
 // image; V_n absent at the first sweep) minus D_SB[phi_b] with the phi_b of
 // this sweep, at the surface points over a slice of the source points
@@ -497,8 +589,11 @@ __global__ void k_full_combine(const FullParams p) {
     if (p.ctl[m].done) return;  // decided by this sweep's pair pass
     const long long o = (long long)m * p.n + i;
     double w = static_cast<const double*>(p.rhs)[o];
+    // slices: those of the two-boundary surface pass, or of the image form's
+    // single layer (nsym of the symmetric pass when it ran)
+    const int ns = full_bed(p, m) ? p.nsplit : (p.nsym > 0 ? p.nsym : p.nsplit);
     if (p.vin || full_bed(p, m))
-        for (int s = 0; s < p.nsplit; ++s) w -= static_cast<const double*>(p.part)[((long long)s * p.batch + m) * p.n + i];
+        for (int s = 0; s < ns; ++s) w -= static_cast<const double*>(p.part)[((long long)s * p.batch + m) * p.n + i];
     static_cast<double*>(p.w)[o] = w;
 }
 
@@ -595,6 +690,11 @@ template <> hipError_t launch_full_t<Real>(const FullParams& p, int what, hipStr
             break;
         case FULL_BED:
             hipLaunchKernelGGL((k_full_bpairs<Real, 3>), dim3(tiles, p.nsplit, p.batch), dim3(kFullThreads), 0, s, p);
+            break;
+        case FULL_SYM:
+            if (n % kSymT != 0) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(k_full_sympairs<Real>, dim3((n / kSymT) * (n / kSymT + 1) / 2, 1, p.batch),
+                               dim3(kSymThreads), 0, s, p);
             break;
         case FULL_SURF:
             hipLaunchKernelGGL(k_full_spairs<Real>, dim3(tiles, p.nsplit, p.batch), dim3(kFullThreads), 0, s, p);

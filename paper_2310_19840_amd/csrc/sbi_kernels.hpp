@@ -196,52 +196,6 @@ struct DiagParams {
     int nblk;
 };
 
-// Fully nonlinear W solve of one-dimensional grids (sbi_full.hip): the
-// operands of its kernels.  Physical fields are [batch][n] with member
-// stride s_phys; FP64 tables: c0 [batch][n] (S0^-1 circulant per member), d1,
-// d2, s2 [n]; FP64 part [nsplit][batch][n] holds the slices of a pair pass and
-// rhs [batch][n] the right-hand side.  Members whose bed is kept as a boundary
-// of its own (bed[m] = 1: a variable bed not too deep to matter) use the
-// two-boundary form: bed geometry bz, bx, bxx, the circulant cm of
-// S0^-1 (S0 - S_flat), the bed right-hand side rb = -D_BS[phi_s] and the bed
-// potential phi_b of the sweeps in pbuf (all FP64 [batch][n]).
-struct FullParams {
-    int n, batch, nsplit;
-    double lx;
-    long long s_phys;
-    const double* href;   // [batch] depth of each member's flat bed
-    const void* eta;      // physical eta
-    const void* phi;      // physical phi_s
-    void* ex;             // eta_x
-    void* exx;            // eta_xx
-    void* rhs;            // pi phi_s + D[phi_s] (FP64, [batch][n])
-    void* part;           // pair-pass slices
-    void* c0;
-    void* d1;
-    void* d2;
-    void* s2;
-    void* lfl;            // [batch][n] the flat image's single-layer term per member
-    void* w;              // FP64 [batch][n]: rhs - (S - S0)[V_n]
-    const void* vin;      // V_n (null: V_0 = 0)
-    void* vout;           // V_(n+1)
-    const void* vbuf[2];  // the two iterate buffers (V_s is in vbuf[s & 1])
-    void* vfinal;         // the decided iterate of each member
-    Ctl* ctl;
-    int sweep, max_sweeps;
-    double tol;
-    const int* bed;       // [batch] 1: two-boundary form (null: no member)
-    void* bz;
-    void* bx;
-    void* bxx;
-    void* cm;
-    void* rb;
-    const void* pbin;     // phi_b of this sweep (null: phi_b = 0)
-    void* pbout;          // phi_b of the next sweep
-};
-enum {
-    FULL_TABLES = 0, FULL_GEOM, FULL_DOUBLE, FULL_RHS, FULL_SINGLE, FULL_COMBINE, FULL_APPLY, FULL_SELECT,
-    FULL_BEDGEOM, FULL_RHSB, FULL_RB, FULL_BED, FULL_PB, FULL_SURF
-};
 
 struct Twiddles {
     const void* tx;   // length nx
@@ -275,8 +229,6 @@ template <typename R> int row_var_mask_t(int sweep, int nx);
 // rows per workgroup of a row variant at its 256-thread launch bound
 template <typename R> int row_rows_cap_t(int nx, int var);
 int row_var_mask(int fp64, int sweep, int nx);
-template <typename R> hipError_t launch_full_t(const FullParams&, int what, hipStream_t);
-hipError_t launch_full(int fp64, const FullParams& p, int what, hipStream_t s);
 int row_rows_cap(int fp64, int nx, int var);
 
 hipError_t launch_row_fwd(int fp64, const RowFwdParams& p, int batch, const Twiddles& tw, hipStream_t s);
