@@ -393,6 +393,7 @@ def run_c2_tank(args, dev):
     for kind in ("tank", "relaxation"):
         s = Solver(g.nx, 1, g.lx, 1.0, cfg["depth"], h_ref=cfg["h_ref"], device=dev, mode="sa",
                    filter_beta=cfg["filter_beta"])
+        plan = s.autotune() if args.autotune else s.plan()
         if kind == "tank":
             s.set_wavemaker([(rz["a"], rz["k"], rz["omega"], 0.0)], x0=7 * g.lx / 8, width=4 * math.pi)
         else:
@@ -406,7 +407,7 @@ def run_c2_tank(args, dev):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         out[kind] = dict(value=g.nx * args.c2_steps / el, ms_per_step=1e3 * el / args.c2_steps, status=st,
-                         max_eta=float(np.abs(eta.cpu().numpy()).max()))
+                         max_eta=float(np.abs(eta.cpu().numpy()).max()), plan=plan)
     r = dict(out["tank"])
     r.update(points=g.nx, steps=args.c2_steps, relaxation_value=out["relaxation"]["value"],
              relaxation_ms_per_step=out["relaxation"]["ms_per_step"])
