@@ -1606,8 +1606,9 @@ static sbi_status hist_after_solve(sbi_ctx* c, int stage, bool capture_safe) {
 // solve, -1 for any other solve.  capture_safe: no host synchronisation
 // (fixed sweep launches, no fallback from a failed learned seed).
 // ---------------------------------------------------------------------------
-// Fully nonlinear W (SBI_MODE_FULL, one dimension, flat bed): the surface
-// boundary-integral equation with the remaining integrals kept (sbi_full.hip)
+// Fully nonlinear W (SBI_MODE_FULL, one dimension): the boundary-integral
+// equations with the remaining integrals kept (sbi_full.hip) -- over a flat
+// bed by its image, over a variable bed with the bed as a second boundary
 // ---------------------------------------------------------------------------
 // physical work fields of the solve (the SA order slots, unused in this mode)
 enum { PF_PHI = P_V0, PF_EX, PF_EXX, PF_V, PF_B0, PF_B1 };
