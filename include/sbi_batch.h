@@ -63,7 +63,9 @@ size_t sbi_batch_workspace_bytes(int32_t m, const sbi_grid* grids);
  * reference depth rule h_ref for all (<= 0: each member's max depth).
  * workspace: caller-owned device memory of sbi_batch_workspace_bytes bytes.
  * flags: SBI_BATCH_GRAPH | SBI_BATCH_AUTOTUNE.
- * Returns SBI_WARN_DEPTH_CRITERION when any member exceeds the Sec. 5 limit.
+ * Returns SBI_WARN_DEPTH_CRITERION when any member exceeds the Sec. 5 limit,
+ * and SBI_ERR_UNSUPPORTED for a member in mode SBI_MODE_FULL or precision
+ * SBI_MIXED (both decide their solves on the host between passes).
  */
 sbi_status sbi_batch_init(sbi_batch** out, int32_t m, const sbi_grid* grids, const double* const* depths,
                           double h_ref, void* workspace, size_t ws_bytes, void* hip_stream, int32_t flags);
