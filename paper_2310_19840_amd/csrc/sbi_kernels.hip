@@ -535,9 +535,9 @@ __device__ __forceinline__ void row_nphi_body(const RowNphiParams& p, const type
     RW::inverse(a, static_cast<const V*>(p.gex) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
     RW::inverse(b, static_cast<const V*>(p.gpx) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
     const double dx = p.g.lx / p.g.nx;
-    // damping weight mu(x) of the wave tank times a potential gradient -> forward half form
-    auto damped = [&](const V (&grad)[E], void* out) {
-        V m[E];
+    // damping weight mu(x) of the wave tank times a potential gradient, in
+    // place (the gradient is spent by then) -> forward half form
+    auto damped = [&](V (&grad)[E], void* out) {
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             const int n = ri.j + k * RW::P;
@@ -547,12 +547,10 @@ __device__ __forceinline__ void row_nphi_body(const RowNphiParams& p, const type
                 const double d = fmod((2 * n + hh) * dx - p.dmp_x0 + 1.5 * p.g.lx, p.g.lx) - 0.5 * p.g.lx;
                 mv[hh] = exp(-(d / p.dmp_w) * (d / p.dmp_w));
             }
-            m[k] = cx<V>(R(mv[0] * (double)grad[k].x), R(mv[1] * (double)grad[k].y));
+            grad[k] = cx<V>(R(mv[0] * (double)grad[k].x), R(mv[1] * (double)grad[k].y));
         }
-        RW::forward(m, static_cast<V*>(out) + hb, rc, lds_all, twN, twX);
+        RW::forward(grad, static_cast<V*>(out) + hb, rc, lds_all, twN, twX);
     };
-    if constexpr (TANK)
-        if (p.dmp_w > 0.0) damped(b, p.hdx);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         q[k] = cx<V>(q[k].x + a[k].x * b[k].x, q[k].y + a[k].y * b[k].y);
@@ -560,10 +558,10 @@ __device__ __forceinline__ void row_nphi_body(const RowNphiParams& p, const type
         pp[k] = rmul(b[k], b[k]);
     }
     if (p.g.ny > 1) {
+        if constexpr (TANK)
+            if (p.dmp_w > 0.0) damped(b, p.hdx);
         RW::inverse(a, static_cast<const V*>(p.gey) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
         RW::inverse(b, static_cast<const V*>(p.gpy) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
-        if constexpr (TANK)
-            if (p.dmp_w > 0.0) damped(b, p.hdy);
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             q[k] = cx<V>(q[k].x + a[k].x * b[k].x, q[k].y + a[k].y * b[k].y);
@@ -576,6 +574,10 @@ __device__ __forceinline__ void row_nphi_body(const RowNphiParams& p, const type
         q[k] = cx<V>(R(0.5) * (q[k].x * q[k].x / (R(1) + gg[k].x) - pp[k].x),
                      R(0.5) * (q[k].y * q[k].y / (R(1) + gg[k].y) - pp[k].y));
     }
+    // the last potential gradient (d_x phi in 1D, d_y phi in 2D), after the
+    // products, when only q is live beside it
+    if constexpr (TANK)
+        if (p.dmp_w > 0.0) damped(b, p.g.ny > 1 ? p.hdy : p.hdx);
     if (TANK && p.wm_n > 0) {
         // pneumatic wavemaker: bell-shaped pressures centred on x = 0, i.e. split
         // over both ends of the periodic domain; the prefactor
@@ -630,40 +632,58 @@ template <typename R, int NX>
 __global__ void __launch_bounds__(row_threads<NX>()) k_row_blend(const RowBlendParams p, const typename cplx_of<R>::type* twN_tab,
                             const typename cplx_of<R>::type* twX_tab) {
     ROW_PROLOGUE(R, NX)
-    V e[E], f[E];
-    RW::inverse(e, static_cast<const V*>(p.ge) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
-    RW::inverse(f, static_cast<const V*>(p.gp) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
     const double dx = p.g.lx / p.g.nx;
     const double r = p.t < p.ramp_time ? 0.5 * (1.0 - cos(M_PI * p.t / p.ramp_time)) : 1.0;
+    // the zones' reciprocal lengths, once: a division per point, unrolled over
+    // the row's elements, would hold more registers than the transforms
+    const double igen = p.gen > 0.0 ? 1.0 / p.gen : 0.0, iabs = p.absl > 0.0 ? 1.0 / p.absl : 0.0;
+    // one field at a time (eta against a r cos, phi against a r / om sin), so
+    // that a single row of values is live
+    auto blend = [&](const void* in, void* out, bool pot) {
+        V v[E];
+        RW::inverse(v, static_cast<const V*>(in) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+        const double amp = pot ? p.a * r / p.om : p.a * r;
+        // target a r cos(k x - om t) for eta and a r / om cos(k x - om t - pi/2)
+        // for phi: one sincos at the thread's first point 2j, then rotations by
+        // k dx (to point 2n + 1) and by 2 P k dx (to the next element), each
+        // exact to rounding (the two fields' phases differ, so that the first
+        // field's rotated values are not kept for the second)
+        double c0, s0, ch, sh, cq, sq;
+        sincos(p.k * (2 * ri.j) * dx - p.om * p.t - (pot ? 0.5 * M_PI : 0.0), &s0, &c0);
+        sincos(p.k * dx, &sh, &ch);
+        sincos(p.k * (2 * RW::P) * dx, &sq, &cq);
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int n = ri.j + q * RW::P;
-        double ev[2] = {(double)e[q].x, (double)e[q].y};
-        double fv[2] = {(double)f[q].x, (double)f[q].y};
+        for (int q = 0; q < E; ++q) {
+            const int n = ri.j + q * RW::P;
+            double fv[2] = {(double)v[q].x, (double)v[q].y};
+            double c = c0, sn = s0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const double x = (2 * n + h) * dx;
-            double wg = 0.0, wa = 0.0;
-            if (x < p.gen) {
-                const double s = x / p.gen;
-                wg = 1.0 - (3 * s * s - 2 * s * s * s);
+            for (int h = 0; h < 2; ++h) {
+                const double x = (2 * n + h) * dx;
+                double wg = 0.0, wa = 0.0;
+                if (x < p.gen) {
+                    const double s = x * igen;
+                    wg = 1.0 - (3 * s * s - 2 * s * s * s);
+                }
+                if (x > p.g.lx - p.absl) {
+                    const double s = (p.g.lx - x) * iabs;
+                    wa = 1.0 - (3 * s * s - 2 * s * s * s);
+                }
+                fv[h] = (1.0 - wg) * fv[h] + wg * (amp * c);
+                fv[h] *= (1.0 - wa);
+                const double cn = c * ch - sn * sh;
+                sn = sn * ch + c * sh;
+                c = cn;
             }
-            if (x > p.g.lx - p.absl) {
-                const double s = (p.g.lx - x) / p.absl;
-                wa = 1.0 - (3 * s * s - 2 * s * s * s);
-            }
-            const double th = p.k * x - p.om * p.t;
-            const double et = p.a * r * cos(th), pt = p.a * r / p.om * sin(th);
-            ev[h] = (1.0 - wg) * ev[h] + wg * et;
-            fv[h] = (1.0 - wg) * fv[h] + wg * pt;
-            ev[h] *= (1.0 - wa);
-            fv[h] *= (1.0 - wa);
+            const double cn = c0 * cq - s0 * sq;
+            s0 = s0 * cq + c0 * sq;
+            c0 = cn;
+            v[q] = cx<V>(R(fv[0]), R(fv[1]));
         }
-        e[q] = cx<V>(R(ev[0]), R(ev[1]));
-        f[q] = cx<V>(R(fv[0]), R(fv[1]));
-    }
-    RW::forward(e, static_cast<V*>(p.he) + hb, rc, lds_all, twN, twX);
-    RW::forward(f, static_cast<V*>(p.hp) + hb, rc, lds_all, twN, twX);
+        RW::forward(v, static_cast<V*>(out) + hb, rc, lds_all, twN, twX);
+    };
+    blend(p.ge, p.he, false);
+    blend(p.gp, p.hp, true);
 }
 
 // Learned-warm-start features of each point, channel-last FP32:
@@ -1933,11 +1953,11 @@ template <typename RWT> struct RowLaunch {
 // kernels (three workgroups per CU) take the cached twiddle powers in FP32
 // only and radix-16 rows only at 512 points; the SA kernel takes both in
 // FP32 from 512 points (radix 16 needs two radix-16 passes in the
-// half-length row) and the cached powers in FP64 too.
+// half-length row) and the cached powers in FP64 too, below 8192 points.
 template <typename R, int NX, int VAR, bool SWEEP> constexpr bool row_var_built() {
     constexpr bool f32 = std::is_same<R, float>::value;
     if constexpr (VAR == 0) return true;
-    if constexpr (VAR == 1) return f32 || !SWEEP;
+    if constexpr (VAR == 1) return f32 || (!SWEEP && NX < 8192);
     if constexpr (VAR == 2) return f32 && (SWEEP ? NX == 512 : NX >= 512);
     // radix 4 (4 values per thread): a row spans two or more wavefronts, so
     // its exchanges take workgroup barriers; from 256-point rows
