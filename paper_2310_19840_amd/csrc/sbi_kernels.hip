@@ -454,6 +454,48 @@ __global__ void __launch_bounds__((row_threads<NX, RowVar<R, NX, VAR>::E>()))
              const typename cplx_of<R>::type* twX_tab) {
     ROW_PROLOGUE_T(RowVar<R, NX, VAR>)
     const int l = p.l;
+    if (p.split > 0) {
+        // a 1D grid has one row per member: its products go to workgroups of
+        // their own (blockIdx.y): eta^j V_(l-j) for j < l, then, over a
+        // variable bed, delta^j d_x phi_b,(l-j), then eta^(l-1) d_x phi_s,
+        // each formed by the same operations as in the sequential form below
+        const int nv = l - 1;
+        const int part = blockIdx.y;
+        const int fam = part < nv ? 0 : ((p.vd && part < 2 * nv) ? 1 : 2);
+        V base[E], pw[E], src[E];
+        RW::load(base, static_cast<const R*>(fam == 1 ? p.delta : p.eta) + po, ri.j, ri.valid);
+#pragma unroll
+        for (int q = 0; q < E; ++q) pw[q] = base[q];
+        if (fam < 2) {
+            const int jj = part - fam * nv + 1;
+            if (jj == 1) {
+                RW::inverse(src, static_cast<const V*>(fam == 0 ? p.gV : p.gbx) + hb, nullptr, R(0), rc, lds_all,
+                            twN, twX, iscale);
+                void* outp = fam == 0 ? p.V_out : p.bx_out;
+                if (outp) RW::store(src, static_cast<R*>(outp) + po, ri.j, ri.valid);
+            } else {
+                for (int i = 2; i <= jj; ++i) {
+#pragma unroll
+                    for (int q = 0; q < E; ++q) pw[q] = rmul(pw[q], base[q]);
+                }
+                RW::load(src, static_cast<const R*>(fam == 0 ? p.Vphys[l - jj] : p.bxphys[l - jj]) + po, ri.j,
+                         ri.valid);
+            }
+#pragma unroll
+            for (int q = 0; q < E; ++q) src[q] = rmul(pw[q], src[q]);
+            RW::forward(src, static_cast<V*>(p.h[fam * nv + jj - 1]) + hb, rc, lds_all, twN, twX);
+        } else {
+            for (int i = 2; i <= nv; ++i) {
+#pragma unroll
+                for (int q = 0; q < E; ++q) pw[q] = rmul(pw[q], base[q]);
+            }
+            RW::load(src, static_cast<const R*>(p.phx) + po, ri.j, ri.valid);
+#pragma unroll
+            for (int q = 0; q < E; ++q) src[q] = rmul(pw[q], src[q]);
+            RW::forward(src, static_cast<V*>(p.h[(p.vd ? 2 : 1) * nv]) + hb, rc, lds_all, twN, twX);
+        }
+        return;
+    }
     int idx = 0;
     V a[E], base[E], pw[E];
     // eta^j V_(l-j)
@@ -750,17 +792,20 @@ template <typename R, int NY, bool QB, int NACC> struct ColCfg {
     static constexpr int C = NY == 1 ? 64 : ((WV || P >= 128) ? 1 : 256 / P);
     static constexpr int LMAX = WV ? 8 : ((sizeof(R) == 8 && !QB) ? 2 : 4);
     static constexpr int FIT = 512 / (C * P);
-    static constexpr int PL = NY == 1 ? 1 : (FIT < 1 ? 1 : (FIT < LMAX ? FIT : LMAX));
+    // 1D grids: four wavefront lanes share a tile's products (each "column"
+    // is one value, so a lane's rounds are one dependent load each)
+    static constexpr int PL = NY == 1 ? 4 : (FIT < 1 ? 1 : (FIT < LMAX ? FIT : LMAX));
     static constexpr int THREADS = PL * C * P;
     static constexpr bool WAVE = P <= 64;
     // the next round's column is loaded during the current transform, except
     // in FP64 wave lanes, whose registers cannot hold a second column (the
     // other wavefront of the SIMD covers the load instead)
     static constexpr bool PREFETCH = !(WV && sizeof(R) == 8);
-    // LDS: the transform exchange area of every lane and column (none for 1D
-    // grids, whose "columns" are single values), then the mode-geometry table
-    // of C * Ky entries of 4 reals
-    static constexpr int XFORM = NY > 1 ? PL * C * fft_lds_elems<NY, E>() : 0;
+    // LDS: the transform exchange area of every lane and column (for 1D
+    // grids, whose "columns" are single values, one value per lane and column
+    // to combine the lanes' sums), then the mode-geometry table of C * Ky
+    // entries of 4 reals
+    static constexpr int XFORM = PL * C * fft_lds_elems<NY, E>();
     static constexpr size_t lds_bytes(int Ky) {
         return (size_t)XFORM * sizeof(typename cplx_of<R>::type) + (size_t)C * Ky * 4 * sizeof(R);
     }
@@ -1900,6 +1945,7 @@ __global__ void k_diag(const DiagParams p) {
 // workgroups along y of a row pass: the sweep splits its product families
 template <typename PT> static int row_families(const PT&) { return 1; }
 static int row_families(const RowSweepParams& p) { return p.nfam > 0 ? p.nfam : 1; }
+static int row_families(const RowSaParams& p) { return p.split > 0 ? p.split : 1; }
 
 template <typename RWT> struct RowLaunch {
     using V = typename RWT::V;
