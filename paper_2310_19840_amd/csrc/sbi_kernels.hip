@@ -792,9 +792,9 @@ template <typename R, int NY, bool QB, int NACC> struct ColCfg {
     static constexpr int C = NY == 1 ? 64 : ((WV || P >= 128) ? 1 : 256 / P);
     static constexpr int LMAX = WV ? 8 : ((sizeof(R) == 8 && !QB) ? 2 : 4);
     static constexpr int FIT = 512 / (C * P);
-    // 1D grids: four wavefront lanes share a tile's products (each "column"
+    // 1D grids: eight wavefront lanes share a tile's products (each "column"
     // is one value, so a lane's rounds are one dependent load each)
-    static constexpr int PL = NY == 1 ? 4 : (FIT < 1 ? 1 : (FIT < LMAX ? FIT : LMAX));
+    static constexpr int PL = NY == 1 ? 8 : (FIT < 1 ? 1 : (FIT < LMAX ? FIT : LMAX));
     static constexpr int THREADS = PL * C * P;
     static constexpr bool WAVE = P <= 64;
     // the next round's column is loaded during the current transform, except
