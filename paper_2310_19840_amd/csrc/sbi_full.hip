@@ -300,12 +300,29 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
 // of the points of block I, column sums to slice I of those of block J, so
 // every point receives n / kSymT slices, one from each block, each written
 // once; a diagonal tile (I = I) evaluates all its pairs and writes rows only.
+// sinh of a scaled elevation difference, formed from the difference itself
+// (from exponentials of each point it would lose its relative accuracy for
+// nearby points): below 1/8 by its Taylor series to the x^11 term, nested as
+// x (1 + x^2/(2*3) (1 + x^2/(4*5) (...))), whose remainder is below 3e-21 of
+// the value there; beyond it by the library function
+template <typename R> __device__ __forceinline__ R sinh_of_difference(R x) {
+    if (fabs(x) >= R(0.125)) return sinh(x);
+    const R x2 = x * x;
+    R s = R(1) + x2 * R(1.0 / 110.0);
+    s = R(1) + x2 * R(1.0 / 72.0) * s;
+    s = R(1) + x2 * R(1.0 / 42.0) * s;
+    s = R(1) + x2 * R(1.0 / 20.0) * s;
+    s = R(1) + x2 * R(1.0 / 6.0) * s;
+    return x * s;
+}
+
 constexpr int kSymT = kFullSymTile;
 constexpr int kSymThreads = 2 * kSymT;  // two threads per row, each over half the tile's columns
+static_assert(kSymT / 2 == 64, "a half tile's columns are the lanes of one wavefront");
 
 template <typename R>
 __global__ void __launch_bounds__(kSymThreads) k_full_sympairs(const FullParams p) {
-    __shared__ R tej[kSymT], tvj[kSymT];
+    __shared__ R tej[kSymT], tvj[kSymT], tsj[kSymT], tcj[kSymT];
     __shared__ double colp[kSymThreads / 64][kSymT / 2];
     __shared__ double rowp[2][kSymT];
     const int t = threadIdx.x;
@@ -339,34 +356,54 @@ __global__ void __launch_bounds__(kSymThreads) k_full_sympairs(const FullParams 
     const int i = I * kSymT + il;
     const R etai = eta[i], exi = ex[i];
     const double vi = (double)v[i];
+    // the image's sinh(pi (eta_j + eta_i + 2h) / L) as sinh(a_j + b_i) =
+    // sinh a_j cosh b_i + cosh a_j sinh b_i, a_j = pi eta_j / L, b_i = pi eta_i
+    // / L + 2 pi h / L: one sinh and cosh per point instead of a sinh per pair
+    // (with the bed below the surface b_i > |a_j|, so the second term
+    // dominates the first and the sum does not cancel)
+    R sbi = R(0), cbi = R(1);
+    if (img) {
+        const R b = pl * etai + b2h;
+        sbi = sinh(b);
+        cbi = cosh(b);
+    }
     if (t < kSymT) {
-        tej[t] = eta[J * kSymT + t];
+        const R ej = eta[J * kSymT + t];
+        tej[t] = ej;
         tvj[t] = v[J * kSymT + t];
+        if (img) {
+            tsj[t] = sinh(pl * ej);
+            tcj[t] = cosh(pl * ej);
+        }
     }
     __syncthreads();
-    const int wv = t / 64;
-    double acc = 0.0;
+    const int wv = t / 64, ln = t & 63;
+    const int from = (ln + 1) & 63;
+    double acc = 0.0, cacc = 0.0;
     for (int jj = 0; jj < kSymT / 2; ++jj) {
-        const int jl = hf * (kSymT / 2) + jj;
+        // lane ln takes the columns of its half in the order ln, ln + 1, ...
+        // (mod 64): at each step the lanes of a wavefront hold 64 different
+        // columns, and the running column sum moves one lane down with its column
+        const int jl = hf * (kSymT / 2) + ((ln + jj) & (kSymT / 2 - 1));
         const int j = J * kSymT + jl;
         const int d = (j - i + n) & (n - 1);
         const R sa2 = R(s2[d]);
-        const R shb = sinh(pl * (tej[jl] - etai));  // as in k_full_pairs
+        const R shb = sinh_of_difference(pl * (tej[jl] - etai));
         R kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb / sa2);
         if (img) {
-            const R shp = sinh(pl * (tej[jl] + etai) + b2h);
+            const R shp = tsj[jl] * cbi + tcj[jl] * sbi;
             kv += R(-0.5) * log(sa2 + shp * shp) + R(lfl[d]);
         }
         acc += (double)kv * (double)tvj[jl];
         if (!diag) {
-            // the pair seen from j: K V_i summed over this wavefront's rows
-            double c = (double)kv * vi;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
-            if ((t & 63) == 0) colp[wv][jj] = c;
+            // the pair seen from j: K V_i added to column jl's sum over this
+            // wavefront's rows, which lane ln - 1 continues at the next step
+            cacc += (double)kv * vi;
+            cacc = __shfl(cacc, from, 64);
         }
     }
     rowp[hf][il] = acc;
+    if (!diag) colp[wv][ln] = cacc;  // after 64 steps lane ln holds column ln of its half
     __syncthreads();
     if (t < kSymT) {
         const double dx = p.lx / n;
