@@ -150,6 +150,7 @@ struct sbi_ctx {
     void* full_d1 = nullptr;
     void* full_d2 = nullptr;
     void* full_s2 = nullptr;
+    void* full_s2a = nullptr;
     void* full_rhs = nullptr;
     void* full_lfl = nullptr;
     void* full_w = nullptr;
@@ -305,13 +306,13 @@ static Layout layout(const sbi_grid* g, int batch) {
                   (g->seed == SBI_SEED_NET
                        ? al(sizeof(HistDev)) + al(sizeof(double) * kHistPart * kHistBlocks * (size_t)batch)
                        : 0);
-    // fully nonlinear solve (FP64 in both precisions): tables [batch + 3][nx]
+    // fully nonlinear solve (FP64 in both precisions): tables [batch + 4][nx]
     // and [batch][nx], right-hand side and source term [batch][nx], pair
-    // slices [kFullSplitMax][batch][nx]; for beds kept as a boundary, the bed
+    // slices [full_slices(nx)][batch][nx]; for beds kept as a boundary, the bed
     // geometry (3 tables), its circulant, its right-hand side and two phi_b
     // iterates [batch][nx], and the per-member flags
     L.bytes_full = g->mode == SBI_MODE_FULL
-                       ? 14 * al((size_t)g->nx * 8 * batch) + al((size_t)full_slices(g->nx) * g->nx * 8 * batch) +
+                       ? 15 * al((size_t)g->nx * 8 * batch) + al((size_t)full_slices(g->nx) * g->nx * 8 * batch) +
                              al(sizeof(int) * batch)
                        : 0;
     // mixed precision: the FP32 context's workspace at the end
@@ -560,8 +561,9 @@ static sbi_status ctx_setup(sbi_ctx* c, const sbi_grid* g, int32_t batch, const 
         c->full_rb = p + 11 * tb;
         c->full_pb[0] = p + 12 * tb;
         c->full_pb[1] = p + 13 * tb;
-        c->full_part = p + 14 * tb;
-        c->full_bed = reinterpret_cast<int*>(p + 14 * tb + al((size_t)full_slices(g->nx) * g->nx * 8 * batch));
+        c->full_s2a = p + 14 * tb;
+        c->full_part = p + 15 * tb;
+        c->full_bed = reinterpret_cast<int*>(p + 15 * tb + al((size_t)full_slices(g->nx) * g->nx * 8 * batch));
     }
     c->col_C = L.C;
     gd.col_C = L.C;
@@ -1625,6 +1627,7 @@ static FullParams full_params(sbi_ctx* c) {
     p.d1 = c->full_d1;
     p.d2 = c->full_d2;
     p.s2 = c->full_s2;
+    p.s2a = c->full_s2a;
     p.part = c->full_part;
     p.phi = PHYS(PF_PHI);
     p.ex = PHYS(PF_EX);
@@ -1723,7 +1726,7 @@ static sbi_status full_solve(sbi_ctx* c, const void* eta_phys, double tol) {
                 c->st.launches += 1;
                 SBI_TRY(hip_ok(launch_full(c->fp64, p, sym ? FULL_SYM : FULL_SINGLE, c->stream)));
             }
-            c->st.launches += 2;
+            c->st.launches += 3;
             ProfScope ps2_(c, K_FULL_APPLY);
             SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_COMBINE, c->stream)));
             SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_APPLY, c->stream)));

@@ -106,6 +106,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_tables(const FullParams p
         static_cast<double*>(p.d2)[j] = d2 / n;
         const double sn = sinpi((double)j / n);
         static_cast<double*>(p.s2)[j] = sn * sn;
+        static_cast<double*>(p.s2a)[j] = sinpi(2.0 * (double)j / n);
     }
 }
 
@@ -197,6 +198,23 @@ __device__ __forceinline__ bool full_decided(const FullParams& p, Ctl* ctl, bool
 // KIND 0: the double layer D[phi_s] (every member); KIND 1: the single layer
 // (S - S0)[V_n] of the image-form members.  Partial sums go to
 // part[split][member][point]; the consumer adds the slices in order.
+// sinh of the small arguments of the pair kernels (scaled height differences
+// pi (y_j - y_i) / L): below 1/8 by its Taylor series to the x^11 term, nested
+// as x (1 + x^2/(2*3) (1 + x^2/(4*5) (...))), whose remainder is below 3e-21
+// of the value there; beyond it by the library function.  A difference is
+// passed as such (from exponentials of each point the sinh would lose its
+// relative accuracy for nearby points).
+template <typename R> __device__ __forceinline__ R sinh_series(R x) {
+    if (fabs(x) >= R(0.125)) return sinh(x);
+    const R x2 = x * x;
+    R s = R(1) + x2 * R(1.0 / 110.0);
+    s = R(1) + x2 * R(1.0 / 72.0) * s;
+    s = R(1) + x2 * R(1.0 / 42.0) * s;
+    s = R(1) + x2 * R(1.0 / 20.0) * s;
+    s = R(1) + x2 * R(1.0 / 6.0) * s;
+    return x * s;
+}
+
 template <typename R, int KIND>
 __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p) {
     __shared__ R te[kFullThreads], tex[kFullThreads], tsrc[kFullThreads];
@@ -216,6 +234,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
     if (KIND == 1 && full_bed(p, m)) return;  // the two-boundary surface pass serves it
     const R* src = static_cast<const R*>(KIND == 0 ? p.phi : p.vin) + mo;
     const double* s2 = static_cast<const double*>(p.s2);
+    const double* s2at = static_cast<const double*>(p.s2a);
     const double* lfl = static_cast<const double*>(p.lfl) + (long long)m * n;
     const R pl = R(M_PI / p.lx);
     const bool deep = full_deep(p, m);
@@ -246,7 +265,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
             // sinh of the scaled elevation difference, formed from the difference
             // itself (from exponentials of each point it would lose all relative
             // accuracy for nearby points)
-            const R shb = sinh(pl * (te[jj] - etai));     // sinh(pi (eta_j - eta_i) / L)
+            const R shb = sinh_series(pl * (te[jj] - etai));  // sinh(pi (eta_j - eta_i) / L)
             R kv;
             if (KIND == 1) {
                 // -1/2 ln(1 + sinh^2 / sin^2); its limit -1/2 ln(1 + eta_x^2) at j = i
@@ -254,13 +273,13 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
                 if (img) {
                     // image minus flat image: -1/2 ln(sin^2 + sinh^2(pi (eta_i + eta_j + 2h) / L))
                     // + 1/2 ln(sin^2 + sinh^2(2 pi h / L))
-                    const R shp = sinh(pl * (te[jj] + etai) + b2h);
+                    const R shp = sinh_series(pl * (te[jj] + etai) + b2h);
                     kv += R(-0.5) * log(sa2 + shp * shp) + R(lfl[d]);
                 }
             } else {
                 // Im[(pi/L) cot(a + i b) (1 + i eta_x,j)], a = pi (x_j - x_i)/L, b = pi (eta_j - eta_i)/L:
                 // cot(a + i b) = (sin 2a - i sinh 2b) / (2 (sin^2 a + sinh^2 b))
-                const R s2a = sinpi(R(2) * R(d) / R(n));  // sin 2a
+                const R s2a = R(s2at[d]);  // sin 2a
                 if (j == i) {
                     kv = R(0);  // the curvature limit is added below
                 } else {
@@ -270,7 +289,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
                 }
                 if (img) {
                     // the image partner: b' = pi (eta_i + eta_j + 2h) / L
-                    const R shp = sinh(pl * (te[jj] + etai) + b2h);
+                    const R shp = sinh_series(pl * (te[jj] + etai) + b2h);
                     const R chp = sqrt(R(1) + shp * shp);
                     const R den = R(2) * (sa2 + shp * shp);
                     kv += pl * (R(-2) * shp * chp + s2a * tex[jj]) / den;
@@ -300,22 +319,6 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
 // of the points of block I, column sums to slice I of those of block J, so
 // every point receives n / kSymT slices, one from each block, each written
 // once; a diagonal tile (I = I) evaluates all its pairs and writes rows only.
-// sinh of a scaled elevation difference, formed from the difference itself
-// (from exponentials of each point it would lose its relative accuracy for
-// nearby points): below 1/8 by its Taylor series to the x^11 term, nested as
-// x (1 + x^2/(2*3) (1 + x^2/(4*5) (...))), whose remainder is below 3e-21 of
-// the value there; beyond it by the library function
-template <typename R> __device__ __forceinline__ R sinh_of_difference(R x) {
-    if (fabs(x) >= R(0.125)) return sinh(x);
-    const R x2 = x * x;
-    R s = R(1) + x2 * R(1.0 / 110.0);
-    s = R(1) + x2 * R(1.0 / 72.0) * s;
-    s = R(1) + x2 * R(1.0 / 42.0) * s;
-    s = R(1) + x2 * R(1.0 / 20.0) * s;
-    s = R(1) + x2 * R(1.0 / 6.0) * s;
-    return x * s;
-}
-
 constexpr int kSymT = kFullSymTile;
 constexpr int kSymThreads = 2 * kSymT;  // two threads per row, each over half the tile's columns
 static_assert(kSymT / 2 == 64, "a half tile's columns are the lanes of one wavefront");
@@ -388,7 +391,7 @@ __global__ void __launch_bounds__(kSymThreads) k_full_sympairs(const FullParams 
         const int j = J * kSymT + jl;
         const int d = (j - i + n) & (n - 1);
         const R sa2 = R(s2[d]);
-        const R shb = sinh_of_difference(pl * (tej[jl] - etai));
+        const R shb = sinh_series(pl * (tej[jl] - etai));
         R kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb / sa2);
         if (img) {
             const R shp = tsj[jl] * cbi + tcj[jl] * sbi;
@@ -445,6 +448,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_spairs(const FullParams p
     const double* bxs = static_cast<const double*>(p.bx) + mb;
     const double* pbs = static_cast<const double*>(p.pbout) + mb;
     const double* s2 = static_cast<const double*>(p.s2);
+    const double* s2at = static_cast<const double*>(p.s2a);
     const R pl = R(M_PI / p.lx);
     const double pld = M_PI / p.lx;
     const bool on = i < n;
@@ -470,15 +474,15 @@ __global__ void __launch_bounds__(kFullThreads) k_full_spairs(const FullParams p
             const int j = j0 + jj;
             const int d = (j - i + n) & (n - 1);
             const R sa2 = R(s2[d]);
-            const R s2a = sinpi(R(2) * R(d) / R(n));
+            const R s2a = R(s2at[d]);
             // the bed source (x_j, b_j): -D_SB = Im[(pi/L) cot(a + i b) (1 + i b_x,j)],
             // b = pi (b_j - eta_i) / L (the bed lies below every surface point)
-            const R sh = sinh(R(pld * (tbz[jj] - (double)etai)));
+            const R sh = sinh_series(R(pld * (tbz[jj] - (double)etai)));
             const R ch = sqrt(R(1) + sh * sh);
             acc += (double)(pl * (R(-2) * sh * ch + s2a * R(tbx[jj])) / (R(2) * (sa2 + sh * sh))) * tpb[jj];
             if (hasv) {
                 // the direct single layer minus the flat one, as in the image form
-                const R shb = sinh(pl * (te[jj] - etai));
+                const R shb = sinh_series(pl * (te[jj] - etai));
                 const R kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb / sa2);
                 acc += (double)kv * (double)tsrc[jj];
             }
@@ -520,6 +524,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_bpairs(const FullParams p
     const double* bxs = static_cast<const double*>(p.bx) + mb;
     const double* pbs = KIND == 3 ? static_cast<const double*>(p.pbin) + mb : nullptr;
     const double* s2 = static_cast<const double*>(p.s2);
+    const double* s2at = static_cast<const double*>(p.s2a);
     const R pl = R(M_PI / p.lx);
     const double pld = M_PI / p.lx;
     const bool on = i < n;
@@ -547,9 +552,9 @@ __global__ void __launch_bounds__(kFullThreads) k_full_bpairs(const FullParams p
             const int j = j0 + jj;
             const int d = (j - i + n) & (n - 1);
             const R sa2 = R(s2[d]);
-            const R s2a = sinpi(R(2) * R(d) / R(n));
+            const R s2a = R(s2at[d]);
             // the surface source (x_j, eta_j) seen from the bed point (x_i, b_i)
-            const R sh = sinh(R(pld * ((double)te[jj] - bzi)));
+            const R sh = sinh_series(R(pld * ((double)te[jj] - bzi)));
             const R den = R(2) * (sa2 + sh * sh);
             if (KIND == 2) {
                 const R ch = sqrt(R(1) + sh * sh);
@@ -558,7 +563,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_bpairs(const FullParams p
                 acc += (double)(R(-0.5) * log(R(2) * den)) * (double)tsrc[jj];
                 if (j != i) {
                     // minus the bed's double layer at (x_j, b_j)
-                    const R shb = sinh(R(pld * (tbz[jj] - bzi)));
+                    const R shb = sinh_series(R(pld * (tbz[jj] - bzi)));
                     const R chb = sqrt(R(1) + shb * shb);
                     const R denb = R(2) * (sa2 + shb * shb);
                     acc += (double)(pl * (R(-2) * shb * chb + s2a * R(tbx[jj])) / denb) * tpb[jj];
@@ -635,33 +640,99 @@ __global__ void k_full_combine(const FullParams p) {
 }
 
 // --- V_(n+1) = S0^-1 w (+ S0^-1 (S0 - S_flat)[V_n] in the two-boundary form)
-// and the residual maxima max|V_(n+1) - V_n|,
-// max|V_(n+1)| into the member's slot `sweep`
+// in two passes.  The sum pass: workgroup (x, s) forms the kApOuts outputs of
+// block x over source slice s; a thread forms kApR consecutive outputs over one
+// of kApLanes ranges of the slice (its wavefront's: the source value is
+// wave-uniform), keeping the kApR circulant entries c[i + r - j] as a window
+// that moves by one entry per source point, so each step loads one table entry
+// for kApR products; the ranges are added in LDS in a fixed order and the
+// slice's sums go to the pair-pass slices, spent by then.  The finish pass adds
+// the slices in order and takes the residual maxima max|V_(n+1) - V_n|,
+// max|V_(n+1)| into the member's slot `sweep`.
+constexpr int kApR = 4, kApLanes = 8, kApB = 16;
+constexpr int kApThreads = 64 * kApLanes;
+constexpr int kApOuts = 64 * kApR;  // outputs per workgroup
+// source slices of the sum pass: enough workgroups to cover the chip at 4096
+// points, each lane's range at least kApB points when n allows
+__host__ __device__ constexpr int apply_slices(int n) { return n / 128 < 1 ? 1 : (n / 128 > 16 ? 16 : n / 128); }
+
 template <typename R>
-__global__ void __launch_bounds__(kFullThreads) k_full_apply(const FullParams p) {
+__global__ void __launch_bounds__(kApThreads) k_full_apply(const FullParams p) {
+    __shared__ double red[kApLanes][kApOuts];
     const int t = threadIdx.x;
-    const int i = blockIdx.x * kOutPerBlock + t / kLanes;
-    const int l = t % kLanes;
+    const int m = blockIdx.z;
+    const int n = p.n;
+    const int msk = n - 1;
+    if (p.ctl[m].done) return;  // decided by this sweep's pair pass (workgroup-uniform)
+    const long long mo = m * p.s_phys;
+    const int lane = __builtin_amdgcn_readfirstlane(t / 64);
+    const int o0 = (t & 63) * kApR;  // this thread's first output within the workgroup
+    const int i0 = blockIdx.x * kApOuts + o0;
+    const int ns = apply_slices(n);
+    const int sl = n / ns;  // points per slice (n and ns are powers of two)
+    const int jn = (sl + kApLanes - 1) / kApLanes;
+    const int jb = blockIdx.y * sl + lane * jn, je = min(blockIdx.y * sl + sl, jb + jn);
+    double acc[kApR];
+#pragma unroll
+    for (int r = 0; r < kApR; ++r) acc[r] = 0.0;
+    // acc_r += sum_j tab[(i0 + r - j) mod n] src_j over this lane's range, in
+    // blocks of kApB source points whose table entries and source values are
+    // all requested before the block's products (one memory latency per block)
+    auto circ = [&](const double* tab, auto src) __attribute__((always_inline)) {
+        double cw[kApR];
+#pragma unroll
+        for (int r = 0; r < kApR; ++r) cw[r] = tab[(i0 + r - jb) & msk];
+        for (int j0 = jb; j0 < je; j0 += kApB) {
+            double nx[kApB], sv[kApB];
+#pragma unroll
+            for (int q = 0; q < kApB; ++q) {
+                const int j = j0 + q;
+                nx[q] = tab[(i0 - j - 1) & msk];        // enters the window after point j
+                sv[q] = j < je ? (double)src[j] : 0.0;  // a short range (small n) ends inside a block
+            }
+#pragma unroll
+            for (int q = 0; q < kApB; ++q) {
+#pragma unroll
+                for (int r = 0; r < kApR; ++r) acc[r] += cw[r] * sv[q];
+#pragma unroll
+                for (int r = kApR - 1; r > 0; --r) cw[r] = cw[r - 1];
+                cw[0] = nx[q];
+            }
+        }
+    };
+    if (jb < je) {
+        circ(static_cast<const double*>(p.c0) + (long long)m * n, static_cast<const double*>(p.w) + (long long)m * n);
+        if (p.vin && full_bed(p, m))
+            // + S0^-1 (S0 - S_flat)[V_n] of the two-boundary form
+            circ(static_cast<const double*>(p.cm) + (long long)m * n, static_cast<const R*>(p.vin) + mo);
+    }
+#pragma unroll
+    for (int r = 0; r < kApR; ++r) red[lane][o0 + r] = acc[r];
+    __syncthreads();
+    const int i = blockIdx.x * kApOuts + t;
+    if (t < kApOuts && i < n) {
+        double a = 0.0;
+#pragma unroll
+        for (int l = 0; l < kApLanes; ++l) a += red[l][t];
+        static_cast<double*>(p.part)[((long long)blockIdx.y * p.batch + m) * n + i] = a;
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kFullThreads) k_full_finish(const FullParams p) {
+    const int t = threadIdx.x;
+    const int i = blockIdx.x * kFullThreads + t;
     const int m = blockIdx.z;
     const int n = p.n;
     Ctl* ctl = p.ctl + m;
-    if (ctl->done) return;  // decided by this sweep's pair pass (workgroup-uniform)
+    if (ctl->done) return;  // workgroup-uniform
     const long long mo = m * p.s_phys;
-    const double* w = static_cast<const double*>(p.w) + (long long)m * n;
-    const double* c = static_cast<const double*>(p.c0) + (long long)m * n;
-    double acc = 0.0;
-    if (i < n)
-        for (int j = l; j < n; j += kLanes) acc += c[(i - j + n) & (n - 1)] * w[j];
-    if (i < n && p.vin && full_bed(p, m)) {
-        // + S0^-1 (S0 - S_flat)[V_n] of the two-boundary form
-        const double* cm = static_cast<const double*>(p.cm) + (long long)m * n;
-        const R* vn = static_cast<const R*>(p.vin) + mo;
-        for (int j = l; j < n; j += kLanes) acc += cm[(i - j + n) & (n - 1)] * (double)vn[j];
-    }
-    acc = lane_fold(acc);
     unsigned long long nu = 0ull, de = 0ull;
-    if (i < n && l == 0) {
-        const R v = R(acc);
+    if (i < n) {
+        const int ns = apply_slices(n);
+        double a = 0.0;
+        for (int s2 = 0; s2 < ns; ++s2) a += static_cast<const double*>(p.part)[((long long)s2 * p.batch + m) * n + i];
+        const R v = R(a);
         static_cast<R*>(p.vout)[mo + i] = v;
         const double vold = p.vin ? (double)static_cast<const R*>(p.vin)[mo + i] : 0.0;
         nu = abs_bits((double)v - vold);
@@ -710,9 +781,14 @@ template <> hipError_t launch_full_t<Real>(const FullParams& p, int what, hipStr
         case FULL_COMBINE:
             hipLaunchKernelGGL(k_full_combine<Real>, dim3(tiles, 1, p.batch), dim3(kFullThreads), 0, s, p);
             break;
-        case FULL_APPLY:
-            hipLaunchKernelGGL(k_full_apply<Real>, dim3(outs, 1, p.batch), dim3(kFullThreads), 0, s, p);
+        case FULL_APPLY: {
+            hipLaunchKernelGGL(k_full_apply<Real>, dim3((n + kApOuts - 1) / kApOuts, apply_slices(n), p.batch),
+                               dim3(kApThreads), 0, s, p);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_full_finish<Real>, dim3(tiles, 1, p.batch), dim3(kFullThreads), 0, s, p);
             break;
+        }
         case FULL_SELECT:
             hipLaunchKernelGGL(k_full_select<Real>, dim3(tiles, 1, p.batch), dim3(kFullThreads), 0, s, p);
             break;

@@ -10,7 +10,7 @@ namespace sbi {
 // Fully nonlinear W solve of one-dimensional grids (sbi_full.hip): the
 // operands of its kernels.  Physical fields are [batch][n] with member
 // stride s_phys; FP64 tables: c0 [batch][n] (S0^-1 circulant per member), d1,
-// d2, s2 [n]; FP64 part [nsplit][batch][n] holds the slices of a pair pass and
+// d2, s2, s2a [n]; FP64 part [slices][batch][n] holds the slices of a pair pass (then of the apply) and
 // rhs [batch][n] the right-hand side.  Members whose bed is kept as a boundary
 // of its own (bed[m] = 1: a variable bed not too deep to matter) use the
 // two-boundary form: bed geometry bz, bx, bxx, the circulant cm of
@@ -26,11 +26,12 @@ struct FullParams {
     void* ex;             // eta_x
     void* exx;            // eta_xx
     void* rhs;            // pi phi_s + D[phi_s] (FP64, [batch][n])
-    void* part;           // pair-pass slices
+    void* part;           // pair-pass slices, then the apply's source slices
     void* c0;
     void* d1;
     void* d2;
     void* s2;
+    void* s2a;            // [n] sin(2 pi j / n) of each index distance
     void* lfl;            // [batch][n] the flat image's single-layer term per member
     void* w;              // FP64 [batch][n]: rhs - (S - S0)[V_n]
     const void* vin;      // V_n (null: V_0 = 0)
