@@ -1382,7 +1382,10 @@ static sbi_status run_sa(sbi_ctx* c, const void* eta_phys) {
         const int np = (l - 1) * (1 + (c->vd ? (two_d ? 2 : 1) : 0)) + (two_d ? 2 : 1);
         if (np > kMaxProd) return SBI_ERR_UNSUPPORTED;
         for (int i = 0; i < np; ++i) rp.h[i] = HALF(H_PROD0 + i);
-        rp.split = two_d ? 0 : np;  // a 1D row: one workgroup per product
+        // few rows (a 1D grid, or up to 1024 rows over all members): one
+        // workgroup per product, so that the pass is not one long chain of
+        // transforms per row block
+        rp.split = (!two_d || (long long)c->grid.ny * c->batch <= 1024) ? np : 0;
         c->st.launches += 1;
         {
         ProfScope ps_(c, K_ROW_SA);

@@ -455,44 +455,50 @@ __global__ void __launch_bounds__((row_threads<NX, RowVar<R, NX, VAR>::E>()))
     ROW_PROLOGUE_T(RowVar<R, NX, VAR>)
     const int l = p.l;
     if (p.split > 0) {
-        // a 1D grid has one row per member: its products go to workgroups of
-        // their own (blockIdx.y): eta^j V_(l-j) for j < l, then, over a
-        // variable bed, delta^j d_x phi_b,(l-j), then eta^(l-1) d_x phi_s,
-        // each formed by the same operations as in the sequential form below
+        // few rows (a 1D grid, a small 2D one): each product of the order in a
+        // workgroup of its own (blockIdx.y), in the order of the sequential
+        // form below and formed by the same operations: eta^j V_(l-j) for
+        // j < l; over a variable bed delta^j d_x phi_b,(l-j), then (2D)
+        // delta^j d_y phi_b,(l-j); then eta^(l-1) d_x phi_s (and d_y phi_s)
         const int nv = l - 1;
+        const int ncomp = p.g.ny > 1 ? 2 : 1;
+        const int nb = p.vd ? ncomp * nv : 0;
         const int part = blockIdx.y;
-        const int fam = part < nv ? 0 : ((p.vd && part < 2 * nv) ? 1 : 2);
+        // fam 0: V; 1: bed component comp; 2: forcing component comp
+        const int fam = part < nv ? 0 : (part < nv + nb ? 1 : 2);
+        const int comp = fam == 1 ? (part - nv) / nv : (fam == 2 ? part - nv - nb : 0);
         V base[E], pw[E], src[E];
         RW::load(base, static_cast<const R*>(fam == 1 ? p.delta : p.eta) + po, ri.j, ri.valid);
 #pragma unroll
         for (int q = 0; q < E; ++q) pw[q] = base[q];
         if (fam < 2) {
-            const int jj = part - fam * nv + 1;
+            const int jj = (fam == 0 ? part : (part - nv) % nv) + 1;
             if (jj == 1) {
-                RW::inverse(src, static_cast<const V*>(fam == 0 ? p.gV : p.gbx) + hb, nullptr, R(0), rc, lds_all,
-                            twN, twX, iscale);
-                void* outp = fam == 0 ? p.V_out : p.bx_out;
+                const void* g = fam == 0 ? p.gV : (comp == 0 ? p.gbx : p.gby);
+                RW::inverse(src, static_cast<const V*>(g) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+                void* outp = fam == 0 ? p.V_out : (comp == 0 ? p.bx_out : p.by_out);
                 if (outp) RW::store(src, static_cast<R*>(outp) + po, ri.j, ri.valid);
             } else {
                 for (int i = 2; i <= jj; ++i) {
 #pragma unroll
                     for (int q = 0; q < E; ++q) pw[q] = rmul(pw[q], base[q]);
                 }
-                RW::load(src, static_cast<const R*>(fam == 0 ? p.Vphys[l - jj] : p.bxphys[l - jj]) + po, ri.j,
-                         ri.valid);
+                const void* const* phys = fam == 0 ? p.Vphys : (comp == 0 ? p.bxphys : p.byphys);
+                RW::load(src, static_cast<const R*>(phys[l - jj]) + po, ri.j, ri.valid);
             }
 #pragma unroll
             for (int q = 0; q < E; ++q) src[q] = rmul(pw[q], src[q]);
-            RW::forward(src, static_cast<V*>(p.h[fam * nv + jj - 1]) + hb, rc, lds_all, twN, twX);
+            const int idx = fam == 0 ? jj - 1 : nv + comp * nv + jj - 1;
+            RW::forward(src, static_cast<V*>(p.h[idx]) + hb, rc, lds_all, twN, twX);
         } else {
             for (int i = 2; i <= nv; ++i) {
 #pragma unroll
                 for (int q = 0; q < E; ++q) pw[q] = rmul(pw[q], base[q]);
             }
-            RW::load(src, static_cast<const R*>(p.phx) + po, ri.j, ri.valid);
+            RW::load(src, static_cast<const R*>(comp == 0 ? p.phx : p.phy) + po, ri.j, ri.valid);
 #pragma unroll
             for (int q = 0; q < E; ++q) src[q] = rmul(pw[q], src[q]);
-            RW::forward(src, static_cast<V*>(p.h[(p.vd ? 2 : 1) * nv]) + hb, rc, lds_all, twN, twX);
+            RW::forward(src, static_cast<V*>(p.h[nv + nb + comp]) + hb, rc, lds_all, twN, twX);
         }
         return;
     }

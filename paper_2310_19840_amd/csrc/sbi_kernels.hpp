@@ -73,7 +73,7 @@ struct RowSaParams {
     const void* phx;    // physical grad phi_s
     const void* phy;
     void* h[kMaxProd];
-    int split;          // 1D grids: > 0 workgroups per row, one product each (blockIdx.y)
+    int split;          // > 0: workgroups per row block, one product each (blockIdx.y)
 };
 
 constexpr int kMaxWavemaker = 8;   // pneumatic wavemaker components
