@@ -949,6 +949,8 @@ static sbi_status row_setup(sbi_ctx* c, const void* eta_user) {
     rp.nprod = iter ? (c->grid.order - 1) * (two_d ? 2 : 1) : 0;
     for (int i = 0; i < rp.nprod; ++i) rp.h[i] = HALF(H_PROD0 + i);
     rp.ctl = c->ctl;
+    // the two components' product chains in workgroups of their own
+    rp.nfam = (two_d && rp.nprod > 0) ? 2 : 1;
     c->st.launches += 1;
     {
         ProfScope ps_(c, K_ROW_SETUP);

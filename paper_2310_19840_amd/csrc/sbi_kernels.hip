@@ -277,15 +277,23 @@ template <typename R, int NX>
 __global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupParams p, const typename cplx_of<R>::type* twN_tab,
                             const typename cplx_of<R>::type* twX_tab) {
     ROW_PROLOGUE(R, NX)
+    const bool two_d = p.g.ny > 1;
+    // with two families (p.nfam = 2, 2D iteration) workgroup row y = 1 takes
+    // the y component: its own copy of eta, d_y phi and their products, formed
+    // by the same operations as in one family
+    const int fam = blockIdx.y;
+    const bool want_x = fam == 0;
+    const bool want_y = two_d && (p.nfam < 2 || fam == 1);
     V e[E];
     if (p.g_eta) {
         RW::inverse(e, static_cast<const V*>(p.g_eta) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
     } else {
         RW::load(e, static_cast<const R*>(p.eta_in) + po, ri.j, ri.valid);
     }
-    if (p.eta_out) RW::store(e, static_cast<R*>(p.eta_out) + po, ri.j, ri.valid);
-    // extrema of eta (relaxation weight)
-    {
+    int bad = 0;
+    if (fam == 0) {
+        if (p.eta_out) RW::store(e, static_cast<R*>(p.eta_out) + po, ri.j, ri.valid);
+        // extrema of eta (relaxation weight)
         unsigned long long mx = 0ull, mn = ~0ull;
         if (ri.valid) {
 #pragma unroll
@@ -303,25 +311,25 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupP
             atomicMax(&p.ctl[ri.mem].eta_max, mx);
             atomicMin(&p.ctl[ri.mem].eta_min, mn);
         }
-    }
-    int bad = 0;
-    if (ri.valid) {
+        if (ri.valid) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) bad |= !isfinite((double)e[q].x) || !isfinite((double)e[q].y);
+            for (int q = 0; q < E; ++q) bad |= !isfinite((double)e[q].x) || !isfinite((double)e[q].y);
+        }
     }
     V px[E], py[E];
-    RW::inverse(px, static_cast<const V*>(p.g_px) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
-    if (p.px_out) RW::store(px, static_cast<R*>(p.px_out) + po, ri.j, ri.valid);
-    const bool two_d = p.g.ny > 1;
-    if (two_d) {
+    if (want_x) {
+        RW::inverse(px, static_cast<const V*>(p.g_px) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
+        if (p.px_out) RW::store(px, static_cast<R*>(p.px_out) + po, ri.j, ri.valid);
+    }
+    if (want_y) {
         RW::inverse(py, static_cast<const V*>(p.g_py) + hb, nullptr, R(0), rc, lds_all, twN, twX, iscale);
         if (p.py_out) RW::store(py, static_cast<R*>(p.py_out) + po, ri.j, ri.valid);
     }
     if (ri.valid) {
 #pragma unroll
         for (int q = 0; q < E; ++q) {
-            bad |= !isfinite((double)px[q].x) || !isfinite((double)px[q].y);
-            if (two_d) bad |= !isfinite((double)py[q].x) || !isfinite((double)py[q].y);
+            if (want_x) bad |= !isfinite((double)px[q].x) || !isfinite((double)px[q].y);
+            if (want_y) bad |= !isfinite((double)py[q].x) || !isfinite((double)py[q].y);
         }
     }
     if (bad && p.ctl) atomicOr(&p.ctl[ri.mem].nonfinite, 1);
@@ -329,20 +337,23 @@ __global__ void __launch_bounds__(row_threads<NX>()) k_row_setup(const RowSetupP
         V ep[E];
 #pragma unroll
         for (int q = 0; q < E; ++q) ep[q] = e[q];
-        int idx = 0;
         for (int l = 2; l <= p.g.order; ++l) {
             if (l > 2) {
 #pragma unroll
                 for (int q = 0; q < E; ++q) ep[q] = rmul(ep[q], e[q]);
             }
+            // products of order l: x at 2 (l - 2), y at 2 (l - 2) + 1 (1D: l - 2)
+            const int idx = two_d ? 2 * (l - 2) : l - 2;
             V w[E];
+            if (want_x) {
 #pragma unroll
-            for (int q = 0; q < E; ++q) w[q] = rmul(ep[q], px[q]);
-            RW::forward(w, static_cast<V*>(p.h[idx++]) + hb, rc, lds_all, twN, twX);
-            if (two_d) {
+                for (int q = 0; q < E; ++q) w[q] = rmul(ep[q], px[q]);
+                RW::forward(w, static_cast<V*>(p.h[idx]) + hb, rc, lds_all, twN, twX);
+            }
+            if (want_y) {
 #pragma unroll
                 for (int q = 0; q < E; ++q) w[q] = rmul(ep[q], py[q]);
-                RW::forward(w, static_cast<V*>(p.h[idx++]) + hb, rc, lds_all, twN, twX);
+                RW::forward(w, static_cast<V*>(p.h[idx + 1]) + hb, rc, lds_all, twN, twX);
             }
         }
     }
@@ -1952,6 +1963,7 @@ __global__ void k_diag(const DiagParams p) {
 template <typename PT> static int row_families(const PT&) { return 1; }
 static int row_families(const RowSweepParams& p) { return p.nfam > 0 ? p.nfam : 1; }
 static int row_families(const RowSaParams& p) { return p.split > 0 ? p.split : 1; }
+static int row_families(const RowSetupParams& p) { return p.nfam > 1 ? p.nfam : 1; }
 
 template <typename RWT> struct RowLaunch {
     using V = typename RWT::V;

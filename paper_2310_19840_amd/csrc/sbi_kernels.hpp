@@ -34,6 +34,7 @@ struct RowSetupParams {
     int nprod;                // forcing products eta^(l-1) grad phi, l = 2..L
     void* h[kMaxProd];
     Ctl* ctl;
+    int nfam;                 // 2: the x and y components in workgroups of their own (blockIdx.y)
 };
 
 struct RowSweepParams {
