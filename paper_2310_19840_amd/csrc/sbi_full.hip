@@ -122,33 +122,6 @@ __device__ __forceinline__ double lane_fold(double v) {
     return v;
 }
 
-// --- eta_x, eta_xx at every point: circulant sums over the member's eta
-template <typename R>
-__global__ void __launch_bounds__(kFullThreads) k_full_geom(const FullParams p) {
-    const int t = threadIdx.x;
-    const int i = blockIdx.x * kOutPerBlock + t / kLanes;
-    const int l = t % kLanes;
-    const int m = blockIdx.z;
-    const int n = p.n;
-    const R* eta = static_cast<const R*>(p.eta) + m * p.s_phys;
-    const double* d1 = static_cast<const double*>(p.d1);
-    const double* d2 = static_cast<const double*>(p.d2);
-    double a1 = 0.0, a2 = 0.0;
-    if (i < n)
-        for (int j = l; j < n; j += kLanes) {
-            const int d = (i - j + n) & (n - 1);  // n is a power of two
-            const double e = (double)eta[j];
-            a1 += d1[d] * e;
-            a2 += d2[d] * e;
-        }
-    a1 = lane_fold(a1);
-    a2 = lane_fold(a2);
-    if (i < n && l == 0) {
-        static_cast<R*>(p.ex)[m * p.s_phys + i] = R(a1);
-        static_cast<R*>(p.exx)[m * p.s_phys + i] = R(a2);
-    }
-}
-
 // --- b_x, b_xx of each member's bed (FP64 heights bz) at set-up
 template <typename R>
 __global__ void __launch_bounds__(kFullThreads) k_full_bedgeom(const FullParams p) {
@@ -656,6 +629,41 @@ constexpr int kApOuts = 64 * kApR;  // outputs per workgroup
 // points, each lane's range at least kApB points when n allows
 __host__ __device__ constexpr int apply_slices(int n) { return n / 128 < 1 ? 1 : (n / 128 > 16 ? 16 : n / 128); }
 
+
+// acc[k][r] += sum_j tab[k][(i0 + r - j) mod n] src_j over j in [jb, je), for
+// NT tables against one source, in blocks of kApB source points whose table
+// entries and source values are all requested before the block's products
+// (one memory latency per block)
+template <int NT, typename S>
+__device__ __forceinline__ void circ_window(const double* const (&tab)[NT], const S* src, int i0, int jb, int je,
+                                            int msk, double (&acc)[NT][kApR]) {
+    double cw[NT][kApR];
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+#pragma unroll
+        for (int r = 0; r < kApR; ++r) cw[k][r] = tab[k][(i0 + r - jb) & msk];
+    for (int j0 = jb; j0 < je; j0 += kApB) {
+        double nx[NT][kApB], sv[kApB];
+#pragma unroll
+        for (int q = 0; q < kApB; ++q) {
+            const int j = j0 + q;
+#pragma unroll
+            for (int k = 0; k < NT; ++k) nx[k][q] = tab[k][(i0 - j - 1) & msk];  // enters the window after point j
+            sv[q] = j < je ? (double)src[j] : 0.0;  // a short range (small n) ends inside a block
+        }
+#pragma unroll
+        for (int q = 0; q < kApB; ++q)
+#pragma unroll
+            for (int k = 0; k < NT; ++k) {
+#pragma unroll
+                for (int r = 0; r < kApR; ++r) acc[k][r] += cw[k][r] * sv[q];
+#pragma unroll
+                for (int r = kApR - 1; r > 0; --r) cw[k][r] = cw[k][r - 1];
+                cw[k][0] = nx[k][q];
+            }
+    }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kApThreads) k_full_apply(const FullParams p) {
     __shared__ double red[kApLanes][kApOuts];
@@ -672,42 +680,20 @@ __global__ void __launch_bounds__(kApThreads) k_full_apply(const FullParams p) {
     const int sl = n / ns;  // points per slice (n and ns are powers of two)
     const int jn = (sl + kApLanes - 1) / kApLanes;
     const int jb = blockIdx.y * sl + lane * jn, je = min(blockIdx.y * sl + sl, jb + jn);
-    double acc[kApR];
+    double acc[1][kApR];
 #pragma unroll
-    for (int r = 0; r < kApR; ++r) acc[r] = 0.0;
-    // acc_r += sum_j tab[(i0 + r - j) mod n] src_j over this lane's range, in
-    // blocks of kApB source points whose table entries and source values are
-    // all requested before the block's products (one memory latency per block)
-    auto circ = [&](const double* tab, auto src) __attribute__((always_inline)) {
-        double cw[kApR];
-#pragma unroll
-        for (int r = 0; r < kApR; ++r) cw[r] = tab[(i0 + r - jb) & msk];
-        for (int j0 = jb; j0 < je; j0 += kApB) {
-            double nx[kApB], sv[kApB];
-#pragma unroll
-            for (int q = 0; q < kApB; ++q) {
-                const int j = j0 + q;
-                nx[q] = tab[(i0 - j - 1) & msk];        // enters the window after point j
-                sv[q] = j < je ? (double)src[j] : 0.0;  // a short range (small n) ends inside a block
-            }
-#pragma unroll
-            for (int q = 0; q < kApB; ++q) {
-#pragma unroll
-                for (int r = 0; r < kApR; ++r) acc[r] += cw[r] * sv[q];
-#pragma unroll
-                for (int r = kApR - 1; r > 0; --r) cw[r] = cw[r - 1];
-                cw[0] = nx[q];
-            }
-        }
-    };
+    for (int r = 0; r < kApR; ++r) acc[0][r] = 0.0;
     if (jb < je) {
-        circ(static_cast<const double*>(p.c0) + (long long)m * n, static_cast<const double*>(p.w) + (long long)m * n);
-        if (p.vin && full_bed(p, m))
+        const double* const c0[1] = {static_cast<const double*>(p.c0) + (long long)m * n};
+        circ_window<1>(c0, static_cast<const double*>(p.w) + (long long)m * n, i0, jb, je, msk, acc);
+        if (p.vin && full_bed(p, m)) {
             // + S0^-1 (S0 - S_flat)[V_n] of the two-boundary form
-            circ(static_cast<const double*>(p.cm) + (long long)m * n, static_cast<const R*>(p.vin) + mo);
+            const double* const cm[1] = {static_cast<const double*>(p.cm) + (long long)m * n};
+            circ_window<1>(cm, static_cast<const R*>(p.vin) + mo, i0, jb, je, msk, acc);
+        }
     }
 #pragma unroll
-    for (int r = 0; r < kApR; ++r) red[lane][o0 + r] = acc[r];
+    for (int r = 0; r < kApR; ++r) red[lane][o0 + r] = acc[0][r];
     __syncthreads();
     const int i = blockIdx.x * kApOuts + t;
     if (t < kApOuts && i < n) {
@@ -746,6 +732,70 @@ __global__ void __launch_bounds__(kFullThreads) k_full_finish(const FullParams p
     }
 }
 
+// --- eta_x, eta_xx at every point: the circulant sums d1 * eta and d2 * eta
+// by the apply's sum pass (both tables against eta; the ex slices first, then
+// the exx slices, in the pair-pass slices, free at the start of a solve) and a
+// pass that adds the slices in order
+__host__ __device__ constexpr int geom_slices(int n) { return apply_slices(n) / 2 < 1 ? 1 : apply_slices(n) / 2; }
+
+template <typename R>
+__global__ void __launch_bounds__(kApThreads) k_full_geom(const FullParams p) {
+    __shared__ double red[2][kApLanes][kApOuts];
+    const int t = threadIdx.x;
+    const int m = blockIdx.z;
+    const int n = p.n;
+    const int msk = n - 1;
+    const int lane = __builtin_amdgcn_readfirstlane(t / 64);
+    const int o0 = (t & 63) * kApR;
+    const int i0 = blockIdx.x * kApOuts + o0;
+    const int ns = geom_slices(n);
+    const int sl = n / ns;
+    const int jn = (sl + kApLanes - 1) / kApLanes;
+    const int jb = blockIdx.y * sl + lane * jn, je = min(blockIdx.y * sl + sl, jb + jn);
+    double acc[2][kApR];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int r = 0; r < kApR; ++r) acc[k][r] = 0.0;
+    if (jb < je) {
+        const double* const tab[2] = {static_cast<const double*>(p.d1), static_cast<const double*>(p.d2)};
+        circ_window<2>(tab, static_cast<const R*>(p.eta) + m * p.s_phys, i0, jb, je, msk, acc);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int r = 0; r < kApR; ++r) red[k][lane][o0 + r] = acc[k][r];
+    __syncthreads();
+    const int i = blockIdx.x * kApOuts + t;
+    if (t < kApOuts && i < n) {
+        double* part = static_cast<double*>(p.part);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            double a = 0.0;
+#pragma unroll
+            for (int l = 0; l < kApLanes; ++l) a += red[k][l][t];
+            part[((long long)(k * ns + blockIdx.y) * p.batch + m) * n + i] = a;
+        }
+    }
+}
+
+template <typename R>
+__global__ void k_full_geomfin(const FullParams p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = blockIdx.z;
+    const int n = p.n;
+    if (i >= n) return;
+    const int ns = geom_slices(n);
+    const double* part = static_cast<const double*>(p.part);
+    double a1 = 0.0, a2 = 0.0;
+    for (int s = 0; s < ns; ++s) {
+        a1 += part[((long long)s * p.batch + m) * n + i];
+        a2 += part[((long long)(ns + s) * p.batch + m) * n + i];
+    }
+    static_cast<R*>(p.ex)[m * p.s_phys + i] = R(a1);
+    static_cast<R*>(p.exx)[m * p.s_phys + i] = R(a2);
+}
+
 // --- the decided iterate V_s of every member (s = its sweep count) -> out
 template <typename R>
 __global__ void k_full_select(const FullParams p) {
@@ -766,9 +816,14 @@ template <> hipError_t launch_full_t<Real>(const FullParams& p, int what, hipStr
         case FULL_TABLES:
             hipLaunchKernelGGL(k_full_tables<Real>, dim3(tiles, p.batch), dim3(kFullThreads), 0, s, p);
             break;
-        case FULL_GEOM:
-            hipLaunchKernelGGL(k_full_geom<Real>, dim3(outs, 1, p.batch), dim3(kFullThreads), 0, s, p);
+        case FULL_GEOM: {
+            hipLaunchKernelGGL(k_full_geom<Real>, dim3((n + kApOuts - 1) / kApOuts, geom_slices(n), p.batch),
+                               dim3(kApThreads), 0, s, p);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_full_geomfin<Real>, dim3(tiles, 1, p.batch), dim3(kFullThreads), 0, s, p);
             break;
+        }
         case FULL_DOUBLE:
             hipLaunchKernelGGL((k_full_pairs<Real, 0>), dim3(tiles, p.nsplit, p.batch), dim3(kFullThreads), 0, s, p);
             break;
