@@ -151,6 +151,7 @@ struct sbi_ctx {
     void* full_d2 = nullptr;
     void* full_s2 = nullptr;
     void* full_s2a = nullptr;
+    void* full_rs2 = nullptr;
     void* full_rhs = nullptr;
     void* full_lfl = nullptr;
     void* full_w = nullptr;
@@ -306,13 +307,13 @@ static Layout layout(const sbi_grid* g, int batch) {
                   (g->seed == SBI_SEED_NET
                        ? al(sizeof(HistDev)) + al(sizeof(double) * kHistPart * kHistBlocks * (size_t)batch)
                        : 0);
-    // fully nonlinear solve (FP64 in both precisions): tables [batch + 4][nx]
+    // fully nonlinear solve (FP64 in both precisions): tables [batch + 5][nx]
     // and [batch][nx], right-hand side and source term [batch][nx], pair
     // slices [full_slices(nx)][batch][nx]; for beds kept as a boundary, the bed
     // geometry (3 tables), its circulant, its right-hand side and two phi_b
     // iterates [batch][nx], and the per-member flags
     L.bytes_full = g->mode == SBI_MODE_FULL
-                       ? 15 * al((size_t)g->nx * 8 * batch) + al((size_t)full_slices(g->nx) * g->nx * 8 * batch) +
+                       ? 16 * al((size_t)g->nx * 8 * batch) + al((size_t)full_slices(g->nx) * g->nx * 8 * batch) +
                              al(sizeof(int) * batch)
                        : 0;
     // mixed precision: the FP32 context's workspace at the end
@@ -562,8 +563,9 @@ static sbi_status ctx_setup(sbi_ctx* c, const sbi_grid* g, int32_t batch, const 
         c->full_pb[0] = p + 12 * tb;
         c->full_pb[1] = p + 13 * tb;
         c->full_s2a = p + 14 * tb;
-        c->full_part = p + 15 * tb;
-        c->full_bed = reinterpret_cast<int*>(p + 15 * tb + al((size_t)full_slices(g->nx) * g->nx * 8 * batch));
+        c->full_rs2 = p + 15 * tb;
+        c->full_part = p + 16 * tb;
+        c->full_bed = reinterpret_cast<int*>(p + 16 * tb + al((size_t)full_slices(g->nx) * g->nx * 8 * batch));
     }
     c->col_C = L.C;
     gd.col_C = L.C;
@@ -1633,6 +1635,7 @@ static FullParams full_params(sbi_ctx* c) {
     p.d2 = c->full_d2;
     p.s2 = c->full_s2;
     p.s2a = c->full_s2a;
+    p.rs2 = c->full_rs2;
     p.part = c->full_part;
     p.phi = PHYS(PF_PHI);
     p.ex = PHYS(PF_EX);

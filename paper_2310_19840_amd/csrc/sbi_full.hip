@@ -107,6 +107,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_tables(const FullParams p
         const double sn = sinpi((double)j / n);
         static_cast<double*>(p.s2)[j] = sn * sn;
         static_cast<double*>(p.s2a)[j] = sinpi(2.0 * (double)j / n);
+        static_cast<double*>(p.rs2)[j] = j == 0 ? 0.0 : 1.0 / (sn * sn);  // unused at j = 0 (the pair limit)
     }
 }
 
@@ -188,6 +189,25 @@ template <typename R> __device__ __forceinline__ R sinh_series(R x) {
     return x * s;
 }
 
+// sinh and cosh of a small argument together: below 1/8 both by their Taylor
+// series (cosh to the x^12 term, nested as 1 + x^2/(1*2) (1 + x^2/(3*4) (...)),
+// remainder below 3e-24), beyond it the library sinh and cosh = sqrt(1 + sinh^2)
+template <typename R> __device__ __forceinline__ R sinh_cosh_series(R x, R* ch) {
+    if (fabs(x) >= R(0.125)) {
+        const R sh = sinh(x);
+        *ch = sqrt(R(1) + sh * sh);
+        return sh;
+    }
+    const R x2 = x * x;
+    R c = R(1) + x2 * R(1.0 / 132.0);
+    c = R(1) + x2 * R(1.0 / 90.0) * c;
+    c = R(1) + x2 * R(1.0 / 56.0) * c;
+    c = R(1) + x2 * R(1.0 / 30.0) * c;
+    c = R(1) + x2 * R(1.0 / 12.0) * c;
+    *ch = R(1) + x2 * R(0.5) * c;
+    return sinh_series(x);
+}
+
 template <typename R, int KIND>
 __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p) {
     __shared__ R te[kFullThreads], tex[kFullThreads], tsrc[kFullThreads];
@@ -207,6 +227,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
     if (KIND == 1 && full_bed(p, m)) return;  // the two-boundary surface pass serves it
     const R* src = static_cast<const R*>(KIND == 0 ? p.phi : p.vin) + mo;
     const double* s2 = static_cast<const double*>(p.s2);
+    const double* rs2 = static_cast<const double*>(p.rs2);
     const double* s2at = static_cast<const double*>(p.s2a);
     const double* lfl = static_cast<const double*>(p.lfl) + (long long)m * n;
     const R pl = R(M_PI / p.lx);
@@ -238,11 +259,12 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
             // sinh of the scaled elevation difference, formed from the difference
             // itself (from exponentials of each point it would lose all relative
             // accuracy for nearby points)
-            const R shb = sinh_series(pl * (te[jj] - etai));  // sinh(pi (eta_j - eta_i) / L)
+            R chb;
+            const R shb = sinh_cosh_series(pl * (te[jj] - etai), &chb);  // sinh(pi (eta_j - eta_i) / L)
             R kv;
             if (KIND == 1) {
                 // -1/2 ln(1 + sinh^2 / sin^2); its limit -1/2 ln(1 + eta_x^2) at j = i
-                kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb / sa2);
+                kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb * R(rs2[d]));
                 if (img) {
                     // image minus flat image: -1/2 ln(sin^2 + sinh^2(pi (eta_i + eta_j + 2h) / L))
                     // + 1/2 ln(sin^2 + sinh^2(2 pi h / L))
@@ -256,14 +278,13 @@ __global__ void __launch_bounds__(kFullThreads) k_full_pairs(const FullParams p)
                 if (j == i) {
                     kv = R(0);  // the curvature limit is added below
                 } else {
-                    const R chb = sqrt(R(1) + shb * shb);
                     const R den = R(2) * (sa2 + shb * shb);
                     kv = pl * (R(-2) * shb * chb + s2a * tex[jj]) / den;
                 }
                 if (img) {
                     // the image partner: b' = pi (eta_i + eta_j + 2h) / L
-                    const R shp = sinh_series(pl * (te[jj] + etai) + b2h);
-                    const R chp = sqrt(R(1) + shp * shp);
+                    R chp;
+                    const R shp = sinh_cosh_series(pl * (te[jj] + etai) + b2h, &chp);
                     const R den = R(2) * (sa2 + shp * shp);
                     kv += pl * (R(-2) * shp * chp + s2a * tex[jj]) / den;
                 }
@@ -324,6 +345,7 @@ __global__ void __launch_bounds__(kSymThreads) k_full_sympairs(const FullParams 
     const R* ex = static_cast<const R*>(p.ex) + mo;
     const R* v = static_cast<const R*>(p.vin) + mo;
     const double* s2 = static_cast<const double*>(p.s2);
+    const double* rs2 = static_cast<const double*>(p.rs2);
     const double* lfl = static_cast<const double*>(p.lfl) + (long long)m * n;
     const R pl = R(M_PI / p.lx);
     const bool img = !full_deep(p, m);
@@ -365,7 +387,7 @@ __global__ void __launch_bounds__(kSymThreads) k_full_sympairs(const FullParams 
         const int d = (j - i + n) & (n - 1);
         const R sa2 = R(s2[d]);
         const R shb = sinh_series(pl * (tej[jl] - etai));
-        R kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb / sa2);
+        R kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb * R(rs2[d]));
         if (img) {
             const R shp = tsj[jl] * cbi + tcj[jl] * sbi;
             kv += R(-0.5) * log(sa2 + shp * shp) + R(lfl[d]);
@@ -421,6 +443,7 @@ __global__ void __launch_bounds__(kFullThreads) k_full_spairs(const FullParams p
     const double* bxs = static_cast<const double*>(p.bx) + mb;
     const double* pbs = static_cast<const double*>(p.pbout) + mb;
     const double* s2 = static_cast<const double*>(p.s2);
+    const double* rs2 = static_cast<const double*>(p.rs2);
     const double* s2at = static_cast<const double*>(p.s2a);
     const R pl = R(M_PI / p.lx);
     const double pld = M_PI / p.lx;
@@ -450,13 +473,13 @@ __global__ void __launch_bounds__(kFullThreads) k_full_spairs(const FullParams p
             const R s2a = R(s2at[d]);
             // the bed source (x_j, b_j): -D_SB = Im[(pi/L) cot(a + i b) (1 + i b_x,j)],
             // b = pi (b_j - eta_i) / L (the bed lies below every surface point)
-            const R sh = sinh_series(R(pld * (tbz[jj] - (double)etai)));
-            const R ch = sqrt(R(1) + sh * sh);
+            R ch;
+            const R sh = sinh_cosh_series(R(pld * (tbz[jj] - (double)etai)), &ch);
             acc += (double)(pl * (R(-2) * sh * ch + s2a * R(tbx[jj])) / (R(2) * (sa2 + sh * sh))) * tpb[jj];
             if (hasv) {
                 // the direct single layer minus the flat one, as in the image form
                 const R shb = sinh_series(pl * (te[jj] - etai));
-                const R kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb / sa2);
+                const R kv = j == i ? R(-0.5) * log1p(exi * exi) : R(-0.5) * log1p(shb * shb * R(rs2[d]));
                 acc += (double)kv * (double)tsrc[jj];
             }
         }
@@ -527,17 +550,17 @@ __global__ void __launch_bounds__(kFullThreads) k_full_bpairs(const FullParams p
             const R sa2 = R(s2[d]);
             const R s2a = R(s2at[d]);
             // the surface source (x_j, eta_j) seen from the bed point (x_i, b_i)
-            const R sh = sinh_series(R(pld * ((double)te[jj] - bzi)));
+            R ch;
+            const R sh = sinh_cosh_series(R(pld * ((double)te[jj] - bzi)), &ch);
             const R den = R(2) * (sa2 + sh * sh);
             if (KIND == 2) {
-                const R ch = sqrt(R(1) + sh * sh);
                 acc += (double)(pl * (R(-2) * sh * ch + s2a * tex[jj]) / den) * (double)tsrc[jj];
             } else {
                 acc += (double)(R(-0.5) * log(R(2) * den)) * (double)tsrc[jj];
                 if (j != i) {
                     // minus the bed's double layer at (x_j, b_j)
-                    const R shb = sinh_series(R(pld * (tbz[jj] - bzi)));
-                    const R chb = sqrt(R(1) + shb * shb);
+                    R chb;
+                    const R shb = sinh_cosh_series(R(pld * (tbz[jj] - bzi)), &chb);
                     const R denb = R(2) * (sa2 + shb * shb);
                     acc += (double)(pl * (R(-2) * shb * chb + s2a * R(tbx[jj])) / denb) * tpb[jj];
                 }

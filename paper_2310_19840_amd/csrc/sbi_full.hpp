@@ -10,7 +10,7 @@ namespace sbi {
 // Fully nonlinear W solve of one-dimensional grids (sbi_full.hip): the
 // operands of its kernels.  Physical fields are [batch][n] with member
 // stride s_phys; FP64 tables: c0 [batch][n] (S0^-1 circulant per member), d1,
-// d2, s2, s2a [n]; FP64 part [slices][batch][n] holds the slices of a pair pass (then of the apply) and
+// d2, s2, s2a, rs2 [n]; FP64 part [slices][batch][n] holds the slices of a pair pass (then of the apply) and
 // rhs [batch][n] the right-hand side.  Members whose bed is kept as a boundary
 // of its own (bed[m] = 1: a variable bed not too deep to matter) use the
 // two-boundary form: bed geometry bz, bx, bxx, the circulant cm of
@@ -32,6 +32,7 @@ struct FullParams {
     void* d2;
     void* s2;
     void* s2a;            // [n] sin(2 pi j / n) of each index distance
+    void* rs2;            // [n] 1 / sin^2(pi j / n) (0 at j = 0)
     void* lfl;            // [batch][n] the flat image's single-layer term per member
     void* w;              // FP64 [batch][n]: rhs - (S - S0)[V_n]
     const void* vin;      // V_n (null: V_0 = 0)
