@@ -166,6 +166,7 @@ struct sbi_ctx {
     int* full_bed = nullptr;    // [batch] device flags
     bool full_bed_any = false;
     bool full_bed_all = false;  // every member two-boundary: no image-form surface pass
+    int full_pred = 0;          // launches the last fully nonlinear solve took (0: none yet)
     // mixed precision (SBI_MIXED): the FP32 context that solves the correction
     // equations, in the tail of this context's workspace, on the same stream
     sbi_ctx* inner = nullptr;
@@ -1709,11 +1710,14 @@ static sbi_status full_solve(sbi_ctx* c, const void* eta_phys, double tol) {
     // Two-boundary members first update phi_b (the bed pass, which then
     // decides, and the phi_b pass), and their surface pass runs from the first
     // launch (phi_b is not zero there).  V_0 = 0, V_n lives in vbuf[n & 1],
-    // phi_b of launch n in pb[n & 1]; the host polls every few launches.
+    // phi_b of launch n in pb[n & 1]; the host polls after a first chunk as
+    // long as the last solve took (and one launch more), then every kChunk.
     const int M = c->grid.max_sweeps;
     constexpr int kChunk = 8;
-    for (int n0 = 0; n0 <= M; n0 += kChunk) {
-        for (int n = n0; n <= M && n < n0 + kChunk; ++n) {
+    int chunk = c->full_pred > 0 ? c->full_pred + 1 : kChunk;
+    bool all = false;
+    for (int n0 = 0; n0 <= M; n0 += chunk, chunk = kChunk) {
+        for (int n = n0; n <= M && n < n0 + chunk; ++n) {
             p.sweep = n;
             p.vin = n == 0 ? nullptr : p.vbuf[n & 1];
             p.vout = const_cast<void*>(p.vbuf[(n + 1) & 1]);
@@ -1740,9 +1744,15 @@ static sbi_status full_solve(sbi_ctx* c, const void* eta_phys, double tol) {
             SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_APPLY, c->stream)));
         }
         SBI_TRY(read_heads(c));
-        bool all = true;
+        all = true;
         for (int b = 0; b < c->batch; ++b) all = all && c->head[b].done;
         if (all) break;
+    }
+    if (all) {
+        // the deciding launch of each member is its sweep count
+        int last = 0;
+        for (int b = 0; b < c->batch; ++b) last = std::max(last, c->head[b].sweeps);
+        c->full_pred = last + 1;
     }
     c->st.launches += 1;
     SBI_TRY(hip_ok(launch_full(c->fp64, p, FULL_SELECT, c->stream)));
